@@ -1,0 +1,9 @@
+"""Seeded synthetic inputs shared by the CPU oracle tests and the device library.
+
+Holds random-number generation and sampling only; no part of the likelihood.
+"""
+from .philox import philox4x32, uniforms, uniforms_at, key_from_seed  # noqa: F401
+from .samplers import (  # noqa: F401
+    BASE_SEED, CONFIG0_TRUTH, CONFIG0_RANGE, DALITZ_MASSES, DALITZ_RESONANCES,
+    mix1d_events, lognormal_sizes, dalitz_events, dalitz_box,
+)
