@@ -1,0 +1,166 @@
+/*
+ * fitnll.h -- C ABI of libfitnll.so, an unbinned maximum-likelihood engine for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * What it computes.  Fitting a probability density to a data sample spends
+ * nearly all its time evaluating the density independently at every event of
+ * the sample (GooFit 2.0, Sec. 1).  The library evaluates, for a model (a
+ * composed density: basic components added with fractions, or a coherent sum
+ * of complex resonance amplitudes whose magnitude squared is the density,
+ * Sec. 1 and 5), a parameter vector theta and an event sample x_1..x_N:
+ *
+ *     NLL(theta) = - sum_i ln P~(x_i | theta) + N ln I(theta),
+ *     I(theta)   = integral of P~ over the observable domain,
+ *
+ * and optionally dNLL/dtheta by a hand-written adjoint pass.  This is the
+ * objective function the paper's fitters hand to Minuit (Sec. 4); the fitter
+ * itself (a quasi-Newton minimizer) and many-fits-per-launch batching sit on
+ * top of the same kernels.
+ *
+ * Conventions shared by every entry point:
+ *  - Every call returns fn_status; FN_OK is 0, errors are negative.  On error
+ *    fn_last_error() returns a message (thread-local, owned by the library,
+ *    valid until the next fn_* call on the same thread).  The paper unified
+ *    its errors in one exception type (Sec. 3); this is the C form of that.
+ *  - Floating point is IEEE binary64 throughout.
+ *  - Events are caller-owned DEVICE memory in structure-of-arrays layout:
+ *    observable j of event i is at ev[j*ld + i], ld >= n.  The library never
+ *    frees or writes them; they must stay valid until the stream work that
+ *    reads them has completed.  (The paper credits its structure-of-arrays
+ *    layout for speed, Sec. 4.)
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream).  Entry
+ *    points documented as synchronous return after the stream work is done;
+ *    *_async ones only enqueue work.
+ *  - A model may be used from one host thread and one stream at a time.
+ *  - Results are deterministic: the event sum is a fixed two-level tree
+ *    (a fixed chunk of events per workgroup, then a fixed-order sum of the
+ *    chunk partials), so repeated calls, and the same fit alone or inside a
+ *    batch, give bitwise identical values.
+ *  - Non-finite or non-positive P~ at any event (or I <= 0) makes the NLL
+ *    +inf, the gradient NaN, and the call returns FN_E_NONFINITE; a minimizer
+ *    treats that as a rejected step.
+ */
+#ifndef FITNLL_H
+#define FITNLL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fn_status;
+enum {
+  FN_OK = 0,
+  FN_E_INVALID = -1,   /* bad argument or malformed model description */
+  FN_E_DOMAIN = -2,    /* events outside the observable domain */
+  FN_E_NONFINITE = -3, /* NLL not finite (P~ <= 0, NaN parameters, I <= 0) */
+  FN_E_NOMEM = -4,     /* device or pinned host allocation failed */
+  FN_E_HIP = -5,       /* a HIP runtime call failed; message has its text */
+  FN_E_BUDGET = -6,    /* request larger than the memory budget */
+  FN_E_CANCELLED = -7  /* request cancelled before it finished */
+};
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* fn_last_error(void);
+/* Library version, major*10000 + minor*100 + patch. */
+int32_t fn_version(void);
+
+/* ---------------------------------------------------------------- context */
+typedef struct fn_ctx fn_ctx;
+/* One context per device; `device` is a HIP device ordinal.  The context owns
+ * nothing but the device binding; models hold their own buffers. */
+fn_status fn_ctx_create(int32_t device, fn_ctx** out);
+fn_status fn_ctx_destroy(fn_ctx* ctx);
+
+/* ------------------------------------------------------------------ model */
+typedef struct fn_model fn_model;
+
+/* Compile a model description (JSON text, UTF-8) into a device model.
+ *
+ * Models follow the paper's composition (Fig. 1): observables with ranges,
+ * parameters addressed by index, components combined into one density.
+ * Integers in the description are indices into theta.
+ *
+ *  kind "mix1d":  {"kind":"mix1d","lo":a,"hi":b,"n_params":P,
+ *                  "components":[{"type":T,"params":[i,j]},...],"fracs":[...]}
+ *     T in gauss(mu,sigma), exp(tau), argus(m0,c) [power 1/2, c<0, lo>=0],
+ *     bw(m0,gamma) [non-relativistic].  K components take K-1 fractions; the
+ *     last gets 1 - sum.  Each component is normalized analytically on
+ *     [lo,b], so I = 1.  One observable.
+ *  kind "dalitz3": {"kind":"dalitz3","M":..,"m":[m1,m2,m3],"r_res":r,
+ *                  "r_D":rD,"grid":[nx,ny],"free_lineshapes":bool,
+ *                  "resonances":[{"pair":"12"|"13"|"23","L":0|1|2,
+ *                                 "m0":..,"w0":..},...]}
+ *     Two observables (s12, s13).  P~ = |sum_k c_k A_k|^2 with relativistic
+ *     Breit-Wigner lineshapes (mass-dependent width, Blatt-Weisskopf
+ *     barriers) times Zemach spin factors; I is the midpoint rule on an
+ *     nx x ny grid over the Dalitz bounding box, cells counted when their
+ *     centre is inside the physical region.  theta = (Re c_k, Im c_k)_k, then
+ *     (m0_k, Gamma0_k)_k when free_lineshapes is true.  Up to 16 resonances.
+ *     With fixed lineshapes the grid is reduced once to the Hermitian matrix
+ *     M_ij = dA sum_cells A_i conj(A_j) and I = c^H M c afterwards (the
+ *     paper's caching of partial results while parameters are unchanged,
+ *     Sec. 4).
+ *  Optional keys for every kind: "chunk" (events per workgroup, a power of two
+ *  in [256, 65536], default chosen per kind) -- fixed per model, it defines
+ *  the summation tree.
+ * Returns FN_E_INVALID with a message for a malformed description. */
+fn_status fn_model_create(fn_ctx* ctx, const char* desc_json, fn_model** out);
+/* Number of parameters, observables, and the summation chunk of a model. */
+fn_status fn_model_info(const fn_model* m, int32_t* n_params, int32_t* n_obs, int32_t* chunk);
+/* Frees the model's device memory.  Streams using it must be synchronised. */
+fn_status fn_model_destroy(fn_model* m);
+
+/* Count events outside the observable domain (range for mix1d; bounding box
+ * and physical region, with a relative tolerance of 1e-9, for dalitz3).
+ * Out-of-range data checks are a paper feature (Sec. 4).  Synchronous.
+ * Returns FN_E_DOMAIN when *n_bad > 0. */
+fn_status fn_events_check(fn_model* m, const double* ev, int64_t n, int64_t ld,
+                          int64_t* n_bad, void* stream);
+
+/* NLL and, when grad_host != NULL, its gradient (P doubles), for host theta
+ * (P doubles, copied before return).  Synchronous.  n may be 0 (NLL = 0). */
+fn_status fn_nll(fn_model* m, const double* theta_host, const double* ev, int64_t n,
+                 int64_t ld, double* nll_host, double* grad_host, void* stream);
+
+/* Asynchronous form for device-resident loops: theta_dev (P doubles) and
+ * out_dev (1+P doubles: NLL then gradient; gradient entries untouched when
+ * with_grad == 0) are device pointers.  No host synchronisation and no
+ * allocation after the first call of a given size; non-finite results are
+ * left in out_dev for the caller to inspect. */
+fn_status fn_nll_async(fn_model* m, const double* theta_dev, const double* ev, int64_t n,
+                       int64_t ld, double* out_dev, int32_t with_grad, void* stream);
+
+/* Normalization integral I(theta) and, when dnorm_host != NULL, dI/dtheta. */
+fn_status fn_norm(fn_model* m, const double* theta_host, double* norm_host,
+                  double* dnorm_host, void* stream);
+
+/* Normalized density P~(x_i)/I per event into p_dev (n doubles, device). */
+fn_status fn_eval(fn_model* m, const double* theta_host, const double* ev, int64_t n,
+                  int64_t ld, double* p_dev, void* stream);
+
+/* ---------------------------------------------------------------- fitting */
+/* One fit by quasi-Newton minimization (BFGS with a line search satisfying
+ * the strong Wolfe conditions) of the NLL on the device, replacing the
+ * paper's FitManager + Minuit loop (Fig. 1, Sec. 4).
+ *  theta0_host: start (P doubles).  free_mask: P int32, nonzero = free
+ *  (NULL = all free).  grad_mode: 0 = adjoint gradient from the device,
+ *  1 = central finite differences of the NLL (2 extra NLL calls per free
+ *  parameter, step 1e-6 max(|theta|,1)).  Outputs (host, P doubles each,
+ *  may be NULL): theta_out, err_out (sqrt of the diagonal of the inverse of
+ *  the Hessian of NLL, which is the covariance for an NLL with error
+ *  definition 1/2; fixed parameters get 0).  nll_out, n_iter, n_calls
+ *  (NLL evaluations) may be NULL.  Convergence: estimated distance to
+ *  minimum g^T H^-1 g / 2 < tol (tol <= 0 selects 1e-7), at most max_iter
+ *  iterations (<= 0 selects 500).  Returns FN_OK when converged, FN_E_NONFINITE
+ *  if the start point is not finite, FN_E_INVALID if it did not converge. */
+fn_status fn_fit(fn_model* m, const double* theta0_host, const int32_t* free_mask,
+                 const double* ev, int64_t n, int64_t ld, int32_t grad_mode, double tol,
+                 int32_t max_iter, double* theta_out, double* err_out, double* nll_out,
+                 int32_t* n_iter, int32_t* n_calls, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FITNLL_H */

@@ -1,0 +1,186 @@
+"""Python surface of libfitnll: argument marshalling only.
+
+Device memory and streams come from PyTorch (ROCm build): event tensors are
+float64 CUDA tensors of shape (n_obs, n) (structure of arrays), and calls run
+on ``torch.cuda.current_stream()`` unless a stream is given.  Every
+computation runs in the HIP kernels behind the C ABI.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import json
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check
+
+_ctx = {}
+
+
+def context(device: int = 0):
+    """The library context of a device (created once)."""
+    if device not in _ctx:
+        lib = _lib.load()
+        h = C.c_void_p()
+        check(lib.fn_ctx_create(int(device), C.byref(h)))
+        _ctx[device] = h
+    return _ctx[device]
+
+
+def _dbl(a):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    return a, a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _events(ev: torch.Tensor, n_obs: int):
+    if not isinstance(ev, torch.Tensor) or not ev.is_cuda or ev.dtype != torch.float64:
+        raise TypeError("events must be a float64 CUDA tensor")
+    if ev.dim() == 1:
+        ev = ev.unsqueeze(0)
+    if ev.dim() != 2 or ev.shape[0] != n_obs:
+        raise ValueError(f"events must have shape ({n_obs}, n)")
+    if ev.stride(1) != 1:
+        raise ValueError("events must be contiguous along the event axis")
+    n = ev.shape[1]
+    ld = ev.stride(0) if n_obs > 1 else n
+    return C.c_void_p(ev.data_ptr() if n > 0 else 0), n, ld
+
+
+@dataclass
+class FitResult:
+    theta: np.ndarray
+    errors: np.ndarray
+    nll: float
+    n_iter: int
+    n_calls: int
+    status: int
+
+
+class Model:
+    """A compiled model on one device (see fn_model_create for descriptions)."""
+
+    def __init__(self, desc: dict | str, device: int = 0):
+        lib = _lib.load()
+        self._lib = lib
+        self.desc = desc if isinstance(desc, dict) else json.loads(desc)
+        self.device = device
+        h = C.c_void_p()
+        check(lib.fn_model_create(context(device), json.dumps(self.desc).encode(), C.byref(h)))
+        self._h = h
+        p, o, c = C.c_int32(), C.c_int32(), C.c_int32()
+        check(lib.fn_model_info(h, C.byref(p), C.byref(o), C.byref(c)))
+        self.n_params, self.n_obs, self.chunk = p.value, o.value, c.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.fn_model_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _theta(self, theta):
+        a, ptr = _dbl(theta)
+        if a.size != self.n_params:
+            raise ValueError(f"theta must have {self.n_params} entries")
+        return a, ptr
+
+    def nll(self, theta, events: torch.Tensor, grad: bool = False, stream=None):
+        """NLL (and gradient as a numpy array when grad=True)."""
+        th, thp = self._theta(theta)
+        evp, n, ld = _events(events, self.n_obs)
+        out = C.c_double()
+        g = np.zeros(self.n_params)
+        gp = g.ctypes.data_as(C.POINTER(C.c_double)) if grad else None
+        check(self._lib.fn_nll(self._h, thp, evp, n, ld, C.byref(out), gp, _stream_ptr(stream)))
+        return (out.value, g) if grad else out.value
+
+    def nll_async(self, theta_dev: torch.Tensor, events: torch.Tensor, out_dev: torch.Tensor,
+                  with_grad: bool = True, stream=None):
+        """Enqueue NLL (+grad) with device theta; out_dev gets 1+P doubles."""
+        evp, n, ld = _events(events, self.n_obs)
+        assert theta_dev.is_cuda and theta_dev.dtype == torch.float64 and theta_dev.numel() >= self.n_params
+        assert out_dev.is_cuda and out_dev.dtype == torch.float64 and out_dev.numel() >= 1 + self.n_params
+        check(self._lib.fn_nll_async(self._h, C.c_void_p(theta_dev.data_ptr()), evp, n, ld,
+                                     C.c_void_p(out_dev.data_ptr()), 1 if with_grad else 0,
+                                     _stream_ptr(stream)))
+
+    def norm(self, theta, stream=None):
+        """(I, dI/dtheta)."""
+        th, thp = self._theta(theta)
+        out = C.c_double()
+        g = np.zeros(self.n_params)
+        check(self._lib.fn_norm(self._h, thp, C.byref(out), g.ctypes.data_as(C.POINTER(C.c_double)),
+                                _stream_ptr(stream)))
+        return out.value, g
+
+    def eval(self, theta, events: torch.Tensor, stream=None) -> torch.Tensor:
+        """Normalized density per event (device tensor)."""
+        th, thp = self._theta(theta)
+        evp, n, ld = _events(events, self.n_obs)
+        p = torch.empty(n, dtype=torch.float64, device=events.device)
+        check(self._lib.fn_eval(self._h, thp, evp, n, ld, C.c_void_p(p.data_ptr() if n else 0),
+                                _stream_ptr(stream)))
+        return p
+
+    def check_events(self, events: torch.Tensor, stream=None) -> int:
+        """Number of events outside the observable domain (0 if all inside)."""
+        evp, n, ld = _events(events, self.n_obs)
+        bad = C.c_int64()
+        st = self._lib.fn_events_check(self._h, evp, n, ld, C.byref(bad), _stream_ptr(stream))
+        if st not in (_lib.FN_OK, _lib.FN_E_DOMAIN):
+            check(st)
+        return bad.value
+
+    def fit(self, theta0, events: torch.Tensor, free=None, grad_mode: str = "adjoint",
+            tol: float = 1e-7, max_iter: int = 500, errors: bool = True, stream=None,
+            raise_on_fail: bool = True) -> FitResult:
+        """Quasi-Newton fit on the device NLL (grad_mode 'adjoint' or 'fd')."""
+        th, thp = self._theta(theta0)
+        evp, n, ld = _events(events, self.n_obs)
+        mask = None
+        if free is not None:
+            m = np.ascontiguousarray(np.asarray(free, dtype=np.int32))
+            mask = m.ctypes.data_as(C.POINTER(C.c_int32))
+        out_t = np.zeros(self.n_params)
+        out_e = np.zeros(self.n_params)
+        nll = C.c_double()
+        it, calls = C.c_int32(), C.c_int32()
+        st = self._lib.fn_fit(self._h, thp, mask, evp, n, ld, 0 if grad_mode == "adjoint" else 1, tol, max_iter,
+                              out_t.ctypes.data_as(C.POINTER(C.c_double)),
+                              out_e.ctypes.data_as(C.POINTER(C.c_double)) if errors else None,
+                              C.byref(nll), C.byref(it), C.byref(calls), _stream_ptr(stream))
+        if st != _lib.FN_OK and raise_on_fail:
+            check(st)
+        return FitResult(out_t, out_e, nll.value, it.value, calls.value, st)
+
+
+class NLLFunction(torch.autograd.Function):
+    """NLL as a differentiable function of theta (a float64 CPU tensor).
+
+    forward runs the device NLL with the adjoint gradient; backward returns
+    grad_output times that gradient.
+    """
+
+    @staticmethod
+    def forward(ctx, theta: torch.Tensor, model: Model, events: torch.Tensor):
+        v, g = model.nll(theta.detach().cpu().numpy(), events, grad=True)
+        ctx.save_for_backward(torch.from_numpy(g).to(theta.dtype))
+        return torch.tensor(v, dtype=theta.dtype)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (g,) = ctx.saved_tensors
+        return grad_out * g, None, None

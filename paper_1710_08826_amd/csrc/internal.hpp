@@ -1,0 +1,77 @@
+// Host-side internals of libfitnll: error type, device buffers, the context
+// and model objects behind the opaque C handles.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <functional>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/fitnll.h"
+#include "model.hpp"
+
+namespace fn {
+
+struct Error : std::runtime_error {
+  fn_status code;
+  Error(fn_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+void hip_check(hipError_t e, const char* what);
+void set_error(const std::string& s);
+fn_status guard(const std::function<void()>& body);
+
+// Grow-only device allocation.
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  void reserve(size_t nbytes);
+  void release();
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+};
+
+enum ModelKind : int { kKindMix1d = 1, kKindDalitz3 = 2 };
+
+}  // namespace fn
+
+struct fn_ctx {
+  int device = 0;
+};
+
+struct fn_model {
+  fn_ctx* ctx = nullptr;
+  int device = 0;
+  int kind = 0;
+  int P = 0;
+  int n_obs = 0;
+  int chunk = 1024;       // events per workgroup (defines the summation tree)
+  int grid_chunk = 1024;  // grid cells per workgroup
+  fn::Mix1dConst mix;
+  fn::DalitzConst dal;
+  std::vector<double> fixed_ls;  // (m0, Gamma0) per resonance when not free
+  bool M_valid = false;          // cached normalization matrix is current
+  fn::DevBuf d_table, d_part, d_npart, d_out, d_fixed, d_M, d_count;
+  double* h_out = nullptr;       // pinned
+  long long stats_calls = 0;
+
+  fn::Mix1dTable* table_mix() { return (fn::Mix1dTable*)d_table.ptr; }
+  fn::DalitzTable* table_dal() { return (fn::DalitzTable*)d_table.ptr; }
+  double* part() { return (double*)d_part.ptr; }
+  double* npart() { return (double*)d_npart.ptr; }
+  double* out() { return (double*)d_out.ptr; }
+  double* fixed() { return (double*)d_fixed.ptr; }
+  double* Mc() { return (double*)d_M.ptr; }
+  ~fn_model();
+};
+
+namespace fn {
+void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const double* ev, int64_t n, int64_t ld,
+             bool grad, double* out_dev, hipStream_t s);
+void nll_host(fn_model* m, const double* theta_host, const double* ev, int64_t n, int64_t ld, double* nll,
+              double* grad, hipStream_t s);
+void check_events_args(fn_model* m, const double* ev, int64_t n, int64_t ld);
+}  // namespace fn

@@ -1,0 +1,455 @@
+// C ABI of libfitnll: contexts, the model compiler (JSON description ->
+// constant structs + device buffers), and the NLL pipeline
+//   prologue (theta -> table) -> normalization -> events pass -> finalize.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/fitnll.h"
+#include "internal.hpp"
+#include "json.hpp"
+#include "kernels.hpp"
+
+namespace fn {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& s) { g_last_error = s; }
+void clear_error() { g_last_error.clear(); }
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw Error(FN_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+fn_status guard(const std::function<void()>& body) {
+  clear_error();
+  try {
+    body();
+    return FN_OK;
+  } catch (const Error& e) {
+    set_error(e.what());
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return FN_E_NOMEM;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return FN_E_INVALID;
+  }
+}
+
+// ------------------------------------------------------------ device buffer
+void DevBuf::reserve(size_t nbytes) {
+  if (nbytes <= bytes) return;
+  if (ptr) hip_check(hipFree(ptr), "hipFree");
+  ptr = nullptr;
+  bytes = 0;
+  const size_t want = nbytes < 256 ? 256 : nbytes;
+  if (hipMalloc(&ptr, want) != hipSuccess) {
+    ptr = nullptr;
+    (void)hipGetLastError();
+    throw Error(FN_E_NOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed");
+  }
+  bytes = want;
+}
+void DevBuf::release() {
+  if (ptr) (void)hipFree(ptr);
+  ptr = nullptr;
+  bytes = 0;
+}
+
+// ------------------------------------------------------------ model compiler
+static bool is_pow2(long v) { return v > 0 && (v & (v - 1)) == 0; }
+
+static void compile_mix1d(const json::Value& d, fn_model* m) {
+  Mix1dConst& mc = m->mix;
+  std::memset(&mc, 0, sizeof(mc));
+  mc.lo = d.at("lo").number();
+  mc.hi = d.at("hi").number();
+  if (!(mc.hi > mc.lo)) throw Error(FN_E_INVALID, "mix1d: need hi > lo");
+  const auto& comps = d.at("components").array();
+  mc.K = (int)comps.size();
+  if (mc.K < 1 || mc.K > kMixMaxComp) throw Error(FN_E_INVALID, "mix1d: 1..8 components");
+  int maxidx = -1;
+  for (int k = 0; k < mc.K; ++k) {
+    const std::string& t = comps[k].at("type").string();
+    const auto& ps = comps[k].at("params").array();
+    int need;
+    if (t == "gauss") { mc.type[k] = kGauss; need = 2; }
+    else if (t == "exp") { mc.type[k] = kExp; need = 1; }
+    else if (t == "argus") { mc.type[k] = kArgus; need = 2; }
+    else if (t == "bw") { mc.type[k] = kBW; need = 2; }
+    else throw Error(FN_E_INVALID, "mix1d: unknown component type \"" + t + "\"");
+    if ((int)ps.size() != need) throw Error(FN_E_INVALID, "mix1d: wrong parameter count for " + t);
+    if (mc.type[k] == kArgus && mc.lo < 0.0) throw Error(FN_E_INVALID, "mix1d: argus needs lo >= 0");
+    mc.npar[k] = need;
+    for (int j = 0; j < need; ++j) {
+      const long idx = ps[j].integer();
+      if (idx < 0 || idx >= kMaxParams) throw Error(FN_E_INVALID, "mix1d: parameter index out of range");
+      mc.pidx[k][j] = (int)idx;
+      if (idx > maxidx) maxidx = (int)idx;
+    }
+  }
+  const auto& fr = d.has("fracs") ? d.at("fracs").array() : std::vector<json::Value>();
+  if ((int)fr.size() != mc.K - 1) throw Error(FN_E_INVALID, "mix1d: need K-1 fractions");
+  for (int k = 0; k < mc.K - 1; ++k) {
+    const long idx = fr[k].integer();
+    if (idx < 0 || idx >= kMaxParams) throw Error(FN_E_INVALID, "mix1d: fraction index out of range");
+    mc.fidx[k] = (int)idx;
+    if (idx > maxidx) maxidx = (int)idx;
+  }
+  int P = maxidx + 1;
+  if (d.has("n_params")) {
+    const long np = d.at("n_params").integer();
+    if (np < P || np > kMaxParams) throw Error(FN_E_INVALID, "mix1d: n_params smaller than the indices used");
+    P = (int)np;
+  }
+  mc.n_params = P;
+  m->P = P;
+  m->n_obs = 1;
+  m->chunk = 2048;
+  m->d_table.reserve(sizeof(Mix1dTable));
+}
+
+static void compile_dalitz3(const json::Value& d, fn_model* m) {
+  DalitzConst& dc = m->dal;
+  std::memset(&dc, 0, sizeof(dc));
+  const double M = d.at("M").number();
+  const auto& ms = d.at("m").array();
+  if (ms.size() != 3) throw Error(FN_E_INVALID, "dalitz3: need three daughter masses");
+  const double mm[4] = {M, ms[0].number(), ms[1].number(), ms[2].number()};
+  if (!(M > mm[1] + mm[2] + mm[3]) || !(mm[1] > 0) || !(mm[2] > 0) || !(mm[3] > 0))
+    throw Error(FN_E_INVALID, "dalitz3: masses must be positive and M > m1 + m2 + m3");
+  const double rr = d.has("r_res") ? d.at("r_res").number() : 1.5;
+  const double rd = d.has("r_D") ? d.at("r_D").number() : 5.0;
+  dc.M2 = M * M;
+  dc.m1s = mm[1] * mm[1];
+  dc.m2s = mm[2] * mm[2];
+  dc.m3s = mm[3] * mm[3];
+  dc.msum = M * M + mm[1] * mm[1] + mm[2] * mm[2] + mm[3] * mm[3];
+  dc.r2 = rr * rr;
+  dc.rD2 = rd * rd;
+  long nx = 1024, ny = 1024;
+  if (d.has("grid")) {
+    const auto& g = d.at("grid").array();
+    if (g.size() != 2) throw Error(FN_E_INVALID, "dalitz3: grid must be [nx, ny]");
+    nx = g[0].integer();
+    ny = g[1].integer();
+  }
+  if (nx < 1 || ny < 1 || nx * ny > (1L << 30)) throw Error(FN_E_INVALID, "dalitz3: bad grid size");
+  dc.nx = (int)nx;
+  dc.ny = (int)ny;
+  dc.a12 = (mm[1] + mm[2]) * (mm[1] + mm[2]);
+  dc.d12 = ((M - mm[3]) * (M - mm[3]) - dc.a12) / nx;
+  dc.a13 = (mm[1] + mm[3]) * (mm[1] + mm[3]);
+  dc.d13 = ((M - mm[2]) * (M - mm[2]) - dc.a13) / ny;
+  dc.dA = dc.d12 * dc.d13;
+  // pairs: 0 = "12" (A,B,C) = (1,2,3); 1 = "13" (1,3,2); 2 = "23" (2,3,1)
+  const int who[3][3] = {{1, 2, 3}, {1, 3, 2}, {2, 3, 1}};
+  for (int c = 0; c < 3; ++c) {
+    DalitzChan& ch = dc.ch[c];
+    const double mA = mm[who[c][0]], mB = mm[who[c][1]], mC = mm[who[c][2]];
+    ch.mA2 = mA * mA;
+    ch.mB2 = mB * mB;
+    ch.mC2 = mC * mC;
+    ch.sum2 = (mA + mB) * (mA + mB);
+    ch.dif2 = (mA - mB) * (mA - mB);
+    ch.Psum2 = (M + mC) * (M + mC);
+    ch.Pdif2 = (M - mC) * (M - mC);
+    ch.zc = (M * M - mC * mC) * (mB * mB - mA * mA);
+  }
+  dc.free_ls = d.has("free_lineshapes") ? (d.at("free_lineshapes").boolean() ? 1 : 0) : 0;
+  const auto& res = d.at("resonances").array();
+  dc.K = (int)res.size();
+  if (dc.K < 1 || dc.K > kDalMaxRes) throw Error(FN_E_INVALID, "dalitz3: 1..16 resonances");
+  m->fixed_ls.assign(2 * dc.K, 0.0);
+  for (int k = 0; k < dc.K; ++k) {
+    const std::string& p = res[k].at("pair").string();
+    int c;
+    if (p == "12") c = 0;
+    else if (p == "13") c = 1;
+    else if (p == "23") c = 2;
+    else throw Error(FN_E_INVALID, "dalitz3: pair must be \"12\", \"13\" or \"23\"");
+    const long L = res[k].at("L").integer();
+    if (L < 0 || L > 2) throw Error(FN_E_INVALID, "dalitz3: L must be 0, 1 or 2");
+    dc.chan[k] = c;
+    dc.L[k] = (int)L;
+    dc.ch[c].useL[L] = 1;
+    m->fixed_ls[2 * k] = res[k].at("m0").number();
+    m->fixed_ls[2 * k + 1] = res[k].at("w0").number();
+  }
+  m->P = dc.free_ls ? 4 * dc.K : 2 * dc.K;
+  m->n_obs = 2;
+  m->chunk = 1024;
+  m->grid_chunk = 1024;
+  m->d_table.reserve(sizeof(DalitzTable));
+  m->d_fixed.reserve(sizeof(double) * 2 * dc.K);
+  hip_check(hipMemcpy(m->d_fixed.ptr, m->fixed_ls.data(), sizeof(double) * 2 * dc.K, hipMemcpyHostToDevice),
+            "hipMemcpy");
+  m->d_M.reserve(sizeof(double) * 2 * dc.K * dc.K);
+}
+
+// ------------------------------------------------------------ pipeline
+static int64_t nchunks_for(int64_t n, int chunk) { return (n + chunk - 1) / chunk; }
+
+void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const double* ev, int64_t n, int64_t ld,
+             bool grad, double* out_dev, hipStream_t s) {
+  const int64_t nch = nchunks_for(n, m->chunk);
+  if (m->kind == kKindMix1d) {
+    const Mix1dConst& mc = m->mix;
+    const int kmax = mix1d_kmax(mc.K);
+    const int nv = mix1d_nv(kmax, grad);
+    m->d_part.reserve(sizeof(double) * (size_t)(nch > 0 ? nch : 1) * nv);
+    ParamBlock zero;
+    mix1d_launch_prologue(mc, pb ? *pb : zero, pb ? nullptr : theta_dev, 1, 0, m->table_mix(), s);
+    mix1d_launch_events(mc, m->table_mix(), ev, n, m->chunk, nch, grad, m->part(), s);
+    mix1d_launch_finalize(mc, m->table_mix(), m->part(), nch, grad, out_dev, s);
+  } else {
+    const DalitzConst& dc = m->dal;
+    const int kmax = dalitz_kmax(dc.K);
+    const int g = grad ? (dc.free_ls ? 2 : 1) : 0;
+    const int nv = dalitz_nv_events(kmax, g);
+    m->d_part.reserve(sizeof(double) * (size_t)(nch > 0 ? nch : 1) * nv);
+    ParamBlock zero;
+    dalitz_launch_prologue(dc, pb ? *pb : zero, pb ? nullptr : theta_dev, m->fixed(), 1, 0, m->table_dal(), s);
+    const double* npart = nullptr;
+    int64_t nrows = 0;
+    int nnv = 0;
+    if (dc.free_ls) {
+      // lineshapes move: integrate P~ (and dP~) over the grid every call
+      const int64_t ncell = (int64_t)dc.nx * dc.ny;
+      nrows = nchunks_for(ncell, m->grid_chunk);
+      nnv = dalitz_nv_events(kmax, g);
+      m->d_npart.reserve(sizeof(double) * (size_t)nrows * nnv);
+      dalitz_launch_grid(dc, m->table_dal(), m->grid_chunk, nrows, g, m->npart(), s);
+      npart = m->npart();
+    } else if (!m->M_valid) {
+      // fixed lineshapes: reduce the grid once to M_ij = dA sum A_i conj(A_j)
+      const int64_t ncell = (int64_t)dc.nx * dc.ny;
+      const int64_t mrows = nchunks_for(ncell, m->grid_chunk);
+      m->d_npart.reserve(sizeof(double) * (size_t)mrows * dalitz_nv_mrows(kmax));
+      for (int i0 = 0; i0 < dc.K; i0 += 4)
+        dalitz_launch_mrows(dc, m->table_dal(), m->grid_chunk, mrows, i0, m->npart(), m->Mc(), s);
+      m->M_valid = true;
+    }
+    dalitz_launch_events(dc, m->table_dal(), ev, ld, n, m->chunk, nch, g, m->part(), s);
+    dalitz_launch_finalize(dc, m->table_dal(), m->part(), nch, nv, npart, nrows, nnv, m->Mc(), (double)n, grad,
+                           out_dev, s);
+  }
+  hip_check(hipGetLastError(), "kernel launch");
+}
+
+void check_events_args(fn_model* m, const double* ev, int64_t n, int64_t ld) {
+  if (n < 0) throw Error(FN_E_INVALID, "n must be >= 0");
+  if (n > 0 && !ev) throw Error(FN_E_INVALID, "events pointer is NULL");
+  if (m->n_obs > 1 && ld < n) throw Error(FN_E_INVALID, "ld must be >= n");
+}
+
+ParamBlock make_block(const fn_model* m, const double* theta_host) {
+  if (!theta_host) throw Error(FN_E_INVALID, "theta is NULL");
+  ParamBlock pb;
+  std::memset(&pb, 0, sizeof(pb));
+  for (int p = 0; p < m->P; ++p) pb.v[p] = theta_host[p];
+  return pb;
+}
+
+void nll_host(fn_model* m, const double* theta_host, const double* ev, int64_t n, int64_t ld, double* nll,
+              double* grad, hipStream_t s) {
+  check_events_args(m, ev, n, ld);
+  const ParamBlock pb = make_block(m, theta_host);
+  const bool g = grad != nullptr;
+  run_nll(m, &pb, nullptr, ev, n, ld, g, m->out(), s);
+  const size_t cnt = (size_t)(g ? 1 + m->P : 1);
+  hip_check(hipMemcpyAsync(m->h_out, m->out(), sizeof(double) * cnt, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+  hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+  const double v = m->h_out[0];
+  m->stats_calls += 1;
+  if (grad)
+    for (int p = 0; p < m->P; ++p) grad[p] = m->h_out[1 + p];
+  if (!std::isfinite(v)) {
+    if (nll) *nll = INFINITY;
+    if (grad)
+      for (int p = 0; p < m->P; ++p) grad[p] = NAN;
+    throw Error(FN_E_NONFINITE, "NLL is not finite (P~ <= 0 at some event, invalid parameters, or I <= 0)");
+  }
+  bool gbad = false;
+  if (grad)
+    for (int p = 0; p < m->P; ++p) gbad |= !std::isfinite(grad[p]);
+  if (nll) *nll = v;
+  if (gbad) throw Error(FN_E_NONFINITE, "gradient is not finite");
+}
+
+}  // namespace fn
+
+using namespace fn;
+
+extern "C" {
+
+const char* fn_last_error(void) { return g_last_error.c_str(); }
+int32_t fn_version(void) { return 10000; }
+
+fn_status fn_ctx_create(int32_t device, fn_ctx** out) {
+  return guard([&] {
+    if (!out) throw Error(FN_E_INVALID, "out is NULL");
+    int n = 0;
+    hip_check(hipGetDeviceCount(&n), "hipGetDeviceCount");
+    if (device < 0 || device >= n) throw Error(FN_E_INVALID, "no such device");
+    hip_check(hipSetDevice(device), "hipSetDevice");
+    fn_ctx* c = new fn_ctx;
+    c->device = device;
+    *out = c;
+  });
+}
+
+fn_status fn_ctx_destroy(fn_ctx* ctx) {
+  return guard([&] { delete ctx; });
+}
+
+fn_status fn_model_create(fn_ctx* ctx, const char* desc_json, fn_model** out) {
+  fn_model* m = nullptr;
+  fn_status st = guard([&] {
+    if (!ctx || !desc_json || !out) throw Error(FN_E_INVALID, "NULL argument");
+    json::Value d;
+    try {
+      d = json::parse(desc_json);
+    } catch (const std::exception& e) {
+      throw Error(FN_E_INVALID, e.what());
+    }
+    hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+    m = new fn_model;
+    m->ctx = ctx;
+    m->device = ctx->device;
+    try {
+      const std::string& kind = d.at("kind").string();
+      if (kind == "mix1d") {
+        m->kind = kKindMix1d;
+        compile_mix1d(d, m);
+      } else if (kind == "dalitz3") {
+        m->kind = kKindDalitz3;
+        compile_dalitz3(d, m);
+      } else {
+        throw Error(FN_E_INVALID, "unknown model kind \"" + kind + "\"");
+      }
+      if (d.has("chunk")) {
+        const long c = d.at("chunk").integer();
+        if (!is_pow2(c) || c < 256 || c > 65536) throw Error(FN_E_INVALID, "chunk must be a power of two in [256, 65536]");
+        m->chunk = (int)c;
+      }
+    } catch (const Error&) {
+      throw;
+    } catch (const std::exception& e) {
+      throw Error(FN_E_INVALID, std::string("model description: ") + e.what());
+    }
+    m->d_out.reserve(sizeof(double) * (2 + 2 * m->P));
+    m->d_count.reserve(sizeof(unsigned long long));
+    if (hipHostMalloc((void**)&m->h_out, sizeof(double) * (2 + 2 * m->P) + 64, hipHostMallocDefault) !=
+        hipSuccess) {
+      m->h_out = nullptr;
+      throw Error(FN_E_NOMEM, "hipHostMalloc failed");
+    }
+    *out = m;
+  });
+  if (st != FN_OK && m) {
+    delete m;
+  }
+  return st;
+}
+
+fn_status fn_model_info(const fn_model* m, int32_t* n_params, int32_t* n_obs, int32_t* chunk) {
+  return guard([&] {
+    if (!m) throw Error(FN_E_INVALID, "model is NULL");
+    if (n_params) *n_params = m->P;
+    if (n_obs) *n_obs = m->n_obs;
+    if (chunk) *chunk = m->chunk;
+  });
+}
+
+fn_status fn_model_destroy(fn_model* m) {
+  return guard([&] { delete m; });
+}
+
+fn_status fn_events_check(fn_model* m, const double* ev, int64_t n, int64_t ld, int64_t* n_bad, void* stream) {
+  return guard([&] {
+    if (!m) throw Error(FN_E_INVALID, "model is NULL");
+    check_events_args(m, ev, n, ld);
+    hip_check(hipSetDevice(m->device), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    hip_check(hipMemsetAsync(m->d_count.ptr, 0, sizeof(unsigned long long), s), "hipMemsetAsync");
+    if (m->kind == kKindMix1d) mix1d_launch_check(m->mix, ev, n, (unsigned long long*)m->d_count.ptr, s);
+    else dalitz_launch_check(m->dal, ev, ld, n, (unsigned long long*)m->d_count.ptr, s);
+    hip_check(hipGetLastError(), "kernel launch");
+    unsigned long long cnt = 0;
+    hip_check(hipMemcpyAsync(m->h_out, m->d_count.ptr, sizeof(cnt), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    std::memcpy(&cnt, m->h_out, sizeof(cnt));
+    if (n_bad) *n_bad = (int64_t)cnt;
+    if (cnt) throw Error(FN_E_DOMAIN, std::to_string(cnt) + " events outside the observable domain");
+  });
+}
+
+fn_status fn_nll(fn_model* m, const double* theta_host, const double* ev, int64_t n, int64_t ld,
+                 double* nll_out, double* grad_host, void* stream) {
+  return guard([&] {
+    if (!m) throw Error(FN_E_INVALID, "model is NULL");
+    hip_check(hipSetDevice(m->device), "hipSetDevice");
+    nll_host(m, theta_host, ev, n, ld, nll_out, grad_host, (hipStream_t)stream);
+  });
+}
+
+fn_status fn_nll_async(fn_model* m, const double* theta_dev, const double* ev, int64_t n, int64_t ld,
+                       double* out_dev, int32_t with_grad, void* stream) {
+  return guard([&] {
+    if (!m || !theta_dev || !out_dev) throw Error(FN_E_INVALID, "NULL argument");
+    check_events_args(m, ev, n, ld);
+    hip_check(hipSetDevice(m->device), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    run_nll(m, nullptr, theta_dev, ev, n, ld, with_grad != 0, m->out(), s);
+    const size_t cnt = (size_t)(with_grad ? 1 + m->P : 1);
+    hip_check(hipMemcpyAsync(out_dev, m->out(), sizeof(double) * cnt, hipMemcpyDeviceToDevice, s),
+              "hipMemcpyAsync");
+  });
+}
+
+fn_status fn_norm(fn_model* m, const double* theta_host, double* norm_host, double* dnorm_host, void* stream) {
+  return guard([&] {
+    if (!m) throw Error(FN_E_INVALID, "model is NULL");
+    hip_check(hipSetDevice(m->device), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    const ParamBlock pb = make_block(m, theta_host);
+    run_nll(m, &pb, nullptr, nullptr, 0, 0, true, m->out(), s);
+    hip_check(hipMemcpyAsync(m->h_out, m->out(), sizeof(double) * (2 + 2 * m->P), hipMemcpyDeviceToHost, s),
+              "hipMemcpyAsync");
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (norm_host) *norm_host = m->h_out[1 + m->P];
+    if (dnorm_host)
+      for (int p = 0; p < m->P; ++p) dnorm_host[p] = m->h_out[2 + m->P + p];
+  });
+}
+
+fn_status fn_eval(fn_model* m, const double* theta_host, const double* ev, int64_t n, int64_t ld, double* p_dev,
+                  void* stream) {
+  return guard([&] {
+    if (!m) throw Error(FN_E_INVALID, "model is NULL");
+    if (n > 0 && !p_dev) throw Error(FN_E_INVALID, "output is NULL");
+    check_events_args(m, ev, n, ld);
+    hip_check(hipSetDevice(m->device), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    const ParamBlock pb = make_block(m, theta_host);
+    run_nll(m, &pb, nullptr, nullptr, 0, 0, false, m->out(), s);
+    if (m->kind == kKindMix1d) mix1d_launch_eval(m->mix, m->table_mix(), ev, n, p_dev, s);
+    else dalitz_launch_eval(m->dal, m->table_dal(), ev, ld, n, m->out() + 1 + m->P, p_dev, s);
+    hip_check(hipGetLastError(), "kernel launch");
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+  });
+}
+
+}  // extern "C"
+
+fn_model::~fn_model() {
+  if (h_out) (void)hipHostFree(h_out);
+}

@@ -18,3 +18,13 @@ def pytest_configure(config):
 import torch  # noqa: E402
 
 torch.set_default_dtype(torch.float64)
+
+
+def pytest_collection_modifyitems(config, items):
+    """GPU tests are skipped (not failed) where no GPU is visible."""
+    if torch.cuda.is_available():
+        return
+    skip = pytest.mark.skip(reason="no GPU visible")
+    for it in items:
+        if "gpu" in it.keywords:
+            it.add_marker(skip)

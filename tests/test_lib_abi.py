@@ -1,0 +1,65 @@
+"""The C-ABI library loads and exports every symbol its header declares (CPU;
+no compute calls)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h")]
+
+
+def declared_functions():
+    names = set()
+    for h in HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b(fn_\w+)\s*\(", text, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for must in ["fn_nll", "fn_nll_async", "fn_model_create", "fn_fit", "fn_norm", "fn_eval", "fn_events_check"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1710_08826_amd import _lib
+    lib = _lib.load()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_python_prototypes_cover_header():
+    from paper_1710_08826_amd import _lib
+    assert set(declared_functions()) <= set(_lib.PROTOTYPES)
+
+
+def test_version_and_error_string():
+    from paper_1710_08826_amd import _lib
+    lib = _lib.load()
+    assert lib.fn_version() >= 10000
+    assert isinstance(lib.fn_last_error(), bytes)
+
+
+def test_null_arguments_rejected_without_gpu():
+    """Argument checks run before any device call."""
+    from paper_1710_08826_amd import _lib
+    lib = _lib.load()
+    assert lib.fn_model_create(None, b"{}", None) == _lib.FN_E_INVALID
+    assert lib.fn_nll(None, None, None, 0, 0, None, None, None) == _lib.FN_E_INVALID
+    assert lib.fn_model_info(None, None, None, None) == _lib.FN_E_INVALID
+    assert b"NULL" in lib.fn_last_error()
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    from paper_1710_08826_amd import _lib
+    with pytest.raises(RuntimeError):
+        _lib._lib, saved = None, _lib._lib
+        try:
+            _lib.load(str(tmp_path / "nope.so"))
+        finally:
+            _lib._lib = saved
