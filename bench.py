@@ -1,0 +1,305 @@
+"""Benchmark: event-NLL(+gradient) evaluations per second on one MI355X.
+
+Workload (one step = one pass of the hot path): the three-body Dalitz model
+with eight resonances, 1M synthetic events (s12, s13) in HBM, sixteen free
+coefficient parameters; a step is prologue -> per-event evaluation with the
+adjoint gradient -> deterministic level-2 reduction -> normalization from the
+cached grid matrix -> NLL and gradient in device memory.  `value` is
+events x steps / second.
+
+Also reported (same process): the dominant kernel's duration from HIP events
+on its stream and its roofline, the plain finite-difference gradient path,
+the other model configurations, single-fit wall times with and without the
+adjoint, and the CPU oracle on a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector, FMA counted as 2
+PEAK_HBM_GBS = 8000.0
+
+# HBM bytes per launch of the config-1 event kernel from the FETCH_SIZE and
+# WRITE_SIZE counter runs (profiles/dalitz_pass_events_grad_1M.md), valid for
+# the kernel sources with this hash; reported as null once they change.
+TRAFFIC_BYTES = 1.644e7
+TRAFFIC_SOURCES = ["paper_1710_08826_amd/csrc/dalitz3.hip", "paper_1710_08826_amd/csrc/fastmath.hpp",
+                   "paper_1710_08826_amd/csrc/device_common.hpp", "paper_1710_08826_amd/csrc/model.hpp"]
+TRAFFIC_HASH = "fc9ca12149e4050f"
+
+
+def measured_traffic():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return TRAFFIC_BYTES if h.hexdigest()[:16] == TRAFFIC_HASH else None
+
+# FP64 FLOPs of the correctly rounded gfx950 sequences of the ROCm device
+# library (FMA = 2, other FP64 arithmetic = 1, compares 0), counted from the
+# ISA of this toolchain: the price of each elementary function in the
+# algorithmic FLOP count (the kernels use cheaper Newton-refined forms).
+W_SQRT, W_RSQRT, W_DIV, W_LOG, W_EXP = 19, 9, 17, 85, 30
+
+
+def dalitz_flops_per_event(desc: dict, grad: int) -> int:
+    """Algorithmic FP64 FLOPs per event of the Dalitz NLL (grad: 0 none,
+    1 coefficients, 2 coefficients + masses and widths), counted from the
+    formula as evaluated: per-pair kinematics shared by the pair's
+    resonances, one complex reciprocal per resonance, one log per event."""
+    pairs = {}
+    for r in desc["resonances"]:
+        pairs.setdefault(r["pair"], set()).add(int(r["L"]))
+    K = len(desc["resonances"])
+    f = 2                                          # s23
+    for Ls in pairs.values():
+        f += 11 + W_RSQRT + W_SQRT                 # 1/sqrt s, 1/s, lambda_q, lambda_p, q^2, q/sqrt s
+        if 1 in Ls or 2 in Ls:
+            f += 7                                 # p^2, z_q, z_p, Z1
+        if 1 in Ls:
+            f += 6 + W_DIV + W_RSQRT               # G1 = (q/sqrt s) q^2/(1+z_q), H1 = Z1/sqrt(..)
+        if 2 in Ls:
+            f += 17 + W_DIV + W_RSQRT              # polynomials, G2, Z2, H2
+    f += K * (16 + W_DIV)                          # T = (a + i b)/(a^2 + b^2), A, coherent sum
+    f += 4 + W_LOG                                 # |S|^2, log, accumulate
+    if grad >= 1:
+        f += 4 + W_DIV + 6 * K                     # -1/P~, 2 Re(conj(S) A) per coefficient
+    if grad >= 2:
+        f += 31 * K                                # mass and width derivatives
+    return f
+
+
+def mix1d_flops_per_event(grad: bool) -> int:
+    """Config-0 mixture (Gaussian + exponential): 2 exp, 1 log, ~14 others;
+    the gradient adds one division and ~22 FLOPs."""
+    f = 2 * W_EXP + W_LOG + 14
+    if grad:
+        f += W_DIV + 22
+    return f
+
+
+def gpu_info():
+    import torch
+    p = torch.cuda.get_device_properties(0)
+    return {"name": p.name, "cus": p.multi_processor_count, "arch": getattr(p, "gcnArchName", "")}
+
+
+def time_async(model, theta_dev, ev, out, steps, warmup, with_grad=True, alt=None):
+    """Wall time of `steps` asynchronous NLL(+grad) calls (device theta)."""
+    import torch
+    for i in range(warmup):
+        model.nll_async(theta_dev if (alt is None or i % 2 == 0) else alt, ev, out, with_grad)
+    torch.cuda.synchronize()
+    model.kernel_time()  # drop warm-up timings
+    model.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        model.nll_async(theta_dev if (alt is None or i % 2 == 0) else alt, ev, out, with_grad)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    model.set_timing(False)
+    kms, launches = model.kernel_time()
+    return t1 - t0, kms / max(launches, 1)
+
+
+def cpu_baseline(events: np.ndarray, desc: dict, theta, budget_s: float = 12.0):
+    """The CPU oracle (NLL + autograd gradient, grid normalization each call)
+    on a bounded sample, repeated until about budget_s seconds."""
+    import torch
+    from oracle import dalitz3 as OD
+    cells = OD.Dalitz(desc).grid_cells()
+    calls = 0
+    t0 = time.perf_counter()
+    while True:
+        OD.nll_grad(theta, events, desc, cells)
+        calls += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": events.shape[1] * calls / dt, "unit": "events/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"{events.shape[1]} events of the same Dalitz workload, NLL + autograd gradient "
+                      f"with the 1024x1024 grid normalization recomputed per call, {calls} calls in {dt:.1f} s"}
+
+
+def pmc_probe(steps: int):
+    """Workload for hardware-counter runs: a plain 256 MiB copy (its counter
+    reading calibrates bytes per counter unit), then config-1 NLL+gradient
+    steps."""
+    import torch
+    import synth
+    from paper_1710_08826_amd import Model
+    src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")  # 256 MiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ev = torch.from_numpy(synth.dalitz_events(1_000_000, seed=synth.BASE_SEED)).cuda()
+    m = Model(synth.dalitz_desc())
+    th = torch.from_numpy(synth.dalitz_truth()).cuda()
+    out = torch.empty(1 + m.n_params, dtype=torch.float64, device="cuda")
+    for _ in range(steps):
+        m.nll_async(th, ev, out, True)
+    torch.cuda.synchronize()
+    print(json.dumps({"pmc_probe": True, "copy_bytes": 2 * src.numel() * 8, "steps": steps,
+                      "nll": float(out[0])}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--quick", action="store_true", help="skip the side measurements and the CPU baseline")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="for counter runs: one 256 MiB device copy (calibration) then --steps "
+                         "config-1 steps, nothing printed but a summary line")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+    if args.pmc_probe:
+        pmc_probe(args.steps)
+        return
+
+    import torch
+    import synth
+    from paper_1710_08826_amd import Model
+
+    dev = "cuda"
+    n1 = 1_000_000
+    desc1 = synth.dalitz_desc()
+    th1 = synth.dalitz_truth()
+    th1b = th1 * (1.0 + 1e-3 * np.cos(np.arange(th1.size)))
+    ev1_np = synth.dalitz_events(n1, seed=synth.BASE_SEED)
+    ev1 = torch.from_numpy(ev1_np).to(dev)
+    m1 = Model(desc1)
+    P1 = m1.n_params
+    tdev = torch.from_numpy(th1).to(dev)
+    tdev_b = torch.from_numpy(th1b).to(dev)
+    out = torch.empty(1 + P1, dtype=torch.float64, device=dev)
+    print(f"[bench] config1 dalitz: {n1} events, P={P1}, warmup {args.warmup}, steps {args.steps}",
+          file=sys.stderr, flush=True)
+    wall, kern_ms = time_async(m1, tdev, ev1, out, args.steps, args.warmup, True, alt=tdev_b)
+    ms_step = 1e3 * wall / args.steps
+    value = n1 * args.steps / wall
+    flops_ev = dalitz_flops_per_event(desc1, 1)
+    achieved = flops_ev * n1 / (kern_ms * 1e-3) / 1e12
+    extra = {}
+    print(f"[bench] {value:.4g} events/s, step {ms_step:.4f} ms, kernel {kern_ms * 1e3:.2f} us",
+          file=sys.stderr, flush=True)
+
+    if not args.quick:
+        # NLL-only evaluations and the plain finite-difference gradient path:
+        # one FD gradient = 2P+1 NLL-only evaluations, one call at a time
+        w0, k0 = time_async(m1, tdev, ev1, out, args.steps, 5, False)
+        nll_only_rate = n1 * args.steps / w0
+        nfd = max(10, args.steps // (2 * P1 + 1))
+        theta_host = th1.copy()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(nfd):
+            m1.nll(theta_host, ev1)
+            for p in range(P1):
+                h = 1e-6 * max(abs(theta_host[p]), 1.0)
+                tp = theta_host.copy(); tp[p] += h
+                tm = theta_host.copy(); tm[p] -= h
+                m1.nll(tp, ev1)
+                m1.nll(tm, ev1)
+        fd_dt = (time.perf_counter() - t0) / nfd
+        extra["config1_nll_only_events_per_s"] = nll_only_rate
+        extra["config1_plain_fd_grad_events_per_s"] = n1 / fd_dt
+        extra["config1_adjoint_vs_plain_fd"] = value / (n1 / fd_dt)
+        extra["config1_nll_only_kernel_us"] = k0 * 1e3
+        print(f"[bench] plain FD gradient {n1 / fd_dt:.4g} events/s", file=sys.stderr, flush=True)
+
+        # config 3: masses and widths free (32 parameters), 4M events, full grid every call
+        desc3 = synth.dalitz_desc(free_lineshapes=True)
+        th3 = synth.dalitz_truth(free_lineshapes=True)
+        ev3 = torch.from_numpy(synth.dalitz_events(4_000_000, seed=synth.BASE_SEED + 3)).to(dev)
+        m3 = Model(desc3)
+        t3 = torch.from_numpy(th3).to(dev)
+        o3 = torch.empty(1 + m3.n_params, dtype=torch.float64, device=dev)
+        s3 = max(10, args.steps // 10)
+        w3, k3 = time_async(m3, t3, ev3, o3, s3, 3, True)
+        extra["config3_events_per_s"] = 4_000_000 * s3 / w3
+        extra["config3_ms_per_step"] = 1e3 * w3 / s3
+        extra["config3_event_kernel_us"] = k3 * 1e3
+        extra["config3_event_kernel_tflops"] = dalitz_flops_per_event(desc3, 2) * 4e6 / (k3 * 1e-3) / 1e12
+        del ev3
+        print(f"[bench] config3 {extra['config3_events_per_s']:.4g} events/s", file=sys.stderr, flush=True)
+
+        # config 0: 1-D mixture, 100k events
+        d0 = synth.mix1d_desc()
+        x0 = torch.from_numpy(synth.mix1d_events(100_000)[None, :]).to(dev)
+        m0 = Model(d0)
+        t0d = torch.from_numpy(np.array(synth.CONFIG0_TRUTH)).to(dev)
+        o0 = torch.empty(5, dtype=torch.float64, device=dev)
+        w00, k00 = time_async(m0, t0d, x0, o0, args.steps, 10, True)
+        extra["config0_events_per_s"] = 100_000 * args.steps / w00
+        extra["config0_ms_per_step"] = 1e3 * w00 / args.steps
+        extra["config0_event_kernel_us"] = k00 * 1e3
+        # single fits: adjoint vs finite-difference gradient (config 0, 100k events)
+        start = np.array(synth.CONFIG0_TRUTH) * 1.1
+        for mode in ("adjoint", "fd"):
+            m0.fit(start, x0, grad_mode=mode)
+            t0 = time.perf_counter()
+            reps = 5
+            for _ in range(reps):
+                r = m0.fit(start, x0, grad_mode=mode)
+            dt = (time.perf_counter() - t0) / reps
+            extra[f"config0_fit_{mode}_ms"] = dt * 1e3
+            extra[f"config0_fit_{mode}_calls"] = r.n_calls
+        extra["config0_fit_speedup_adjoint_vs_fd"] = extra["config0_fit_fd_ms"] / extra["config0_fit_adjoint_ms"]
+        print(f"[bench] config0 fits: adjoint {extra['config0_fit_adjoint_ms']:.2f} ms, "
+              f"fd {extra['config0_fit_fd_ms']:.2f} ms", file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.quick and not args.no_cpu:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(ev1_np[:, :100_000], desc1, th1)
+
+    line = {
+        "metric": "event-NLL(+grad) evals/sec vs plain; toy fits/sec with p50/p99 latency",
+        "value": value,
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "dalitz3 8-resonance amplitude fit, NLL + adjoint gradient",
+                   "events": n1, "params": P1, "grid": [1024, 1024], "normalization": "cached grid matrix",
+                   "chunk": m1.chunk, "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(),
+                     "kernel": "dalitz_pass<events, coefficient gradient>",
+                     "kernel_us": kern_ms * 1e3, "flops_per_event": flops_ev,
+                     "hbm_gbs": 16 * n1 / (kern_ms * 1e-3) / 1e9},
+        "cpu_baseline": cpu,
+        "extra": extra,
+        "gpu": gpu_info(),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -140,6 +140,14 @@ fn_status fn_norm(fn_model* m, const double* theta_host, double* norm_host,
 fn_status fn_eval(fn_model* m, const double* theta_host, const double* ev, int64_t n,
                   int64_t ld, double* p_dev, void* stream);
 
+/* Kernel timing (measurement support, not on the result path).  With timing
+ * enabled, every per-event evaluation launch of the model is bracketed by HIP
+ * events recorded on the launch stream.  fn_model_kernel_time waits for the
+ * recorded events, returns the summed duration in milliseconds and the launch
+ * count since the last query, and resets both. */
+fn_status fn_model_timing(fn_model* m, int32_t enable);
+fn_status fn_model_kernel_time(fn_model* m, double* total_ms, int64_t* launches);
+
 /* ---------------------------------------------------------------- fitting */
 /* One fit by quasi-Newton minimization (BFGS with a line search satisfying
  * the strong Wolfe conditions) of the NLL on the device, replacing the

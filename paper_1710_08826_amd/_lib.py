@@ -45,6 +45,8 @@ PROTOTYPES = {
     "fn_nll_async": (i32, [vp, vp, vp, i64, i64, vp, i32, vp]),
     "fn_norm": (i32, [vp, dp, dp, dp, vp]),
     "fn_eval": (i32, [vp, dp, vp, i64, i64, vp, vp]),
+    "fn_model_timing": (i32, [vp, i32]),
+    "fn_model_kernel_time": (i32, [vp, dp, C.POINTER(i64)]),
     "fn_fit": (i32, [vp, dp, C.POINTER(i32), vp, i64, i64, i32, C.c_double, i32, dp, dp, dp,
                      C.POINTER(i32), C.POINTER(i32), vp]),
 }

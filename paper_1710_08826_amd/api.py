@@ -135,6 +135,17 @@ class Model:
                                 _stream_ptr(stream)))
         return p
 
+    def set_timing(self, enable: bool):
+        """Bracket every per-event kernel launch with HIP events."""
+        check(self._lib.fn_model_timing(self._h, 1 if enable else 0))
+
+    def kernel_time(self):
+        """(total ms, launches) of timed per-event kernels since the last query."""
+        ms = C.c_double()
+        cnt = C.c_int64()
+        check(self._lib.fn_model_kernel_time(self._h, C.byref(ms), C.byref(cnt)))
+        return ms.value, cnt.value
+
     def check_events(self, events: torch.Tensor, stream=None) -> int:
         """Number of events outside the observable domain (0 if all inside)."""
         evp, n, ld = _events(events, self.n_obs)

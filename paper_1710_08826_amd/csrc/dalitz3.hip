@@ -31,6 +31,7 @@
 #include <cmath>
 
 #include "device_common.hpp"
+#include "fastmath.hpp"
 #include "kernels.hpp"
 
 namespace fn {
@@ -99,32 +100,36 @@ struct PairTerms {
   double H[3];      // F_L(q r) F_L(p r_D) Z_L
 };
 
-__device__ inline void pair_terms(const DalitzChan& ch, double s_ab, double s_ac, double s_bc, double r2,
-                                  double rD2, PairTerms& o) {
-  const double is = 1.0 / s_ab;
-  const double irs = sqrt(is);
+// G and H of one pair from (s_AB, s_AC, s_BC):
+//   q/sqrt(s) = sqrt(lambda_q) / (2 s),  q^2 = lambda_q / (4 s),  p^2 = lambda_p / (4 s)
+//   G_1 = (q/sqrt s) q^2 / (1 + z_q),          H_1 = Z_1 / sqrt((1 + z_q)(1 + z_p))
+//   G_2 = (q/sqrt s) q^4 / (z_q^2 + 3 z_q + 9), H_2 = Z_2 / sqrt(poly(z_q) poly(z_p))
+__device__ __forceinline__ void pair_terms(const DalitzChan& ch, double s_ab, double s_ac, double s_bc, double r2,
+                                           double rD2, PairTerms& o) {
+  const double irs = rsqrt_nr(s_ab);
+  const double is = irs * irs;
   const double lq = fmax((s_ab - ch.sum2) * (s_ab - ch.dif2), 0.0);
   const double lp = fmax((s_ab - ch.Psum2) * (s_ab - ch.Pdif2), 0.0);
   const double q2 = 0.25 * lq * is;
-  const double p2 = 0.25 * lp * is;
-  const double qirs = sqrt(q2) * irs;
+  const double qirs = 0.5 * sqrt_nr(lq) * is;
   o.s = s_ab;
   o.G[0] = qirs;
   o.H[0] = 1.0;
   o.G[1] = o.G[2] = o.H[1] = o.H[2] = 0.0;
   if (ch.useL[1] | ch.useL[2]) {
+    const double p2 = 0.25 * lp * is;
     const double zq = q2 * r2, zp = p2 * rD2;
-    const double z1 = s_ac - s_bc + ch.zc * is;
+    const double z1 = __builtin_fma(ch.zc, is, s_ac - s_bc);
     if (ch.useL[1]) {
-      const double b1q = 1.0 / (1.0 + zq), b1p = 1.0 / (1.0 + zp);
-      o.G[1] = qirs * q2 * b1q;
-      o.H[1] = z1 * sqrt(b1q * b1p);
+      const double uq = 1.0 + zq, up = 1.0 + zp;
+      o.G[1] = qirs * q2 * rcp_nr(uq);
+      o.H[1] = z1 * rsqrt_nr(uq * up);
     }
     if (ch.useL[2]) {
-      const double b2q = 1.0 / (zq * zq + 3.0 * zq + 9.0), b2p = 1.0 / (zp * zp + 3.0 * zp + 9.0);
-      o.G[2] = qirs * q2 * q2 * b2q;
+      const double vq = __builtin_fma(zq, zq + 3.0, 9.0), vp = __builtin_fma(zp, zp + 3.0, 9.0);
+      o.G[2] = qirs * q2 * q2 * rcp_nr(vq);
       const double z2 = z1 * z1 - (lp * is) * (lq * is) * (1.0 / 3.0);
-      o.H[2] = z2 * sqrt(b2q * b2p);
+      o.H[2] = z2 * rsqrt_nr(vq * vp);
     }
   }
 }
@@ -148,6 +153,8 @@ __device__ inline bool dalitz_inside(const DalitzConst& dc, double s12, double s
 
 // ------------------------------------------------------------ chunk routine
 // GRAD: 0 none, 1 coefficients only, 2 coefficients + masses and widths.
+// Pairs are visited one at a time (only one pair's G/H are live) and each
+// resonance of the pair adds c_k A_k to the coherent sum.
 template <int MODE, int GRAD, int KMAX>
 __device__ inline void dalitz_chunk(const DalitzConst& dc, const DalitzTable* __restrict__ tab,
                                     const double* __restrict__ ev, int64_t ld, int64_t n, int64_t chunk_idx,
@@ -174,48 +181,52 @@ __device__ inline void dalitz_chunk(const DalitzConst& dc, const DalitzTable* __
       if (!dalitz_inside(dc, s12, s13)) continue;
     }
     const double s23 = dc.msum - s12 - s13;
-    PairTerms pt[3];
-    // pair "12": (A,B,C) = (1,2,3); "13": (1,3,2); "23": (2,3,1)
-    pair_terms(dc.ch[0], s12, s13, s23, dc.r2, dc.rD2, pt[0]);
-    pair_terms(dc.ch[1], s13, s12, s23, dc.r2, dc.rD2, pt[1]);
-    pair_terms(dc.ch[2], s23, s12, s13, dc.r2, dc.rD2, pt[2]);
     double Are[KMAX], Aim[KMAX], Tre[KMAX], Tim[KMAX], Gk[KMAX];
     double Sre = 0.0, Sim = 0.0;
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
-      if (k < dc.K) {
-        const int c = dc.chan[k], L = dc.L[k];
-        const double* rk = r + k * kDalFields;
-        double s, G, H;
-        if (c == 0) { s = pt[0].s; G = pt[0].G[0]; H = pt[0].H[0]; if (L == 1) { G = pt[0].G[1]; H = pt[0].H[1]; } if (L == 2) { G = pt[0].G[2]; H = pt[0].H[2]; } }
-        else if (c == 1) { s = pt[1].s; G = pt[1].G[0]; H = pt[1].H[0]; if (L == 1) { G = pt[1].G[1]; H = pt[1].H[1]; } if (L == 2) { G = pt[1].G[2]; H = pt[1].H[2]; } }
-        else { s = pt[2].s; G = pt[2].G[0]; H = pt[2].H[0]; if (L == 1) { G = pt[2].G[1]; H = pt[2].H[1]; } if (L == 2) { G = pt[2].G[2]; H = pt[2].H[2]; } }
-        const double a = rk[dM0SQ] - s;
-        const double b = rk[dKW] * G;
-        const double d = 1.0 / (a * a + b * b);
-        const double tr = a * d, ti = b * d;
-        const double kh = rk[dKA] * H;
-        const double ar = kh * tr, ai = kh * ti;
-        if (KEEP_A) { Are[k] = ar; Aim[k] = ai; }
-        if (KEEP_T) { Tre[k] = tr; Tim[k] = ti; Gk[k] = G; }
-        if (MODE != kMRows) {
-          const double cr = rk[dCRE], ci = rk[dCIM];
-          Sre += cr * ar - ci * ai;
-          Sim += cr * ai + ci * ar;
+    for (int c = 0; c < 3; ++c) {
+      const DalitzChan& ch = dc.ch[c];
+      if (!(ch.useL[0] | ch.useL[1] | ch.useL[2])) continue;
+      // pair "12": (A,B,C) = (1,2,3); "13": (1,3,2); "23": (2,3,1)
+      const double s_ab = c == 0 ? s12 : (c == 1 ? s13 : s23);
+      const double s_ac = c == 0 ? s13 : s12;
+      const double s_bc = c == 2 ? s13 : s23;
+      PairTerms pt;
+      pair_terms(ch, s_ab, s_ac, s_bc, dc.r2, dc.rD2, pt);
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) {
+        if (k < dc.K && dc.chan[k] == c) {
+          const int L = dc.L[k];
+          const double* rk = r + k * kDalFields;
+          const double G = L == 0 ? pt.G[0] : (L == 1 ? pt.G[1] : pt.G[2]);
+          const double H = L == 0 ? pt.H[0] : (L == 1 ? pt.H[1] : pt.H[2]);
+          const double a = rk[dM0SQ] - pt.s;
+          const double b = rk[dKW] * G;
+          const double d = rcp_nr(__builtin_fma(a, a, b * b));
+          const double tr = a * d, ti = b * d;
+          const double kh = rk[dKA] * H;
+          const double ar = kh * tr, ai = kh * ti;
+          if (KEEP_A) { Are[k] = ar; Aim[k] = ai; }
+          if (KEEP_T) { Tre[k] = tr; Tim[k] = ti; Gk[k] = G; }
+          if (MODE != kMRows) {
+            const double cr = rk[dCRE], ci = rk[dCIM];
+            Sre += cr * ar - ci * ai;
+            Sim += cr * ai + ci * ar;
+          }
         }
       }
     }
     if (MODE == kMRows) {
 #pragma unroll
       for (int ib = 0; ib < kMRowBlock; ++ib) {
+        // A_i for i = i0 + ib, selected from registers with uniform guards
+        double xr = 0.0, xi = 0.0;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+          if (k == i0 + ib) { xr = Are[k]; xi = Aim[k]; }
 #pragma unroll
         for (int j = 0; j < KMAX; ++j) {
           if (j < dc.K) {
-            // A_i conj(A_j) for i = i0 + ib (uniform selection from registers)
-            double xr = 0.0, xi = 0.0;
-#pragma unroll
-            for (int k = 0; k < KMAX; ++k)
-              if (k == i0 + ib) { xr = Are[k]; xi = Aim[k]; }
             acc[2 * (ib * KMAX + j)] += xr * Are[j] + xi * Aim[j];
             acc[2 * (ib * KMAX + j) + 1] += xi * Are[j] - xr * Aim[j];
           }
@@ -223,23 +234,24 @@ __device__ inline void dalitz_chunk(const DalitzConst& dc, const DalitzTable* __
       }
       continue;
     }
-    const double Pt = Sre * Sre + Sim * Sim;
+    const double Pt = __builtin_fma(Sre, Sre, Sim * Sim);
     double w;  // multiplies dP~/dtheta
     if (MODE == kEvents) {
-      acc[0] -= log(Pt);
-      w = -1.0 / Pt;
+      acc[0] -= log_fast(Pt);
+      w = -rcp_nr(Pt);
     } else {
       acc[0] += Pt;
       w = 1.0;
     }
     if (GRAD >= 1) {
       const double w2 = 2.0 * w;
+      const double ur = w2 * Sre, ui = w2 * Sim;
 #pragma unroll
       for (int k = 0; k < KMAX; ++k) {
         if (k < dc.K) {
           // dP~/dRe c = 2 Re(conj(S) A), dP~/dIm c = 2 (Sim Are - Sre Aim)
-          acc[1 + 2 * k] += w2 * (Sre * Are[k] + Sim * Aim[k]);
-          acc[2 + 2 * k] += w2 * (Sim * Are[k] - Sre * Aim[k]);
+          acc[1 + 2 * k] += ur * Are[k] + ui * Aim[k];
+          acc[2 + 2 * k] += ui * Are[k] - ur * Aim[k];
         }
       }
     }
@@ -269,8 +281,112 @@ __device__ inline void dalitz_chunk(const DalitzConst& dc, const DalitzTable* __
   block_sum_row<NV>(acc, lds, out_row);
 }
 
+// FN_DALITZ_WAVES > 0 asks the register allocator for that many waves per
+// SIMD (a tuning knob; 0 leaves the choice to the compiler).
+#ifndef FN_DALITZ_WAVES
+#define FN_DALITZ_WAVES 0
+#endif
+#if FN_DALITZ_WAVES > 0
+#define FN_DALITZ_WAVES_ATTR __attribute__((amdgpu_waves_per_eu(FN_DALITZ_WAVES, 8)))
+#else
+#define FN_DALITZ_WAVES_ATTR
+#endif
+
+// ------------------------------------------------------------- finalize
+// Arguments of the level-2 + NLL assembly step.
+struct DalFinal {
+  const double* npart;       // grid rows (free lineshapes) or nullptr (cached M)
+  int64_t n_rows;
+  int n_nv;
+  const double* Mc;          // cached M (K x K complex) when npart == nullptr
+  double n_events;
+  int with_grad;
+  double* out;               // [NLL, grad(P), I, dI(P)]
+  double* out_user;          // optional [NLL, grad(P)]
+};
+
+struct DalFinalLds {
+  double scratch[kBlock];
+  double res[kBlock];
+  double nres[kBlock];
+  double cre[kDalMaxRes], cim[kDalMaxRes], ipart[kDalMaxRes];
+  double dI[4 * kDalMaxRes];
+  double I;
+};
+
+// Level-2 over the event rows and the normalization (grid rows or cached M),
+// then NLL = -sum ln P~ + N ln I and its gradient, one thread per entry.
+__device__ void dalitz_finalize_body(const DalitzConst& dc, const DalitzTable* __restrict__ tab,
+                                     const double* __restrict__ evpart, int64_t ev_rows, int ev_nv, int kmax,
+                                     const DalFinal& f, DalFinalLds& L) {
+  const int K = dc.K;
+  const int P = dc.free_ls ? 4 * K : 2 * K;
+  const int t = threadIdx.x;
+  sum_rows(evpart, ev_rows, ev_nv, L.scratch, L.res);
+  if (f.npart) sum_rows(f.npart, f.n_rows, f.n_nv, L.scratch, L.nres);
+  if (t < K) {
+    L.cre[t] = tab->r[t][dCRE];
+    L.cim[t] = tab->r[t][dCIM];
+  }
+  if (t < P) L.dI[t] = 0.0;
+  __syncthreads();
+  if (f.npart) {
+    if (t < K && f.n_nv > 1) {
+      L.dI[2 * t] = dc.dA * L.nres[1 + 2 * t];
+      L.dI[2 * t + 1] = dc.dA * L.nres[2 + 2 * t];
+      if (dc.free_ls && f.n_nv > 1 + 2 * kmax) {
+        L.dI[2 * K + 2 * t] = dc.dA * L.nres[1 + 2 * kmax + 2 * t];
+        L.dI[2 * K + 2 * t + 1] = dc.dA * L.nres[2 + 2 * kmax + 2 * t];
+      }
+    }
+    if (t == 0) L.I = dc.dA * L.nres[0];
+  } else if (t < K) {
+    // I = sum_k Re(c_k X_k), X_k = sum_j M_kj conj(c_j);
+    // dI/dRe c_k = 2 Re X_k, dI/dIm c_k = -2 Im X_k
+    double xr = 0.0, xi = 0.0;
+    for (int j = 0; j < K; ++j) {
+      const double mr = f.Mc[2 * (t * K + j)], mi = f.Mc[2 * (t * K + j) + 1];
+      xr += mr * L.cre[j] + mi * L.cim[j];
+      xi += mi * L.cre[j] - mr * L.cim[j];
+    }
+    L.ipart[t] = L.cre[t] * xr - L.cim[t] * xi;
+    L.dI[2 * t] = 2.0 * xr;
+    L.dI[2 * t + 1] = -2.0 * xi;
+  }
+  __syncthreads();
+  if (!f.npart && t == 0) {
+    double I = 0.0;
+    for (int k = 0; k < K; ++k) I += L.ipart[k];
+    L.I = I;
+  }
+  __syncthreads();
+  const double I = L.I;
+  const bool okI = tab->valid != 0.0 && I > 0.0 && isfinite(I);
+  if (t == 0) {
+    const double v = okI ? L.res[0] + f.n_events * log(I) : INFINITY;
+    f.out[0] = v;
+    f.out[1 + P] = I;
+    if (f.out_user) f.out_user[0] = v;
+  }
+  if (t < P) {
+    f.out[2 + P + t] = L.dI[t];
+    if (f.with_grad) {
+      // event slot of parameter t: coefficients at 1 + t, lineshapes after 2 kmax
+      const int slot = t < 2 * K ? 1 + t : 1 + 2 * kmax + (t - 2 * K);
+      const double e = slot < ev_nv ? L.res[slot] : 0.0;
+      const double g = okI ? e + f.n_events * L.dI[t] / I : NAN;
+      f.out[1 + t] = g;
+      if (f.out_user) f.out_user[1 + t] = g;
+    }
+  }
+}
+
+// Evaluation pass: one workgroup per chunk, one row of partial sums each.
+// (Finishing the level-2 sum inside the last workgroup to retire, behind a
+// device-scope fence per workgroup, measured 2.5x slower on MI355X than the
+// separate level-2 launch below, so the two steps stay separate kernels.)
 template <int MODE, int GRAD, int KMAX>
-__global__ __launch_bounds__(kBlock) void dalitz_pass(DalitzConst dc, const DalitzTable* __restrict__ tab,
+__global__ __launch_bounds__(kBlock) FN_DALITZ_WAVES_ATTR void dalitz_pass(DalitzConst dc, const DalitzTable* __restrict__ tab,
                                                       const double* __restrict__ ev, int64_t ld, int64_t n,
                                                       int chunk, int i0, double* __restrict__ part) {
   constexpr int NV = dal_nv(MODE, GRAD, KMAX);
@@ -279,74 +395,12 @@ __global__ __launch_bounds__(kBlock) void dalitz_pass(DalitzConst dc, const Dali
                                  lds);
 }
 
-// ------------------------------------------------------------- finalize
-// Level-2 over the event rows and the normalization (grid rows or cached M),
-// then NLL = -sum ln P~ + N ln I and its gradient.  out: [NLL, grad(P), I, dI(P)].
-__global__ __launch_bounds__(kBlock) void dalitz_finalize(
-    DalitzConst dc, const DalitzTable* __restrict__ tab, const double* __restrict__ evpart, int64_t ev_rows,
-    int ev_nv, const double* __restrict__ npart, int64_t n_rows, int n_nv, const double* __restrict__ Mc,
-    int kmax, double n_events, int with_grad, double* __restrict__ out) {
-  __shared__ double scratch[kBlock];
-  __shared__ double res[kBlock];
-  __shared__ double nres[kBlock];
-  const int K = dc.K;
-  const int P = dc.free_ls ? 4 * K : 2 * K;
-  sum_rows(evpart, ev_rows, ev_nv, scratch, res);
-  if (npart) sum_rows(npart, n_rows, n_nv, scratch, nres);
-  if (threadIdx.x != 0) return;
-  const bool ok = tab->valid != 0.0;
-  double I;
-  double dI[4 * kDalMaxRes];
-  for (int p = 0; p < P; ++p) dI[p] = 0.0;
-  if (npart) {
-    I = dc.dA * nres[0];
-    if (n_nv > 1) {
-      for (int k = 0; k < K; ++k) {
-        dI[2 * k] = dc.dA * nres[1 + 2 * k];
-        dI[2 * k + 1] = dc.dA * nres[2 + 2 * k];
-        if (dc.free_ls && n_nv > 1 + 2 * kmax) {
-          dI[2 * K + 2 * k] = dc.dA * nres[1 + 2 * kmax + 2 * k];
-          dI[2 * K + 2 * k + 1] = dc.dA * nres[2 + 2 * kmax + 2 * k];
-        }
-      }
-    }
-  } else {
-    // I = sum_ij c_i conj(c_j) M_ij;  dI/dRe c_k = 2 Re X_k, dI/dIm c_k = -2 Im X_k,
-    // X_k = sum_j M_kj conj(c_j)
-    I = 0.0;
-    for (int k = 0; k < K; ++k) {
-      const double ckr = tab->r[k][dCRE], cki = tab->r[k][dCIM];
-      double xr = 0.0, xi = 0.0;
-      for (int j = 0; j < K; ++j) {
-        const double mr = Mc[2 * (k * K + j)], mi = Mc[2 * (k * K + j) + 1];
-        const double cjr = tab->r[j][dCRE], cji = -tab->r[j][dCIM];
-        xr += mr * cjr - mi * cji;
-        xi += mr * cji + mi * cjr;
-      }
-      // c_k X_k summed over k gives I
-      I += ckr * xr - cki * xi;
-      dI[2 * k] = 2.0 * xr;
-      dI[2 * k + 1] = -2.0 * xi;
-    }
-  }
-  const bool okI = ok && I > 0.0 && isfinite(I);
-  out[0] = okI ? res[0] + n_events * log(I) : INFINITY;
-  if (with_grad) {
-    for (int k = 0; k < K; ++k) {
-      out[1 + 2 * k] = res[1 + 2 * k] + n_events * dI[2 * k] / I;
-      out[2 + 2 * k] = res[2 + 2 * k] + n_events * dI[2 * k + 1] / I;
-      if (dc.free_ls) {
-        const double e0 = ev_nv > 1 + 2 * kmax ? res[1 + 2 * kmax + 2 * k] : 0.0;
-        const double e1 = ev_nv > 1 + 2 * kmax ? res[2 + 2 * kmax + 2 * k] : 0.0;
-        out[1 + 2 * K + 2 * k] = e0 + n_events * dI[2 * K + 2 * k] / I;
-        out[2 + 2 * K + 2 * k] = e1 + n_events * dI[2 * K + 2 * k + 1] / I;
-      }
-    }
-    if (!okI)
-      for (int p = 0; p < P; ++p) out[1 + p] = NAN;
-  }
-  out[1 + P] = I;
-  for (int p = 0; p < P; ++p) out[2 + P + p] = dI[p];
+// Level-2 step: one workgroup.
+__global__ __launch_bounds__(kBlock) void dalitz_finalize(DalitzConst dc, const DalitzTable* __restrict__ tab,
+                                                          const double* __restrict__ evpart, int64_t ev_rows,
+                                                          int ev_nv, int kmax, DalFinal fin) {
+  __shared__ DalFinalLds L;
+  dalitz_finalize_body(dc, tab, evpart, ev_rows, ev_nv, kmax, fin, L);
 }
 
 // Level-2 of the M-row passes: rows i0..i0+3 of M (scaled by dA) into Mc.
@@ -442,12 +496,35 @@ static void launch_pass_k(const DalitzConst& dc, const DalitzTable* tab, const d
                        ld, n, chunk, i0, part);
 }
 
+static DalFinal make_final(const double* npart, int64_t n_rows, int n_nv, const double* Mc, double n_events,
+                           bool grad, double* out, double* out_user) {
+  DalFinal f;
+  f.npart = npart;
+  f.n_rows = n_rows;
+  f.n_nv = n_nv;
+  f.Mc = Mc;
+  f.n_events = n_events;
+  f.with_grad = grad ? 1 : 0;
+  f.out = out;
+  f.out_user = out_user;
+  return f;
+}
+
 void dalitz_launch_events(const DalitzConst& dc, const DalitzTable* tab, const double* ev, int64_t ld, int64_t n,
                           int chunk, int64_t nchunks, int grad, double* part, hipStream_t s) {
   if (nchunks == 0) return;
   if (grad == 0) launch_pass_k<kEvents, 0>(dc, tab, ev, ld, n, chunk, nchunks, 0, part, s);
   else if (grad == 1) launch_pass_k<kEvents, 1>(dc, tab, ev, ld, n, chunk, nchunks, 0, part, s);
   else launch_pass_k<kEvents, 2>(dc, tab, ev, ld, n, chunk, nchunks, 0, part, s);
+}
+
+void dalitz_launch_finalize(const DalitzConst& dc, const DalitzTable* tab, const double* evpart, int64_t ev_rows,
+                            int grad, const double* npart, int64_t n_rows, int n_nv, const double* Mc,
+                            double n_events, double* out, double* out_user, hipStream_t s) {
+  const int kmax = dalitz_kmax(dc.K);
+  const DalFinal fin = make_final(npart, n_rows, n_nv, Mc, n_events, grad != 0, out, out_user);
+  hipLaunchKernelGGL(dalitz_finalize, dim3(1), dim3(kBlock), 0, s, dc, tab, evpart, ev_rows,
+                     dal_nv(kEvents, grad, kmax), kmax, fin);
 }
 
 void dalitz_launch_grid(const DalitzConst& dc, const DalitzTable* tab, int chunk, int64_t nchunks, int grad,
@@ -465,13 +542,6 @@ void dalitz_launch_mrows(const DalitzConst& dc, const DalitzTable* tab, int chun
   const int kmax = dalitz_kmax(dc.K);
   hipLaunchKernelGGL(dalitz_mrows_finalize, dim3(1), dim3(kBlock), 0, s, dc, part, nchunks,
                      dal_nv(kMRows, 0, kmax), kmax, i0, Mc);
-}
-
-void dalitz_launch_finalize(const DalitzConst& dc, const DalitzTable* tab, const double* evpart, int64_t ev_rows,
-                            int ev_nv, const double* npart, int64_t n_rows, int n_nv, const double* Mc,
-                            double n_events, bool grad, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(dalitz_finalize, dim3(1), dim3(kBlock), 0, s, dc, tab, evpart, ev_rows, ev_nv, npart, n_rows,
-                     n_nv, Mc, dalitz_kmax(dc.K), n_events, grad ? 1 : 0, out);
 }
 
 void dalitz_launch_eval(const DalitzConst& dc, const DalitzTable* tab, const double* ev, int64_t ld, int64_t n,

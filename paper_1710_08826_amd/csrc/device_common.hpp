@@ -40,27 +40,37 @@ __device__ inline void block_sum_row(double (&v)[NV], double* lds /* kWaves*NV *
 
 // Level 2: res[v] = sum over rows r of part[r*nv + v], for v < nv <= kBlock.
 // Thread t takes column t % nv and rows g, g+G, g+2G, ... with g = t / nv,
-// G = kBlock / nv, keeping four interleaved partial sums; the groups are then
-// added in order of g.  scratch holds kBlock doubles; res is LDS or global.
+// G = kBlock / nv, in sixteen interleaved partial sums (sixteen independent
+// loads in flight per thread: the rows were just written by other compute
+// units, so this step is load-latency bound); the partial sums are added
+// pairwise and the groups in order of g.  scratch holds kBlock doubles.
 __device__ inline void sum_rows(const double* __restrict__ part, int64_t nrows, int nv,
                                 double* scratch, double* res) {
+  constexpr int U = 16;
   const int t = threadIdx.x;
   const int G = kBlock / nv;
   const int g = t / nv;
   const int v = t - g * nv;
   double s = 0.0;
   if (g < G) {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    double a[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) a[u] = 0.0;
     int64_t r = g;
     const int64_t step = G;
-    for (; r + 3 * step < nrows; r += 4 * step) {
-      s0 += part[r * nv + v];
-      s1 += part[(r + step) * nv + v];
-      s2 += part[(r + 2 * step) * nv + v];
-      s3 += part[(r + 3 * step) * nv + v];
+    for (; r + (U - 1) * step < nrows; r += U * step) {
+      double x[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) x[u] = part[(r + u * step) * nv + v];
+#pragma unroll
+      for (int u = 0; u < U; ++u) a[u] += x[u];
     }
-    for (; r < nrows; r += step) s0 += part[r * nv + v];
-    s = (s0 + s1) + (s2 + s3);
+    for (; r < nrows; r += step) a[0] += part[r * nv + v];
+#pragma unroll
+    for (int w = U / 2; w > 0; w >>= 1)
+#pragma unroll
+      for (int u = 0; u < w; ++u) a[u] += a[u + w];
+    s = a[0];
   }
   scratch[t] = s;
   __syncthreads();

@@ -1,0 +1,73 @@
+// FP64 reciprocal, square root and logarithm for the per-event loops.
+//
+// rcp/rsqrt start from the hardware approximations (v_rcp_f64, v_rsq_f64)
+// and apply two Newton-Raphson steps on the exactly computed residual
+// (e = 1 - x r with an FMA), each step squaring the relative error, which
+// leaves an error of about one unit in the last place.  They take finite,
+// positive, normal arguments; callers clamp where a zero can occur.
+//
+// log_fast: argument reduction x = 2^e m with m in [sqrt(1/2), sqrt(2))
+// (Cody & Waite, Software Manual for the Elementary Functions, 1980), then
+// ln m = 2 atanh(f) = 2 (f + f^3/3 + f^5/5 + ...), f = (m-1)/(m+1), |f| <=
+// 0.1716 (Abramowitz & Stegun 4.1.27); eleven terms bring the truncation
+// below 3e-17 relative.  ln 2 is split into a 32-bit head and a tail so that
+// e ln 2 is formed without rounding error in the head.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace fn {
+
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double e = __builtin_fma(-x * y, y, 1.0);
+  y = __builtin_fma(0.5 * y, e, y);
+  e = __builtin_fma(-x * y, y, 1.0);
+  return __builtin_fma(0.5 * y, e, y);
+}
+
+// sqrt for x >= 0; arguments below 1e-300 are treated as 1e-300.
+__device__ __forceinline__ double sqrt_nr(double x) {
+  const double xc = __builtin_fmax(x, 1e-300);
+  return xc * rsqrt_nr(xc);
+}
+
+__device__ __forceinline__ double log_fast(double x) {
+  double m = __builtin_amdgcn_frexp_mant(x);  // [0.5, 1)
+  int e = __builtin_amdgcn_frexp_exp(x);
+  const bool lo = m < 0.70710678118654752440;
+  m = lo ? 2.0 * m : m;
+  e = lo ? e - 1 : e;
+  const double f = (m - 1.0) * rcp_nr(m + 1.0);
+  const double f2 = f * f;
+  double p = 1.0 / 23.0;
+  p = __builtin_fma(p, f2, 1.0 / 21.0);
+  p = __builtin_fma(p, f2, 1.0 / 19.0);
+  p = __builtin_fma(p, f2, 1.0 / 17.0);
+  p = __builtin_fma(p, f2, 1.0 / 15.0);
+  p = __builtin_fma(p, f2, 1.0 / 13.0);
+  p = __builtin_fma(p, f2, 1.0 / 11.0);
+  p = __builtin_fma(p, f2, 1.0 / 9.0);
+  p = __builtin_fma(p, f2, 1.0 / 7.0);
+  p = __builtin_fma(p, f2, 1.0 / 5.0);
+  p = __builtin_fma(p, f2, 1.0 / 3.0);
+  const double f2x = 2.0 * f;
+  const double lm = __builtin_fma(f2x * f2, p, f2x);
+  const double de = (double)e;
+  // ln 2 rounded to 32 significant bits, and the remainder
+  constexpr double kLn2Hi = 0x1.62e42ff000000p-1;
+  constexpr double kLn2Lo = -0x1.718432a1b0e26p-35;
+  const double r = __builtin_fma(de, kLn2Hi, __builtin_fma(de, kLn2Lo, lm));
+  // IEEE results outside (0, inf): -inf at 0, +inf at inf, NaN below 0 or NaN
+  const bool finite_pos = x > 0.0 && x <= 1.7976931348623157e308;
+  return finite_pos ? r : (x == 0.0 ? -__builtin_inf() : (x > 0.0 ? x : __builtin_nan("")));
+}
+
+}  // namespace fn

@@ -57,6 +57,10 @@ struct fn_model {
   fn::DevBuf d_table, d_part, d_npart, d_out, d_fixed, d_M, d_count;
   double* h_out = nullptr;       // pinned
   long long stats_calls = 0;
+  bool timing = false;           // bracket event-pass launches with HIP events
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
+  hipEvent_t take_event();
 
   fn::Mix1dTable* table_mix() { return (fn::Mix1dTable*)d_table.ptr; }
   fn::DalitzTable* table_dal() { return (fn::DalitzTable*)d_table.ptr; }
@@ -70,7 +74,7 @@ struct fn_model {
 
 namespace fn {
 void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const double* ev, int64_t n, int64_t ld,
-             bool grad, double* out_dev, hipStream_t s);
+             bool grad, double* out_user, hipStream_t s);
 void nll_host(fn_model* m, const double* theta_host, const double* ev, int64_t n, int64_t ld, double* nll,
               double* grad, hipStream_t s);
 void check_events_args(fn_model* m, const double* ev, int64_t n, int64_t ld);

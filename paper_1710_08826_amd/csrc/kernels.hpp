@@ -9,14 +9,17 @@ int mix1d_kmax(int K);
 int mix1d_nv(int kmax, bool grad);
 void mix1d_launch_prologue(const Mix1dConst& mc, const ParamBlock& pb, const double* theta_dev, int n_fits,
                            int theta_stride, Mix1dTable* tab, hipStream_t s);
+// Events pass (one row of partial sums per chunk) and the level-2 step.
 void mix1d_launch_events(const Mix1dConst& mc, const Mix1dTable* tab, const double* x, int64_t n, int chunk,
                          int64_t nchunks, bool grad, double* part, hipStream_t s);
+void mix1d_launch_finalize(const Mix1dConst& mc, const Mix1dTable* tab, const double* part, int64_t nrows,
+                           bool grad, double* out, double* out_user, hipStream_t s);
+// Many fits in one launch: work items (fit, chunk); then one level-2
+// workgroup per fit writing out + fit * out_stride.
 void mix1d_launch_events_batched(const Mix1dConst& mc, const Mix1dTable* tabs, const double* const* ev,
                                  const int64_t* n, const int32_t* item_fit, const int64_t* item_chunk,
                                  const int64_t* part_base, int64_t n_items, int chunk, bool grad, double* part,
                                  hipStream_t s);
-void mix1d_launch_finalize(const Mix1dConst& mc, const Mix1dTable* tab, const double* part, int64_t nrows,
-                           bool grad, double* out, hipStream_t s);
 void mix1d_launch_finalize_batched(const Mix1dConst& mc, const Mix1dTable* tabs, const double* part,
                                    const int64_t* part_base, const int64_t* nrows, int n_fits, bool grad,
                                    double* out, int out_stride, hipStream_t s);
@@ -30,15 +33,18 @@ int dalitz_nv_events(int kmax, int grad);
 int dalitz_nv_mrows(int kmax);
 void dalitz_launch_prologue(const DalitzConst& dc, const ParamBlock& pb, const double* theta_dev,
                             const double* fixed_ls, int n_fits, int theta_stride, DalitzTable* tab, hipStream_t s);
+// Events pass: one row of partial sums per chunk of events.
 void dalitz_launch_events(const DalitzConst& dc, const DalitzTable* tab, const double* ev, int64_t ld, int64_t n,
                           int chunk, int64_t nchunks, int grad, double* part, hipStream_t s);
+// Level-2 sum of the event rows and of the normalization (grid rows, or the
+// cached M when npart is null), NLL assembly: out = [NLL, grad, I, dI].
+void dalitz_launch_finalize(const DalitzConst& dc, const DalitzTable* tab, const double* evpart, int64_t ev_rows,
+                            int grad, const double* npart, int64_t n_rows, int n_nv, const double* Mc,
+                            double n_events, double* out, double* out_user, hipStream_t s);
 void dalitz_launch_grid(const DalitzConst& dc, const DalitzTable* tab, int chunk, int64_t nchunks, int grad,
                         double* part, hipStream_t s);
 void dalitz_launch_mrows(const DalitzConst& dc, const DalitzTable* tab, int chunk, int64_t nchunks, int i0,
                          double* part, double* Mc, hipStream_t s);
-void dalitz_launch_finalize(const DalitzConst& dc, const DalitzTable* tab, const double* evpart, int64_t ev_rows,
-                            int ev_nv, const double* npart, int64_t n_rows, int n_nv, const double* Mc,
-                            double n_events, bool grad, double* out, hipStream_t s);
 void dalitz_launch_eval(const DalitzConst& dc, const DalitzTable* tab, const double* ev, int64_t ld, int64_t n,
                         const double* norm, double* p, hipStream_t s);
 void dalitz_launch_check(const DalitzConst& dc, const double* ev, int64_t ld, int64_t n, unsigned long long* bad,

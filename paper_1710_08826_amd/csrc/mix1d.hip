@@ -18,6 +18,7 @@
 #include <cmath>
 
 #include "device_common.hpp"
+#include "fastmath.hpp"
 #include "kernels.hpp"
 
 namespace fn {
@@ -158,7 +159,7 @@ __device__ inline double mix_shape(int type, const Mix1dTable& t, int k, double 
     }
     default: {  // kBW
       const double d = x - t.a[k];
-      const double s = 1.0 / (d * d + t.b[k]);
+      const double s = rcp_nr(__builtin_fma(d, d, t.b[k]));
       if (GRAD) { dl0 = 2.0 * d * s; dl1 = -0.5 * t.c[k] * s; }
       return s;
     }
@@ -190,9 +191,9 @@ __device__ inline void mix1d_chunk(const Mix1dConst& mc, const Mix1dTable* __res
         P += t.frac[k] * u[k];
       }
     }
-    acc[0] -= log(P);
+    acc[0] -= log_fast(P);
     if (GRAD) {
-      const double w = -1.0 / P;
+      const double w = -rcp_nr(P);
       double ul = 0.0;  // density of the last component (it takes 1 - sum f)
 #pragma unroll
       for (int k = 0; k < KMAX; ++k)
@@ -211,6 +212,38 @@ __device__ inline void mix1d_chunk(const Mix1dConst& mc, const Mix1dTable* __res
   block_sum_row<NV>(acc, lds, out_row);
 }
 
+// Level 2 and the slot -> parameter map (slots sharing a parameter are added
+// in slot order).  out: [NLL, grad(P), I = 1, dI = 0]; out_user: [NLL, grad(P)].
+__device__ inline void mix1d_finalize_one(const Mix1dConst& mc, const Mix1dTable& t,
+                                          const double* part, int64_t nrows, int nv, int kmax,
+                                          int with_grad, double* out, double* out_user, double* scratch,
+                                          double* res) {
+  sum_rows(part, nrows, nv, scratch, res);
+  const int P = mc.n_params;
+  const int p = threadIdx.x;
+  const bool ok = t.valid != 0.0;
+  if (p == 0) {
+    out[0] = ok ? res[0] : INFINITY;
+    out[1 + P] = 1.0;
+    if (out_user) out_user[0] = out[0];
+  }
+  if (p < P) {
+    out[2 + P + p] = 0.0;
+    if (with_grad) {
+      double g = 0.0;
+      for (int k = 0; k < mc.K; ++k) {
+        for (int j = 0; j < mc.npar[k]; ++j)
+          if (mc.pidx[k][j] == p) g += res[1 + 2 * k + j];
+        if (k < mc.K - 1 && mc.fidx[k] == p) g += res[1 + 2 * kmax + k];
+      }
+      if (!ok) g = NAN;
+      out[1 + p] = g;
+      if (out_user) out_user[1 + p] = g;
+    }
+  }
+}
+
+// Single fit: one workgroup per chunk of events, one row of partial sums each.
 template <bool GRAD, int KMAX>
 __global__ __launch_bounds__(kBlock) void mix1d_events(Mix1dConst mc, const Mix1dTable* __restrict__ tab,
                                                        const double* __restrict__ x, int64_t n, int chunk,
@@ -221,7 +254,9 @@ __global__ __launch_bounds__(kBlock) void mix1d_events(Mix1dConst mc, const Mix1
 }
 
 // Batched form: work item w = (fit, chunk) from a flat list; per-fit tables,
-// event pointers and sizes come from device arrays.
+// event pointers, sizes and row bases come from device arrays.  The chunk
+// routine is the one the single-fit kernel runs, so a fit's rows hold the same
+// bits alone and in a batch.
 template <bool GRAD, int KMAX>
 __global__ __launch_bounds__(kBlock) void mix1d_events_batched(
     Mix1dConst mc, const Mix1dTable* __restrict__ tabs, const double* const* __restrict__ ev,
@@ -232,42 +267,10 @@ __global__ __launch_bounds__(kBlock) void mix1d_events_batched(
   __shared__ double lds[kWaves * NV];
   const int fit = item_fit[blockIdx.x];
   const int64_t ch = item_chunk[blockIdx.x];
-  mix1d_chunk<GRAD, KMAX>(mc, tabs + fit, ev[fit], n[fit], ch, chunk,
-                          part + (part_base[fit] + ch) * NV, lds);
+  mix1d_chunk<GRAD, KMAX>(mc, tabs + fit, ev[fit], n[fit], ch, chunk, part + (part_base[fit] + ch) * NV, lds);
 }
 
-__device__ inline void mix1d_finalize_one(const Mix1dConst& mc, const Mix1dTable& t,
-                                          const double* part, int64_t nrows, int nv, int kmax,
-                                          int with_grad, double* out, double* scratch, double* res) {
-  sum_rows(part, nrows, nv, scratch, res);
-  if (threadIdx.x == 0) {
-    const int P = mc.n_params;
-    const bool ok = t.valid != 0.0;
-    out[0] = ok ? res[0] : INFINITY;
-    if (with_grad) {
-      for (int p = 0; p < P; ++p) out[1 + p] = 0.0;
-      for (int k = 0; k < mc.K; ++k) {
-        for (int j = 0; j < mc.npar[k]; ++j) out[1 + mc.pidx[k][j]] += res[1 + 2 * k + j];
-        if (k < mc.K - 1) out[1 + mc.fidx[k]] += res[1 + 2 * kmax + k];
-      }
-      if (!ok)
-        for (int p = 0; p < P; ++p) out[1 + p] = NAN;
-    }
-    out[1 + P] = 1.0;
-    for (int p = 0; p < P; ++p) out[2 + P + p] = 0.0;
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void mix1d_finalize(Mix1dConst mc, const Mix1dTable* __restrict__ tab,
-                                                         const double* __restrict__ part, int64_t nrows,
-                                                         int nv, int kmax, int with_grad,
-                                                         double* __restrict__ out) {
-  __shared__ double scratch[kBlock];
-  __shared__ double res[kBlock];
-  mix1d_finalize_one(mc, *tab, part, nrows, nv, kmax, with_grad, out, scratch, res);
-}
-
-// Batched finalize: one workgroup per fit; out rows of stride out_stride.
+// Batched level-2: one workgroup per fit, output rows of stride out_stride.
 __global__ __launch_bounds__(kBlock) void mix1d_finalize_batched(
     Mix1dConst mc, const Mix1dTable* __restrict__ tabs, const double* __restrict__ part,
     const int64_t* __restrict__ part_base, const int64_t* __restrict__ nrows, int nv, int kmax,
@@ -276,7 +279,17 @@ __global__ __launch_bounds__(kBlock) void mix1d_finalize_batched(
   __shared__ double res[kBlock];
   const int f = blockIdx.x;
   mix1d_finalize_one(mc, tabs[f], part + part_base[f] * nv, nrows[f], nv, kmax, with_grad,
-                     out + (int64_t)f * out_stride, scratch, res);
+                     out + (int64_t)f * out_stride, nullptr, scratch, res);
+}
+
+// Level-2 step of a single fit.
+__global__ __launch_bounds__(kBlock) void mix1d_finalize(Mix1dConst mc, const Mix1dTable* __restrict__ tab,
+                                                         const double* __restrict__ part, int64_t nrows,
+                                                         int nv, int kmax, int with_grad,
+                                                         double* __restrict__ out, double* __restrict__ out_user) {
+  __shared__ double scratch[kBlock];
+  __shared__ double res[kBlock];
+  mix1d_finalize_one(mc, *tab, part, nrows, nv, kmax, with_grad, out, out_user, scratch, res);
 }
 
 __global__ void mix1d_eval(Mix1dConst mc, const Mix1dTable* __restrict__ tab, const double* __restrict__ x,
@@ -298,13 +311,6 @@ __global__ void mix1d_check(Mix1dConst mc, const double* __restrict__ x, int64_t
 }
 
 // ---------------------------------------------------------------- launchers
-template <bool GRAD, int KMAX>
-static void launch_events(const Mix1dConst& mc, const Mix1dTable* tab, const double* x, int64_t n,
-                          int chunk, int64_t nchunks, double* part, hipStream_t s) {
-  hipLaunchKernelGGL((mix1d_events<GRAD, KMAX>), dim3((unsigned)nchunks), dim3(kBlock), 0, s, mc, tab, x,
-                     n, chunk, part);
-}
-
 int mix1d_kmax(int K) { return K <= 2 ? 2 : 8; }
 int mix1d_nv(int kmax, bool grad) { return grad ? mix_nv(kmax) : 1; }
 
@@ -318,13 +324,21 @@ void mix1d_launch_events(const Mix1dConst& mc, const Mix1dTable* tab, const doub
                          int64_t nchunks, bool grad, double* part, hipStream_t s) {
   if (nchunks == 0) return;
   const int kmax = mix1d_kmax(mc.K);
+  const dim3 g((unsigned)nchunks), b(kBlock);
+#define FN_MIX(G, K) hipLaunchKernelGGL((mix1d_events<G, K>), g, b, 0, s, mc, tab, x, n, chunk, part)
   if (kmax == 2) {
-    if (grad) launch_events<true, 2>(mc, tab, x, n, chunk, nchunks, part, s);
-    else launch_events<false, 2>(mc, tab, x, n, chunk, nchunks, part, s);
+    if (grad) FN_MIX(true, 2); else FN_MIX(false, 2);
   } else {
-    if (grad) launch_events<true, 8>(mc, tab, x, n, chunk, nchunks, part, s);
-    else launch_events<false, 8>(mc, tab, x, n, chunk, nchunks, part, s);
+    if (grad) FN_MIX(true, 8); else FN_MIX(false, 8);
   }
+#undef FN_MIX
+}
+
+void mix1d_launch_finalize(const Mix1dConst& mc, const Mix1dTable* tab, const double* part, int64_t nrows,
+                           bool grad, double* out, double* out_user, hipStream_t s) {
+  const int kmax = mix1d_kmax(mc.K);
+  hipLaunchKernelGGL(mix1d_finalize, dim3(1), dim3(kBlock), 0, s, mc, tab, part, nrows, mix1d_nv(kmax, grad),
+                     kmax, grad ? 1 : 0, out, out_user);
 }
 
 void mix1d_launch_events_batched(const Mix1dConst& mc, const Mix1dTable* tabs, const double* const* ev,
@@ -334,21 +348,15 @@ void mix1d_launch_events_batched(const Mix1dConst& mc, const Mix1dTable* tabs, c
   if (n_items == 0) return;
   const int kmax = mix1d_kmax(mc.K);
   const dim3 g((unsigned)n_items), b(kBlock);
-#define FN_MIXB(G, K) \
-  hipLaunchKernelGGL((mix1d_events_batched<G, K>), g, b, 0, s, mc, tabs, ev, n, item_fit, item_chunk, part_base, chunk, part)
+#define FN_MIXB(G, K)                                                                                        \
+  hipLaunchKernelGGL((mix1d_events_batched<G, K>), g, b, 0, s, mc, tabs, ev, n, item_fit, item_chunk, part_base, \
+                     chunk, part)
   if (kmax == 2) {
     if (grad) FN_MIXB(true, 2); else FN_MIXB(false, 2);
   } else {
     if (grad) FN_MIXB(true, 8); else FN_MIXB(false, 8);
   }
 #undef FN_MIXB
-}
-
-void mix1d_launch_finalize(const Mix1dConst& mc, const Mix1dTable* tab, const double* part, int64_t nrows,
-                           bool grad, double* out, hipStream_t s) {
-  const int kmax = mix1d_kmax(mc.K);
-  hipLaunchKernelGGL(mix1d_finalize, dim3(1), dim3(kBlock), 0, s, mc, tab, part, nrows, mix1d_nv(kmax, grad),
-                     kmax, grad ? 1 : 0, out);
 }
 
 void mix1d_launch_finalize_batched(const Mix1dConst& mc, const Mix1dTable* tabs, const double* part,

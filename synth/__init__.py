@@ -7,3 +7,4 @@ from .samplers import (  # noqa: F401
     BASE_SEED, CONFIG0_TRUTH, CONFIG0_RANGE, DALITZ_MASSES, DALITZ_RESONANCES,
     mix1d_events, lognormal_sizes, dalitz_events, dalitz_box,
 )
+from .workloads import mix1d_desc, mix1d_truth, dalitz_desc, dalitz_truth  # noqa: F401,E402
