@@ -168,6 +168,51 @@ fn_status fn_fit(fn_model* m, const double* theta0_host, const int32_t* free_mas
                  int32_t max_iter, double* theta_out, double* err_out, double* nll_out,
                  int32_t* n_iter, int32_t* n_calls, void* stream);
 
+/* ---------------------------------------------------------------- batching
+ * Many independent fits of one "mix1d" model advanced together on the device
+ * (the paper's toy Monte Carlo studies: many fits of the same PDF to
+ * different samples, Sec. 5).  Each fit occupies a slot; a step evaluates
+ * NLL + gradient for every running slot at its trial point and advances that
+ * slot's BFGS / strong-Wolfe line-search state machine by one evaluation
+ * (the same minimizer as fn_fit, state kept in device memory).  Fits never
+ * interact: a fit's result bits do not depend on the other slots.  Step
+ * launches are captured once in a hipGraph on an internal stream and replayed;
+ * the host reads back only the running-slot count between groups of steps.
+ * A batch uses its own stream; calls on one batch must not overlap. */
+typedef struct fn_batch fn_batch;
+enum { FN_FIT_IDLE = 0, FN_FIT_RUNNING = 1, FN_FIT_CONVERGED = 2, FN_FIT_FAILED = 3 };
+
+/* max_fits slots for a mix1d model with at most 24 parameters; events per fit
+ * up to max_events_per_fit.  Allocates all device state up front. */
+fn_status fn_batch_create(fn_model* m, int32_t max_fits, int64_t max_events_per_fit, fn_batch** out);
+fn_status fn_batch_destroy(fn_batch* b);
+/* Put a fit into slot `slot`: device events (n, caller-owned, valid until the
+ * slot is cleared or the fit finishes), host start point theta0 (P doubles),
+ * free mask (P int32, NULL = all free).  The slot becomes RUNNING. */
+fn_status fn_batch_set_slot(fn_batch* b, int32_t slot, const double* ev, int64_t n, const double* theta0,
+                            const int32_t* free_mask);
+/* Mark a slot IDLE (frees it for reuse; its last results stay readable). */
+fn_status fn_batch_clear_slot(fn_batch* b, int32_t slot);
+/* Convergence tolerance on the estimated distance to minimum (<= 0: 1e-7)
+ * and iteration limit (<= 0: 500) for fits set after this call. */
+fn_status fn_batch_config(fn_batch* b, double tol, int32_t max_iter, int32_t use_graph);
+/* Run up to max_steps steps (poll the running count every poll_every steps);
+ * returns the number of steps run and the slots still running. */
+fn_status fn_batch_run(fn_batch* b, int32_t max_steps, int32_t poll_every, int32_t* steps_done,
+                       int32_t* n_running);
+/* Per-slot results (host arrays of max_fits entries; any may be NULL):
+ * status, theta (max_fits x P), nll, errors (sqrt of the diagonal of the BFGS
+ * inverse-Hessian estimate; 0 for fixed parameters), iterations, evaluations. */
+fn_status fn_batch_results(fn_batch* b, int32_t* status, double* theta, double* nll, double* errors,
+                           int32_t* iters, int32_t* n_evals);
+
+/* Device toy generation (Philox4x32-10 counters (i, attempt, word) under key
+ * (seed, fit)) of n events of the Gaussian(mu, sigma) fraction f + exponential
+ * (tau) mixture on [lo, hi], theta_gen = (mu, sigma, tau, f) on the host,
+ * into caller-owned device memory x (n doubles).  Synchronous. */
+fn_status fn_generate_mix1d(uint32_t seed, uint32_t fit, int64_t n, const double* theta_gen, double lo, double hi,
+                            double* x, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -4,11 +4,11 @@ thin Python binding.  Import is cheap; the shared library loads on first use.
 """
 from ._lib import FitNLLError, load  # noqa: F401
 
-__all__ = ["FitNLLError", "load", "Model", "NLLFunction", "FitResult"]
+__all__ = ["FitNLLError", "load", "Model", "NLLFunction", "FitResult", "Batch", "generate_mix1d"]
 
 
 def __getattr__(name):
-    if name in ("Model", "NLLFunction", "FitResult", "context"):
+    if name in ("Model", "NLLFunction", "FitResult", "context", "Batch", "BatchResults", "generate_mix1d"):
         from . import api
         return getattr(api, name)
     raise AttributeError(name)

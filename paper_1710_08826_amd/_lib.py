@@ -20,6 +20,8 @@ FN_E_HIP = -5
 FN_E_BUDGET = -6
 FN_E_CANCELLED = -7
 
+FN_FIT_IDLE, FN_FIT_RUNNING, FN_FIT_CONVERGED, FN_FIT_FAILED = 0, 1, 2, 3
+
 STATUS_NAMES = {
     FN_E_INVALID: "FN_E_INVALID", FN_E_DOMAIN: "FN_E_DOMAIN", FN_E_NONFINITE: "FN_E_NONFINITE",
     FN_E_NOMEM: "FN_E_NOMEM", FN_E_HIP: "FN_E_HIP", FN_E_BUDGET: "FN_E_BUDGET",
@@ -49,6 +51,14 @@ PROTOTYPES = {
     "fn_model_kernel_time": (i32, [vp, dp, C.POINTER(i64)]),
     "fn_fit": (i32, [vp, dp, C.POINTER(i32), vp, i64, i64, i32, C.c_double, i32, dp, dp, dp,
                      C.POINTER(i32), C.POINTER(i32), vp]),
+    "fn_batch_create": (i32, [vp, i32, i64, C.POINTER(vp)]),
+    "fn_batch_destroy": (i32, [vp]),
+    "fn_batch_set_slot": (i32, [vp, i32, vp, i64, dp, C.POINTER(i32)]),
+    "fn_batch_clear_slot": (i32, [vp, i32]),
+    "fn_batch_config": (i32, [vp, C.c_double, i32, i32]),
+    "fn_batch_run": (i32, [vp, i32, i32, C.POINTER(i32), C.POINTER(i32)]),
+    "fn_batch_results": (i32, [vp, C.POINTER(i32), dp, dp, dp, C.POINTER(i32), C.POINTER(i32)]),
+    "fn_generate_mix1d": (i32, [C.c_uint32, C.c_uint32, i64, dp, C.c_double, C.c_double, vp, vp]),
 }
 
 _lib = None

@@ -195,3 +195,84 @@ class NLLFunction(torch.autograd.Function):
     def backward(ctx, grad_out):
         (g,) = ctx.saved_tensors
         return grad_out * g, None, None
+
+
+@dataclass
+class BatchResults:
+    status: np.ndarray
+    theta: np.ndarray
+    nll: np.ndarray
+    errors: np.ndarray
+    iters: np.ndarray
+    n_evals: np.ndarray
+
+
+class Batch:
+    """Slots of independent fits of one mix1d model advanced together on the
+    device (see fn_batch_* in include/fitnll.h)."""
+
+    def __init__(self, model: Model, max_fits: int, max_events_per_fit: int):
+        self.model = model
+        self._lib = model._lib
+        self.max_fits = max_fits
+        h = C.c_void_p()
+        check(self._lib.fn_batch_create(model._h, int(max_fits), int(max_events_per_fit), C.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.fn_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def config(self, tol: float = 1e-7, max_iter: int = 500, use_graph: bool = True):
+        check(self._lib.fn_batch_config(self._h, float(tol), int(max_iter), 1 if use_graph else 0))
+
+    def set_slot(self, slot: int, events: torch.Tensor, theta0, free=None):
+        evp, n, _ = _events(events, 1)
+        th, thp = _dbl(theta0)
+        mask = None
+        if free is not None:
+            m = np.ascontiguousarray(np.asarray(free, dtype=np.int32))
+            mask = m.ctypes.data_as(C.POINTER(C.c_int32))
+        check(self._lib.fn_batch_set_slot(self._h, int(slot), evp, n, thp, mask))
+        self._keep[slot] = events  # the slot reads these events until cleared
+
+    def clear_slot(self, slot: int):
+        check(self._lib.fn_batch_clear_slot(self._h, int(slot)))
+        self._keep.pop(slot, None)
+
+    def run(self, max_steps: int = 2000, poll_every: int = 8):
+        done, running = C.c_int32(), C.c_int32()
+        check(self._lib.fn_batch_run(self._h, int(max_steps), int(poll_every), C.byref(done), C.byref(running)))
+        return done.value, running.value
+
+    def results(self) -> BatchResults:
+        n, P = self.max_fits, self.model.n_params
+        st = np.zeros(n, np.int32)
+        th = np.zeros((n, P))
+        nll = np.zeros(n)
+        er = np.zeros((n, P))
+        it = np.zeros(n, np.int32)
+        ne = np.zeros(n, np.int32)
+        i32p = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
+        f64p = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+        check(self._lib.fn_batch_results(self._h, i32p(st), f64p(th), f64p(nll), f64p(er), i32p(it), i32p(ne)))
+        return BatchResults(st, th, nll, er, it, ne)
+
+
+def generate_mix1d(n: int, seed: int, fit: int, theta_gen, lo: float = -10.0, hi: float = 10.0,
+                   device: str = "cuda", stream=None) -> torch.Tensor:
+    """Device toy events of the Gaussian + exponential mixture, shape (1, n)."""
+    lib = _lib.load()
+    th, thp = _dbl(theta_gen)
+    x = torch.empty((1, n), dtype=torch.float64, device=device)
+    check(lib.fn_generate_mix1d(C.c_uint32(seed & 0xFFFFFFFF), C.c_uint32(fit & 0xFFFFFFFF), int(n), thp,
+                                float(lo), float(hi), C.c_void_p(x.data_ptr() if n else 0), _stream_ptr(stream)))
+    return x

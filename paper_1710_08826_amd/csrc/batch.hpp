@@ -1,0 +1,47 @@
+// Batched fits: per-fit minimizer state and the device buffers of a batch.
+#pragma once
+#include "kernels.hpp"
+#include "mix1d_device.hpp"
+
+namespace fn {
+
+constexpr int kBatchMaxP = 24;      // parameters per batched fit
+constexpr int kMaxLineSearch = 40;  // evaluations per line search before giving up
+constexpr int kGenMaxAttempts = 64; // redraws per generated event
+
+enum FitStatus : int { kFitIdle = 0, kFitRunning = 1, kFitConverged = 2, kFitFailed = 3 };
+enum FitPhase : int { kPhaseStart = 0, kPhaseBracket = 1, kPhaseZoom = 2, kPhaseAcceptLo = 3 };
+
+// One fit's BFGS + line-search state (device memory, one thread per fit).
+struct BfgsState {
+  double xt[kBatchMaxP];   // trial point: the next evaluation happens here
+  double x[kBatchMaxP];    // accepted point
+  double g[kBatchMaxP];    // gradient at x
+  double p[kBatchMaxP];    // search direction
+  double H[kBatchMaxP * kBatchMaxP];  // inverse Hessian approximation
+  double f, d0, alpha, h0, edm;
+  double a_prev, f_prev, d_prev, a_lo, f_lo, d_lo, a_hi, f_hi;
+  int mask[kBatchMaxP];    // 1 = free parameter
+  int status, phase, iter, ls_it, n_eval, pad;
+};
+
+// Device pointers of a batch (n_fits slots).
+struct BatchDev {
+  BfgsState* st;
+  Mix1dTable* tabs;
+  const double** ev;       // event pointer per slot
+  int64_t* nev;            // events per slot
+  int64_t* item_base;      // n_fits + 1
+  int64_t* part_base;      // first partial row of each slot
+  double* part;            // partial rows
+  double* out;             // per slot [NLL, grad(P), I, dI(P)]
+  int* n_running;
+};
+
+void batch_launch_step(const BatchDev& b, const Mix1dConst& mc, int n_fits, int P, int chunk, int eval_grid,
+                       double tol, int max_iter, hipStream_t s);
+int batch_eval_blocks_per_cu(const Mix1dConst& mc);
+void batch_launch_gen_mix1d(uint32_t k0, uint32_t k1, uint32_t word, int64_t n, const double* theta_gen, double lo,
+                            double hi, double* x, unsigned int* n_unresolved, hipStream_t s);
+
+}  // namespace fn

@@ -1,0 +1,276 @@
+// Host side of batched fits (fn_batch_*) and device toy generation.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "batch.hpp"
+#include "internal.hpp"
+
+using namespace fn;
+
+struct fn_batch {
+  fn_model* m = nullptr;
+  int max_fits = 0;
+  int64_t max_ev = 0;
+  int P = 0;
+  int chunk = 0;
+  int64_t rows_per_slot = 0;
+  int eval_grid = 0;
+  double tol = 1e-7;
+  int max_iter = 500;
+  bool use_graph = true;
+  hipStream_t stream = nullptr;
+  hipGraphExec_t exec = nullptr;
+  DevBuf st, tabs, evp, nev, item_base, part_base, part, out, nrun;
+  // pinned staging of per-slot inputs (stable sources for async copies)
+  BfgsState* h_st = nullptr;
+  const double** h_ev = nullptr;
+  int64_t* h_nev = nullptr;
+  int* h_nrun = nullptr;
+  BatchDev dev() {
+    BatchDev d;
+    d.st = (BfgsState*)st.ptr;
+    d.tabs = (Mix1dTable*)tabs.ptr;
+    d.ev = (const double**)evp.ptr;
+    d.nev = (int64_t*)nev.ptr;
+    d.item_base = (int64_t*)item_base.ptr;
+    d.part_base = (int64_t*)part_base.ptr;
+    d.part = (double*)part.ptr;
+    d.out = (double*)out.ptr;
+    d.n_running = (int*)nrun.ptr;
+    return d;
+  }
+  void drop_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    exec = nullptr;
+  }
+  ~fn_batch() {
+    drop_graph();
+    if (stream) (void)hipStreamDestroy(stream);
+    if (h_st) (void)hipHostFree(h_st);
+    if (h_ev) (void)hipHostFree(h_ev);
+    if (h_nev) (void)hipHostFree(h_nev);
+    if (h_nrun) (void)hipHostFree(h_nrun);
+  }
+};
+
+static void* pinned(size_t bytes) {
+  void* p = nullptr;
+  if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) throw Error(FN_E_NOMEM, "hipHostMalloc failed");
+  std::memset(p, 0, bytes);
+  return p;
+}
+
+static void step(fn_batch* b) {
+  if (b->use_graph) {
+    if (!b->exec) {
+      hipGraph_t g = nullptr;
+      hip_check(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+      batch_launch_step(b->dev(), b->m->mix, b->max_fits, b->P, b->chunk, b->eval_grid, b->tol, b->max_iter,
+                        b->stream);
+      hip_check(hipStreamEndCapture(b->stream, &g), "hipStreamEndCapture");
+      const hipError_t e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      hip_check(e, "hipGraphInstantiate");
+    }
+    hip_check(hipGraphLaunch(b->exec, b->stream), "hipGraphLaunch");
+  } else {
+    batch_launch_step(b->dev(), b->m->mix, b->max_fits, b->P, b->chunk, b->eval_grid, b->tol, b->max_iter,
+                      b->stream);
+    hip_check(hipGetLastError(), "kernel launch");
+  }
+}
+
+extern "C" {
+
+fn_status fn_batch_create(fn_model* m, int32_t max_fits, int64_t max_events_per_fit, fn_batch** out) {
+  fn_batch* b = nullptr;
+  const fn_status st = guard([&] {
+    if (!m || !out) throw Error(FN_E_INVALID, "NULL argument");
+    if (m->kind != kKindMix1d) throw Error(FN_E_INVALID, "batches support mix1d models");
+    if (m->P > kBatchMaxP) throw Error(FN_E_INVALID, "batched fits take at most 24 parameters");
+    if (max_fits < 1 || max_fits > (1 << 20)) throw Error(FN_E_INVALID, "max_fits out of range");
+    if (max_events_per_fit < 1) throw Error(FN_E_INVALID, "max_events_per_fit must be >= 1");
+    hip_check(hipSetDevice(m->device), "hipSetDevice");
+    b = new fn_batch;
+    b->m = m;
+    b->max_fits = max_fits;
+    b->max_ev = max_events_per_fit;
+    b->P = m->P;
+    b->chunk = m->chunk;
+    b->rows_per_slot = (max_events_per_fit + m->chunk - 1) / m->chunk;
+    const int kmax = mix1d_kmax(m->mix.K);
+    const int nv = mix1d_nv(kmax, true);
+    hip_check(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking), "hipStreamCreate");
+    b->st.reserve(sizeof(BfgsState) * max_fits);
+    b->tabs.reserve(sizeof(Mix1dTable) * max_fits);
+    b->evp.reserve(sizeof(double*) * max_fits);
+    b->nev.reserve(sizeof(int64_t) * max_fits);
+    b->item_base.reserve(sizeof(int64_t) * (max_fits + 1));
+    b->part_base.reserve(sizeof(int64_t) * max_fits);
+    b->part.reserve(sizeof(double) * (size_t)b->rows_per_slot * max_fits * nv);
+    b->out.reserve(sizeof(double) * (size_t)max_fits * (2 + 2 * b->P));
+    b->nrun.reserve(sizeof(int));
+    b->h_st = (BfgsState*)pinned(sizeof(BfgsState) * max_fits);
+    b->h_ev = (const double**)pinned(sizeof(double*) * max_fits);
+    b->h_nev = (int64_t*)pinned(sizeof(int64_t) * max_fits);
+    b->h_nrun = (int*)pinned(sizeof(int));
+    std::vector<int64_t> pb(max_fits);
+    for (int f = 0; f < max_fits; ++f) pb[f] = (int64_t)f * b->rows_per_slot;
+    // all slots idle, no events
+    hip_check(hipMemcpyAsync(b->st.ptr, b->h_st, sizeof(BfgsState) * max_fits, hipMemcpyHostToDevice, b->stream),
+              "hipMemcpyAsync");
+    hip_check(hipMemcpyAsync(b->evp.ptr, b->h_ev, sizeof(double*) * max_fits, hipMemcpyHostToDevice, b->stream),
+              "hipMemcpyAsync");
+    hip_check(hipMemcpyAsync(b->nev.ptr, b->h_nev, sizeof(int64_t) * max_fits, hipMemcpyHostToDevice, b->stream),
+              "hipMemcpyAsync");
+    hip_check(hipMemcpyAsync(b->part_base.ptr, pb.data(), sizeof(int64_t) * max_fits, hipMemcpyHostToDevice,
+                             b->stream),
+              "hipMemcpyAsync");
+    hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    int cus = 0;
+    hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device), "hipDeviceGetAttribute");
+    b->eval_grid = cus * batch_eval_blocks_per_cu(m->mix);
+    *out = b;
+  });
+  if (st != FN_OK) delete b;
+  return st;
+}
+
+fn_status fn_batch_destroy(fn_batch* b) {
+  return guard([&] {
+    if (b) {
+      (void)hipStreamSynchronize(b->stream);
+      delete b;
+    }
+  });
+}
+
+fn_status fn_batch_config(fn_batch* b, double tol, int32_t max_iter, int32_t use_graph) {
+  return guard([&] {
+    if (!b) throw Error(FN_E_INVALID, "batch is NULL");
+    b->tol = tol > 0.0 ? tol : 1e-7;
+    b->max_iter = max_iter > 0 ? max_iter : 500;
+    b->use_graph = use_graph != 0;
+    b->drop_graph();
+  });
+}
+
+fn_status fn_batch_set_slot(fn_batch* b, int32_t slot, const double* ev, int64_t n, const double* theta0,
+                            const int32_t* free_mask) {
+  return guard([&] {
+    if (!b || !theta0) throw Error(FN_E_INVALID, "NULL argument");
+    if (slot < 0 || slot >= b->max_fits) throw Error(FN_E_INVALID, "slot out of range");
+    if (n < 1 || n > b->max_ev) throw Error(FN_E_INVALID, "event count must be in [1, max_events_per_fit]");
+    if (!ev) throw Error(FN_E_INVALID, "events pointer is NULL");
+    hip_check(hipSetDevice(b->m->device), "hipSetDevice");
+    // the previous copy out of this staging entry must have completed
+    hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    BfgsState& s = b->h_st[slot];
+    std::memset(&s, 0, sizeof(s));
+    for (int i = 0; i < b->P; ++i) {
+      s.xt[i] = theta0[i];
+      s.mask[i] = free_mask ? (free_mask[i] != 0) : 1;
+    }
+    s.status = kFitRunning;
+    s.phase = kPhaseStart;
+    b->h_ev[slot] = ev;
+    b->h_nev[slot] = n;
+    hip_check(hipMemcpyAsync((BfgsState*)b->st.ptr + slot, &s, sizeof(BfgsState), hipMemcpyHostToDevice, b->stream),
+              "hipMemcpyAsync");
+    hip_check(hipMemcpyAsync((const double**)b->evp.ptr + slot, &b->h_ev[slot], sizeof(double*),
+                             hipMemcpyHostToDevice, b->stream),
+              "hipMemcpyAsync");
+    hip_check(hipMemcpyAsync((int64_t*)b->nev.ptr + slot, &b->h_nev[slot], sizeof(int64_t), hipMemcpyHostToDevice,
+                             b->stream),
+              "hipMemcpyAsync");
+  });
+}
+
+fn_status fn_batch_clear_slot(fn_batch* b, int32_t slot) {
+  return guard([&] {
+    if (!b) throw Error(FN_E_INVALID, "batch is NULL");
+    if (slot < 0 || slot >= b->max_fits) throw Error(FN_E_INVALID, "slot out of range");
+    hip_check(hipSetDevice(b->m->device), "hipSetDevice");
+    hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    // status lives at a fixed offset: write only that int
+    b->h_st[slot].status = kFitIdle;
+    hip_check(hipMemcpyAsync(&((BfgsState*)b->st.ptr)[slot].status, &b->h_st[slot].status, sizeof(int),
+                             hipMemcpyHostToDevice, b->stream),
+              "hipMemcpyAsync");
+    hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+  });
+}
+
+fn_status fn_batch_run(fn_batch* b, int32_t max_steps, int32_t poll_every, int32_t* steps_done,
+                       int32_t* n_running) {
+  return guard([&] {
+    if (!b) throw Error(FN_E_INVALID, "batch is NULL");
+    hip_check(hipSetDevice(b->m->device), "hipSetDevice");
+    if (poll_every < 1) poll_every = 1;
+    int done = 0;
+    int running = -1;
+    while (done < max_steps) {
+      const int k = std::min(poll_every, max_steps - done);
+      for (int i = 0; i < k; ++i) step(b);
+      done += k;
+      hip_check(hipMemcpyAsync(b->h_nrun, b->nrun.ptr, sizeof(int), hipMemcpyDeviceToHost, b->stream),
+                "hipMemcpyAsync");
+      hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+      running = *b->h_nrun;
+      if (running == 0) break;
+    }
+    if (steps_done) *steps_done = done;
+    if (n_running) *n_running = running;
+  });
+}
+
+fn_status fn_batch_results(fn_batch* b, int32_t* status, double* theta, double* nll, double* errors,
+                           int32_t* iters, int32_t* n_evals) {
+  return guard([&] {
+    if (!b) throw Error(FN_E_INVALID, "batch is NULL");
+    hip_check(hipSetDevice(b->m->device), "hipSetDevice");
+    std::vector<BfgsState> hs(b->max_fits);
+    hip_check(hipMemcpyAsync(hs.data(), b->st.ptr, sizeof(BfgsState) * b->max_fits, hipMemcpyDeviceToHost,
+                             b->stream),
+              "hipMemcpyAsync");
+    hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    const int P = b->P;
+    for (int f = 0; f < b->max_fits; ++f) {
+      const BfgsState& s = hs[f];
+      if (status) status[f] = s.status;
+      if (theta)
+        for (int i = 0; i < P; ++i) theta[(size_t)f * P + i] = s.x[i];
+      if (nll) nll[f] = s.f;
+      if (errors)
+        for (int i = 0; i < P; ++i)
+          errors[(size_t)f * P + i] = s.mask[i] ? std::sqrt(std::fabs(s.H[i * kBatchMaxP + i])) : 0.0;
+      if (iters) iters[f] = s.iter;
+      if (n_evals) n_evals[f] = s.n_eval;
+    }
+  });
+}
+
+fn_status fn_generate_mix1d(uint32_t seed, uint32_t fit, int64_t n, const double* theta_gen, double lo, double hi,
+                            double* x, void* stream) {
+  return guard([&] {
+    if (!theta_gen) throw Error(FN_E_INVALID, "theta_gen is NULL");
+    if (n < 0 || (n > 0 && !x)) throw Error(FN_E_INVALID, "bad output");
+    if (!(hi > lo) || !(theta_gen[1] > 0.0)) throw Error(FN_E_INVALID, "need hi > lo and sigma > 0");
+    if (n == 0) return;
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf cnt;
+    cnt.reserve(sizeof(unsigned int));
+    hip_check(hipMemsetAsync(cnt.ptr, 0, sizeof(unsigned int), s), "hipMemsetAsync");
+    batch_launch_gen_mix1d(seed, fit, 0u, n, theta_gen, lo, hi, x, (unsigned int*)cnt.ptr, s);
+    hip_check(hipGetLastError(), "kernel launch");
+    unsigned int bad = 0;
+    hip_check(hipMemcpyAsync(&bad, cnt.ptr, sizeof(bad), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (bad) throw Error(FN_E_DOMAIN, std::to_string(bad) + " events not resolved within the attempt limit");
+  });
+}
+
+}  // extern "C"

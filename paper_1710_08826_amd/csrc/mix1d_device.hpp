@@ -1,0 +1,230 @@
+// Device code of the one-observable mixture shared by the single-fit kernels
+// (mix1d.hip) and the batched ones (batch.hip): the prologue table, the
+// component shapes, the per-chunk evaluation and the level-2 step.
+#pragma once
+#include <cmath>
+
+#include "device_common.hpp"
+#include "fastmath.hpp"
+
+namespace fn {
+
+// Lower incomplete gamma function gamma(a, y), y >= 0, for a = 3/2 and 5/2.
+// Series y^a e^-y sum_n y^n / (a (a+1) ... (a+n)) below y = 1, closed forms
+// through erf above (gamma(3/2,y) = sqrt(pi)/2 erf(sqrt y) - sqrt(y) e^-y and
+// gamma(5/2,y) = 3/2 gamma(3/2,y) - y^(3/2) e^-y).
+__device__ inline double lower_gamma_half(int twice_a, double y) {
+  const double a = 0.5 * twice_a;
+  if (y <= 0.0) return 0.0;
+  if (y < 1.0) {
+    double term = 1.0 / a, sum = term;
+    for (int n = 1; n < 60; ++n) {
+      term *= y / (a + n);
+      sum += term;
+      if (term < 1e-18 * sum) break;
+    }
+    return pow(y, a) * exp(-y) * sum;
+  }
+  const double ry = sqrt(y);
+  const double g32 = 0.88622692545275801365 * erf(ry) - ry * exp(-y);
+  if (twice_a == 3) return g32;
+  return 1.5 * g32 - y * ry * exp(-y);
+}
+
+// theta -> per-fit table: fractions, 1/N_k and d ln N_k / d(parameters) of
+// each component from its closed-form integral on [lo, hi], shape constants.
+__device__ inline void mix1d_table(const Mix1dConst& mc, const double* __restrict__ th, Mix1dTable& out) {
+  Mix1dTable t;
+  bool ok = true;
+  const double lo = mc.lo, hi = mc.hi;
+  double rest = 1.0;
+  for (int k = 0; k < kMixMaxComp; ++k) {
+    t.frac[k] = 0.0; t.invN[k] = 0.0; t.a[k] = 0.0; t.b[k] = 0.0; t.c[k] = 0.0;
+    t.dlnN[k][0] = 0.0; t.dlnN[k][1] = 0.0;
+  }
+  for (int k = 0; k < mc.K; ++k) {
+    if (k < mc.K - 1) {
+      t.frac[k] = th[mc.fidx[k]];
+      rest -= t.frac[k];
+    } else {
+      t.frac[k] = rest;
+    }
+    const double p0 = th[mc.pidx[k][0]];
+    const double p1 = mc.npar[k] > 1 ? th[mc.pidx[k][1]] : 0.0;
+    double N = 0.0, d0 = 0.0, d1 = 0.0;
+    switch (mc.type[k]) {
+      case kGauss: {
+        const double mu = p0, sg = p1;
+        if (!(sg > 0.0)) { ok = false; break; }
+        const double s2 = sg * 1.41421356237309504880;
+        const double A = (lo - mu) / s2, B = (hi - mu) / s2;
+        double D;
+        if (A > 0.0) D = erfc(A) - erfc(B);
+        else if (B < 0.0) D = erfc(-B) - erfc(-A);
+        else D = erf(B) - erf(A);
+        N = sg * 1.25331413731550025121 * D;  // sqrt(pi/2)
+        const double eA = exp(-A * A), eB = exp(-B * B);
+        d0 = (eA - eB) / N;
+        d1 = 1.0 / sg + 1.41421356237309504880 * (A * eA - B * eB) / N;
+        t.a[k] = mu; t.b[k] = 1.0 / sg;
+        break;
+      }
+      case kExp: {
+        const double tau = p0, D = hi - lo;
+        if (fabs(tau) < 1e-12) N = D * (1.0 + 0.5 * tau * (hi + lo));
+        else N = exp(tau * lo) * expm1(tau * D) / tau;
+        const double td = tau * D;
+        if (fabs(td) < 1e-3) d0 = 0.5 * (hi + lo) + tau * D * D / 12.0 - td * td * td * D / 720.0;
+        else d0 = lo + D / (-expm1(-td)) - 1.0 / tau;
+        t.a[k] = tau;
+        break;
+      }
+      case kArgus: {
+        const double m0 = p0, c = p1;
+        if (!(m0 > 0.0) || !(c < 0.0)) { ok = false; break; }
+        const double kk = -c, im2 = 1.0 / (m0 * m0);
+        const double wlo = fmax(0.0, 1.0 - lo * lo * im2), whi = fmax(0.0, 1.0 - hi * hi * im2);
+        const double k32 = pow(kk, -1.5), k52 = pow(kk, -2.5), h = 0.5 * m0 * m0;
+        N = h * k32 * (lower_gamma_half(3, kk * wlo) - lower_gamma_half(3, kk * whi));
+        const double dNc = h * k52 * (lower_gamma_half(5, kk * wlo) - lower_gamma_half(5, kk * whi));
+        const double im3 = im2 / m0;
+        const double flo = wlo > 0.0 ? sqrt(wlo) * exp(-kk * wlo) * 2.0 * lo * lo * im3 : 0.0;
+        const double fhi = whi > 0.0 ? sqrt(whi) * exp(-kk * whi) * 2.0 * hi * hi * im3 : 0.0;
+        const double dNm = 2.0 * N / m0 + h * (flo - fhi);
+        d0 = dNm / N;
+        d1 = dNc / N;
+        t.a[k] = im2; t.b[k] = c; t.c[k] = 1.0 / m0;
+        break;
+      }
+      case kBW: {
+        const double m0 = p0, g = p1;
+        if (!(g > 0.0)) { ok = false; break; }
+        const double hg = 0.5 * g, uh = (hi - m0) / hg, ul = (lo - m0) / hg;
+        N = (atan(uh) - atan(ul)) / hg;
+        const double ih = 1.0 / (1.0 + uh * uh), il = 1.0 / (1.0 + ul * ul);
+        const double dNm = (il - ih) / (hg * hg);
+        const double dNg = -N / g + (-uh * ih + ul * il) / (g * hg);
+        d0 = dNm / N;
+        d1 = dNg / N;
+        t.a[k] = m0; t.b[k] = hg * hg; t.c[k] = g;
+        break;
+      }
+      default:
+        ok = false;
+    }
+    if (!(N > 0.0) || !isfinite(N)) ok = false;
+    t.invN[k] = 1.0 / N;
+    t.dlnN[k][0] = d0;
+    t.dlnN[k][1] = d1;
+  }
+  t.valid = ok ? 1.0 : 0.0;
+  out = t;
+}
+
+// Component shape s(x) and d ln s / d(its parameters).
+template <bool GRAD>
+__device__ inline double mix_shape(int type, const Mix1dTable& t, int k, double x,
+                                   double& dl0, double& dl1) {
+  switch (type) {
+    case kGauss: {
+      const double z = (x - t.a[k]) * t.b[k];
+      if (GRAD) { dl0 = z * t.b[k]; dl1 = z * z * t.b[k]; }
+      return exp(-0.5 * z * z);
+    }
+    case kExp: {
+      if (GRAD) { dl0 = x; dl1 = 0.0; }
+      return exp(t.a[k] * x);
+    }
+    case kArgus: {
+      const double w = 1.0 - x * x * t.a[k];
+      if (!(w > 0.0)) { if (GRAD) { dl0 = 0.0; dl1 = 0.0; } return 0.0; }
+      if (GRAD) { dl0 = (0.5 / w + t.b[k]) * 2.0 * x * x * t.a[k] * t.c[k]; dl1 = w; }
+      return x * sqrt(w) * exp(t.b[k] * w);
+    }
+    default: {  // kBW
+      const double d = x - t.a[k];
+      const double s = rcp_nr(__builtin_fma(d, d, t.b[k]));
+      if (GRAD) { dl0 = 2.0 * d * s; dl1 = -0.5 * t.c[k] * s; }
+      return s;
+    }
+  }
+}
+
+// One chunk of events -> one partial row (shared by the single-fit and the
+// batched launches so that both produce the same bits).
+template <bool GRAD, int KMAX>
+__device__ inline void mix1d_chunk(const Mix1dConst& mc, const Mix1dTable* __restrict__ tabp,
+                                   const double* __restrict__ x, int64_t n, int64_t chunk_idx,
+                                   int chunk, double* __restrict__ out_row, double* lds) {
+  constexpr int NV = GRAD ? mix_nv(KMAX) : 1;
+  const Mix1dTable& t = *tabp;
+  double acc[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+  const int64_t base = chunk_idx * chunk;
+  const int64_t end = base + chunk < n ? base + chunk : n;
+  for (int64_t i = base + threadIdx.x; i < end; i += kBlock) {
+    const double xv = x[i];
+    double u[KMAX], dl[KMAX][2];
+    double P = 0.0;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      u[k] = 0.0; dl[k][0] = 0.0; dl[k][1] = 0.0;
+      if (k < mc.K) {
+        u[k] = mix_shape<GRAD>(mc.type[k], t, k, xv, dl[k][0], dl[k][1]) * t.invN[k];
+        P += t.frac[k] * u[k];
+      }
+    }
+    acc[0] -= log_fast(P);
+    if (GRAD) {
+      const double w = -rcp_nr(P);
+      double ul = 0.0;  // density of the last component (it takes 1 - sum f)
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k)
+        if (k == mc.K - 1) ul = u[k];
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) {
+        if (k < mc.K) {
+          const double wu = w * t.frac[k] * u[k];
+          acc[1 + 2 * k] += wu * (dl[k][0] - t.dlnN[k][0]);
+          acc[2 + 2 * k] += wu * (dl[k][1] - t.dlnN[k][1]);
+          if (k < mc.K - 1) acc[1 + 2 * KMAX + k] += w * (u[k] - ul);
+        }
+      }
+    }
+  }
+  block_sum_row<NV>(acc, lds, out_row);
+}
+
+// Level 2 and the slot -> parameter map (slots sharing a parameter are added
+// in slot order).  out: [NLL, grad(P), I = 1, dI = 0]; out_user: [NLL, grad(P)].
+__device__ inline void mix1d_finalize_one(const Mix1dConst& mc, const Mix1dTable& t,
+                                          const double* part, int64_t nrows, int nv, int kmax,
+                                          int with_grad, double* out, double* out_user, double* scratch,
+                                          double* res) {
+  sum_rows(part, nrows, nv, scratch, res);
+  const int P = mc.n_params;
+  const int p = threadIdx.x;
+  const bool ok = t.valid != 0.0;
+  if (p == 0) {
+    out[0] = ok ? res[0] : INFINITY;
+    out[1 + P] = 1.0;
+    if (out_user) out_user[0] = out[0];
+  }
+  if (p < P) {
+    out[2 + P + p] = 0.0;
+    if (with_grad) {
+      double g = 0.0;
+      for (int k = 0; k < mc.K; ++k) {
+        for (int j = 0; j < mc.npar[k]; ++j)
+          if (mc.pidx[k][j] == p) g += res[1 + 2 * k + j];
+        if (k < mc.K - 1 && mc.fidx[k] == p) g += res[1 + 2 * kmax + k];
+      }
+      if (!ok) g = NAN;
+      out[1 + p] = g;
+      if (out_user) out_user[1 + p] = g;
+    }
+  }
+}
+
+}  // namespace fn

@@ -1,0 +1,125 @@
+"""Batched fits on the device: agreement with the single-fit path and the
+oracle's minimum, alone-vs-mix bitwise identity, slot reuse, fixed
+parameters; device toy generation against the shared sampler."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import mix1d as OM
+from tests.gpu_util import say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+D0 = synth.mix1d_desc()
+TRUTH = synth.mix1d_truth()
+START = TRUTH * np.array([1.1, 0.9, 1.15, 0.95])
+
+
+@pytest.fixture(scope="module")
+def model():
+    from paper_1710_08826_amd import Model
+    return Model(D0)
+
+
+def test_generator_matches_sampler():
+    from paper_1710_08826_amd import generate_mix1d
+    for n, seed, fit in ((1, 5, 0), (100_003, synth.BASE_SEED, 3), (20_000, 77, 4095)):
+        say("generate", n, seed, fit)
+        x = generate_mix1d(n, seed, fit, TRUTH).cpu().numpy()[0]
+        ref = synth.mix1d_events(n, seed=seed, fit=fit)
+        assert np.allclose(x, ref, rtol=1e-14, atol=1e-14), np.abs(x - ref).max()
+        assert (x >= -10).all() and (x <= 10).all()
+
+
+def _events(sizes, seed=900):
+    return [to_dev(synth.mix1d_events(int(n), seed=seed, fit=i)) for i, n in enumerate(sizes)]
+
+
+def test_batch_matches_single_fit_and_oracle(model):
+    from scipy import optimize
+    from paper_1710_08826_amd import Batch
+    sizes = [20_000, 3_000, 50_000, 1_000]
+    evs = _events(sizes)
+    b = Batch(model, len(sizes), max(sizes))
+    for i, e in enumerate(evs):
+        b.set_slot(i, e, START)
+    steps, running = b.run(2000, 4)
+    r = b.results()
+    say("steps", steps, "iters", r.iters, "evals", r.n_evals)
+    assert running == 0 and (r.status == 2).all()
+    for i, e in enumerate(evs):
+        one = model.fit(START, e)
+        x = e.cpu().numpy()[0]
+        res = optimize.minimize(lambda t: OM.nll_grad(t, x, D0), START, jac=True, method="L-BFGS-B",
+                                bounds=[(-5, 5), (0.1, 5), (-3, 3), (0.01, 0.99)],
+                                options={"ftol": 1e-15, "gtol": 1e-9, "maxiter": 2000})
+        assert (np.abs(r.theta[i] - one.theta) < 2e-3 * one.errors).all(), (r.theta[i], one.theta)
+        assert (np.abs(r.theta[i] - res.x) < 2e-3 * one.errors).all(), (r.theta[i], res.x)
+        assert abs(r.nll[i] - one.nll) < 1e-6
+        # BFGS inverse-Hessian errors approximate the numerical-Hessian errors
+        assert (np.abs(r.errors[i] / one.errors - 1) < 0.3).all(), (r.errors[i], one.errors)
+
+
+def test_alone_vs_mix_bitwise(model):
+    from paper_1710_08826_amd import Batch
+    sizes = [7_000, 40_000, 1_000, 120_000, 15_000, 2_500, 64_000, 9_999]
+    evs = _events(sizes, seed=901)
+    mix = Batch(model, len(sizes), max(sizes))
+    for i, e in enumerate(evs):
+        mix.set_slot(i, e, START)
+    mix.run(3000, 8)
+    rm = mix.results()
+    for i in (0, 3, 7):
+        alone = Batch(model, 1, sizes[i])
+        alone.set_slot(0, evs[i], START)
+        alone.run(3000, 8)
+        ra = alone.results()
+        assert ra.status[0] == rm.status[i] == 2
+        assert np.array_equal(ra.theta[0], rm.theta[i]) and ra.nll[0] == rm.nll[i]
+        assert ra.iters[0] == rm.iters[i] and ra.n_evals[0] == rm.n_evals[i]
+
+
+def test_graph_and_direct_launch_agree(model):
+    from paper_1710_08826_amd import Batch
+    evs = _events([30_000, 5_000], seed=902)
+    out = []
+    for g in (True, False):
+        b = Batch(model, 2, 30_000)
+        b.config(use_graph=g)
+        for i, e in enumerate(evs):
+            b.set_slot(i, e, START)
+        b.run(2000, 3)
+        out.append(b.results())
+    assert np.array_equal(out[0].theta, out[1].theta) and np.array_equal(out[0].nll, out[1].nll)
+
+
+def test_slot_reuse_and_fixed_parameters(model):
+    from paper_1710_08826_amd import Batch
+    evs = _events([10_000, 20_000], seed=903)
+    b = Batch(model, 1, 20_000)
+    b.set_slot(0, evs[0], START)
+    b.run(2000, 4)
+    first = b.results()
+    b.clear_slot(0)
+    assert b.results().status[0] == 0
+    start = START.copy()
+    start[2] = TRUTH[2]
+    b.set_slot(0, evs[1], start, free=[1, 1, 0, 1])
+    b.run(2000, 4)
+    r = b.results()
+    assert r.status[0] == 2 and r.theta[0][2] == TRUTH[2] and r.errors[0][2] == 0.0
+    one = model.fit(start, evs[1], free=[1, 1, 0, 1])
+    assert (np.abs(r.theta[0] - one.theta)[[0, 1, 3]] < 2e-3 * one.errors[[0, 1, 3]]).all()
+    assert first.status[0] == 2
+
+
+def test_invalid_start_fails_cleanly(model):
+    from paper_1710_08826_amd import Batch
+    evs = _events([5_000], seed=904)
+    b = Batch(model, 2, 5_000)
+    b.set_slot(0, evs[0], [0.2, -1.0, -0.3, 0.7])  # sigma < 0: not a density
+    b.set_slot(1, evs[0], START)
+    b.run(2000, 4)
+    r = b.results()
+    assert r.status[0] == 3 and r.status[1] == 2
