@@ -157,6 +157,73 @@ def pmc_probe(steps: int):
                       "nll": float(out[0])}), flush=True)
 
 
+def serving_leg(n_fits: int = 4096, one_at_a_time: int = 256, fd_fits: int = 32, lam_frac: float = 0.7):
+    """Config 2: toy fits of the config-0 model with per-fit sizes drawn
+    log-uniform in [1e3, 2e6], events generated on the device at admission.
+    Returns fits/s and latency percentiles for (a) all requests at t = 0 and
+    (b) Poisson arrivals at lam_frac x the batched throughput, on the
+    continuous-batching server; (c) one fit at a time (host BFGS, adjoint
+    gradient) and (d) one fit at a time with finite-difference gradients, on
+    subsamples of the same request list."""
+    import torch
+    import synth
+    from paper_1710_08826_amd import Model, Server, generate_mix1d
+    truth = synth.mix1d_truth()
+    start = truth * np.array([1.1, 0.9, 1.15, 0.95])
+    sizes = synth.lognormal_sizes(n_fits)
+    model = Model(synth.mix1d_desc())
+    base = [dict(id=i, n_events=int(sizes[i]), seed=synth.BASE_SEED, fit=i, theta_gen=truth, theta0=start,
+                 arrival_s=0.0) for i in range(n_fits)]
+    budget = int(min(200 << 30, 2 * int(sizes.sum()) * 8 + (1 << 30)))
+
+    def serve(reqs, slots):
+        srv = Server(model, max_slots=slots, max_events_per_fit=2_000_000, budget_bytes=budget)
+        srv.submit(reqs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        srv.run(poll_every=2)
+        wall = time.perf_counter() - t0
+        res = srv.results()
+        srv.close()
+        lat = np.array([r.latency for r in res])
+        ok = sum(1 for r in res if r.status == 2)
+        return {"fits": len(res), "converged": ok, "wall_s": wall, "fits_per_s": len(res) / wall,
+                "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+                "events": int(sum(r["n_events"] for r in reqs))}
+
+    out = {}
+    serve(base[:64], 64)  # warm-up: graph capture, allocations
+    out["closed_loop"] = serve(base, n_fits)
+    rate = lam_frac * out["closed_loop"]["fits_per_s"]
+    u, _ = synth.uniforms(n_fits, synth.key_from_seed(synth.BASE_SEED, 0xABC), 5)
+    arrivals = np.cumsum(-np.log1p(-u) / rate)
+    pois = [dict(r, arrival_s=float(arrivals[i])) for i, r in enumerate(base)]
+    out["poisson"] = serve(pois, n_fits)
+    out["poisson"]["rate_per_s"] = rate
+
+    def sequential(reqs, mode):
+        lat = []
+        t0 = time.perf_counter()
+        for q in reqs:
+            ev = generate_mix1d(q["n_events"], q["seed"], q["fit"], truth)
+            model.fit(start, ev, grad_mode=mode, raise_on_fail=False)
+            lat.append(time.perf_counter() - t0)
+        wall = time.perf_counter() - t0
+        return {"fits": len(reqs), "wall_s": wall, "fits_per_s": len(reqs) / wall,
+                "events": int(sum(r["n_events"] for r in reqs))}
+
+    sub = base[:: max(1, n_fits // one_at_a_time)][:one_at_a_time]
+    out["one_at_a_time_adjoint"] = sequential(sub, "adjoint")
+    subfd = base[:: max(1, n_fits // fd_fits)][:fd_fits]
+    out["one_at_a_time_fd"] = sequential(subfd, "fd")
+    # the same request subsample on the batched server, for a like-for-like ratio
+    out["batched_same_subsample_fd"] = serve(subfd, len(subfd))
+    out["speedup_batched_vs_plain_fd"] = out["closed_loop"]["fits_per_s"] / out["one_at_a_time_fd"]["fits_per_s"]
+    out["speedup_batched_vs_one_at_a_time_adjoint"] = (out["closed_loop"]["fits_per_s"]
+                                                      / out["one_at_a_time_adjoint"]["fits_per_s"])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -267,6 +334,16 @@ def main():
         extra["config0_fit_speedup_adjoint_vs_fd"] = extra["config0_fit_fd_ms"] / extra["config0_fit_adjoint_ms"]
         print(f"[bench] config0 fits: adjoint {extra['config0_fit_adjoint_ms']:.2f} ms, "
               f"fd {extra['config0_fit_fd_ms']:.2f} ms", file=sys.stderr, flush=True)
+
+    if not args.quick:
+        print("[bench] config2 serving (4096 toy fits) ...", file=sys.stderr, flush=True)
+        sv = serving_leg()
+        extra["config2_serving"] = sv
+        print(f"[bench] config2: {sv['closed_loop']['fits_per_s']:.4g} fits/s closed loop, "
+              f"Poisson p50 {sv['poisson']['p50_latency_s'] * 1e3:.2f} ms p99 "
+              f"{sv['poisson']['p99_latency_s'] * 1e3:.2f} ms; one-at-a-time adjoint "
+              f"{sv['one_at_a_time_adjoint']['fits_per_s']:.4g} fits/s, plain FD "
+              f"{sv['one_at_a_time_fd']['fits_per_s']:.4g} fits/s", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.quick and not args.no_cpu:

@@ -213,6 +213,51 @@ fn_status fn_batch_results(fn_batch* b, int32_t* status, double* theta, double* 
 fn_status fn_generate_mix1d(uint32_t seed, uint32_t fit, int64_t n, const double* theta_gen, double lo, double hi,
                             double* x, void* stream);
 
+/* ----------------------------------------------------------------- serving
+ * A request loop over one batch: requests (toy-MC or systematic-variation
+ * fits of a mix1d model) arrive at given times, are admitted at step
+ * boundaries when a slot is free and their events fit the device-memory
+ * budget, have their events generated on the device (or use caller events),
+ * run inside the batch with the fits already on the GPU, and retire when
+ * converged or failed, freeing slot and memory for queued requests
+ * (continuous batching).  A request's result does not depend on which other
+ * requests shared the batch. */
+typedef struct fn_server fn_server;
+
+typedef struct {
+  int64_t id;
+  int64_t n_events;
+  uint32_t seed, fit;       /* generation key when events == NULL */
+  const double* events;     /* optional caller-owned device events (n_events) */
+  double theta_gen[4];      /* generation point (mu, sigma, tau, f) */
+  double theta0[24];        /* start point, first P entries used */
+  double arrival_s;         /* arrival time, seconds after fn_server_run starts */
+} fn_request;
+
+typedef struct {
+  int64_t id;
+  int32_t status;           /* FN_FIT_CONVERGED, FN_FIT_FAILED, or FN_E_BUDGET if it can never fit */
+  int32_t iters, n_evals, pad;
+  double nll;
+  double theta[24], errors[24];
+  double t_arrival, t_admit, t_done;  /* seconds after the run started */
+} fn_result;
+
+/* Server over a mix1d model whose components are (gauss, exp) when events are
+ * generated: max_slots concurrent fits, at most max_events_per_fit events per
+ * request, budget_bytes of device memory for request events. */
+fn_status fn_server_create(fn_model* m, int32_t max_slots, int64_t max_events_per_fit, int64_t budget_bytes,
+                           fn_server** out);
+fn_status fn_server_destroy(fn_server* s);
+/* Queue requests (copied). */
+fn_status fn_server_submit(fn_server* s, const fn_request* reqs, int32_t n);
+/* Serve every queued request (arrival times relative to the call), stepping
+ * the batch poll_every steps between admission/retirement checks; stops early
+ * after max_seconds (> 0).  Synchronous. */
+fn_status fn_server_run(fn_server* s, int32_t poll_every, double max_seconds, int32_t* n_done);
+/* Results of finished requests, in completion order; *n_out <= max. */
+fn_status fn_server_results(fn_server* s, fn_result* out, int32_t max, int32_t* n_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -59,6 +59,11 @@ PROTOTYPES = {
     "fn_batch_run": (i32, [vp, i32, i32, C.POINTER(i32), C.POINTER(i32)]),
     "fn_batch_results": (i32, [vp, C.POINTER(i32), dp, dp, dp, C.POINTER(i32), C.POINTER(i32)]),
     "fn_generate_mix1d": (i32, [C.c_uint32, C.c_uint32, i64, dp, C.c_double, C.c_double, vp, vp]),
+    "fn_server_create": (i32, [vp, i32, i64, i64, C.POINTER(vp)]),
+    "fn_server_destroy": (i32, [vp]),
+    "fn_server_submit": (i32, [vp, vp, i32]),
+    "fn_server_run": (i32, [vp, i32, C.c_double, C.POINTER(i32)]),
+    "fn_server_results": (i32, [vp, vp, i32, C.POINTER(i32)]),
 }
 
 _lib = None

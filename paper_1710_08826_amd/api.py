@@ -276,3 +276,103 @@ def generate_mix1d(n: int, seed: int, fit: int, theta_gen, lo: float = -10.0, hi
     check(lib.fn_generate_mix1d(C.c_uint32(seed & 0xFFFFFFFF), C.c_uint32(fit & 0xFFFFFFFF), int(n), thp,
                                 float(lo), float(hi), C.c_void_p(x.data_ptr() if n else 0), _stream_ptr(stream)))
     return x
+
+
+class _Request(C.Structure):
+    _fields_ = [("id", C.c_int64), ("n_events", C.c_int64), ("seed", C.c_uint32), ("fit", C.c_uint32),
+                ("events", C.c_void_p), ("theta_gen", C.c_double * 4), ("theta0", C.c_double * 24),
+                ("arrival_s", C.c_double)]
+
+
+class _Result(C.Structure):
+    _fields_ = [("id", C.c_int64), ("status", C.c_int32), ("iters", C.c_int32), ("n_evals", C.c_int32),
+                ("pad", C.c_int32), ("nll", C.c_double), ("theta", C.c_double * 24), ("errors", C.c_double * 24),
+                ("t_arrival", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double)]
+
+
+@dataclass
+class ServeResult:
+    id: int
+    status: int
+    iters: int
+    n_evals: int
+    nll: float
+    theta: np.ndarray
+    errors: np.ndarray
+    t_arrival: float
+    t_admit: float
+    t_done: float
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.t_arrival
+
+
+class Server:
+    """Continuous-batching request loop for toy fits of a mix1d model (see
+    fn_server_* in include/fitnll.h)."""
+
+    def __init__(self, model: Model, max_slots: int, max_events_per_fit: int, budget_bytes: int):
+        self.model = model
+        self._lib = model._lib
+        h = C.c_void_p()
+        check(self._lib.fn_server_create(model._h, int(max_slots), int(max_events_per_fit), int(budget_bytes),
+                                         C.byref(h)))
+        self._h = h
+        self._keep = []
+        self._n_submitted = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.fn_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, requests):
+        """requests: iterable of dicts with id, n_events, theta0, arrival_s and
+        either (seed, fit, theta_gen) or events (a (1, n) float64 CUDA tensor)."""
+        reqs = list(requests)
+        arr = (_Request * len(reqs))()
+        P = self.model.n_params
+        for i, q in enumerate(reqs):
+            r = arr[i]
+            r.id = int(q["id"])
+            r.n_events = int(q["n_events"])
+            r.seed = int(q.get("seed", 0)) & 0xFFFFFFFF
+            r.fit = int(q.get("fit", 0)) & 0xFFFFFFFF
+            ev = q.get("events")
+            if ev is not None:
+                self._keep.append(ev)
+                r.events = ev.data_ptr()
+            else:
+                r.events = None
+            for j, v in enumerate(q.get("theta_gen", [0.0, 1.0, 0.0, 0.0])[:4]):
+                r.theta_gen[j] = float(v)
+            for j, v in enumerate(list(q["theta0"])[:P]):
+                r.theta0[j] = float(v)
+            r.arrival_s = float(q.get("arrival_s", 0.0))
+        check(self._lib.fn_server_submit(self._h, arr, len(reqs)))
+        self._n_submitted += len(reqs)
+
+    def run(self, poll_every: int = 4, max_seconds: float = 0.0) -> int:
+        n = C.c_int32()
+        check(self._lib.fn_server_run(self._h, int(poll_every), float(max_seconds), C.byref(n)))
+        return n.value
+
+    def results(self):
+        cap = max(self._n_submitted, 1)
+        arr = (_Result * cap)()
+        n = C.c_int32()
+        check(self._lib.fn_server_results(self._h, arr, cap, C.byref(n)))
+        P = self.model.n_params
+        out = []
+        for i in range(n.value):
+            r = arr[i]
+            out.append(ServeResult(r.id, r.status, r.iters, r.n_evals, r.nll, np.array(r.theta[:P]),
+                                   np.array(r.errors[:P]), r.t_arrival, r.t_admit, r.t_done))
+        return out

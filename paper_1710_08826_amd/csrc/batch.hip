@@ -285,13 +285,7 @@ __device__ inline double zoom_trial(const BfgsState& s) {
   return a;
 }
 
-__global__ void batch_bfgs(BfgsState* __restrict__ st, const double* __restrict__ out, int out_stride, int n_fits,
-                           int P, double tol, int max_iter) {
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= n_fits) return;
-  BfgsState& s = st[f];
-  if (s.status != kFitRunning) return;
-  const double* o = out + (int64_t)f * out_stride;
+__device__ void bfgs_update(BfgsState& s, const double* __restrict__ o, int P, double tol, int max_iter) {
   double ft = o[0];
   double gt[kBatchMaxP];
   bool ok = isfinite(ft);
@@ -393,6 +387,30 @@ __global__ void batch_bfgs(BfgsState* __restrict__ st, const double* __restrict_
   set_trial(s, P, zoom_trial(s));
 }
 
+// One minimizer step per running fit; every slot's status is mirrored into
+// stat[], and a fit that retires in this step writes its result row
+// [NLL, iterations, evaluations, theta(P), sqrt|H_ii|(P)] into rres.
+__global__ void batch_bfgs(BfgsState* __restrict__ st, const double* __restrict__ out, int out_stride, int n_fits,
+                           int P, double tol, int max_iter, int* __restrict__ stat, double* __restrict__ rres) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= n_fits) return;
+  BfgsState& s = st[f];
+  if (s.status == kFitRunning) {
+    bfgs_update(s, out + (int64_t)f * out_stride, P, tol, max_iter);
+    if (s.status != kFitRunning) {
+      double* r = rres + (int64_t)f * (3 + 2 * P);
+      r[0] = s.f;
+      r[1] = s.iter;
+      r[2] = s.n_eval;
+      for (int i = 0; i < P; ++i) {
+        r[3 + i] = s.x[i];
+        r[3 + P + i] = s.mask[i] ? sqrt(fabs(s.H[i * kBatchMaxP + i])) : 0.0;
+      }
+    }
+  }
+  stat[f] = s.status;
+}
+
 // ---------------------------------------------------------------- launchers
 void batch_launch_gen_mix1d(uint32_t k0, uint32_t k1, uint32_t word, int64_t n, const double* theta_gen, double lo,
                             double hi, double* x, unsigned int* n_unresolved, hipStream_t s) {
@@ -416,7 +434,7 @@ void batch_launch_step(const BatchDev& b, const Mix1dConst& mc, int n_fits, int 
                        b.item_base, b.part_base, n_fits, chunk, b.part);
   hipLaunchKernelGGL(batch_finalize, dim3(n_fits), dim3(kBlock), 0, s, mc, b.tabs, b.st, b.nev, b.part_base, b.part,
                      chunk, nv, kmax, b.out, 2 + 2 * P);
-  hipLaunchKernelGGL(batch_bfgs, fg, fb, 0, s, b.st, b.out, 2 + 2 * P, n_fits, P, tol, max_iter);
+  hipLaunchKernelGGL(batch_bfgs, fg, fb, 0, s, b.st, b.out, 2 + 2 * P, n_fits, P, tol, max_iter, b.stat, b.rres);
 }
 
 int batch_eval_blocks_per_cu(const Mix1dConst& mc) {

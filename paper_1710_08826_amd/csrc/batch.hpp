@@ -36,6 +36,8 @@ struct BatchDev {
   double* part;            // partial rows
   double* out;             // per slot [NLL, grad(P), I, dI(P)]
   int* n_running;
+  int* stat;               // per slot status, mirrored every step
+  double* rres;            // per slot result row, written when the fit retires (3 + 2P)
 };
 
 void batch_launch_step(const BatchDev& b, const Mix1dConst& mc, int n_fits, int P, int chunk, int eval_grid,

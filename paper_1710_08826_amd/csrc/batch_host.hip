@@ -23,7 +23,7 @@ struct fn_batch {
   bool use_graph = true;
   hipStream_t stream = nullptr;
   hipGraphExec_t exec = nullptr;
-  DevBuf st, tabs, evp, nev, item_base, part_base, part, out, nrun;
+  DevBuf st, tabs, evp, nev, item_base, part_base, part, out, nrun, stat, rres;
   // pinned staging of per-slot inputs (stable sources for async copies)
   BfgsState* h_st = nullptr;
   const double** h_ev = nullptr;
@@ -40,6 +40,8 @@ struct fn_batch {
     d.part = (double*)part.ptr;
     d.out = (double*)out.ptr;
     d.n_running = (int*)nrun.ptr;
+    d.stat = (int*)stat.ptr;
+    d.rres = (double*)rres.ptr;
     return d;
   }
   void drop_graph() {
@@ -113,6 +115,9 @@ fn_status fn_batch_create(fn_model* m, int32_t max_fits, int64_t max_events_per_
     b->part.reserve(sizeof(double) * (size_t)b->rows_per_slot * max_fits * nv);
     b->out.reserve(sizeof(double) * (size_t)max_fits * (2 + 2 * b->P));
     b->nrun.reserve(sizeof(int));
+    b->stat.reserve(sizeof(int) * max_fits);
+    b->rres.reserve(sizeof(double) * (size_t)max_fits * (3 + 2 * b->P));
+    hip_check(hipMemsetAsync(b->stat.ptr, 0, sizeof(int) * max_fits, b->stream), "hipMemsetAsync");
     b->h_st = (BfgsState*)pinned(sizeof(BfgsState) * max_fits);
     b->h_ev = (const double**)pinned(sizeof(double*) * max_fits);
     b->h_nev = (int64_t*)pinned(sizeof(int64_t) * max_fits);
@@ -274,3 +279,56 @@ fn_status fn_generate_mix1d(uint32_t seed, uint32_t fit, int64_t n, const double
 }
 
 }  // extern "C"
+
+// ------------------------------------------------ internal hooks for serving
+namespace fn {
+
+hipStream_t batch_stream(fn_batch* b) { return b->stream; }
+int batch_params(fn_batch* b) { return b->P; }
+int batch_slots(fn_batch* b) { return b->max_fits; }
+
+// Enqueue a fit into a slot without waiting: the staging entry of this slot
+// is only rewritten after the caller has synchronised the batch stream.
+void batch_set_slot_async(fn_batch* b, int slot, const double* ev, int64_t n, const double* theta0) {
+  BfgsState& s = b->h_st[slot];
+  std::memset(&s, 0, sizeof(s));
+  for (int i = 0; i < b->P; ++i) {
+    s.xt[i] = theta0[i];
+    s.mask[i] = 1;
+  }
+  s.status = kFitRunning;
+  s.phase = kPhaseStart;
+  b->h_ev[slot] = ev;
+  b->h_nev[slot] = n;
+  hip_check(hipMemcpyAsync((BfgsState*)b->st.ptr + slot, &s, sizeof(BfgsState), hipMemcpyHostToDevice, b->stream),
+            "hipMemcpyAsync");
+  hip_check(hipMemcpyAsync((const double**)b->evp.ptr + slot, &b->h_ev[slot], sizeof(double*), hipMemcpyHostToDevice,
+                           b->stream),
+            "hipMemcpyAsync");
+  hip_check(hipMemcpyAsync((int64_t*)b->nev.ptr + slot, &b->h_nev[slot], sizeof(int64_t), hipMemcpyHostToDevice,
+                           b->stream),
+            "hipMemcpyAsync");
+}
+
+void batch_steps(fn_batch* b, int k) {
+  for (int i = 0; i < k; ++i) step(b);
+}
+
+// Copy the per-slot status mirror to pinned host memory and wait.
+void batch_poll(fn_batch* b, int* stat_host) {
+  hip_check(hipMemcpyAsync(stat_host, b->stat.ptr, sizeof(int) * b->max_fits, hipMemcpyDeviceToHost, b->stream),
+            "hipMemcpyAsync");
+  hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+}
+
+// Copy the result rows (3 + 2P doubles) of the given slots and wait.
+void batch_read_rows(fn_batch* b, const int* slots, int n, double* rows_host) {
+  const int w = 3 + 2 * b->P;
+  for (int i = 0; i < n; ++i)
+    hip_check(hipMemcpyAsync(rows_host + (size_t)i * w, (double*)b->rres.ptr + (size_t)slots[i] * w,
+                             sizeof(double) * w, hipMemcpyDeviceToHost, b->stream),
+              "hipMemcpyAsync");
+  hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+}
+
+}  // namespace fn

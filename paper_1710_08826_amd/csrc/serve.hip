@@ -1,0 +1,266 @@
+// Continuous-batching request loop over one fn_batch (fn_server_*).
+//
+// Loop: admit visible requests into free slots while their events fit the
+// device-memory budget (first-fit arena, no hipMalloc/hipFree in the loop),
+// generate their events on the batch stream, advance the batch poll_every
+// steps, read the per-slot status mirror, retire finished fits (result rows,
+// timestamps, arena space and slot released), repeat.  New requests join at
+// step boundaries while earlier ones are still running.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <map>
+#include <thread>
+#include <vector>
+
+#include "batch.hpp"
+#include "internal.hpp"
+#include "serve.hpp"
+
+using namespace fn;
+
+namespace {
+
+// First-fit allocator over [0, size) with coalescing, in 256-byte units.
+class Arena {
+ public:
+  explicit Arena(int64_t size = 0) { reset(size); }
+  void reset(int64_t size) {
+    free_.clear();
+    if (size > 0) free_[0] = size;
+    size_ = size;
+  }
+  int64_t alloc(int64_t bytes) {
+    bytes = (bytes + 255) & ~int64_t(255);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        const int64_t off = it->first, rest = it->second - bytes;
+        free_.erase(it);
+        if (rest > 0) free_[off + bytes] = rest;
+        return off;
+      }
+    }
+    return -1;
+  }
+  void release(int64_t off, int64_t bytes) {
+    bytes = (bytes + 255) & ~int64_t(255);
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  int64_t size() const { return size_; }
+
+ private:
+  std::map<int64_t, int64_t> free_;
+  int64_t size_ = 0;
+};
+
+struct Pending {
+  fn_request r;
+  int64_t off = -1;
+  int64_t bytes = 0;
+  double t_admit = -1.0;
+};
+
+}  // namespace
+
+struct fn_server {
+  fn_model* m = nullptr;
+  fn_batch* b = nullptr;
+  int slots = 0;
+  int P = 0;
+  int64_t max_ev = 0;
+  int64_t budget = 0;
+  DevBuf arena_mem;
+  Arena arena;
+  DevBuf gen_count;
+  std::vector<Pending> queue;           // submitted, not yet admitted
+  std::vector<int> slot_req;            // slot -> index into running, -1 free
+  std::vector<Pending> running;         // by slot
+  std::vector<fn_result> done;
+  int* h_stat = nullptr;
+  double* h_rows = nullptr;
+  ~fn_server() {
+    if (b) fn_batch_destroy(b);
+    if (h_stat) (void)hipHostFree(h_stat);
+    if (h_rows) (void)hipHostFree(h_rows);
+  }
+};
+
+extern "C" {
+
+fn_status fn_server_create(fn_model* m, int32_t max_slots, int64_t max_events_per_fit, int64_t budget_bytes,
+                           fn_server** out) {
+  fn_server* s = nullptr;
+  const fn_status st = guard([&] {
+    if (!m || !out) throw Error(FN_E_INVALID, "NULL argument");
+    if (budget_bytes < 256) throw Error(FN_E_INVALID, "budget too small");
+    s = new fn_server;
+    s->m = m;
+    const fn_status bs = fn_batch_create(m, max_slots, max_events_per_fit, &s->b);
+    if (bs != FN_OK) throw Error(bs, fn_last_error());
+    s->slots = max_slots;
+    s->P = m->P;
+    s->max_ev = max_events_per_fit;
+    s->budget = budget_bytes;
+    s->arena_mem.reserve((size_t)budget_bytes);
+    s->arena.reset(budget_bytes);
+    s->gen_count.reserve(sizeof(unsigned int));
+    s->slot_req.assign(max_slots, -1);
+    s->running.resize(max_slots);
+    if (hipHostMalloc((void**)&s->h_stat, sizeof(int) * max_slots, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&s->h_rows, sizeof(double) * max_slots * (3 + 2 * s->P), hipHostMallocDefault) !=
+            hipSuccess)
+      throw Error(FN_E_NOMEM, "hipHostMalloc failed");
+    *out = s;
+  });
+  if (st != FN_OK) delete s;
+  return st;
+}
+
+fn_status fn_server_destroy(fn_server* s) {
+  return guard([&] { delete s; });
+}
+
+fn_status fn_server_submit(fn_server* s, const fn_request* reqs, int32_t n) {
+  return guard([&] {
+    if (!s || (n > 0 && !reqs)) throw Error(FN_E_INVALID, "NULL argument");
+    for (int i = 0; i < n; ++i) {
+      Pending p;
+      p.r = reqs[i];
+      if (p.r.n_events < 1 || p.r.n_events > s->max_ev) throw Error(FN_E_INVALID, "request event count out of range");
+      p.bytes = p.r.n_events * (int64_t)sizeof(double);
+      s->queue.push_back(p);
+    }
+    std::stable_sort(s->queue.begin(), s->queue.end(),
+                     [](const Pending& a, const Pending& c) { return a.r.arrival_s < c.r.arrival_s; });
+  });
+}
+
+fn_status fn_server_run(fn_server* s, int32_t poll_every, double max_seconds, int32_t* n_done) {
+  return guard([&] {
+    if (!s) throw Error(FN_E_INVALID, "server is NULL");
+    hip_check(hipSetDevice(s->m->device), "hipSetDevice");
+    if (poll_every < 1) poll_every = 1;
+    const Mix1dConst& mc = s->m->mix;
+    const bool can_generate = mc.K == 2 && mc.type[0] == kGauss && mc.type[1] == kExp;
+    hipStream_t st = batch_stream(s->b);
+    const auto t0 = std::chrono::steady_clock::now();
+    auto now = [&] { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
+    const int W = 3 + 2 * s->P;
+    size_t next = 0;  // queue is sorted by arrival
+    int n_running = 0;
+    std::vector<int> fin_slots;
+    while (true) {
+      const double t = now();
+      if (max_seconds > 0.0 && t > max_seconds) break;
+      // admission: arrivals visible now, free slot, budget
+      bool admitted = false;
+      while (next < s->queue.size() && s->queue[next].r.arrival_s <= t) {
+        Pending& p = s->queue[next];
+        if (p.bytes > s->budget) {
+          fn_result r;
+          std::memset(&r, 0, sizeof(r));
+          r.id = p.r.id;
+          r.status = FN_E_BUDGET;
+          r.t_arrival = p.r.arrival_s;
+          r.t_admit = r.t_done = t;
+          s->done.push_back(r);
+          ++next;
+          continue;
+        }
+        int slot = -1;
+        for (int k = 0; k < s->slots; ++k)
+          if (s->slot_req[k] < 0) {
+            slot = k;
+            break;
+          }
+        if (slot < 0) break;
+        const double* ev = p.r.events;
+        if (!ev) {
+          if (!can_generate) throw Error(FN_E_INVALID, "generation needs a (gauss, exp) mixture model");
+          p.off = s->arena.alloc(p.bytes);
+          if (p.off < 0) break;  // wait for memory to free up
+          double* x = (double*)((char*)s->arena_mem.ptr + p.off);
+          batch_launch_gen_mix1d(p.r.seed, p.r.fit, 0u, p.r.n_events, p.r.theta_gen, mc.lo, mc.hi, x,
+                                 (unsigned int*)s->gen_count.ptr, st);
+          ev = x;
+        }
+        p.t_admit = t;
+        batch_set_slot_async(s->b, slot, ev, p.r.n_events, p.r.theta0);
+        s->running[slot] = p;
+        s->slot_req[slot] = 1;
+        ++n_running;
+        ++next;
+        admitted = true;
+      }
+      if (admitted) hip_check(hipGetLastError(), "kernel launch");
+      if (n_running == 0) {
+        if (next >= s->queue.size()) break;
+        // idle until the next arrival
+        const double wait = s->queue[next].r.arrival_s - now();
+        if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(std::min(wait, 1e-3)));
+        continue;
+      }
+      batch_steps(s->b, poll_every);
+      batch_poll(s->b, s->h_stat);
+      fin_slots.clear();
+      for (int k = 0; k < s->slots; ++k)
+        if (s->slot_req[k] >= 0 && (s->h_stat[k] == kFitConverged || s->h_stat[k] == kFitFailed))
+          fin_slots.push_back(k);
+      if (!fin_slots.empty()) {
+        batch_read_rows(s->b, fin_slots.data(), (int)fin_slots.size(), s->h_rows);
+        const double td = now();
+        for (size_t i = 0; i < fin_slots.size(); ++i) {
+          const int k = fin_slots[i];
+          Pending& p = s->running[k];
+          const double* row = s->h_rows + i * W;
+          fn_result r;
+          std::memset(&r, 0, sizeof(r));
+          r.id = p.r.id;
+          r.status = s->h_stat[k];
+          r.nll = row[0];
+          r.iters = (int32_t)row[1];
+          r.n_evals = (int32_t)row[2];
+          for (int j = 0; j < s->P; ++j) {
+            r.theta[j] = row[3 + j];
+            r.errors[j] = row[3 + s->P + j];
+          }
+          r.t_arrival = p.r.arrival_s;
+          r.t_admit = p.t_admit;
+          r.t_done = td;
+          s->done.push_back(r);
+          if (p.off >= 0) s->arena.release(p.off, p.bytes);
+          s->slot_req[k] = -1;
+          --n_running;
+        }
+      }
+    }
+    // drop what was admitted (their results are in `done`)
+    s->queue.erase(s->queue.begin(), s->queue.begin() + next);
+    if (n_done) *n_done = (int32_t)s->done.size();
+  });
+}
+
+fn_status fn_server_results(fn_server* s, fn_result* out, int32_t max, int32_t* n_out) {
+  return guard([&] {
+    if (!s || (max > 0 && !out)) throw Error(FN_E_INVALID, "NULL argument");
+    const int n = std::min<int>(max, (int)s->done.size());
+    for (int i = 0; i < n; ++i) out[i] = s->done[i];
+    if (n_out) *n_out = n;
+  });
+}
+
+}  // extern "C"

@@ -63,3 +63,22 @@ def test_missing_library_fails_loudly(tmp_path):
             _lib.load(str(tmp_path / "nope.so"))
         finally:
             _lib._lib = saved
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """sizeof/offsetof of the request/result structs, compiled from the C
+    header with gcc, equal the ctypes mirrors in the binding."""
+    import subprocess
+    from paper_1710_08826_amd import api
+    src = tmp_path / "s.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "fitnll.h"\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(fn_request), sizeof(fn_result),'
+                   ' offsetof(fn_request, arrival_s), offsetof(fn_result, t_done), offsetof(fn_result, theta));'
+                   'return 0;}\n')
+    exe = tmp_path / "s"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    got = [int(v) for v in out]
+    want = [C.sizeof(api._Request), C.sizeof(api._Result), api._Request.arrival_s.offset,
+            api._Result.t_done.offset, api._Result.theta.offset]
+    assert got == want
