@@ -1,0 +1,212 @@
+"""Oracle for the time-dependent four-body amplitude model (the paper's
+four-body time-dependent amplitude analyses, Abstract and Sec. 5; the paper
+gives no formulas, so everything here is a reading).
+
+Final state D0 -> h1 h2 h3 h4 with pairs (12) and (34); observables
+(m12, m34, cos theta12, cos theta34, phi, t): two pair masses, the two
+helicity angles, the angle between the decay planes and the decay time.
+
+Amplitudes.  Basis functions B_k = a12[r1_k](m12) a34[r2_k](m34) Omega_k with
+  a[r](m) = 1 for a non-resonant entry (m0 = 0), else
+  [F_L(q r)/F_L(q0 r)] T(m^2), T = 1/(m0^2 - s - i m0 Gamma(s)) with the
+  mass-dependent width of the three-body model (q: daughter momentum in the
+  pair frame, Blatt-Weisskopf F_0 = 1, F_1 = (1+z)^-1/2),
+  Omega by helicity structure: 0 S x S: 1;  1 S x V: c34;  2 V x S: c12;
+  3 V x V (lambda 0): c12 c34;  4 V x V (lambda +1): 1/2 s12 s34 e^{i phi};
+  5 V x V (lambda -1): 1/2 s12 s34 e^{-i phi}   (s = sqrt(1 - c^2)).
+A = sum_k c_k B_k and Abar = sum_k cbar_k B_k (same basis, two coefficient sets).
+
+Time dependence (q/p = 1, Gamma = 1/tau, mixing x, y):
+  R(x, t) = 1/2 e^{-Gamma t} [(|A|^2 + |Abar|^2) cosh(y Gamma t) + (|A|^2 - |Abar|^2) cos(x Gamma t)
+            - 2 Re(A* Abar) sinh(y Gamma t) - 2 Im(A* Abar) sin(x Gamma t)]   (t >= 0),
+convolved with a Gaussian resolution of width sigma_t: with
+  h(a; t) = [e^{-a u} theta(u)] (x) G_sigma (t) = 1/2 exp(a^2 sigma^2/2 - a t) erfc((a sigma^2 - t)/(sigma sqrt2)),
+e^{-Gamma t} cosh -> (h(G(1-y)) + h(G(1+y)))/2, sinh -> (h(G(1-y)) - h(G(1+y)))/2,
+cos -> Re h(G(1 - i x)), sin -> Im h(G(1 - i x)).  h is evaluated through the
+Faddeeva function w (scipy.special.wofz here): with z = (a sigma^2 - t)/(sigma sqrt2),
+h = 1/2 e^{-t^2/(2 sigma^2)} w(i z) for Re z >= 0, and
+h = e^{a^2 sigma^2/2 - a t} - 1/2 e^{-t^2/(2 sigma^2)} w(-i z) otherwise.
+
+Normalization: the t integral over the real line keeps the unconvolved
+integrals 1/(G(1-y^2)), y/(G(1-y^2)), 1/(G(1+x^2)), x/(G(1+x^2)); I is the
+average over an unweighted phase-space sample of
+  1/2 [(|A|^2+|Abar|^2)/(G(1-y^2)) + (|A|^2-|Abar|^2)/(G(1+x^2))
+       - 2 Re(A* Abar) y/(G(1-y^2)) - 2 Im(A* Abar) x/(G(1+x^2))].
+
+theta = (Re c_k, Im c_k)_k, (Re cbar_k, Im cbar_k)_k, x, y.
+
+Pins (tests/test_oracle_td4.py): h against direct quadrature of the
+convolution (real and complex a, t from -0.3 to 5 ps), the sigma -> 0 limit,
+the integral of h over t equal to 1/a, the t-integral of R against the
+normalization formula, factorization at x = y = 0, orthogonality of the six
+angular functions on the angle space, the pole-mass value of T, and
+autograd against central differences.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+from scipy.special import wofz
+
+from .common import as_t, fsum, nll_value
+
+SQRT_2PI = math.sqrt(2.0 * math.pi)
+
+
+class _H(torch.autograd.Function):
+    """h(a; t) for a complex scalar a (0-d complex128) and a vector t."""
+
+    @staticmethod
+    def forward(ctx, a, t, sigma):
+        av = complex(a.detach())
+        tv = t.detach().numpy()
+        z = (av * sigma * sigma - tv) / (sigma * math.sqrt(2.0))
+        g = np.exp(-tv * tv / (2.0 * sigma * sigma))
+        h = np.empty(tv.shape, dtype=np.complex128)
+        up = z.real >= 0.0
+        h[up] = 0.5 * g[up] * wofz(1j * z[up])
+        dn = ~up
+        h[dn] = np.exp(av * av * sigma * sigma / 2.0 - av * tv[dn]) - 0.5 * g[dn] * wofz(-1j * z[dn])
+        ht = torch.from_numpy(h.astype(np.complex128))
+        ctx.save_for_backward(ht, t)
+        ctx.sigma = sigma
+        ctx.a = av
+        return ht
+
+    @staticmethod
+    def backward(ctx, grad):
+        h, t = ctx.saved_tensors
+        s = ctx.sigma
+        # dh/da = (a s^2 - t) h - s/sqrt(2 pi) exp(-t^2/(2 s^2))
+        dh = (ctx.a * s * s - t) * h - (s / SQRT_2PI) * torch.exp(-t * t / (2.0 * s * s))
+        ga = (grad * dh.conj()).sum()
+        return ga, None, None
+
+
+def h_conv(a, t, sigma: float):
+    if not isinstance(a, torch.Tensor):
+        a = torch.tensor(complex(a), dtype=torch.complex128)
+    if not torch.is_complex(a):
+        a = torch.complex(a, torch.zeros_like(a))
+    return _H.apply(a, t, sigma)
+
+
+class TD4:
+    def __init__(self, desc: dict):
+        if desc.get("kind") != "td4":
+            raise ValueError("not a td4 model")
+        self.M = float(desc["M"])
+        self.m = [float(v) for v in desc["m"]]
+        self.r = float(desc.get("r_res", 1.5))
+        self.tau = float(desc["tau"])
+        self.sigma = float(desc["sigma_t"])
+        self.r12 = [(int(e["L"]), float(e["m0"]), float(e["w0"])) for e in desc["r12"]]
+        self.r34 = [(int(e["L"]), float(e["m0"]), float(e["w0"])) for e in desc["r34"]]
+        self.amps = [tuple(int(v) for v in a) for a in desc["amps"]]
+        self.K = len(self.amps)
+        self.P = 4 * self.K + 2
+
+    @staticmethod
+    def lam(a, b, c):
+        return a * a + b * b + c * c - 2 * a * b - 2 * a * c - 2 * b * c
+
+    @staticmethod
+    def bw_factor(L, z):
+        return torch.ones_like(z) if L == 0 else 1.0 / torch.sqrt(1.0 + z)
+
+    def pair_amp(self, m, ma, mb, res):
+        L, m0, w0 = res
+        if m0 == 0.0:
+            return torch.ones(m.shape, dtype=torch.complex128)
+        s = m * m
+        q = torch.sqrt(torch.clamp(self.lam(s, ma * ma, mb * mb), min=0.0)) / (2.0 * m)
+        q0 = math.sqrt(self.lam(m0 * m0, ma * ma, mb * mb)) / (2.0 * m0)
+        fr = self.bw_factor(L, (q * self.r) ** 2) / self.bw_factor(L, torch.tensor((q0 * self.r) ** 2))
+        gam = w0 * (q / q0) ** (2 * L + 1) * (m0 / m) * fr * fr
+        t = 1.0 / torch.complex(m0 * m0 - s, -m0 * gam)
+        return fr * t
+
+    @staticmethod
+    def omega(typ, c12, c34, phi):
+        one = torch.ones(c12.shape, dtype=torch.complex128)
+        if typ == 0:
+            return one
+        if typ == 1:
+            return c34 * one
+        if typ == 2:
+            return c12 * one
+        if typ == 3:
+            return c12 * c34 * one
+        s = 0.5 * torch.sqrt(1.0 - c12 * c12) * torch.sqrt(1.0 - c34 * c34)
+        if typ == 4:
+            return torch.polar(s, phi)
+        if typ == 5:
+            return torch.polar(s, -phi)
+        raise ValueError(typ)
+
+    def basis(self, kin):
+        """B_k for kinematics kin = (m12, m34, c12, c34, phi) tensors."""
+        m12, m34, c12, c34, phi = kin
+        m1, m2, m3, m4 = self.m
+        a12 = [self.pair_amp(m12, m1, m2, r) for r in self.r12]
+        a34 = [self.pair_amp(m34, m3, m4, r) for r in self.r34]
+        return [a12[i] * a34[j] * self.omega(typ, c12, c34, phi) for (i, j, typ) in self.amps]
+
+    def amplitudes(self, theta, B):
+        K = self.K
+        A = sum(torch.complex(theta[2 * k], theta[2 * k + 1]) * B[k] for k in range(K))
+        Ab = sum(torch.complex(theta[2 * K + 2 * k], theta[2 * K + 2 * k + 1]) * B[k] for k in range(K))
+        return A, Ab
+
+    def rate(self, theta, ev):
+        """R(x, t) convolved with the resolution, per event."""
+        B = self.basis(ev[:5])
+        A, Ab = self.amplitudes(theta, B)
+        t = ev[5]
+        x, y = theta[self.P - 2], theta[self.P - 1]
+        G = 1.0 / self.tau
+        one = torch.ones((), dtype=torch.float64)
+        hp = h_conv(torch.complex(G * (1.0 - y), 0.0 * y), t, self.sigma).real
+        hm = h_conv(torch.complex(G * (1.0 + y), 0.0 * y), t, self.sigma).real
+        hc = h_conv(torch.complex(G * one, -G * x), t, self.sigma)
+        a2 = A.real ** 2 + A.imag ** 2
+        b2 = Ab.real ** 2 + Ab.imag ** 2
+        z = A.conj() * Ab
+        return 0.5 * ((a2 + b2) * 0.5 * (hp + hm) + (a2 - b2) * hc.real
+                      - 2.0 * z.real * 0.5 * (hp - hm) - 2.0 * z.imag * hc.imag)
+
+    def integrated_rate(self, theta, kin):
+        """The t-integral of R at each phase-space point."""
+        B = self.basis(kin)
+        A, Ab = self.amplitudes(theta, B)
+        x, y = theta[self.P - 2], theta[self.P - 1]
+        G = 1.0 / self.tau
+        a2 = A.real ** 2 + A.imag ** 2
+        b2 = Ab.real ** 2 + Ab.imag ** 2
+        z = A.conj() * Ab
+        cy = 1.0 / (G * (1.0 - y * y))
+        cx = 1.0 / (G * (1.0 + x * x))
+        return 0.5 * ((a2 + b2) * cy + (a2 - b2) * cx - 2.0 * z.real * y * cy - 2.0 * z.imag * x * cx)
+
+
+def nll(theta, ev, mc, desc) -> float:
+    model = TD4(desc)
+    with torch.no_grad():
+        th = as_t(theta)
+        r = model.rate(th, as_t(ev))
+        norm = fsum(model.integrated_rate(th, as_t(mc))) / mc.shape[1]
+    return nll_value(torch.log(r), ev.shape[1], math.log(norm))
+
+
+def nll_grad(theta, ev, mc, desc):
+    model = TD4(desc)
+    th = as_t(theta, requires_grad=True)
+    lr = torch.log(model.rate(th, as_t(ev)))
+    ir = model.integrated_rate(th, as_t(mc))
+    loss = -lr.sum() + ev.shape[1] * torch.log(ir.mean())
+    loss.backward()
+    with torch.no_grad():
+        norm = fsum(ir.detach()) / mc.shape[1]
+    return nll_value(lr.detach(), ev.shape[1], math.log(norm)), th.grad.numpy().copy()

@@ -8,3 +8,6 @@ from .samplers import (  # noqa: F401
     mix1d_events, lognormal_sizes, dalitz_events, dalitz_box,
 )
 from .workloads import mix1d_desc, mix1d_truth, dalitz_desc, dalitz_truth  # noqa: F401,E402
+from .td4 import (  # noqa: F401,E402
+    TD4_MASSES, TD4_TAU, TD4_SIGMA_T, td4_desc, td4_truth, td4_phase_space, td4_events,
+)

@@ -1,0 +1,125 @@
+"""Pins of the time-dependent four-body oracle (CPU only)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+from scipy import integrate
+
+import synth
+from oracle import common, td4 as OT
+
+DESC = synth.td4_desc()
+TH = synth.td4_truth()
+MODEL = OT.TD4(DESC)
+SIG = synth.TD4_SIGMA_T
+
+
+def h(a, t, sigma=SIG):
+    return OT.h_conv(complex(a), torch.tensor(np.atleast_1d(t), dtype=torch.float64), sigma).numpy()
+
+
+@pytest.mark.parametrize("a", [2.439 * (1 - 0.006), 2.439 * (1 + 0.3), complex(2.439, -2.439 * 0.004),
+                               complex(1.2, 0.9)])
+@pytest.mark.parametrize("t", [-0.3, -0.05, 0.0, 0.004, 0.3, 2.0, 5.0])
+def test_h_against_direct_convolution(a, t):
+    """h(a; t) = int_0^inf e^{-a u} G_sigma(t - u) du by adaptive quadrature."""
+    g = lambda u: math.exp(-(t - u) ** 2 / (2 * SIG * SIG)) / (SIG * math.sqrt(2 * math.pi))
+    lo, hi = max(0.0, t - 12 * SIG), max(0.0, t + 12 * SIG)
+    re = integrate.quad(lambda u: (np.exp(-a * u)).real * g(u), lo, hi, epsabs=1e-16, epsrel=1e-13, limit=200)[0]
+    im = integrate.quad(lambda u: (np.exp(-a * u)).imag * g(u), lo, hi, epsabs=1e-16, epsrel=1e-13, limit=200)[0]
+    got = h(a, t)[0]
+    ref = complex(re, im)
+    assert abs(got - ref) <= 1e-11 * max(abs(ref), 1e-30) + 1e-300
+
+
+@pytest.mark.parametrize("a", [2.4, complex(2.4, -0.3)])
+def test_h_sigma_to_zero_and_unit_integral(a):
+    t = np.array([0.5, 1.0, 3.0])
+    assert np.allclose(h(a, t, sigma=1e-4), np.exp(-a * t), rtol=1e-10)
+    re = integrate.quad(lambda v: h(a, v)[0].real, -1, 40, limit=400, epsabs=1e-14)[0]
+    im = integrate.quad(lambda v: h(a, v)[0].imag, -1, 40, limit=400, epsabs=1e-14)[0]
+    assert abs(complex(re, im) - 1 / a) < 1e-10
+
+
+def _one_point():
+    kin = synth.td4_phase_space(1, seed=5)
+    return [torch.tensor(kin[i]) for i in range(5)]
+
+
+@pytest.mark.parametrize("xy", [(0.004, 0.006), (0.2, -0.3), (0.0, 0.0)])
+def test_time_integral_of_rate_equals_normalization_formula(xy):
+    th = TH.copy()
+    th[-2:] = xy
+    kin = _one_point()
+    tht = torch.tensor(th)
+
+    def rate(t):
+        ev = torch.stack([k.reshape(1) for k in kin] + [torch.tensor([t])])
+        with torch.no_grad():
+            return float(MODEL.rate(tht, ev)[0])
+    val = integrate.quad(rate, -1.0, 30.0, limit=500, epsabs=1e-15, epsrel=1e-12, points=[0.0, 0.5])[0]
+    with torch.no_grad():
+        ref = float(MODEL.integrated_rate(tht, torch.stack([k.reshape(1) for k in kin]))[0])
+    assert abs(val / ref - 1) < 1e-9
+
+
+def test_no_mixing_factorizes():
+    """x = y = 0: R(x, t) = |A(x)|^2 h(Gamma; t)."""
+    th = TH.copy()
+    th[-2:] = 0.0
+    ev = synth.td4_events(200, seed=6)
+    with torch.no_grad():
+        r = MODEL.rate(torch.tensor(th), torch.tensor(ev)).numpy()
+        A, _ = MODEL.amplitudes(torch.tensor(th), MODEL.basis(torch.tensor(ev[:5])))
+    hg = h(1 / synth.TD4_TAU, ev[5]).real
+    assert np.allclose(r, (A.abs() ** 2).numpy() * hg, rtol=1e-12)
+
+
+def test_angular_functions_orthogonal():
+    """The six helicity structures are orthogonal on (c12, c34, phi)."""
+    x, w = np.polynomial.legendre.leggauss(12)
+    pf = np.linspace(-math.pi, math.pi, 33)[:-1] + math.pi / 32
+    C12, C34, PHI = np.meshgrid(x, x, pf, indexing="ij")
+    W = (w[:, None, None] * w[None, :, None]) * (2 * math.pi / 32)
+    tens = [OT.TD4.omega(k, torch.tensor(C12), torch.tensor(C34), torch.tensor(PHI)).numpy() for k in range(6)]
+    gram = np.array([[np.sum(W * a * np.conj(b)) for b in tens] for a in tens])
+    off = gram - np.diag(np.diag(gram))
+    assert np.abs(off).max() < 1e-12 * np.abs(np.diag(gram)).max()
+    assert np.abs(gram[0, 0] - 8 * math.pi) < 1e-12
+
+
+def test_lineshape_pole():
+    from synth.td4 import TD4_R34
+    L, m0, w0 = TD4_R34[1]
+    amp = MODEL.pair_amp(torch.tensor([m0]), 0.140, 0.140, (L, m0, w0))
+    assert abs(amp[0] - 1j / (m0 * w0)) < 1e-12 / (m0 * w0)
+
+
+def test_autograd_vs_central_fd():
+    ev = synth.td4_events(1500, seed=7)
+    mc = synth.td4_phase_space(3000, seed=8)
+    th = TH * (1 + 0.05 * np.sin(np.arange(TH.size)))
+    th[-2:] = [0.05, -0.04]
+    _, g = OT.nll_grad(th, ev, mc, DESC)
+    fd = common.central_fd(lambda q: OT.nll(q, ev, mc, DESC), th, rel_step=1e-6)
+    tol = 1e-6 * np.maximum(np.abs(fd), 1e-3 * np.abs(fd).max())
+    assert (np.abs(g - fd) <= tol).all(), np.abs(g - fd) / tol
+
+
+def test_phase_space_marginal():
+    """m12 marginal of the phase-space sample against 1-D quadrature of the
+    phase-space density (chi-square over 20 bins)."""
+    M, m1, m2, m3, m4 = synth.TD4_MASSES
+    ps = synth.td4_phase_space(200_000, seed=9)
+    q = lambda m, a, b: math.sqrt(max((m * m - (a + b) ** 2) * (m * m - (a - b) ** 2), 0.0)) / (2 * m)
+    dens = lambda m12: integrate.quad(lambda m34: q(M, m12, m34) * q(m12, m1, m2) * q(m34, m3, m4),
+                                      m3 + m4, M - m12, limit=200)[0]
+    edges = np.linspace(m1 + m2, M - m3 - m4, 21)
+    probs = np.array([integrate.quad(dens, a, b, limit=200)[0] for a, b in zip(edges[:-1], edges[1:])])
+    probs /= probs.sum()
+    counts, _ = np.histogram(ps[0], edges)
+    exp = probs * ps.shape[1]
+    keep = exp > 20
+    chi2 = (((counts - exp) ** 2) / exp)[keep].sum()
+    assert chi2 < 50, chi2  # 19 dof
