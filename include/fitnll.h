@@ -102,6 +102,25 @@ typedef struct fn_model fn_model;
  *     M_ij = dA sum_cells A_i conj(A_j) and I = c^H M c afterwards (the
  *     paper's caching of partial results while parameters are unchanged,
  *     Sec. 4).
+ *  kind "td4":   {"kind":"td4","M":..,"m":[m1,m2,m3,m4],"r_res":r,"tau":..,
+ *                 "sigma_t":..,"r12":[{"L":0|1,"m0":..,"w0":..},...],
+ *                 "r34":[...],"amps":[[i12,i34,type],...]}
+ *     The time-dependent four-body amplitude model (the paper's four-body
+ *     time-dependent analyses, Abstract and Sec. 5).  Six observables
+ *     (m12, m34, cos theta12, cos theta34, phi, t).  Basis amplitudes
+ *     B_k = a12[i12] a34[i34] Omega_type with relativistic Breit-Wigner
+ *     lineshapes (m0 = 0 marks a flat non-resonant entry; L = 0 or 1; up to 4
+ *     entries per pair) and helicity angular factors: type 0 -> 1, 1 -> c34,
+ *     2 -> c12, 3 -> c12 c34, 4/5 -> sin12 sin34 exp(+-i phi) / 2.  A = sum c_k B_k,
+ *     Abar = sum cbar_k B_k (up to 12 amplitudes); the rate mixes them with
+ *     decay time through Gamma = 1/tau and mixing parameters x, y, convolved
+ *     with a Gaussian time resolution of width sigma_t.  I is the average of
+ *     the time-integrated rate over a phase-space sample that must be given
+ *     with fn_model_set_norm_sample before the first evaluation.
+ *     theta = (Re c_k, Im c_k)_k, (Re cbar_k, Im cbar_k)_k, x, y  (P = 4K + 2).
+ *     The lineshape constants and sigma_t form the model's fixed-constant
+ *     vector (fn_model_fixed): (m0, w0) of every r12 entry, of every r34
+ *     entry, then sigma_t.
  *  Optional keys for every kind: "chunk" (events per workgroup, a power of two
  *  in [256, 65536], default chosen per kind) -- fixed per model, it defines
  *  the summation tree.
@@ -140,6 +159,17 @@ fn_status fn_norm(fn_model* m, const double* theta_host, double* norm_host,
 fn_status fn_eval(fn_model* m, const double* theta_host, const double* ev, int64_t n,
                   int64_t ld, double* p_dev, void* stream);
 
+/* td4 only: the phase-space sample that defines the normalization average
+ * (the paper integrates four-body phase space by Monte Carlo, Sec. 5).
+ * mc_dev: device memory, 5 rows (m12, m34, cos theta12, cos theta34, phi) of
+ * n_mc unweighted points, row j at mc_dev[j*ld + i]; copied into model-owned
+ * memory before return (the caller may free it).  Synchronous.  Replaces any
+ * previous sample and invalidates the cached normalization matrix. */
+fn_status fn_model_set_norm_sample(fn_model* m, const double* mc_dev, int64_t n_mc, int64_t ld, void* stream);
+/* td4 only: size of the fixed-constant vector and (fixed_host != NULL) the
+ * values from the description. */
+fn_status fn_model_fixed(const fn_model* m, int32_t* n_fixed, double* fixed_host);
+
 /* Kernel timing (measurement support, not on the result path).  With timing
  * enabled, every per-event evaluation launch of the model is bracketed by HIP
  * events recorded on the launch stream.  fn_model_kernel_time waits for the
@@ -167,6 +197,45 @@ fn_status fn_fit(fn_model* m, const double* theta0_host, const int32_t* free_mas
                  const double* ev, int64_t n, int64_t ld, int32_t grad_mode, double tol,
                  int32_t max_iter, double* theta_out, double* err_out, double* nll_out,
                  int32_t* n_iter, int32_t* n_calls, void* stream);
+
+/* ------------------------------------------------- systematic variations
+ * Many fits of one "td4" model to ONE event sample that differ in their fixed
+ * constants (the model's fixed-constant vector: lineshape masses and widths,
+ * time resolution) and start points -- the systematic-variation fits of a
+ * time-dependent amplitude analysis (Sec. 5), advanced together on the
+ * device.  Every step evaluates NLL + gradient for all running fits in one
+ * events pass (one workgroup per (event chunk, fit)), then advances each
+ * fit's BFGS / strong-Wolfe state machine (the minimizer of fn_fit, state in
+ * device memory) by one evaluation.  Each fit's normalization matrix over the
+ * model's phase-space sample is built once per batch and kept until its fixed
+ * constants or the sample change.  A fit's NLL is bitwise the single-fit
+ * fn_nll value of a model with the same constants.  A batch uses its own
+ * stream, ordered after `stream` (the stream that produced the events);
+ * calls are synchronous and must not overlap on one batch. */
+typedef struct fn_vbatch fn_vbatch;
+/* n_fits in [1, 4096]; every fit starts with the model's fixed constants. */
+fn_status fn_vbatch_create(fn_model* m, int32_t n_fits, fn_vbatch** out);
+fn_status fn_vbatch_destroy(fn_vbatch* b);
+/* Fixed constants of fit `fit` (host, the model's fixed-constant vector
+ * layout, see fn_model_fixed; NULL restores the model's).  FN_E_INVALID for
+ * unphysical values (m0 at or below threshold, w0 <= 0, sigma_t <= 0). */
+fn_status fn_vbatch_set_fixed(fn_vbatch* b, int32_t fit, const double* fixed_host);
+/* NLL of every fit at theta_host (n_fits x P, row-major) into nll_host
+ * (n_fits) and, when grad_host != NULL, gradients (n_fits x P).  One events
+ * pass for all fits.  FN_E_NONFINITE if any fit's NLL is not finite (the
+ * values are still written). */
+fn_status fn_vbatch_nll(fn_vbatch* b, const double* theta_host, const double* ev, int64_t n, int64_t ld,
+                        double* nll_host, double* grad_host, void* stream);
+/* Minimize every fit from theta0_host (n_fits x P); free_mask (P int32, NULL =
+ * all free) applies to all fits.  tol, max_iter as for fn_fit; use_graph != 0
+ * replays one captured step graph.  Outputs (host, may be NULL): status
+ * (n_fits, FN_FIT_*), theta and err (n_fits x P; err = sqrt of the diagonal of
+ * the BFGS inverse-Hessian approximation, 0 for fixed parameters), nll,
+ * iterations and evaluations (n_fits). */
+fn_status fn_vbatch_fit(fn_vbatch* b, const double* theta0_host, const int32_t* free_mask, const double* ev,
+                        int64_t n, int64_t ld, double tol, int32_t max_iter, int32_t use_graph, int32_t* status_out,
+                        double* theta_out, double* err_out, double* nll_out, int32_t* iters_out,
+                        int32_t* n_evals_out, void* stream);
 
 /* ---------------------------------------------------------------- batching
  * Many independent fits of one "mix1d" model advanced together on the device

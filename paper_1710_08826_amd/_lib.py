@@ -47,10 +47,18 @@ PROTOTYPES = {
     "fn_nll_async": (i32, [vp, vp, vp, i64, i64, vp, i32, vp]),
     "fn_norm": (i32, [vp, dp, dp, dp, vp]),
     "fn_eval": (i32, [vp, dp, vp, i64, i64, vp, vp]),
+    "fn_model_set_norm_sample": (i32, [vp, vp, i64, i64, vp]),
+    "fn_model_fixed": (i32, [vp, C.POINTER(i32), dp]),
     "fn_model_timing": (i32, [vp, i32]),
     "fn_model_kernel_time": (i32, [vp, dp, C.POINTER(i64)]),
     "fn_fit": (i32, [vp, dp, C.POINTER(i32), vp, i64, i64, i32, C.c_double, i32, dp, dp, dp,
                      C.POINTER(i32), C.POINTER(i32), vp]),
+    "fn_vbatch_create": (i32, [vp, i32, C.POINTER(vp)]),
+    "fn_vbatch_destroy": (i32, [vp]),
+    "fn_vbatch_set_fixed": (i32, [vp, i32, dp]),
+    "fn_vbatch_nll": (i32, [vp, dp, vp, i64, i64, dp, dp, vp]),
+    "fn_vbatch_fit": (i32, [vp, dp, C.POINTER(i32), vp, i64, i64, C.c_double, i32, i32, C.POINTER(i32), dp, dp,
+                            dp, C.POINTER(i32), C.POINTER(i32), vp]),
     "fn_batch_create": (i32, [vp, i32, i64, C.POINTER(vp)]),
     "fn_batch_destroy": (i32, [vp]),
     "fn_batch_set_slot": (i32, [vp, i32, vp, i64, dp, C.POINTER(i32)]),

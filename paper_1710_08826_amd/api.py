@@ -135,6 +135,23 @@ class Model:
                                 _stream_ptr(stream)))
         return p
 
+    def set_norm_sample(self, mc: torch.Tensor, stream=None):
+        """td4: phase-space sample (5, n_mc) float64 CUDA tensor defining I."""
+        if not isinstance(mc, torch.Tensor) or not mc.is_cuda or mc.dtype != torch.float64:
+            raise TypeError("the sample must be a float64 CUDA tensor")
+        if mc.dim() != 2 or mc.shape[0] != 5 or mc.stride(1) != 1:
+            raise ValueError("the sample must have shape (5, n_mc), contiguous along points")
+        check(self._lib.fn_model_set_norm_sample(self._h, C.c_void_p(mc.data_ptr()), mc.shape[1], mc.stride(0),
+                                                 _stream_ptr(stream)))
+
+    def fixed(self) -> np.ndarray:
+        """td4: the description's fixed-constant vector."""
+        n = C.c_int32()
+        check(self._lib.fn_model_fixed(self._h, C.byref(n), None))
+        v = np.zeros(n.value)
+        check(self._lib.fn_model_fixed(self._h, None, v.ctypes.data_as(C.POINTER(C.c_double))))
+        return v
+
     def set_timing(self, enable: bool):
         """Bracket every per-event kernel launch with HIP events."""
         check(self._lib.fn_model_timing(self._h, 1 if enable else 0))
@@ -265,6 +282,75 @@ class Batch:
         f64p = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
         check(self._lib.fn_batch_results(self._h, i32p(st), f64p(th), f64p(nll), f64p(er), i32p(it), i32p(ne)))
         return BatchResults(st, th, nll, er, it, ne)
+
+
+class VariationBatch:
+    """Fits of one td4 model to one event sample that differ in their fixed
+    constants (see fn_vbatch_* in include/fitnll.h)."""
+
+    def __init__(self, model: Model, n_fits: int):
+        self.model = model
+        self._lib = model._lib
+        self.n_fits = int(n_fits)
+        h = C.c_void_p()
+        check(self._lib.fn_vbatch_create(model._h, self.n_fits, C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.fn_vbatch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_fixed(self, fit: int, fixed=None):
+        if fixed is None:
+            check(self._lib.fn_vbatch_set_fixed(self._h, int(fit), None))
+            return
+        a, p = _dbl(fixed)
+        check(self._lib.fn_vbatch_set_fixed(self._h, int(fit), p))
+
+    def _thetas(self, theta):
+        a = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
+        if a.shape != (self.n_fits, self.model.n_params):
+            raise ValueError(f"theta must have shape ({self.n_fits}, {self.model.n_params})")
+        return a
+
+    def nll(self, theta, events: torch.Tensor, grad: bool = False, stream=None):
+        th = self._thetas(theta)
+        evp, n, ld = _events(events, self.model.n_obs)
+        v = np.zeros(self.n_fits)
+        g = np.zeros((self.n_fits, self.model.n_params))
+        f64p = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+        check(self._lib.fn_vbatch_nll(self._h, f64p(th), evp, n, ld, f64p(v), f64p(g) if grad else None,
+                                      _stream_ptr(stream)))
+        return (v, g) if grad else v
+
+    def fit(self, theta0, events: torch.Tensor, free=None, tol: float = 1e-7, max_iter: int = 500,
+            use_graph: bool = True, stream=None) -> BatchResults:
+        th = self._thetas(theta0)
+        evp, n, ld = _events(events, self.model.n_obs)
+        F, P = self.n_fits, self.model.n_params
+        mask = None
+        if free is not None:
+            mk = np.ascontiguousarray(np.asarray(free, dtype=np.int32))
+            mask = mk.ctypes.data_as(C.POINTER(C.c_int32))
+        st = np.zeros(F, np.int32)
+        x = np.zeros((F, P))
+        er = np.zeros((F, P))
+        v = np.zeros(F)
+        it = np.zeros(F, np.int32)
+        ne = np.zeros(F, np.int32)
+        i32p = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
+        f64p = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+        check(self._lib.fn_vbatch_fit(self._h, f64p(th), mask, evp, n, ld, float(tol), int(max_iter),
+                                      1 if use_graph else 0, i32p(st), f64p(x), f64p(er), f64p(v), i32p(it),
+                                      i32p(ne), _stream_ptr(stream)))
+        return BatchResults(st, x, v, er, it, ne)
 
 
 def generate_mix1d(n: int, seed: int, fit: int, theta_gen, lo: float = -10.0, hi: float = 10.0,

@@ -178,239 +178,6 @@ __global__ __launch_bounds__(kBlock) void batch_finalize(Mix1dConst mc, const Mi
                      nullptr, scratch, res);
 }
 
-// --------------------------------------------------------------- BFGS step
-__device__ inline double dotp(const double* a, const double* b, int P) {
-  double s = 0.0;
-  for (int i = 0; i < P; ++i) s += a[i] * b[i];
-  return s;
-}
-
-// Direction p = -H g (fixed parameters have zero rows/columns in H).
-__device__ inline void new_direction(BfgsState& s, int P) {
-  for (int i = 0; i < P; ++i) {
-    double v = 0.0;
-    for (int j = 0; j < P; ++j) v += s.H[i * kBatchMaxP + j] * s.g[j];
-    s.p[i] = -v;
-  }
-  s.d0 = dotp(s.g, s.p, P);
-}
-
-__device__ inline void set_trial(BfgsState& s, int P, double a) {
-  s.alpha = a;
-  for (int i = 0; i < P; ++i) s.xt[i] = s.x[i] + a * s.p[i];
-}
-
-// Start the next iteration from the accepted point (x, f, g) in s.
-__device__ inline void begin_iteration(BfgsState& s, int P, double tol, int max_iter) {
-  // estimated distance to the minimum
-  double edm = 0.0;
-  for (int i = 0; i < P; ++i) {
-    double v = 0.0;
-    for (int j = 0; j < P; ++j) v += s.H[i * kBatchMaxP + j] * s.g[j];
-    edm += s.g[i] * v;
-  }
-  edm *= 0.5;
-  s.edm = edm;
-  if (edm >= 0.0 && edm < tol) {
-    s.status = kFitConverged;
-    return;
-  }
-  if (s.iter >= max_iter) {
-    s.status = kFitFailed;
-    return;
-  }
-  new_direction(s, P);
-  if (!(s.d0 < 0.0)) {
-    // not a descent direction: restart from a scaled identity
-    for (int i = 0; i < P; ++i)
-      for (int j = 0; j < P; ++j) s.H[i * kBatchMaxP + j] = (i == j && s.mask[i]) ? s.h0 : 0.0;
-    new_direction(s, P);
-    if (!(s.d0 < 0.0)) {
-      s.status = kFitFailed;
-      return;
-    }
-  }
-  s.phase = kPhaseBracket;
-  s.ls_it = 0;
-  s.a_prev = 0.0;
-  s.f_prev = s.f;
-  s.d_prev = s.d0;
-  set_trial(s, P, 1.0);
-}
-
-__device__ inline void accept_trial(BfgsState& s, int P, const double* gt, double ft, double tol, int max_iter) {
-  double sv[kBatchMaxP], yv[kBatchMaxP], Hy[kBatchMaxP];
-  for (int i = 0; i < P; ++i) {
-    sv[i] = s.xt[i] - s.x[i];
-    yv[i] = gt[i] - s.g[i];
-  }
-  const double sy = dotp(sv, yv, P);
-  if (sy > 0.0) {
-    if (s.iter == 0) {
-      // Nocedal & Wright Eq. 6.20: rescale the initial matrix before the first update
-      const double sc = sy / dotp(yv, yv, P);
-      for (int i = 0; i < P; ++i)
-        for (int j = 0; j < P; ++j) s.H[i * kBatchMaxP + j] = (i == j && s.mask[i]) ? sc : 0.0;
-      s.h0 = sc;
-    }
-    const double rho = 1.0 / sy;
-    for (int i = 0; i < P; ++i) {
-      double v = 0.0;
-      for (int j = 0; j < P; ++j) v += s.H[i * kBatchMaxP + j] * yv[j];
-      Hy[i] = v;
-    }
-    const double yHy = dotp(yv, Hy, P);
-    for (int i = 0; i < P; ++i)
-      for (int j = 0; j < P; ++j)
-        s.H[i * kBatchMaxP + j] += rho * ((1.0 + rho * yHy) * sv[i] * sv[j] - Hy[i] * sv[j] - sv[i] * Hy[j]);
-  }
-  for (int i = 0; i < P; ++i) {
-    s.x[i] = s.xt[i];
-    s.g[i] = gt[i];
-  }
-  s.f = ft;
-  s.iter += 1;
-  begin_iteration(s, P, tol, max_iter);
-}
-
-// Safeguarded quadratic interpolation in [lo, hi] from (lo, f_lo, d_lo), (hi, f_hi).
-__device__ inline double zoom_trial(const BfgsState& s) {
-  const double lo = s.a_lo, hi = s.a_hi, dh = hi - lo;
-  double a;
-  const double den = 2.0 * (s.f_hi - s.f_lo - s.d_lo * dh);
-  if (isfinite(s.f_hi) && den > 0.0) a = lo - s.d_lo * dh * dh / den;
-  else a = lo + 0.5 * dh;
-  const double b0 = fmin(lo, hi) + 0.1 * fabs(dh), b1 = fmax(lo, hi) - 0.1 * fabs(dh);
-  if (!(a >= b0 && a <= b1)) a = lo + 0.5 * dh;
-  return a;
-}
-
-__device__ void bfgs_update(BfgsState& s, const double* __restrict__ o, int P, double tol, int max_iter) {
-  double ft = o[0];
-  double gt[kBatchMaxP];
-  bool ok = isfinite(ft);
-  for (int i = 0; i < P; ++i) {
-    gt[i] = s.mask[i] ? o[1 + i] : 0.0;
-    ok = ok && isfinite(gt[i]);
-  }
-  if (!ok) ft = INFINITY;
-  s.n_eval += 1;
-  const double c1 = 1e-4, c2 = 0.9;
-  if (s.phase == kPhaseStart) {
-    if (!ok) {
-      s.status = kFitFailed;
-      return;
-    }
-    for (int i = 0; i < P; ++i) {
-      s.x[i] = s.xt[i];
-      s.g[i] = gt[i];
-    }
-    s.f = ft;
-    // starting inverse Hessian: first step moves the largest gradient component by 1e-3 of its scale
-    double gmax = 0.0;
-    for (int i = 0; i < P; ++i) gmax = fmax(gmax, fabs(gt[i]));
-    s.h0 = gmax > 0.0 ? 1e-3 / gmax : 1.0;
-    for (int i = 0; i < P; ++i)
-      for (int j = 0; j < P; ++j) s.H[i * kBatchMaxP + j] = (i == j && s.mask[i]) ? s.h0 : 0.0;
-    s.iter = 0;
-    begin_iteration(s, P, tol, max_iter);
-    return;
-  }
-  const double dt = ok ? dotp(gt, s.p, P) : NAN;
-  const double a = s.alpha;
-  s.ls_it += 1;
-  if (s.ls_it > kMaxLineSearch) {
-    // give up on this line: accept the best sufficient-decrease point if any
-    if (s.phase == kPhaseZoom && s.a_lo > 0.0 && s.f_lo < s.f) {
-      set_trial(s, P, s.a_lo);
-      s.phase = kPhaseAcceptLo;
-      return;
-    }
-    s.status = kFitFailed;
-    return;
-  }
-  if (s.phase == kPhaseAcceptLo) {
-    if (!ok) {
-      s.status = kFitFailed;
-      return;
-    }
-    accept_trial(s, P, gt, ft, tol, max_iter);
-    return;
-  }
-  if (s.phase == kPhaseBracket) {
-    if (!ok || ft > s.f + c1 * a * s.d0 || (s.a_prev > 0.0 && ft >= s.f_prev)) {
-      s.a_lo = s.a_prev; s.f_lo = s.f_prev; s.d_lo = s.d_prev;
-      s.a_hi = a; s.f_hi = ft;
-      s.phase = kPhaseZoom;
-      set_trial(s, P, zoom_trial(s));
-      return;
-    }
-    if (fabs(dt) <= -c2 * s.d0) {
-      accept_trial(s, P, gt, ft, tol, max_iter);
-      return;
-    }
-    if (dt >= 0.0) {
-      s.a_lo = a; s.f_lo = ft; s.d_lo = dt;
-      s.a_hi = s.a_prev; s.f_hi = s.f_prev;
-      s.phase = kPhaseZoom;
-      set_trial(s, P, zoom_trial(s));
-      return;
-    }
-    s.a_prev = a; s.f_prev = ft; s.d_prev = dt;
-    set_trial(s, P, 2.0 * a);
-    return;
-  }
-  // zoom
-  if (!ok || ft > s.f + c1 * a * s.d0 || ft >= s.f_lo) {
-    s.a_hi = a;
-    s.f_hi = ft;
-  } else {
-    if (fabs(dt) <= -c2 * s.d0) {
-      accept_trial(s, P, gt, ft, tol, max_iter);
-      return;
-    }
-    if (dt * (s.a_hi - s.a_lo) >= 0.0) {
-      s.a_hi = s.a_lo;
-      s.f_hi = s.f_lo;
-    }
-    s.a_lo = a; s.f_lo = ft; s.d_lo = dt;
-  }
-  if (fabs(s.a_hi - s.a_lo) < 1e-15 * fmax(1.0, fabs(s.a_lo))) {
-    if (s.a_lo > 0.0 && s.f_lo < s.f) {
-      set_trial(s, P, s.a_lo);
-      s.phase = kPhaseAcceptLo;
-      return;
-    }
-    s.status = kFitFailed;
-    return;
-  }
-  set_trial(s, P, zoom_trial(s));
-}
-
-// One minimizer step per running fit; every slot's status is mirrored into
-// stat[], and a fit that retires in this step writes its result row
-// [NLL, iterations, evaluations, theta(P), sqrt|H_ii|(P)] into rres.
-__global__ void batch_bfgs(BfgsState* __restrict__ st, const double* __restrict__ out, int out_stride, int n_fits,
-                           int P, double tol, int max_iter, int* __restrict__ stat, double* __restrict__ rres) {
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= n_fits) return;
-  BfgsState& s = st[f];
-  if (s.status == kFitRunning) {
-    bfgs_update(s, out + (int64_t)f * out_stride, P, tol, max_iter);
-    if (s.status != kFitRunning) {
-      double* r = rres + (int64_t)f * (3 + 2 * P);
-      r[0] = s.f;
-      r[1] = s.iter;
-      r[2] = s.n_eval;
-      for (int i = 0; i < P; ++i) {
-        r[3 + i] = s.x[i];
-        r[3 + P + i] = s.mask[i] ? sqrt(fabs(s.H[i * kBatchMaxP + i])) : 0.0;
-      }
-    }
-  }
-  stat[f] = s.status;
-}
-
 // ---------------------------------------------------------------- launchers
 void batch_launch_gen_mix1d(uint32_t k0, uint32_t k1, uint32_t word, int64_t n, const double* theta_gen, double lo,
                             double hi, double* x, unsigned int* n_unresolved, hipStream_t s) {
@@ -434,7 +201,7 @@ void batch_launch_step(const BatchDev& b, const Mix1dConst& mc, int n_fits, int 
                        b.item_base, b.part_base, n_fits, chunk, b.part);
   hipLaunchKernelGGL(batch_finalize, dim3(n_fits), dim3(kBlock), 0, s, mc, b.tabs, b.st, b.nev, b.part_base, b.part,
                      chunk, nv, kmax, b.out, 2 + 2 * P);
-  hipLaunchKernelGGL(batch_bfgs, fg, fb, 0, s, b.st, b.out, 2 + 2 * P, n_fits, P, tol, max_iter, b.stat, b.rres);
+  hipLaunchKernelGGL((bfgs_step<kBatchMaxP>), fg, fb, 0, s, b.st, b.out, 2 + 2 * P, n_fits, P, tol, max_iter, b.stat, b.rres);
 }
 
 int batch_eval_blocks_per_cu(const Mix1dConst& mc) {

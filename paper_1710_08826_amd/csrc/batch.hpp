@@ -1,29 +1,15 @@
 // Batched fits: per-fit minimizer state and the device buffers of a batch.
 #pragma once
 #include "kernels.hpp"
+#include "bfgs_device.hpp"
 #include "mix1d_device.hpp"
 
 namespace fn {
 
 constexpr int kBatchMaxP = 24;      // parameters per batched fit
-constexpr int kMaxLineSearch = 40;  // evaluations per line search before giving up
 constexpr int kGenMaxAttempts = 64; // redraws per generated event
 
-enum FitStatus : int { kFitIdle = 0, kFitRunning = 1, kFitConverged = 2, kFitFailed = 3 };
-enum FitPhase : int { kPhaseStart = 0, kPhaseBracket = 1, kPhaseZoom = 2, kPhaseAcceptLo = 3 };
-
-// One fit's BFGS + line-search state (device memory, one thread per fit).
-struct BfgsState {
-  double xt[kBatchMaxP];   // trial point: the next evaluation happens here
-  double x[kBatchMaxP];    // accepted point
-  double g[kBatchMaxP];    // gradient at x
-  double p[kBatchMaxP];    // search direction
-  double H[kBatchMaxP * kBatchMaxP];  // inverse Hessian approximation
-  double f, d0, alpha, h0, edm;
-  double a_prev, f_prev, d_prev, a_lo, f_lo, d_lo, a_hi, f_hi;
-  int mask[kBatchMaxP];    // 1 = free parameter
-  int status, phase, iter, ls_it, n_eval, pad;
-};
+using BfgsState = BfgsStateT<kBatchMaxP>;
 
 // Device pointers of a batch (n_fits slots).
 struct BatchDev {

@@ -10,6 +10,7 @@
 
 #include "../../include/fitnll.h"
 #include "model.hpp"
+#include "td4.hpp"
 
 namespace fn {
 
@@ -34,7 +35,7 @@ struct DevBuf {
   ~DevBuf() { release(); }
 };
 
-enum ModelKind : int { kKindMix1d = 1, kKindDalitz3 = 2 };
+enum ModelKind : int { kKindMix1d = 1, kKindDalitz3 = 2, kKindTd4 = 3 };
 
 }  // namespace fn
 
@@ -52,9 +53,12 @@ struct fn_model {
   int grid_chunk = 1024;  // grid cells per workgroup
   fn::Mix1dConst mix;
   fn::DalitzConst dal;
-  std::vector<double> fixed_ls;  // (m0, Gamma0) per resonance when not free
+  fn::Td4Const td4;
+  std::vector<double> fixed_ls;  // (m0, Gamma0) per resonance when not free; td4: fixed-constant vector
+  int64_t n_mc = 0;              // td4 normalization sample size (0 = not set)
+  int64_t mc_gen = 0;            // bumped whenever the sample is replaced
   bool M_valid = false;          // cached normalization matrix is current
-  fn::DevBuf d_table, d_part, d_npart, d_out, d_fixed, d_M, d_count;
+  fn::DevBuf d_table, d_part, d_npart, d_out, d_fixed, d_M, d_count, d_mc;
   double* h_out = nullptr;       // pinned
   long long stats_calls = 0;
   bool timing = false;           // bracket event-pass launches with HIP events
@@ -64,6 +68,7 @@ struct fn_model {
 
   fn::Mix1dTable* table_mix() { return (fn::Mix1dTable*)d_table.ptr; }
   fn::DalitzTable* table_dal() { return (fn::DalitzTable*)d_table.ptr; }
+  fn::Td4Table* table_td4() { return (fn::Td4Table*)d_table.ptr; }
   double* part() { return (double*)d_part.ptr; }
   double* npart() { return (double*)d_npart.ptr; }
   double* out() { return (double*)d_out.ptr; }
@@ -78,4 +83,8 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
 void nll_host(fn_model* m, const double* theta_host, const double* ev, int64_t n, int64_t ld, double* nll,
               double* grad, hipStream_t s);
 void check_events_args(fn_model* m, const double* ev, int64_t n, int64_t ld);
+// td4 fixed-constant vector ((m0, Gamma0) of every r12 entry, then of every
+// r34 entry, then sigma_t) -> per-fit constants; throws on invalid values.
+Td4FitConst td4_fit_const(const Td4Const& tc, const double* fixed);
+int td4_n_fixed(const Td4Const& tc);
 }  // namespace fn

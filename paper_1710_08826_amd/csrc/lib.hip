@@ -196,6 +196,99 @@ static void compile_dalitz3(const json::Value& d, fn_model* m) {
   m->d_M.reserve(sizeof(double) * 2 * dc.K * dc.K);
 }
 
+int td4_n_fixed(const Td4Const& tc) { return 2 * (tc.n12 + tc.n34) + 1; }
+
+Td4FitConst td4_fit_const(const Td4Const& tc, const double* fixed) {
+  Td4FitConst fc;
+  std::memset(&fc, 0, sizeof(fc));
+  const double lo12 = std::sqrt(tc.sum12), lo34 = std::sqrt(tc.sum34);
+  for (int r = 0; r < tc.n12; ++r) {
+    fc.m0_12[r] = fixed[2 * r];
+    fc.w0_12[r] = fixed[2 * r + 1];
+    if (!tc.nr12[r] && !(fc.m0_12[r] > lo12 && fc.w0_12[r] > 0.0 && std::isfinite(fc.m0_12[r] + fc.w0_12[r])))
+      throw Error(FN_E_INVALID, "td4: r12 resonance " + std::to_string(r) + " needs m0 > m1 + m2 and w0 > 0");
+  }
+  const double* f34 = fixed + 2 * tc.n12;
+  for (int r = 0; r < tc.n34; ++r) {
+    fc.m0_34[r] = f34[2 * r];
+    fc.w0_34[r] = f34[2 * r + 1];
+    if (!tc.nr34[r] && !(fc.m0_34[r] > lo34 && fc.w0_34[r] > 0.0 && std::isfinite(fc.m0_34[r] + fc.w0_34[r])))
+      throw Error(FN_E_INVALID, "td4: r34 resonance " + std::to_string(r) + " needs m0 > m3 + m4 and w0 > 0");
+  }
+  fc.sigma = fixed[2 * (tc.n12 + tc.n34)];
+  if (!(fc.sigma > 0.0) || !std::isfinite(fc.sigma)) throw Error(FN_E_INVALID, "td4: sigma_t must be > 0");
+  return fc;
+}
+
+static void compile_td4(const json::Value& d, fn_model* m) {
+  Td4Const& tc = m->td4;
+  std::memset(&tc, 0, sizeof(tc));
+  const double M = d.at("M").number();
+  const auto& ms = d.at("m").array();
+  if (ms.size() != 4) throw Error(FN_E_INVALID, "td4: need four daughter masses");
+  double mm[4];
+  for (int i = 0; i < 4; ++i) mm[i] = ms[i].number();
+  if (!(mm[0] > 0 && mm[1] > 0 && mm[2] > 0 && mm[3] > 0) || !(M > mm[0] + mm[1] + mm[2] + mm[3]))
+    throw Error(FN_E_INVALID, "td4: masses must be positive and M > m1 + m2 + m3 + m4");
+  tc.M = M;
+  tc.m1s = mm[0] * mm[0];
+  tc.m2s = mm[1] * mm[1];
+  tc.m3s = mm[2] * mm[2];
+  tc.m4s = mm[3] * mm[3];
+  tc.sum12 = (mm[0] + mm[1]) * (mm[0] + mm[1]);
+  tc.dif12 = (mm[0] - mm[1]) * (mm[0] - mm[1]);
+  tc.sum34 = (mm[2] + mm[3]) * (mm[2] + mm[3]);
+  tc.dif34 = (mm[2] - mm[3]) * (mm[2] - mm[3]);
+  const double rr = d.has("r_res") ? d.at("r_res").number() : 1.5;
+  if (!(rr >= 0.0)) throw Error(FN_E_INVALID, "td4: r_res must be >= 0");
+  tc.r2 = rr * rr;
+  const double tau = d.at("tau").number();
+  if (!(tau > 0.0)) throw Error(FN_E_INVALID, "td4: tau must be > 0");
+  tc.gamma = 1.0 / tau;
+  td4_weideman_coefficients(tc.wa, &tc.wL);
+  std::vector<double> fixed;
+  auto pair = [&](const char* key, int* n, int* L, int* nr) {
+    const auto& rs = d.at(key).array();
+    *n = (int)rs.size();
+    if (*n < 1 || *n > kTd4MaxRes) throw Error(FN_E_INVALID, std::string("td4: ") + key + " needs 1..4 entries");
+    for (int r = 0; r < *n; ++r) {
+      const long l = rs[r].at("L").integer();
+      if (l < 0 || l > 1) throw Error(FN_E_INVALID, "td4: L must be 0 or 1");
+      L[r] = (int)l;
+      const double m0 = rs[r].at("m0").number(), w0 = rs[r].at("w0").number();
+      nr[r] = m0 == 0.0 ? 1 : 0;
+      fixed.push_back(m0);
+      fixed.push_back(w0);
+    }
+  };
+  pair("r12", &tc.n12, tc.L12, tc.nr12);
+  pair("r34", &tc.n34, tc.L34, tc.nr34);
+  fixed.push_back(d.at("sigma_t").number());
+  const auto& amps = d.at("amps").array();
+  tc.K = (int)amps.size();
+  if (tc.K < 1 || tc.K > kTd4MaxAmp) throw Error(FN_E_INVALID, "td4: 1..12 amplitudes");
+  for (int k = 0; k < tc.K; ++k) {
+    const auto& a = amps[k].array();
+    if (a.size() != 3) throw Error(FN_E_INVALID, "td4: an amplitude is [r12 index, r34 index, angular type]");
+    const long r1 = a[0].integer(), r2 = a[1].integer(), ty = a[2].integer();
+    if (r1 < 0 || r1 >= tc.n12 || r2 < 0 || r2 >= tc.n34 || ty < 0 || ty > 5)
+      throw Error(FN_E_INVALID, "td4: amplitude index out of range");
+    tc.amp1[k] = (int)r1;
+    tc.amp2[k] = (int)r2;
+    tc.atype[k] = (int)ty;
+  }
+  tc.n_params = 4 * tc.K + 2;
+  const Td4FitConst fc = td4_fit_const(tc, fixed.data());
+  m->fixed_ls = fixed;
+  m->P = tc.n_params;
+  m->n_obs = 6;
+  m->chunk = 1024;
+  m->d_table.reserve(sizeof(Td4Table));
+  m->d_fixed.reserve(sizeof(Td4FitConst));
+  hip_check(hipMemcpy(m->d_fixed.ptr, &fc, sizeof(fc), hipMemcpyHostToDevice), "hipMemcpy");
+  m->d_M.reserve(sizeof(double) * 2 * kTd4MaxAmp * kTd4MaxAmp);
+}
+
 // ------------------------------------------------------------ pipeline
 static int64_t nchunks_for(int64_t n, int chunk) { return (n + chunk - 1) / chunk; }
 
@@ -221,6 +314,34 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
       m->ev_pending.emplace_back(t0, t1);
     }
     mix1d_launch_finalize(mc, m->table_mix(), m->part(), nch, grad, m->out(), out_user, s);
+  } else if (m->kind == kKindTd4) {
+    const Td4Const& tc = m->td4;
+    if (m->n_mc <= 0) throw Error(FN_E_INVALID, "td4: normalization sample not set (fn_model_set_norm_sample)");
+    const int kmax = td4_kmax(tc.K);
+    m->d_part.reserve(sizeof(double) * (size_t)(nch > 0 ? nch : 1) * td4_nv(kmax, grad));
+    const Td4FitConst* fc = (const Td4FitConst*)m->d_fixed.ptr;
+    td4_launch_prologue(tc, pb, theta_dev, m->P, fc, nullptr, 1, m->table_td4(), s);
+    if (!m->M_valid) {
+      const int mchunk = 1024;
+      const int64_t mrows = nchunks_for(m->n_mc, mchunk);
+      m->d_npart.reserve(sizeof(double) * (size_t)mrows * 8 * kmax);
+      td4_launch_mmatrix(tc, m->table_td4(), 1, (const double*)m->d_mc.ptr, m->n_mc, m->n_mc, mchunk, m->npart(),
+                         m->Mc(), s);
+      m->M_valid = true;
+    }
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (m->timing && nch > 0) {
+      t0 = m->take_event();
+      t1 = m->take_event();
+      hip_check(hipEventRecord(t0, s), "hipEventRecord");
+    }
+    td4_launch_events(tc, m->table_td4(), nullptr, 1, ev, ld, n, m->chunk, grad, m->part(), s);
+    if (t0) {
+      hip_check(hipEventRecord(t1, s), "hipEventRecord");
+      m->ev_pending.emplace_back(t0, t1);
+    }
+    td4_launch_finalize(tc, m->table_td4(), nullptr, 1, m->part(), nch, grad, m->Mc(), (double)n, m->out(), 0,
+                        out_user, s);
   } else {
     const DalitzConst& dc = m->dal;
     const int kmax = dalitz_kmax(dc.K);
@@ -354,6 +475,9 @@ fn_status fn_model_create(fn_ctx* ctx, const char* desc_json, fn_model** out) {
       } else if (kind == "dalitz3") {
         m->kind = kKindDalitz3;
         compile_dalitz3(d, m);
+      } else if (kind == "td4") {
+        m->kind = kKindTd4;
+        compile_td4(d, m);
       } else {
         throw Error(FN_E_INVALID, "unknown model kind \"" + kind + "\"");
       }
@@ -403,6 +527,7 @@ fn_status fn_events_check(fn_model* m, const double* ev, int64_t n, int64_t ld, 
     hipStream_t s = (hipStream_t)stream;
     hip_check(hipMemsetAsync(m->d_count.ptr, 0, sizeof(unsigned long long), s), "hipMemsetAsync");
     if (m->kind == kKindMix1d) mix1d_launch_check(m->mix, ev, n, (unsigned long long*)m->d_count.ptr, s);
+    else if (m->kind == kKindTd4) td4_launch_check(m->td4, ev, ld, n, (unsigned long long*)m->d_count.ptr, s);
     else dalitz_launch_check(m->dal, ev, ld, n, (unsigned long long*)m->d_count.ptr, s);
     hip_check(hipGetLastError(), "kernel launch");
     unsigned long long cnt = 0;
@@ -461,9 +586,38 @@ fn_status fn_eval(fn_model* m, const double* theta_host, const double* ev, int64
     const ParamBlock pb = make_block(m, theta_host);
     run_nll(m, &pb, nullptr, nullptr, 0, 0, false, nullptr, s);
     if (m->kind == kKindMix1d) mix1d_launch_eval(m->mix, m->table_mix(), ev, n, p_dev, s);
+    else if (m->kind == kKindTd4) td4_launch_eval(m->td4, m->table_td4(), ev, ld, n, m->out() + 1 + m->P, p_dev, s);
     else dalitz_launch_eval(m->dal, m->table_dal(), ev, ld, n, m->out() + 1 + m->P, p_dev, s);
     hip_check(hipGetLastError(), "kernel launch");
     hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+  });
+}
+
+fn_status fn_model_set_norm_sample(fn_model* m, const double* mc_dev, int64_t n_mc, int64_t ld, void* stream) {
+  return guard([&] {
+    if (!m) throw Error(FN_E_INVALID, "model is NULL");
+    if (m->kind != kKindTd4) throw Error(FN_E_INVALID, "only td4 models take a normalization sample");
+    if (n_mc <= 0 || !mc_dev) throw Error(FN_E_INVALID, "need n_mc > 0 and a sample pointer");
+    if (ld < n_mc) throw Error(FN_E_INVALID, "ld must be >= n_mc");
+    hip_check(hipSetDevice(m->device), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    m->d_mc.reserve(sizeof(double) * 5 * (size_t)n_mc);
+    hip_check(hipMemcpy2DAsync(m->d_mc.ptr, sizeof(double) * n_mc, mc_dev, sizeof(double) * ld,
+                               sizeof(double) * n_mc, 5, hipMemcpyDeviceToDevice, s),
+              "hipMemcpy2DAsync");
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    m->n_mc = n_mc;
+    m->mc_gen += 1;
+    m->M_valid = false;
+  });
+}
+
+fn_status fn_model_fixed(const fn_model* m, int32_t* n_fixed, double* fixed_host) {
+  return guard([&] {
+    if (!m) throw Error(FN_E_INVALID, "model is NULL");
+    if (m->kind != kKindTd4) throw Error(FN_E_INVALID, "only td4 models have a fixed-constant vector");
+    if (n_fixed) *n_fixed = (int32_t)m->fixed_ls.size();
+    if (fixed_host) std::memcpy(fixed_host, m->fixed_ls.data(), sizeof(double) * m->fixed_ls.size());
   });
 }
 
