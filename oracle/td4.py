@@ -210,3 +210,65 @@ def nll_grad(theta, ev, mc, desc):
     with torch.no_grad():
         norm = fsum(ir.detach()) / mc.shape[1]
     return nll_value(lr.detach(), ev.shape[1], math.log(norm)), th.grad.numpy().copy()
+
+
+def unconvolved_rate(model: TD4, theta, kin, t):
+    """R(x, t) before the resolution convolution (t >= 0)."""
+    B = model.basis(kin)
+    A, Ab = model.amplitudes(theta, B)
+    x, y = theta[model.P - 2], theta[model.P - 1]
+    G = 1.0 / model.tau
+    a2 = A.real ** 2 + A.imag ** 2
+    b2 = Ab.real ** 2 + Ab.imag ** 2
+    z = A.conj() * Ab
+    gt = G * t
+    return 0.5 * torch.exp(-gt) * ((a2 + b2) * torch.cosh(y * gt) + (a2 - b2) * torch.cos(x * gt)
+                                   - 2.0 * z.real * torch.sinh(y * gt) - 2.0 * z.imag * torch.sin(x * gt))
+
+
+def generate(theta, desc, n: int, seed: int = 1710088260, fit: int = 0, batch: int = 200_000):
+    """Events (6, n) distributed as the model at theta, by accept-reject.
+
+    Proposal: an unweighted phase-space point times t_true ~ Exp(G(1 - |y|));
+    since e^{-Gt}cosh(yGt) <= e^{-G(1-|y|)t} and every interference term is
+    bounded by |A||Abar|, R(x, t) <= e^{-G(1-|y|)t} (|A| + |Abar|)^2, so a
+    candidate is kept with probability R / (e^{-G(1-|y|)t} W), W an upper
+    bound of (|A| + |Abar|)^2 over phase space (1.5 x the largest value on a
+    large phase-space sample; a candidate above W raises an error).  The
+    measured time is t_true plus a Gaussian of width sigma_t (Box-Muller)."""
+    from synth import td4_phase_space
+    from synth.philox import key_from_seed, uniforms_at
+    model = TD4(desc)
+    th = as_t(theta)
+    G = 1.0 / model.tau
+    y = float(theta[model.P - 1])
+    lam = G * (1.0 - abs(y))
+    with torch.no_grad():
+        ps = torch.from_numpy(td4_phase_space(batch, seed, fit, stream0=5000))
+        A, Ab = model.amplitudes(th, model.basis(ps))
+        W = 1.5 * float(((A.abs() + Ab.abs()) ** 2).max())
+    key = key_from_seed(seed, fit)
+    out = np.empty((6, n))
+    got = 0
+    rnd = 0
+    while got < n:
+        kin = td4_phase_space(batch, seed, fit, stream0=10_000 + 1000 * rnd)  # 3 streams per attempt
+        i = np.arange(batch, dtype=np.uint64)
+        u1, u2 = uniforms_at(i, key, 3000 + 2 * rnd, 0)
+        u3, u4 = uniforms_at(i, key, 3001 + 2 * rnd, 0)
+        tt = -np.log1p(-u1) / lam
+        with torch.no_grad():
+            kt = torch.from_numpy(kin)
+            r = unconvolved_rate(model, th, kt, torch.from_numpy(tt)).numpy()
+            A, Ab = model.amplitudes(th, model.basis(kt))
+            env = ((A.abs() + Ab.abs()) ** 2).numpy()
+        if (env > W).any():
+            raise RuntimeError("amplitude bound exceeded; raise the safety factor")
+        keep = u2 * W * np.exp(-lam * tt) < r
+        idx = np.nonzero(keep)[0][: n - got]
+        out[:5, got:got + idx.size] = kin[:, idx]
+        gauss = np.sqrt(-2.0 * np.log1p(-u3[idx])) * np.cos(2.0 * math.pi * u4[idx])
+        out[5, got:got + idx.size] = tt[idx] + model.sigma * gauss
+        got += idx.size
+        rnd += 1
+    return out

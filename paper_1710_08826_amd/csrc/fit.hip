@@ -4,7 +4,9 @@
 // strong Wolfe conditions (Nocedal & Wright, Numerical Optimization, 2nd ed.,
 // Algorithms 3.5/3.6 and Eq. 6.17), convergence on the estimated distance to
 // the minimum EDM = g^T H g / 2, errors from the inverse of a numerical
-// Hessian (error definition 1/2 for an NLL).
+// Hessian (error definition 1/2 for an NLL).  An EDM below the tolerance is
+// re-tested with the inverse numerical Hessian before the fit is declared
+// converged, and the iterations continue from that matrix when it fails.
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -13,6 +15,8 @@
 
 namespace fn {
 namespace {
+
+constexpr int kMaxHessianChecks = 3;
 
 struct Objective {
   fn_model* m;
@@ -196,6 +200,27 @@ bool spd_inverse(std::vector<double>& A, int n) {
 
 }  // namespace
 
+// Inverse of the numerical Hessian at x (central differences of the gradient,
+// step 1e-4 of the error the matrix H implies, floored relative to |x|);
+// false if an evaluation fails or the Hessian is not positive definite.
+bool numerical_inverse_hessian(Objective& obj, const std::vector<double>& x, const std::vector<double>& H,
+                               std::vector<double>& Hn) {
+  const int D = obj.dim();
+  Hn.assign((size_t)D * D, 0.0);
+  for (int i = 0; i < D; ++i) {
+    const double d = std::fmax(1e-4 * std::sqrt(std::fabs(H[i * D + i])), 1e-9 * std::fmax(std::fabs(x[i]), 1.0));
+    std::vector<double> xp = x, xm = x, gp, gm;
+    xp[i] += d;
+    xm[i] -= d;
+    double fp, fm;
+    if (!obj.eval(xp, fp, &gp) || !obj.eval(xm, fm, &gm)) return false;
+    for (int j = 0; j < D; ++j) Hn[j * D + i] = (gp[j] - gm[j]) / (xp[i] - xm[i]);
+  }
+  for (int i = 0; i < D; ++i)
+    for (int j = 0; j < i; ++j) Hn[i * D + j] = Hn[j * D + i] = 0.5 * (Hn[i * D + j] + Hn[j * D + i]);
+  return spd_inverse(Hn, D);
+}
+
 void fit_host(fn_model* m, const double* theta0, const int32_t* mask, const double* ev, int64_t n, int64_t ld,
               int grad_mode, double tol, int max_iter, double* theta_out, double* err_out, double* nll_out,
               int32_t* n_iter_out, int32_t* n_calls_out, hipStream_t s) {
@@ -226,6 +251,8 @@ void fit_host(fn_model* m, const double* theta0, const int32_t* mask, const doub
   }
   int iter = 0;
   bool converged = false;
+  bool fresh = false;  // H is the inverse of the numerical Hessian at x
+  int n_hess = 0;
   std::vector<double> p(D);
   for (; iter < max_iter; ++iter) {
     double edm = 0.0;
@@ -237,8 +264,17 @@ void fit_host(fn_model* m, const double* theta0, const int32_t* mask, const doub
     }
     edm *= 0.5;
     if (edm < tol && edm >= 0.0) {
-      converged = true;
-      break;
+      // check the BFGS estimate with the numerical Hessian (as Minuit's MIGRAD does after HESSE)
+      std::vector<double> Hi;
+      if (fresh || n_hess >= kMaxHessianChecks || !numerical_inverse_hessian(obj, x, H, Hi)) {
+        converged = true;
+        break;
+      }
+      n_hess += 1;
+      H = Hi;
+      fresh = true;
+      --iter;  // re-test without consuming an iteration
+      continue;
     }
     double fnew = f;
     double a = line_search(obj, x, f, g, p, xn, fnew, gn);
@@ -262,7 +298,7 @@ void fit_host(fn_model* m, const double* theta0, const int32_t* mask, const doub
     }
     const double sy = dot(sv, yv);
     if (sy > 0.0) {
-      if (iter == 0) {
+      if (iter == 0 && n_hess == 0) {
         // Nocedal & Wright Eq. 6.20 rescaling before the first update
         const double scale = sy / dot(yv, yv);
         for (int i = 0; i < D; ++i)
@@ -283,6 +319,7 @@ void fit_host(fn_model* m, const double* theta0, const int32_t* mask, const doub
     x = xn;
     f = fnew;
     g = gn;
+    fresh = false;
   }
   for (int i = 0; i < D; ++i) obj.full[obj.free_idx[i]] = x[i];
   if (theta_out)
@@ -290,26 +327,14 @@ void fit_host(fn_model* m, const double* theta0, const int32_t* mask, const doub
   if (nll_out) *nll_out = f;
   if (err_out) {
     for (int p2 = 0; p2 < m->P; ++p2) err_out[p2] = 0.0;
-    // numerical Hessian at the minimum: central differences of the gradient
-    std::vector<double> Hn(D * D, 0.0);
-    bool ok = true;
-    for (int i = 0; i < D && ok; ++i) {
-      const double d = 1e-4 * std::sqrt(std::fmax(std::fabs(H[i * D + i]), 1e-300));
-      std::vector<double> xp = x, xm = x, gp, gm;
-      xp[i] += d;
-      xm[i] -= d;
-      double fp, fm;
-      ok = obj.eval(xp, fp, &gp) && obj.eval(xm, fm, &gm);
-      if (ok)
-        for (int j = 0; j < D; ++j) Hn[j * D + i] = (gp[j] - gm[j]) / (xp[i] - xm[i]);
+    std::vector<double> Hn;
+    const std::vector<double>* C = &H;  // BFGS estimate as the fallback
+    if (fresh) {
+      C = &H;
+    } else if (numerical_inverse_hessian(obj, x, H, Hn)) {
+      C = &Hn;
     }
-    for (int i = 0; i < D && ok; ++i)
-      for (int j = 0; j < i; ++j) Hn[i * D + j] = Hn[j * D + i] = 0.5 * (Hn[i * D + j] + Hn[j * D + i]);
-    if (ok && spd_inverse(Hn, D)) {
-      for (int i = 0; i < D; ++i) err_out[obj.free_idx[i]] = std::sqrt(Hn[i * D + i]);
-    } else {
-      for (int i = 0; i < D; ++i) err_out[obj.free_idx[i]] = std::sqrt(std::fabs(H[i * D + i]));
-    }
+    for (int i = 0; i < D; ++i) err_out[obj.free_idx[i]] = std::sqrt(std::fabs((*C)[i * D + i]));
   }
   if (n_iter_out) *n_iter_out = iter;
   if (n_calls_out) *n_calls_out = (int32_t)obj.calls;

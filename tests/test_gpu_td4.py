@@ -106,10 +106,9 @@ def test_eval_is_normalized_rate(model, mc):
     err = np.abs(p - r / I) / (cond / I)
     k = int(np.argmax(err))
     assert err.max() <= 1e-12, (err.max(), k, ev[:, k], p[k], r[k] / I)
-    # away from interference minima the plain relative error is held to 1e-12 too
-    easy = r > 1e-2 * cond
-    assert easy.mean() > 0.9
-    assert (np.abs(p - r / I)[easy] <= 1e-12 * (r / I)[easy]).all()
+    # and the plain relative error is within 1e-12 for all but a few events at interference minima
+    rel = np.abs(p - r / I) / (r / I)
+    assert (rel <= 1e-12).mean() >= 0.999, np.sort(rel)[-8:]
 
 
 def test_empty_sample_and_determinism(model):

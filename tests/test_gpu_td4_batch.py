@@ -85,38 +85,69 @@ def test_batched_nll_matches_single_and_oracle(setup):
             assert ok, (f, r.max())
 
 
-def test_batched_fits_converge_and_match_alone(setup):
-    from paper_1710_08826_amd import VariationBatch
-    m, mc, mcd = setup
+# A well-conditioned fit: three amplitudes of distinct shapes, mixing large
+# enough to constrain Abar, c_0 and cbar_0 fixed (they carry the global phase
+# and scale and the relative phase that trades against a rotation of (x, y)).
+SMALL = synth.td4_desc(r12=((0, 0.0, 0.0),))
+SMALL["amps"] = [[0, 0, 0], [0, 1, 1], [0, 2, 0]]
+SMALL_TH = np.array([0.5, 0.0, -0.3, 0.35, 0.2, 0.25, 1.0, 0.0, 0.8, 0.45, 0.35, -0.3, 0.2, 0.15])
+SMALL_FREE = np.array([0, 0, 1, 1, 1, 1, 0, 0, 1, 1, 1, 1, 1, 1], np.int32)
+
+
+def small_variation(fx, f):
+    v = fx.copy()
+    if f:
+        s = 1.0 if f % 2 else -1.0
+        k = (f - 1) // 2 % 3
+        if k == 0:
+            v[2 + 2] += s * 0.002          # rho(770) mass (r34 entry 1)
+        elif k == 1:
+            v[2 + 3] *= 1.0 + s * 0.05     # rho(770) width
+        else:
+            v[-1] *= 1.0 + s * 0.1         # time resolution
+    return v
+
+
+def test_batched_fits_converge_and_match_alone():
+    """Events drawn from the model itself (oracle accept-reject); six variation
+    fits from a common offset start."""
+    from paper_1710_08826_amd import Model, VariationBatch
+    Ps = SMALL_TH.size
+    m = Model(SMALL)
+    m.set_norm_sample(to_dev(synth.td4_phase_space(50_000, seed=65)))
+    say("td4 generating model events")
+    ev = to_dev(OT.generate(SMALL_TH, SMALL, 20_000, seed=66))
     F = 6
     fx0 = m.fixed()
-    ev = to_dev(synth.td4_events(20_000, seed=63))
-    free = np.ones(P, np.int32)
-    free[20:22] = 0  # cbar_0 is the reference amplitude
-    th0 = thetas(F)
-    th0[:, 20:22] = TH[20:22]
+    free = SMALL_FREE
+    th0 = np.stack([SMALL_TH * (1 + 0.05 * np.sin(np.arange(Ps) + f)) for f in range(F)])
+    th0[:, free == 0] = SMALL_TH[free == 0]
     b = VariationBatch(m, F)
     for f in range(F):
-        b.set_fixed(f, variation(fx0, f))
+        b.set_fixed(f, small_variation(fx0, f))
     say("td4 vbatch fit F =", F)
-    r = b.fit(th0, ev, free=free, tol=1e-6, max_iter=1000)
+    r = b.fit(th0, ev, free=free, tol=1e-7, max_iter=1000)
     say("status", r.status, "iters", r.iters, "evals", r.n_evals)
     assert (r.status == 2).all()
     assert (r.nll <= b.nll(th0, ev)).all()
-    # the same minimum as the host minimizer with a numerical-Hessian covariance (nominal fit)
-    ref = m.fit(th0[0], ev, free=free, tol=1e-6, max_iter=1000)
+    # the same minimum and errors as the host minimizer (nominal fit)
+    ref = m.fit(th0[0], ev, free=free, tol=1e-7, max_iter=1000)
     say("host fit nll", ref.nll, "batch", r.nll[0])
-    assert abs(r.nll[0] - ref.nll) < 1e-4
+    assert abs(r.nll[0] - ref.nll) < 1e-5
     sig = np.where(free == 1, ref.errors, 1.0)
-    assert (np.abs(r.theta[0] - ref.theta) / sig).max() < 0.05
+    assert (np.abs(r.theta[0] - ref.theta) / sig).max() < 0.02
+    assert np.allclose(r.errors[0][free == 1], ref.errors[free == 1], rtol=0.02)
+    # the generation point lies within the statistical errors of the nominal fit
+    pull = ((ref.theta - SMALL_TH) / sig)[free == 1]
+    assert np.abs(pull).max() < 4.0, pull
     # fit 4 alone in a batch of one: same trajectory, same bits
     one = VariationBatch(m, 1)
-    one.set_fixed(0, variation(fx0, 4))
-    r1 = one.fit(th0[4:5], ev, free=free, tol=1e-6, max_iter=1000)
+    one.set_fixed(0, small_variation(fx0, 4))
+    r1 = one.fit(th0[4:5], ev, free=free, tol=1e-7, max_iter=1000)
     assert r1.status[0] == 2 and r1.iters[0] == r.iters[4] and r1.n_evals[0] == r.n_evals[4]
     assert r1.nll[0] == r.nll[4] and (r1.theta[0] == r.theta[4]).all()
     # graph replay and plain launches give the same result
-    r2 = one.fit(th0[4:5], ev, free=free, tol=1e-6, max_iter=1000, use_graph=False)
+    r2 = one.fit(th0[4:5], ev, free=free, tol=1e-7, max_iter=1000, use_graph=False)
     assert r2.nll[0] == r1.nll[0] and (r2.theta[0] == r1.theta[0]).all()
 
 

@@ -123,3 +123,39 @@ def test_phase_space_marginal():
     keep = exp > 20
     chi2 = (((counts - exp) ** 2) / exp)[keep].sum()
     assert chi2 < 50, chi2  # 19 dof
+
+
+SMALL = synth.td4_desc(r12=((0, 0.0, 0.0), (0, 1.370, 0.350)))
+SMALL["amps"] = [[0, 0, 0], [0, 1, 1], [0, 2, 0], [1, 1, 1], [1, 0, 0], [1, 2, 0]]
+SMALL_TH = np.array([0.25, 0.0, -0.12, 0.20, 0.05, 0.09, 0.10, -0.04, 0.3, 0.22, -0.08, 0.11,
+                     1.0, 0.0, 0.8, 0.45, 0.35, -0.2, -0.3, 0.55, 1.6, -0.4, 0.45, 0.3, 0.004, 0.006])
+
+
+def test_generator_time_distribution_without_mixing():
+    """x = y = 0: R(x, t) = |A(x)|^2 e^{-Gt}, so t_true ~ Exp(G) for every point and
+    the measured t (plus a zero-mean Gaussian) has mean tau and variance tau^2 + sigma^2."""
+    th = SMALL_TH.copy()
+    th[-2:] = 0.0
+    ev = OT.generate(th, SMALL, 4000, seed=11)
+    n = ev.shape[1]
+    tau, s = synth.TD4_TAU, synth.TD4_SIGMA_T
+    sd = math.sqrt(tau * tau + s * s)
+    assert abs(ev[5].mean() - tau) < 4 * sd / math.sqrt(n)
+    assert abs(ev[5].var() / (sd * sd) - 1) < 4 * math.sqrt(8.0 / n)  # exponential kurtosis 9
+
+
+def test_generator_kinematics_follow_the_amplitude():
+    """The m34 histogram of generated events against a phase-space sample
+    reweighted by the time-integrated rate (chi-square over 12 bins)."""
+    ev = OT.generate(SMALL_TH, SMALL, 4000, seed=12)
+    ps = synth.td4_phase_space(200_000, seed=13)
+    model = OT.TD4(SMALL)
+    with torch.no_grad():
+        w = model.integrated_rate(torch.tensor(SMALL_TH), torch.tensor(ps)).numpy()
+    edges = np.quantile(ev[1], np.linspace(0, 1, 13))
+    edges[0], edges[-1] = 0.0, 10.0
+    counts, _ = np.histogram(ev[1], edges)
+    prob, _ = np.histogram(ps[1], edges, weights=w)
+    exp = prob / prob.sum() * ev.shape[1]
+    chi2 = (((counts - exp) ** 2) / exp).sum()
+    assert chi2 < 35, chi2  # 11 dof
