@@ -52,6 +52,7 @@ def measured_traffic():
 # ISA of this toolchain: the price of each elementary function in the
 # algorithmic FLOP count (the kernels use cheaper Newton-refined forms).
 W_SQRT, W_RSQRT, W_DIV, W_LOG, W_EXP = 19, 9, 17, 85, 30
+W_SINCOS = 59  # the small-argument path (|x| below the large-reduction threshold)
 
 
 def dalitz_flops_per_event(desc: dict, grad: int) -> int:
@@ -78,6 +79,49 @@ def dalitz_flops_per_event(desc: dict, grad: int) -> int:
         f += 4 + W_DIV + 6 * K                     # -1/P~, 2 Re(conj(S) A) per coefficient
     if grad >= 2:
         f += 31 * K                                # mass and width derivatives
+    return f
+
+
+def td4_flops_per_event(desc: dict, grad: bool) -> int:
+    """Algorithmic FP64 FLOPs per (event, fit) of the time-dependent
+    four-body NLL, counted from the formula as evaluated: per-pair kinematics
+    shared by the pair's resonances, one complex reciprocal per resonance,
+    products with flat (non-resonant) entries free, the three time terms
+    through the rational Faddeeva approximation (40 coefficients, Horner),
+    one log per event."""
+    N = 40
+    f = 0
+    pairs = (desc["r12"], desc["r34"])
+    for entries in pairs:
+        res = [e for e in entries if e["m0"] != 0.0]
+        f += 7 + W_DIV + W_SQRT                    # s, 1/m, lambda, q^2, q, G0
+        if any(int(e["L"]) == 1 for e in res):
+            f += 6 + W_RSQRT                       # z, F1 = (1+z)^-1/2, G1
+        f += len(res) * (9 + W_DIV)                # a, b, 1/(a^2+b^2), amplitude
+    types = [int(a[2]) for a in desc["amps"]]
+    f += 2 * (2 + W_SQRT) + 2                      # sin12 sin34 / 2
+    if any(t >= 4 for t in types):
+        f += W_SINCOS                              # e^{i phi}
+    if 3 in types:
+        f += 1                                     # c12 c34
+    flat12 = [e["m0"] == 0.0 for e in desc["r12"]]
+    flat34 = [e["m0"] == 0.0 for e in desc["r34"]]
+    for i12, i34, t in desc["amps"]:
+        f += 0 if (flat12[i12] or flat34[i34]) else 6
+        f += 0 if t == 0 else (2 if t <= 3 else 6)
+    K = len(desc["amps"])
+    f += 16 * K                                    # A and Abar
+    f += 2 + W_EXP                                 # exp(-t^2 / 2 sigma^2)
+    horner_r = (N - 1) * 2
+    h_real = 3 + (1 + W_DIV) + 2 + horner_r + 4 + (4 + W_EXP) + 3
+    horner_c = (N - 1) * 7
+    w_c = 1 + (5 + W_DIV) + 7 + horner_c + 8 + 7
+    h_cplx = 5 + w_c + 9 + W_SINCOS + W_EXP + 7
+    f += 2 * h_real + h_cplx
+    f += 27 + W_LOG + 1                            # rate, log, accumulate
+    if grad:
+        f += 2 * 3 + 8                             # dh/da of the three time terms
+        f += 1 + W_DIV + 2 + 40 * K + 20           # -1/R, per-amplitude adjoint, x and y
     return f
 
 
@@ -224,6 +268,87 @@ def serving_leg(n_fits: int = 4096, one_at_a_time: int = 256, fd_fits: int = 32,
     return out
 
 
+def td4_leg(steps: int = 10):
+    """Config 4: the time-dependent four-body model, 10M events, 5M-point
+    phase-space normalization sample; single-fit NLL + adjoint gradient, the
+    plain finite-difference gradient, and 64 systematic-variation fits sharing
+    the events (one events pass for all fits per step)."""
+    import torch
+    import synth
+    from paper_1710_08826_amd import Model, VariationBatch
+    n, n_mc, F = 10_000_000, 5_000_000, 64
+    t0 = time.perf_counter()
+    ev = torch.from_numpy(synth.td4_events(n, seed=synth.BASE_SEED + 4)).cuda()
+    mc = torch.from_numpy(synth.td4_phase_space(n_mc, seed=synth.BASE_SEED + 5)).cuda()
+    gen_s = time.perf_counter() - t0
+    desc = synth.td4_desc()
+    th = synth.td4_truth()
+    m = Model(desc)
+    m.set_norm_sample(mc)
+    del mc
+    P = m.n_params
+    tdev = torch.from_numpy(th).cuda()
+    tb = torch.from_numpy(th * (1.0 + 1e-3 * np.cos(np.arange(P)))).cuda()
+    out = torch.empty(1 + P, dtype=torch.float64, device="cuda")
+    fl_g, fl_0 = td4_flops_per_event(desc, True), td4_flops_per_event(desc, False)
+    w, k = time_async(m, tdev, ev, out, steps, 2, True, alt=tb)
+    w0, k0 = time_async(m, tdev, ev, out, steps, 2, False, alt=tb)
+    r = {"events": n, "mc_points": n_mc, "params": P, "cpu_generation_s": gen_s,
+         "single_events_per_s": n * steps / w, "single_ms_per_step": 1e3 * w / steps,
+         "single_event_kernel_ms": k, "single_event_kernel_tflops": fl_g * n / (k * 1e-3) / 1e12,
+         "nll_only_event_kernel_ms": k0, "nll_only_event_kernel_tflops": fl_0 * n / (k0 * 1e-3) / 1e12,
+         "flops_per_event_fit": fl_g, "flops_per_event_fit_nll_only": fl_0}
+    # plain finite differences: 2P + 1 NLL-only evaluations per gradient, one call at a time
+    reps = 2
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        m.nll(th, ev)
+        for p in range(P):
+            h = 1e-6 * max(abs(th[p]), 1.0)
+            tp = th.copy(); tp[p] += h
+            tm = th.copy(); tm[p] -= h
+            m.nll(tp, ev)
+            m.nll(tm, ev)
+    fd = (time.perf_counter() - t0) / reps
+    r["plain_fd_grad_events_per_s"] = n / fd
+    r["adjoint_vs_plain_fd"] = r["single_events_per_s"] / r["plain_fd_grad_events_per_s"]
+    # 64 systematic variations: +-shifts of lineshape constants and the time resolution
+    b = VariationBatch(m, F)
+    fx = m.fixed()
+    for f in range(F):
+        v = fx.copy()
+        j = (3, 8, 9, 11, 12)[f % 5]
+        v[j] *= 1.0 + 0.002 * ((f // 5) - 6)
+        b.set_fixed(f, v)
+    ths = np.stack([th * (1.0 + 1e-3 * np.sin(np.arange(P) + f)) for f in range(F)])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.nll(ths, ev, grad=True)  # builds the 64 normalization matrices
+    r["batch_first_call_s"] = time.perf_counter() - t0
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.nll(ths, ev, grad=True)
+    wb = (time.perf_counter() - t0) / reps
+    r["batch_fits"] = F
+    r["batch_event_fits_per_s"] = n * F / wb
+    r["batch_ms_per_step"] = 1e3 * wb
+    r["batch_tflops"] = fl_g * n * F / wb / 1e12
+    r["batch_vs_single_calls"] = (F * r["single_ms_per_step"]) / r["batch_ms_per_step"]
+    # batched minimizer steps (evaluation + device BFGS update), a few iterations
+    free = np.ones(P, np.int32)
+    K = (P - 2) // 4
+    free[2 * K: 2 * K + 2] = 0  # cbar_0 is the reference amplitude
+    t0 = time.perf_counter()
+    res = b.fit(ths, ev, free=free, max_iter=4)
+    wf = time.perf_counter() - t0
+    r["batch_fit_steps"] = int(res.n_evals.max())
+    r["batch_fit_ms_per_step"] = 1e3 * wf / max(1, int(res.n_evals.max()))
+    b.close()
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -334,6 +459,15 @@ def main():
         extra["config0_fit_speedup_adjoint_vs_fd"] = extra["config0_fit_fd_ms"] / extra["config0_fit_adjoint_ms"]
         print(f"[bench] config0 fits: adjoint {extra['config0_fit_adjoint_ms']:.2f} ms, "
               f"fd {extra['config0_fit_fd_ms']:.2f} ms", file=sys.stderr, flush=True)
+
+    if not args.quick:
+        print("[bench] config4 td4 (10M events, 5M-point sample, 64 variation fits) ...", file=sys.stderr,
+              flush=True)
+        extra["config4"] = td4_leg()
+        c4 = extra["config4"]
+        print(f"[bench] config4: single {c4['single_events_per_s']:.4g} events/s "
+              f"({c4['single_event_kernel_tflops']:.2f} TFLOP/s), 64 fits {c4['batch_event_fits_per_s']:.4g} "
+              f"event-fits/s, adjoint vs FD {c4['adjoint_vs_plain_fd']:.1f}x", file=sys.stderr, flush=True)
 
     if not args.quick:
         print("[bench] config2 serving (4096 toy fits) ...", file=sys.stderr, flush=True)
