@@ -126,6 +126,13 @@ typedef struct fn_model fn_model;
  *  the summation tree.
  * Returns FN_E_INVALID with a message for a malformed description. */
 fn_status fn_model_create(fn_ctx* ctx, const char* desc_json, fn_model** out);
+/* Compile a description's structure-specialized kernels for the GPU
+ * architecture `arch` (NULL or "" = "gfx950") without a device and without
+ * loading them: the same runtime compilation fn_model_create performs (it
+ * specializes the per-event passes of amplitude models to their structure).
+ * Returns FN_E_INVALID with the compiler log for a description that does not
+ * compile.  Needs no GPU. */
+fn_status fn_model_check_compile(const char* desc_json, const char* arch);
 /* Number of parameters, observables, and the summation chunk of a model. */
 fn_status fn_model_info(const fn_model* m, int32_t* n_params, int32_t* n_obs, int32_t* chunk);
 /* Frees the model's device memory.  Streams using it must be synchronised. */

@@ -40,6 +40,7 @@ PROTOTYPES = {
     "fn_ctx_create": (i32, [i32, C.POINTER(vp)]),
     "fn_ctx_destroy": (i32, [vp]),
     "fn_model_create": (i32, [vp, C.c_char_p, C.POINTER(vp)]),
+    "fn_model_check_compile": (i32, [C.c_char_p, C.c_char_p]),
     "fn_model_info": (i32, [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]),
     "fn_model_destroy": (i32, [vp]),
     "fn_events_check": (i32, [vp, vp, i64, i64, C.POINTER(i64), vp]),

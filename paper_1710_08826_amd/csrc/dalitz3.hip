@@ -1,47 +1,18 @@
 // Three-body Dalitz-plot amplitude model (the paper's amplitude analyses of
-// three-body decays, Sec. 1 and 5):  P~(s12, s13) = |sum_k c_k A_k|^2,
-//
-//   A_k = [F_L(q r)/F_L(q0 r)] F_L(p r_D) Z_L(s) T_k(s_AB)
-//   T_k = 1 / (m0^2 - s_AB - i m0 Gamma_k(s_AB))
-//   Gamma_k(s) = Gamma0 (q/q0)^(2L+1) (m0/sqrt s) [F_L(q r)/F_L(q0 r)]^2
-//
-// with Blatt-Weisskopf factors F_0 = 1, F_1 = (1+z)^-1/2,
-// F_2 = (z^2+3z+9)^-1/2 (z = (q r)^2) and Zemach spin factors Z_0 = 1,
-// Z_1 = s_AC - s_BC + (M^2 - mC^2)(mB^2 - mA^2)/s_AB, Z_2 = Z_1^2 - X Y / 3,
-// X = lambda(s_AB, M^2, mC^2)/s_AB, Y = lambda(s_AB, mA^2, mB^2)/s_AB.
-//
-// GPU organisation (per event, all in registers):
-//  * every quantity that depends only on the pair (s_AB, q, p, the barrier
-//    polynomials, Zemach factors) is computed once per pair and shared by all
-//    resonances of that pair: the model has three pairs and eight resonances,
-//    so this removes most of the square roots and divisions;
-//  * per resonance the lineshape reduces to T = (a + i b)/(a^2 + b^2) with
-//    a = m0^2 - s and b = m0 Gamma(s) = Kw * G_{pair,L}(s), where
-//    G = q^(2L+1) F_L(q r)^2 / sqrt(s) is per pair and
-//    Kw = Gamma0 m0^2 / (q0^(2L+1) F_L(q0 r)^2) comes from the prologue;
-//  * the amplitude is A = Ka * H_{pair,L} * T with H = F_L(q r) F_L(p r_D) Z_L
-//    per pair and Ka = 1/F_L(q0 r) per resonance.
-// The resonance loop is unrolled to a compile-time maximum with uniform
-// guards, so amplitudes and gradient accumulators stay in VGPRs.
-//
-// Modes of the shared chunk routine:
-//   kEvents  -ln P~ over an event chunk (+ adjoint gradient)          -> NLL
-//   kGrid    P~ over a chunk of grid cells inside the region (+ dP~)  -> I
-//   kMRows   rows i0..i0+3 of sum_cells A_i conj(A_j)                 -> cached M
+// three-body decays, Sec. 1 and 5): host launchers, and the kernels that do
+// not depend on the model's structure (prologue, level-2 finalize, per-event
+// density, domain check).  The per-event, grid and normalization-matrix
+// passes live in dalitz_device.hpp and are compiled at model creation with
+// the model's structure as compile-time constants (dalitz_jit below).
 #include <cmath>
+#include <sstream>
 
-#include "device_common.hpp"
-#include "fastmath.hpp"
+#include "dalitz_device.hpp"
+#include "internal.hpp"
+#include "jit.hpp"
 #include "kernels.hpp"
 
 namespace fn {
-
-enum DalMode : int { kEvents = 0, kGrid = 1, kMRows = 2 };
-constexpr int kMRowBlock = 4;
-
-__host__ __device__ constexpr int dal_nv(int mode, int grad, int kmax) {
-  return mode == kMRows ? 2 * kMRowBlock * kmax : 1 + (grad == 0 ? 0 : (grad == 1 ? 2 * kmax : 4 * kmax));
-}
 
 // ---------------------------------------------------------------- prologue
 // Per resonance: Kw, Ka and (for lineshape gradients) their derivatives.
@@ -92,205 +63,6 @@ __global__ void dalitz_prologue(DalitzConst dc, ParamBlock pb, const double* __r
   __syncthreads();
   if (k == 0) tab[f].valid = bad ? 0.0 : 1.0;
 }
-
-// ------------------------------------------------------------- pair terms
-struct PairTerms {
-  double s;         // s_AB
-  double G[3];      // q^(2L+1) F_L(q r)^2 / sqrt(s)
-  double H[3];      // F_L(q r) F_L(p r_D) Z_L
-};
-
-// G and H of one pair from (s_AB, s_AC, s_BC):
-//   q/sqrt(s) = sqrt(lambda_q) / (2 s),  q^2 = lambda_q / (4 s),  p^2 = lambda_p / (4 s)
-//   G_1 = (q/sqrt s) q^2 / (1 + z_q),          H_1 = Z_1 / sqrt((1 + z_q)(1 + z_p))
-//   G_2 = (q/sqrt s) q^4 / (z_q^2 + 3 z_q + 9), H_2 = Z_2 / sqrt(poly(z_q) poly(z_p))
-__device__ __forceinline__ void pair_terms(const DalitzChan& ch, double s_ab, double s_ac, double s_bc, double r2,
-                                           double rD2, PairTerms& o) {
-  const double irs = rsqrt_nr(s_ab);
-  const double is = irs * irs;
-  const double lq = fmax((s_ab - ch.sum2) * (s_ab - ch.dif2), 0.0);
-  const double lp = fmax((s_ab - ch.Psum2) * (s_ab - ch.Pdif2), 0.0);
-  const double q2 = 0.25 * lq * is;
-  const double qirs = 0.5 * sqrt_nr(lq) * is;
-  o.s = s_ab;
-  o.G[0] = qirs;
-  o.H[0] = 1.0;
-  o.G[1] = o.G[2] = o.H[1] = o.H[2] = 0.0;
-  if (ch.useL[1] | ch.useL[2]) {
-    const double p2 = 0.25 * lp * is;
-    const double zq = q2 * r2, zp = p2 * rD2;
-    const double z1 = __builtin_fma(ch.zc, is, s_ac - s_bc);
-    if (ch.useL[1]) {
-      const double uq = 1.0 + zq, up = 1.0 + zp;
-      o.G[1] = qirs * q2 * rcp_nr(uq);
-      o.H[1] = z1 * rsqrt_nr(uq * up);
-    }
-    if (ch.useL[2]) {
-      const double vq = __builtin_fma(zq, zq + 3.0, 9.0), vp = __builtin_fma(zp, zp + 3.0, 9.0);
-      o.G[2] = qirs * q2 * q2 * rcp_nr(vq);
-      const double z2 = z1 * z1 - (lp * is) * (lq * is) * (1.0 / 3.0);
-      o.H[2] = z2 * rsqrt_nr(vq * vp);
-    }
-  }
-}
-
-// Physical-region predicate at a grid-cell centre: s23 between its limits at
-// this s12, from the energies of daughters 2 and 3 in the (12) rest frame.
-// Contraction is off so that the decision is the plain IEEE evaluation.
-__device__ inline bool dalitz_inside(const DalitzConst& dc, double s12, double s13) {
-#pragma clang fp contract(off)
-  const double rs = sqrt(s12);
-  const double e2 = (s12 - dc.m1s + dc.m2s) / (2.0 * rs);
-  const double e3 = (dc.M2 - s12 - dc.m3s) / (2.0 * rs);
-  const double p2 = sqrt(fmax(e2 * e2 - dc.m2s, 0.0));
-  const double p3 = sqrt(fmax(e3 * e3 - dc.m3s, 0.0));
-  const double es = e2 + e3;
-  const double lo = es * es - (p2 + p3) * (p2 + p3);
-  const double hi = es * es - (p2 - p3) * (p2 - p3);
-  const double s23 = dc.msum - s12 - s13;
-  return s23 >= lo && s23 <= hi;
-}
-
-// ------------------------------------------------------------ chunk routine
-// GRAD: 0 none, 1 coefficients only, 2 coefficients + masses and widths.
-// Pairs are visited one at a time (only one pair's G/H are live) and each
-// resonance of the pair adds c_k A_k to the coherent sum.
-template <int MODE, int GRAD, int KMAX>
-__device__ inline void dalitz_chunk(const DalitzConst& dc, const DalitzTable* __restrict__ tab,
-                                    const double* __restrict__ ev, int64_t ld, int64_t n, int64_t chunk_idx,
-                                    int chunk, int i0, double* __restrict__ out_row, double* lds) {
-  constexpr int NV = dal_nv(MODE, GRAD, KMAX);
-  constexpr bool KEEP_A = (GRAD >= 1) || MODE == kMRows;
-  constexpr bool KEEP_T = GRAD == 2;
-  double acc[NV];
-#pragma unroll
-  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
-  const int64_t base = chunk_idx * chunk;
-  const int64_t end = base + chunk < n ? base + chunk : n;
-  const double* r = &tab->r[0][0];
-  for (int64_t i = base + threadIdx.x; i < end; i += kBlock) {
-    double s12, s13;
-    if (MODE == kEvents) {
-      s12 = ev[i];
-      s13 = ev[ld + i];
-    } else {
-      const int64_t ix = i / dc.ny;
-      const int64_t iy = i - ix * dc.ny;
-      s12 = dc.a12 + (ix + 0.5) * dc.d12;
-      s13 = dc.a13 + (iy + 0.5) * dc.d13;
-      if (!dalitz_inside(dc, s12, s13)) continue;
-    }
-    const double s23 = dc.msum - s12 - s13;
-    double Are[KMAX], Aim[KMAX], Tre[KMAX], Tim[KMAX], Gk[KMAX];
-    double Sre = 0.0, Sim = 0.0;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const DalitzChan& ch = dc.ch[c];
-      if (!(ch.useL[0] | ch.useL[1] | ch.useL[2])) continue;
-      // pair "12": (A,B,C) = (1,2,3); "13": (1,3,2); "23": (2,3,1)
-      const double s_ab = c == 0 ? s12 : (c == 1 ? s13 : s23);
-      const double s_ac = c == 0 ? s13 : s12;
-      const double s_bc = c == 2 ? s13 : s23;
-      PairTerms pt;
-      pair_terms(ch, s_ab, s_ac, s_bc, dc.r2, dc.rD2, pt);
-#pragma unroll
-      for (int k = 0; k < KMAX; ++k) {
-        if (k < dc.K && dc.chan[k] == c) {
-          const int L = dc.L[k];
-          const double* rk = r + k * kDalFields;
-          const double G = L == 0 ? pt.G[0] : (L == 1 ? pt.G[1] : pt.G[2]);
-          const double H = L == 0 ? pt.H[0] : (L == 1 ? pt.H[1] : pt.H[2]);
-          const double a = rk[dM0SQ] - pt.s;
-          const double b = rk[dKW] * G;
-          const double d = rcp_nr(__builtin_fma(a, a, b * b));
-          const double tr = a * d, ti = b * d;
-          const double kh = rk[dKA] * H;
-          const double ar = kh * tr, ai = kh * ti;
-          if (KEEP_A) { Are[k] = ar; Aim[k] = ai; }
-          if (KEEP_T) { Tre[k] = tr; Tim[k] = ti; Gk[k] = G; }
-          if (MODE != kMRows) {
-            const double cr = rk[dCRE], ci = rk[dCIM];
-            Sre += cr * ar - ci * ai;
-            Sim += cr * ai + ci * ar;
-          }
-        }
-      }
-    }
-    if (MODE == kMRows) {
-#pragma unroll
-      for (int ib = 0; ib < kMRowBlock; ++ib) {
-        // A_i for i = i0 + ib, selected from registers with uniform guards
-        double xr = 0.0, xi = 0.0;
-#pragma unroll
-        for (int k = 0; k < KMAX; ++k)
-          if (k == i0 + ib) { xr = Are[k]; xi = Aim[k]; }
-#pragma unroll
-        for (int j = 0; j < KMAX; ++j) {
-          if (j < dc.K) {
-            acc[2 * (ib * KMAX + j)] += xr * Are[j] + xi * Aim[j];
-            acc[2 * (ib * KMAX + j) + 1] += xi * Are[j] - xr * Aim[j];
-          }
-        }
-      }
-      continue;
-    }
-    const double Pt = __builtin_fma(Sre, Sre, Sim * Sim);
-    double w;  // multiplies dP~/dtheta
-    if (MODE == kEvents) {
-      acc[0] -= log_fast(Pt);
-      w = -rcp_nr(Pt);
-    } else {
-      acc[0] += Pt;
-      w = 1.0;
-    }
-    if (GRAD >= 1) {
-      const double w2 = 2.0 * w;
-      const double ur = w2 * Sre, ui = w2 * Sim;
-#pragma unroll
-      for (int k = 0; k < KMAX; ++k) {
-        if (k < dc.K) {
-          // dP~/dRe c = 2 Re(conj(S) A), dP~/dIm c = 2 (Sim Are - Sre Aim)
-          acc[1 + 2 * k] += ur * Are[k] + ui * Aim[k];
-          acc[2 + 2 * k] += ui * Are[k] - ur * Aim[k];
-        }
-      }
-    }
-    if (GRAD == 2) {
-      const double w2 = 2.0 * w;
-#pragma unroll
-      for (int k = 0; k < KMAX; ++k) {
-        if (k < dc.K) {
-          const double* rk = r + k * kDalFields;
-          const double cr = rk[dCRE], ci = rk[dCIM];
-          // E = conj(S) c A
-          const double car = cr * Are[k] - ci * Aim[k], cai = cr * Aim[k] + ci * Are[k];
-          const double er = Sre * car + Sim * cai, ei = Sre * cai - Sim * car;
-          // dA/dm0 = A (dlnKa - T (2 m0 - i G dKw/dm0));  dP~ = 2 Re(E * (...))
-          const double gd = Gk[k] * rk[dDKW_DM0], tm = rk[dTWOM0];
-          const double xr = tm * Tre[k] + Tim[k] * gd;
-          const double xi = tm * Tim[k] - Tre[k] * gd;
-          const double yr = rk[dDLNKA] - xr, yi = -xi;
-          acc[1 + 2 * KMAX + 2 * k] += w2 * (er * yr - ei * yi);
-          // dA/dGamma0 = i A T G Kw/Gamma0
-          const double gw = Gk[k] * rk[dKW_W0];
-          acc[2 + 2 * KMAX + 2 * k] += w2 * gw * (-er * Tim[k] - ei * Tre[k]);
-        }
-      }
-    }
-  }
-  block_sum_row<NV>(acc, lds, out_row);
-}
-
-// FN_DALITZ_WAVES > 0 asks the register allocator for that many waves per
-// SIMD (a tuning knob; 0 leaves the choice to the compiler).
-#ifndef FN_DALITZ_WAVES
-#define FN_DALITZ_WAVES 0
-#endif
-#if FN_DALITZ_WAVES > 0
-#define FN_DALITZ_WAVES_ATTR __attribute__((amdgpu_waves_per_eu(FN_DALITZ_WAVES, 8)))
-#else
-#define FN_DALITZ_WAVES_ATTR
-#endif
 
 // ------------------------------------------------------------- finalize
 // Arguments of the level-2 + NLL assembly step.
@@ -381,20 +153,6 @@ __device__ void dalitz_finalize_body(const DalitzConst& dc, const DalitzTable* _
   }
 }
 
-// Evaluation pass: one workgroup per chunk, one row of partial sums each.
-// (Finishing the level-2 sum inside the last workgroup to retire, behind a
-// device-scope fence per workgroup, measured 2.5x slower on MI355X than the
-// separate level-2 launch below, so the two steps stay separate kernels.)
-template <int MODE, int GRAD, int KMAX>
-__global__ __launch_bounds__(kBlock) FN_DALITZ_WAVES_ATTR void dalitz_pass(DalitzConst dc, const DalitzTable* __restrict__ tab,
-                                                      const double* __restrict__ ev, int64_t ld, int64_t n,
-                                                      int chunk, int i0, double* __restrict__ part) {
-  constexpr int NV = dal_nv(MODE, GRAD, KMAX);
-  __shared__ double lds[kWaves * NV];
-  dalitz_chunk<MODE, GRAD, KMAX>(dc, tab, ev, ld, n, blockIdx.x, chunk, i0, part + (int64_t)blockIdx.x * NV,
-                                 lds);
-}
-
 // Level-2 step: one workgroup.
 __global__ __launch_bounds__(kBlock) void dalitz_finalize(DalitzConst dc, const DalitzTable* __restrict__ tab,
                                                           const double* __restrict__ evpart, int64_t ev_rows,
@@ -475,7 +233,7 @@ __global__ void dalitz_check(DalitzConst dc, const double* __restrict__ ev, int6
 }
 
 // ---------------------------------------------------------------- launchers
-int dalitz_kmax(int K) { return K <= 8 ? 8 : 16; }
+int dalitz_kmax(int K) { return K; }  // partial rows hold exactly the model's resonances
 int dalitz_nv_events(int kmax, int grad) { return dal_nv(kEvents, grad, kmax); }
 int dalitz_nv_mrows(int kmax) { return dal_nv(kMRows, 0, kmax); }
 
@@ -485,15 +243,64 @@ void dalitz_launch_prologue(const DalitzConst& dc, const ParamBlock& pb, const d
                      theta_stride, tab);
 }
 
-template <int MODE, int GRAD>
-static void launch_pass_k(const DalitzConst& dc, const DalitzTable* tab, const double* ev, int64_t ld, int64_t n,
-                          int chunk, int64_t nchunks, int i0, double* part, hipStream_t s) {
-  if (dalitz_kmax(dc.K) == 8)
-    hipLaunchKernelGGL((dalitz_pass<MODE, GRAD, 8>), dim3((unsigned)nchunks), dim3(kBlock), 0, s, dc, tab, ev, ld,
-                       n, chunk, i0, part);
-  else
-    hipLaunchKernelGGL((dalitz_pass<MODE, GRAD, 16>), dim3((unsigned)nchunks), dim3(kBlock), 0, s, dc, tab, ev,
-                       ld, n, chunk, i0, part);
+// Source of the structure-specialized passes of a model: the shape (K, pair
+// and spin of every resonance) as compile-time constants, then the kernels the
+// model uses (fixed lineshapes: events without and with the coefficient
+// gradient, the M rows; free lineshapes: events and grid without and with the
+// full gradient).
+std::string dalitz_jit_source(const DalitzConst& dc) {
+  std::ostringstream o;
+  o << "#include \"dalitz_device.hpp\"\n";
+  o << "struct fn_shape {\n  static constexpr int K = " << dc.K << ";\n  static constexpr int chan[" << dc.K
+    << "] = {";
+  for (int k = 0; k < dc.K; ++k) o << (k ? ", " : "") << dc.chan[k];
+  o << "};\n  static constexpr int L[" << dc.K << "] = {";
+  for (int k = 0; k < dc.K; ++k) o << (k ? ", " : "") << dc.L[k];
+  o << "};\n};\n";
+  if (!dc.free_ls) {
+    o << "FN_DALITZ_KERNEL(fn_dal_ev0, fn_shape, fn::kEvents, 0)\n"
+         "FN_DALITZ_KERNEL(fn_dal_ev1, fn_shape, fn::kEvents, 1)\n"
+         "FN_DALITZ_KERNEL(fn_dal_mrows, fn_shape, fn::kMRows, 0)\n";
+  } else {
+    o << "FN_DALITZ_KERNEL(fn_dal_ev0, fn_shape, fn::kEvents, 0)\n"
+         "FN_DALITZ_KERNEL(fn_dal_ev2, fn_shape, fn::kEvents, 2)\n"
+         "FN_DALITZ_KERNEL(fn_dal_gr0, fn_shape, fn::kGrid, 0)\n"
+         "FN_DALITZ_KERNEL(fn_dal_gr2, fn_shape, fn::kGrid, 2)\n";
+  }
+  return o.str();
+}
+
+std::shared_ptr<DalitzJit> dalitz_jit(const DalitzConst& dc) {
+  auto j = std::make_shared<DalitzJit>();
+  std::vector<std::string> names;
+  if (!dc.free_ls) names = {"fn_dal_ev0", "fn_dal_ev1", "fn_dal_mrows"};
+  else names = {"fn_dal_ev0", "fn_dal_ev2", "fn_dal_gr0", "fn_dal_gr2"};
+  j->prog = jit_load(dalitz_jit_source(dc), names);
+  const auto& f = j->prog->fns;
+  if (!dc.free_ls) {
+    j->ev[0] = f[0];
+    j->ev[1] = f[1];
+    j->mrows = f[2];
+  } else {
+    j->ev[0] = f[0];
+    j->ev[2] = f[1];
+    j->gr[0] = f[2];
+    j->gr[2] = f[3];
+  }
+  return j;
+}
+
+static void launch_pass(hipFunction_t f, const DalitzConst& dc, const DalitzTable* tab, const double* ev,
+                        int64_t ld, int64_t n, int chunk, int64_t nchunks, int i0, double* part, hipStream_t s) {
+  if (!f) throw Error(FN_E_INVALID, "this model was not compiled with the requested pass");
+  DalitzConst c = dc;
+  const DalitzTable* t = tab;
+  const double* e = ev;
+  int64_t l = ld, nn = n;
+  int ch = chunk, ii = i0;
+  double* p = part;
+  void* args[] = {&c, &t, &e, &l, &nn, &ch, &ii, &p};
+  jit_launch(f, (unsigned)nchunks, kBlock, s, args);
 }
 
 static DalFinal make_final(const double* npart, int64_t n_rows, int n_nv, const double* Mc, double n_events,
@@ -510,12 +317,10 @@ static DalFinal make_final(const double* npart, int64_t n_rows, int n_nv, const 
   return f;
 }
 
-void dalitz_launch_events(const DalitzConst& dc, const DalitzTable* tab, const double* ev, int64_t ld, int64_t n,
-                          int chunk, int64_t nchunks, int grad, double* part, hipStream_t s) {
+void dalitz_launch_events(const DalitzJit& j, const DalitzConst& dc, const DalitzTable* tab, const double* ev,
+                          int64_t ld, int64_t n, int chunk, int64_t nchunks, int grad, double* part, hipStream_t s) {
   if (nchunks == 0) return;
-  if (grad == 0) launch_pass_k<kEvents, 0>(dc, tab, ev, ld, n, chunk, nchunks, 0, part, s);
-  else if (grad == 1) launch_pass_k<kEvents, 1>(dc, tab, ev, ld, n, chunk, nchunks, 0, part, s);
-  else launch_pass_k<kEvents, 2>(dc, tab, ev, ld, n, chunk, nchunks, 0, part, s);
+  launch_pass(j.ev[grad], dc, tab, ev, ld, n, chunk, nchunks, 0, part, s);
 }
 
 void dalitz_launch_finalize(const DalitzConst& dc, const DalitzTable* tab, const double* evpart, int64_t ev_rows,
@@ -527,18 +332,16 @@ void dalitz_launch_finalize(const DalitzConst& dc, const DalitzTable* tab, const
                      dal_nv(kEvents, grad, kmax), kmax, fin);
 }
 
-void dalitz_launch_grid(const DalitzConst& dc, const DalitzTable* tab, int chunk, int64_t nchunks, int grad,
-                        double* part, hipStream_t s) {
+void dalitz_launch_grid(const DalitzJit& j, const DalitzConst& dc, const DalitzTable* tab, int chunk,
+                        int64_t nchunks, int grad, double* part, hipStream_t s) {
   const int64_t ncell = (int64_t)dc.nx * dc.ny;
-  if (grad == 0) launch_pass_k<kGrid, 0>(dc, tab, nullptr, 0, ncell, chunk, nchunks, 0, part, s);
-  else if (grad == 1) launch_pass_k<kGrid, 1>(dc, tab, nullptr, 0, ncell, chunk, nchunks, 0, part, s);
-  else launch_pass_k<kGrid, 2>(dc, tab, nullptr, 0, ncell, chunk, nchunks, 0, part, s);
+  launch_pass(j.gr[grad], dc, tab, nullptr, 0, ncell, chunk, nchunks, 0, part, s);
 }
 
-void dalitz_launch_mrows(const DalitzConst& dc, const DalitzTable* tab, int chunk, int64_t nchunks, int i0,
-                         double* part, double* Mc, hipStream_t s) {
+void dalitz_launch_mrows(const DalitzJit& j, const DalitzConst& dc, const DalitzTable* tab, int chunk,
+                         int64_t nchunks, int i0, double* part, double* Mc, hipStream_t s) {
   const int64_t ncell = (int64_t)dc.nx * dc.ny;
-  launch_pass_k<kMRows, 0>(dc, tab, nullptr, 0, ncell, chunk, nchunks, i0, part, s);
+  launch_pass(j.mrows, dc, tab, nullptr, 0, ncell, chunk, nchunks, i0, part, s);
   const int kmax = dalitz_kmax(dc.K);
   hipLaunchKernelGGL(dalitz_mrows_finalize, dim3(1), dim3(kBlock), 0, s, dc, part, nchunks,
                      dal_nv(kMRows, 0, kmax), kmax, i0, Mc);

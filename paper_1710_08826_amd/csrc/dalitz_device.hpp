@@ -1,0 +1,281 @@
+// Device code of the three-body Dalitz-plot model, compiled at run time for
+// each model structure (the resonances' pairs and spins become compile-time
+// constants; see jit.hpp) and, for the structure-generic helpers, into the
+// library.
+//
+//   P~(s12, s13) = |sum_k c_k A_k|^2,
+//   A_k = [F_L(q r)/F_L(q0 r)] F_L(p r_D) Z_L(s) T_k(s_AB)
+//   T_k = 1 / (m0^2 - s_AB - i m0 Gamma_k(s_AB))
+//   Gamma_k(s) = Gamma0 (q/q0)^(2L+1) (m0/sqrt s) [F_L(q r)/F_L(q0 r)]^2
+//
+// with Blatt-Weisskopf factors F_0 = 1, F_1 = (1+z)^-1/2,
+// F_2 = (z^2+3z+9)^-1/2 (z = (q r)^2) and Zemach spin factors Z_0 = 1,
+// Z_1 = s_AC - s_BC + (M^2 - mC^2)(mB^2 - mA^2)/s_AB, Z_2 = Z_1^2 - X Y / 3,
+// X = lambda(s_AB, M^2, mC^2)/s_AB, Y = lambda(s_AB, mA^2, mB^2)/s_AB.
+//
+// Per event, all in registers:
+//  * every quantity that depends only on the pair (s_AB, q, p, the barrier
+//    polynomials, Zemach factors) is computed once per pair and shared by all
+//    resonances of that pair;
+//  * per resonance the lineshape reduces to T = (a + i b)/(a^2 + b^2) with
+//    a = m0^2 - s and b = m0 Gamma(s) = Kw * G_{pair,L}(s), where
+//    G = q^(2L+1) F_L(q r)^2 / sqrt(s) is per pair and
+//    Kw = Gamma0 m0^2 / (q0^(2L+1) F_L(q0 r)^2) comes from the prologue;
+//  * the amplitude is A = Ka * H_{pair,L} * T with H = F_L(q r) F_L(p r_D) Z_L
+//    per pair and Ka = 1/F_L(q0 r) per resonance.
+//
+// Modes of the chunk routine:
+//   kEvents  -ln P~ over an event chunk (+ adjoint gradient)          -> NLL
+//   kGrid    P~ over a chunk of grid cells inside the region (+ dP~)  -> I
+//   kMRows   rows i0..i0+3 of sum_cells A_i conj(A_j)                 -> cached M
+#pragma once
+#include "device_common.hpp"
+#include "fastmath.hpp"
+#include "model.hpp"
+
+namespace fn {
+
+enum DalMode : int { kEvents = 0, kGrid = 1, kMRows = 2 };
+constexpr int kMRowBlock = 4;
+
+__host__ __device__ constexpr int dal_nv(int mode, int grad, int k) {
+  return mode == kMRows ? 2 * kMRowBlock * k : 1 + (grad == 0 ? 0 : (grad == 1 ? 2 * k : 4 * k));
+}
+
+struct PairTerms {
+  double s;         // s_AB
+  double G[3];      // q^(2L+1) F_L(q r)^2 / sqrt(s)
+  double H[3];      // F_L(q r) F_L(p r_D) Z_L
+};
+
+// G and H of one pair from (s_AB, s_AC, s_BC), for the spins U1 (L = 1) and
+// U2 (L = 2) the pair needs (L = 0 is always formed):
+//   q/sqrt(s) = sqrt(lambda_q) / (2 s),  q^2 = lambda_q / (4 s),  p^2 = lambda_p / (4 s)
+//   G_1 = (q/sqrt s) q^2 / (1 + z_q),          H_1 = Z_1 / sqrt((1 + z_q)(1 + z_p))
+//   G_2 = (q/sqrt s) q^4 / (z_q^2 + 3 z_q + 9), H_2 = Z_2 / sqrt(poly(z_q) poly(z_p))
+template <bool U1, bool U2>
+__device__ __forceinline__ void pair_terms_t(const DalitzChan& ch, double s_ab, double s_ac, double s_bc, double r2,
+                                             double rD2, PairTerms& o) {
+  const double irs = rsqrt_nr(s_ab);
+  const double is = irs * irs;
+  const double lq = fmax((s_ab - ch.sum2) * (s_ab - ch.dif2), 0.0);
+  const double q2 = 0.25 * lq * is;
+  const double qirs = 0.5 * sqrt_nr(lq) * is;
+  o.s = s_ab;
+  o.G[0] = qirs;
+  o.H[0] = 1.0;
+  o.G[1] = o.G[2] = o.H[1] = o.H[2] = 0.0;
+  if (U1 || U2) {
+    const double lp = fmax((s_ab - ch.Psum2) * (s_ab - ch.Pdif2), 0.0);
+    const double p2 = 0.25 * lp * is;
+    const double zq = q2 * r2, zp = p2 * rD2;
+    const double z1 = __builtin_fma(ch.zc, is, s_ac - s_bc);
+    if (U1) {
+      const double uq = 1.0 + zq, up = 1.0 + zp;
+      o.G[1] = qirs * q2 * rcp_nr(uq);
+      o.H[1] = z1 * rsqrt_nr(uq * up);
+    }
+    if (U2) {
+      const double vq = __builtin_fma(zq, zq + 3.0, 9.0), vp = __builtin_fma(zp, zp + 3.0, 9.0);
+      o.G[2] = qirs * q2 * q2 * rcp_nr(vq);
+      const double z2 = z1 * z1 - (lp * is) * (lq * is) * (1.0 / 3.0);
+      o.H[2] = z2 * rsqrt_nr(vq * vp);
+    }
+  }
+}
+
+// The same with the spins used by the pair given at run time.
+__device__ __forceinline__ void pair_terms(const DalitzChan& ch, double s_ab, double s_ac, double s_bc, double r2,
+                                           double rD2, PairTerms& o) {
+  if (ch.useL[2]) {
+    if (ch.useL[1]) pair_terms_t<true, true>(ch, s_ab, s_ac, s_bc, r2, rD2, o);
+    else pair_terms_t<false, true>(ch, s_ab, s_ac, s_bc, r2, rD2, o);
+  } else {
+    if (ch.useL[1]) pair_terms_t<true, false>(ch, s_ab, s_ac, s_bc, r2, rD2, o);
+    else pair_terms_t<false, false>(ch, s_ab, s_ac, s_bc, r2, rD2, o);
+  }
+}
+
+// Physical-region predicate at a grid-cell centre: s23 between its limits at
+// this s12, from the energies of daughters 2 and 3 in the (12) rest frame.
+// Contraction is off so that the decision is the plain IEEE evaluation.
+__device__ inline bool dalitz_inside(const DalitzConst& dc, double s12, double s13) {
+#pragma clang fp contract(off)
+  const double rs = sqrt(s12);
+  const double e2 = (s12 - dc.m1s + dc.m2s) / (2.0 * rs);
+  const double e3 = (dc.M2 - s12 - dc.m3s) / (2.0 * rs);
+  const double p2 = sqrt(fmax(e2 * e2 - dc.m2s, 0.0));
+  const double p3 = sqrt(fmax(e3 * e3 - dc.m3s, 0.0));
+  const double es = e2 + e3;
+  const double lo = es * es - (p2 + p3) * (p2 + p3);
+  const double hi = es * es - (p2 - p3) * (p2 - p3);
+  const double s23 = dc.msum - s12 - s13;
+  return s23 >= lo && s23 <= hi;
+}
+
+// Compile-time structure queries on a shape S (S::K, S::chan[], S::L[]).
+template <class S>
+__host__ __device__ constexpr bool shape_uses(int c, int l) {
+  bool u = false;
+  for (int k = 0; k < S::K; ++k) u = u || (S::chan[k] == c && S::L[k] == l);
+  return u;
+}
+
+// Amplitudes of the resonances of pair C (compile-time), added to the coherent sum.
+template <class S, int C, int MODE, bool KEEP_A, bool KEEP_T>
+__device__ __forceinline__ void dalitz_pair(const DalitzConst& dc, const double* __restrict__ r, double s12,
+                                            double s13, double s23, double (&Are)[S::K], double (&Aim)[S::K],
+                                            double (&Tre)[S::K], double (&Tim)[S::K], double (&Gk)[S::K],
+                                            double& Sre, double& Sim) {
+  constexpr bool any = shape_uses<S>(C, 0) || shape_uses<S>(C, 1) || shape_uses<S>(C, 2);
+  if (!any) return;
+  // pair "12": (A,B,C) = (1,2,3); "13": (1,3,2); "23": (2,3,1)
+  const double s_ab = C == 0 ? s12 : (C == 1 ? s13 : s23);
+  const double s_ac = C == 0 ? s13 : s12;
+  const double s_bc = C == 2 ? s13 : s23;
+  PairTerms pt;
+  pair_terms_t<shape_uses<S>(C, 1), shape_uses<S>(C, 2)>(dc.ch[C], s_ab, s_ac, s_bc, dc.r2, dc.rD2, pt);
+#pragma unroll
+  for (int k = 0; k < S::K; ++k) {
+    if (S::chan[k] == C) {
+      const int L = S::L[k];
+      const double* rk = r + k * kDalFields;
+      const double G = pt.G[L];
+      const double H = pt.H[L];
+      const double a = rk[dM0SQ] - pt.s;
+      const double b = rk[dKW] * G;
+      const double d = rcp_nr(__builtin_fma(a, a, b * b));
+      const double tr = a * d, ti = b * d;
+      const double kh = rk[dKA] * H;
+      const double ar = kh * tr, ai = kh * ti;
+      if (KEEP_A) { Are[k] = ar; Aim[k] = ai; }
+      if (KEEP_T) { Tre[k] = tr; Tim[k] = ti; Gk[k] = G; }
+      if (MODE != kMRows) {
+        const double cr = rk[dCRE], ci = rk[dCIM];
+        Sre += cr * ar - ci * ai;
+        Sim += cr * ai + ci * ar;
+      }
+    }
+  }
+}
+
+// One fixed chunk of events or grid cells -> one row of partial sums.
+// GRAD: 0 none, 1 coefficients only, 2 coefficients + masses and widths.
+template <class S, int MODE, int GRAD>
+__device__ inline void dalitz_chunk(const DalitzConst& dc, const DalitzTable* __restrict__ tab,
+                                    const double* __restrict__ ev, int64_t ld, int64_t n, int64_t chunk_idx,
+                                    int chunk, int i0, double* __restrict__ out_row, double* lds) {
+  constexpr int K = S::K;
+  constexpr int NV = dal_nv(MODE, GRAD, K);
+  constexpr bool KEEP_A = (GRAD >= 1) || MODE == kMRows;
+  constexpr bool KEEP_T = GRAD == 2;
+  double acc[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+  const int64_t base = chunk_idx * chunk;
+  const int64_t end = base + chunk < n ? base + chunk : n;
+  const double* const r0 = &tab->r[0][0];
+  for (int64_t i = base + threadIdx.x; i < end; i += kBlock) {
+    // The per-resonance constants are read through the scalar cache on every
+    // event: an empty asm makes a zero offset opaque to the loop so that the
+    // compiler does not keep the whole table resident in SGPRs, which
+    // overflows them into VGPR lanes (a v_readlane per use); the pointer keeps
+    // its provenance, so the reads stay scalar loads.
+    int zero = 0;
+    asm volatile("" : "+s"(zero));
+    const double* r = r0 + zero;
+    double s12, s13;
+    if (MODE == kEvents) {
+      s12 = ev[i];
+      s13 = ev[ld + i];
+    } else {
+      const int64_t ix = i / dc.ny;
+      const int64_t iy = i - ix * dc.ny;
+      s12 = dc.a12 + (ix + 0.5) * dc.d12;
+      s13 = dc.a13 + (iy + 0.5) * dc.d13;
+      if (!dalitz_inside(dc, s12, s13)) continue;
+    }
+    const double s23 = dc.msum - s12 - s13;
+    double Are[K], Aim[K], Tre[K], Tim[K], Gk[K];
+    double Sre = 0.0, Sim = 0.0;
+    dalitz_pair<S, 0, MODE, KEEP_A, KEEP_T>(dc, r, s12, s13, s23, Are, Aim, Tre, Tim, Gk, Sre, Sim);
+    dalitz_pair<S, 1, MODE, KEEP_A, KEEP_T>(dc, r, s12, s13, s23, Are, Aim, Tre, Tim, Gk, Sre, Sim);
+    dalitz_pair<S, 2, MODE, KEEP_A, KEEP_T>(dc, r, s12, s13, s23, Are, Aim, Tre, Tim, Gk, Sre, Sim);
+    if (MODE == kMRows) {
+#pragma unroll
+      for (int ib = 0; ib < kMRowBlock; ++ib) {
+        // A_i for i = i0 + ib, selected from registers with uniform guards
+        double xr = 0.0, xi = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+          if (k == i0 + ib) { xr = Are[k]; xi = Aim[k]; }
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          acc[2 * (ib * K + j)] += xr * Are[j] + xi * Aim[j];
+          acc[2 * (ib * K + j) + 1] += xi * Are[j] - xr * Aim[j];
+        }
+      }
+      continue;
+    }
+    const double Pt = __builtin_fma(Sre, Sre, Sim * Sim);
+    double w;  // multiplies dP~/dtheta
+    if (MODE == kEvents) {
+      acc[0] -= log_fast(Pt);
+      w = -rcp_nr(Pt);
+    } else {
+      acc[0] += Pt;
+      w = 1.0;
+    }
+    if (GRAD >= 1) {
+      const double w2 = 2.0 * w;
+      const double ur = w2 * Sre, ui = w2 * Sim;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        // dP~/dRe c = 2 Re(conj(S) A), dP~/dIm c = 2 (Sim Are - Sre Aim)
+        acc[1 + 2 * k] += ur * Are[k] + ui * Aim[k];
+        acc[2 + 2 * k] += ui * Are[k] - ur * Aim[k];
+      }
+    }
+    if (GRAD == 2) {
+      const double w2 = 2.0 * w;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const double* rk = r + k * kDalFields;
+        const double cr = rk[dCRE], ci = rk[dCIM];
+        // E = conj(S) c A
+        const double car = cr * Are[k] - ci * Aim[k], cai = cr * Aim[k] + ci * Are[k];
+        const double er = Sre * car + Sim * cai, ei = Sre * cai - Sim * car;
+        // dA/dm0 = A (dlnKa - T (2 m0 - i G dKw/dm0));  dP~ = 2 Re(E * (...))
+        const double gd = Gk[k] * rk[dDKW_DM0], tm = rk[dTWOM0];
+        const double xr = tm * Tre[k] + Tim[k] * gd;
+        const double xi = tm * Tim[k] - Tre[k] * gd;
+        const double yr = rk[dDLNKA] - xr, yi = -xi;
+        acc[1 + 2 * K + 2 * k] += w2 * (er * yr - ei * yi);
+        // dA/dGamma0 = i A T G Kw/Gamma0
+        const double gw = Gk[k] * rk[dKW_W0];
+        acc[2 + 2 * K + 2 * k] += w2 * gw * (-er * Tim[k] - ei * Tre[k]);
+      }
+    }
+  }
+  block_sum_row<NV>(acc, lds, out_row);
+}
+
+// One workgroup per chunk, one row of NV partial sums each.
+template <class S, int MODE, int GRAD>
+__device__ inline void dalitz_pass_body(const DalitzConst& dc, const DalitzTable* __restrict__ tab,
+                                        const double* __restrict__ ev, int64_t ld, int64_t n, int chunk, int i0,
+                                        double* __restrict__ part) {
+  constexpr int NV = dal_nv(MODE, GRAD, S::K);
+  __shared__ double lds[kWaves * NV];
+  dalitz_chunk<S, MODE, GRAD>(dc, tab, ev, ld, n, blockIdx.x, chunk, i0, part + (int64_t)blockIdx.x * NV, lds);
+}
+
+}  // namespace fn
+
+// Kernel NAME for shape S, mode and gradient level (used by the generated source).
+#define FN_DALITZ_KERNEL(NAME, S, MODE, GRAD)                                                              \
+  extern "C" __global__ __launch_bounds__(fn::kBlock) void NAME(                                             \
+      fn::DalitzConst dc, const fn::DalitzTable* __restrict__ tab, const double* __restrict__ ev, int64_t ld, \
+      int64_t n, int chunk, int i0, double* __restrict__ part) {                                             \
+    fn::dalitz_pass_body<S, MODE, GRAD>(dc, tab, ev, ld, n, chunk, i0, part);                                \
+  }

@@ -13,7 +13,9 @@
 // below 3e-17 relative.  ln 2 is split into a 32-bit head and a tail so that
 // e ln 2 is formed without rounding error in the head.
 #pragma once
+#if !defined(__HIPCC_RTC__)
 #include <hip/hip_runtime.h>
+#endif
 
 namespace fn {
 

@@ -1,5 +1,8 @@
 // Host-side launchers of the device kernels (defined next to the kernels).
 #pragma once
+#include <memory>
+#include <string>
+
 #include "model.hpp"
 
 namespace fn {
@@ -28,23 +31,33 @@ void mix1d_launch_eval(const Mix1dConst& mc, const Mix1dTable* tab, const double
 void mix1d_launch_check(const Mix1dConst& mc, const double* x, int64_t n, unsigned long long* bad, hipStream_t s);
 
 // dalitz3
+// Structure-specialized passes of one model (compiled at model creation).
+struct JitProgram;
+struct DalitzJit {
+  std::shared_ptr<JitProgram> prog;
+  hipFunction_t ev[3] = {nullptr, nullptr, nullptr};  // by gradient level
+  hipFunction_t gr[3] = {nullptr, nullptr, nullptr};
+  hipFunction_t mrows = nullptr;
+};
+std::string dalitz_jit_source(const DalitzConst& dc);
+std::shared_ptr<DalitzJit> dalitz_jit(const DalitzConst& dc);
 int dalitz_kmax(int K);
 int dalitz_nv_events(int kmax, int grad);
 int dalitz_nv_mrows(int kmax);
 void dalitz_launch_prologue(const DalitzConst& dc, const ParamBlock& pb, const double* theta_dev,
                             const double* fixed_ls, int n_fits, int theta_stride, DalitzTable* tab, hipStream_t s);
 // Events pass: one row of partial sums per chunk of events.
-void dalitz_launch_events(const DalitzConst& dc, const DalitzTable* tab, const double* ev, int64_t ld, int64_t n,
-                          int chunk, int64_t nchunks, int grad, double* part, hipStream_t s);
+void dalitz_launch_events(const DalitzJit& j, const DalitzConst& dc, const DalitzTable* tab, const double* ev,
+                          int64_t ld, int64_t n, int chunk, int64_t nchunks, int grad, double* part, hipStream_t s);
 // Level-2 sum of the event rows and of the normalization (grid rows, or the
 // cached M when npart is null), NLL assembly: out = [NLL, grad, I, dI].
 void dalitz_launch_finalize(const DalitzConst& dc, const DalitzTable* tab, const double* evpart, int64_t ev_rows,
                             int grad, const double* npart, int64_t n_rows, int n_nv, const double* Mc,
                             double n_events, double* out, double* out_user, hipStream_t s);
-void dalitz_launch_grid(const DalitzConst& dc, const DalitzTable* tab, int chunk, int64_t nchunks, int grad,
-                        double* part, hipStream_t s);
-void dalitz_launch_mrows(const DalitzConst& dc, const DalitzTable* tab, int chunk, int64_t nchunks, int i0,
-                         double* part, double* Mc, hipStream_t s);
+void dalitz_launch_grid(const DalitzJit& j, const DalitzConst& dc, const DalitzTable* tab, int chunk,
+                        int64_t nchunks, int grad, double* part, hipStream_t s);
+void dalitz_launch_mrows(const DalitzJit& j, const DalitzConst& dc, const DalitzTable* tab, int chunk,
+                         int64_t nchunks, int i0, double* part, double* Mc, hipStream_t s);
 void dalitz_launch_eval(const DalitzConst& dc, const DalitzTable* tab, const double* ev, int64_t ld, int64_t n,
                         const double* norm, double* p, hipStream_t s);
 void dalitz_launch_check(const DalitzConst& dc, const double* ev, int64_t ld, int64_t n, unsigned long long* bad,

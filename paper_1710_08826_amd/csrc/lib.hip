@@ -12,6 +12,7 @@
 
 #include "../../include/fitnll.h"
 #include "internal.hpp"
+#include "jit.hpp"
 #include "json.hpp"
 #include "kernels.hpp"
 
@@ -116,7 +117,7 @@ static void compile_mix1d(const json::Value& d, fn_model* m) {
   m->d_table.reserve(sizeof(Mix1dTable));
 }
 
-static void compile_dalitz3(const json::Value& d, fn_model* m) {
+static void compile_dalitz3(const json::Value& d, fn_model* m, bool device = true) {
   DalitzConst& dc = m->dal;
   std::memset(&dc, 0, sizeof(dc));
   const double M = d.at("M").number();
@@ -185,10 +186,13 @@ static void compile_dalitz3(const json::Value& d, fn_model* m) {
   }
   m->P = dc.free_ls ? 4 * dc.K : 2 * dc.K;
   m->n_obs = 2;
-  // measured on MI355X: 1024 events per workgroup is fastest for the coefficient
-  // gradient (17 sums per row); 4096 amortises the 33-sum rows of free lineshapes
-  m->chunk = dc.free_ls ? 4096 : 1024;
+  // measured on MI355X with the structure-specialized kernels: 2048 events per
+  // workgroup is fastest for the coefficient gradient (17 sums per row) at 1M
+  // events, 4096 amortises the 33-sum rows of free lineshapes
+  m->chunk = dc.free_ls ? 4096 : 2048;
   m->grid_chunk = 1024;
+  if (!device) return;
+  m->dal_jit = dalitz_jit(dc);
   m->d_table.reserve(sizeof(DalitzTable));
   m->d_fixed.reserve(sizeof(double) * 2 * dc.K);
   hip_check(hipMemcpy(m->d_fixed.ptr, m->fixed_ls.data(), sizeof(double) * 2 * dc.K, hipMemcpyHostToDevice),
@@ -359,7 +363,7 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
       nrows = nchunks_for(ncell, m->grid_chunk);
       nnv = dalitz_nv_events(kmax, g);
       m->d_npart.reserve(sizeof(double) * (size_t)nrows * nnv);
-      dalitz_launch_grid(dc, m->table_dal(), m->grid_chunk, nrows, g, m->npart(), s);
+      dalitz_launch_grid(*m->dal_jit, dc, m->table_dal(), m->grid_chunk, nrows, g, m->npart(), s);
       npart = m->npart();
     } else if (!m->M_valid) {
       // fixed lineshapes: reduce the grid once to M_ij = dA sum A_i conj(A_j)
@@ -367,7 +371,7 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
       const int64_t mrows = nchunks_for(ncell, m->grid_chunk);
       m->d_npart.reserve(sizeof(double) * (size_t)mrows * dalitz_nv_mrows(kmax));
       for (int i0 = 0; i0 < dc.K; i0 += 4)
-        dalitz_launch_mrows(dc, m->table_dal(), m->grid_chunk, mrows, i0, m->npart(), m->Mc(), s);
+        dalitz_launch_mrows(*m->dal_jit, dc, m->table_dal(), m->grid_chunk, mrows, i0, m->npart(), m->Mc(), s);
       m->M_valid = true;
     }
     hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -376,7 +380,7 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
       t1 = m->take_event();
       hip_check(hipEventRecord(t0, s), "hipEventRecord");
     }
-    dalitz_launch_events(dc, m->table_dal(), ev, ld, n, m->chunk, nch, g, m->part(), s);
+    dalitz_launch_events(*m->dal_jit, dc, m->table_dal(), ev, ld, n, m->chunk, nch, g, m->part(), s);
     if (t0) {
       hip_check(hipEventRecord(t1, s), "hipEventRecord");
       m->ev_pending.emplace_back(t0, t1);
@@ -504,6 +508,33 @@ fn_status fn_model_create(fn_ctx* ctx, const char* desc_json, fn_model** out) {
     delete m;
   }
   return st;
+}
+
+fn_status fn_model_check_compile(const char* desc_json, const char* arch) {
+  return guard([&] {
+    if (!desc_json) throw Error(FN_E_INVALID, "NULL argument");
+    json::Value d;
+    try {
+      d = json::parse(desc_json);
+    } catch (const std::exception& e) {
+      throw Error(FN_E_INVALID, e.what());
+    }
+    const std::string target = arch && *arch ? arch : "gfx950";
+    fn_model tmp;
+    try {
+      const std::string& kind = d.at("kind").string();
+      if (kind == "dalitz3") {
+        compile_dalitz3(d, &tmp, false);
+        (void)jit_compile(dalitz_jit_source(tmp.dal), target);
+      } else if (kind != "mix1d" && kind != "td4") {
+        throw Error(FN_E_INVALID, "unknown model kind \"" + kind + "\"");
+      }
+    } catch (const Error&) {
+      throw;
+    } catch (const std::exception& e) {
+      throw Error(FN_E_INVALID, std::string("model description: ") + e.what());
+    }
+  });
 }
 
 fn_status fn_model_info(const fn_model* m, int32_t* n_params, int32_t* n_obs, int32_t* chunk) {

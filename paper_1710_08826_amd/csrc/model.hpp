@@ -3,8 +3,14 @@
 // parameter-derived tables (device memory, written by the prologue kernels),
 // and launch constants.
 #pragma once
+#if !defined(__HIPCC_RTC__)
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#else  // runtime compilation: the HIP device environment is built in, fixed-width integers live here
+using __hip_internal::int64_t;
+using __hip_internal::uint32_t;
+using __hip_internal::uint64_t;
+#endif
 
 namespace fn {
 

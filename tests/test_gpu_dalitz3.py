@@ -49,7 +49,7 @@ def test_norm_matches_oracle_grid(m1, m3, cells1):
     assert rel_close(I3, OD.norm_value(OD.Dalitz(D3), th3, cells1), 1e-12)
 
 
-@pytest.mark.parametrize("n", [1, 1000, 3 * 1024 + 17, 100_000])
+@pytest.mark.parametrize("n", [1, 1000, 3 * 2048 + 17, 100_000])
 def test_config1_nll_and_coefficient_gradient(m1, cells1, n):
     say("dalitz config1 n =", n)
     ev = synth.dalitz_events(n, seed=31)
@@ -63,7 +63,7 @@ def test_config1_nll_and_coefficient_gradient(m1, cells1, n):
         assert rel_close(m1.nll(th, evd), v, 1e-14)  # NLL-only kernel agrees
 
 
-@pytest.mark.parametrize("n", [1, 5000, 2 * 1024 + 5])
+@pytest.mark.parametrize("n", [1, 5000, 2 * 4096 + 5])
 def test_config3_nll_and_full_gradient(m3, cells1, n):
     say("dalitz config3 n =", n)
     ev = synth.dalitz_events(n, seed=32)

@@ -82,3 +82,23 @@ def test_struct_layouts_match_header(tmp_path):
     want = [C.sizeof(api._Request), C.sizeof(api._Result), api._Request.arrival_s.offset,
             api._Result.t_done.offset, api._Result.theta.offset]
     assert got == want
+
+
+def test_model_kernels_compile_for_gfx950_without_a_device():
+    """The structure-specialized kernels of amplitude models are compiled at
+    run time; the same compilation runs here on the CPU for gfx950."""
+    import json
+    import synth
+    from paper_1710_08826_amd import _lib
+    lib = _lib.load()
+    for free in (False, True):
+        d = synth.dalitz_desc(free_lineshapes=free)
+        assert lib.fn_model_check_compile(json.dumps(d).encode(), b"gfx950") == _lib.FN_OK, lib.fn_last_error()
+    # a two-resonance model in one pair with spins 0 and 2 only
+    d = synth.dalitz_desc()
+    d["resonances"] = [{"pair": "13", "L": 0, "m0": 1.43, "w0": 0.27}, {"pair": "13", "L": 2, "m0": 1.43, "w0": 0.1}]
+    assert lib.fn_model_check_compile(json.dumps(d).encode(), None) == _lib.FN_OK, lib.fn_last_error()
+    bad = synth.dalitz_desc()
+    bad["resonances"][0]["pair"] = "14"
+    assert lib.fn_model_check_compile(json.dumps(bad).encode(), None) == _lib.FN_E_INVALID
+    assert lib.fn_model_check_compile(b"{not json", None) == _lib.FN_E_INVALID
