@@ -145,7 +145,7 @@ __global__ __launch_bounds__(kBlock) void batch_eval(Mix1dConst mc, const Mix1dT
                                                      const int64_t* __restrict__ part_base, int n_fits, int chunk,
                                                      double* __restrict__ part) {
   constexpr int NV = GRAD ? mix_nv(KMAX) : 1;
-  __shared__ double lds[kWaves * NV];
+  __shared__ double lds[block_sum_lds(NV)];
   const int64_t total = item_base[n_fits];
   for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
     // fit f with item_base[f] <= it < item_base[f+1] (non-running fits have

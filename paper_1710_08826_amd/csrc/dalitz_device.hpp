@@ -266,7 +266,7 @@ __device__ inline void dalitz_pass_body(const DalitzConst& dc, const DalitzTable
                                         const double* __restrict__ ev, int64_t ld, int64_t n, int chunk, int i0,
                                         double* __restrict__ part) {
   constexpr int NV = dal_nv(MODE, GRAD, S::K);
-  __shared__ double lds[kWaves * NV];
+  __shared__ double lds[block_sum_lds(NV)];
   dalitz_chunk<S, MODE, GRAD>(dc, tab, ev, ld, n, blockIdx.x, chunk, i0, part + (int64_t)blockIdx.x * NV, lds);
 }
 

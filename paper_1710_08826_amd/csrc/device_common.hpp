@@ -1,9 +1,12 @@
 // Device helpers: the deterministic two-level FP64 reduction.
 //
 // Level 1 (inside an evaluation kernel): every workgroup owns one fixed chunk
-// of events.  Each thread sums its events in index order, the 64 lanes of a
-// wave combine with a fixed xor butterfly, and the 4 waves combine through
-// LDS in wave order.  The workgroup writes one row of NV doubles.
+// of events.  Each thread sums its events in index order; every quad of lanes
+// combines with two DPP exchanges (lane ^ 1, then lane ^ 2: register moves, no
+// LDS traffic); one lane per quad stores its sums to LDS; four threads per
+// value then add the workgroup's 64 quad sums, each taking every fourth quad
+// in index order, and a last quad exchange combines the four.  The workgroup
+// writes one row of NV doubles.
 // Level 2 (a single workgroup): rows are summed in a fixed interleaving that
 // depends only on the number of rows and NV.
 // Nothing depends on scheduling, so results are bitwise reproducible, and a
@@ -13,28 +16,40 @@
 
 namespace fn {
 
+constexpr int kQuads = kBlock / 4;  // quad sums per workgroup
+
+// LDS doubles block_sum_row needs for NV values.
+__host__ __device__ constexpr int block_sum_lds(int nv) { return kQuads * nv; }
+
+// Sum over the four lanes of a quad, the same value in all four (fixed order:
+// (a + b) + (c + d) pairs by lane ^ 1 first, then lane ^ 2).
+__device__ __forceinline__ double quad_sum(double x) {
+  x += __builtin_amdgcn_update_dpp(0.0, x, 0xB1, 0xF, 0xF, true);  // quad_perm [1,0,3,2]
+  x += __builtin_amdgcn_update_dpp(0.0, x, 0x4E, 0xF, 0xF, true);  // quad_perm [2,3,0,1]
+  return x;
+}
+
 template <int NV>
-__device__ inline void block_sum_row(double (&v)[NV], double* lds /* kWaves*NV */,
+__device__ inline void block_sum_row(double (&v)[NV], double* lds /* block_sum_lds(NV) */,
                                      double* __restrict__ out_row) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int t = threadIdx.x;
 #pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    double x = v[i];
+  for (int i = 0; i < NV; ++i) v[i] = quad_sum(v[i]);
+  if ((t & 3) == 0) {
+    const int q = t >> 2;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    v[i] = x;
-  }
-  if (lane == 0) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) lds[wave * NV + i] = v[i];
+    for (int i = 0; i < NV; ++i) lds[q * NV + i] = v[i];
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < NV; i += kBlock) {
-    double s = lds[i];
+  // thread (i, p) = (u >> 2, u & 3) adds quads p, p + 4, ..., p + 60 of value i;
+  // the four threads of a value form one quad, so a quad sum combines them
+  for (int u = t; u < 4 * NV; u += kBlock) {
+    const int i = u >> 2, p = u & 3;
+    double s = 0.0;
 #pragma unroll
-    for (int w = 1; w < kWaves; ++w) s += lds[w * NV + i];
-    out_row[i] = s;
+    for (int j = 0; j < kQuads / 4; ++j) s += lds[(p + 4 * j) * NV + i];
+    s = quad_sum(s);
+    if (p == 0) out_row[i] = s;
   }
 }
 

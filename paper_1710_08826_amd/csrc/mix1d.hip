@@ -36,7 +36,7 @@ __global__ __launch_bounds__(kBlock) void mix1d_events(Mix1dConst mc, const Mix1
                                                        const double* __restrict__ x, int64_t n, int chunk,
                                                        double* __restrict__ part) {
   constexpr int NV = GRAD ? mix_nv(KMAX) : 1;
-  __shared__ double lds[kWaves * NV];
+  __shared__ double lds[block_sum_lds(NV)];
   mix1d_chunk<GRAD, KMAX>(mc, tab, x, n, blockIdx.x, chunk, part + (int64_t)blockIdx.x * NV, lds);
 }
 
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(kBlock) void mix1d_events_batched(
     const int64_t* __restrict__ item_chunk, const int64_t* __restrict__ part_base, int chunk,
     double* __restrict__ part) {
   constexpr int NV = GRAD ? mix_nv(KMAX) : 1;
-  __shared__ double lds[kWaves * NV];
+  __shared__ double lds[block_sum_lds(NV)];
   const int fit = item_fit[blockIdx.x];
   const int64_t ch = item_chunk[blockIdx.x];
   mix1d_chunk<GRAD, KMAX>(mc, tabs + fit, ev[fit], n[fit], ch, chunk, part + (part_base[fit] + ch) * NV, lds);

@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void td4_events(Td4Const tc, const Td4Table
                                                      int64_t ld, int64_t n, int chunk, int64_t nch, int n_fits,
                                                      double* __restrict__ part) {
   constexpr int NV = GRAD ? 3 + 4 * KMAX : 1;
-  __shared__ double lds[kWaves * NV];
+  __shared__ double lds[block_sum_lds(NV)];
   // fits vary fastest: the workgroups of one event chunk run together and share it through L2
   const int64_t ch = blockIdx.x / n_fits;
   const int f = (int)(blockIdx.x - ch * n_fits);
@@ -288,7 +288,7 @@ __global__ __launch_bounds__(kBlock) void td4_mrows(Td4Const tc, const Td4Table*
                                                     const double* __restrict__ mc, int64_t ld, int64_t n, int chunk,
                                                     int64_t nch, int n_fits, int i0, double* __restrict__ part) {
   constexpr int NV = 2 * kTd4RowBlock * KMAX;
-  __shared__ double lds[kWaves * NV];
+  __shared__ double lds[block_sum_lds(NV)];
   const int64_t ch = blockIdx.x / n_fits;
   const int f = (int)(blockIdx.x - ch * n_fits);
   const Td4Table& tb = tabs[f];
