@@ -54,6 +54,8 @@ __global__ void dalitz_prologue(DalitzConst dc, ParamBlock pb, const double* __r
     r[dKA] = ka;
     r[dCRE] = th[2 * k];
     r[dCIM] = th[2 * k + 1];
+    tab[f].coef[2 * k] = th[2 * k];
+    tab[f].coef[2 * k + 1] = th[2 * k + 1];
     r[dDLNKA] = dlnka;
     r[dDKW_DM0] = kw * dlnkw;
     r[dKW_W0] = x * poly / q0pow;
@@ -71,6 +73,7 @@ struct DalFinal {
   int64_t n_rows;
   int n_nv;
   const double* Mc;          // cached M (K x K complex) when npart == nullptr
+  const double* coef;        // (Re c_k, Im c_k)
   double n_events;
   int with_grad;
   double* out;               // [NLL, grad(P), I, dI(P)]
@@ -78,7 +81,7 @@ struct DalFinal {
 };
 
 struct DalFinalLds {
-  double scratch[kBlock];
+  double scratch[kFinalBlock];
   double res[kBlock];
   double nres[kBlock];
   double cre[kDalMaxRes], cim[kDalMaxRes], ipart[kDalMaxRes];
@@ -94,11 +97,11 @@ __device__ void dalitz_finalize_body(const DalitzConst& dc, const DalitzTable* _
   const int K = dc.K;
   const int P = dc.free_ls ? 4 * K : 2 * K;
   const int t = threadIdx.x;
-  sum_rows(evpart, ev_rows, ev_nv, L.scratch, L.res);
-  if (f.npart) sum_rows(f.npart, f.n_rows, f.n_nv, L.scratch, L.nres);
+  sum_rows_t<kFinalBlock>(evpart, ev_rows, ev_nv, L.scratch, L.res);
+  if (f.npart) sum_rows_t<kFinalBlock>(f.npart, f.n_rows, f.n_nv, L.scratch, L.nres);
   if (t < K) {
-    L.cre[t] = tab->r[t][dCRE];
-    L.cim[t] = tab->r[t][dCIM];
+    L.cre[t] = f.coef[2 * t];
+    L.cim[t] = f.coef[2 * t + 1];
   }
   if (t < P) L.dI[t] = 0.0;
   __syncthreads();
@@ -154,7 +157,7 @@ __device__ void dalitz_finalize_body(const DalitzConst& dc, const DalitzTable* _
 }
 
 // Level-2 step: one workgroup.
-__global__ __launch_bounds__(kBlock) void dalitz_finalize(DalitzConst dc, const DalitzTable* __restrict__ tab,
+__global__ __launch_bounds__(kFinalBlock) void dalitz_finalize(DalitzConst dc, const DalitzTable* __restrict__ tab,
                                                           const double* __restrict__ evpart, int64_t ev_rows,
                                                           int ev_nv, int kmax, DalFinal fin) {
   __shared__ DalFinalLds L;
@@ -290,26 +293,29 @@ std::shared_ptr<DalitzJit> dalitz_jit(const DalitzConst& dc) {
   return j;
 }
 
-static void launch_pass(hipFunction_t f, const DalitzConst& dc, const DalitzTable* tab, const double* ev,
-                        int64_t ld, int64_t n, int chunk, int64_t nchunks, int i0, double* part, hipStream_t s) {
+static void launch_pass(hipFunction_t f, const DalitzConst& dc, const DalitzTable* tab, const double* coef,
+                        const double* ev, int64_t ld, int64_t n, int chunk, int64_t nchunks, int i0, double* part,
+                        hipStream_t s) {
   if (!f) throw Error(FN_E_INVALID, "this model was not compiled with the requested pass");
   DalitzConst c = dc;
   const DalitzTable* t = tab;
+  const double* cf = coef;
   const double* e = ev;
   int64_t l = ld, nn = n;
   int ch = chunk, ii = i0;
   double* p = part;
-  void* args[] = {&c, &t, &e, &l, &nn, &ch, &ii, &p};
+  void* args[] = {&c, &t, &cf, &e, &l, &nn, &ch, &ii, &p};
   jit_launch(f, (unsigned)nchunks, kBlock, s, args);
 }
 
-static DalFinal make_final(const double* npart, int64_t n_rows, int n_nv, const double* Mc, double n_events,
-                           bool grad, double* out, double* out_user) {
+static DalFinal make_final(const double* npart, int64_t n_rows, int n_nv, const double* Mc, const double* coef,
+                           double n_events, bool grad, double* out, double* out_user) {
   DalFinal f;
   f.npart = npart;
   f.n_rows = n_rows;
   f.n_nv = n_nv;
   f.Mc = Mc;
+  f.coef = coef;
   f.n_events = n_events;
   f.with_grad = grad ? 1 : 0;
   f.out = out;
@@ -317,31 +323,32 @@ static DalFinal make_final(const double* npart, int64_t n_rows, int n_nv, const 
   return f;
 }
 
-void dalitz_launch_events(const DalitzJit& j, const DalitzConst& dc, const DalitzTable* tab, const double* ev,
-                          int64_t ld, int64_t n, int chunk, int64_t nchunks, int grad, double* part, hipStream_t s) {
+void dalitz_launch_events(const DalitzJit& j, const DalitzConst& dc, const DalitzTable* tab, const double* coef,
+                          const double* ev, int64_t ld, int64_t n, int chunk, int64_t nchunks, int grad, double* part,
+                          hipStream_t s) {
   if (nchunks == 0) return;
-  launch_pass(j.ev[grad], dc, tab, ev, ld, n, chunk, nchunks, 0, part, s);
+  launch_pass(j.ev[grad], dc, tab, coef, ev, ld, n, chunk, nchunks, 0, part, s);
 }
 
-void dalitz_launch_finalize(const DalitzConst& dc, const DalitzTable* tab, const double* evpart, int64_t ev_rows,
-                            int grad, const double* npart, int64_t n_rows, int n_nv, const double* Mc,
-                            double n_events, double* out, double* out_user, hipStream_t s) {
+void dalitz_launch_finalize(const DalitzConst& dc, const DalitzTable* tab, const double* coef, const double* evpart,
+                            int64_t ev_rows, int grad, const double* npart, int64_t n_rows, int n_nv,
+                            const double* Mc, double n_events, double* out, double* out_user, hipStream_t s) {
   const int kmax = dalitz_kmax(dc.K);
-  const DalFinal fin = make_final(npart, n_rows, n_nv, Mc, n_events, grad != 0, out, out_user);
-  hipLaunchKernelGGL(dalitz_finalize, dim3(1), dim3(kBlock), 0, s, dc, tab, evpart, ev_rows,
+  const DalFinal fin = make_final(npart, n_rows, n_nv, Mc, coef, n_events, grad != 0, out, out_user);
+  hipLaunchKernelGGL(dalitz_finalize, dim3(1), dim3(kFinalBlock), 0, s, dc, tab, evpart, ev_rows,
                      dal_nv(kEvents, grad, kmax), kmax, fin);
 }
 
-void dalitz_launch_grid(const DalitzJit& j, const DalitzConst& dc, const DalitzTable* tab, int chunk,
-                        int64_t nchunks, int grad, double* part, hipStream_t s) {
+void dalitz_launch_grid(const DalitzJit& j, const DalitzConst& dc, const DalitzTable* tab, const double* coef,
+                        int chunk, int64_t nchunks, int grad, double* part, hipStream_t s) {
   const int64_t ncell = (int64_t)dc.nx * dc.ny;
-  launch_pass(j.gr[grad], dc, tab, nullptr, 0, ncell, chunk, nchunks, 0, part, s);
+  launch_pass(j.gr[grad], dc, tab, coef, nullptr, 0, ncell, chunk, nchunks, 0, part, s);
 }
 
 void dalitz_launch_mrows(const DalitzJit& j, const DalitzConst& dc, const DalitzTable* tab, int chunk,
                          int64_t nchunks, int i0, double* part, double* Mc, hipStream_t s) {
   const int64_t ncell = (int64_t)dc.nx * dc.ny;
-  launch_pass(j.mrows, dc, tab, nullptr, 0, ncell, chunk, nchunks, i0, part, s);
+  launch_pass(j.mrows, dc, tab, nullptr, nullptr, 0, ncell, chunk, nchunks, i0, part, s);
   const int kmax = dalitz_kmax(dc.K);
   hipLaunchKernelGGL(dalitz_mrows_finalize, dim3(1), dim3(kBlock), 0, s, dc, part, nchunks,
                      dal_nv(kMRows, 0, kmax), kmax, i0, Mc);

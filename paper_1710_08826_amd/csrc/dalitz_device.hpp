@@ -123,7 +123,8 @@ __host__ __device__ constexpr bool shape_uses(int c, int l) {
 
 // Amplitudes of the resonances of pair C (compile-time), added to the coherent sum.
 template <class S, int C, int MODE, bool KEEP_A, bool KEEP_T>
-__device__ __forceinline__ void dalitz_pair(const DalitzConst& dc, const double* __restrict__ r, double s12,
+__device__ __forceinline__ void dalitz_pair(const DalitzConst& dc, const double* __restrict__ r,
+                                            const double* __restrict__ coef, double s12,
                                             double s13, double s23, double (&Are)[S::K], double (&Aim)[S::K],
                                             double (&Tre)[S::K], double (&Tim)[S::K], double (&Gk)[S::K],
                                             double& Sre, double& Sim) {
@@ -151,7 +152,7 @@ __device__ __forceinline__ void dalitz_pair(const DalitzConst& dc, const double*
       if (KEEP_A) { Are[k] = ar; Aim[k] = ai; }
       if (KEEP_T) { Tre[k] = tr; Tim[k] = ti; Gk[k] = G; }
       if (MODE != kMRows) {
-        const double cr = rk[dCRE], ci = rk[dCIM];
+        const double cr = coef[2 * k], ci = coef[2 * k + 1];
         Sre += cr * ar - ci * ai;
         Sim += cr * ai + ci * ar;
       }
@@ -163,7 +164,8 @@ __device__ __forceinline__ void dalitz_pair(const DalitzConst& dc, const double*
 // GRAD: 0 none, 1 coefficients only, 2 coefficients + masses and widths.
 template <class S, int MODE, int GRAD>
 __device__ inline void dalitz_chunk(const DalitzConst& dc, const DalitzTable* __restrict__ tab,
-                                    const double* __restrict__ ev, int64_t ld, int64_t n, int64_t chunk_idx,
+                                    const double* __restrict__ coef0, const double* __restrict__ ev, int64_t ld,
+                                    int64_t n, int64_t chunk_idx,
                                     int chunk, int i0, double* __restrict__ out_row, double* lds) {
   constexpr int K = S::K;
   constexpr int NV = dal_nv(MODE, GRAD, K);
@@ -184,6 +186,7 @@ __device__ inline void dalitz_chunk(const DalitzConst& dc, const DalitzTable* __
     int zero = 0;
     asm volatile("" : "+s"(zero));
     const double* r = r0 + zero;
+    const double* coef = coef0 + zero;
     double s12, s13;
     if (MODE == kEvents) {
       s12 = ev[i];
@@ -198,9 +201,9 @@ __device__ inline void dalitz_chunk(const DalitzConst& dc, const DalitzTable* __
     const double s23 = dc.msum - s12 - s13;
     double Are[K], Aim[K], Tre[K], Tim[K], Gk[K];
     double Sre = 0.0, Sim = 0.0;
-    dalitz_pair<S, 0, MODE, KEEP_A, KEEP_T>(dc, r, s12, s13, s23, Are, Aim, Tre, Tim, Gk, Sre, Sim);
-    dalitz_pair<S, 1, MODE, KEEP_A, KEEP_T>(dc, r, s12, s13, s23, Are, Aim, Tre, Tim, Gk, Sre, Sim);
-    dalitz_pair<S, 2, MODE, KEEP_A, KEEP_T>(dc, r, s12, s13, s23, Are, Aim, Tre, Tim, Gk, Sre, Sim);
+    dalitz_pair<S, 0, MODE, KEEP_A, KEEP_T>(dc, r, coef, s12, s13, s23, Are, Aim, Tre, Tim, Gk, Sre, Sim);
+    dalitz_pair<S, 1, MODE, KEEP_A, KEEP_T>(dc, r, coef, s12, s13, s23, Are, Aim, Tre, Tim, Gk, Sre, Sim);
+    dalitz_pair<S, 2, MODE, KEEP_A, KEEP_T>(dc, r, coef, s12, s13, s23, Are, Aim, Tre, Tim, Gk, Sre, Sim);
     if (MODE == kMRows) {
 #pragma unroll
       for (int ib = 0; ib < kMRowBlock; ++ib) {
@@ -241,7 +244,7 @@ __device__ inline void dalitz_chunk(const DalitzConst& dc, const DalitzTable* __
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         const double* rk = r + k * kDalFields;
-        const double cr = rk[dCRE], ci = rk[dCIM];
+        const double cr = coef[2 * k], ci = coef[2 * k + 1];
         // E = conj(S) c A
         const double car = cr * Are[k] - ci * Aim[k], cai = cr * Aim[k] + ci * Are[k];
         const double er = Sre * car + Sim * cai, ei = Sre * cai - Sim * car;
@@ -261,21 +264,24 @@ __device__ inline void dalitz_chunk(const DalitzConst& dc, const DalitzTable* __
 }
 
 // One workgroup per chunk, one row of NV partial sums each.
+// coef: (Re c_k, Im c_k) of the resonances (theta's first 2K entries, or the
+// table's copy of them); unused by kMRows.
 template <class S, int MODE, int GRAD>
 __device__ inline void dalitz_pass_body(const DalitzConst& dc, const DalitzTable* __restrict__ tab,
-                                        const double* __restrict__ ev, int64_t ld, int64_t n, int chunk, int i0,
-                                        double* __restrict__ part) {
+                                        const double* __restrict__ coef, const double* __restrict__ ev, int64_t ld,
+                                        int64_t n, int chunk, int i0, double* __restrict__ part) {
   constexpr int NV = dal_nv(MODE, GRAD, S::K);
   __shared__ double lds[block_sum_lds(NV)];
-  dalitz_chunk<S, MODE, GRAD>(dc, tab, ev, ld, n, blockIdx.x, chunk, i0, part + (int64_t)blockIdx.x * NV, lds);
+  dalitz_chunk<S, MODE, GRAD>(dc, tab, coef, ev, ld, n, blockIdx.x, chunk, i0, part + (int64_t)blockIdx.x * NV,
+                              lds);
 }
 
 }  // namespace fn
 
 // Kernel NAME for shape S, mode and gradient level (used by the generated source).
-#define FN_DALITZ_KERNEL(NAME, S, MODE, GRAD)                                                              \
-  extern "C" __global__ __launch_bounds__(fn::kBlock) void NAME(                                             \
-      fn::DalitzConst dc, const fn::DalitzTable* __restrict__ tab, const double* __restrict__ ev, int64_t ld, \
-      int64_t n, int chunk, int i0, double* __restrict__ part) {                                             \
-    fn::dalitz_pass_body<S, MODE, GRAD>(dc, tab, ev, ld, n, chunk, i0, part);                                \
+#define FN_DALITZ_KERNEL(NAME, S, MODE, GRAD)                                                                \
+  extern "C" __global__ __launch_bounds__(fn::kBlock) void NAME(                                               \
+      fn::DalitzConst dc, const fn::DalitzTable* __restrict__ tab, const double* __restrict__ coef,           \
+      const double* __restrict__ ev, int64_t ld, int64_t n, int chunk, int i0, double* __restrict__ part) {   \
+    fn::dalitz_pass_body<S, MODE, GRAD>(dc, tab, coef, ev, ld, n, chunk, i0, part);                            \
   }

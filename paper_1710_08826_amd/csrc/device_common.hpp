@@ -17,6 +17,7 @@
 namespace fn {
 
 constexpr int kQuads = kBlock / 4;  // quad sums per workgroup
+constexpr int kFinalBlock = 1024;   // level-2 block size
 
 // LDS doubles block_sum_row needs for NV values.
 __host__ __device__ constexpr int block_sum_lds(int nv) { return kQuads * nv; }
@@ -53,17 +54,20 @@ __device__ inline void block_sum_row(double (&v)[NV], double* lds /* block_sum_l
   }
 }
 
-// Level 2: res[v] = sum over rows r of part[r*nv + v], for v < nv <= kBlock.
-// Thread t takes column t % nv and rows g, g+G, g+2G, ... with g = t / nv,
-// G = kBlock / nv, in sixteen interleaved partial sums (sixteen independent
-// loads in flight per thread: the rows were just written by other compute
-// units, so this step is load-latency bound); the partial sums are added
-// pairwise and the groups in order of g.  scratch holds kBlock doubles.
-__device__ inline void sum_rows(const double* __restrict__ part, int64_t nrows, int nv,
-                                double* scratch, double* res) {
-  constexpr int U = 16;
+// Level 2: res[v] = sum over rows r of part[r*nv + v], for v < nv <= TB (the
+// block size).  Thread t takes column t % nv and rows g, g+G, g+2G, ... with
+// g = t / nv, G = TB / nv, in eight interleaved partial sums (eight
+// independent loads in flight per thread: the rows were just written by other
+// compute units, so this step is load-latency bound; a large block keeps the
+// number of rounds per thread small); the partial sums are added pairwise and
+// the G group sums of each column by a pairwise tree over g.  scratch holds TB
+// doubles.
+template <int TB>
+__device__ inline void sum_rows_t(const double* __restrict__ part, int64_t nrows, int nv, double* scratch,
+                                  double* res) {
+  constexpr int U = 8;
   const int t = threadIdx.x;
-  const int G = kBlock / nv;
+  const int G = TB / nv;
   const int g = t / nv;
   const int v = t - g * nv;
   double s = 0.0;
@@ -89,12 +93,19 @@ __device__ inline void sum_rows(const double* __restrict__ part, int64_t nrows, 
   }
   scratch[t] = s;
   __syncthreads();
-  if (t < nv) {
-    double acc = scratch[t];
-    for (int gg = 1; gg < G; ++gg) acc += scratch[gg * nv + t];
-    res[t] = acc;
+  int h = 1;
+  while (h < G) h <<= 1;
+  for (h >>= 1; h > 0; h >>= 1) {
+    if (g < h && g + h < G) scratch[t] += scratch[t + h * nv];
+    __syncthreads();
   }
+  if (t < nv) res[t] = scratch[t];
   __syncthreads();
+}
+
+__device__ inline void sum_rows(const double* __restrict__ part, int64_t nrows, int nv, double* scratch,
+                                double* res) {
+  sum_rows_t<kBlock>(part, nrows, nv, scratch, res);
 }
 
 }  // namespace fn

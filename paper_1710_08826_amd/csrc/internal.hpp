@@ -60,6 +60,7 @@ struct fn_model {
   int64_t n_mc = 0;              // td4 normalization sample size (0 = not set)
   int64_t mc_gen = 0;            // bumped whenever the sample is replaced
   bool M_valid = false;          // cached normalization matrix is current
+  bool table_ready = false;      // fixed lineshapes: the table's lineshape constants are built
   fn::DevBuf d_table, d_part, d_npart, d_out, d_fixed, d_M, d_count, d_mc;
   double* h_out = nullptr;       // pinned
   long long stats_calls = 0;

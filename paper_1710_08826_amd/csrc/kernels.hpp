@@ -47,15 +47,17 @@ int dalitz_nv_mrows(int kmax);
 void dalitz_launch_prologue(const DalitzConst& dc, const ParamBlock& pb, const double* theta_dev,
                             const double* fixed_ls, int n_fits, int theta_stride, DalitzTable* tab, hipStream_t s);
 // Events pass: one row of partial sums per chunk of events.
-void dalitz_launch_events(const DalitzJit& j, const DalitzConst& dc, const DalitzTable* tab, const double* ev,
-                          int64_t ld, int64_t n, int chunk, int64_t nchunks, int grad, double* part, hipStream_t s);
+// coef: (Re c_k, Im c_k) in device memory (theta itself, or the table's copy).
+void dalitz_launch_events(const DalitzJit& j, const DalitzConst& dc, const DalitzTable* tab, const double* coef,
+                          const double* ev, int64_t ld, int64_t n, int chunk, int64_t nchunks, int grad, double* part,
+                          hipStream_t s);
 // Level-2 sum of the event rows and of the normalization (grid rows, or the
 // cached M when npart is null), NLL assembly: out = [NLL, grad, I, dI].
-void dalitz_launch_finalize(const DalitzConst& dc, const DalitzTable* tab, const double* evpart, int64_t ev_rows,
-                            int grad, const double* npart, int64_t n_rows, int n_nv, const double* Mc,
-                            double n_events, double* out, double* out_user, hipStream_t s);
-void dalitz_launch_grid(const DalitzJit& j, const DalitzConst& dc, const DalitzTable* tab, int chunk,
-                        int64_t nchunks, int grad, double* part, hipStream_t s);
+void dalitz_launch_finalize(const DalitzConst& dc, const DalitzTable* tab, const double* coef, const double* evpart,
+                            int64_t ev_rows, int grad, const double* npart, int64_t n_rows, int n_nv,
+                            const double* Mc, double n_events, double* out, double* out_user, hipStream_t s);
+void dalitz_launch_grid(const DalitzJit& j, const DalitzConst& dc, const DalitzTable* tab, const double* coef,
+                        int chunk, int64_t nchunks, int grad, double* part, hipStream_t s);
 void dalitz_launch_mrows(const DalitzJit& j, const DalitzConst& dc, const DalitzTable* tab, int chunk,
                          int64_t nchunks, int i0, double* part, double* Mc, hipStream_t s);
 void dalitz_launch_eval(const DalitzConst& dc, const DalitzTable* tab, const double* ev, int64_t ld, int64_t n,

@@ -352,8 +352,16 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
     const int g = grad ? (dc.free_ls ? 2 : 1) : 0;
     const int nv = dalitz_nv_events(kmax, g);
     m->d_part.reserve(sizeof(double) * (size_t)(nch > 0 ? nch : 1) * nv);
-    ParamBlock zero;
-    dalitz_launch_prologue(dc, pb ? *pb : zero, pb ? nullptr : theta_dev, m->fixed(), 1, 0, m->table_dal(), s);
+    // The table holds the lineshape constants (functions of theta only when the
+    // lineshapes are free) and a copy of the coefficients; with fixed lineshapes
+    // and theta on the device, the passes read the coefficients from theta and
+    // the table is built once.
+    if (dc.free_ls || pb || !m->table_ready) {
+      ParamBlock zero;
+      dalitz_launch_prologue(dc, pb ? *pb : zero, pb ? nullptr : theta_dev, m->fixed(), 1, 0, m->table_dal(), s);
+      if (!dc.free_ls) m->table_ready = true;
+    }
+    const double* coef = theta_dev ? theta_dev : m->table_dal()->coef;
     const double* npart = nullptr;
     int64_t nrows = 0;
     int nnv = 0;
@@ -363,7 +371,7 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
       nrows = nchunks_for(ncell, m->grid_chunk);
       nnv = dalitz_nv_events(kmax, g);
       m->d_npart.reserve(sizeof(double) * (size_t)nrows * nnv);
-      dalitz_launch_grid(*m->dal_jit, dc, m->table_dal(), m->grid_chunk, nrows, g, m->npart(), s);
+      dalitz_launch_grid(*m->dal_jit, dc, m->table_dal(), coef, m->grid_chunk, nrows, g, m->npart(), s);
       npart = m->npart();
     } else if (!m->M_valid) {
       // fixed lineshapes: reduce the grid once to M_ij = dA sum A_i conj(A_j)
@@ -380,13 +388,13 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
       t1 = m->take_event();
       hip_check(hipEventRecord(t0, s), "hipEventRecord");
     }
-    dalitz_launch_events(*m->dal_jit, dc, m->table_dal(), ev, ld, n, m->chunk, nch, g, m->part(), s);
+    dalitz_launch_events(*m->dal_jit, dc, m->table_dal(), coef, ev, ld, n, m->chunk, nch, g, m->part(), s);
     if (t0) {
       hip_check(hipEventRecord(t1, s), "hipEventRecord");
       m->ev_pending.emplace_back(t0, t1);
     }
-    dalitz_launch_finalize(dc, m->table_dal(), m->part(), nch, g, npart, nrows, nnv, m->Mc(), (double)n, m->out(),
-                           out_user, s);
+    dalitz_launch_finalize(dc, m->table_dal(), coef, m->part(), nch, g, npart, nrows, nnv, m->Mc(), (double)n,
+                           m->out(), out_user, s);
   }
   hip_check(hipGetLastError(), "kernel launch");
 }

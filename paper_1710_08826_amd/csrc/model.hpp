@@ -85,6 +85,7 @@ enum DalField : int {
 };
 struct DalitzTable {
   double r[kDalMaxRes][kDalFields];
+  double coef[2 * kDalMaxRes];  // (Re c_k, Im c_k), the layout of theta's first 2K entries
   double valid;
 };
 

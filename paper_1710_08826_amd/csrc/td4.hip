@@ -316,16 +316,16 @@ __global__ __launch_bounds__(kBlock) void td4_mrows(Td4Const tc, const Td4Table*
   block_sum_row<NV>(acc, lds, part + ((int64_t)f * nch + ch) * NV);
 }
 
-__global__ __launch_bounds__(kBlock) void td4_mrows_finalize(Td4Const tc, const double* __restrict__ part,
-                                                             int64_t nch, int nv, int kmax, int i0, double inv_n,
-                                                             double* __restrict__ Mc) {
-  __shared__ double scratch[kBlock];
+__global__ __launch_bounds__(kFinalBlock) void td4_mrows_finalize(Td4Const tc, const double* __restrict__ part,
+                                                                  int64_t nch, int nv, int kmax, int i0,
+                                                                  double inv_n, double* __restrict__ Mc) {
+  __shared__ double scratch[kFinalBlock];
   __shared__ double res[kBlock];
   const int f = blockIdx.x;
-  sum_rows(part + (int64_t)f * nch * nv, nch, nv, scratch, res);
+  sum_rows_t<kFinalBlock>(part + (int64_t)f * nch * nv, nch, nv, scratch, res);
   const int K = tc.K;
   double* M = Mc + (int64_t)f * 2 * kTd4MaxAmp * kTd4MaxAmp;
-  for (int t = threadIdx.x; t < kTd4RowBlock * kmax; t += kBlock) {
+  for (int t = threadIdx.x; t < kTd4RowBlock * kmax; t += kFinalBlock) {
     const int ib = t / kmax, j = t - ib * kmax;
     const int i = i0 + ib;
     if (i < K && j < K) {
@@ -340,13 +340,13 @@ __global__ __launch_bounds__(kBlock) void td4_mrows_finalize(Td4Const tc, const 
 // b for Abar, z = <conj(A) Abar> = sum_kl conj(c_k) cb_l M_lk; cy = 1/(G(1-y^2)),
 // cx = 1/(G(1+x^2)).  X_k = sum_j M_kj conj(c_j), Y_k = sum_j M_kj conj(cb_j),
 // U_k = sum_l cb_l M_lk, V_l = sum_k conj(c_k) M_lk.
-__global__ __launch_bounds__(kBlock) void td4_finalize(Td4Const tc, const Td4Table* __restrict__ tabs,
+__global__ __launch_bounds__(kFinalBlock) void td4_finalize(Td4Const tc, const Td4Table* __restrict__ tabs,
                                                        const int* __restrict__ status, const double* __restrict__ part,
                                                        int64_t rows, int nv, int kmax, int with_grad,
                                                        const double* __restrict__ Mc, double n_events,
                                                        double* __restrict__ out, int out_stride,
                                                        double* __restrict__ out_user) {
-  __shared__ double scratch[kBlock];
+  __shared__ double scratch[kFinalBlock];
   __shared__ double res[kBlock];
   __shared__ double M[2 * kTd4MaxAmp * kTd4MaxAmp];
   __shared__ double gI[4 * kTd4MaxAmp + 2];
@@ -356,8 +356,8 @@ __global__ __launch_bounds__(kBlock) void td4_finalize(Td4Const tc, const Td4Tab
   const Td4Table& tb = tabs[f];
   const int K = tc.K, P = tc.n_params;
   const int t = threadIdx.x;
-  sum_rows(part + (int64_t)f * rows * nv, rows, nv, scratch, res);
-  for (int i = t; i < 2 * kTd4MaxAmp * kTd4MaxAmp; i += kBlock)
+  sum_rows_t<kFinalBlock>(part + (int64_t)f * rows * nv, rows, nv, scratch, res);
+  for (int i = t; i < 2 * kTd4MaxAmp * kTd4MaxAmp; i += kFinalBlock)
     M[i] = Mc[(int64_t)f * 2 * kTd4MaxAmp * kTd4MaxAmp + i];
   __syncthreads();
   if (t == 0) {
@@ -521,7 +521,7 @@ void td4_launch_mmatrix(const Td4Const& tc, const Td4Table* tabs, int n_fits, co
       hipLaunchKernelGGL((td4_mrows<10>), g, b, 0, s, tc, tabs, mc, ld_mc, n_mc, chunk, nch, n_fits, i0, part);
     else
       hipLaunchKernelGGL((td4_mrows<12>), g, b, 0, s, tc, tabs, mc, ld_mc, n_mc, chunk, nch, n_fits, i0, part);
-    hipLaunchKernelGGL(td4_mrows_finalize, dim3(n_fits), dim3(kBlock), 0, s, tc, part, nch, nv, kmax, i0,
+    hipLaunchKernelGGL(td4_mrows_finalize, dim3(n_fits), dim3(kFinalBlock), 0, s, tc, part, nch, nv, kmax, i0,
                        1.0 / (double)n_mc, Mc);
   }
 }
@@ -546,7 +546,7 @@ void td4_launch_finalize(const Td4Const& tc, const Td4Table* tabs, const int* st
                          int64_t rows_per_fit, bool grad, const double* Mc, double n_events, double* out,
                          int out_stride, double* out_user, hipStream_t s) {
   const int kmax = td4_kmax(tc.K);
-  hipLaunchKernelGGL(td4_finalize, dim3(n_fits), dim3(kBlock), 0, s, tc, tabs, status, part, rows_per_fit,
+  hipLaunchKernelGGL(td4_finalize, dim3(n_fits), dim3(kFinalBlock), 0, s, tc, tabs, status, part, rows_per_fit,
                      td4_nv(kmax, grad), kmax, grad ? 1 : 0, Mc, n_events, out, out_stride, out_user);
 }
 
