@@ -121,7 +121,7 @@ def td4_flops_per_event(desc: dict, grad: bool) -> int:
     f += 27 + W_LOG + 1                            # rate, log, accumulate
     if grad:
         f += 2 * 3 + 8                             # dh/da of the three time terms
-        f += 1 + W_DIV + 2 + 40 * K + 20           # -1/R, per-amplitude adjoint, x and y
+        f += 1 + W_DIV + 2 + 24 + 16 * K + 20      # -1/R, the two complex weights, lc B_k and lb B_k, x and y
     return f
 
 

@@ -56,6 +56,7 @@ struct fn_model {
   fn::DalitzConst dal;
   fn::Td4Const td4;
   std::shared_ptr<fn::DalitzJit> dal_jit;  // structure-specialized passes
+  std::shared_ptr<fn::Td4Jit> td4_jit;
   std::vector<double> fixed_ls;  // (m0, Gamma0) per resonance when not free; td4: fixed-constant vector
   int64_t n_mc = 0;              // td4 normalization sample size (0 = not set)
   int64_t mc_gen = 0;            // bumped whenever the sample is replaced

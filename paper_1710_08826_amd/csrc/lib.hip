@@ -224,7 +224,7 @@ Td4FitConst td4_fit_const(const Td4Const& tc, const double* fixed) {
   return fc;
 }
 
-static void compile_td4(const json::Value& d, fn_model* m) {
+static void compile_td4(const json::Value& d, fn_model* m, bool device = true) {
   Td4Const& tc = m->td4;
   std::memset(&tc, 0, sizeof(tc));
   const double M = d.at("M").number();
@@ -287,6 +287,8 @@ static void compile_td4(const json::Value& d, fn_model* m) {
   m->P = tc.n_params;
   m->n_obs = 6;
   m->chunk = 1024;
+  if (!device) return;
+  m->td4_jit = td4_jit(tc);
   m->d_table.reserve(sizeof(Td4Table));
   m->d_fixed.reserve(sizeof(Td4FitConst));
   hip_check(hipMemcpy(m->d_fixed.ptr, &fc, sizeof(fc), hipMemcpyHostToDevice), "hipMemcpy");
@@ -329,7 +331,8 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
       const int mchunk = 1024;
       const int64_t mrows = nchunks_for(m->n_mc, mchunk);
       m->d_npart.reserve(sizeof(double) * (size_t)mrows * 8 * kmax);
-      td4_launch_mmatrix(tc, m->table_td4(), 1, (const double*)m->d_mc.ptr, m->n_mc, m->n_mc, mchunk, m->npart(),
+      td4_launch_mmatrix(*m->td4_jit, tc, m->table_td4(), 1, (const double*)m->d_mc.ptr, m->n_mc, m->n_mc, mchunk,
+                         m->npart(),
                          m->Mc(), s);
       m->M_valid = true;
     }
@@ -339,7 +342,7 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
       t1 = m->take_event();
       hip_check(hipEventRecord(t0, s), "hipEventRecord");
     }
-    td4_launch_events(tc, m->table_td4(), nullptr, 1, ev, ld, n, m->chunk, grad, m->part(), s);
+    td4_launch_events(*m->td4_jit, tc, m->table_td4(), nullptr, 1, ev, ld, n, m->chunk, grad, m->part(), s);
     if (t0) {
       hip_check(hipEventRecord(t1, s), "hipEventRecord");
       m->ev_pending.emplace_back(t0, t1);
@@ -534,7 +537,10 @@ fn_status fn_model_check_compile(const char* desc_json, const char* arch) {
       if (kind == "dalitz3") {
         compile_dalitz3(d, &tmp, false);
         (void)jit_compile(dalitz_jit_source(tmp.dal), target);
-      } else if (kind != "mix1d" && kind != "td4") {
+      } else if (kind == "td4") {
+        compile_td4(d, &tmp, false);
+        (void)jit_compile(td4_jit_source(tmp.td4), target);
+      } else if (kind != "mix1d") {
         throw Error(FN_E_INVALID, "unknown model kind \"" + kind + "\"");
       }
     } catch (const Error&) {

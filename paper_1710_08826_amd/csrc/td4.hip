@@ -1,105 +1,19 @@
 // Time-dependent four-body amplitude model (the paper's four-body
-// time-dependent amplitude analyses, Abstract and Sec. 5).
-//
-// Per event (m12, m34, c12, c34, phi, t) and fit:
-//   a12[r], a34[r]   pair lineshapes: 1 (non-resonant) or Ka F_L(q r) T with
-//                    T = (a + i b)/(a^2 + b^2), a = m0^2 - s, b = Kw G_L(s),
-//                    G_L = q^(2L+1) F_L(q r)^2 / sqrt(s) (as in the three-body kernel)
-//   B_k = a12[r1_k] a34[r2_k] Omega_k(c12, c34, phi), A = sum c_k B_k, Abar = sum cbar_k B_k
-//   R = 1/2 [(|A|^2+|Abar|^2) Hc + (|A|^2-|Abar|^2) Hcos - 2 Re(A* Abar) Hs - 2 Im(A* Abar) Hsin]
-// with Hc, Hs = (h(G(1-y)) +- h(G(1+y)))/2 and Hcos + i Hsin = h(G(1 - i x)), where
-// h(a; t) = exp(a^2 s^2/2 - a t) erfc((a s^2 - t)/(s sqrt2)) / 2 is the exponential
-// convolved with the Gaussian resolution of width s, evaluated through the
-// Faddeeva function w (Weideman, SIAM J. Numer. Anal. 31 (1994) 1497:
-// w(z) = [2 p(Z)/(L - i z) + 1/sqrt(pi)] / (L - i z), Z = (L + i z)/(L - i z),
-// p a polynomial of degree N-1 whose coefficients are the Fourier
-// coefficients of exp(-t^2)(L^2 + t^2), t = L tan(theta/2); N = 40, L = sqrt(N/sqrt 2)).
-// dh/da = (a s^2 - t) h - s/sqrt(2 pi) exp(-t^2/(2 s^2)) gives the x, y derivatives.
-// I is the phase-space average of the t-integrated rate, a quadratic form in the
-// coefficients through the per-fit matrix M_ij = <B_i conj(B_j)>.
+// time-dependent amplitude analyses, Abstract and Sec. 5): host launchers and
+// the kernels that do not depend on the model's shape (prologue, level-2
+// finalize, per-event density, domain check).  The per-event and
+// normalization-matrix passes live in td4_device.hpp and are compiled at model
+// creation with the model's shape as compile-time constants (td4_jit below).
 #include <cmath>
+#include <sstream>
 #include <vector>
 
-#include "device_common.hpp"
-#include "fastmath.hpp"
+#include "internal.hpp"
+#include "jit.hpp"
 #include "td4.hpp"
+#include "td4_device.hpp"
 
 namespace fn {
-
-namespace {
-
-struct cplx {
-  double re, im;
-};
-__device__ __forceinline__ cplx cmul(cplx a, cplx b) {
-  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
-}
-__device__ __forceinline__ cplx crcp(cplx a) {
-  const double d = rcp_nr(__builtin_fma(a.re, a.re, a.im * a.im));
-  return {a.re * d, -a.im * d};
-}
-
-constexpr double kInvSqrtPi = 0.56418958354775628695;
-constexpr double kInvSqrt2Pi = 0.39894228040143267794;
-constexpr double kInvSqrt2 = 0.70710678118654752440;
-
-}  // namespace
-
-// w(z) for Im z >= 0.
-__device__ inline cplx faddeeva(const Td4Const& tc, cplx z) {
-  const cplx d = {tc.wL + z.im, -z.re};      // L - i z
-  const cplx id = crcp(d);
-  const cplx Z = cmul({tc.wL - z.im, z.re}, id);  // (L + i z)/(L - i z)
-  cplx p = {tc.wa[kWeidN - 1], 0.0};
-#pragma unroll
-  for (int n = kWeidN - 2; n >= 0; --n) {
-    const cplx q = cmul(p, Z);
-    p = {q.re + tc.wa[n], q.im};
-  }
-  const cplx t = cmul({2.0 * p.re, 2.0 * p.im}, id);
-  return cmul({t.re + kInvSqrtPi, t.im}, id);
-}
-
-// w(i y), y >= 0 (real on the imaginary axis): Z = (L - y)/(L + y).
-__device__ inline double faddeeva_imag(const Td4Const& tc, double y) {
-  const double id = rcp_nr(tc.wL + y);
-  const double Z = (tc.wL - y) * id;
-  double p = tc.wa[kWeidN - 1];
-#pragma unroll
-  for (int n = kWeidN - 2; n >= 0; --n) p = __builtin_fma(p, Z, tc.wa[n]);
-  return __builtin_fma(2.0 * p, id, kInvSqrtPi) * id;
-}
-
-// h(a; t) and dh/da for real a.  g = exp(-t^2/(2 s^2)).
-__device__ inline void h_real(const Td4Const& tc, double a, double t, double s, double s2, double g, double& h,
-                              double& dh) {
-  const double u = a * s2 - t;
-  const double z = u * (kInvSqrt2 / s);
-  const double w = faddeeva_imag(tc, fabs(z));
-  h = z >= 0.0 ? 0.5 * g * w : exp(0.5 * a * a * s2 - a * t) - 0.5 * g * w;
-  dh = u * h - s * kInvSqrt2Pi * g;
-}
-
-// h(a; t) and dh/da for complex a.
-__device__ inline void h_cplx(const Td4Const& tc, cplx a, double t, double s, double s2, double g, cplx& h, cplx& dh) {
-  const cplx u = {a.re * s2 - t, a.im * s2};
-  const cplx z = {u.re * (kInvSqrt2 / s), u.im * (kInvSqrt2 / s)};
-  const bool up = z.re >= 0.0;
-  const cplx arg = up ? cplx{-z.im, z.re} : cplx{z.im, -z.re};  // i z or -i z, Im >= 0
-  const cplx w = faddeeva(tc, arg);
-  if (up) {
-    h = {0.5 * g * w.re, 0.5 * g * w.im};
-  } else {
-    const double er = 0.5 * (a.re * a.re - a.im * a.im) * s2 - a.re * t;
-    const double ei = a.re * a.im * s2 - a.im * t;
-    double sn, cs;
-    sincos(ei, &sn, &cs);
-    const double e = exp(er);
-    h = {e * cs - 0.5 * g * w.re, e * sn - 0.5 * g * w.im};
-  }
-  const cplx uh = cmul(u, h);
-  dh = {uh.re - s * kInvSqrt2Pi * g, uh.im};
-}
 
 // Lineshapes of one pair from its invariant mass m: amp[r] for every resonance of the pair.
 template <int NR>
@@ -208,114 +122,7 @@ __global__ void td4_prologue(Td4Const tc, ParamBlock pb, const double* __restric
   tabs[f] = t;
 }
 
-// ----------------------------------------------------------- events pass
-template <bool GRAD, int KMAX>
-__global__ __launch_bounds__(kBlock) void td4_events(Td4Const tc, const Td4Table* __restrict__ tabs,
-                                                     const int* __restrict__ status, const double* __restrict__ ev,
-                                                     int64_t ld, int64_t n, int chunk, int64_t nch, int n_fits,
-                                                     double* __restrict__ part) {
-  constexpr int NV = GRAD ? 3 + 4 * KMAX : 1;
-  __shared__ double lds[block_sum_lds(NV)];
-  // fits vary fastest: the workgroups of one event chunk run together and share it through L2
-  const int64_t ch = blockIdx.x / n_fits;
-  const int f = (int)(blockIdx.x - ch * n_fits);
-  if (status && status[f] != 1) return;
-  const Td4Table& tb = tabs[f];
-  double acc[NV];
-#pragma unroll
-  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
-  const double s = tb.sigma, s2 = s * s, inv2s2 = 0.5 / s2;
-  const double G = tc.gamma;
-  const double ap = G * (1.0 - tb.y), am = G * (1.0 + tb.y);
-  const cplx ac = {G, -G * tb.x};
-  const int64_t base = ch * chunk;
-  const int64_t end = base + chunk < n ? base + chunk : n;
-  for (int64_t i = base + threadIdx.x; i < end; i += kBlock) {
-    cplx B[KMAX];
-    td4_basis<KMAX>(tc, tb, ev[i], ev[ld + i], ev[2 * ld + i], ev[3 * ld + i], ev[4 * ld + i], B);
-    const double t = ev[5 * ld + i];
-    cplx A = {0.0, 0.0}, Ab = {0.0, 0.0};
-#pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
-      if (k < tc.K) {
-        const cplx x = cmul({tb.c[k][0], tb.c[k][1]}, B[k]);
-        const cplx y = cmul({tb.cb[k][0], tb.cb[k][1]}, B[k]);
-        A = {A.re + x.re, A.im + x.im};
-        Ab = {Ab.re + y.re, Ab.im + y.im};
-      }
-    }
-    const double g = exp(-t * t * inv2s2);
-    double hp, dhp, hm, dhm;
-    cplx hc, dhc;
-    h_real(tc, ap, t, s, s2, g, hp, dhp);
-    h_real(tc, am, t, s, s2, g, hm, dhm);
-    h_cplx(tc, ac, t, s, s2, g, hc, dhc);
-    const double Hc = 0.5 * (hp + hm), Hs = 0.5 * (hp - hm);
-    const double a2 = A.re * A.re + A.im * A.im, b2 = Ab.re * Ab.re + Ab.im * Ab.im;
-    const double zr = A.re * Ab.re + A.im * Ab.im, zi = A.re * Ab.im - A.im * Ab.re;  // conj(A) Abar
-    const double R = 0.5 * ((a2 + b2) * Hc + (a2 - b2) * hc.re - 2.0 * zr * Hs - 2.0 * zi * hc.im);
-    acc[0] -= log_fast(R);
-    if (GRAD) {
-      const double w = -rcp_nr(R);
-      const double hpc = Hc + hc.re, hmc = Hc - hc.re;
-#pragma unroll
-      for (int k = 0; k < KMAX; ++k) {
-        if (k < tc.K) {
-          // u = conj(A) B_k, v = conj(Abar) B_k
-          const cplx u = {A.re * B[k].re + A.im * B[k].im, A.re * B[k].im - A.im * B[k].re};
-          const cplx v = {Ab.re * B[k].re + Ab.im * B[k].im, Ab.re * B[k].im - Ab.im * B[k].re};
-          acc[1 + 2 * k] += w * (hpc * u.re - Hs * v.re + hc.im * v.im);
-          acc[2 + 2 * k] += w * (-hpc * u.im + Hs * v.im + hc.im * v.re);
-          acc[1 + 2 * KMAX + 2 * k] += w * (hmc * v.re - Hs * u.re - hc.im * u.im);
-          acc[2 + 2 * KMAX + 2 * k] += w * (-hmc * v.im + Hs * u.im - hc.im * u.re);
-        }
-      }
-      // x: d hc/dx = -i G dh(ac);  y: d hp/dy = -G dh(ap), d hm/dy = +G dh(am)
-      const double dcos = G * dhc.im, dsin = -G * dhc.re;
-      acc[1 + 4 * KMAX] += w * 0.5 * ((a2 - b2) * dcos - 2.0 * zi * dsin);
-      const double dHc = 0.5 * G * (dhm - dhp), dHs = -0.5 * G * (dhp + dhm);
-      acc[2 + 4 * KMAX] += w * 0.5 * ((a2 + b2) * dHc - 2.0 * zr * dHs);
-    }
-  }
-  block_sum_row<NV>(acc, lds, part + ((int64_t)f * nch + ch) * NV);
-}
-
 // ---------------------------------------------------- normalization matrix
-constexpr int kTd4RowBlock = 4;
-
-template <int KMAX>
-__global__ __launch_bounds__(kBlock) void td4_mrows(Td4Const tc, const Td4Table* __restrict__ tabs,
-                                                    const double* __restrict__ mc, int64_t ld, int64_t n, int chunk,
-                                                    int64_t nch, int n_fits, int i0, double* __restrict__ part) {
-  constexpr int NV = 2 * kTd4RowBlock * KMAX;
-  __shared__ double lds[block_sum_lds(NV)];
-  const int64_t ch = blockIdx.x / n_fits;
-  const int f = (int)(blockIdx.x - ch * n_fits);
-  const Td4Table& tb = tabs[f];
-  double acc[NV];
-#pragma unroll
-  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
-  const int64_t base = ch * chunk;
-  const int64_t end = base + chunk < n ? base + chunk : n;
-  for (int64_t i = base + threadIdx.x; i < end; i += kBlock) {
-    cplx B[KMAX];
-    td4_basis<KMAX>(tc, tb, mc[i], mc[ld + i], mc[2 * ld + i], mc[3 * ld + i], mc[4 * ld + i], B);
-#pragma unroll
-    for (int ib = 0; ib < kTd4RowBlock; ++ib) {
-      cplx bi = {0.0, 0.0};
-#pragma unroll
-      for (int k = 0; k < KMAX; ++k)
-        if (k == i0 + ib) bi = B[k];
-#pragma unroll
-      for (int j = 0; j < KMAX; ++j) {
-        acc[2 * (ib * KMAX + j)] += bi.re * B[j].re + bi.im * B[j].im;
-        acc[2 * (ib * KMAX + j) + 1] += bi.im * B[j].re - bi.re * B[j].im;
-      }
-    }
-  }
-  block_sum_row<NV>(acc, lds, part + ((int64_t)f * nch + ch) * NV);
-}
-
 __global__ __launch_bounds__(kFinalBlock) void td4_mrows_finalize(Td4Const tc, const double* __restrict__ part,
                                                                   int64_t nch, int nv, int kmax, int i0,
                                                                   double inv_n, double* __restrict__ Mc) {
@@ -462,9 +269,9 @@ __global__ void td4_eval(Td4Const tc, const Td4Table* __restrict__ tab, const do
   const double g = exp(-t * t * 0.5 / s2), G = tc.gamma;
   double hp, dhp, hm, dhm;
   cplx hc, dhc;
-  h_real(tc, G * (1.0 - tb.y), t, s, s2, g, hp, dhp);
-  h_real(tc, G * (1.0 + tb.y), t, s, s2, g, hm, dhm);
-  h_cplx(tc, {G, -G * tb.x}, t, s, s2, g, hc, dhc);
+  h_real(tc.wa, tc.wL, G * (1.0 - tb.y), t, s, s2, g, hp, dhp);
+  h_real(tc.wa, tc.wL, G * (1.0 + tb.y), t, s, s2, g, hm, dhm);
+  h_cplx(tc.wa, tc.wL, {G, -G * tb.x}, t, s, s2, g, hc, dhc);
   const double a2 = A.re * A.re + A.im * A.im, b2 = Ab.re * Ab.re + Ab.im * Ab.im;
   const double zr = A.re * Ab.re + A.im * Ab.im, zi = A.re * Ab.im - A.im * Ab.re;
   const double R = 0.5 * ((a2 + b2) * 0.5 * (hp + hm) + (a2 - b2) * hc.re - 2.0 * zr * 0.5 * (hp - hm) -
@@ -473,7 +280,7 @@ __global__ void td4_eval(Td4Const tc, const Td4Table* __restrict__ tab, const do
 }
 
 // ---------------------------------------------------------------- launchers
-int td4_kmax(int K) { return K <= 10 ? 10 : 12; }
+int td4_kmax(int K) { return K; }  // partial rows hold exactly the model's amplitudes
 int td4_nv(int kmax, bool grad) { return grad ? 3 + 4 * kmax : 1; }
 
 // Fourier coefficients a_n (n = 1..N) of f(theta) = exp(-t^2)(L^2 + t^2),
@@ -510,36 +317,75 @@ void td4_launch_check(const Td4Const& tc, const double* ev, int64_t ld, int64_t 
   hipLaunchKernelGGL(td4_check, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tc, ev, ld, n, bad);
 }
 
-void td4_launch_mmatrix(const Td4Const& tc, const Td4Table* tabs, int n_fits, const double* mc, int64_t ld_mc,
-                        int64_t n_mc, int chunk, double* part, double* Mc, hipStream_t s) {
+// Source of the shape-specialized passes of a model: the pair entries (spin,
+// flat or resonant) and every amplitude's entries and angular factor as
+// compile-time constants, then the events pass without and with the gradient
+// and the M rows.
+std::string td4_jit_source(const Td4Const& tc) {
+  std::ostringstream o;
+  auto arr = [&](const char* name, const int* v, int n) {
+    o << "  static constexpr int " << name << "[" << n << "] = {";
+    for (int i = 0; i < n; ++i) o << (i ? ", " : "") << v[i];
+    o << "};\n";
+  };
+  o << "#include \"td4_device.hpp\"\n";
+  o << "struct fn_td4_shape {\n  static constexpr int K = " << tc.K
+    << ";\n  static constexpr int N12 = " << tc.n12 << ";\n  static constexpr int N34 = " << tc.n34 << ";\n";
+  arr("L12", tc.L12, tc.n12);
+  arr("NR12", tc.nr12, tc.n12);
+  arr("L34", tc.L34, tc.n34);
+  arr("NR34", tc.nr34, tc.n34);
+  arr("A1", tc.amp1, tc.K);
+  arr("A2", tc.amp2, tc.K);
+  arr("T", tc.atype, tc.K);
+  o << "};\n"
+       "FN_TD4_EVENTS(fn_td4_ev0, fn_td4_shape, false)\n"
+       "FN_TD4_EVENTS(fn_td4_ev1, fn_td4_shape, true)\n"
+       "FN_TD4_MROWS(fn_td4_mrows, fn_td4_shape)\n";
+  return o.str();
+}
+
+std::shared_ptr<Td4Jit> td4_jit(const Td4Const& tc) {
+  auto j = std::make_shared<Td4Jit>();
+  j->prog = jit_load(td4_jit_source(tc), {"fn_td4_ev0", "fn_td4_ev1", "fn_td4_mrows"});
+  j->ev[0] = j->prog->fns[0];
+  j->ev[1] = j->prog->fns[1];
+  j->mrows = j->prog->fns[2];
+  return j;
+}
+
+void td4_launch_mmatrix(const Td4Jit& j, const Td4Const& tc, const Td4Table* tabs, int n_fits, const double* mc,
+                        int64_t ld_mc, int64_t n_mc, int chunk, double* part, double* Mc, hipStream_t s) {
   const int kmax = td4_kmax(tc.K);
   const int64_t nch = (n_mc + chunk - 1) / chunk;
   const int nv = 2 * kTd4RowBlock * kmax;
   for (int i0 = 0; i0 < tc.K; i0 += kTd4RowBlock) {
-    const dim3 g((unsigned)(nch * n_fits)), b(kBlock);
-    if (kmax == 10)
-      hipLaunchKernelGGL((td4_mrows<10>), g, b, 0, s, tc, tabs, mc, ld_mc, n_mc, chunk, nch, n_fits, i0, part);
-    else
-      hipLaunchKernelGGL((td4_mrows<12>), g, b, 0, s, tc, tabs, mc, ld_mc, n_mc, chunk, nch, n_fits, i0, part);
+    Td4Const c = tc;
+    const Td4Table* t = tabs;
+    const double* m = mc;
+    int64_t l = ld_mc, nn = n_mc, nc = nch;
+    int ck = chunk, nf = n_fits, ii = i0;
+    double* p = part;
+    void* args[] = {&c, &t, &m, &l, &nn, &ck, &nc, &nf, &ii, &p};
+    jit_launch(j.mrows, (unsigned)(nch * n_fits), kBlock, s, args);
     hipLaunchKernelGGL(td4_mrows_finalize, dim3(n_fits), dim3(kFinalBlock), 0, s, tc, part, nch, nv, kmax, i0,
                        1.0 / (double)n_mc, Mc);
   }
 }
 
-void td4_launch_events(const Td4Const& tc, const Td4Table* tabs, const int* status, int n_fits, const double* ev,
-                       int64_t ld, int64_t n, int chunk, bool grad, double* part, hipStream_t s) {
+void td4_launch_events(const Td4Jit& j, const Td4Const& tc, const Td4Table* tabs, const int* status, int n_fits,
+                       const double* ev, int64_t ld, int64_t n, int chunk, bool grad, double* part, hipStream_t s) {
   const int64_t nch = (n + chunk - 1) / chunk;
   if (nch == 0) return;
-  const int kmax = td4_kmax(tc.K);
-  const dim3 g((unsigned)(nch * n_fits)), b(kBlock);
-#define FN_TD4(G, K) \
-  hipLaunchKernelGGL((td4_events<G, K>), g, b, 0, s, tc, tabs, status, ev, ld, n, chunk, nch, n_fits, part)
-  if (kmax == 10) {
-    if (grad) FN_TD4(true, 10); else FN_TD4(false, 10);
-  } else {
-    if (grad) FN_TD4(true, 12); else FN_TD4(false, 12);
-  }
-#undef FN_TD4
+  Td4Const c = tc;
+  const Td4Table* t = tabs;
+  const int* st = status;
+  const double* e = ev;
+  int64_t l = ld, nn = n, nc = nch;
+  int ck = chunk, nf = n_fits;
+  double* p = part;
+  void* args[] = {&c, &t, &st, &e, &l, &nn, &ck, &nc, &nf, &p};
+  jit_launch(j.ev[grad ? 1 : 0], (unsigned)(nch * n_fits), kBlock, s, args);
 }
 
 void td4_launch_finalize(const Td4Const& tc, const Td4Table* tabs, const int* status, int n_fits, const double* part,

@@ -1,0 +1,316 @@
+// Device code of the time-dependent four-body model (the paper's four-body
+// time-dependent amplitude analyses, Abstract and Sec. 5).  The per-event and
+// normalization-matrix passes are compiled at run time for each model shape
+// (which pair entries are resonant and with which spin, which entries and
+// angular factor every basis amplitude takes) as compile-time constants; the
+// time functions are shared with the library's own kernels.
+//
+// Per event (m12, m34, c12, c34, phi, t) and fit:
+//   a12[r], a34[r]   pair lineshapes: 1 (non-resonant) or Ka F_L(q r) T with
+//                    T = (a + i b)/(a^2 + b^2), a = m0^2 - s, b = Kw G_L(s),
+//                    G_L = q^(2L+1) F_L(q r)^2 / sqrt(s) (as in the three-body kernel)
+//   B_k = a12[r1_k] a34[r2_k] Omega_k(c12, c34, phi), A = sum c_k B_k, Abar = sum cbar_k B_k
+//   R = 1/2 [(|A|^2+|Abar|^2) Hc + (|A|^2-|Abar|^2) Hcos - 2 Re(A* Abar) Hs - 2 Im(A* Abar) Hsin]
+// with Hc, Hs = (h(G(1-y)) +- h(G(1+y)))/2 and Hcos + i Hsin = h(G(1 - i x)), where
+// h(a; t) = exp(a^2 s^2/2 - a t) erfc((a s^2 - t)/(s sqrt2)) / 2 is the exponential
+// convolved with the Gaussian resolution of width s, evaluated through the
+// Faddeeva function w (Weideman, SIAM J. Numer. Anal. 31 (1994) 1497:
+// w(z) = [2 p(Z)/(L - i z) + 1/sqrt(pi)] / (L - i z), Z = (L + i z)/(L - i z),
+// p a polynomial of degree N-1 whose coefficients are the Fourier
+// coefficients of exp(-t^2)(L^2 + t^2), t = L tan(theta/2); N = 40, L = sqrt(N/sqrt 2)).
+// dh/da = (a s^2 - t) h - s/sqrt(2 pi) exp(-t^2/(2 s^2)) gives the x, y derivatives.
+// I is the phase-space average of the t-integrated rate, a quadratic form in the
+// coefficients through the per-fit matrix M_ij = <B_i conj(B_j)>.
+#pragma once
+#include "device_common.hpp"
+#include "fastmath.hpp"
+#include "td4_types.hpp"
+
+namespace fn {
+
+struct cplx {
+  double re, im;
+};
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__device__ __forceinline__ cplx crcp(cplx a) {
+  const double d = rcp_nr(__builtin_fma(a.re, a.re, a.im * a.im));
+  return {a.re * d, -a.im * d};
+}
+
+constexpr double kInvSqrtPi = 0.56418958354775628695;
+constexpr double kInvSqrt2Pi = 0.39894228040143267794;
+constexpr double kInvSqrt2 = 0.70710678118654752440;
+
+// The rational approximation: scale L and coefficients wa[0..N-1] = a_1..a_N.
+
+// w(z) for Im z >= 0.
+__device__ inline cplx faddeeva(const double* __restrict__ wa, double L, cplx z) {
+  const cplx d = {L + z.im, -z.re};           // L - i z
+  const cplx id = crcp(d);
+  const cplx Z = cmul({L - z.im, z.re}, id);  // (L + i z)/(L - i z)
+  cplx p = {wa[kWeidN - 1], 0.0};
+#pragma unroll
+  for (int n = kWeidN - 2; n >= 0; --n) {
+    const cplx q = cmul(p, Z);
+    p = {q.re + wa[n], q.im};
+  }
+  const cplx t = cmul({2.0 * p.re, 2.0 * p.im}, id);
+  return cmul({t.re + kInvSqrtPi, t.im}, id);
+}
+
+// w(i y), y >= 0 (real on the imaginary axis): Z = (L - y)/(L + y).
+__device__ inline double faddeeva_imag(const double* __restrict__ wa, double L, double y) {
+  const double id = rcp_nr(L + y);
+  const double Z = (L - y) * id;
+  double p = wa[kWeidN - 1];
+#pragma unroll
+  for (int n = kWeidN - 2; n >= 0; --n) p = __builtin_fma(p, Z, wa[n]);
+  return __builtin_fma(2.0 * p, id, kInvSqrtPi) * id;
+}
+
+// h(a; t) and dh/da for real a.  g = exp(-t^2/(2 s^2)).
+__device__ inline void h_real(const double* __restrict__ wa, double L, double a, double t, double s, double s2,
+                              double g, double& h, double& dh) {
+  const double u = a * s2 - t;
+  const double z = u * (kInvSqrt2 / s);
+  const double w = faddeeva_imag(wa, L, fabs(z));
+  h = z >= 0.0 ? 0.5 * g * w : exp(0.5 * a * a * s2 - a * t) - 0.5 * g * w;
+  dh = u * h - s * kInvSqrt2Pi * g;
+}
+
+// h(a; t) and dh/da for complex a.
+__device__ inline void h_cplx(const double* __restrict__ wa, double L, cplx a, double t, double s, double s2, double g,
+                              cplx& h, cplx& dh) {
+  const cplx u = {a.re * s2 - t, a.im * s2};
+  const cplx z = {u.re * (kInvSqrt2 / s), u.im * (kInvSqrt2 / s)};
+  const bool up = z.re >= 0.0;
+  const cplx arg = up ? cplx{-z.im, z.re} : cplx{z.im, -z.re};  // i z or -i z, Im >= 0
+  const cplx w = faddeeva(wa, L, arg);
+  if (up) {
+    h = {0.5 * g * w.re, 0.5 * g * w.im};
+  } else {
+    const double er = 0.5 * (a.re * a.re - a.im * a.im) * s2 - a.re * t;
+    const double ei = a.re * a.im * s2 - a.im * t;
+    double sn, cs;
+    sincos(ei, &sn, &cs);
+    const double e = exp(er);
+    h = {e * cs - 0.5 * g * w.re, e * sn - 0.5 * g * w.im};
+  }
+  const cplx uh = cmul(u, h);
+  dh = {uh.re - s * kInvSqrt2Pi * g, uh.im};
+}
+
+// ------------------------------------------------------- shape-specialized
+// A shape S gives, as compile-time constants: K, N12, N34, L12[], NR12[],
+// L34[], NR34[] (NR = 1 marks a flat entry), A1[], A2[] (pair entries of
+// every basis amplitude) and T[] (angular factor).
+
+template <int N>
+__device__ __host__ constexpr bool any_l1(const int (&L)[N], const int (&NR)[N]) {
+  bool u = false;
+  for (int r = 0; r < N; ++r) u = u || (L[r] == 1 && !NR[r]);
+  return u;
+}
+
+// Lineshapes of one pair from its invariant mass m (rt: the fit's m0^2, Kw, Ka).
+template <int N, const int (&L)[N], const int (&NR)[N]>
+__device__ __forceinline__ void pair_amps_s(double m, double sum2, double dif2, double r2,
+                                            const double (*__restrict__ rt)[3], cplx (&amp)[N]) {
+  const double s = m * m;
+  const double im = rcp_nr(m);
+  const double lq = fmax((s - sum2) * (s - dif2), 0.0);
+  const double q2 = 0.25 * lq * im * im;
+  const double G0 = sqrt_nr(q2) * im;
+  double F1 = 1.0, G1 = 0.0;
+  if (any_l1<N>(L, NR)) {
+    F1 = rsqrt_nr(1.0 + q2 * r2);
+    G1 = G0 * q2 * F1 * F1;
+  }
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    amp[r] = {1.0, 0.0};
+    if (!NR[r]) {
+      const double G = L[r] == 1 ? G1 : G0;
+      const double a = rt[r][0] - s;
+      const double b = rt[r][1] * G;
+      const double d = rcp_nr(__builtin_fma(a, a, b * b));
+      const double k = (L[r] == 1 ? rt[r][2] * F1 : rt[r][2]) * d;
+      amp[r] = {k * a, k * b};
+    }
+  }
+}
+
+// Basis amplitudes B_k of one kinematic point under one fit's lineshapes;
+// products with flat entries and real angular factors are formed as such.
+template <class S>
+__device__ __forceinline__ void td4_basis_s(const Td4Const& tc, const Td4Table& tb, double m12, double m34, double c12,
+                                            double c34, double phi, cplx (&B)[S::K]) {
+  cplx a12[S::N12], a34[S::N34];
+  pair_amps_s<S::N12, S::L12, S::NR12>(m12, tc.sum12, tc.dif12, tc.r2, tb.r12, a12);
+  pair_amps_s<S::N34, S::L34, S::NR34>(m34, tc.sum34, tc.dif34, tc.r2, tb.r34, a34);
+  constexpr bool has_sc = [] {
+    bool u = false;
+    for (int k = 0; k < S::K; ++k) u = u || S::T[k] >= 4;
+    return u;
+  }();
+  double ss = 0.0, sp = 0.0, cp = 1.0;
+  if (has_sc) {
+    ss = 0.5 * sqrt_nr(fmax(1.0 - c12 * c12, 0.0)) * sqrt_nr(fmax(1.0 - c34 * c34, 0.0));
+    sincos(phi, &sp, &cp);
+  }
+#pragma unroll
+  for (int k = 0; k < S::K; ++k) {
+    const int r1 = S::A1[k], r2 = S::A2[k];
+    cplx xy;
+    if (S::NR12[r1] && S::NR34[r2]) xy = {1.0, 0.0};
+    else if (S::NR12[r1]) xy = a34[r2];
+    else if (S::NR34[r2]) xy = a12[r1];
+    else xy = cmul(a12[r1], a34[r2]);
+    switch (S::T[k]) {
+      case 0: B[k] = xy; break;
+      case 1: B[k] = {xy.re * c34, xy.im * c34}; break;
+      case 2: B[k] = {xy.re * c12, xy.im * c12}; break;
+      case 3: { const double cc = c12 * c34; B[k] = {xy.re * cc, xy.im * cc}; } break;
+      case 4: B[k] = cmul(xy, {ss * cp, ss * sp}); break;
+      default: B[k] = cmul(xy, {ss * cp, -ss * sp}); break;
+    }
+  }
+}
+
+// Events pass for n_fits fits sharing one sample: one workgroup per (chunk,
+// fit), fits fastest so the workgroups of a chunk share it through L2; a fit
+// whose status entry is not running is skipped (status may be null).
+template <class S, bool GRAD>
+__device__ inline void td4_events_body(const Td4Const& tc, const Td4Table* __restrict__ tabs,
+                                       const int* __restrict__ status, const double* __restrict__ ev, int64_t ld,
+                                       int64_t n, int chunk, int64_t nch, int n_fits, double* __restrict__ part) {
+  constexpr int K = S::K;
+  constexpr int NV = GRAD ? 3 + 4 * K : 1;
+  __shared__ double lds[block_sum_lds(NV)];
+  const int64_t ch = blockIdx.x / n_fits;
+  const int f = (int)(blockIdx.x - ch * n_fits);
+  if (status && status[f] != 1) return;
+  double acc[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+  const double s = tabs[f].sigma, s2 = s * s, inv2s2 = 0.5 / s2;
+  const double G = tc.gamma;
+  const double ap = G * (1.0 - tabs[f].y), am = G * (1.0 + tabs[f].y);
+  const cplx ac = {G, -G * tabs[f].x};
+  const int64_t base = ch * chunk;
+  const int64_t end = base + chunk < n ? base + chunk : n;
+  for (int64_t i = base + threadIdx.x; i < end; i += kBlock) {
+    // the fit's constants are re-read through the scalar cache on every event
+    // (an opaque zero offset keeps them from being hoisted into SGPRs that
+    // would overflow into VGPR lanes)
+    int zero = 0;
+    asm volatile("" : "+s"(zero));
+    const Td4Table& tb = tabs[f + zero];
+    // time functions first: the basis amplitudes are not live across the
+    // three rational-approximation evaluations
+    const double t = ev[5 * ld + i];
+    const double g = exp(-t * t * inv2s2);
+    double hp, dhp, hm, dhm;
+    cplx hc, dhc;
+    const double* wa = tc.wa + zero;  // re-read per event, like the table
+    h_real(wa, tc.wL, ap, t, s, s2, g, hp, dhp);
+    h_real(wa, tc.wL, am, t, s, s2, g, hm, dhm);
+    h_cplx(wa, tc.wL, ac, t, s, s2, g, hc, dhc);
+    cplx B[K];
+    td4_basis_s<S>(tc, tb, ev[i], ev[ld + i], ev[2 * ld + i], ev[3 * ld + i], ev[4 * ld + i], B);
+    cplx A = {0.0, 0.0}, Ab = {0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const cplx x = cmul({tb.c[k][0], tb.c[k][1]}, B[k]);
+      const cplx y = cmul({tb.cb[k][0], tb.cb[k][1]}, B[k]);
+      A = {A.re + x.re, A.im + x.im};
+      Ab = {Ab.re + y.re, Ab.im + y.im};
+    }
+    const double Hc = 0.5 * (hp + hm), Hs = 0.5 * (hp - hm);
+    const double a2 = A.re * A.re + A.im * A.im, b2 = Ab.re * Ab.re + Ab.im * Ab.im;
+    const double zr = A.re * Ab.re + A.im * Ab.im, zi = A.re * Ab.im - A.im * Ab.re;  // conj(A) Abar
+    const double R = 0.5 * ((a2 + b2) * Hc + (a2 - b2) * hc.re - 2.0 * zr * Hs - 2.0 * zi * hc.im);
+    acc[0] -= log_fast(R);
+    if (GRAD) {
+      const double w = -rcp_nr(R);
+      const double hpc = Hc + hc.re, hmc = Hc - hc.re;
+      // dR/dRe c_k - i dR/dIm c_k = lc B_k and the same for cbar with lb, where
+      // lc = hpc conj(A) - (Hs + i Hsin) conj(Abar), lb = hmc conj(Abar) - (Hs - i Hsin) conj(A)
+      // (the event's factor w = -1/R included)
+      const cplx lc = {w * (hpc * A.re - Hs * Ab.re - hc.im * Ab.im), w * (-hpc * A.im + Hs * Ab.im - hc.im * Ab.re)};
+      const cplx lb = {w * (hmc * Ab.re - Hs * A.re + hc.im * A.im), w * (-hmc * Ab.im + Hs * A.im + hc.im * A.re)};
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const cplx ec = cmul(lc, B[k]), eb = cmul(lb, B[k]);
+        acc[1 + 2 * k] += ec.re;
+        acc[2 + 2 * k] -= ec.im;
+        acc[1 + 2 * K + 2 * k] += eb.re;
+        acc[2 + 2 * K + 2 * k] -= eb.im;
+      }
+      // x: d hc/dx = -i G dh(ac);  y: d hp/dy = -G dh(ap), d hm/dy = +G dh(am)
+      const double dcos = G * dhc.im, dsin = -G * dhc.re;
+      acc[1 + 4 * K] += w * 0.5 * ((a2 - b2) * dcos - 2.0 * zi * dsin);
+      const double dHc = 0.5 * G * (dhm - dhp), dHs = -0.5 * G * (dhp + dhm);
+      acc[2 + 4 * K] += w * 0.5 * ((a2 + b2) * dHc - 2.0 * zr * dHs);
+    }
+  }
+  block_sum_row<NV>(acc, lds, part + ((int64_t)f * nch + ch) * NV);
+}
+
+constexpr int kTd4RowBlock = 4;
+
+// Rows i0..i0+3 of M = sum over the phase-space sample of B_i conj(B_j) (per fit).
+template <class S>
+__device__ inline void td4_mrows_body(const Td4Const& tc, const Td4Table* __restrict__ tabs,
+                                      const double* __restrict__ mc, int64_t ld, int64_t n, int chunk, int64_t nch,
+                                      int n_fits, int i0, double* __restrict__ part) {
+  constexpr int K = S::K;
+  constexpr int NV = 2 * kTd4RowBlock * K;
+  __shared__ double lds[block_sum_lds(NV)];
+  const int64_t ch = blockIdx.x / n_fits;
+  const int f = (int)(blockIdx.x - ch * n_fits);
+  double acc[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+  const int64_t base = ch * chunk;
+  const int64_t end = base + chunk < n ? base + chunk : n;
+  for (int64_t i = base + threadIdx.x; i < end; i += kBlock) {
+    int zero = 0;
+    asm volatile("" : "+s"(zero));
+    const Td4Table& tb = tabs[f + zero];
+    cplx B[K];
+    td4_basis_s<S>(tc, tb, mc[i], mc[ld + i], mc[2 * ld + i], mc[3 * ld + i], mc[4 * ld + i], B);
+#pragma unroll
+    for (int ib = 0; ib < kTd4RowBlock; ++ib) {
+      cplx bi = {0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        if (k == i0 + ib) bi = B[k];
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        acc[2 * (ib * K + j)] += bi.re * B[j].re + bi.im * B[j].im;
+        acc[2 * (ib * K + j) + 1] += bi.im * B[j].re - bi.re * B[j].im;
+      }
+    }
+  }
+  block_sum_row<NV>(acc, lds, part + ((int64_t)f * nch + ch) * NV);
+}
+
+}  // namespace fn
+
+// Kernels for shape S (used by the generated source).
+#define FN_TD4_EVENTS(NAME, S, GRAD)                                                                           \
+  extern "C" __global__ __launch_bounds__(fn::kBlock) void NAME(                                                \
+      fn::Td4Const tc, const fn::Td4Table* __restrict__ tabs, const int* __restrict__ status,                  \
+      const double* __restrict__ ev, int64_t ld, int64_t n, int chunk, int64_t nch, int n_fits,                \
+      double* __restrict__ part) {                                                                              \
+    fn::td4_events_body<S, GRAD>(tc, tabs, status, ev, ld, n, chunk, nch, n_fits, part);                       \
+  }
+#define FN_TD4_MROWS(NAME, S)                                                                                  \
+  extern "C" __global__ __launch_bounds__(fn::kBlock) void NAME(                                                \
+      fn::Td4Const tc, const fn::Td4Table* __restrict__ tabs, const double* __restrict__ mc, int64_t ld,       \
+      int64_t n, int chunk, int64_t nch, int n_fits, int i0, double* __restrict__ part) {                      \
+    fn::td4_mrows_body<S>(tc, tabs, mc, ld, n, chunk, nch, n_fits, i0, part);                                   \
+  }

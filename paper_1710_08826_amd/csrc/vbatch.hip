@@ -110,8 +110,8 @@ void build_matrices(fn_vbatch* b) {
   const int mchunk = 1024;
   const int64_t rows = (m->n_mc + mchunk - 1) / mchunk;
   b->mpart.reserve(sizeof(double) * (size_t)rows * b->F * 8 * td4_kmax(m->td4.K));
-  td4_launch_mmatrix(m->td4, (const Td4Table*)b->tabs.ptr, b->F, (const double*)m->d_mc.ptr, m->n_mc, m->n_mc,
-                     mchunk, (double*)b->mpart.ptr, (double*)b->Mc.ptr, b->stream);
+  td4_launch_mmatrix(*m->td4_jit, m->td4, (const Td4Table*)b->tabs.ptr, b->F, (const double*)m->d_mc.ptr, m->n_mc,
+                     m->n_mc, mchunk, (double*)b->mpart.ptr, (double*)b->Mc.ptr, b->stream);
   hip_check(hipGetLastError(), "kernel launch");
   b->M_valid = true;
   b->mc_gen = m->mc_gen;
@@ -131,7 +131,8 @@ void launch_step(fn_vbatch* b, const double* ev, int64_t n, int64_t ld, double t
   auto* stat = (const int*)b->stat.ptr;
   td4_launch_prologue(tc, nullptr, (const double*)b->st.ptr, stride, (const Td4FitConst*)b->fc.ptr, stat, b->F, tabs,
                       b->stream);
-  td4_launch_events(tc, tabs, stat, b->F, ev, ld, n, m->chunk, true, (double*)b->part.ptr, b->stream);
+  td4_launch_events(*m->td4_jit, tc, tabs, stat, b->F, ev, ld, n, m->chunk, true, (double*)b->part.ptr,
+                    b->stream);
   td4_launch_finalize(tc, tabs, stat, b->F, (const double*)b->part.ptr, nch, true, (const double*)b->Mc.ptr,
                       (double)n, (double*)b->out.ptr, 2 + 2 * b->P, nullptr, b->stream);
   bfgs_launch<kVbMaxP>((VState*)b->st.ptr, (const double*)b->out.ptr, 2 + 2 * b->P, b->F, b->P, tol, max_iter,
@@ -243,7 +244,8 @@ fn_status fn_vbatch_nll(fn_vbatch* b, const double* theta_host, const double* ev
     td4_launch_prologue(m->td4, nullptr, (const double*)b->theta.ptr, P, (const Td4FitConst*)b->fc.ptr, nullptr, F,
                         tabs, b->stream);
     build_matrices(b);
-    td4_launch_events(m->td4, tabs, nullptr, F, ev, ld, n, m->chunk, grad, (double*)b->part.ptr, b->stream);
+    td4_launch_events(*m->td4_jit, m->td4, tabs, nullptr, F, ev, ld, n, m->chunk, grad, (double*)b->part.ptr,
+                      b->stream);
     const int64_t nch = (n + m->chunk - 1) / m->chunk;
     td4_launch_finalize(m->td4, tabs, nullptr, F, (const double*)b->part.ptr, nch, grad, (const double*)b->Mc.ptr,
                         (double)n, (double*)b->out.ptr, 2 + 2 * P, nullptr, b->stream);
