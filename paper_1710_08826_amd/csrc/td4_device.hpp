@@ -302,7 +302,7 @@ __device__ inline void td4_mrows_body(const Td4Const& tc, const Td4Table* __rest
 
 // Kernels for shape S (used by the generated source).
 #define FN_TD4_EVENTS(NAME, S, GRAD)                                                                           \
-  extern "C" __global__ __launch_bounds__(fn::kBlock) void NAME(                                                \
+  extern "C" __global__ __launch_bounds__(fn::kBlock) __attribute__((amdgpu_waves_per_eu(2))) void NAME(        \
       fn::Td4Const tc, const fn::Td4Table* __restrict__ tabs, const int* __restrict__ status,                  \
       const double* __restrict__ ev, int64_t ld, int64_t n, int chunk, int64_t nch, int n_fits,                \
       double* __restrict__ part) {                                                                              \
