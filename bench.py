@@ -31,21 +31,28 @@ PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector, FMA counted as 2
 PEAK_HBM_GBS = 8000.0
 
 # HBM bytes per launch of the config-1 event kernel from the FETCH_SIZE and
-# WRITE_SIZE counter runs (profiles/dalitz_pass_events_grad_1M.md), valid for
-# the kernel sources with this hash; reported as null once they change.
-TRAFFIC_BYTES = 1.644e7
-TRAFFIC_SOURCES = ["paper_1710_08826_amd/csrc/dalitz3.hip", "paper_1710_08826_amd/csrc/fastmath.hpp",
-                   "paper_1710_08826_amd/csrc/device_common.hpp", "paper_1710_08826_amd/csrc/model.hpp"]
-TRAFFIC_HASH = "fc9ca12149e4050f"
+# WRITE_SIZE counter runs (profiles/dalitz_pass_events_grad_1M.md), and its
+# executed FP64 FLOPs per event from SQ_INSTS_VALU_FLOPS_FP64, valid for the
+# kernel sources with this hash; reported as null once they change.
+TRAFFIC_BYTES = 1.620e7
+COUNTED_FP64_FLOPS_PER_EVENT = 598.4
+TRAFFIC_SOURCES = ["paper_1710_08826_amd/csrc/dalitz_device.hpp", "paper_1710_08826_amd/csrc/dalitz3.hip",
+                   "paper_1710_08826_amd/csrc/fastmath.hpp", "paper_1710_08826_amd/csrc/device_common.hpp",
+                   "paper_1710_08826_amd/csrc/model.hpp"]
+TRAFFIC_HASH = "2439cfa01022d04f"
 
 
-def measured_traffic():
+def counters_current() -> bool:
     import hashlib
     h = hashlib.sha256()
     for f in TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    return TRAFFIC_BYTES if h.hexdigest()[:16] == TRAFFIC_HASH else None
+    return h.hexdigest()[:16] == TRAFFIC_HASH
+
+
+def measured_traffic():
+    return TRAFFIC_BYTES if counters_current() else None
 
 # FP64 FLOPs of the correctly rounded gfx950 sequences of the ROCm device
 # library (FMA = 2, other FP64 arithmetic = 1, compares 0), counted from the
@@ -356,6 +363,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--quick", action="store_true", help="skip the side measurements and the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--td4-only", action="store_true",
+                    help="run only the time-dependent four-body leg and print its figures (for profiling)")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="for counter runs: one 256 MiB device copy (calibration) then --steps "
                          "config-1 steps, nothing printed but a summary line")
@@ -366,6 +375,9 @@ def main():
         sys.exit(2)
     if args.pmc_probe:
         pmc_probe(args.steps)
+        return
+    if args.td4_only:
+        print(json.dumps({"config4": td4_leg()}), flush=True)
         return
 
     import torch
@@ -502,8 +514,11 @@ def main():
                    "chunk": m1.chunk, "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(),
-                     "kernel": "dalitz_pass<events, coefficient gradient>",
+                     "kernel": "fn_dal_ev1 (Dalitz events pass, coefficient gradient)",
                      "kernel_us": kern_ms * 1e3, "flops_per_event": flops_ev,
+                     "counted_fp64_flops_per_event": COUNTED_FP64_FLOPS_PER_EVENT if counters_current() else None,
+                     "counted_fp64_tflops": (COUNTED_FP64_FLOPS_PER_EVENT * n1 / (kern_ms * 1e-3) / 1e12
+                                             if counters_current() else None),
                      "hbm_gbs": 16 * n1 / (kern_ms * 1e-3) / 1e9},
         "cpu_baseline": cpu,
         "extra": extra,
