@@ -261,14 +261,14 @@ std::string dalitz_jit_source(const DalitzConst& dc) {
   for (int k = 0; k < dc.K; ++k) o << (k ? ", " : "") << dc.L[k];
   o << "};\n};\n";
   if (!dc.free_ls) {
-    o << "FN_DALITZ_KERNEL(fn_dal_ev0, fn_shape, fn::kEvents, 0)\n"
-         "FN_DALITZ_KERNEL(fn_dal_ev1, fn_shape, fn::kEvents, 1)\n"
-         "FN_DALITZ_KERNEL(fn_dal_mrows, fn_shape, fn::kMRows, 0)\n";
+    o << "FN_DALITZ_KERNEL(fn_dal_ev0, fn_shape, fn::kEvents, 0, 1)\n"
+         "FN_DALITZ_KERNEL(fn_dal_ev1, fn_shape, fn::kEvents, 1, 1)\n"
+         "FN_DALITZ_KERNEL(fn_dal_mrows, fn_shape, fn::kMRows, 0, 1)\n";
   } else {
-    o << "FN_DALITZ_KERNEL(fn_dal_ev0, fn_shape, fn::kEvents, 0)\n"
-         "FN_DALITZ_KERNEL(fn_dal_ev2, fn_shape, fn::kEvents, 2)\n"
-         "FN_DALITZ_KERNEL(fn_dal_gr0, fn_shape, fn::kGrid, 0)\n"
-         "FN_DALITZ_KERNEL(fn_dal_gr2, fn_shape, fn::kGrid, 2)\n";
+    o << "FN_DALITZ_KERNEL(fn_dal_ev0, fn_shape, fn::kEvents, 0, 1)\n"
+         "FN_DALITZ_KERNEL(fn_dal_ev2, fn_shape, fn::kEvents, 2, 1)\n"
+         "FN_DALITZ_KERNEL(fn_dal_gr0, fn_shape, fn::kGrid, 0, 1)\n"
+         "FN_DALITZ_KERNEL(fn_dal_gr2, fn_shape, fn::kGrid, 2, 1)\n";
   }
   return o.str();
 }

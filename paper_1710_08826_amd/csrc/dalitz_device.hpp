@@ -160,24 +160,98 @@ __device__ __forceinline__ void dalitz_pair(const DalitzConst& dc, const double*
   }
 }
 
-// One fixed chunk of events or grid cells -> one row of partial sums.
-// GRAD: 0 none, 1 coefficients only, 2 coefficients + masses and widths.
+// One event or grid cell: its terms added to acc when `valid` (otherwise it
+// contributes exact zeros, so the sum is unchanged).
 template <class S, int MODE, int GRAD>
-__device__ inline void dalitz_chunk(const DalitzConst& dc, const DalitzTable* __restrict__ tab,
-                                    const double* __restrict__ coef0, const double* __restrict__ ev, int64_t ld,
-                                    int64_t n, int64_t chunk_idx,
-                                    int chunk, int i0, double* __restrict__ out_row, double* lds) {
+__device__ __forceinline__ void dalitz_point(const DalitzConst& dc, const double* __restrict__ r,
+                                             const double* __restrict__ coef, double s12, double s13, bool valid,
+                                             int i0, double (&acc)[dal_nv(MODE, GRAD, S::K)]) {
   constexpr int K = S::K;
-  constexpr int NV = dal_nv(MODE, GRAD, K);
   constexpr bool KEEP_A = (GRAD >= 1) || MODE == kMRows;
   constexpr bool KEEP_T = GRAD == 2;
+  const double s23 = dc.msum - s12 - s13;
+  double Are[K], Aim[K], Tre[K], Tim[K], Gk[K];
+  double Sre = 0.0, Sim = 0.0;
+  dalitz_pair<S, 0, MODE, KEEP_A, KEEP_T>(dc, r, coef, s12, s13, s23, Are, Aim, Tre, Tim, Gk, Sre, Sim);
+  dalitz_pair<S, 1, MODE, KEEP_A, KEEP_T>(dc, r, coef, s12, s13, s23, Are, Aim, Tre, Tim, Gk, Sre, Sim);
+  dalitz_pair<S, 2, MODE, KEEP_A, KEEP_T>(dc, r, coef, s12, s13, s23, Are, Aim, Tre, Tim, Gk, Sre, Sim);
+  auto add = [&](int idx, double v) { acc[idx] += valid ? v : 0.0; };
+  if (MODE == kMRows) {
+#pragma unroll
+    for (int ib = 0; ib < kMRowBlock; ++ib) {
+      // A_i for i = i0 + ib, selected from registers with uniform guards
+      double xr = 0.0, xi = 0.0;
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        if (k == i0 + ib) { xr = Are[k]; xi = Aim[k]; }
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        add(2 * (ib * K + j), xr * Are[j] + xi * Aim[j]);
+        add(2 * (ib * K + j) + 1, xi * Are[j] - xr * Aim[j]);
+      }
+    }
+    return;
+  }
+  const double Pt = __builtin_fma(Sre, Sre, Sim * Sim);
+  double w;  // multiplies dP~/dtheta
+  if (MODE == kEvents) {
+    add(0, -log_fast(Pt));
+    if (GRAD >= 1) w = -rcp_nr(Pt);
+  } else {
+    add(0, Pt);
+    w = 1.0;
+  }
+  if (GRAD >= 1) {
+    const double w2 = 2.0 * w;
+    const double ur = w2 * Sre, ui = w2 * Sim;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      // dP~/dRe c = 2 Re(conj(S) A), dP~/dIm c = 2 (Sim Are - Sre Aim)
+      add(1 + 2 * k, ur * Are[k] + ui * Aim[k]);
+      add(2 + 2 * k, ui * Are[k] - ur * Aim[k]);
+    }
+  }
+  if (GRAD == 2) {
+    const double w2 = 2.0 * w;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const double* rk = r + k * kDalFields;
+      const double cr = coef[2 * k], ci = coef[2 * k + 1];
+      // E = conj(S) c A
+      const double car = cr * Are[k] - ci * Aim[k], cai = cr * Aim[k] + ci * Are[k];
+      const double er = Sre * car + Sim * cai, ei = Sre * cai - Sim * car;
+      // dA/dm0 = A (dlnKa - T (2 m0 - i G dKw/dm0));  dP~ = 2 Re(E * (...))
+      const double gd = Gk[k] * rk[dDKW_DM0], tm = rk[dTWOM0];
+      const double xr = tm * Tre[k] + Tim[k] * gd;
+      const double xi = tm * Tim[k] - Tre[k] * gd;
+      const double yr = rk[dDLNKA] - xr, yi = -xi;
+      add(1 + 2 * K + 2 * k, w2 * (er * yr - ei * yi));
+      // dA/dGamma0 = i A T G Kw/Gamma0
+      const double gw = Gk[k] * rk[dKW_W0];
+      add(2 + 2 * K + 2 * k, w2 * gw * (-er * Tim[k] - ei * Tre[k]));
+    }
+  }
+}
+
+// One fixed chunk of events or grid cells -> one row of partial sums.
+// GRAD: 0 none, 1 coefficients only, 2 coefficients + masses and widths.
+// EPT events per thread and loop iteration (independent work for the
+// scheduler to interleave); each thread still adds its points in index order.
+// Two per iteration measured slower than one for the config-1 structure on
+// MI355X (more VGPRs, one wave less per SIMD), so the generated kernels use one.
+template <class S, int MODE, int GRAD, int EPT = 1>
+__device__ inline void dalitz_chunk(const DalitzConst& dc, const DalitzTable* __restrict__ tab,
+                                    const double* __restrict__ coef0, const double* __restrict__ ev, int64_t ld,
+                                    int64_t n, int64_t chunk_idx, int chunk, int i0, double* __restrict__ out_row,
+                                    double* lds) {
+  constexpr int NV = dal_nv(MODE, GRAD, S::K);
   double acc[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) acc[i] = 0.0;
   const int64_t base = chunk_idx * chunk;
   const int64_t end = base + chunk < n ? base + chunk : n;
   const double* const r0 = &tab->r[0][0];
-  for (int64_t i = base + threadIdx.x; i < end; i += kBlock) {
+  for (int64_t i = base + threadIdx.x; i < end; i += EPT * kBlock) {
     // The per-resonance constants are read through the scalar cache on every
     // event: an empty asm makes a zero offset opaque to the loop so that the
     // compiler does not keep the whole table resident in SGPRs, which
@@ -187,77 +261,28 @@ __device__ inline void dalitz_chunk(const DalitzConst& dc, const DalitzTable* __
     asm volatile("" : "+s"(zero));
     const double* r = r0 + zero;
     const double* coef = coef0 + zero;
-    double s12, s13;
-    if (MODE == kEvents) {
-      s12 = ev[i];
-      s13 = ev[ld + i];
-    } else {
-      const int64_t ix = i / dc.ny;
-      const int64_t iy = i - ix * dc.ny;
-      s12 = dc.a12 + (ix + 0.5) * dc.d12;
-      s13 = dc.a13 + (iy + 0.5) * dc.d13;
-      if (!dalitz_inside(dc, s12, s13)) continue;
-    }
-    const double s23 = dc.msum - s12 - s13;
-    double Are[K], Aim[K], Tre[K], Tim[K], Gk[K];
-    double Sre = 0.0, Sim = 0.0;
-    dalitz_pair<S, 0, MODE, KEEP_A, KEEP_T>(dc, r, coef, s12, s13, s23, Are, Aim, Tre, Tim, Gk, Sre, Sim);
-    dalitz_pair<S, 1, MODE, KEEP_A, KEEP_T>(dc, r, coef, s12, s13, s23, Are, Aim, Tre, Tim, Gk, Sre, Sim);
-    dalitz_pair<S, 2, MODE, KEEP_A, KEEP_T>(dc, r, coef, s12, s13, s23, Are, Aim, Tre, Tim, Gk, Sre, Sim);
-    if (MODE == kMRows) {
 #pragma unroll
-      for (int ib = 0; ib < kMRowBlock; ++ib) {
-        // A_i for i = i0 + ib, selected from registers with uniform guards
-        double xr = 0.0, xi = 0.0;
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-          if (k == i0 + ib) { xr = Are[k]; xi = Aim[k]; }
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-          acc[2 * (ib * K + j)] += xr * Are[j] + xi * Aim[j];
-          acc[2 * (ib * K + j) + 1] += xi * Are[j] - xr * Aim[j];
+    for (int e = 0; e < EPT; ++e) {
+      const int64_t j = i + e * kBlock;
+      bool valid = e == 0 || j < end;
+      const int64_t jj = valid ? j : i;  // a valid index; its terms are masked out
+      double s12, s13;
+      if (MODE == kEvents) {
+        s12 = ev[jj];
+        s13 = ev[ld + jj];
+      } else {
+        const int64_t ix = jj / dc.ny;
+        const int64_t iy = jj - ix * dc.ny;
+        s12 = dc.a12 + (ix + 0.5) * dc.d12;
+        s13 = dc.a13 + (iy + 0.5) * dc.d13;
+        const bool inside = dalitz_inside(dc, s12, s13);
+        if (EPT == 1) {
+          if (!inside) continue;
+        } else {
+          valid = valid && inside;
         }
       }
-      continue;
-    }
-    const double Pt = __builtin_fma(Sre, Sre, Sim * Sim);
-    double w;  // multiplies dP~/dtheta
-    if (MODE == kEvents) {
-      acc[0] -= log_fast(Pt);
-      w = -rcp_nr(Pt);
-    } else {
-      acc[0] += Pt;
-      w = 1.0;
-    }
-    if (GRAD >= 1) {
-      const double w2 = 2.0 * w;
-      const double ur = w2 * Sre, ui = w2 * Sim;
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        // dP~/dRe c = 2 Re(conj(S) A), dP~/dIm c = 2 (Sim Are - Sre Aim)
-        acc[1 + 2 * k] += ur * Are[k] + ui * Aim[k];
-        acc[2 + 2 * k] += ui * Are[k] - ur * Aim[k];
-      }
-    }
-    if (GRAD == 2) {
-      const double w2 = 2.0 * w;
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const double* rk = r + k * kDalFields;
-        const double cr = coef[2 * k], ci = coef[2 * k + 1];
-        // E = conj(S) c A
-        const double car = cr * Are[k] - ci * Aim[k], cai = cr * Aim[k] + ci * Are[k];
-        const double er = Sre * car + Sim * cai, ei = Sre * cai - Sim * car;
-        // dA/dm0 = A (dlnKa - T (2 m0 - i G dKw/dm0));  dP~ = 2 Re(E * (...))
-        const double gd = Gk[k] * rk[dDKW_DM0], tm = rk[dTWOM0];
-        const double xr = tm * Tre[k] + Tim[k] * gd;
-        const double xi = tm * Tim[k] - Tre[k] * gd;
-        const double yr = rk[dDLNKA] - xr, yi = -xi;
-        acc[1 + 2 * K + 2 * k] += w2 * (er * yr - ei * yi);
-        // dA/dGamma0 = i A T G Kw/Gamma0
-        const double gw = Gk[k] * rk[dKW_W0];
-        acc[2 + 2 * K + 2 * k] += w2 * gw * (-er * Tim[k] - ei * Tre[k]);
-      }
+      dalitz_point<S, MODE, GRAD>(dc, r, coef, s12, s13, valid, i0, acc);
     }
   }
   block_sum_row<NV>(acc, lds, out_row);
@@ -266,22 +291,23 @@ __device__ inline void dalitz_chunk(const DalitzConst& dc, const DalitzTable* __
 // One workgroup per chunk, one row of NV partial sums each.
 // coef: (Re c_k, Im c_k) of the resonances (theta's first 2K entries, or the
 // table's copy of them); unused by kMRows.
-template <class S, int MODE, int GRAD>
+template <class S, int MODE, int GRAD, int EPT = 1>
 __device__ inline void dalitz_pass_body(const DalitzConst& dc, const DalitzTable* __restrict__ tab,
                                         const double* __restrict__ coef, const double* __restrict__ ev, int64_t ld,
                                         int64_t n, int chunk, int i0, double* __restrict__ part) {
   constexpr int NV = dal_nv(MODE, GRAD, S::K);
   __shared__ double lds[block_sum_lds(NV)];
-  dalitz_chunk<S, MODE, GRAD>(dc, tab, coef, ev, ld, n, blockIdx.x, chunk, i0, part + (int64_t)blockIdx.x * NV,
-                              lds);
+  dalitz_chunk<S, MODE, GRAD, EPT>(dc, tab, coef, ev, ld, n, blockIdx.x, chunk, i0,
+                                   part + (int64_t)blockIdx.x * NV, lds);
 }
 
 }  // namespace fn
 
-// Kernel NAME for shape S, mode and gradient level (used by the generated source).
-#define FN_DALITZ_KERNEL(NAME, S, MODE, GRAD)                                                                \
+// Kernel NAME for shape S, mode, gradient level and events per thread and
+// iteration (used by the generated source).
+#define FN_DALITZ_KERNEL(NAME, S, MODE, GRAD, EPT)                                                           \
   extern "C" __global__ __launch_bounds__(fn::kBlock) void NAME(                                               \
       fn::DalitzConst dc, const fn::DalitzTable* __restrict__ tab, const double* __restrict__ coef,           \
       const double* __restrict__ ev, int64_t ld, int64_t n, int chunk, int i0, double* __restrict__ part) {   \
-    fn::dalitz_pass_body<S, MODE, GRAD>(dc, tab, coef, ev, ld, n, chunk, i0, part);                            \
+    fn::dalitz_pass_body<S, MODE, GRAD, EPT>(dc, tab, coef, ev, ld, n, chunk, i0, part);                       \
   }
