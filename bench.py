@@ -363,8 +363,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--quick", action="store_true", help="skip the side measurements and the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--td4-only", action="store_true",
-                    help="run only the time-dependent four-body leg and print its figures (for profiling)")
+    ap.add_argument("--leg", choices=["td4", "serve"],
+                    help="run only the four-body leg or the serving leg and print its figures (for profiling)")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="for counter runs: one 256 MiB device copy (calibration) then --steps "
                          "config-1 steps, nothing printed but a summary line")
@@ -376,8 +376,11 @@ def main():
     if args.pmc_probe:
         pmc_probe(args.steps)
         return
-    if args.td4_only:
+    if args.leg == "td4":
         print(json.dumps({"config4": td4_leg()}), flush=True)
+        return
+    if args.leg == "serve":
+        print(json.dumps({"config2_serving": serving_leg()}), flush=True)
         return
 
     import torch

@@ -90,15 +90,16 @@ __global__ void gen_mix1d_kernel(uint32_t k0, uint32_t k1, uint32_t word, int64_
 }
 
 // ------------------------------------------------------------------ steps
-__global__ void batch_prologue(Mix1dConst mc, BfgsState* __restrict__ st, int n_fits, Mix1dTable* __restrict__ tabs) {
+__global__ void batch_prologue(Mix1dConst mc, const BfgsState* __restrict__ st, const int* __restrict__ stat,
+                               int n_fits, Mix1dTable* __restrict__ tabs) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= n_fits || st[f].status != kFitRunning) return;
+  if (f >= n_fits || stat[f] != kFitRunning) return;
   mix1d_table(mc, st[f].xt, tabs[f]);
 }
 
 // Single workgroup: item_base[f] = sum of chunk counts of running fits < f;
 // item_base[n_fits] = total; *n_running = number of running fits.
-__global__ __launch_bounds__(kBlock) void batch_scan(const BfgsState* __restrict__ st, const int64_t* __restrict__ nev,
+__global__ __launch_bounds__(kBlock) void batch_scan(const int* __restrict__ stat, const int64_t* __restrict__ nev,
                                                      int n_fits, int chunk, int64_t* __restrict__ item_base,
                                                      int* __restrict__ n_running) {
   __shared__ int64_t sums[kBlock];
@@ -109,7 +110,7 @@ __global__ __launch_bounds__(kBlock) void batch_scan(const BfgsState* __restrict
   int64_t s = 0;
   int c = 0;
   for (int f = f0; f < f1; ++f) {
-    if (st[f].status == kFitRunning) {
+    if (stat[f] == kFitRunning) {
       s += (nev[f] + chunk - 1) / chunk;
       ++c;
     }
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(kBlock) void batch_scan(const BfgsState* __restrict
   int64_t b = sums[t];
   for (int f = f0; f < f1; ++f) {
     item_base[f] = b;
-    if (st[f].status == kFitRunning) b += (nev[f] + chunk - 1) / chunk;
+    if (stat[f] == kFitRunning) b += (nev[f] + chunk - 1) / chunk;
   }
 }
 
@@ -164,7 +165,7 @@ __global__ __launch_bounds__(kBlock) void batch_eval(Mix1dConst mc, const Mix1dT
 }
 
 __global__ __launch_bounds__(kBlock) void batch_finalize(Mix1dConst mc, const Mix1dTable* __restrict__ tabs,
-                                                         const BfgsState* __restrict__ st,
+                                                         const int* __restrict__ stat,
                                                          const int64_t* __restrict__ nev,
                                                          const int64_t* __restrict__ part_base, const double* part,
                                                          int chunk, int nv, int kmax, double* __restrict__ out,
@@ -172,7 +173,7 @@ __global__ __launch_bounds__(kBlock) void batch_finalize(Mix1dConst mc, const Mi
   __shared__ double scratch[kBlock];
   __shared__ double res[kBlock];
   const int f = blockIdx.x;
-  if (st[f].status != kFitRunning) return;
+  if (stat[f] != kFitRunning) return;
   const int64_t rows = (nev[f] + chunk - 1) / chunk;
   mix1d_finalize_one(mc, tabs[f], part + part_base[f] * nv, rows, nv, kmax, 1, out + (int64_t)f * out_stride,
                      nullptr, scratch, res);
@@ -191,17 +192,18 @@ void batch_launch_step(const BatchDev& b, const Mix1dConst& mc, int n_fits, int 
   const int kmax = mix1d_kmax(mc.K);
   const int nv = mix1d_nv(kmax, true);
   const dim3 fg((n_fits + 63) / 64), fb(64);
-  hipLaunchKernelGGL(batch_prologue, fg, fb, 0, s, mc, b.st, n_fits, b.tabs);
-  hipLaunchKernelGGL(batch_scan, dim3(1), dim3(kBlock), 0, s, b.st, b.nev, n_fits, chunk, b.item_base, b.n_running);
+  hipLaunchKernelGGL(batch_prologue, fg, fb, 0, s, mc, b.st, b.stat, n_fits, b.tabs);
+  hipLaunchKernelGGL(batch_scan, dim3(1), dim3(kBlock), 0, s, b.stat, b.nev, n_fits, chunk, b.item_base,
+                     b.n_running);
   if (kmax == 2)
     hipLaunchKernelGGL((batch_eval<true, 2>), dim3(eval_grid), dim3(kBlock), 0, s, mc, b.tabs, b.ev, b.nev,
                        b.item_base, b.part_base, n_fits, chunk, b.part);
   else
     hipLaunchKernelGGL((batch_eval<true, 8>), dim3(eval_grid), dim3(kBlock), 0, s, mc, b.tabs, b.ev, b.nev,
                        b.item_base, b.part_base, n_fits, chunk, b.part);
-  hipLaunchKernelGGL(batch_finalize, dim3(n_fits), dim3(kBlock), 0, s, mc, b.tabs, b.st, b.nev, b.part_base, b.part,
+  hipLaunchKernelGGL(batch_finalize, dim3(n_fits), dim3(kBlock), 0, s, mc, b.tabs, b.stat, b.nev, b.part_base, b.part,
                      chunk, nv, kmax, b.out, 2 + 2 * P);
-  hipLaunchKernelGGL((bfgs_step<kBatchMaxP>), fg, fb, 0, s, b.st, b.out, 2 + 2 * P, n_fits, P, tol, max_iter, b.stat, b.rres);
+  bfgs_launch<kBatchMaxP>(b.st, b.out, 2 + 2 * P, n_fits, P, tol, max_iter, b.stat, b.rres, s);
 }
 
 int batch_eval_blocks_per_cu(const Mix1dConst& mc) {

@@ -185,6 +185,9 @@ fn_status fn_batch_set_slot(fn_batch* b, int32_t slot, const double* ev, int64_t
     b->h_nev[slot] = n;
     hip_check(hipMemcpyAsync((BfgsState*)b->st.ptr + slot, &s, sizeof(BfgsState), hipMemcpyHostToDevice, b->stream),
               "hipMemcpyAsync");
+    // the per-slot status mirror is what the step kernels consult
+    hip_check(hipMemcpyAsync((int*)b->stat.ptr + slot, &s.status, sizeof(int), hipMemcpyHostToDevice, b->stream),
+              "hipMemcpyAsync");
     hip_check(hipMemcpyAsync((const double**)b->evp.ptr + slot, &b->h_ev[slot], sizeof(double*),
                              hipMemcpyHostToDevice, b->stream),
               "hipMemcpyAsync");
@@ -204,6 +207,9 @@ fn_status fn_batch_clear_slot(fn_batch* b, int32_t slot) {
     b->h_st[slot].status = kFitIdle;
     hip_check(hipMemcpyAsync(&((BfgsState*)b->st.ptr)[slot].status, &b->h_st[slot].status, sizeof(int),
                              hipMemcpyHostToDevice, b->stream),
+              "hipMemcpyAsync");
+    hip_check(hipMemcpyAsync((int*)b->stat.ptr + slot, &b->h_st[slot].status, sizeof(int), hipMemcpyHostToDevice,
+                             b->stream),
               "hipMemcpyAsync");
     hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
   });
@@ -301,6 +307,8 @@ void batch_set_slot_async(fn_batch* b, int slot, const double* ev, int64_t n, co
   b->h_ev[slot] = ev;
   b->h_nev[slot] = n;
   hip_check(hipMemcpyAsync((BfgsState*)b->st.ptr + slot, &s, sizeof(BfgsState), hipMemcpyHostToDevice, b->stream),
+            "hipMemcpyAsync");
+  hip_check(hipMemcpyAsync((int*)b->stat.ptr + slot, &s.status, sizeof(int), hipMemcpyHostToDevice, b->stream),
             "hipMemcpyAsync");
   hip_check(hipMemcpyAsync((const double**)b->evp.ptr + slot, &b->h_ev[slot], sizeof(double*), hipMemcpyHostToDevice,
                            b->stream),

@@ -72,15 +72,6 @@ struct fn_vbatch {
   }
 };
 
-namespace fn {
-template <int PM>
-void bfgs_launch(BfgsStateT<PM>* st, const double* out, int out_stride, int n_fits, int P, double tol, int max_iter,
-                 int* stat, double* rres, hipStream_t s) {
-  hipLaunchKernelGGL((bfgs_step<PM>), dim3((n_fits + 63) / 64), dim3(64), 0, s, st, out, out_stride, n_fits, P, tol,
-                     max_iter, stat, rres);
-}
-}  // namespace fn
-
 namespace {
 
 // The caller's stream must have produced the events: order the batch stream after it.
