@@ -177,12 +177,16 @@ fn_status fn_model_set_norm_sample(fn_model* m, const double* mc_dev, int64_t n_
  * values from the description. */
 fn_status fn_model_fixed(const fn_model* m, int32_t* n_fixed, double* fixed_host);
 
-/* Kernel timing (measurement support, not on the result path).  With timing
- * enabled, every per-event evaluation launch of the model is bracketed by HIP
- * events recorded on the launch stream.  fn_model_kernel_time waits for the
- * recorded events, returns the summed duration in milliseconds and the launch
- * count since the last query, and resets both. */
-fn_status fn_model_timing(fn_model* m, int32_t enable);
+/* Kernel timing (measurement support, not on the result path).  With
+ * every = k >= 1, the 1st, (k+1)-th, (2k+1)-th ... per-event evaluation launch
+ * of the model from this call on is bracketed by HIP events recorded on the
+ * launch stream (k = 1: every launch; the events themselves add a few
+ * microseconds of device time to the launches they bracket, so a large k keeps
+ * a timed loop close to an untimed one); every = 0 turns timing off.
+ * FN_E_INVALID if every < 0.  fn_model_kernel_time waits for the recorded
+ * events, returns the summed duration in milliseconds and the number of timed
+ * launches since the last query, and resets both. */
+fn_status fn_model_timing(fn_model* m, int32_t every);
 fn_status fn_model_kernel_time(fn_model* m, double* total_ms, int64_t* launches);
 
 /* ---------------------------------------------------------------- fitting */

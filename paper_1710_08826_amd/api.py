@@ -152,9 +152,9 @@ class Model:
         check(self._lib.fn_model_fixed(self._h, None, v.ctypes.data_as(C.POINTER(C.c_double))))
         return v
 
-    def set_timing(self, enable: bool):
-        """Bracket every per-event kernel launch with HIP events."""
-        check(self._lib.fn_model_timing(self._h, 1 if enable else 0))
+    def set_timing(self, enable: bool, every: int = 1):
+        """Bracket every `every`-th per-event kernel launch with HIP events."""
+        check(self._lib.fn_model_timing(self._h, every if enable else 0))
 
     def kernel_time(self):
         """(total ms, launches) of timed per-event kernels since the last query."""

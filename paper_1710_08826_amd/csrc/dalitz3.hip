@@ -86,8 +86,10 @@ struct DalFinalLds {
   double nres[kBlock];
   double cre[kDalMaxRes], cim[kDalMaxRes], ipart[kDalMaxRes];
   double dI[4 * kDalMaxRes];
+  double M[2 * kDalMaxRes * kDalMaxRes];
   double I;
 };
+static_assert(2 * kDalMaxRes * kDalMaxRes <= kFinalBlock, "one entry of M per thread");
 
 // Level-2 over the event rows and the normalization (grid rows or cached M),
 // then NLL = -sum ln P~ + N ln I and its gradient, one thread per entry.
@@ -97,12 +99,13 @@ __device__ void dalitz_finalize_body(const DalitzConst& dc, const DalitzTable* _
   const int K = dc.K;
   const int P = dc.free_ls ? 4 * K : 2 * K;
   const int t = threadIdx.x;
+  // the small inputs are loaded first: their latency overlaps the row sums
+  const double mv = !f.npart && t < 2 * K * K ? f.Mc[t] : 0.0;
+  const double cv = t < 2 * K ? f.coef[t] : 0.0;
   sum_rows_t<kFinalBlock>(evpart, ev_rows, ev_nv, L.scratch, L.res);
   if (f.npart) sum_rows_t<kFinalBlock>(f.npart, f.n_rows, f.n_nv, L.scratch, L.nres);
-  if (t < K) {
-    L.cre[t] = f.coef[2 * t];
-    L.cim[t] = f.coef[2 * t + 1];
-  }
+  if (t < 2 * K * K) L.M[t] = mv;
+  if (t < 2 * K) (t & 1 ? L.cim : L.cre)[t >> 1] = cv;
   if (t < P) L.dI[t] = 0.0;
   __syncthreads();
   if (f.npart) {
@@ -120,7 +123,7 @@ __device__ void dalitz_finalize_body(const DalitzConst& dc, const DalitzTable* _
     // dI/dRe c_k = 2 Re X_k, dI/dIm c_k = -2 Im X_k
     double xr = 0.0, xi = 0.0;
     for (int j = 0; j < K; ++j) {
-      const double mr = f.Mc[2 * (t * K + j)], mi = f.Mc[2 * (t * K + j) + 1];
+      const double mr = L.M[2 * (t * K + j)], mi = L.M[2 * (t * K + j) + 1];
       xr += mr * L.cre[j] + mi * L.cim[j];
       xi += mi * L.cre[j] - mr * L.cim[j];
     }

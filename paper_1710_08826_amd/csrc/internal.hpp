@@ -65,10 +65,13 @@ struct fn_model {
   fn::DevBuf d_table, d_part, d_npart, d_out, d_fixed, d_M, d_count, d_mc;
   double* h_out = nullptr;       // pinned
   long long stats_calls = 0;
-  bool timing = false;           // bracket event-pass launches with HIP events
+  int timing = 0;                // bracket every timing-th event-pass launch with HIP events (0 = off)
+  int64_t timing_count = 0;
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
   hipEvent_t take_event();
+  // Whether this event-pass launch is one of the timed ones.
+  bool timed_launch() { return timing > 0 && timing_count++ % timing == 0; }
 
   fn::Mix1dTable* table_mix() { return (fn::Mix1dTable*)d_table.ptr; }
   fn::DalitzTable* table_dal() { return (fn::DalitzTable*)d_table.ptr; }

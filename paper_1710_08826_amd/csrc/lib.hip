@@ -309,7 +309,7 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
     ParamBlock zero;
     mix1d_launch_prologue(mc, pb ? *pb : zero, pb ? nullptr : theta_dev, 1, 0, m->table_mix(), s);
     hipEvent_t t0 = nullptr, t1 = nullptr;
-    if (m->timing && nch > 0) {
+    if (nch > 0 && m->timed_launch()) {
       t0 = m->take_event();
       t1 = m->take_event();
       hip_check(hipEventRecord(t0, s), "hipEventRecord");
@@ -337,7 +337,7 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
       m->M_valid = true;
     }
     hipEvent_t t0 = nullptr, t1 = nullptr;
-    if (m->timing && nch > 0) {
+    if (nch > 0 && m->timed_launch()) {
       t0 = m->take_event();
       t1 = m->take_event();
       hip_check(hipEventRecord(t0, s), "hipEventRecord");
@@ -386,7 +386,7 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
       m->M_valid = true;
     }
     hipEvent_t t0 = nullptr, t1 = nullptr;
-    if (m->timing && nch > 0) {
+    if (nch > 0 && m->timed_launch()) {
       t0 = m->take_event();
       t1 = m->take_event();
       hip_check(hipEventRecord(t0, s), "hipEventRecord");
@@ -666,10 +666,12 @@ fn_status fn_model_fixed(const fn_model* m, int32_t* n_fixed, double* fixed_host
   });
 }
 
-fn_status fn_model_timing(fn_model* m, int32_t enable) {
+fn_status fn_model_timing(fn_model* m, int32_t every) {
   return guard([&] {
     if (!m) throw Error(FN_E_INVALID, "model is NULL");
-    m->timing = enable != 0;
+    if (every < 0) throw Error(FN_E_INVALID, "every must be >= 0");
+    m->timing = every;
+    m->timing_count = 0;
   });
 }
 

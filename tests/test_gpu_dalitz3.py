@@ -121,6 +121,44 @@ def test_bitwise_repeatable(m3):
         assert v == ref[0] and np.array_equal(g, ref[1])
 
 
+def test_back_to_back_async_evaluations(m1):
+    """Evaluations queued without waiting, alternating parameters, sample
+    sizes (so numbers of partial-sum rows) and gradient level, each equal
+    bitwise to the same evaluation run on its own."""
+    say("dalitz back-to-back async")
+    sizes = [100_000, 3 * 2048 + 17, 1, 50_000]
+    evs = [to_dev(synth.dalitz_events(n, seed=40 + i)) for i, n in enumerate(sizes)]
+    ths = [torch.from_numpy(th).cuda() for th in (TH1, offset(TH1))]
+    P = m1.n_params
+    ref = {}
+    for e in range(len(evs)):
+        for t in range(2):
+            for g in (True, False):
+                out = torch.empty(1 + P, dtype=torch.float64, device="cuda")
+                m1.nll_async(ths[t], evs[e], out, g)
+                torch.cuda.synchronize()
+                ref[e, t, g] = out.cpu().numpy()
+    plan = [(i % len(evs), (i // 2) % 2, i % 3 != 0) for i in range(48)]
+    outs = torch.empty(len(plan), 1 + P, dtype=torch.float64, device="cuda")
+    for i, (e, t, g) in enumerate(plan):
+        m1.nll_async(ths[t], evs[e], outs[i], g)
+    torch.cuda.synchronize()
+    got = outs.cpu().numpy()
+    for i, (e, t, g) in enumerate(plan):
+        k = 1 + P if g else 1
+        assert np.array_equal(got[i, :k], ref[e, t, g][:k]), (i, e, t, g)
+
+
+def test_empty_sample(m1, m3):
+    """No events: NLL = 0 and, for free lineshapes too, a zero gradient
+    (N ln I and N dI/I vanish); the level-2 step still runs on its own."""
+    say("dalitz empty sample")
+    empty = torch.zeros((2, 0), dtype=torch.float64, device="cuda")
+    for m, th in ((m1, TH1), (m3, offset(TH3))):
+        v, g = m.nll(th, empty, grad=True)
+        assert v == 0.0 and not np.any(g), (v, g)
+
+
 def test_events_check(m1):
     ev = synth.dalitz_events(3000, seed=37)
     assert m1.check_events(to_dev(ev)) == 0
