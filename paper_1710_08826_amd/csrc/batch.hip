@@ -60,14 +60,11 @@ __device__ __forceinline__ void philox_uniforms(uint64_t i, uint32_t stream, uin
 // mu, sigma, tau, f): component by a uniform draw, Gaussian by Box-Muller with
 // redraws outside the range, exponential by the inverse CDF of the truncated
 // exponential.  Event i, attempt a uses counters (i, 2a, word) and (i, 2a+1, word).
-__global__ void gen_mix1d_kernel(uint32_t k0, uint32_t k1, uint32_t word, int64_t n, double mu, double sigma,
-                                 double tau, double frac, double lo, double hi, double* __restrict__ x,
-                                 unsigned int* __restrict__ n_unresolved) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// NaN when no attempt lands in the range.
+__device__ __forceinline__ double gen_mix1d_event(int64_t i, uint32_t k0, uint32_t k1, uint32_t word, double mu,
+                                                  double sigma, double tau, double frac, double lo, double hi) {
   const double width = hi - lo;
   const double em = tau != 0.0 ? expm1(tau * width) : 0.0;
-  double v = NAN;
   for (int a = 0; a < kGenMaxAttempts; ++a) {
     double uc, u1, u2, unused;
     philox_uniforms((uint64_t)i, 2u * a, word, k0, k1, uc, u1);
@@ -80,13 +77,74 @@ __global__ void gen_mix1d_kernel(uint32_t k0, uint32_t k1, uint32_t word, int64_
       t = tau != 0.0 ? lo + log1p(u1 * em) / tau : lo + u1 * width;
       t = fmin(fmax(t, lo), hi);
     }
-    if (t >= lo && t <= hi) {
-      v = t;
-      break;
-    }
+    if (t >= lo && t <= hi) return t;
   }
+  return NAN;
+}
+
+__global__ void gen_mix1d_kernel(uint32_t k0, uint32_t k1, uint32_t word, int64_t n, double mu, double sigma,
+                                 double tau, double frac, double lo, double hi, double* __restrict__ x,
+                                 unsigned int* __restrict__ n_unresolved) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = gen_mix1d_event(i, k0, k1, word, mu, sigma, tau, frac, lo, hi);
   x[i] = v;
   if (v != v) atomicAdd(n_unresolved, 1u);
+}
+
+// ------------------------------------------------------------- admission
+static_assert(sizeof(BfgsState) % sizeof(uint64_t) == 0, "state is cleared in 8-byte words");
+
+__global__ __launch_bounds__(kBlock) void batch_admit(const AdmitRec* __restrict__ recs, int n_recs, int P,
+                                                      double lo, double hi, BatchDev b,
+                                                      unsigned int* __restrict__ n_unresolved) {
+  const int64_t blk = blockIdx.x;
+  if (blk < n_recs) {
+    // a fresh fit: every field zero but the start point, the free mask, status and phase
+    const AdmitRec& r = recs[blk];
+    uint64_t* w = reinterpret_cast<uint64_t*>(b.st + r.slot);
+    constexpr int kWords = (int)(sizeof(BfgsState) / sizeof(uint64_t));
+    for (int i = threadIdx.x; i < kWords; i += blockDim.x) w[i] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      BfgsState& st = b.st[r.slot];
+      for (int i = 0; i < P; ++i) {
+        st.xt[i] = r.theta0[i];
+        st.mask[i] = 1;
+      }
+      st.status = kFitRunning;
+      st.phase = kPhaseStart;
+      b.stat[r.slot] = kFitRunning;
+      b.ev[r.slot] = r.ev;
+      b.nev[r.slot] = r.n;
+    }
+    return;
+  }
+  // generation workgroup g: the last record with block0 <= g owns it (records
+  // without generation own no workgroups, so a later record with the same
+  // block0 is the owner)
+  const int64_t g = blk - n_recs;
+  int a = 0, c = n_recs - 1;
+  while (a < c) {
+    const int mid = (a + c + 1) / 2;
+    if (recs[mid].block0 <= g) a = mid;
+    else c = mid - 1;
+  }
+  const AdmitRec& r = recs[a];
+  const int64_t i = (g - r.block0) * kBlock + threadIdx.x;
+  if (!r.generate || i >= r.n) return;
+  const double v = gen_mix1d_event(i, r.seed, r.fit, 0u, r.theta_gen[0], r.theta_gen[1], r.theta_gen[2],
+                                   r.theta_gen[3], lo, hi);
+  r.ev[i] = v;
+  if (v != v) atomicAdd(n_unresolved, 1u);
+}
+
+__global__ void batch_gather_rows(const double* __restrict__ rres, const int* __restrict__ slots, int n, int w,
+                                  double* __restrict__ rows) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * w) return;
+  const int i = (int)(t / w), j = (int)(t - (int64_t)i * w);
+  rows[t] = rres[(int64_t)slots[i] * w + j];
 }
 
 // ------------------------------------------------------------------ steps
@@ -185,6 +243,21 @@ void batch_launch_gen_mix1d(uint32_t k0, uint32_t k1, uint32_t word, int64_t n, 
   if (n == 0) return;
   hipLaunchKernelGGL(gen_mix1d_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, k0, k1, word, n,
                      theta_gen[0], theta_gen[1], theta_gen[2], theta_gen[3], lo, hi, x, n_unresolved);
+}
+
+void batch_launch_admit(const BatchDev& b, const AdmitRec* recs, int n_recs, int64_t gen_blocks, int P, double lo,
+                        double hi, unsigned int* n_unresolved, hipStream_t s) {
+  if (n_recs == 0) return;
+  hipLaunchKernelGGL(batch_admit, dim3((unsigned)(n_recs + gen_blocks)), dim3(kBlock), 0, s, recs, n_recs, P, lo, hi,
+                     b, n_unresolved);
+}
+
+void batch_launch_gather_rows(const BatchDev& b, const int* slots, int n, int P, double* rows_out, hipStream_t s) {
+  if (n == 0) return;
+  const int w = 3 + 2 * P;
+  const int64_t total = (int64_t)n * w;
+  hipLaunchKernelGGL(batch_gather_rows, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, b.rres, slots, n, w,
+                     rows_out);
 }
 
 void batch_launch_step(const BatchDev& b, const Mix1dConst& mc, int n_fits, int P, int chunk, int eval_grid,

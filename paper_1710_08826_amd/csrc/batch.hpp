@@ -26,6 +26,30 @@ struct BatchDev {
   double* rres;            // per slot result row, written when the fit retires (3 + 2P)
 };
 
+// One request admitted into a slot (host staging, copied to the device once
+// per admission round).  generate = 1: the slot's events are generated into ev
+// by the admission launch (the mix1d toy generator, key (seed, fit), word 0).
+struct AdmitRec {
+  int32_t slot;
+  int32_t generate;
+  int64_t n;                   // events
+  double* ev;                  // device events of the slot
+  int64_t block0;              // first generation workgroup of this record in the launch
+  uint32_t seed, fit;
+  double theta_gen[4];         // mu, sigma, tau, f
+  double theta0[kBatchMaxP];   // start point
+};
+
+// Admission of n_recs records (device copy): one workgroup per record resets
+// its slot's minimizer state to a fresh fit at theta0 (all free) and sets the
+// slot's status mirror and event pointer/count; gen_blocks more workgroups
+// generate the events of the records with generate = 1 (record r owns
+// workgroups [block0, block0 + ceil(n/256)), block0 ascending).
+void batch_launch_admit(const BatchDev& b, const AdmitRec* recs, int n_recs, int64_t gen_blocks, int P, double lo,
+                        double hi, unsigned int* n_unresolved, hipStream_t s);
+// rows_out[i] = rres row of slot slots[i] (3 + 2P doubles), for n slots.
+void batch_launch_gather_rows(const BatchDev& b, const int* slots, int n, int P, double* rows_out, hipStream_t s);
+
 void batch_launch_step(const BatchDev& b, const Mix1dConst& mc, int n_fits, int P, int chunk, int eval_grid,
                        double tol, int max_iter, hipStream_t s);
 int batch_eval_blocks_per_cu(const Mix1dConst& mc);

@@ -24,11 +24,13 @@ struct fn_batch {
   hipStream_t stream = nullptr;
   hipGraphExec_t exec = nullptr;
   DevBuf st, tabs, evp, nev, item_base, part_base, part, out, nrun, stat, rres;
+  DevBuf adm, fin_slots, fin_rows;  // serving: admission records, finished-slot list and gathered rows
   // pinned staging of per-slot inputs (stable sources for async copies)
   BfgsState* h_st = nullptr;
   const double** h_ev = nullptr;
   int64_t* h_nev = nullptr;
   int* h_nrun = nullptr;
+  int* h_fin = nullptr;  // finished-slot list staging
   BatchDev dev() {
     BatchDev d;
     d.st = (BfgsState*)st.ptr;
@@ -55,6 +57,7 @@ struct fn_batch {
     if (h_ev) (void)hipHostFree(h_ev);
     if (h_nev) (void)hipHostFree(h_nev);
     if (h_nrun) (void)hipHostFree(h_nrun);
+    if (h_fin) (void)hipHostFree(h_fin);
   }
 };
 
@@ -122,6 +125,7 @@ fn_status fn_batch_create(fn_model* m, int32_t max_fits, int64_t max_events_per_
     b->h_ev = (const double**)pinned(sizeof(double*) * max_fits);
     b->h_nev = (int64_t*)pinned(sizeof(int64_t) * max_fits);
     b->h_nrun = (int*)pinned(sizeof(int));
+    b->h_fin = (int*)pinned(sizeof(int) * max_fits);
     std::vector<int64_t> pb(max_fits);
     for (int f = 0; f < max_fits; ++f) pb[f] = (int64_t)f * b->rows_per_slot;
     // all slots idle, no events
@@ -293,29 +297,18 @@ hipStream_t batch_stream(fn_batch* b) { return b->stream; }
 int batch_params(fn_batch* b) { return b->P; }
 int batch_slots(fn_batch* b) { return b->max_fits; }
 
-// Enqueue a fit into a slot without waiting: the staging entry of this slot
-// is only rewritten after the caller has synchronised the batch stream.
-void batch_set_slot_async(fn_batch* b, int slot, const double* ev, int64_t n, const double* theta0) {
-  BfgsState& s = b->h_st[slot];
-  std::memset(&s, 0, sizeof(s));
-  for (int i = 0; i < b->P; ++i) {
-    s.xt[i] = theta0[i];
-    s.mask[i] = 1;
-  }
-  s.status = kFitRunning;
-  s.phase = kPhaseStart;
-  b->h_ev[slot] = ev;
-  b->h_nev[slot] = n;
-  hip_check(hipMemcpyAsync((BfgsState*)b->st.ptr + slot, &s, sizeof(BfgsState), hipMemcpyHostToDevice, b->stream),
+// Admit n records (staging entries in pinned host memory, left untouched
+// until the caller has synchronised the batch stream) in one copy and one
+// launch.
+void batch_admit_async(fn_batch* b, const AdmitRec* recs_host, int n, int64_t gen_blocks, double lo, double hi,
+                       unsigned int* n_unresolved) {
+  if (n == 0) return;
+  if (n > b->max_fits) throw Error(FN_E_INVALID, "more admissions than slots");
+  b->adm.reserve(sizeof(AdmitRec) * (size_t)b->max_fits);
+  hip_check(hipMemcpyAsync(b->adm.ptr, recs_host, sizeof(AdmitRec) * n, hipMemcpyHostToDevice, b->stream),
             "hipMemcpyAsync");
-  hip_check(hipMemcpyAsync((int*)b->stat.ptr + slot, &s.status, sizeof(int), hipMemcpyHostToDevice, b->stream),
-            "hipMemcpyAsync");
-  hip_check(hipMemcpyAsync((const double**)b->evp.ptr + slot, &b->h_ev[slot], sizeof(double*), hipMemcpyHostToDevice,
-                           b->stream),
-            "hipMemcpyAsync");
-  hip_check(hipMemcpyAsync((int64_t*)b->nev.ptr + slot, &b->h_nev[slot], sizeof(int64_t), hipMemcpyHostToDevice,
-                           b->stream),
-            "hipMemcpyAsync");
+  batch_launch_admit(b->dev(), (const AdmitRec*)b->adm.ptr, n, gen_blocks, b->P, lo, hi, n_unresolved, b->stream);
+  hip_check(hipGetLastError(), "kernel launch");
 }
 
 void batch_steps(fn_batch* b, int k) {
@@ -329,13 +322,28 @@ void batch_poll(fn_batch* b, int* stat_host) {
   hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
 }
 
-// Copy the result rows (3 + 2P doubles) of the given slots and wait.
+// Copy the result rows (3 + 2P doubles) of the given slots and wait: a few
+// rows by one copy each, more by one gather launch and one copy.
 void batch_read_rows(fn_batch* b, const int* slots, int n, double* rows_host) {
   const int w = 3 + 2 * b->P;
-  for (int i = 0; i < n; ++i)
-    hip_check(hipMemcpyAsync(rows_host + (size_t)i * w, (double*)b->rres.ptr + (size_t)slots[i] * w,
-                             sizeof(double) * w, hipMemcpyDeviceToHost, b->stream),
+  if (n <= 2) {
+    for (int i = 0; i < n; ++i)
+      hip_check(hipMemcpyAsync(rows_host + (size_t)i * w, (double*)b->rres.ptr + (size_t)slots[i] * w,
+                               sizeof(double) * w, hipMemcpyDeviceToHost, b->stream),
+                "hipMemcpyAsync");
+  } else {
+    if (n > b->max_fits) throw Error(FN_E_INVALID, "more rows than slots");
+    b->fin_slots.reserve(sizeof(int) * (size_t)b->max_fits);
+    b->fin_rows.reserve(sizeof(double) * (size_t)b->max_fits * w);
+    std::memcpy(b->h_fin, slots, sizeof(int) * n);
+    hip_check(hipMemcpyAsync(b->fin_slots.ptr, b->h_fin, sizeof(int) * n, hipMemcpyHostToDevice, b->stream),
               "hipMemcpyAsync");
+    batch_launch_gather_rows(b->dev(), (const int*)b->fin_slots.ptr, n, b->P, (double*)b->fin_rows.ptr, b->stream);
+    hip_check(hipGetLastError(), "kernel launch");
+    hip_check(hipMemcpyAsync(rows_host, b->fin_rows.ptr, sizeof(double) * (size_t)n * w, hipMemcpyDeviceToHost,
+                             b->stream),
+              "hipMemcpyAsync");
+  }
   hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
 }
 

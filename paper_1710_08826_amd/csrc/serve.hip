@@ -88,14 +88,17 @@ struct fn_server {
   DevBuf gen_count;
   std::vector<Pending> queue;           // submitted, not yet admitted
   std::vector<int> slot_req;            // slot -> index into running, -1 free
+  std::vector<int> free_slots;          // stack of free slots
   std::vector<Pending> running;         // by slot
   std::vector<fn_result> done;
   int* h_stat = nullptr;
   double* h_rows = nullptr;
+  AdmitRec* h_adm = nullptr;            // admission records of one round (pinned)
   ~fn_server() {
     if (b) fn_batch_destroy(b);
     if (h_stat) (void)hipHostFree(h_stat);
     if (h_rows) (void)hipHostFree(h_rows);
+    if (h_adm) (void)hipHostFree(h_adm);
   }
 };
 
@@ -119,10 +122,12 @@ fn_status fn_server_create(fn_model* m, int32_t max_slots, int64_t max_events_pe
     s->arena.reset(budget_bytes);
     s->gen_count.reserve(sizeof(unsigned int));
     s->slot_req.assign(max_slots, -1);
+    for (int k = max_slots - 1; k >= 0; --k) s->free_slots.push_back(k);  // lowest slot on top
     s->running.resize(max_slots);
     if (hipHostMalloc((void**)&s->h_stat, sizeof(int) * max_slots, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&s->h_rows, sizeof(double) * max_slots * (3 + 2 * s->P), hipHostMallocDefault) !=
-            hipSuccess)
+            hipSuccess ||
+        hipHostMalloc((void**)&s->h_adm, sizeof(AdmitRec) * max_slots, hipHostMallocDefault) != hipSuccess)
       throw Error(FN_E_NOMEM, "hipHostMalloc failed");
     *out = s;
   });
@@ -156,7 +161,6 @@ fn_status fn_server_run(fn_server* s, int32_t poll_every, double max_seconds, in
     if (poll_every < 1) poll_every = 1;
     const Mix1dConst& mc = s->m->mix;
     const bool can_generate = mc.K == 2 && mc.type[0] == kGauss && mc.type[1] == kExp;
-    hipStream_t st = batch_stream(s->b);
     const auto t0 = std::chrono::steady_clock::now();
     auto now = [&] { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
     const int W = 3 + 2 * s->P;
@@ -166,8 +170,11 @@ fn_status fn_server_run(fn_server* s, int32_t poll_every, double max_seconds, in
     while (true) {
       const double t = now();
       if (max_seconds > 0.0 && t > max_seconds) break;
-      // admission: arrivals visible now, free slot, budget
-      bool admitted = false;
+      // admission: arrivals visible now, free slot, budget; the round's
+      // records go to the device in one copy and one launch (state reset,
+      // status, event pointers, event generation)
+      int n_adm = 0;
+      int64_t gen_blocks = 0;
       while (next < s->queue.size() && s->queue[next].r.arrival_s <= t) {
         Pending& p = s->queue[next];
         if (p.bytes > s->budget) {
@@ -181,32 +188,35 @@ fn_status fn_server_run(fn_server* s, int32_t poll_every, double max_seconds, in
           ++next;
           continue;
         }
-        int slot = -1;
-        for (int k = 0; k < s->slots; ++k)
-          if (s->slot_req[k] < 0) {
-            slot = k;
-            break;
-          }
-        if (slot < 0) break;
+        if (s->free_slots.empty()) break;
+        const int slot = s->free_slots.back();
         const double* ev = p.r.events;
-        if (!ev) {
+        const bool gen = ev == nullptr;
+        if (gen) {
           if (!can_generate) throw Error(FN_E_INVALID, "generation needs a (gauss, exp) mixture model");
           p.off = s->arena.alloc(p.bytes);
           if (p.off < 0) break;  // wait for memory to free up
-          double* x = (double*)((char*)s->arena_mem.ptr + p.off);
-          batch_launch_gen_mix1d(p.r.seed, p.r.fit, 0u, p.r.n_events, p.r.theta_gen, mc.lo, mc.hi, x,
-                                 (unsigned int*)s->gen_count.ptr, st);
-          ev = x;
+          ev = (const double*)((char*)s->arena_mem.ptr + p.off);
         }
+        s->free_slots.pop_back();
+        AdmitRec& a = s->h_adm[n_adm++];
+        a.slot = slot;
+        a.generate = gen ? 1 : 0;
+        a.n = p.r.n_events;
+        a.ev = const_cast<double*>(ev);
+        a.block0 = gen_blocks;
+        a.seed = p.r.seed;
+        a.fit = p.r.fit;
+        for (int j = 0; j < 4; ++j) a.theta_gen[j] = p.r.theta_gen[j];
+        for (int j = 0; j < kBatchMaxP; ++j) a.theta0[j] = j < s->P ? p.r.theta0[j] : 0.0;
+        if (gen) gen_blocks += (p.r.n_events + kBlock - 1) / kBlock;
         p.t_admit = t;
-        batch_set_slot_async(s->b, slot, ev, p.r.n_events, p.r.theta0);
         s->running[slot] = p;
         s->slot_req[slot] = 1;
         ++n_running;
         ++next;
-        admitted = true;
       }
-      if (admitted) hip_check(hipGetLastError(), "kernel launch");
+      batch_admit_async(s->b, s->h_adm, n_adm, gen_blocks, mc.lo, mc.hi, (unsigned int*)s->gen_count.ptr);
       if (n_running == 0) {
         if (next >= s->queue.size()) break;
         // idle until the next arrival
@@ -244,6 +254,7 @@ fn_status fn_server_run(fn_server* s, int32_t poll_every, double max_seconds, in
           s->done.push_back(r);
           if (p.off >= 0) s->arena.release(p.off, p.bytes);
           s->slot_req[k] = -1;
+          s->free_slots.push_back(k);
           --n_running;
         }
       }
