@@ -441,6 +441,15 @@ def main():
         extra["config1_adjoint_vs_plain_fd"] = value / (n1 / fd_dt)
         extra["config1_nll_only_kernel_us"] = k0 * 1e3
         print(f"[bench] plain FD gradient {n1 / fd_dt:.4g} events/s", file=sys.stderr, flush=True)
+        # device toy generation of 1M config-1 events (accept-reject on the model density)
+        _, wgen = m1.generate(th1, 1000, seed=7)
+        m1.generate(th1, n1, seed=7, envelope=wgen)
+        t0 = time.perf_counter()
+        for r in range(3):
+            m1.generate(th1, n1, seed=8 + r, envelope=wgen)
+        extra["config1_generate_events_per_s"] = 3 * n1 / (time.perf_counter() - t0)
+        print(f"[bench] device generation {extra['config1_generate_events_per_s']:.4g} events/s",
+              file=sys.stderr, flush=True)
 
         # config 3: masses and widths free (32 parameters), 4M events, full grid every call
         desc3 = synth.dalitz_desc(free_lineshapes=True)

@@ -41,6 +41,12 @@ region area against 1-D quadrature of the s23 limits; the grid I against 2-D
 adaptive quadrature; invariance of the NLL under a complex rescaling of all
 coefficients (and the two gradient identities it implies); invariance under
 relabelling daughters 2 and 3; autograd against central differences.
+
+Toy generation (`generate`, the paper's Monte Carlo generation for toy
+studies, Sec. 5): accept-reject on the kinematic box with counter-based
+uniforms per event and attempt.  Pins: sample moments against quadrature of
+P~, every event in the region, the per-event (prefix) property, a too-low
+envelope reported.
 """
 from __future__ import annotations
 
@@ -264,35 +270,58 @@ RESONANCES = (
 )
 
 
-def generate(n: int, theta, desc: dict, seed: int, fit: int = 0):
-    """Accept-reject sample from P~ (tests only; uses the oracle density).
+GEN_ENVELOPE_FACTOR = 1.2  # automatic envelope: this factor x the grid maximum
+GEN_MAX_ATTEMPTS = 4096    # attempts per event before it is left unresolved (NaN)
 
-    Uniform proposals in the bounding box, kept inside the region, accepted
-    with probability P~/(1.05 max P~), max from the grid centres.
-    """
+
+def envelope(theta, desc: dict, cells=None) -> float:
+    """Automatic accept-reject envelope: 1.2 x the largest P~ over the centres
+    of the integration-grid cells inside the region."""
+    model = Dalitz(desc)
+    c12, c13, _ = cells if cells is not None else model.grid_cells()
+    with torch.no_grad():
+        return GEN_ENVELOPE_FACTOR * float(model.density_unnorm(as_t(theta), as_t(c12), as_t(c13)).max())
+
+
+def generate(theta, desc: dict, n: int, seed: int, fit: int = 0, W: float | None = None):
+    """Toy events (2, n) distributed as P~ by accept-reject, event by event.
+
+    Event i, attempt a takes (u1, u2) from Philox counter (i, 2a, word 1) and
+    u3 from (i, 2a + 1, word 1) under key (seed, fit).  The candidate
+    s12 = lo12 + u1 (hi12 - lo12), s13 = lo13 + u2 (hi13 - lo13) on the
+    kinematic box (bounds as products, (m1 + m2)(m1 + m2) and so on) is kept
+    when it lies in the region and u3 W < P~; an event not kept within
+    GEN_MAX_ATTEMPTS attempts stays NaN.  W defaults to `envelope`.
+    Returns (events, W, number of kept events whose P~ exceeds W)."""
     from synth.philox import key_from_seed, uniforms_at
     model = Dalitz(desc)
-    (a12, b12), (a13, b13) = model.box()
-    c12, c13, _ = model.grid_cells()
-    with torch.no_grad():
-        pmax = 1.05 * float(model.density_unnorm(as_t(theta), as_t(c12), as_t(c13)).max())
+    M, m = model.M, model.m
+    lo12, hi12 = (m[1] + m[2]) * (m[1] + m[2]), (M - m[3]) * (M - m[3])
+    lo13, hi13 = (m[1] + m[3]) * (m[1] + m[3]), (M - m[2]) * (M - m[2])
+    if W is None:
+        W = envelope(theta, desc)
     key = key_from_seed(seed, fit)
-    out12, out13 = [], []
-    got = 0
-    batch = 0
-    while got < n:
-        idx = np.arange(batch * 4 * n, (batch + 1) * 4 * n, dtype=np.uint64)
-        u1, u2 = uniforms_at(idx, key, 11, 0)
-        u3, _ = uniforms_at(idx, key, 12, 0)
-        s12 = a12 + u1 * (b12 - a12)
-        s13 = a13 + u2 * (b13 - a13)
+    out = np.full((2, n), np.nan)
+    todo = np.arange(n, dtype=np.uint64)
+    above = 0
+    th = as_t(theta)
+    for a in range(GEN_MAX_ATTEMPTS):
+        if todo.size == 0:
+            break
+        u1, u2 = uniforms_at(todo, key, 2 * a, 1)
+        u3, _ = uniforms_at(todo, key, 2 * a + 1, 1)
+        s12 = lo12 + u1 * (hi12 - lo12)
+        s13 = lo13 + u2 * (hi13 - lo13)
         ins = model.inside(s12, s13)
-        s12, s13, u3 = s12[ins], s13[ins], u3[ins]
-        with torch.no_grad():
-            pv = model.density_unnorm(as_t(theta), as_t(s12), as_t(s13)).numpy()
-        acc = u3 * pmax < pv
-        out12.append(s12[acc])
-        out13.append(s13[acc])
-        got += int(acc.sum())
-        batch += 1
-    return np.stack([np.concatenate(out12)[:n], np.concatenate(out13)[:n]])
+        keep = np.zeros(todo.size, dtype=bool)
+        if ins.any():
+            with torch.no_grad():
+                pv = model.density_unnorm(th, as_t(s12[ins]), as_t(s13[ins])).numpy()
+            k = u3[ins] * W < pv
+            keep[np.flatnonzero(ins)[k]] = True
+            above += int((pv[k] > W).sum())
+        idx = todo[keep].astype(np.int64)
+        out[0, idx] = s12[keep]
+        out[1, idx] = s13[keep]
+        todo = todo[~keep]
+    return out, W, above

@@ -152,6 +152,17 @@ class Model:
         check(self._lib.fn_model_fixed(self._h, None, v.ctypes.data_as(C.POINTER(C.c_double))))
         return v
 
+    def generate(self, theta, n: int, seed: int, fit: int = 0, envelope: float = 0.0, stream=None):
+        """dalitz3: n toy events at theta by accept-reject on the device, as a
+        (2, n) float64 CUDA tensor, and the envelope used (fn_generate)."""
+        th, thp = self._theta(theta)
+        ev = torch.empty((self.n_obs, n), dtype=torch.float64, device=f"cuda:{self.device}")
+        used = C.c_double()
+        check(self._lib.fn_generate(self._h, thp, C.c_uint32(seed & 0xFFFFFFFF), C.c_uint32(fit & 0xFFFFFFFF),
+                                    int(n), float(envelope), C.c_void_p(ev.data_ptr() if n else 0), int(n),
+                                    C.byref(used), _stream_ptr(stream)))
+        return ev, used.value
+
     def set_timing(self, enable: bool, every: int = 1):
         """Bracket every `every`-th per-event kernel launch with HIP events."""
         check(self._lib.fn_model_timing(self._h, every if enable else 0))

@@ -4,6 +4,7 @@
 // density, domain check).  The per-event, grid and normalization-matrix
 // passes live in dalitz_device.hpp and are compiled at model creation with
 // the model's structure as compile-time constants (dalitz_jit below).
+#include <algorithm>
 #include <cmath>
 #include <sstream>
 
@@ -273,6 +274,7 @@ std::string dalitz_jit_source(const DalitzConst& dc) {
          "FN_DALITZ_KERNEL(fn_dal_gr0, fn_shape, fn::kGrid, 0, 1)\n"
          "FN_DALITZ_KERNEL(fn_dal_gr2, fn_shape, fn::kGrid, 2, 1)\n";
   }
+  o << "FN_DALITZ_GEN(fn_dal_gmax, fn_dal_gen, fn_shape)\n";
   return o.str();
 }
 
@@ -281,6 +283,9 @@ std::shared_ptr<DalitzJit> dalitz_jit(const DalitzConst& dc) {
   std::vector<std::string> names;
   if (!dc.free_ls) names = {"fn_dal_ev0", "fn_dal_ev1", "fn_dal_mrows"};
   else names = {"fn_dal_ev0", "fn_dal_ev2", "fn_dal_gr0", "fn_dal_gr2"};
+  const size_t ngen = names.size();
+  names.push_back("fn_dal_gmax");
+  names.push_back("fn_dal_gen");
   j->prog = jit_load(dalitz_jit_source(dc), names);
   const auto& f = j->prog->fns;
   if (!dc.free_ls) {
@@ -293,6 +298,8 @@ std::shared_ptr<DalitzJit> dalitz_jit(const DalitzConst& dc) {
     j->gr[0] = f[2];
     j->gr[2] = f[3];
   }
+  j->gmax = f[ngen];
+  j->gen = f[ngen + 1];
   return j;
 }
 
@@ -355,6 +362,33 @@ void dalitz_launch_mrows(const DalitzJit& j, const DalitzConst& dc, const Dalitz
   const int kmax = dalitz_kmax(dc.K);
   hipLaunchKernelGGL(dalitz_mrows_finalize, dim3(1), dim3(kBlock), 0, s, dc, part, nchunks,
                      dal_nv(kMRows, 0, kmax), kmax, i0, Mc);
+}
+
+void dalitz_launch_gridmax(const DalitzJit& j, const DalitzConst& dc, const DalitzTable* tab,
+                           unsigned long long* vmax, hipStream_t s) {
+  const int64_t ncell = (int64_t)dc.nx * dc.ny;
+  const int64_t blocks = std::min<int64_t>((ncell + kBlock - 1) / kBlock, 4096);
+  DalitzConst c = dc;
+  const DalitzTable* t = tab;
+  unsigned long long* v = vmax;
+  void* args[] = {&c, &t, &v};
+  jit_launch(j.gmax, (unsigned)blocks, kBlock, s, args);
+}
+
+void dalitz_launch_gen(const DalitzJit& j, const DalitzConst& dc, const DalitzTable* tab, uint32_t k0, uint32_t k1,
+                       int64_t n, double W, const double box[4], int max_attempts, double* ev, int64_t ld,
+                       unsigned long long* bad, hipStream_t s) {
+  if (n == 0) return;
+  DalitzConst c = dc;
+  const DalitzTable* t = tab;
+  uint32_t a0 = k0, a1 = k1;
+  int64_t nn = n, l = ld;
+  double w = W, b0 = box[0], b1 = box[1], b2 = box[2], b3 = box[3];
+  int ma = max_attempts;
+  double* e = ev;
+  unsigned long long* b = bad;
+  void* args[] = {&c, &t, &a0, &a1, &nn, &w, &b0, &b1, &b2, &b3, &ma, &e, &l, &b};
+  jit_launch(j.gen, (unsigned)((n + kBlock - 1) / kBlock), kBlock, s, args);
 }
 
 void dalitz_launch_eval(const DalitzConst& dc, const DalitzTable* tab, const double* ev, int64_t ld, int64_t n,

@@ -32,6 +32,7 @@
 #include "device_common.hpp"
 #include "fastmath.hpp"
 #include "model.hpp"
+#include "philox.hpp"
 
 namespace fn {
 
@@ -301,6 +302,86 @@ __device__ inline void dalitz_pass_body(const DalitzConst& dc, const DalitzTable
                                    part + (int64_t)blockIdx.x * NV, lds);
 }
 
+// ---------------------------------------------------------------- toy events
+// P~(s12, s13) = |sum_k c_k A_k|^2 at one point.
+template <class S>
+__device__ __forceinline__ double dalitz_value(const DalitzConst& dc, const double* __restrict__ r,
+                                               const double* __restrict__ coef, double s12, double s13) {
+  constexpr int K = S::K;
+  const double s23 = dc.msum - s12 - s13;
+  double Are[K], Aim[K], Tre[K], Tim[K], Gk[K];
+  double Sre = 0.0, Sim = 0.0;
+  dalitz_pair<S, 0, kGrid, false, false>(dc, r, coef, s12, s13, s23, Are, Aim, Tre, Tim, Gk, Sre, Sim);
+  dalitz_pair<S, 1, kGrid, false, false>(dc, r, coef, s12, s13, s23, Are, Aim, Tre, Tim, Gk, Sre, Sim);
+  dalitz_pair<S, 2, kGrid, false, false>(dc, r, coef, s12, s13, s23, Are, Aim, Tre, Tim, Gk, Sre, Sim);
+  return __builtin_fma(Sre, Sre, Sim * Sim);
+}
+
+// Largest P~ over the centres of the grid cells inside the region, as the
+// bit pattern of a non-negative double (ordered like the value) in *vmax.
+template <class S>
+__device__ inline void dalitz_gridmax_body(const DalitzConst& dc, const DalitzTable* __restrict__ tab,
+                                           unsigned long long* __restrict__ vmax) {
+  __shared__ double lds[kBlock];
+  const int64_t ncell = (int64_t)dc.nx * dc.ny;
+  const double* r = &tab->r[0][0];
+  double m = 0.0;
+  for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < ncell; c += (int64_t)gridDim.x * kBlock) {
+    const int64_t ix = c / dc.ny, iy = c - ix * dc.ny;
+    const double s12 = dc.a12 + (ix + 0.5) * dc.d12;
+    const double s13 = dc.a13 + (iy + 0.5) * dc.d13;
+    if (!dalitz_inside(dc, s12, s13)) continue;
+    m = fmax(m, dalitz_value<S>(dc, r, tab->coef, s12, s13));
+  }
+  lds[threadIdx.x] = m;
+  __syncthreads();
+  for (int h = kBlock / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) lds[threadIdx.x] = fmax(lds[threadIdx.x], lds[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(vmax, (unsigned long long)__double_as_longlong(lds[0]));
+}
+
+// Events distributed as P~ by accept-reject from the bounding box
+// [box12] x [box13] (the box of the kinematic limits, as the host computes
+// it): event i, attempt a takes (u1, u2) from counter (i, 2a, 1) and u3 from
+// counter (i, 2a + 1, 1) under key (k0, k1); the candidate
+// (box12.lo + u1 (box12.hi - box12.lo), box13.lo + u2 (...)) is kept when it
+// lies in the region and u3 W < P~.  An event whose accepted P~ exceeds W
+// (the envelope was too low there) counts in bad[0]; an event not accepted
+// within max_attempts is NaN and counts in bad[1].
+template <class S>
+__device__ inline void dalitz_gen_body(const DalitzConst& dc, const DalitzTable* __restrict__ tab, uint32_t k0,
+                                       uint32_t k1, int64_t n, double W, double lo12, double hi12, double lo13,
+                                       double hi13, int max_attempts, double* __restrict__ ev, int64_t ld,
+                                       unsigned long long* __restrict__ bad) {
+#pragma clang fp contract(off)
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double* r = &tab->r[0][0];
+  const double w12 = hi12 - lo12, w13 = hi13 - lo13;
+  double x12 = __builtin_nan(""), x13 = __builtin_nan(""), px = 0.0;
+  for (int a = 0; a < max_attempts; ++a) {
+    double u1, u2, u3, unused;
+    philox_uniforms((uint64_t)i, 2u * a, 1u, k0, k1, u1, u2);
+    philox_uniforms((uint64_t)i, 2u * a + 1u, 1u, k0, k1, u3, unused);
+    const double s12 = lo12 + u1 * w12;
+    const double s13 = lo13 + u2 * w13;
+    if (!dalitz_inside(dc, s12, s13)) continue;
+    const double p = dalitz_value<S>(dc, r, tab->coef, s12, s13);
+    if (u3 * W < p) {
+      x12 = s12;
+      x13 = s13;
+      px = p;
+      break;
+    }
+  }
+  ev[i] = x12;
+  ev[ld + i] = x13;
+  if (px > W) atomicAdd(bad, 1ull);
+  if (x12 != x12) atomicAdd(bad + 1, 1ull);
+}
+
 }  // namespace fn
 
 // Kernel NAME for shape S, mode, gradient level and events per thread and
@@ -310,4 +391,17 @@ __device__ inline void dalitz_pass_body(const DalitzConst& dc, const DalitzTable
       fn::DalitzConst dc, const fn::DalitzTable* __restrict__ tab, const double* __restrict__ coef,           \
       const double* __restrict__ ev, int64_t ld, int64_t n, int chunk, int i0, double* __restrict__ part) {   \
     fn::dalitz_pass_body<S, MODE, GRAD, EPT>(dc, tab, coef, ev, ld, n, chunk, i0, part);                       \
+  }
+
+// Grid maximum and accept-reject generator for shape S.
+#define FN_DALITZ_GEN(GRIDMAX, GEN, S)                                                                        \
+  extern "C" __global__ __launch_bounds__(fn::kBlock) void GRIDMAX(                                            \
+      fn::DalitzConst dc, const fn::DalitzTable* __restrict__ tab, unsigned long long* __restrict__ vmax) {   \
+    fn::dalitz_gridmax_body<S>(dc, tab, vmax);                                                                 \
+  }                                                                                                            \
+  extern "C" __global__ __launch_bounds__(fn::kBlock) void GEN(                                                \
+      fn::DalitzConst dc, const fn::DalitzTable* __restrict__ tab, uint32_t k0, uint32_t k1, int64_t n,        \
+      double W, double lo12, double hi12, double lo13, double hi13, int max_attempts,                          \
+      double* __restrict__ ev, int64_t ld, unsigned long long* __restrict__ bad) {                             \
+    fn::dalitz_gen_body<S>(dc, tab, k0, k1, n, W, lo12, hi12, lo13, hi13, max_attempts, ev, ld, bad);         \
   }

@@ -62,7 +62,8 @@ struct fn_model {
   int64_t mc_gen = 0;            // bumped whenever the sample is replaced
   bool M_valid = false;          // cached normalization matrix is current
   bool table_ready = false;      // fixed lineshapes: the table's lineshape constants are built
-  fn::DevBuf d_table, d_part, d_npart, d_out, d_fixed, d_M, d_count, d_mc;
+  fn::DevBuf d_table, d_part, d_npart, d_out, d_fixed, d_M, d_count, d_mc, d_gen;
+  double box[4] = {0.0, 0.0, 0.0, 0.0};  // Dalitz: kinematic box (s12 lo, hi, s13 lo, hi)
   double* h_out = nullptr;       // pinned
   long long stats_calls = 0;
   int timing = 0;                // bracket every timing-th event-pass launch with HIP events (0 = off)

@@ -38,6 +38,7 @@ struct DalitzJit {
   hipFunction_t ev[3] = {nullptr, nullptr, nullptr};  // by gradient level
   hipFunction_t gr[3] = {nullptr, nullptr, nullptr};
   hipFunction_t mrows = nullptr;
+  hipFunction_t gmax = nullptr, gen = nullptr;  // toy generation: grid maximum, accept-reject
 };
 std::string dalitz_jit_source(const DalitzConst& dc);
 std::shared_ptr<DalitzJit> dalitz_jit(const DalitzConst& dc);
@@ -60,6 +61,16 @@ void dalitz_launch_grid(const DalitzJit& j, const DalitzConst& dc, const DalitzT
                         int chunk, int64_t nchunks, int grad, double* part, hipStream_t s);
 void dalitz_launch_mrows(const DalitzJit& j, const DalitzConst& dc, const DalitzTable* tab, int chunk,
                          int64_t nchunks, int i0, double* part, double* Mc, hipStream_t s);
+// Toy events: vmax (zeroed by the caller) receives the bits of the largest P~
+// over the grid cells inside the region; the generator writes n events (SoA,
+// leading dimension ld) by accept-reject under envelope W from the box
+// box = {lo12, hi12, lo13, hi13}; bad[0] counts accepted points above W,
+// bad[1] events left unresolved after max_attempts (zeroed by the caller).
+void dalitz_launch_gridmax(const DalitzJit& j, const DalitzConst& dc, const DalitzTable* tab,
+                           unsigned long long* vmax, hipStream_t s);
+void dalitz_launch_gen(const DalitzJit& j, const DalitzConst& dc, const DalitzTable* tab, uint32_t k0, uint32_t k1,
+                       int64_t n, double W, const double box[4], int max_attempts, double* ev, int64_t ld,
+                       unsigned long long* bad, hipStream_t s);
 void dalitz_launch_eval(const DalitzConst& dc, const DalitzTable* tab, const double* ev, int64_t ld, int64_t n,
                         const double* norm, double* p, hipStream_t s);
 void dalitz_launch_check(const DalitzConst& dc, const double* ev, int64_t ld, int64_t n, unsigned long long* bad,

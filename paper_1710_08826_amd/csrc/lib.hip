@@ -18,6 +18,11 @@
 
 namespace fn {
 
+// Device toy generation by model: envelope = this factor x the largest density
+// on the integration grid when the caller gives none; attempts per event.
+constexpr double kGenEnvelopeFactor = 1.2;
+constexpr int kGenMaxAttemptsModel = 4096;
+
 static thread_local std::string g_last_error;
 
 void set_error(const std::string& s) { g_last_error = s; }
@@ -150,6 +155,10 @@ static void compile_dalitz3(const json::Value& d, fn_model* m, bool device = tru
   dc.a13 = (mm[1] + mm[3]) * (mm[1] + mm[3]);
   dc.d13 = ((M - mm[2]) * (M - mm[2]) - dc.a13) / ny;
   dc.dA = dc.d12 * dc.d13;
+  m->box[0] = dc.a12;
+  m->box[1] = (M - mm[3]) * (M - mm[3]);
+  m->box[2] = dc.a13;
+  m->box[3] = (M - mm[2]) * (M - mm[2]);
   // pairs: 0 = "12" (A,B,C) = (1,2,3); 1 = "13" (1,3,2); 2 = "23" (2,3,1)
   const int who[3][3] = {{1, 2, 3}, {1, 3, 2}, {2, 3, 1}};
   for (int c = 0; c < 3; ++c) {
@@ -635,6 +644,56 @@ fn_status fn_eval(fn_model* m, const double* theta_host, const double* ev, int64
     else dalitz_launch_eval(m->dal, m->table_dal(), ev, ld, n, m->out() + 1 + m->P, p_dev, s);
     hip_check(hipGetLastError(), "kernel launch");
     hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+  });
+}
+
+fn_status fn_generate(fn_model* m, const double* theta_host, uint32_t seed, uint32_t fit, int64_t n,
+                      double envelope, double* ev_dev, int64_t ld, double* envelope_used, void* stream) {
+  return guard([&] {
+    if (!m || !theta_host) throw Error(FN_E_INVALID, "NULL argument");
+    if (m->kind != kKindDalitz3)
+      throw Error(FN_E_INVALID, "device generation by model is available for dalitz3 models "
+                                "(mix1d: fn_generate_mix1d)");
+    if (n < 0 || (n > 0 && !ev_dev)) throw Error(FN_E_INVALID, "bad output");
+    if (ld < n) throw Error(FN_E_INVALID, "ld must be >= n");
+    if (!(envelope >= 0.0) || !std::isfinite(envelope)) throw Error(FN_E_INVALID, "envelope must be finite and >= 0");
+    hip_check(hipSetDevice(m->device), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    const DalitzConst& dc = m->dal;
+    const ParamBlock pb = make_block(m, theta_host);
+    dalitz_launch_prologue(dc, pb, nullptr, m->fixed(), 1, 0, m->table_dal(), s);
+    m->d_gen.reserve(3 * sizeof(unsigned long long));
+    unsigned long long* g = (unsigned long long*)m->d_gen.ptr;
+    hip_check(hipMemsetAsync(g, 0, 3 * sizeof(unsigned long long), s), "hipMemsetAsync");
+    double valid = 0.0;
+    hip_check(hipMemcpyAsync(&valid, &m->table_dal()->valid, sizeof(double), hipMemcpyDeviceToHost, s),
+              "hipMemcpyAsync");
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (valid == 0.0) throw Error(FN_E_INVALID, "invalid lineshape parameters");
+    double W = envelope;
+    if (W == 0.0) {
+      dalitz_launch_gridmax(*m->dal_jit, dc, m->table_dal(), g, s);
+      hip_check(hipGetLastError(), "kernel launch");
+      unsigned long long bits = 0;
+      hip_check(hipMemcpyAsync(&bits, g, sizeof(bits), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+      hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+      double vmax;
+      std::memcpy(&vmax, &bits, sizeof(vmax));
+      if (!(vmax > 0.0) || !std::isfinite(vmax)) throw Error(FN_E_INVALID, "the density vanishes on the grid");
+      W = kGenEnvelopeFactor * vmax;
+    }
+    if (envelope_used) *envelope_used = W;
+    if (n == 0) return;
+    dalitz_launch_gen(*m->dal_jit, dc, m->table_dal(), seed, fit, n, W, m->box, kGenMaxAttemptsModel, ev_dev, ld,
+                      g + 1, s);
+    hip_check(hipGetLastError(), "kernel launch");
+    unsigned long long bad[2] = {0, 0};
+    hip_check(hipMemcpyAsync(bad, g + 1, sizeof(bad), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (bad[0])
+      throw Error(FN_E_DOMAIN, std::to_string(bad[0]) + " accepted events lie above the envelope " +
+                                   std::to_string(W) + ": raise it");
+    if (bad[1]) throw Error(FN_E_DOMAIN, std::to_string(bad[1]) + " events not resolved within the attempt limit");
   });
 }
 

@@ -226,3 +226,55 @@ def test_width_and_barriers_vs_spherical_hankel(k):
     amp = MODEL.amplitude(k, s12, s13, torch.tensor(m0), torch.tensor(w0)).numpy()
     expect = bf(q * r) / bf(q0 * r) * bf(p * rd) * z * t.numpy()
     assert np.allclose(amp, expect, rtol=1e-10, atol=1e-14 * np.abs(expect).max())
+
+
+# ------------------------------------------------------------ toy generation
+@pytest.fixture(scope="module")
+def toy_sample():
+    d = D.config1_desc(grid=(256, 256))
+    th = D.truth_theta(d)
+    ev, W, above = D.generate(th, d, 12_000, seed=5, fit=2)
+    return d, th, ev, W, above
+
+
+def test_generated_moments_match_the_density(toy_sample):
+    """Sample means of s12, s13, s12^2 and s12 s13 agree with their
+    expectations under P~ (fine-grid quadrature over the region) within 4
+    standard errors: a swapped coordinate, a wrong box, an inverted accept
+    test or a dropped region cut moves them by many."""
+    d, th, ev, W, above = toy_sample
+    assert above == 0 and np.isfinite(ev).all()
+    model = D.Dalitz(dict(d, grid=[1024, 1024]))
+    c12, c13, _ = model.grid_cells()
+    with torch.no_grad():
+        w = model.density_unnorm(common.as_t(th), common.as_t(c12), common.as_t(c13)).numpy()
+    w = w / w.sum()
+    for f in (lambda a, b: a, lambda a, b: b, lambda a, b: a * a, lambda a, b: a * b):
+        x = f(ev[0], ev[1])
+        expect = float((w * f(c12, c13)).sum())
+        se = x.std() / math.sqrt(x.size)
+        assert abs(x.mean() - expect) < 4.0 * se, (x.mean(), expect, se)
+
+
+def test_generated_events_lie_in_the_region(toy_sample):
+    d, th, ev, W, above = toy_sample
+    model = D.Dalitz(d)
+    assert model.inside(ev[0], ev[1]).all()
+
+
+def test_generation_is_per_event(toy_sample):
+    """Event i depends only on (theta, seed, fit, W, i): a shorter run is a
+    prefix, another fit index gives other events."""
+    d, th, ev, W, above = toy_sample
+    head, W2, _ = D.generate(th, d, 500, seed=5, fit=2, W=W)
+    assert W2 == W and np.array_equal(head, ev[:, :500])
+    other, _, _ = D.generate(th, d, 500, seed=5, fit=3, W=W)
+    assert not np.any(other[0] == ev[0, :500])
+
+
+def test_low_envelope_is_reported():
+    d = D.config1_desc(grid=(128, 128))
+    th = D.truth_theta(d)
+    W = D.envelope(th, d)
+    _, _, above = D.generate(th, d, 2000, seed=6, W=0.2 * W)
+    assert above > 0
