@@ -31,11 +31,12 @@ PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector, FMA counted as 2
 PEAK_HBM_GBS = 8000.0
 
 # HBM bytes per launch of the config-1 event kernel from the FETCH_SIZE and
-# WRITE_SIZE counter runs (profiles/dalitz_pass_events_grad_1M.md), and its
-# executed FP64 FLOPs per event from SQ_INSTS_VALU_FLOPS_FP64, valid for the
-# kernel sources with this hash; reported as null once they change.
-TRAFFIC_BYTES = 1.620e7
-COUNTED_FP64_FLOPS_PER_EVENT = 598.4
+# WRITE_SIZE counter runs (profiles/dalitz_events_grad_1M.md), by summation
+# chunk, and its executed FP64 FLOPs per event from SQ_INSTS_VALU_FLOPS_FP64,
+# valid for the kernel sources with this hash; reported as null once they
+# change or for a chunk without a counter run.
+TRAFFIC_BYTES = {2048: 1.620e7}
+COUNTED_FP64_FLOPS_PER_EVENT = {2048: 598.4}
 TRAFFIC_SOURCES = ["paper_1710_08826_amd/csrc/dalitz_device.hpp", "paper_1710_08826_amd/csrc/dalitz3.hip",
                    "paper_1710_08826_amd/csrc/fastmath.hpp", "paper_1710_08826_amd/csrc/device_common.hpp",
                    "paper_1710_08826_amd/csrc/model.hpp"]
@@ -51,8 +52,12 @@ def counters_current() -> bool:
     return h.hexdigest()[:16] == TRAFFIC_HASH
 
 
-def measured_traffic():
-    return TRAFFIC_BYTES if counters_current() else None
+def measured_traffic(chunk: int):
+    return TRAFFIC_BYTES.get(chunk) if counters_current() else None
+
+
+def counted_flops(chunk: int):
+    return COUNTED_FP64_FLOPS_PER_EVENT.get(chunk) if counters_current() else None
 
 # FP64 FLOPs of the correctly rounded gfx950 sequences of the ROCm device
 # library (FMA = 2, other FP64 arithmetic = 1, compares 0), counted from the
@@ -194,10 +199,10 @@ def cpu_baseline(events: np.ndarray, desc: dict, theta, budget_s: float = 12.0):
                       f"with the 1024x1024 grid normalization recomputed per call, {calls} calls in {dt:.1f} s"}
 
 
-def pmc_probe(steps: int):
+def pmc_probe(steps: int, chunk: int):
     """Workload for hardware-counter runs: a plain 256 MiB copy (its counter
     reading calibrates bytes per counter unit), then config-1 NLL+gradient
-    steps."""
+    steps at the given summation chunk."""
     import torch
     import synth
     from paper_1710_08826_amd import Model
@@ -206,13 +211,13 @@ def pmc_probe(steps: int):
     dst.copy_(src)
     torch.cuda.synchronize()
     ev = torch.from_numpy(synth.dalitz_events(1_000_000, seed=synth.BASE_SEED)).cuda()
-    m = Model(synth.dalitz_desc())
+    m = Model(synth.dalitz_desc(chunk=chunk))
     th = torch.from_numpy(synth.dalitz_truth()).cuda()
     out = torch.empty(1 + m.n_params, dtype=torch.float64, device="cuda")
     for _ in range(steps):
         m.nll_async(th, ev, out, True)
     torch.cuda.synchronize()
-    print(json.dumps({"pmc_probe": True, "copy_bytes": 2 * src.numel() * 8, "steps": steps,
+    print(json.dumps({"pmc_probe": True, "copy_bytes": 2 * src.numel() * 8, "steps": steps, "chunk": m.chunk,
                       "nll": float(out[0])}), flush=True)
 
 
@@ -376,13 +381,14 @@ def main():
     ap.add_argument("--pmc-probe", action="store_true",
                     help="for counter runs: one 256 MiB device copy (calibration) then --steps "
                          "config-1 steps, nothing printed but a summary line")
+    ap.add_argument("--chunk", type=int, default=2048, help="summation chunk of the --pmc-probe steps")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
         sys.exit(2)
     if args.pmc_probe:
-        pmc_probe(args.steps)
+        pmc_probe(args.steps, args.chunk)
         return
     if args.leg == "td4":
         print(json.dumps({"config4": td4_leg()}), flush=True)
@@ -407,14 +413,16 @@ def main():
     tdev = torch.from_numpy(th1).to(dev)
     tdev_b = torch.from_numpy(th1b).to(dev)
     out = torch.empty(1 + P1, dtype=torch.float64, device=dev)
-    print(f"[bench] config1 dalitz: {n1} events, P={P1}, warmup {args.warmup}, steps {args.steps}",
-          file=sys.stderr, flush=True)
+    # summation chunk from the library's autotuner on this sample
+    tuned_chunk, tune_us = m1.autotune(th1, ev1, reps=20)
+    print(f"[bench] config1 dalitz: {n1} events, P={P1}, chunk {tuned_chunk} (autotuned), warmup {args.warmup}, "
+          f"steps {args.steps}", file=sys.stderr, flush=True)
     wall, kern_ms = time_async(m1, tdev, ev1, out, args.steps, args.warmup, True, alt=tdev_b)
     ms_step = 1e3 * wall / args.steps
     value = n1 * args.steps / wall
     flops_ev = dalitz_flops_per_event(desc1, 1)
     achieved = flops_ev * n1 / (kern_ms * 1e-3) / 1e12
-    extra = {}
+    extra = {"config1_autotune_us": {str(k): v for k, v in tune_us.items()}}
     print(f"[bench] {value:.4g} events/s, step {ms_step:.4f} ms, kernel {kern_ms * 1e3:.2f} us",
           file=sys.stderr, flush=True)
 
@@ -533,12 +541,12 @@ def main():
                    "events": n1, "params": P1, "grid": [1024, 1024], "normalization": "cached grid matrix",
                    "chunk": m1.chunk, "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(),
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(m1.chunk),
                      "kernel": "fn_dal_ev1 (Dalitz events pass, coefficient gradient)",
                      "kernel_us": kern_ms * 1e3, "flops_per_event": flops_ev,
-                     "counted_fp64_flops_per_event": COUNTED_FP64_FLOPS_PER_EVENT if counters_current() else None,
-                     "counted_fp64_tflops": (COUNTED_FP64_FLOPS_PER_EVENT * n1 / (kern_ms * 1e-3) / 1e12
-                                             if counters_current() else None),
+                     "counted_fp64_flops_per_event": counted_flops(m1.chunk),
+                     "counted_fp64_tflops": (counted_flops(m1.chunk) * n1 / (kern_ms * 1e-3) / 1e12
+                                             if counted_flops(m1.chunk) else None),
                      "hbm_gbs": 16 * n1 / (kern_ms * 1e-3) / 1e9},
         "cpu_baseline": cpu,
         "extra": extra,

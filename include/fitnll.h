@@ -137,6 +137,18 @@ fn_status fn_model_check_compile(const char* desc_json, const char* arch);
 fn_status fn_model_info(const fn_model* m, int32_t* n_params, int32_t* n_obs, int32_t* chunk);
 /* Frees the model's device memory.  Streams using it must be synchronised. */
 fn_status fn_model_destroy(fn_model* m);
+/* Autotuner of the summation chunk (events per workgroup; it also fixes the
+ * order of the sums): times the full NLL + gradient evaluation at theta (host,
+ * P doubles) on the caller's events (device, as fn_nll) for the chunks 256,
+ * 512, ..., 16384 (3 warm-up calls, then the median of reps timed calls, HIP
+ * events on `stream`; reps < 1 means 20), keeps the fastest as the model's
+ * chunk (reported by fn_model_info and used by every later evaluation and by
+ * batches created afterwards) and writes it to *chunk_out.  us_out (may be
+ * NULL) receives the 7 median times in microseconds.  Synchronous.
+ * FN_E_INVALID for NULL theta, n < 1 or bad event arguments; the model keeps
+ * its previous chunk on any error. */
+fn_status fn_model_autotune(fn_model* m, const double* theta_host, const double* ev, int64_t n, int64_t ld,
+                            int32_t reps, int32_t* chunk_out, double* us_out, void* stream);
 
 /* Count events outside the observable domain (range for mix1d; bounding box
  * and physical region, with a relative tolerance of 1e-9, for dalitz3).

@@ -48,9 +48,9 @@ def _events(ev: torch.Tensor, n_obs: int):
         ev = ev.unsqueeze(0)
     if ev.dim() != 2 or ev.shape[0] != n_obs:
         raise ValueError(f"events must have shape ({n_obs}, n)")
-    if ev.stride(1) != 1:
-        raise ValueError("events must be contiguous along the event axis")
     n = ev.shape[1]
+    if n > 1 and ev.stride(1) != 1:
+        raise ValueError("events must be contiguous along the event axis")
     ld = ev.stride(0) if n_obs > 1 else n
     return C.c_void_p(ev.data_ptr() if n > 0 else 0), n, ld
 
@@ -162,6 +162,20 @@ class Model:
                                     int(n), float(envelope), C.c_void_p(ev.data_ptr() if n else 0), int(n),
                                     C.byref(used), _stream_ptr(stream)))
         return ev, used.value
+
+    TUNE_CHUNKS = (256, 512, 1024, 2048, 4096, 8192, 16384)
+
+    def autotune(self, theta, events: torch.Tensor, reps: int = 20, stream=None):
+        """Pick the fastest summation chunk for these events (fn_model_autotune);
+        returns (chunk, {chunk: median microseconds per NLL + gradient})."""
+        th, thp = self._theta(theta)
+        evp, n, ld = _events(events, self.n_obs)
+        best = C.c_int32()
+        us = (C.c_double * len(self.TUNE_CHUNKS))()
+        check(self._lib.fn_model_autotune(self._h, thp, evp, n, ld, int(reps), C.byref(best), us,
+                                          _stream_ptr(stream)))
+        self.chunk = best.value
+        return best.value, dict(zip(self.TUNE_CHUNKS, list(us)))
 
     def set_timing(self, enable: bool, every: int = 1):
         """Bracket every `every`-th per-event kernel launch with HIP events."""

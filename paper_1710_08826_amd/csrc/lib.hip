@@ -3,6 +3,7 @@
 //   prologue (theta -> table) -> normalization -> events pass -> finalize.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -22,6 +23,10 @@ namespace fn {
 // on the integration grid when the caller gives none; attempts per event.
 constexpr double kGenEnvelopeFactor = 1.2;
 constexpr int kGenMaxAttemptsModel = 4096;
+
+// Chunk sizes (events per workgroup) tried by fn_model_autotune.
+constexpr int kTuneChunks[] = {256, 512, 1024, 2048, 4096, 8192, 16384};
+constexpr int kTuneCount = (int)(sizeof(kTuneChunks) / sizeof(kTuneChunks[0]));
 
 static thread_local std::string g_last_error;
 
@@ -571,6 +576,56 @@ fn_status fn_model_info(const fn_model* m, int32_t* n_params, int32_t* n_obs, in
 
 fn_status fn_model_destroy(fn_model* m) {
   return guard([&] { delete m; });
+}
+
+fn_status fn_model_autotune(fn_model* m, const double* theta_host, const double* ev, int64_t n, int64_t ld,
+                            int32_t reps, int32_t* chunk_out, double* us_out, void* stream) {
+  return guard([&] {
+    if (!m || !theta_host) throw Error(FN_E_INVALID, "NULL argument");
+    if (n < 1) throw Error(FN_E_INVALID, "autotuning needs events");
+    check_events_args(m, ev, n, ld);
+    if (reps < 1) reps = 20;
+    hip_check(hipSetDevice(m->device), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    const ParamBlock pb = make_block(m, theta_host);
+    const int saved = m->chunk;
+    std::vector<hipEvent_t> evs(2 * (size_t)reps);
+    for (auto& e : evs) hip_check(hipEventCreate(&e), "hipEventCreate");
+    int best = saved;
+    double best_us = INFINITY;
+    try {
+      for (int c = 0; c < kTuneCount; ++c) {
+        m->chunk = kTuneChunks[c];
+        for (int w = 0; w < 3; ++w) run_nll(m, &pb, nullptr, ev, n, ld, true, nullptr, s);  // warm-up, buffers
+        for (int r = 0; r < reps; ++r) {
+          hip_check(hipEventRecord(evs[2 * r], s), "hipEventRecord");
+          run_nll(m, &pb, nullptr, ev, n, ld, true, nullptr, s);
+          hip_check(hipEventRecord(evs[2 * r + 1], s), "hipEventRecord");
+        }
+        hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+        std::vector<double> t(reps);
+        for (int r = 0; r < reps; ++r) {
+          float ms = 0.0f;
+          hip_check(hipEventElapsedTime(&ms, evs[2 * r], evs[2 * r + 1]), "hipEventElapsedTime");
+          t[r] = 1e3 * ms;
+        }
+        std::nth_element(t.begin(), t.begin() + reps / 2, t.end());
+        const double med = t[reps / 2];
+        if (us_out) us_out[c] = med;
+        if (med < best_us) {
+          best_us = med;
+          best = kTuneChunks[c];
+        }
+      }
+    } catch (...) {
+      m->chunk = saved;
+      for (auto& e : evs) (void)hipEventDestroy(e);
+      throw;
+    }
+    for (auto& e : evs) (void)hipEventDestroy(e);
+    m->chunk = best;
+    if (chunk_out) *chunk_out = best;
+  });
 }
 
 fn_status fn_events_check(fn_model* m, const double* ev, int64_t n, int64_t ld, int64_t* n_bad, void* stream) {
