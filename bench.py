@@ -35,12 +35,12 @@ PEAK_HBM_GBS = 8000.0
 # chunk, and its executed FP64 FLOPs per event from SQ_INSTS_VALU_FLOPS_FP64,
 # valid for the kernel sources with this hash; reported as null once they
 # change or for a chunk without a counter run.
-TRAFFIC_BYTES = {2048: 1.620e7}
-COUNTED_FP64_FLOPS_PER_EVENT = {2048: 598.4}
+TRAFFIC_BYTES = {2048: 1.620e7, 1024: 1.628e7}
+COUNTED_FP64_FLOPS_PER_EVENT = {2048: 598.4, 1024: 603.7}
 TRAFFIC_SOURCES = ["paper_1710_08826_amd/csrc/dalitz_device.hpp", "paper_1710_08826_amd/csrc/dalitz3.hip",
                    "paper_1710_08826_amd/csrc/fastmath.hpp", "paper_1710_08826_amd/csrc/device_common.hpp",
                    "paper_1710_08826_amd/csrc/model.hpp"]
-TRAFFIC_HASH = "ff178d3fb5c739f8"
+TRAFFIC_HASH = "14239f8c42c15b62"
 
 
 def counters_current() -> bool:
@@ -382,6 +382,8 @@ def main():
                     help="for counter runs: one 256 MiB device copy (calibration) then --steps "
                          "config-1 steps, nothing printed but a summary line")
     ap.add_argument("--chunk", type=int, default=2048, help="summation chunk of the --pmc-probe steps")
+    ap.add_argument("--chunk-c1", type=int, default=0,
+                    help="config-1 summation chunk instead of the autotuner's choice (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -413,9 +415,13 @@ def main():
     tdev = torch.from_numpy(th1).to(dev)
     tdev_b = torch.from_numpy(th1b).to(dev)
     out = torch.empty(1 + P1, dtype=torch.float64, device=dev)
-    # summation chunk from the library's autotuner on this sample
-    tuned_chunk, tune_us = m1.autotune(th1, ev1, reps=20)
-    print(f"[bench] config1 dalitz: {n1} events, P={P1}, chunk {tuned_chunk} (autotuned), warmup {args.warmup}, "
+    # summation chunk from the library's autotuner on this sample (or given, for profiling runs)
+    if args.chunk_c1:
+        m1 = Model(dict(desc1, chunk=args.chunk_c1))
+        tuned_chunk, tune_us = m1.chunk, {}
+    else:
+        tuned_chunk, tune_us = m1.autotune(th1, ev1, reps=20)
+    print(f"[bench] config1 dalitz: {n1} events, P={P1}, chunk {tuned_chunk}, warmup {args.warmup}, "
           f"steps {args.steps}", file=sys.stderr, flush=True)
     wall, kern_ms = time_async(m1, tdev, ev1, out, args.steps, args.warmup, True, alt=tdev_b)
     ms_step = 1e3 * wall / args.steps

@@ -141,9 +141,10 @@ fn_status fn_model_destroy(fn_model* m);
  * order of the sums): times the full NLL + gradient evaluation at theta (host,
  * P doubles) on the caller's events (device, as fn_nll) for the chunks 256,
  * 512, ..., 16384 (3 warm-up calls, then the median of reps timed calls, HIP
- * events on `stream`; reps < 1 means 20), keeps the fastest as the model's
- * chunk (reported by fn_model_info and used by every later evaluation and by
- * batches created afterwards) and writes it to *chunk_out.  us_out (may be
+ * events on `stream`; reps < 1 means 20), keeps the largest chunk whose time
+ * is within 2% of the fastest as the model's chunk (reported by fn_model_info
+ * and used by every later evaluation and by batches created afterwards) and
+ * writes it to *chunk_out.  us_out (may be
  * NULL) receives the 7 median times in microseconds.  Synchronous.
  * FN_E_INVALID for NULL theta, n < 1 or bad event arguments; the model keeps
  * its previous chunk on any error. */

@@ -166,7 +166,8 @@ class Model:
     TUNE_CHUNKS = (256, 512, 1024, 2048, 4096, 8192, 16384)
 
     def autotune(self, theta, events: torch.Tensor, reps: int = 20, stream=None):
-        """Pick the fastest summation chunk for these events (fn_model_autotune);
+        """Pick the summation chunk for these events (fn_model_autotune: the
+        largest within 2% of the fastest);
         returns (chunk, {chunk: median microseconds per NLL + gradient})."""
         th, thp = self._theta(theta)
         evp, n, ld = _events(events, self.n_obs)

@@ -27,6 +27,7 @@ constexpr int kGenMaxAttemptsModel = 4096;
 // Chunk sizes (events per workgroup) tried by fn_model_autotune.
 constexpr int kTuneChunks[] = {256, 512, 1024, 2048, 4096, 8192, 16384};
 constexpr int kTuneCount = (int)(sizeof(kTuneChunks) / sizeof(kTuneChunks[0]));
+constexpr double kTuneTie = 0.02;  // relative time difference treated as a tie
 
 static thread_local std::string g_last_error;
 
@@ -591,8 +592,7 @@ fn_status fn_model_autotune(fn_model* m, const double* theta_host, const double*
     const int saved = m->chunk;
     std::vector<hipEvent_t> evs(2 * (size_t)reps);
     for (auto& e : evs) hip_check(hipEventCreate(&e), "hipEventCreate");
-    int best = saved;
-    double best_us = INFINITY;
+    std::vector<double> med(kTuneCount, INFINITY);
     try {
       for (int c = 0; c < kTuneCount; ++c) {
         m->chunk = kTuneChunks[c];
@@ -610,12 +610,8 @@ fn_status fn_model_autotune(fn_model* m, const double* theta_host, const double*
           t[r] = 1e3 * ms;
         }
         std::nth_element(t.begin(), t.begin() + reps / 2, t.end());
-        const double med = t[reps / 2];
-        if (us_out) us_out[c] = med;
-        if (med < best_us) {
-          best_us = med;
-          best = kTuneChunks[c];
-        }
+        med[c] = t[reps / 2];
+        if (us_out) us_out[c] = med[c];
       }
     } catch (...) {
       m->chunk = saved;
@@ -623,6 +619,12 @@ fn_status fn_model_autotune(fn_model* m, const double* theta_host, const double*
       throw;
     }
     for (auto& e : evs) (void)hipEventDestroy(e);
+    // the largest chunk within kTuneTie of the fastest: fewer partial rows for
+    // the level-2 step, and a stable choice when candidates time alike
+    const double fastest = *std::min_element(med.begin(), med.end());
+    int best = kTuneChunks[0];
+    for (int c = 0; c < kTuneCount; ++c)
+      if (med[c] <= (1.0 + kTuneTie) * fastest) best = kTuneChunks[c];
     m->chunk = best;
     if (chunk_out) *chunk_out = best;
   });

@@ -1,4 +1,5 @@
-"""Chunk autotuner: the chosen chunk is the fastest of the timed candidates,
+"""Chunk autotuner: the chosen chunk is the largest of the timed candidates
+within 2% of the fastest,
 becomes the model's chunk, and the evaluations that follow still match the
 oracle; an invalid call leaves the model's chunk alone."""
 import ctypes as C
@@ -29,7 +30,8 @@ def test_dalitz_autotune_then_parity():
     ev = to_dev(x)
     chunk, table = m.autotune(th, ev, reps=10)
     say("  chunk", chunk, {k: round(v, 1) for k, v in table.items()})
-    assert chunk in m.TUNE_CHUNKS and table[chunk] == min(table.values())
+    assert chunk in m.TUNE_CHUNKS and table[chunk] <= 1.02 * min(table.values())
+    assert all(table[c] > 1.02 * min(table.values()) for c in m.TUNE_CHUNKS if c > chunk)
     assert all(np.isfinite(v) and v > 0 for v in table.values())
     assert m.chunk == chunk == _info_chunk(m)
     v, g = m.nll(th, ev, grad=True)
