@@ -87,7 +87,9 @@ typedef struct fn_model fn_model;
  *     T in gauss(mu,sigma), exp(tau), argus(m0,c) [power 1/2, c<0, lo>=0],
  *     bw(m0,gamma) [non-relativistic].  K components take K-1 fractions; the
  *     last gets 1 - sum.  Each component is normalized analytically on
- *     [lo,b], so I = 1.  One observable.
+ *     [lo,b], so I = 1.  One observable.  Optional "yield": i makes the
+ *     likelihood extended with expected count nu = theta[i] > 0: the NLL of
+ *     N events gains nu - N ln nu, and binned data take nu as their total.
  *  kind "dalitz3": {"kind":"dalitz3","M":..,"m":[m1,m2,m3],"r_res":r,
  *                  "r_D":rD,"grid":[nx,ny],"free_lineshapes":bool,
  *                  "resonances":[{"pair":"12"|"13"|"23","L":0|1|2,
@@ -171,6 +173,21 @@ fn_status fn_nll(fn_model* m, const double* theta_host, const double* ev, int64_
 fn_status fn_nll_async(fn_model* m, const double* theta_dev, const double* ev, int64_t n,
                        int64_t ld, double* out_dev, int32_t with_grad, void* stream);
 
+/* Binned data of a mix1d model (the paper's binned DataSet, Fig. 1 and
+ * Sec. 4): counts_dev holds n_bins >= 1 counts (device doubles, finite and
+ * >= 0) of uniform bins on [lo, hi].  The expected count of bin b is
+ * nu_b = N Delta P(x_b) at the bin centre x_b = lo + (b + 1/2) Delta,
+ * Delta = (hi - lo)/n_bins, with N the yield parameter of an extended model,
+ * otherwise the total count W.  stat 0: Poisson NLL sum_b (nu_b - n_b ln nu_b)
+ * (the constant sum ln n_b! is omitted); stat 1: chi^2
+ * sum_{b: n_b > 0} (n_b - nu_b)^2 / n_b.  value_host gets the statistic and
+ * grad_host (may be NULL) its gradient (P doubles).  Synchronous.
+ * FN_E_INVALID for another model kind, n_bins < 1, NULL counts or another
+ * stat; FN_E_NONFINITE when the statistic is not finite (P = 0 in a filled
+ * bin, invalid parameters, no events in a non-extended fit). */
+fn_status fn_nll_binned(fn_model* m, const double* theta_host, const double* counts_dev, int64_t n_bins,
+                        int32_t stat, double* value_host, double* grad_host, void* stream);
+
 /* Normalization integral I(theta) and, when dnorm_host != NULL, dI/dtheta. */
 fn_status fn_norm(fn_model* m, const double* theta_host, double* norm_host,
                   double* dnorm_host, void* stream);
@@ -221,6 +238,13 @@ fn_status fn_fit(fn_model* m, const double* theta0_host, const int32_t* free_mas
                  const double* ev, int64_t n, int64_t ld, int32_t grad_mode, double tol,
                  int32_t max_iter, double* theta_out, double* err_out, double* nll_out,
                  int32_t* n_iter, int32_t* n_calls, void* stream);
+/* The same fit of binned data (fn_nll_binned's counts, n_bins and stat);
+ * value_out receives the minimum of the statistic, and errors use the error
+ * definition of the statistic (1/2 for the Poisson NLL, 1 for chi^2). */
+fn_status fn_fit_binned(fn_model* m, const double* theta0_host, const int32_t* free_mask,
+                        const double* counts_dev, int64_t n_bins, int32_t stat, int32_t grad_mode, double tol,
+                        int32_t max_iter, double* theta_out, double* err_out, double* value_out,
+                        int32_t* n_iter, int32_t* n_calls, void* stream);
 
 /* ------------------------------------------------- systematic variations
  * Many fits of one "td4" model to ONE event sample that differ in their fixed

@@ -29,12 +29,24 @@ Integrals used here (each a closed form):
          incomplete gamma function P(3/2, .) for c < 0
 * bw:    (2/gamma) [atan(2(hi-m0)/gamma) - atan(2(lo-m0)/gamma)]
 
+Extended likelihood (optional "yield": i): with nu = theta[i] expected events
+the NLL of N events gains nu - N ln nu.  Binned data (the paper's binned
+DataSet): counts n_b of uniform bins on [lo, hi], expected nu_b = N Delta
+P(x_b) at the bin centres (N = nu, or the total count when not extended);
+Poisson NLL sum_b (nu_b - n_b ln nu_b) without the constant ln n_b!, or chi^2
+over the filled bins.
+
 Pins (tests/test_oracle_mix1d.py): adaptive quadrature of every normalized
 component and of the mixture; mpmath brute force on 10 events with
 normalizations taken by quadrature; the Gaussian maximum-likelihood
 estimate (sample mean and biased variance) is a stationary point; the
 truncated-exponential MLE from a quadrature moment equation is a stationary
-point; translation invariance; autograd against central differences.
+point; translation invariance; autograd against central differences;
+extended: the yield's MLE is N; binned: a histogram with one event at each
+of N bin centres reproduces the unbinned NLL up to the closed-form terms
+N Delta sum_b P_b - N ln(N Delta), the extended Poisson yield MLE is
+W / (Delta sum_b P_b), chi^2 vanishes with zero gradient when the counts are
+the expected counts.
 """
 from __future__ import annotations
 
@@ -141,11 +153,28 @@ def density(theta: torch.Tensor, x: torch.Tensor, desc: dict) -> torch.Tensor:
     return total
 
 
+def yield_index(desc: dict):
+    """Index of the expected-yield parameter of an extended model, or None."""
+    return int(desc["yield"]) if "yield" in desc else None
+
+
+def extended_term(theta, n: int, desc: dict):
+    """nu - N ln nu for an extended model (Poisson probability of observing N
+    events when nu are expected, up to the constant ln N!), else 0."""
+    i = yield_index(desc)
+    if i is None:
+        return 0.0
+    nu = theta[i]
+    return nu - n * torch.log(nu) if isinstance(nu, torch.Tensor) else nu - n * math.log(nu)
+
+
 def nll(theta, x, desc: dict) -> float:
-    """NLL value, events summed exactly rounded (I = 1 by construction)."""
+    """NLL value, events summed exactly rounded (I = 1 by construction); an
+    extended model adds nu - N ln nu."""
     with torch.no_grad():
         p = density(as_t(theta), as_t(x), desc)
-        return nll_value(torch.log(p), int(np.size(x)), 0.0)
+        v = nll_value(torch.log(p), int(np.size(x)), 0.0)
+    return v + float(extended_term(np.asarray(theta, dtype=np.float64), int(np.size(x)), desc))
 
 
 def nll_grad(theta, x, desc: dict):
@@ -153,9 +182,45 @@ def nll_grad(theta, x, desc: dict):
     th = as_t(theta, requires_grad=True)
     p = density(th, as_t(x), desc)
     lp = torch.log(p)
-    loss = -lp.sum()
+    loss = -lp.sum() + extended_term(th, int(np.size(x)), desc)
     loss.backward()
-    return nll_value(lp.detach(), int(np.size(x)), 0.0), th.grad.numpy().copy()
+    v = nll_value(lp.detach(), int(np.size(x)), 0.0)
+    v += float(extended_term(np.asarray(theta, dtype=np.float64), int(np.size(x)), desc))
+    return v, th.grad.numpy().copy()
+
+
+def bin_centres(desc: dict, n_bins: int) -> np.ndarray:
+    lo, hi, _, _ = parse(desc)
+    delta = (hi - lo) / n_bins
+    return lo + (np.arange(n_bins) + 0.5) * delta
+
+
+def binned_tensor(theta: torch.Tensor, counts, desc: dict, stat: str) -> torch.Tensor:
+    """Binned statistic of histogram counts on n_bins uniform bins over
+    [lo, hi]: expected counts nu_b = N Delta P(x_b) at the bin centres, N the
+    yield of an extended model or the total count; "poisson":
+    sum_b (nu_b - n_b ln nu_b); "chi2": sum over n_b > 0 of (n_b - nu_b)^2 / n_b."""
+    lo, hi, _, _ = parse(desc)
+    n = as_t(np.asarray(counts, dtype=np.float64))
+    nb = n.numel()
+    delta = (hi - lo) / nb
+    p = density(theta, as_t(bin_centres(desc, nb)), desc)
+    i = yield_index(desc)
+    N = theta[i] if i is not None else n.sum()
+    nu = N * delta * p
+    if stat == "poisson":
+        filled = n > 0
+        return nu.sum() - (n[filled] * torch.log(nu[filled])).sum()
+    filled = n > 0
+    return ((n[filled] - nu[filled]) ** 2 / n[filled]).sum()
+
+
+def binned_value_grad(theta, counts, desc: dict, stat: str):
+    """(statistic, gradient by autograd)."""
+    th = as_t(theta, requires_grad=True)
+    v = binned_tensor(th, counts, desc, stat)
+    v.backward()
+    return float(v.detach()), th.grad.numpy().copy()
 
 
 def config0_desc(lo: float = -10.0, hi: float = 10.0) -> dict:

@@ -220,6 +220,52 @@ class Model:
             check(st)
         return FitResult(out_t, out_e, nll.value, it.value, calls.value, st)
 
+    _STATS = {"poisson": 0, "chi2": 1}
+
+    @staticmethod
+    def _counts(counts: torch.Tensor):
+        if not isinstance(counts, torch.Tensor) or not counts.is_cuda or counts.dtype != torch.float64:
+            raise TypeError("counts must be a float64 CUDA tensor")
+        if counts.dim() != 1 or (counts.numel() > 1 and counts.stride(0) != 1):
+            raise ValueError("counts must be a contiguous 1-D tensor")
+        return C.c_void_p(counts.data_ptr() if counts.numel() else 0), counts.numel()
+
+    def nll_binned(self, theta, counts: torch.Tensor, stat: str = "poisson", grad: bool = False, stream=None):
+        """mix1d: binned Poisson NLL or chi^2 of histogram counts on uniform bins
+        over [lo, hi] (fn_nll_binned); (value, gradient) when grad=True."""
+        th, thp = self._theta(theta)
+        cp, nb = self._counts(counts)
+        v = C.c_double()
+        g = np.zeros(self.n_params)
+        check(self._lib.fn_nll_binned(self._h, thp, cp, nb, self._STATS[stat], C.byref(v),
+                                      g.ctypes.data_as(C.POINTER(C.c_double)) if grad else None,
+                                      _stream_ptr(stream)))
+        return (v.value, g) if grad else v.value
+
+    def fit_binned(self, theta0, counts: torch.Tensor, stat: str = "poisson", free=None,
+                   grad_mode: str = "adjoint", tol: float = 1e-7, max_iter: int = 500, errors: bool = True,
+                   stream=None, raise_on_fail: bool = True) -> FitResult:
+        """Quasi-Newton fit of binned data (fn_fit_binned); FitResult.nll holds
+        the minimum of the statistic."""
+        th, thp = self._theta(theta0)
+        cp, nb = self._counts(counts)
+        mask = None
+        if free is not None:
+            mk = np.ascontiguousarray(np.asarray(free, dtype=np.int32))
+            mask = mk.ctypes.data_as(C.POINTER(C.c_int32))
+        out_t = np.zeros(self.n_params)
+        out_e = np.zeros(self.n_params)
+        val = C.c_double()
+        it, calls = C.c_int32(), C.c_int32()
+        st = self._lib.fn_fit_binned(self._h, thp, mask, cp, nb, self._STATS[stat],
+                                     0 if grad_mode == "adjoint" else 1, tol, max_iter,
+                                     out_t.ctypes.data_as(C.POINTER(C.c_double)),
+                                     out_e.ctypes.data_as(C.POINTER(C.c_double)) if errors else None,
+                                     C.byref(val), C.byref(it), C.byref(calls), _stream_ptr(stream))
+        if st != _lib.FN_OK and raise_on_fail:
+            check(st)
+        return FitResult(out_t, out_e, val.value, it.value, calls.value, st)
+
 
 class NLLFunction(torch.autograd.Function):
     """NLL as a differentiable function of theta (a float64 CPU tensor).

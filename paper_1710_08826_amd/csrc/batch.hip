@@ -201,7 +201,8 @@ __global__ __launch_bounds__(kBlock) void batch_finalize(Mix1dConst mc, const Mi
   const int f = blockIdx.x;
   if (stat[f] != kFitRunning) return;
   const int64_t rows = (nev[f] + chunk - 1) / chunk;
-  mix1d_finalize_one(mc, tabs[f], part + part_base[f] * nv, rows, nv, kmax, 1, out + (int64_t)f * out_stride,
+  mix1d_finalize_one(mc, tabs[f], part + part_base[f] * nv, rows, nv, kmax, 1, (double)nev[f],
+                     out + (int64_t)f * out_stride,
                      nullptr, scratch, res);
 }
 

@@ -26,7 +26,13 @@ struct Objective {
   int grad_mode;                // 0 adjoint, 1 central differences
   std::vector<int> free_idx;    // indices of free parameters
   std::vector<double> full;     // full theta (fixed entries stay)
+  const BinnedData* binned = nullptr;  // binned data instead of events
   long long calls = 0;
+
+  void value(const double* th, double* f, double* g) {
+    if (binned) nll_binned_host(m, th, *binned, f, g, s);
+    else nll_host(m, th, ev, n, ld, f, g, s);
+  }
 
   int dim() const { return (int)free_idx.size(); }
 
@@ -54,7 +60,7 @@ struct Objective {
     }
     calls += 1;
     try {
-      nll_host(m, full.data(), ev, n, ld, &f, gfull.data(), s);
+      value(full.data(), &f, gfull.data());
     } catch (const Error& e) {
       if (e.code == FN_E_NONFINITE) return false;
       throw;
@@ -67,7 +73,7 @@ struct Objective {
   bool nll_only(const std::vector<double>& th, double& f) {
     calls += 1;
     try {
-      nll_host(m, th.data(), ev, n, ld, &f, nullptr, s);
+      value(th.data(), &f, nullptr);
     } catch (const Error& e) {
       if (e.code == FN_E_NONFINITE) return false;
       throw;
@@ -222,12 +228,13 @@ bool numerical_inverse_hessian(Objective& obj, const std::vector<double>& x, con
 }
 
 void fit_host(fn_model* m, const double* theta0, const int32_t* mask, const double* ev, int64_t n, int64_t ld,
-              int grad_mode, double tol, int max_iter, double* theta_out, double* err_out, double* nll_out,
-              int32_t* n_iter_out, int32_t* n_calls_out, hipStream_t s) {
+              const BinnedData* binned, int grad_mode, double tol, int max_iter, double* theta_out, double* err_out,
+              double* nll_out, int32_t* n_iter_out, int32_t* n_calls_out, hipStream_t s) {
   if (!theta0) throw Error(FN_E_INVALID, "theta0 is NULL");
   if (grad_mode != 0 && grad_mode != 1) throw Error(FN_E_INVALID, "grad_mode must be 0 or 1");
-  check_events_args(m, ev, n, ld);
+  if (!binned) check_events_args(m, ev, n, ld);
   Objective obj{m, ev, n, ld, s, grad_mode, {}, std::vector<double>(theta0, theta0 + m->P)};
+  obj.binned = binned;
   for (int p = 0; p < m->P; ++p)
     if (!mask || mask[p]) obj.free_idx.push_back(p);
   const int D = obj.dim();
@@ -334,7 +341,9 @@ void fit_host(fn_model* m, const double* theta0, const int32_t* mask, const doub
     } else if (numerical_inverse_hessian(obj, x, H, Hn)) {
       C = &Hn;
     }
-    for (int i = 0; i < D; ++i) err_out[obj.free_idx[i]] = std::sqrt(std::fabs((*C)[i * D + i]));
+    // error definition: 1/2 for an NLL, 1 for chi^2 (covariance 2 H^-1)
+    const double up2 = binned && binned->stat == 1 ? 2.0 : 1.0;
+    for (int i = 0; i < D; ++i) err_out[obj.free_idx[i]] = std::sqrt(up2 * std::fabs((*C)[i * D + i]));
   }
   if (n_iter_out) *n_iter_out = iter;
   if (n_calls_out) *n_calls_out = (int32_t)obj.calls;
@@ -350,7 +359,23 @@ extern "C" fn_status fn_fit(fn_model* m, const double* theta0_host, const int32_
   return fn::guard([&] {
     if (!m) throw fn::Error(FN_E_INVALID, "model is NULL");
     fn::hip_check(hipSetDevice(m->device), "hipSetDevice");
-    fn::fit_host(m, theta0_host, free_mask, ev, n, ld, grad_mode, tol, max_iter, theta_out, err_out, nll_out, n_iter,
-                 n_calls, (hipStream_t)stream);
+    fn::fit_host(m, theta0_host, free_mask, ev, n, ld, nullptr, grad_mode, tol, max_iter, theta_out, err_out,
+                 nll_out, n_iter, n_calls, (hipStream_t)stream);
+  });
+}
+
+extern "C" fn_status fn_fit_binned(fn_model* m, const double* theta0_host, const int32_t* free_mask,
+                                   const double* counts_dev, int64_t n_bins, int32_t stat, int32_t grad_mode,
+                                   double tol, int32_t max_iter, double* theta_out, double* err_out,
+                                   double* value_out, int32_t* n_iter, int32_t* n_calls, void* stream) {
+  return fn::guard([&] {
+    if (!m) throw fn::Error(FN_E_INVALID, "model is NULL");
+    if (m->kind != fn::kKindMix1d) throw fn::Error(FN_E_INVALID, "binned data: mix1d models only");
+    if (n_bins < 1 || !counts_dev) throw fn::Error(FN_E_INVALID, "binned data: need n_bins >= 1 and counts");
+    if (stat != 0 && stat != 1) throw fn::Error(FN_E_INVALID, "stat must be 0 (Poisson) or 1 (chi^2)");
+    fn::hip_check(hipSetDevice(m->device), "hipSetDevice");
+    const fn::BinnedData bd{counts_dev, n_bins, stat};
+    fn::fit_host(m, theta0_host, free_mask, nullptr, 0, 0, &bd, grad_mode, tol, max_iter, theta_out, err_out,
+                 value_out, n_iter, n_calls, (hipStream_t)stream);
   });
 }

@@ -91,6 +91,15 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
 void nll_host(fn_model* m, const double* theta_host, const double* ev, int64_t n, int64_t ld, double* nll,
               double* grad, hipStream_t s);
 void check_events_args(fn_model* m, const double* ev, int64_t n, int64_t ld);
+// Binned data of a mix1d model: counts of nb uniform bins on [lo, hi] (device),
+// statistic 0 Poisson NLL, 1 chi^2.
+struct BinnedData {
+  const double* counts;
+  int64_t nb;
+  int stat;
+};
+void nll_binned_host(fn_model* m, const double* theta_host, const BinnedData& bd, double* value, double* grad,
+                     hipStream_t s);
 // td4 fixed-constant vector ((m0, Gamma0) of every r12 entry, then of every
 // r34 entry, then sigma_t) -> per-fit constants; throws on invalid values.
 Td4FitConst td4_fit_const(const Td4Const& tc, const double* fixed);

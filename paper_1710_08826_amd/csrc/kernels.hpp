@@ -16,16 +16,14 @@ void mix1d_launch_prologue(const Mix1dConst& mc, const ParamBlock& pb, const dou
 void mix1d_launch_events(const Mix1dConst& mc, const Mix1dTable* tab, const double* x, int64_t n, int chunk,
                          int64_t nchunks, bool grad, double* part, hipStream_t s);
 void mix1d_launch_finalize(const Mix1dConst& mc, const Mix1dTable* tab, const double* part, int64_t nrows,
-                           bool grad, double* out, double* out_user, hipStream_t s);
-// Many fits in one launch: work items (fit, chunk); then one level-2
-// workgroup per fit writing out + fit * out_stride.
-void mix1d_launch_events_batched(const Mix1dConst& mc, const Mix1dTable* tabs, const double* const* ev,
-                                 const int64_t* n, const int32_t* item_fit, const int64_t* item_chunk,
-                                 const int64_t* part_base, int64_t n_items, int chunk, bool grad, double* part,
-                                 hipStream_t s);
-void mix1d_launch_finalize_batched(const Mix1dConst& mc, const Mix1dTable* tabs, const double* part,
-                                   const int64_t* part_base, const int64_t* nrows, int n_fits, bool grad,
-                                   double* out, int out_stride, hipStream_t s);
+                           bool grad, double n_events, double* out, double* out_user, hipStream_t s);
+// Binned data (counts of nb uniform bins on [lo, hi]): bins pass (one row per
+// chunk of bins) and level-2 step; stat 0 Poisson NLL, 1 chi^2; out = [F, grad(P)].
+int mix1d_nv_binned(int kmax, bool grad);
+// nbuf: one device double of scratch (the total count for chi^2 without a yield).
+void mix1d_launch_binned(const Mix1dConst& mc, const Mix1dTable* tab, const double* counts, int64_t nb, int chunk,
+                         int64_t nchunks, int stat, bool grad, double* part, double* nbuf, double* out,
+                         hipStream_t s);
 void mix1d_launch_eval(const Mix1dConst& mc, const Mix1dTable* tab, const double* x, int64_t n, double* p,
                        hipStream_t s);
 void mix1d_launch_check(const Mix1dConst& mc, const double* x, int64_t n, unsigned long long* bad, hipStream_t s);

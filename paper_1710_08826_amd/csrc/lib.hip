@@ -121,6 +121,15 @@ static void compile_mix1d(const json::Value& d, fn_model* m) {
     if (np < P || np > kMaxParams) throw Error(FN_E_INVALID, "mix1d: n_params smaller than the indices used");
     P = (int)np;
   }
+  mc.yidx = -1;
+  if (d.has("yield")) {
+    const long idx = d.at("yield").integer();
+    if (idx < 0 || idx >= kMaxParams) throw Error(FN_E_INVALID, "mix1d: yield index out of range");
+    mc.yidx = (int)idx;
+    if (idx + 1 > P) P = (int)idx + 1;
+    if (d.has("n_params") && d.at("n_params").integer() < idx + 1)
+      throw Error(FN_E_INVALID, "mix1d: n_params smaller than the indices used");
+  }
   mc.n_params = P;
   m->P = P;
   m->n_obs = 1;
@@ -334,7 +343,7 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
       hip_check(hipEventRecord(t1, s), "hipEventRecord");
       m->ev_pending.emplace_back(t0, t1);
     }
-    mix1d_launch_finalize(mc, m->table_mix(), m->part(), nch, grad, m->out(), out_user, s);
+    mix1d_launch_finalize(mc, m->table_mix(), m->part(), nch, grad, (double)n, m->out(), out_user, s);
   } else if (m->kind == kKindTd4) {
     const Td4Const& tc = m->td4;
     if (m->n_mc <= 0) throw Error(FN_E_INVALID, "td4: normalization sample not set (fn_model_set_norm_sample)");
@@ -454,6 +463,39 @@ void nll_host(fn_model* m, const double* theta_host, const double* ev, int64_t n
   if (grad)
     for (int p = 0; p < m->P; ++p) gbad |= !std::isfinite(grad[p]);
   if (nll) *nll = v;
+  if (gbad) throw Error(FN_E_NONFINITE, "gradient is not finite");
+}
+
+void nll_binned_host(fn_model* m, const double* theta_host, const BinnedData& bd, double* value, double* grad,
+                     hipStream_t s) {
+  if (m->kind != kKindMix1d) throw Error(FN_E_INVALID, "binned data: mix1d models only");
+  if (bd.nb < 1 || !bd.counts) throw Error(FN_E_INVALID, "binned data: need n_bins >= 1 and a counts pointer");
+  if (bd.stat != 0 && bd.stat != 1) throw Error(FN_E_INVALID, "binned data: stat must be 0 (Poisson) or 1 (chi^2)");
+  const ParamBlock pb = make_block(m, theta_host);
+  const Mix1dConst& mc = m->mix;
+  const bool g = grad != nullptr;
+  mix1d_launch_prologue(mc, pb, nullptr, 1, 0, m->table_mix(), s);
+  const int64_t nch = nchunks_for(bd.nb, m->chunk);
+  m->d_part.reserve(sizeof(double) * (size_t)nch * mix1d_nv_binned(mix1d_kmax(mc.K), g));
+  m->d_gen.reserve(3 * sizeof(unsigned long long));
+  mix1d_launch_binned(mc, m->table_mix(), bd.counts, bd.nb, m->chunk, nch, bd.stat, g, m->part(),
+                      (double*)m->d_gen.ptr, m->out(), s);
+  hip_check(hipGetLastError(), "kernel launch");
+  const size_t cnt = (size_t)(g ? 1 + m->P : 1);
+  hip_check(hipMemcpyAsync(m->h_out, m->out(), sizeof(double) * cnt, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+  hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+  m->stats_calls += 1;
+  const double v = m->h_out[0];
+  bool gbad = false;
+  if (g)
+    for (int p = 0; p < m->P; ++p) {
+      grad[p] = m->h_out[1 + p];
+      gbad |= !std::isfinite(grad[p]);
+    }
+  if (value) *value = std::isfinite(v) ? v : INFINITY;
+  if (!std::isfinite(v))
+    throw Error(FN_E_NONFINITE, "binned statistic is not finite (P <= 0 in a filled bin, invalid parameters, "
+                                "or no events)");
   if (gbad) throw Error(FN_E_NONFINITE, "gradient is not finite");
 }
 
@@ -701,6 +743,16 @@ fn_status fn_eval(fn_model* m, const double* theta_host, const double* ev, int64
     else dalitz_launch_eval(m->dal, m->table_dal(), ev, ld, n, m->out() + 1 + m->P, p_dev, s);
     hip_check(hipGetLastError(), "kernel launch");
     hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+  });
+}
+
+fn_status fn_nll_binned(fn_model* m, const double* theta_host, const double* counts_dev, int64_t n_bins,
+                        int32_t stat, double* value_host, double* grad_host, void* stream) {
+  return guard([&] {
+    if (!m || !theta_host) throw Error(FN_E_INVALID, "NULL argument");
+    hip_check(hipSetDevice(m->device), "hipSetDevice");
+    nll_binned_host(m, theta_host, BinnedData{counts_dev, n_bins, stat}, value_host, grad_host,
+                    (hipStream_t)stream);
   });
 }
 

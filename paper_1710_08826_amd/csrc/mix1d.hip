@@ -40,43 +40,41 @@ __global__ __launch_bounds__(kBlock) void mix1d_events(Mix1dConst mc, const Mix1
   mix1d_chunk<GRAD, KMAX>(mc, tab, x, n, blockIdx.x, chunk, part + (int64_t)blockIdx.x * NV, lds);
 }
 
-// Batched form: work item w = (fit, chunk) from a flat list; per-fit tables,
-// event pointers, sizes and row bases come from device arrays.  The chunk
-// routine is the one the single-fit kernel runs, so a fit's rows hold the same
-// bits alone and in a batch.
-template <bool GRAD, int KMAX>
-__global__ __launch_bounds__(kBlock) void mix1d_events_batched(
-    Mix1dConst mc, const Mix1dTable* __restrict__ tabs, const double* const* __restrict__ ev,
-    const int64_t* __restrict__ n, const int32_t* __restrict__ item_fit,
-    const int64_t* __restrict__ item_chunk, const int64_t* __restrict__ part_base, int chunk,
-    double* __restrict__ part) {
-  constexpr int NV = GRAD ? mix_nv(KMAX) : 1;
-  __shared__ double lds[block_sum_lds(NV)];
-  const int fit = item_fit[blockIdx.x];
-  const int64_t ch = item_chunk[blockIdx.x];
-  mix1d_chunk<GRAD, KMAX>(mc, tabs + fit, ev[fit], n[fit], ch, chunk, part + (part_base[fit] + ch) * NV, lds);
-}
-
-// Batched level-2: one workgroup per fit, output rows of stride out_stride.
-__global__ __launch_bounds__(kBlock) void mix1d_finalize_batched(
-    Mix1dConst mc, const Mix1dTable* __restrict__ tabs, const double* __restrict__ part,
-    const int64_t* __restrict__ part_base, const int64_t* __restrict__ nrows, int nv, int kmax,
-    int with_grad, double* __restrict__ out, int out_stride) {
-  __shared__ double scratch[kBlock];
-  __shared__ double res[kBlock];
-  const int f = blockIdx.x;
-  mix1d_finalize_one(mc, tabs[f], part + part_base[f] * nv, nrows[f], nv, kmax, with_grad,
-                     out + (int64_t)f * out_stride, nullptr, scratch, res);
-}
-
 // Level-2 step of a single fit.
 __global__ __launch_bounds__(kBlock) void mix1d_finalize(Mix1dConst mc, const Mix1dTable* __restrict__ tab,
                                                          const double* __restrict__ part, int64_t nrows,
-                                                         int nv, int kmax, int with_grad,
+                                                         int nv, int kmax, int with_grad, double n_events,
                                                          double* __restrict__ out, double* __restrict__ out_user) {
   __shared__ double scratch[kBlock];
   __shared__ double res[kBlock];
-  mix1d_finalize_one(mc, *tab, part, nrows, nv, kmax, with_grad, out, out_user, scratch, res);
+  mix1d_finalize_one(mc, *tab, part, nrows, nv, kmax, with_grad, n_events, out, out_user, scratch, res);
+}
+
+// Binned data: one workgroup per chunk of bins, then the level-2 step.
+template <bool GRAD, int KMAX, int STAT>
+__global__ __launch_bounds__(kBlock) void mix1d_binned(Mix1dConst mc, const Mix1dTable* __restrict__ tab,
+                                                       const double* __restrict__ counts, int64_t nb,
+                                                       const double* nptr, int chunk, double* __restrict__ part) {
+  constexpr int NV = mix1d_binned_nv<KMAX, STAT, GRAD>();
+  __shared__ double lds[block_sum_lds(NV)];
+  mix1d_binned_chunk<GRAD, KMAX, STAT>(mc, tab, counts, nb, nptr, blockIdx.x, chunk,
+                                       part + (int64_t)blockIdx.x * NV, lds);
+}
+
+__global__ __launch_bounds__(kBlock) void mix1d_binned_total(const double* __restrict__ part, int64_t nrows,
+                                                             double* __restrict__ total) {
+  __shared__ double scratch[kBlock];
+  __shared__ double res[kBlock];
+  mix1d_binned_total_one(part, nrows, total, scratch, res);
+}
+
+__global__ __launch_bounds__(kBlock) void mix1d_binned_finalize(Mix1dConst mc, const Mix1dTable* __restrict__ tab,
+                                                                const double* __restrict__ part, int64_t nrows,
+                                                                int nv, int kmax, int stat, int64_t nb,
+                                                                int with_grad, double* __restrict__ out) {
+  __shared__ double scratch[kBlock];
+  __shared__ double res[kBlock];
+  mix1d_binned_finalize_one(mc, *tab, part, nrows, nv, kmax, stat, nb, with_grad, out, scratch, res);
 }
 
 __global__ void mix1d_eval(Mix1dConst mc, const Mix1dTable* __restrict__ tab, const double* __restrict__ x,
@@ -122,37 +120,47 @@ void mix1d_launch_events(const Mix1dConst& mc, const Mix1dTable* tab, const doub
 }
 
 void mix1d_launch_finalize(const Mix1dConst& mc, const Mix1dTable* tab, const double* part, int64_t nrows,
-                           bool grad, double* out, double* out_user, hipStream_t s) {
+                           bool grad, double n_events, double* out, double* out_user, hipStream_t s) {
   const int kmax = mix1d_kmax(mc.K);
   hipLaunchKernelGGL(mix1d_finalize, dim3(1), dim3(kBlock), 0, s, mc, tab, part, nrows, mix1d_nv(kmax, grad),
-                     kmax, grad ? 1 : 0, out, out_user);
+                     kmax, grad ? 1 : 0, n_events, out, out_user);
 }
 
-void mix1d_launch_events_batched(const Mix1dConst& mc, const Mix1dTable* tabs, const double* const* ev,
-                                 const int64_t* n, const int32_t* item_fit, const int64_t* item_chunk,
-                                 const int64_t* part_base, int64_t n_items, int chunk, bool grad, double* part,
-                                 hipStream_t s) {
-  if (n_items == 0) return;
+int mix1d_nv_binned(int kmax, bool grad) {
+  // the largest row of the passes (Poisson: two gradient groups)
+  return kmax == 2 ? mix1d_binned_nv<2, 0, true>() : mix1d_binned_nv<8, 0, true>();
+}
+
+void mix1d_launch_binned(const Mix1dConst& mc, const Mix1dTable* tab, const double* counts, int64_t nb, int chunk,
+                         int64_t nchunks, int stat, bool grad, double* part, double* nbuf, double* out,
+                         hipStream_t s) {
   const int kmax = mix1d_kmax(mc.K);
-  const dim3 g((unsigned)n_items), b(kBlock);
-#define FN_MIXB(G, K)                                                                                        \
-  hipLaunchKernelGGL((mix1d_events_batched<G, K>), g, b, 0, s, mc, tabs, ev, n, item_fit, item_chunk, part_base, \
-                     chunk, part)
-  if (kmax == 2) {
-    if (grad) FN_MIXB(true, 2); else FN_MIXB(false, 2);
-  } else {
-    if (grad) FN_MIXB(true, 8); else FN_MIXB(false, 8);
+  const dim3 g((unsigned)nchunks), b(kBlock);
+  const double* nptr = nullptr;
+  if (stat == 1 && mc.yidx < 0) {
+    // chi^2 with N = W: the total count first
+    if (kmax == 2) hipLaunchKernelGGL((mix1d_binned<false, 2, 2>), g, b, 0, s, mc, tab, counts, nb, nullptr, chunk, part);
+    else hipLaunchKernelGGL((mix1d_binned<false, 8, 2>), g, b, 0, s, mc, tab, counts, nb, nullptr, chunk, part);
+    hipLaunchKernelGGL(mix1d_binned_total, dim3(1), dim3(kBlock), 0, s, part, nchunks, nbuf);
+    nptr = nbuf;
   }
-#undef FN_MIXB
-}
-
-void mix1d_launch_finalize_batched(const Mix1dConst& mc, const Mix1dTable* tabs, const double* part,
-                                   const int64_t* part_base, const int64_t* nrows, int n_fits, bool grad,
-                                   double* out, int out_stride, hipStream_t s) {
-  if (n_fits == 0) return;
-  const int kmax = mix1d_kmax(mc.K);
-  hipLaunchKernelGGL(mix1d_finalize_batched, dim3(n_fits), dim3(kBlock), 0, s, mc, tabs, part, part_base, nrows,
-                     mix1d_nv(kmax, grad), kmax, grad ? 1 : 0, out, out_stride);
+#define FN_BIN(G, K, S) \
+  hipLaunchKernelGGL((mix1d_binned<G, K, S>), g, b, 0, s, mc, tab, counts, nb, nptr, chunk, part)
+#define FN_BIN_K(G, S)            \
+  if (kmax == 2) FN_BIN(G, 2, S); \
+  else FN_BIN(G, 8, S)
+  if (stat == 0) {
+    if (grad) { FN_BIN_K(true, 0); } else { FN_BIN_K(false, 0); }
+  } else {
+    if (grad) { FN_BIN_K(true, 1); } else { FN_BIN_K(false, 1); }
+  }
+#undef FN_BIN_K
+#undef FN_BIN
+  const int nv = stat == 0 ? (kmax == 2 ? mix1d_binned_nv<2, 0, true>() : mix1d_binned_nv<8, 0, true>())
+                           : (kmax == 2 ? mix1d_binned_nv<2, 1, true>() : mix1d_binned_nv<8, 1, true>());
+  const int nv_used = grad ? nv : 3;
+  hipLaunchKernelGGL(mix1d_binned_finalize, dim3(1), dim3(kBlock), 0, s, mc, tab, part, nchunks, nv_used, kmax,
+                     stat, nb, grad ? 1 : 0, out);
 }
 
 void mix1d_launch_eval(const Mix1dConst& mc, const Mix1dTable* tab, const double* x, int64_t n, double* p,

@@ -117,6 +117,8 @@ __device__ inline void mix1d_table(const Mix1dConst& mc, const double* __restric
     t.dlnN[k][0] = d0;
     t.dlnN[k][1] = d1;
   }
+  t.yield = mc.yidx >= 0 ? th[mc.yidx] : 0.0;
+  if (mc.yidx >= 0 && !(t.yield > 0.0 && isfinite(t.yield))) ok = false;
   t.valid = ok ? 1.0 : 0.0;
   out = t;
 }
@@ -150,6 +152,27 @@ __device__ inline double mix_shape(int type, const Mix1dTable& t, int k, double 
   }
 }
 
+// slot[s] += w * dP/d(slot s) at one point: shape parameters of component k at
+// 2k, 2k + 1 (dP = f_k u_k (d ln s_k - d ln N_k)), fraction k < K-1 at
+// 2 KMAX + k (dP = u_k - u_{K-1}, the last component taking 1 - sum f).
+template <int KMAX>
+__device__ __forceinline__ void mix1d_add_dp(const Mix1dConst& mc, const Mix1dTable& t, const double (&u)[KMAX],
+                                             const double (&dl)[KMAX][2], double w, double* slot) {
+  double ul = 0.0;
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k)
+    if (k == mc.K - 1) ul = u[k];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    if (k < mc.K) {
+      const double wu = w * t.frac[k] * u[k];
+      slot[2 * k] += wu * (dl[k][0] - t.dlnN[k][0]);
+      slot[2 * k + 1] += wu * (dl[k][1] - t.dlnN[k][1]);
+      if (k < mc.K - 1) slot[2 * KMAX + k] += w * (u[k] - ul);
+    }
+  }
+}
+
 // One chunk of events -> one partial row (shared by the single-fit and the
 // batched launches so that both produce the same bits).
 template <bool GRAD, int KMAX>
@@ -176,55 +199,156 @@ __device__ inline void mix1d_chunk(const Mix1dConst& mc, const Mix1dTable* __res
       }
     }
     acc[0] -= log_fast(P);
-    if (GRAD) {
-      const double w = -rcp_nr(P);
-      double ul = 0.0;  // density of the last component (it takes 1 - sum f)
+    if (GRAD) mix1d_add_dp<KMAX>(mc, t, u, dl, -rcp_nr(P), acc + 1);
+  }
+  block_sum_row<NV>(acc, lds, out_row);
+}
+
+// Binned data: bin b of nb uniform bins on [lo, hi] holds n_b events, and the
+// density at its centre x_b = lo + (b + 1/2) Delta gives the expected count
+// nu_b = N Delta P(x_b).  One chunk of bins -> one partial row:
+//   STAT 0 (Poisson): [W, X, Y, dX slots, dY slots], W = sum n_b,
+//                     X = sum_b P_b, Y = sum_b n_b ln P_b (N enters at the end)
+//   STAT 1 (chi^2 over the bins with n_b > 0, N = *nptr):
+//                     [W, C, D, dC slots], C = sum (n_b - nu_b)^2 / n_b,
+//                     D = dC/dN = -2 Delta sum (n_b - nu_b) P_b / n_b
+//   STAT 2:           [W] (the total count, when N = W for chi^2)
+template <int KMAX, int STAT, bool GRAD>
+__host__ __device__ constexpr int mix1d_binned_nv() {
+  return STAT == 2 ? 1 : (GRAD ? 3 + (STAT == 0 ? 2 : 1) * (mix_nv(KMAX) - 1) : 3);
+}
+
+template <bool GRAD, int KMAX, int STAT>
+__device__ inline void mix1d_binned_chunk(const Mix1dConst& mc, const Mix1dTable* __restrict__ tabp,
+                                          const double* __restrict__ counts, int64_t nb, const double* nptr,
+                                          int64_t chunk_idx, int chunk, double* __restrict__ out_row, double* lds) {
+  constexpr int G = mix_nv(KMAX) - 1;
+  constexpr int NV = mix1d_binned_nv<KMAX, STAT, GRAD>();
+  const Mix1dTable& t = *tabp;
+  double acc[NV];
 #pragma unroll
-      for (int k = 0; k < KMAX; ++k)
-        if (k == mc.K - 1) ul = u[k];
+  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+  const double delta = (mc.hi - mc.lo) / (double)nb;
+  const double N = STAT == 1 ? (nptr ? *nptr : t.yield) : 0.0;
+  const int64_t base = chunk_idx * chunk;
+  const int64_t end = base + chunk < nb ? base + chunk : nb;
+  for (int64_t b = base + threadIdx.x; b < end; b += kBlock) {
+    const double n = counts[b];
+    acc[0] += n;
+    if (STAT == 2) continue;
+    const double xv = mc.lo + ((double)b + 0.5) * delta;
+    double u[KMAX], dl[KMAX][2];
+    double P = 0.0;
 #pragma unroll
-      for (int k = 0; k < KMAX; ++k) {
-        if (k < mc.K) {
-          const double wu = w * t.frac[k] * u[k];
-          acc[1 + 2 * k] += wu * (dl[k][0] - t.dlnN[k][0]);
-          acc[2 + 2 * k] += wu * (dl[k][1] - t.dlnN[k][1]);
-          if (k < mc.K - 1) acc[1 + 2 * KMAX + k] += w * (u[k] - ul);
-        }
+    for (int k = 0; k < KMAX; ++k) {
+      u[k] = 0.0; dl[k][0] = 0.0; dl[k][1] = 0.0;
+      if (k < mc.K) {
+        u[k] = mix_shape<GRAD>(mc.type[k], t, k, xv, dl[k][0], dl[k][1]) * t.invN[k];
+        P += t.frac[k] * u[k];
       }
+    }
+    if (STAT == 0) {
+      acc[1] += P;
+      const double cy = n != 0.0 ? n * rcp_nr(P) : 0.0;
+      if (n != 0.0) acc[2] += n * log_fast(P);
+      if (GRAD) {
+        mix1d_add_dp<KMAX>(mc, t, u, dl, 1.0, acc + 3);
+        mix1d_add_dp<KMAX>(mc, t, u, dl, cy, acc + 3 + G);
+      }
+    } else if (n > 0.0) {
+      const double in = 1.0 / n;
+      const double r = n - N * delta * P;  // n_b - nu_b
+      acc[1] += r * r * in;
+      acc[2] -= 2.0 * delta * r * P * in;
+      if (GRAD) mix1d_add_dp<KMAX>(mc, t, u, dl, -2.0 * N * delta * r * in, acc + 3);
     }
   }
   block_sum_row<NV>(acc, lds, out_row);
 }
 
-// Level 2 and the slot -> parameter map (slots sharing a parameter are added
-// in slot order).  out: [NLL, grad(P), I = 1, dI = 0]; out_user: [NLL, grad(P)].
+// Gradient of parameter p from gradient slots (slots sharing a parameter are
+// added in slot order).
+__device__ inline double mix1d_param_grad(const Mix1dConst& mc, int kmax, const double* slots, int p) {
+  double g = 0.0;
+  for (int k = 0; k < mc.K; ++k) {
+    for (int j = 0; j < mc.npar[k]; ++j)
+      if (mc.pidx[k][j] == p) g += slots[2 * k + j];
+    if (k < mc.K - 1 && mc.fidx[k] == p) g += slots[2 * kmax + k];
+  }
+  return g;
+}
+
+// Level 2 and the slot -> parameter map; with an expected yield nu (extended
+// likelihood) NLL gains nu - N ln nu and d/dnu = 1 - N/nu.
+// out: [NLL, grad(P), I = 1, dI = 0]; out_user: [NLL, grad(P)].
 __device__ inline void mix1d_finalize_one(const Mix1dConst& mc, const Mix1dTable& t,
                                           const double* part, int64_t nrows, int nv, int kmax,
-                                          int with_grad, double* out, double* out_user, double* scratch,
-                                          double* res) {
+                                          int with_grad, double n_events, double* out, double* out_user,
+                                          double* scratch, double* res) {
   sum_rows(part, nrows, nv, scratch, res);
   const int P = mc.n_params;
   const int p = threadIdx.x;
   const bool ok = t.valid != 0.0;
+  const bool ext = mc.yidx >= 0;
   if (p == 0) {
-    out[0] = ok ? res[0] : INFINITY;
+    double v = res[0];
+    if (ext) v += t.yield - n_events * log(t.yield);
+    out[0] = ok ? v : INFINITY;
     out[1 + P] = 1.0;
     if (out_user) out_user[0] = out[0];
   }
   if (p < P) {
     out[2 + P + p] = 0.0;
     if (with_grad) {
-      double g = 0.0;
-      for (int k = 0; k < mc.K; ++k) {
-        for (int j = 0; j < mc.npar[k]; ++j)
-          if (mc.pidx[k][j] == p) g += res[1 + 2 * k + j];
-        if (k < mc.K - 1 && mc.fidx[k] == p) g += res[1 + 2 * kmax + k];
-      }
+      double g = mix1d_param_grad(mc, kmax, res + 1, p);
+      if (ext && p == mc.yidx) g += 1.0 - n_events / t.yield;
       if (!ok) g = NAN;
       out[1 + p] = g;
       if (out_user) out_user[1 + p] = g;
     }
   }
+}
+
+// Level 2 of binned data and the statistic, N the yield parameter (extended)
+// or the total count W:
+//   Poisson  F = sum_b (nu_b - n_b ln nu_b) = N Delta X - W ln(N Delta) - Y
+//   chi^2    F = C
+// out: [F, grad(P)].
+__device__ inline void mix1d_binned_finalize_one(const Mix1dConst& mc, const Mix1dTable& t, const double* part,
+                                                 int64_t nrows, int nv, int kmax, int stat, int64_t nb,
+                                                 int with_grad, double* out, double* scratch, double* res) {
+  sum_rows(part, nrows, nv, scratch, res);
+  const int P = mc.n_params;
+  const int G = 3 * kmax;
+  const int p = threadIdx.x;
+  const bool ok = t.valid != 0.0;
+  const bool ext = mc.yidx >= 0;
+  const double W = res[0];
+  const double delta = (mc.hi - mc.lo) / (double)nb;
+  const double N = ext ? t.yield : W;
+  const double nd = N * delta;
+  if (p == 0) {
+    const double v = stat == 0 ? nd * res[1] - W * log(nd) - res[2] : res[1];
+    out[0] = ok ? v : INFINITY;
+  }
+  if (with_grad && p < P) {
+    double g;
+    if (stat == 0) {
+      g = nd * mix1d_param_grad(mc, kmax, res + 3, p) - mix1d_param_grad(mc, kmax, res + 3 + G, p);
+      if (ext && p == mc.yidx) g += delta * res[1] - W / N;
+    } else {
+      g = mix1d_param_grad(mc, kmax, res + 3, p);
+      if (ext && p == mc.yidx) g += res[2];
+    }
+    out[1 + p] = ok ? g : NAN;
+  }
+}
+
+// Total of the rows' first entries into *total (one workgroup).
+__device__ inline void mix1d_binned_total_one(const double* part, int64_t nrows, double* total, double* scratch,
+                                              double* res) {
+  sum_rows(part, nrows, 1, scratch, res);
+  if (threadIdx.x == 0) *total = res[0];
 }
 
 }  // namespace fn

@@ -35,6 +35,7 @@ struct Mix1dConst {
   int pidx[kMixMaxComp][2];       // parameter indices of each component
   int npar[kMixMaxComp];          // 1 or 2
   int fidx[kMixMaxComp];          // fraction index for k < K-1
+  int yidx;                       // expected-yield parameter (extended likelihood), -1 for none
 };
 
 // Gradient slots of a mix1d partial: [0] NLL, then 2 per component (its shape
@@ -49,6 +50,7 @@ struct Mix1dTable {
   double b[kMixMaxComp];          // gauss: 1/sigma        argus: c       bw: gamma^2/4
   double c[kMixMaxComp];          // argus: 1/m0            bw: gamma
   double dlnN[kMixMaxComp][2];    // d ln N_k / d (its parameters)
+  double yield;                   // expected yield (extended likelihood), 0 when none
   double valid;                   // 1 when the parameters define a density
 };
 

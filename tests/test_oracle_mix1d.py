@@ -174,3 +174,84 @@ def test_pulls_unit_width():
     pulls = np.array(pulls)
     assert (np.abs(pulls.mean(0)) < 0.35).all(), pulls.mean(0)
     assert (np.abs(pulls.std(0) - 1) < 0.25).all(), pulls.std(0)
+
+
+# ------------------------------------------------ extended and binned data
+def _ext(desc, idx):
+    return dict(desc, n_params=idx + 1, **{"yield": idx})
+
+
+def test_extended_yield_mle_is_the_event_count():
+    """d/dnu (nu - N ln nu) vanishes at nu = N, and the extended NLL exceeds
+    the plain one by exactly that term, which is smallest there."""
+    d = mix1d.config0_desc()
+    de = _ext(d, 4)
+    x = synth.mix1d_events(500, seed=3)
+    th = np.array(list(synth.CONFIG0_TRUTH) + [500.0])
+    v, g = mix1d.nll_grad(th, x, de)
+    assert abs(g[4]) < 1e-12
+    v0 = mix1d.nll(th[:4], x, d)
+    assert abs((v - v0) - (500.0 - 500.0 * math.log(500.0))) < 1e-9
+    for s in (0.999, 1.001):
+        assert mix1d.nll(np.r_[th[:4], 500.0 * s], x, de) > v
+
+
+def test_binned_poisson_with_events_at_bin_centres():
+    """Events placed at bin centres (several per bin for some bins): the
+    binned Poisson NLL equals N Delta sum_b P_b - N ln(N Delta) plus the
+    unbinned NLL of those events."""
+    d = mix1d.config0_desc()
+    nb = 400
+    rng = np.random.default_rng(4)
+    counts = np.zeros(nb)
+    idx = rng.integers(0, nb, 300)
+    np.add.at(counts, idx, 1.0)
+    x = mix1d.bin_centres(d, nb)[idx]
+    th = np.array(synth.CONFIG0_TRUTH) * np.array([1.1, 0.95, 1.05, 0.97])
+    N = counts.sum()
+    delta = 20.0 / nb
+    with torch.no_grad():
+        psum = float(mix1d.density(common.as_t(th), common.as_t(mix1d.bin_centres(d, nb)), d).sum())
+    expect = N * delta * psum - N * math.log(N * delta) + mix1d.nll(th, x, d)
+    v, _ = mix1d.binned_value_grad(th, counts, d, "poisson")
+    assert abs(v - expect) < 1e-9 * abs(expect)
+
+
+def test_extended_binned_yield_mle():
+    """Extended binned Poisson: d/dnu vanishes at nu = W / (Delta sum_b P_b)."""
+    d = _ext(mix1d.config0_desc(), 4)
+    nb = 250
+    counts = np.histogram(synth.mix1d_events(4000, seed=5), bins=nb, range=(-10.0, 10.0))[0].astype(np.float64)
+    th4 = np.array(synth.CONFIG0_TRUTH)
+    with torch.no_grad():
+        psum = float(mix1d.density(common.as_t(th4), common.as_t(mix1d.bin_centres(d, nb)), d).sum())
+    nu = counts.sum() / ((20.0 / nb) * psum)
+    _, g = mix1d.binned_value_grad(np.r_[th4, nu], counts, d, "poisson")
+    assert abs(g[4]) < 1e-10
+
+
+def test_chi2_vanishes_at_the_expected_counts():
+    d = _ext(mix1d.config0_desc(), 4)
+    nb = 64
+    th = np.r_[np.array(synth.CONFIG0_TRUTH), 1.0e4]
+    with torch.no_grad():
+        p = mix1d.density(common.as_t(th), common.as_t(mix1d.bin_centres(d, nb)), d).numpy()
+    counts = th[4] * (20.0 / nb) * p
+    v, g = mix1d.binned_value_grad(th, counts, d, "chi2")
+    assert v < 1e-20 and np.max(np.abs(g)) < 1e-12
+
+
+@pytest.mark.parametrize("stat", ["poisson", "chi2"])
+@pytest.mark.parametrize("ext", [False, True])
+def test_binned_autograd_vs_central_fd(stat, ext):
+    d = mix1d.config0_desc()
+    if ext:
+        d = _ext(d, 4)
+    nb = 120
+    counts = np.histogram(synth.mix1d_events(3000, seed=6), bins=nb, range=(-10.0, 10.0))[0].astype(np.float64)
+    th = np.array(synth.CONFIG0_TRUTH) * np.array([1.1, 0.95, 1.05, 0.97])
+    if ext:
+        th = np.r_[th, 2900.0]
+    _, g = mix1d.binned_value_grad(th, counts, d, stat)
+    fd = common.central_fd(lambda t: mix1d.binned_value_grad(t, counts, d, stat)[0], th, rel_step=1e-6)
+    assert np.allclose(g, fd, rtol=1e-6, atol=1e-6 * np.max(np.abs(fd)))
