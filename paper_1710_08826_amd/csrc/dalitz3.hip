@@ -359,6 +359,11 @@ void dalitz_launch_mrows(const DalitzJit& j, const DalitzConst& dc, const Dalitz
                          int64_t nchunks, int i0, double* part, double* Mc, hipStream_t s) {
   const int64_t ncell = (int64_t)dc.nx * dc.ny;
   launch_pass(j.mrows, dc, tab, nullptr, nullptr, 0, ncell, chunk, nchunks, i0, part, s);
+  dalitz_launch_mrows_finalize(dc, part, nchunks, i0, Mc, s);
+}
+
+void dalitz_launch_mrows_finalize(const DalitzConst& dc, const double* part, int64_t nchunks, int i0, double* Mc,
+                                  hipStream_t s) {
   const int kmax = dalitz_kmax(dc.K);
   hipLaunchKernelGGL(dalitz_mrows_finalize, dim3(1), dim3(kBlock), 0, s, dc, part, nchunks,
                      dal_nv(kMRows, 0, kmax), kmax, i0, Mc);

@@ -12,6 +12,7 @@
 #include "kernels.hpp"
 #include "model.hpp"
 #include "td4.hpp"
+#include "tddp.hpp"
 
 namespace fn {
 
@@ -36,7 +37,7 @@ struct DevBuf {
   ~DevBuf() { release(); }
 };
 
-enum ModelKind : int { kKindMix1d = 1, kKindDalitz3 = 2, kKindTd4 = 3 };
+enum ModelKind : int { kKindMix1d = 1, kKindDalitz3 = 2, kKindTd4 = 3, kKindTddp3 = 4 };
 
 }  // namespace fn
 
@@ -57,6 +58,8 @@ struct fn_model {
   fn::Td4Const td4;
   std::shared_ptr<fn::DalitzJit> dal_jit;  // structure-specialized passes
   std::shared_ptr<fn::Td4Jit> td4_jit;
+  std::shared_ptr<fn::TddpJit> tddp_jit;  // time-dependent Dalitz passes
+  fn::TddpTime tdt;                        // its decay-time constants
   std::vector<double> fixed_ls;  // (m0, Gamma0) per resonance when not free; td4: fixed-constant vector
   int64_t n_mc = 0;              // td4 normalization sample size (0 = not set)
   int64_t mc_gen = 0;            // bumped whenever the sample is replaced
@@ -64,6 +67,7 @@ struct fn_model {
   bool table_ready = false;      // fixed lineshapes: the table's lineshape constants are built
   fn::DevBuf d_table, d_part, d_npart, d_out, d_fixed, d_M, d_count, d_mc, d_gen;
   double box[4] = {0.0, 0.0, 0.0, 0.0};  // Dalitz: kinematic box (s12 lo, hi, s13 lo, hi)
+  fn::DevBuf d_theta;                    // tddp3: theta on the device for host-theta calls
   double* h_out = nullptr;       // pinned
   long long stats_calls = 0;
   int timing = 0;                // bracket every timing-th event-pass launch with HIP events (0 = off)

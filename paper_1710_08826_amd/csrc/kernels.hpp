@@ -57,6 +57,10 @@ void dalitz_launch_finalize(const DalitzConst& dc, const DalitzTable* tab, const
                             const double* Mc, double n_events, double* out, double* out_user, hipStream_t s);
 void dalitz_launch_grid(const DalitzJit& j, const DalitzConst& dc, const DalitzTable* tab, const double* coef,
                         int chunk, int64_t nchunks, int grad, double* part, hipStream_t s);
+// Level-2 of a row-block pass of K x K matrices (rows i0..i0+3, 2 K doubles
+// each per chunk row) into Mc, scaled by the cell area.
+void dalitz_launch_mrows_finalize(const DalitzConst& dc, const double* part, int64_t nchunks, int i0, double* Mc,
+                                  hipStream_t s);
 void dalitz_launch_mrows(const DalitzJit& j, const DalitzConst& dc, const DalitzTable* tab, int chunk,
                          int64_t nchunks, int i0, double* part, double* Mc, hipStream_t s);
 // Toy events: vmax (zeroed by the caller) receives the bits of the largest P~

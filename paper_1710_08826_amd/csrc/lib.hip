@@ -224,6 +224,33 @@ static void compile_dalitz3(const json::Value& d, fn_model* m, bool device = tru
   m->d_M.reserve(sizeof(double) * 2 * dc.K * dc.K);
 }
 
+static void compile_tddp3(const json::Value& d, fn_model* m, bool device = true) {
+  if (d.has("free_lineshapes") && d.at("free_lineshapes").boolean())
+    throw Error(FN_E_INVALID, "tddp3: the lineshapes are fixed");
+  compile_dalitz3(d, m, false);  // kinematics, grid and resonances of the three-body model
+  const auto& ms = d.at("m").array();
+  if (ms[1].number() != ms[2].number())
+    throw Error(FN_E_INVALID, "tddp3: daughters 2 and 3 must be charge conjugates (equal masses)");
+  const DalitzConst& dc = m->dal;
+  if (dc.nx != dc.ny) throw Error(FN_E_INVALID, "tddp3: the grid must be square (nx == ny)");
+  const double tau = d.at("tau").number(), sig = d.at("sigma_t").number();
+  if (!(tau > 0.0) || !(sig > 0.0)) throw Error(FN_E_INVALID, "tddp3: need tau > 0 and sigma_t > 0");
+  m->tdt.gamma = 1.0 / tau;
+  m->tdt.sigma = sig;
+  td4_weideman_coefficients(m->tdt.wa, &m->tdt.wL);
+  m->P = 4 * dc.K + 2;
+  m->n_obs = 3;
+  m->chunk = 1024;
+  if (!device) return;
+  m->tddp_jit = tddp_jit(dc);
+  m->d_table.reserve(sizeof(DalitzTable));
+  m->d_fixed.reserve(sizeof(double) * 2 * dc.K);
+  hip_check(hipMemcpy(m->d_fixed.ptr, m->fixed_ls.data(), sizeof(double) * 2 * dc.K, hipMemcpyHostToDevice),
+            "hipMemcpy");
+  m->d_M.reserve(sizeof(double) * 6 * dc.K * dc.K);
+  m->d_theta.reserve(sizeof(double) * m->P);
+}
+
 int td4_n_fixed(const Td4Const& tc) { return 2 * (tc.n12 + tc.n34) + 1; }
 
 Td4FitConst td4_fit_const(const Td4Const& tc, const double* fixed) {
@@ -344,6 +371,41 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
       m->ev_pending.emplace_back(t0, t1);
     }
     mix1d_launch_finalize(mc, m->table_mix(), m->part(), nch, grad, (double)n, m->out(), out_user, s);
+  } else if (m->kind == kKindTddp3) {
+    const DalitzConst& dc = m->dal;
+    const int nv = tddp_nv(dc.K, grad);
+    m->d_part.reserve(sizeof(double) * (size_t)(nch > 0 ? nch : 1) * nv);
+    if (pb || !m->table_ready) {
+      ParamBlock zero;
+      dalitz_launch_prologue(dc, pb ? *pb : zero, pb ? nullptr : theta_dev, m->fixed(), 1, 0, m->table_dal(), s);
+      m->table_ready = true;
+    }
+    const double* coef = theta_dev;
+    if (pb) {
+      tddp_launch_copy_theta(*pb, m->P, (double*)m->d_theta.ptr, s);
+      coef = (const double*)m->d_theta.ptr;
+    }
+    if (!m->M_valid) {
+      const int64_t ncell = (int64_t)dc.nx * dc.ny;
+      const int64_t mrows = nchunks_for(ncell, m->grid_chunk);
+      m->d_npart.reserve(sizeof(double) * (size_t)mrows * 2 * kMRowBlock * dc.K);
+      tddp_launch_mmatrices(*m->tddp_jit, dc, m->table_dal(), m->grid_chunk, m->npart(), m->Mc(), s);
+      m->M_valid = true;
+    }
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (nch > 0 && m->timed_launch()) {
+      t0 = m->take_event();
+      t1 = m->take_event();
+      hip_check(hipEventRecord(t0, s), "hipEventRecord");
+    }
+    tddp_launch_events(*m->tddp_jit, dc, m->table_dal(), m->tdt, coef, ev, ld, n, m->chunk, nch, grad, m->part(),
+                       s);
+    if (t0) {
+      hip_check(hipEventRecord(t1, s), "hipEventRecord");
+      m->ev_pending.emplace_back(t0, t1);
+    }
+    tddp_launch_finalize(dc, m->table_dal(), m->tdt, coef, m->part(), nch, grad, m->Mc(), (double)n, m->out(),
+                         out_user, s);
   } else if (m->kind == kKindTd4) {
     const Td4Const& tc = m->td4;
     if (m->n_mc <= 0) throw Error(FN_E_INVALID, "td4: normalization sample not set (fn_model_set_norm_sample)");
@@ -550,6 +612,9 @@ fn_status fn_model_create(fn_ctx* ctx, const char* desc_json, fn_model** out) {
       } else if (kind == "td4") {
         m->kind = kKindTd4;
         compile_td4(d, m);
+      } else if (kind == "tddp3") {
+        m->kind = kKindTddp3;
+        compile_tddp3(d, m);
       } else {
         throw Error(FN_E_INVALID, "unknown model kind \"" + kind + "\"");
       }
@@ -597,6 +662,9 @@ fn_status fn_model_check_compile(const char* desc_json, const char* arch) {
       } else if (kind == "td4") {
         compile_td4(d, &tmp, false);
         (void)jit_compile(td4_jit_source(tmp.td4), target);
+      } else if (kind == "tddp3") {
+        compile_tddp3(d, &tmp, false);
+        (void)jit_compile(tddp_jit_source(tmp.dal), target);
       } else if (kind != "mix1d") {
         throw Error(FN_E_INVALID, "unknown model kind \"" + kind + "\"");
       }
@@ -732,6 +800,7 @@ fn_status fn_eval(fn_model* m, const double* theta_host, const double* ev, int64
                   void* stream) {
   return guard([&] {
     if (!m) throw Error(FN_E_INVALID, "model is NULL");
+    if (m->kind == kKindTddp3) throw Error(FN_E_INVALID, "fn_eval is not available for tddp3 models");
     if (n > 0 && !p_dev) throw Error(FN_E_INVALID, "output is NULL");
     check_events_args(m, ev, n, ld);
     hip_check(hipSetDevice(m->device), "hipSetDevice");

@@ -1,0 +1,197 @@
+// Device code of the time-dependent three-body Dalitz-plot model with mixing
+// (the paper's pi+ pi- pi0 time-dependent amplitude fit, Sec. 1 Table 2 and
+// Fig. 2), compiled at run time for each model structure like the
+// time-integrated three-body passes.
+//
+// Daughters 2 and 3 are charge conjugates (m2 = m3), so the Dbar0 amplitude
+// at (s12, s13) is the D0 one at (s13, s12):
+//   A = sum_k c_k A_k(s12, s13),  Abar = sum_k cbar_k A_k(s13, s12),
+// with A_k the isobar amplitudes of dalitz_device.hpp (fixed lineshapes), and
+// the rate is the mixing and resolution form of td4_device.hpp:
+//   R = 1/2 [(|A|^2+|Abar|^2) Hc + (|A|^2-|Abar|^2) Hcos - 2 Re(A* Abar) Hs - 2 Im(A* Abar) Hsin].
+// The normalization is the grid integral of the t-integrated rate, a
+// quadratic form in (c, cbar) through three K x K matrices of grid sums,
+//   MAA_ij = dA sum A_i conj(A_j),  MBB_ij = dA sum B_i conj(B_j),
+//   MAB_ij = dA sum conj(A_i) B_j,  B_k(s12, s13) = A_k(s13, s12),
+// built once per model (the lineshapes are fixed).
+#pragma once
+#include "dalitz_device.hpp"
+#include "td4_device.hpp"
+
+namespace fn {
+
+// Decay-time constants of a model: 1/tau, the resolution width and the
+// Faddeeva approximation of the resolution functions.
+struct TddpTime {
+  double gamma;
+  double sigma;
+  double wL;
+  double wa[kWeidN];
+};
+
+// Amplitudes A_k(s12, s13) (or, SWAP, A_k(s13, s12)) of every resonance.
+template <class S, bool SWAP>
+__device__ __forceinline__ void tddp_basis(const DalitzConst& dc, const double* __restrict__ r, double s12,
+                                           double s13, double (&re)[S::K], double (&im)[S::K]) {
+  constexpr int K = S::K;
+  const double u = SWAP ? s13 : s12, v = SWAP ? s12 : s13;
+  const double s23 = dc.msum - s12 - s13;
+  double Tre[K], Tim[K], Gk[K];
+  double Sre = 0.0, Sim = 0.0;
+  dalitz_pair<S, 0, kMRows, true, false>(dc, r, nullptr, u, v, s23, re, im, Tre, Tim, Gk, Sre, Sim);
+  dalitz_pair<S, 1, kMRows, true, false>(dc, r, nullptr, u, v, s23, re, im, Tre, Tim, Gk, Sre, Sim);
+  dalitz_pair<S, 2, kMRows, true, false>(dc, r, nullptr, u, v, s23, re, im, Tre, Tim, Gk, Sre, Sim);
+}
+
+// Events pass: one workgroup per chunk of events (s12, s13, t rows at
+// ev, ev + ld, ev + 2 ld), one row of partial sums each:
+// [-sum ln R, d/dRe c_k, d/dIm c_k (k), d/dRe cbar_k, d/dIm cbar_k (k), d/dx, d/dy].
+// coef: theta on the device, (c, cbar, x, y).
+template <class S, bool GRAD>
+__device__ inline void tddp_events_body(const DalitzConst& dc, const DalitzTable* __restrict__ tab,
+                                        const TddpTime& tt, const double* __restrict__ coef0,
+                                        const double* __restrict__ ev, int64_t ld, int64_t n, int chunk,
+                                        double* __restrict__ part) {
+  constexpr int K = S::K;
+  constexpr int NV = GRAD ? 3 + 4 * K : 1;
+  __shared__ double lds[block_sum_lds(NV)];
+  double acc[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+  const double s = tt.sigma, s2 = s * s, inv2s2 = 0.5 / s2;
+  const double G = tt.gamma;
+  const double x = coef0[4 * K], y = coef0[4 * K + 1];
+  const double ap = G * (1.0 - y), am = G * (1.0 + y);
+  const cplx ac = {G, -G * x};
+  const int64_t base = (int64_t)blockIdx.x * chunk;
+  const int64_t end = base + chunk < n ? base + chunk : n;
+  const double* const r0 = &tab->r[0][0];
+  for (int64_t i = base + threadIdx.x; i < end; i += kBlock) {
+    // constants re-read through the scalar cache per event (an opaque zero
+    // offset keeps them out of SGPRs that would overflow into VGPR lanes)
+    int zero = 0;
+    asm volatile("" : "+s"(zero));
+    const double* r = r0 + zero;
+    const double* coef = coef0 + zero;
+    const double* wa = tt.wa + zero;
+    const double t = ev[2 * ld + i];
+    const double g = exp(-t * t * inv2s2);
+    double hp, dhp, hm, dhm;
+    cplx hc, dhc;
+    h_real(wa, tt.wL, ap, t, s, s2, g, hp, dhp);
+    h_real(wa, tt.wL, am, t, s, s2, g, hm, dhm);
+    h_cplx(wa, tt.wL, ac, t, s, s2, g, hc, dhc);
+    const double s12 = ev[i], s13 = ev[ld + i];
+    double Are[K], Aim[K], Bre[K], Bim[K];
+    tddp_basis<S, false>(dc, r, s12, s13, Are, Aim);
+    tddp_basis<S, true>(dc, r, s12, s13, Bre, Bim);
+    cplx A = {0.0, 0.0}, Ab = {0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const double cr = coef[2 * k], ci = coef[2 * k + 1];
+      const double br = coef[2 * K + 2 * k], bi = coef[2 * K + 2 * k + 1];
+      A = {A.re + cr * Are[k] - ci * Aim[k], A.im + cr * Aim[k] + ci * Are[k]};
+      Ab = {Ab.re + br * Bre[k] - bi * Bim[k], Ab.im + br * Bim[k] + bi * Bre[k]};
+    }
+    const double Hc = 0.5 * (hp + hm), Hs = 0.5 * (hp - hm);
+    const double a2 = A.re * A.re + A.im * A.im, b2 = Ab.re * Ab.re + Ab.im * Ab.im;
+    const double zr = A.re * Ab.re + A.im * Ab.im, zi = A.re * Ab.im - A.im * Ab.re;  // conj(A) Abar
+    const double R = 0.5 * ((a2 + b2) * Hc + (a2 - b2) * hc.re - 2.0 * zr * Hs - 2.0 * zi * hc.im);
+    acc[0] -= log_fast(R);
+    if (GRAD) {
+      const double w = -rcp_nr(R);
+      const double hpc = Hc + hc.re, hmc = Hc - hc.re;
+      // dR/dRe c_k - i dR/dIm c_k = lc A_k, and with lb and B_k for cbar:
+      // lc = hpc conj(A) - (Hs + i Hsin) conj(Abar), lb = hmc conj(Abar) - (Hs - i Hsin) conj(A)
+      // (the event's factor w = -1/R included)
+      const cplx lc = {w * (hpc * A.re - Hs * Ab.re - hc.im * Ab.im), w * (-hpc * A.im + Hs * Ab.im - hc.im * Ab.re)};
+      const cplx lb = {w * (hmc * Ab.re - Hs * A.re + hc.im * A.im), w * (-hmc * Ab.im + Hs * A.im + hc.im * A.re)};
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const cplx ec = cmul(lc, {Are[k], Aim[k]}), eb = cmul(lb, {Bre[k], Bim[k]});
+        acc[1 + 2 * k] += ec.re;
+        acc[2 + 2 * k] -= ec.im;
+        acc[1 + 2 * K + 2 * k] += eb.re;
+        acc[2 + 2 * K + 2 * k] -= eb.im;
+      }
+      // x: d hc/dx = -i G dh(ac);  y: d hp/dy = -G dh(ap), d hm/dy = +G dh(am)
+      const double dcos = G * dhc.im, dsin = -G * dhc.re;
+      acc[1 + 4 * K] += w * 0.5 * ((a2 - b2) * dcos - 2.0 * zi * dsin);
+      const double dHc = 0.5 * G * (dhm - dhp), dHs = -0.5 * G * (dhp + dhm);
+      acc[2 + 4 * K] += w * 0.5 * ((a2 + b2) * dHc - 2.0 * zr * dHs);
+    }
+  }
+  block_sum_row<NV>(acc, lds, part + (int64_t)blockIdx.x * NV);
+}
+
+// Rows i0..i0+3 of one normalization matrix over one chunk of grid cells:
+// WHICH 0: A_i conj(A_j), 1: B_i conj(B_j), 2: conj(A_i) B_j (re, im pairs).
+template <class S, int WHICH>
+__device__ inline void tddp_mrows_body(const DalitzConst& dc, const DalitzTable* __restrict__ tab, int chunk,
+                                       int i0, double* __restrict__ part) {
+  constexpr int K = S::K;
+  constexpr int NV = 2 * kMRowBlock * K;
+  __shared__ double lds[block_sum_lds(NV)];
+  double acc[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+  const int64_t ncell = (int64_t)dc.nx * dc.ny;
+  const int64_t base = (int64_t)blockIdx.x * chunk;
+  const int64_t end = base + chunk < ncell ? base + chunk : ncell;
+  const double* const r0 = &tab->r[0][0];
+  for (int64_t c = base + threadIdx.x; c < end; c += kBlock) {
+    int zero = 0;
+    asm volatile("" : "+s"(zero));
+    const double* r = r0 + zero;
+    const int64_t ix = c / dc.ny, iy = c - ix * dc.ny;
+    const double s12 = dc.a12 + (ix + 0.5) * dc.d12;
+    const double s13 = dc.a13 + (iy + 0.5) * dc.d13;
+    if (!dalitz_inside(dc, s12, s13)) continue;
+    double Lre[K], Lim[K], Rre[K], Rim[K];
+    tddp_basis<S, WHICH == 1>(dc, r, s12, s13, Lre, Lim);
+    if (WHICH == 2) {
+      tddp_basis<S, true>(dc, r, s12, s13, Rre, Rim);
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        Rre[k] = Lre[k];
+        Rim[k] = Lim[k];
+      }
+    }
+#pragma unroll
+    for (int ib = 0; ib < kMRowBlock; ++ib) {
+      double xr = 0.0, xi = 0.0;  // left factor i = i0 + ib, selected with uniform guards
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        if (k == i0 + ib) {
+          xr = Lre[k];
+          xi = WHICH == 2 ? -Lim[k] : Lim[k];
+        }
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        // (xr + i xi) times conj(R_j) for WHICH 0/1, times R_j for WHICH 2
+        const double rr = Rre[j], ri = WHICH == 2 ? Rim[j] : -Rim[j];
+        acc[2 * (ib * K + j)] += xr * rr - xi * ri;
+        acc[2 * (ib * K + j) + 1] += xr * ri + xi * rr;
+      }
+    }
+  }
+  block_sum_row<NV>(acc, lds, part + (int64_t)blockIdx.x * NV);
+}
+
+}  // namespace fn
+
+// Kernels for shape S (used by the generated source).
+#define FN_TDDP_EVENTS(NAME, S, GRAD)                                                                          \
+  extern "C" __global__ __launch_bounds__(fn::kBlock) void NAME(                                               \
+      fn::DalitzConst dc, const fn::DalitzTable* __restrict__ tab, fn::TddpTime tt,                            \
+      const double* __restrict__ coef, const double* __restrict__ ev, int64_t ld, int64_t n, int chunk,       \
+      double* __restrict__ part) {                                                                             \
+    fn::tddp_events_body<S, GRAD>(dc, tab, tt, coef, ev, ld, n, chunk, part);                                 \
+  }
+#define FN_TDDP_MROWS(NAME, S, WHICH)                                                                          \
+  extern "C" __global__ __launch_bounds__(fn::kBlock) void NAME(                                               \
+      fn::DalitzConst dc, const fn::DalitzTable* __restrict__ tab, int chunk, int i0,                          \
+      double* __restrict__ part) {                                                                             \
+    fn::tddp_mrows_body<S, WHICH>(dc, tab, chunk, i0, part);                                                   \
+  }

@@ -1,0 +1,107 @@
+"""Parity of the time-dependent Dalitz-plot NLL, normalization and adjoint
+gradient with the oracle (oracle/tddp3.py)."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import common, tddp3 as T
+from tests.gpu_util import grad_close, rel_close, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def events(n, seed, desc):
+    d = synth.dalitz_events(n, seed=seed, masses=T.MASSES, resonances=T.RESONANCES)
+    u, v = synth.uniforms(n, synth.key_from_seed(seed, 9), 0)
+    w, _ = synth.uniforms(n, synth.key_from_seed(seed, 9), 1)
+    t = -desc["tau"] * np.log1p(-u) + desc["sigma_t"] * np.sqrt(-2.0 * np.log1p(-v)) * np.cos(2.0 * math.pi * w)
+    return np.vstack([d, t[None, :]])
+
+
+def theta(x=0.02, y=0.03):
+    th = T.truth_theta(x=x, y=y)
+    th[16:32] = np.roll(th[16:32], 2) * 0.9 + 0.01   # cbar != c
+    return th
+
+
+D256 = T.pipipi0_desc(grid=(256, 256))
+
+
+@pytest.fixture(scope="module")
+def m256():
+    from paper_1710_08826_amd import Model
+    return Model(D256)
+
+
+@pytest.fixture(scope="module")
+def cells256():
+    return T.TDDP(D256).dal.grid_cells()
+
+
+def test_norm_matches_oracle(m256, cells256):
+    say("tddp3 norm")
+    for th in (theta(), theta(0.3, -0.2)):
+        I, dI = m256.norm(th)
+        Io = T.norm_value(T.TDDP(D256), th, cells256)
+        assert rel_close(I, Io, 1e-12), (I, Io)
+
+
+@pytest.mark.parametrize("n", [1, 1000, 3 * 1024 + 17, 50_000])
+def test_nll_and_gradient(m256, cells256, n):
+    say("tddp3 n =", n)
+    ev = events(n, 61, D256)
+    for th in (theta(), theta(0.3, -0.2)):
+        v, g = m256.nll(th, to_dev(ev), grad=True)
+        vo, go = T.nll_grad(th, ev, D256, cells256)
+        assert rel_close(v, vo, 1e-12), (v, vo, (v - vo) / vo)
+        ok, r = grad_close(g, go, 1e-10)
+        assert ok, r
+        assert rel_close(m256.nll(th, to_dev(ev)), v, 1e-14)
+
+
+def test_gradient_vs_central_fd():
+    from paper_1710_08826_amd import Model
+    d = T.pipipi0_desc(grid=(64, 64))
+    m = Model(d)
+    ev = events(2000, 62, d)
+    th = theta(0.05, 0.04)
+    _, g = m.nll(th, to_dev(ev), grad=True)
+    fd = common.central_fd(lambda t: T.nll(t, ev, d), th, rel_step=2e-7)
+    ok, r = grad_close(g, fd, 1e-6)
+    assert ok, r
+
+
+def test_full_size():
+    """1M events on the 1024 x 1024 grid, the benchmark's configuration."""
+    from paper_1710_08826_amd import Model
+    d = T.pipipi0_desc()
+    m = Model(d)
+    ev = events(1_000_000, 63, d)
+    th = theta()
+    v = m.nll(th, to_dev(ev))
+    vo = T.nll(th, ev, d)
+    assert rel_close(v, vo, 1e-12), (v, vo)
+
+
+def test_bitwise_repeatable_and_empty(m256):
+    ev = to_dev(events(20_000, 64, D256))
+    th = theta()
+    a = m256.nll(th, ev, grad=True)
+    b = m256.nll(th, ev, grad=True)
+    assert a[0] == b[0] and np.array_equal(a[1], b[1])
+    import torch
+    v, g = m256.nll(th, torch.zeros((3, 0), dtype=torch.float64, device="cuda"), grad=True)
+    assert v == 0.0 and not np.any(g)
+
+
+def test_invalid_descriptions_and_calls(m256):
+    from paper_1710_08826_amd import FitNLLError, Model
+    bad = [dict(D256, m=[0.135, 0.1396, 0.1350]), dict(D256, grid=[256, 128]), dict(D256, tau=0.0),
+           dict(D256, sigma_t=-1.0), dict(D256, free_lineshapes=True)]
+    for d in bad:
+        with pytest.raises(FitNLLError):
+            Model(d)
+    with pytest.raises(FitNLLError):
+        m256.eval(theta(), to_dev(events(10, 65, D256)))
