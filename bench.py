@@ -137,6 +137,30 @@ def td4_flops_per_event(desc: dict, grad: bool) -> int:
     return f
 
 
+def time_terms_flops() -> int:
+    """The three resolution-convolved time terms per event (rational Faddeeva
+    approximation, 40 coefficients) and exp(-t^2 / 2 sigma^2)."""
+    N = 40
+    h_real = 3 + (1 + W_DIV) + 2 + (N - 1) * 2 + 4 + (4 + W_EXP) + 3
+    w_c = 1 + (5 + W_DIV) + 7 + (N - 1) * 7 + 8 + 7
+    h_cplx = 5 + w_c + 9 + W_SINCOS + W_EXP + 7
+    return 2 + W_EXP + 2 * h_real + h_cplx
+
+
+def tddp3_flops_per_event(desc: dict, grad: bool) -> int:
+    """Algorithmic FP64 FLOPs per event of the time-dependent Dalitz NLL: the
+    three-body amplitudes at (s12, s13) and at (s13, s12) (per-pair kinematics
+    shared by the pair's resonances, one complex reciprocal per resonance),
+    both coherent sums, the time terms, the rate and its log."""
+    K = len(desc["resonances"])
+    amp = dalitz_flops_per_event(dict(desc, kind="dalitz3"), 0) - (4 + W_LOG)  # one amplitude set + sum
+    f = 2 * amp + time_terms_flops() + 27 + W_LOG + 1
+    if grad:
+        f += 2 * 3 + 8                              # dh/da of the three time terms
+        f += 1 + W_DIV + 2 + 24 + 16 * K + 20       # -1/R, the two complex weights, c and cbar slots, x and y
+    return f
+
+
 def mix1d_flops_per_event(grad: bool) -> int:
     """Config-0 mixture (Gaussian + exponential): 2 exp, 1 log, ~14 others;
     the gradient adds one division and ~22 FLOPs."""
@@ -288,6 +312,33 @@ def serving_leg(n_fits: int = 4096, one_at_a_time: int = 256, fd_fits: int = 32,
     return out
 
 
+def tddp3_leg(steps: int = 50):
+    """Time-dependent Dalitz-plot fit (the paper's pi+ pi- pi0 mixing
+    workload class): 1M events, 34 parameters, NLL + adjoint gradient, and the
+    plain finite-difference gradient (2P + 1 NLL-only calls)."""
+    import torch
+    import synth
+    from paper_1710_08826_amd import Model
+    n = 1_000_000
+    desc = synth.tddp3_desc()
+    th = synth.tddp3_truth()
+    ev = torch.from_numpy(synth.tddp3_events(n, seed=synth.BASE_SEED + 7)).cuda()
+    m = Model(desc)
+    P = m.n_params
+    tdev = torch.from_numpy(th).cuda()
+    tb = torch.from_numpy(th * (1.0 + 1e-3 * np.cos(np.arange(P)))).cuda()
+    out = torch.empty(1 + P, dtype=torch.float64, device="cuda")
+    w, k = time_async(m, tdev, ev, out, steps, 3, True, alt=tb)
+    w0, k0 = time_async(m, tdev, ev, out, steps, 3, False, alt=tb)
+    fl = tddp3_flops_per_event(desc, True)
+    fd_step = (2 * P + 1) * w0 / steps
+    return {"events": n, "params": P, "grid": desc["grid"], "chunk": m.chunk,
+            "events_per_s": n * steps / w, "ms_per_step": 1e3 * w / steps,
+            "event_kernel_us": k * 1e3, "nll_only_event_kernel_us": k0 * 1e3,
+            "flops_per_event": fl, "event_kernel_tflops": fl * n / (k * 1e-3) / 1e12,
+            "plain_fd_grad_events_per_s": n / fd_step, "adjoint_vs_plain_fd": fd_step / (w / steps)}
+
+
 def td4_leg(steps: int = 10):
     """Config 4: the time-dependent four-body model, 10M events, 5M-point
     phase-space normalization sample; single-fit NLL + adjoint gradient, the
@@ -376,7 +427,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--quick", action="store_true", help="skip the side measurements and the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--leg", choices=["td4", "serve"],
+    ap.add_argument("--leg", choices=["td4", "serve", "tddp3"],
                     help="run only the four-body leg or the serving leg and print its figures (for profiling)")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="for counter runs: one 256 MiB device copy (calibration) then --steps "
@@ -397,6 +448,9 @@ def main():
         return
     if args.leg == "serve":
         print(json.dumps({"config2_serving": serving_leg()}), flush=True)
+        return
+    if args.leg == "tddp3":
+        print(json.dumps({"tddp3": tddp3_leg()}), flush=True)
         return
 
     import torch
@@ -505,6 +559,14 @@ def main():
         extra["config0_fit_speedup_adjoint_vs_fd"] = extra["config0_fit_fd_ms"] / extra["config0_fit_adjoint_ms"]
         print(f"[bench] config0 fits: adjoint {extra['config0_fit_adjoint_ms']:.2f} ms, "
               f"fd {extra['config0_fit_fd_ms']:.2f} ms", file=sys.stderr, flush=True)
+
+    if not args.quick:
+        print("[bench] time-dependent Dalitz (pi+ pi- pi0-like, 8 resonances, 1M events) ...", file=sys.stderr,
+              flush=True)
+        extra["tddp3"] = tddp3_leg()
+        t3 = extra["tddp3"]
+        print(f"[bench] tddp3: {t3['events_per_s']:.4g} events/s ({t3['event_kernel_tflops']:.2f} TFLOP/s), "
+              f"adjoint vs FD {t3['adjoint_vs_plain_fd']:.1f}x", file=sys.stderr, flush=True)
 
     if not args.quick:
         print("[bench] config4 td4 (10M events, 5M-point sample, 64 variation fits) ...", file=sys.stderr,

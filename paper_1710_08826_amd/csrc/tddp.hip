@@ -50,6 +50,7 @@ __global__ void tddp_copy_theta(ParamBlock pb, int P, double* __restrict__ dst) 
 
 struct TddpFinalLds {
   double scratch[kFinalBlock];
+  double M[6 * kDalMaxRes * kDalMaxRes];
   double res[kBlock];
   double cre[kDalMaxRes], cim[kDalMaxRes], bre[kDalMaxRes], bim[kDalMaxRes];
   double X[kDalMaxRes][2], Xb[kDalMaxRes][2], U[kDalMaxRes][2], V[kDalMaxRes][2];
@@ -75,7 +76,20 @@ __global__ __launch_bounds__(kFinalBlock) void tddp_finalize(DalitzConst dc, con
   const int K = dc.K;
   const int P = 4 * K + 2;
   const int t = threadIdx.x;
+  // the three matrices are loaded first: their latency overlaps the row sums
+  const int nm = 6 * K * K;
+  double mv[(6 * kDalMaxRes * kDalMaxRes + kFinalBlock - 1) / kFinalBlock];
+#pragma unroll
+  for (int u = 0; u < (int)(sizeof(mv) / sizeof(mv[0])); ++u) {
+    const int i = t + u * kFinalBlock;
+    mv[u] = i < nm ? Mc[i] : 0.0;
+  }
   sum_rows_t<kFinalBlock>(part, nrows, nv, L.scratch, L.res);
+#pragma unroll
+  for (int u = 0; u < (int)(sizeof(mv) / sizeof(mv[0])); ++u) {
+    const int i = t + u * kFinalBlock;
+    if (i < nm) L.M[i] = mv[u];
+  }
   if (t < K) {
     L.cre[t] = coef[2 * t];
     L.cim[t] = coef[2 * t + 1];
@@ -83,9 +97,9 @@ __global__ __launch_bounds__(kFinalBlock) void tddp_finalize(DalitzConst dc, con
     L.bim[t] = coef[2 * K + 2 * t + 1];
   }
   __syncthreads();
-  const double* MAA = Mc;
-  const double* MBB = Mc + 2 * K * K;
-  const double* MAB = Mc + 4 * K * K;
+  const double* MAA = L.M;
+  const double* MBB = L.M + 2 * K * K;
+  const double* MAB = L.M + 4 * K * K;
   if (t < K) {
     double xr = 0.0, xi = 0.0, br = 0.0, bi = 0.0, ur = 0.0, ui = 0.0, vr = 0.0, vi = 0.0;
     for (int j = 0; j < K; ++j) {

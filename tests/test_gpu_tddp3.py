@@ -13,11 +13,7 @@ pytestmark = pytest.mark.gpu
 
 
 def events(n, seed, desc):
-    d = synth.dalitz_events(n, seed=seed, masses=T.MASSES, resonances=T.RESONANCES)
-    u, v = synth.uniforms(n, synth.key_from_seed(seed, 9), 0)
-    w, _ = synth.uniforms(n, synth.key_from_seed(seed, 9), 1)
-    t = -desc["tau"] * np.log1p(-u) + desc["sigma_t"] * np.sqrt(-2.0 * np.log1p(-v)) * np.cos(2.0 * math.pi * w)
-    return np.vstack([d, t[None, :]])
+    return synth.tddp3_events(n, seed, desc["tau"], desc["sigma_t"])
 
 
 def theta(x=0.02, y=0.03):

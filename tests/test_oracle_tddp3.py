@@ -12,13 +12,7 @@ from oracle.td4 import h_conv
 
 
 def events(n, seed, desc):
-    """(s12, s13, t): Dalitz points from the synthetic three-body sampler with
-    this model's masses and resonances, t exponential(tau) plus Gaussian(sigma_t)."""
-    d = synth.dalitz_events(n, seed=seed, masses=T.MASSES, resonances=T.RESONANCES)
-    u, v = synth.uniforms(n, synth.key_from_seed(seed, 9), 0)
-    w, _ = synth.uniforms(n, synth.key_from_seed(seed, 9), 1)
-    t = -desc["tau"] * np.log1p(-u) + desc["sigma_t"] * np.sqrt(-2.0 * np.log1p(-v)) * np.cos(2.0 * math.pi * w)
-    return np.vstack([d, t[None, :]])
+    return synth.tddp3_events(n, seed, desc["tau"], desc["sigma_t"])
 
 
 def dalitz_desc(desc):
