@@ -187,3 +187,74 @@ def truth_theta(resonances=None, x: float = X_MIX, y: float = Y_MIX) -> np.ndarr
     table = resonances if resonances is not None else RESONANCES
     c = [v for (_p, _L, _m0, _w0, cc) in table for v in cc]
     return np.array(c + c + [x, y], dtype=np.float64)
+
+
+GEN_ENVELOPE_FACTOR = 1.2  # automatic envelope: this factor x the grid maximum of (|A| + |Abar|)^2
+GEN_MAX_ATTEMPTS = 4096
+
+
+def envelope(theta, desc: dict, cells=None) -> float:
+    """1.2 x the largest (|A| + |Abar|)^2 over the integration-grid cell centres."""
+    model = TDDP(desc)
+    c12, c13, _ = cells if cells is not None else model.dal.grid_cells()
+    with torch.no_grad():
+        A, Ab = model.amplitudes(as_t(theta), as_t(c12), as_t(c13))
+        return GEN_ENVELOPE_FACTOR * float(((A.abs() + Ab.abs()) ** 2).max())
+
+
+def generate(theta, desc: dict, n: int, seed: int, fit: int = 0, W: float | None = None):
+    """Toy events (3, n) distributed as the model by accept-reject, event by
+    event.  The unconvolved rate obeys R(s12, s13, t) <= e^{-lam t} (|A| + |Abar|)^2
+    with lam = G (1 - |y|) (|sinh| <= cosh, |cos|, |sin| <= 1 and cosh >= 1
+    bound the bracket by cosh(y G t) (2 max(|A|^2, |Abar|^2) + 4 |A||Abar|), and
+    e^{-Gt} cosh(y G t) <= e^{-lam t}), so: event i, attempt a takes
+    (u1, u2) from Philox counter (i, 2a, word 2) and (u3, u4) from
+    (i, 2a + 1, word 2) under key (seed, fit); s12 = lo12 + u1 (hi12 - lo12),
+    s13 = lo13 + u2 (hi13 - lo13) on the kinematic box, t_true = -ln(1 - u3)/lam;
+    the candidate is kept when it lies in the region and
+    u4 W e^{-lam t_true} < R(s12, s13, t_true).  The measured time adds a
+    Gaussian of width sigma_t from counter (i, 0, word 3) (Box-Muller).  An
+    event not kept within GEN_MAX_ATTEMPTS attempts stays NaN.
+    Returns (events, W, number of kept events whose (|A| + |Abar|)^2 exceeds W)."""
+    from synth.philox import key_from_seed, uniforms_at
+    model = TDDP(desc)
+    d = model.dal
+    M, m = d.M, d.m
+    lo12, hi12 = (m[1] + m[2]) * (m[1] + m[2]), (M - m[3]) * (M - m[3])
+    lo13, hi13 = (m[1] + m[3]) * (m[1] + m[3]), (M - m[2]) * (M - m[2])
+    if W is None:
+        W = envelope(theta, desc)
+    y = float(theta[model.P - 1])
+    lam = (1.0 - abs(y)) / model.tau
+    key = key_from_seed(seed, fit)
+    out = np.full((3, n), np.nan)
+    todo = np.arange(n, dtype=np.uint64)
+    above = 0
+    th = as_t(theta)
+    for a in range(GEN_MAX_ATTEMPTS):
+        if todo.size == 0:
+            break
+        u1, u2 = uniforms_at(todo, key, 2 * a, 2)
+        u3, u4 = uniforms_at(todo, key, 2 * a + 1, 2)
+        s12 = lo12 + u1 * (hi12 - lo12)
+        s13 = lo13 + u2 * (hi13 - lo13)
+        tt = -np.log1p(-u3) / lam
+        ins = d.inside(s12, s13)
+        keep = np.zeros(todo.size, dtype=bool)
+        if ins.any():
+            with torch.no_grad():
+                r = model.unconvolved_rate(th, as_t(s12[ins]), as_t(s13[ins]), as_t(tt[ins])).numpy()
+                A, Ab = model.amplitudes(th, as_t(s12[ins]), as_t(s13[ins]))
+                env = ((A.abs() + Ab.abs()) ** 2).numpy()
+            k = u4[ins] * W * np.exp(-lam * tt[ins]) < r
+            keep[np.flatnonzero(ins)[k]] = True
+            above += int((env[k] > W).sum())
+        idx = todo[keep].astype(np.int64)
+        out[0, idx] = s12[keep]
+        out[1, idx] = s13[keep]
+        out[2, idx] = tt[keep]
+        todo = todo[~keep]
+    i = np.arange(n, dtype=np.uint64)
+    v1, v2 = uniforms_at(i, key, 0, 3)
+    out[2] = out[2] + model.sigma * np.sqrt(-2.0 * np.log1p(-v1)) * np.cos(2.0 * math.pi * v2)
+    return out, W, above

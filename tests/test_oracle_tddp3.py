@@ -109,3 +109,49 @@ def test_conjugate_amplitude_is_the_mirrored_resonance():
                                              torch.from_numpy(ev[0]), torch.from_numpy(ev[1]))
         b2 = (Ab.real ** 2 + Ab.imag ** 2).numpy()
         assert np.allclose(b2, p.numpy(), rtol=1e-12, atol=0.0), pair
+
+
+# ------------------------------------------------------------ toy generation
+@pytest.fixture(scope="module")
+def toys():
+    desc = T.pipipi0_desc(grid=(128, 128))
+    th = T.truth_theta(x=0.3, y=0.2)
+    th[16:32] = np.roll(th[16:32], 2) * 0.8
+    ev, W, above = T.generate(th, desc, 5000, seed=21, fit=1)
+    return desc, th, ev, W, above
+
+
+def test_generated_time_and_dalitz_moments(toys):
+    """Mean measured decay time and mean s12, s13 against quadrature of the
+    model: the t moments come from closed forms (int t e^{-at} dt = 1/a^2 for
+    each exponential of the rate), the Dalitz sums from a fine grid."""
+    desc, th, ev, W, above = toys
+    assert above == 0 and np.isfinite(ev).all()
+    m = T.TDDP(dict(desc, grid=[512, 512]))
+    c12, c13, _ = m.dal.grid_cells()
+    G = 1.0 / m.tau
+    x, y = th[-2], th[-1]
+    with torch.no_grad():
+        A, Ab = m.amplitudes(common.as_t(th), common.as_t(c12), common.as_t(c13))
+    a2, b2 = (A.abs() ** 2).numpy(), (Ab.abs() ** 2).numpy()
+    z = (A.conj() * Ab).numpy()
+    # zeroth and first t moments of e^{-Gt} cosh, cos, sinh, sin
+    ap, am, ac = G * (1 - y), G * (1 + y), G * (1 - 1j * x)
+    m0 = (0.5 * (1 / ap + 1 / am), (1 / ac).real, 0.5 * (1 / ap - 1 / am), (1 / ac).imag)
+    m1 = (0.5 * (1 / ap ** 2 + 1 / am ** 2), (1 / ac ** 2).real, 0.5 * (1 / ap ** 2 - 1 / am ** 2), (1 / ac ** 2).imag)
+
+    def moment(mm):
+        return 0.5 * ((a2 + b2) * mm[0] + (a2 - b2) * mm[1] - 2 * z.real * mm[2] - 2 * z.imag * mm[3])
+
+    w0, w1 = moment(m0), moment(m1)
+    checks = [(ev[2], w1.sum() / w0.sum()), (ev[0], (w0 * c12).sum() / w0.sum()), (ev[1], (w0 * c13).sum() / w0.sum())]
+    for sample, expect in checks:
+        se = sample.std() / math.sqrt(sample.size)
+        assert abs(sample.mean() - expect) < 4.0 * se, (sample.mean(), expect, se)
+
+
+def test_generation_is_per_event(toys):
+    desc, th, ev, W, above = toys
+    head, W2, _ = T.generate(th, desc, 300, seed=21, fit=1, W=W)
+    assert W2 == W and np.array_equal(head, ev[:, :300])
+    assert T.TDDP(desc).dal.inside(ev[0], ev[1]).all()
