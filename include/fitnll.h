@@ -330,10 +330,19 @@ fn_status fn_batch_results(fn_batch* b, int32_t* status, double* theta, double* 
 fn_status fn_generate_mix1d(uint32_t seed, uint32_t fit, int64_t n, const double* theta_gen, double lo, double hi,
                             double* x, void* stream);
 
-/* Toy events of a dalitz3 model at theta (host, P doubles) by accept-reject on
- * the device, for toy studies (the paper's Monte Carlo generation with
- * MCBooster, Sec. 5).  Event i, attempt a draws (u1, u2) from Philox4x32-10
- * counter (i, 2a, 1) and u3 from (i, 2a + 1, 1) under key (seed, fit); the
+/* Toy events of a dalitz3 or tddp3 model at theta (host, P doubles) by
+ * accept-reject on the device, for toy studies (the paper's Monte Carlo
+ * generation with MCBooster, Sec. 5).  tddp3 (three rows s12, s13, t): event
+ * i, attempt a takes (u1, u2) from counter (i, 2a, 2) and (u3, u4) from
+ * (i, 2a + 1, 2); the candidate point in the box below with
+ * t = -ln(1 - u3)/lam, lam = (1 - |y|)/tau, is kept inside the region when
+ * u4 * envelope * exp(-lam t) < R(s12, s13, t) (the unconvolved rate, which
+ * is at most exp(-lam t) (|A| + |Abar|)^2), then t gains sigma_t times a
+ * Box-Muller normal from counter (i, 0, 3); the automatic envelope is 1.2 x
+ * the largest (|A| + |Abar|)^2 at the grid-cell centres; t goes to
+ * ev_dev[2 ld + i].  dalitz3: event i, attempt a draws (u1, u2) from
+ * Philox4x32-10 counter (i, 2a, 1) and u3 from (i, 2a + 1, 1) under key
+ * (seed, fit); the
  * candidate s12 = lo12 + u1 (hi12 - lo12), s13 = lo13 + u2 (hi13 - lo13) in
  * the kinematic box [(m1+m2)^2, (M-m3)^2] x [(m1+m3)^2, (M-m2)^2] is kept when
  * it lies in the Dalitz region and u3 * envelope < P~(s12, s13) (the
@@ -344,10 +353,10 @@ fn_status fn_generate_mix1d(uint32_t seed, uint32_t fit, int64_t n, const double
  *  ev_dev: caller-owned device memory, s12 at ev_dev[i], s13 at ev_dev[ld + i]
  *  (ld >= n).  Synchronous on `stream`.
  * FN_E_INVALID for another model kind, NULL pointers, ld < n, a negative or
- * non-finite envelope, invalid lineshape parameters, or a density that
- * vanishes on the grid; FN_E_DOMAIN if an accepted event lies above the
- * envelope (raise it) or an event was not accepted within the attempts (it is
- * NaN).  Event i depends only on (theta, seed, fit, envelope, i). */
+ * non-finite envelope, invalid lineshape parameters, |y| >= 1 (tddp3), or a
+ * density that vanishes on the grid; FN_E_DOMAIN if an accepted event lies
+ * above the envelope (raise it) or an event was not accepted within the
+ * attempts (it is NaN).  Event i depends only on (theta, seed, fit, envelope, i). */
 fn_status fn_generate(fn_model* m, const double* theta_host, uint32_t seed, uint32_t fit, int64_t n,
                       double envelope, double* ev_dev, int64_t ld, double* envelope_used, void* stream);
 

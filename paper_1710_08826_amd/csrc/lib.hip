@@ -829,9 +829,10 @@ fn_status fn_generate(fn_model* m, const double* theta_host, uint32_t seed, uint
                       double envelope, double* ev_dev, int64_t ld, double* envelope_used, void* stream) {
   return guard([&] {
     if (!m || !theta_host) throw Error(FN_E_INVALID, "NULL argument");
-    if (m->kind != kKindDalitz3)
-      throw Error(FN_E_INVALID, "device generation by model is available for dalitz3 models "
+    if (m->kind != kKindDalitz3 && m->kind != kKindTddp3)
+      throw Error(FN_E_INVALID, "device generation by model is available for dalitz3 and tddp3 models "
                                 "(mix1d: fn_generate_mix1d)");
+    const bool td = m->kind == kKindTddp3;
     if (n < 0 || (n > 0 && !ev_dev)) throw Error(FN_E_INVALID, "bad output");
     if (ld < n) throw Error(FN_E_INVALID, "ld must be >= n");
     if (!(envelope >= 0.0) || !std::isfinite(envelope)) throw Error(FN_E_INVALID, "envelope must be finite and >= 0");
@@ -840,6 +841,10 @@ fn_status fn_generate(fn_model* m, const double* theta_host, uint32_t seed, uint
     const DalitzConst& dc = m->dal;
     const ParamBlock pb = make_block(m, theta_host);
     dalitz_launch_prologue(dc, pb, nullptr, m->fixed(), 1, 0, m->table_dal(), s);
+    if (td) tddp_launch_copy_theta(pb, m->P, (double*)m->d_theta.ptr, s);
+    const double* coef = (const double*)m->d_theta.ptr;
+    if (td && !(std::fabs(theta_host[m->P - 1]) < 1.0))
+      throw Error(FN_E_INVALID, "tddp3 generation needs |y| < 1");
     m->d_gen.reserve(3 * sizeof(unsigned long long));
     unsigned long long* g = (unsigned long long*)m->d_gen.ptr;
     hip_check(hipMemsetAsync(g, 0, 3 * sizeof(unsigned long long), s), "hipMemsetAsync");
@@ -850,7 +855,8 @@ fn_status fn_generate(fn_model* m, const double* theta_host, uint32_t seed, uint
     if (valid == 0.0) throw Error(FN_E_INVALID, "invalid lineshape parameters");
     double W = envelope;
     if (W == 0.0) {
-      dalitz_launch_gridmax(*m->dal_jit, dc, m->table_dal(), g, s);
+      if (td) tddp_launch_gridmax(*m->tddp_jit, dc, m->table_dal(), coef, g, s);
+      else dalitz_launch_gridmax(*m->dal_jit, dc, m->table_dal(), g, s);
       hip_check(hipGetLastError(), "kernel launch");
       unsigned long long bits = 0;
       hip_check(hipMemcpyAsync(&bits, g, sizeof(bits), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
@@ -862,8 +868,12 @@ fn_status fn_generate(fn_model* m, const double* theta_host, uint32_t seed, uint
     }
     if (envelope_used) *envelope_used = W;
     if (n == 0) return;
-    dalitz_launch_gen(*m->dal_jit, dc, m->table_dal(), seed, fit, n, W, m->box, kGenMaxAttemptsModel, ev_dev, ld,
-                      g + 1, s);
+    if (td)
+      tddp_launch_gen(*m->tddp_jit, dc, m->table_dal(), coef, m->tdt, seed, fit, n, W, m->box, kGenMaxAttemptsModel,
+                      ev_dev, ld, g + 1, s);
+    else
+      dalitz_launch_gen(*m->dal_jit, dc, m->table_dal(), seed, fit, n, W, m->box, kGenMaxAttemptsModel, ev_dev, ld,
+                        g + 1, s);
     hip_check(hipGetLastError(), "kernel launch");
     unsigned long long bad[2] = {0, 0};
     hip_check(hipMemcpyAsync(bad, g + 1, sizeof(bad), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");

@@ -4,6 +4,7 @@
 // level-2 step with the normalization quadratic form).  The per-event and
 // normalization-matrix passes live in tddp_device.hpp and are compiled at
 // model creation with the model's structure as compile-time constants.
+#include <algorithm>
 #include <sstream>
 
 #include "internal.hpp"
@@ -28,17 +29,21 @@ std::string tddp_jit_source(const DalitzConst& dc) {
        "FN_TDDP_EVENTS(fn_tddp_ev1, fn_shape, true)\n"
        "FN_TDDP_MROWS(fn_tddp_maa, fn_shape, 0)\n"
        "FN_TDDP_MROWS(fn_tddp_mbb, fn_shape, 1)\n"
-       "FN_TDDP_MROWS(fn_tddp_mab, fn_shape, 2)\n";
+       "FN_TDDP_MROWS(fn_tddp_mab, fn_shape, 2)\n"
+       "FN_TDDP_GEN(fn_tddp_gmax, fn_tddp_gen, fn_shape)\n";
   return o.str();
 }
 
 std::shared_ptr<TddpJit> tddp_jit(const DalitzConst& dc) {
   auto j = std::make_shared<TddpJit>();
-  j->prog = jit_load(tddp_jit_source(dc), {"fn_tddp_ev0", "fn_tddp_ev1", "fn_tddp_maa", "fn_tddp_mbb", "fn_tddp_mab"});
+  j->prog = jit_load(tddp_jit_source(dc), {"fn_tddp_ev0", "fn_tddp_ev1", "fn_tddp_maa", "fn_tddp_mbb", "fn_tddp_mab",
+                                           "fn_tddp_gmax", "fn_tddp_gen"});
   const auto& f = j->prog->fns;
   j->ev[0] = f[0];
   j->ev[1] = f[1];
   for (int w = 0; w < 3; ++w) j->mrows[w] = f[2 + w];
+  j->gmax = f[5];
+  j->gen = f[6];
   return j;
 }
 
@@ -197,6 +202,36 @@ void tddp_launch_mmatrices(const TddpJit& j, const DalitzConst& dc, const Dalitz
       dalitz_launch_mrows_finalize(dc, part, nch, i0, Mc + (int64_t)w * 2 * K * K, s);
     }
   }
+}
+
+void tddp_launch_gridmax(const TddpJit& j, const DalitzConst& dc, const DalitzTable* tab, const double* coef,
+                         unsigned long long* vmax, hipStream_t s) {
+  const int64_t ncell = (int64_t)dc.nx * dc.ny;
+  const int64_t blocks = std::min<int64_t>((ncell + kBlock - 1) / kBlock, 4096);
+  DalitzConst c = dc;
+  const DalitzTable* t = tab;
+  const double* cf = coef;
+  unsigned long long* v = vmax;
+  void* args[] = {&c, &t, &cf, &v};
+  jit_launch(j.gmax, (unsigned)blocks, kBlock, s, args);
+}
+
+void tddp_launch_gen(const TddpJit& j, const DalitzConst& dc, const DalitzTable* tab, const double* coef,
+                     const TddpTime& tt, uint32_t k0, uint32_t k1, int64_t n, double W, const double box[4],
+                     int max_attempts, double* ev, int64_t ld, unsigned long long* bad, hipStream_t s) {
+  if (n == 0) return;
+  DalitzConst c = dc;
+  const DalitzTable* t = tab;
+  const double* cf = coef;
+  TddpTime tm = tt;
+  uint32_t a0 = k0, a1 = k1;
+  int64_t nn = n, l = ld;
+  double w = W, b0 = box[0], b1 = box[1], b2 = box[2], b3 = box[3];
+  int ma = max_attempts;
+  double* e = ev;
+  unsigned long long* b = bad;
+  void* args[] = {&c, &t, &cf, &tm, &a0, &a1, &nn, &w, &b0, &b1, &b2, &b3, &ma, &e, &l, &b};
+  jit_launch(j.gen, (unsigned)((n + kBlock - 1) / kBlock), kBlock, s, args);
 }
 
 void tddp_launch_events(const TddpJit& j, const DalitzConst& dc, const DalitzTable* tab, const TddpTime& tt,

@@ -13,6 +13,7 @@ struct TddpJit {
   std::shared_ptr<JitProgram> prog;
   hipFunction_t ev[2] = {nullptr, nullptr};   // without, with the gradient
   hipFunction_t mrows[3] = {nullptr, nullptr, nullptr};  // MAA, MBB, MAB row blocks
+  hipFunction_t gmax = nullptr, gen = nullptr;            // toy generation
 };
 std::string tddp_jit_source(const DalitzConst& dc);
 std::shared_ptr<TddpJit> tddp_jit(const DalitzConst& dc);
@@ -29,6 +30,14 @@ void tddp_launch_events(const TddpJit& j, const DalitzConst& dc, const DalitzTab
 void tddp_launch_finalize(const DalitzConst& dc, const DalitzTable* tab, const TddpTime& tt, const double* coef,
                           const double* part, int64_t nrows, bool grad, const double* Mc, double n_events,
                           double* out, double* out_user, hipStream_t s);
+// Toy generation: vmax (zeroed by the caller) receives the bits of the largest
+// (|A| + |Abar|)^2 over the grid; the generator writes n events (3 rows,
+// leading dimension ld), bad[0] / bad[1] as for the three-body generator.
+void tddp_launch_gridmax(const TddpJit& j, const DalitzConst& dc, const DalitzTable* tab, const double* coef,
+                         unsigned long long* vmax, hipStream_t s);
+void tddp_launch_gen(const TddpJit& j, const DalitzConst& dc, const DalitzTable* tab, const double* coef,
+                     const TddpTime& tt, uint32_t k0, uint32_t k1, int64_t n, double W, const double box[4],
+                     int max_attempts, double* ev, int64_t ld, unsigned long long* bad, hipStream_t s);
 // theta (P doubles) passed by value -> device copy.
 void tddp_launch_copy_theta(const ParamBlock& pb, int P, double* dst, hipStream_t s);
 

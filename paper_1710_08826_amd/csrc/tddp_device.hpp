@@ -179,6 +179,116 @@ __device__ inline void tddp_mrows_body(const DalitzConst& dc, const DalitzTable*
   block_sum_row<NV>(acc, lds, part + (int64_t)blockIdx.x * NV);
 }
 
+// ---------------------------------------------------------------- toy events
+// A and Abar at one point.
+template <class S>
+__device__ __forceinline__ void tddp_amps(const DalitzConst& dc, const double* __restrict__ r,
+                                          const double* __restrict__ coef, double s12, double s13, cplx& A,
+                                          cplx& Ab) {
+  constexpr int K = S::K;
+  double Are[K], Aim[K], Bre[K], Bim[K];
+  tddp_basis<S, false>(dc, r, s12, s13, Are, Aim);
+  tddp_basis<S, true>(dc, r, s12, s13, Bre, Bim);
+  A = {0.0, 0.0};
+  Ab = {0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const double cr = coef[2 * k], ci = coef[2 * k + 1];
+    const double br = coef[2 * K + 2 * k], bi = coef[2 * K + 2 * k + 1];
+    A = {A.re + cr * Are[k] - ci * Aim[k], A.im + cr * Aim[k] + ci * Are[k]};
+    Ab = {Ab.re + br * Bre[k] - bi * Bim[k], Ab.im + br * Bim[k] + bi * Bre[k]};
+  }
+}
+
+// Largest (|A| + |Abar|)^2 over the grid-cell centres inside the region (bits
+// of a non-negative double, ordered like the value) in *vmax.
+template <class S>
+__device__ inline void tddp_gridmax_body(const DalitzConst& dc, const DalitzTable* __restrict__ tab,
+                                         const double* __restrict__ coef, unsigned long long* __restrict__ vmax) {
+  __shared__ double lds[kBlock];
+  const int64_t ncell = (int64_t)dc.nx * dc.ny;
+  const double* r = &tab->r[0][0];
+  double m = 0.0;
+  for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < ncell; c += (int64_t)gridDim.x * kBlock) {
+    const int64_t ix = c / dc.ny, iy = c - ix * dc.ny;
+    const double s12 = dc.a12 + (ix + 0.5) * dc.d12;
+    const double s13 = dc.a13 + (iy + 0.5) * dc.d13;
+    if (!dalitz_inside(dc, s12, s13)) continue;
+    cplx A, Ab;
+    tddp_amps<S>(dc, r, coef, s12, s13, A, Ab);
+    const double e = sqrt(A.re * A.re + A.im * A.im) + sqrt(Ab.re * Ab.re + Ab.im * Ab.im);
+    m = fmax(m, e * e);
+  }
+  lds[threadIdx.x] = m;
+  __syncthreads();
+  for (int h = kBlock / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) lds[threadIdx.x] = fmax(lds[threadIdx.x], lds[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(vmax, (unsigned long long)__double_as_longlong(lds[0]));
+}
+
+// Accept-reject toy events: R(s12, s13, t) <= e^{-lam t} (|A| + |Abar|)^2 with
+// lam = G (1 - |y|), so event i, attempt a takes (u1, u2) from counter
+// (i, 2a, 2) and (u3, u4) from (i, 2a + 1, 2) under key (k0, k1): the
+// candidate (lo12 + u1 (hi12 - lo12), lo13 + u2 (hi13 - lo13), t = -ln(1 - u3)/lam)
+// is kept when it lies in the region and u4 W e^{-lam t} < R; the measured
+// time adds sigma_t times a Box-Muller normal from counter (i, 0, 3).  bad[0]
+// counts kept events with (|A| + |Abar|)^2 > W, bad[1] events left NaN after
+// max_attempts.
+template <class S>
+__device__ inline void tddp_gen_body(const DalitzConst& dc, const DalitzTable* __restrict__ tab,
+                                     const double* __restrict__ coef, const TddpTime& tt, uint32_t k0, uint32_t k1,
+                                     int64_t n, double W, double lo12, double hi12, double lo13, double hi13,
+                                     int max_attempts, double* __restrict__ ev, int64_t ld,
+                                     unsigned long long* __restrict__ bad) {
+#pragma clang fp contract(off)
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double* r = &tab->r[0][0];
+  constexpr int K = S::K;
+  const double x = coef[4 * K], y = coef[4 * K + 1];
+  const double G = tt.gamma;
+  const double lam = G * (1.0 - fabs(y));
+  const double w12 = hi12 - lo12, w13 = hi13 - lo13;
+  double o12 = __builtin_nan(""), o13 = __builtin_nan(""), ot = __builtin_nan(""), env = 0.0;
+  for (int a = 0; a < max_attempts; ++a) {
+    double u1, u2, u3, u4;
+    philox_uniforms((uint64_t)i, 2u * a, 2u, k0, k1, u1, u2);
+    philox_uniforms((uint64_t)i, 2u * a + 1u, 2u, k0, k1, u3, u4);
+    const double s12 = lo12 + u1 * w12;
+    const double s13 = lo13 + u2 * w13;
+    if (!dalitz_inside(dc, s12, s13)) continue;
+    const double t = -log1p(-u3) / lam;
+    cplx A, Ab;
+    tddp_amps<S>(dc, r, coef, s12, s13, A, Ab);
+    const double a2 = A.re * A.re + A.im * A.im, b2 = Ab.re * Ab.re + Ab.im * Ab.im;
+    const double zr = A.re * Ab.re + A.im * Ab.im, zi = A.re * Ab.im - A.im * Ab.re;
+    const double gt = G * t;
+    const double ep = exp(y * gt), em = exp(-y * gt);
+    double sx, cx;
+    sincos(x * gt, &sx, &cx);
+    const double R = 0.5 * exp(-gt) *
+                     ((a2 + b2) * (0.5 * (ep + em)) + (a2 - b2) * cx - 2.0 * zr * (0.5 * (ep - em)) - 2.0 * zi * sx);
+    if (u4 * W * exp(-lam * t) < R) {
+      o12 = s12;
+      o13 = s13;
+      ot = t;
+      const double e = sqrt(a2) + sqrt(b2);
+      env = e * e;
+      break;
+    }
+  }
+  double v1, v2;
+  philox_uniforms((uint64_t)i, 0u, 3u, k0, k1, v1, v2);
+  ot = ot + tt.sigma * (sqrt(-2.0 * log1p(-v1)) * cos(2.0 * 3.14159265358979323846 * v2));
+  ev[i] = o12;
+  ev[ld + i] = o13;
+  ev[2 * ld + i] = ot;
+  if (env > W) atomicAdd(bad, 1ull);
+  if (o12 != o12) atomicAdd(bad + 1, 1ull);
+}
+
 }  // namespace fn
 
 // Kernels for shape S (used by the generated source).
@@ -194,4 +304,16 @@ __device__ inline void tddp_mrows_body(const DalitzConst& dc, const DalitzTable*
       fn::DalitzConst dc, const fn::DalitzTable* __restrict__ tab, int chunk, int i0,                          \
       double* __restrict__ part) {                                                                             \
     fn::tddp_mrows_body<S, WHICH>(dc, tab, chunk, i0, part);                                                   \
+  }
+#define FN_TDDP_GEN(GRIDMAX, GEN, S)                                                                           \
+  extern "C" __global__ __launch_bounds__(fn::kBlock) void GRIDMAX(                                            \
+      fn::DalitzConst dc, const fn::DalitzTable* __restrict__ tab, const double* __restrict__ coef,            \
+      unsigned long long* __restrict__ vmax) {                                                                 \
+    fn::tddp_gridmax_body<S>(dc, tab, coef, vmax);                                                             \
+  }                                                                                                            \
+  extern "C" __global__ __launch_bounds__(fn::kBlock) void GEN(                                                \
+      fn::DalitzConst dc, const fn::DalitzTable* __restrict__ tab, const double* __restrict__ coef,            \
+      fn::TddpTime tt, uint32_t k0, uint32_t k1, int64_t n, double W, double lo12, double hi12, double lo13,   \
+      double hi13, int max_attempts, double* __restrict__ ev, int64_t ld, unsigned long long* __restrict__ bad) { \
+    fn::tddp_gen_body<S>(dc, tab, coef, tt, k0, k1, n, W, lo12, hi12, lo13, hi13, max_attempts, ev, ld, bad);  \
   }
