@@ -312,6 +312,24 @@ def serving_leg(n_fits: int = 4096, one_at_a_time: int = 256, fd_fits: int = 32,
     return out
 
 
+def config3_leg(steps: int = 20):
+    """Config 3: masses and widths free (32 parameters), 4M events, the full
+    grid normalization every call."""
+    import torch
+    import synth
+    from paper_1710_08826_amd import Model
+    desc3 = synth.dalitz_desc(free_lineshapes=True)
+    th3 = synth.dalitz_truth(free_lineshapes=True)
+    ev3 = torch.from_numpy(synth.dalitz_events(4_000_000, seed=synth.BASE_SEED + 3)).cuda()
+    m3 = Model(desc3)
+    t3 = torch.from_numpy(th3).cuda()
+    o3 = torch.empty(1 + m3.n_params, dtype=torch.float64, device="cuda")
+    w3, k3 = time_async(m3, t3, ev3, o3, steps, 3, True)
+    return {"config3_events_per_s": 4_000_000 * steps / w3, "config3_ms_per_step": 1e3 * w3 / steps,
+            "config3_event_kernel_us": k3 * 1e3,
+            "config3_event_kernel_tflops": dalitz_flops_per_event(desc3, 2) * 4e6 / (k3 * 1e-3) / 1e12}
+
+
 def tddp3_leg(steps: int = 50):
     """Time-dependent Dalitz-plot fit (the paper's pi+ pi- pi0 mixing
     workload class): 1M events, 34 parameters, NLL + adjoint gradient, and the
@@ -325,6 +343,7 @@ def tddp3_leg(steps: int = 50):
     ev = torch.from_numpy(synth.tddp3_events(n, seed=synth.BASE_SEED + 7)).cuda()
     m = Model(desc)
     P = m.n_params
+    _, tune_us = m.autotune(th, ev, reps=10)
     tdev = torch.from_numpy(th).cuda()
     tb = torch.from_numpy(th * (1.0 + 1e-3 * np.cos(np.arange(P)))).cuda()
     out = torch.empty(1 + P, dtype=torch.float64, device="cuda")
@@ -333,6 +352,7 @@ def tddp3_leg(steps: int = 50):
     fl = tddp3_flops_per_event(desc, True)
     fd_step = (2 * P + 1) * w0 / steps
     return {"events": n, "params": P, "grid": desc["grid"], "chunk": m.chunk,
+            "autotune_us": {str(c): v for c, v in tune_us.items()},
             "events_per_s": n * steps / w, "ms_per_step": 1e3 * w / steps,
             "event_kernel_us": k * 1e3, "nll_only_event_kernel_us": k0 * 1e3,
             "flops_per_event": fl, "event_kernel_tflops": fl * n / (k * 1e-3) / 1e12,
@@ -427,7 +447,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--quick", action="store_true", help="skip the side measurements and the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--leg", choices=["td4", "serve", "tddp3"],
+    ap.add_argument("--leg", choices=["td4", "serve", "tddp3", "config3"],
                     help="run only the four-body leg or the serving leg and print its figures (for profiling)")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="for counter runs: one 256 MiB device copy (calibration) then --steps "
@@ -451,6 +471,9 @@ def main():
         return
     if args.leg == "tddp3":
         print(json.dumps({"tddp3": tddp3_leg()}), flush=True)
+        return
+    if args.leg == "config3":
+        print(json.dumps(config3_leg()), flush=True)
         return
 
     import torch
@@ -519,20 +542,7 @@ def main():
         print(f"[bench] device generation {extra['config1_generate_events_per_s']:.4g} events/s",
               file=sys.stderr, flush=True)
 
-        # config 3: masses and widths free (32 parameters), 4M events, full grid every call
-        desc3 = synth.dalitz_desc(free_lineshapes=True)
-        th3 = synth.dalitz_truth(free_lineshapes=True)
-        ev3 = torch.from_numpy(synth.dalitz_events(4_000_000, seed=synth.BASE_SEED + 3)).to(dev)
-        m3 = Model(desc3)
-        t3 = torch.from_numpy(th3).to(dev)
-        o3 = torch.empty(1 + m3.n_params, dtype=torch.float64, device=dev)
-        s3 = max(10, args.steps // 10)
-        w3, k3 = time_async(m3, t3, ev3, o3, s3, 3, True)
-        extra["config3_events_per_s"] = 4_000_000 * s3 / w3
-        extra["config3_ms_per_step"] = 1e3 * w3 / s3
-        extra["config3_event_kernel_us"] = k3 * 1e3
-        extra["config3_event_kernel_tflops"] = dalitz_flops_per_event(desc3, 2) * 4e6 / (k3 * 1e-3) / 1e12
-        del ev3
+        extra.update(config3_leg(max(10, args.steps // 10)))
         print(f"[bench] config3 {extra['config3_events_per_s']:.4g} events/s", file=sys.stderr, flush=True)
 
         # config 0: 1-D mixture, 100k events
