@@ -370,13 +370,16 @@ def td4_leg(steps: int = 10):
     n, n_mc, F = 10_000_000, 5_000_000, 64
     t0 = time.perf_counter()
     ev = torch.from_numpy(synth.td4_events(n, seed=synth.BASE_SEED + 4)).cuda()
-    mc = torch.from_numpy(synth.td4_phase_space(n_mc, seed=synth.BASE_SEED + 5)).cuda()
     gen_s = time.perf_counter() - t0
     desc = synth.td4_desc()
     th = synth.td4_truth()
     m = Model(desc)
-    m.set_norm_sample(mc)
-    del mc
+    # the normalization sample generated on the device (the same points as
+    # synth.td4_phase_space(n_mc, seed=BASE_SEED + 5))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.generate_norm_sample(n_mc, seed=synth.BASE_SEED + 5)
+    mc_gen_s = time.perf_counter() - t0
     P = m.n_params
     tdev = torch.from_numpy(th).cuda()
     tb = torch.from_numpy(th * (1.0 + 1e-3 * np.cos(np.arange(P)))).cuda()
@@ -384,7 +387,7 @@ def td4_leg(steps: int = 10):
     fl_g, fl_0 = td4_flops_per_event(desc, True), td4_flops_per_event(desc, False)
     w, k = time_async(m, tdev, ev, out, steps, 2, True, alt=tb)
     w0, k0 = time_async(m, tdev, ev, out, steps, 2, False, alt=tb)
-    r = {"events": n, "mc_points": n_mc, "params": P, "cpu_generation_s": gen_s,
+    r = {"events": n, "mc_points": n_mc, "params": P, "cpu_generation_s": gen_s, "device_mc_sample_s": mc_gen_s,
          "single_events_per_s": n * steps / w, "single_ms_per_step": 1e3 * w / steps,
          "single_event_kernel_ms": k, "single_event_kernel_tflops": fl_g * n / (k * 1e-3) / 1e12,
          "nll_only_event_kernel_ms": k0, "nll_only_event_kernel_tflops": fl_0 * n / (k0 * 1e-3) / 1e12,

@@ -203,6 +203,17 @@ fn_status fn_eval(fn_model* m, const double* theta_host, const double* ev, int64
  * memory before return (the caller may free it).  Synchronous.  Replaces any
  * previous sample and invalidates the cached normalization matrix. */
 fn_status fn_model_set_norm_sample(fn_model* m, const double* mc_dev, int64_t n_mc, int64_t ld, void* stream);
+/* td4 only: the normalization sample generated on the device instead of
+ * copied: n_mc unweighted four-body phase-space points, point i by
+ * accept-reject with Philox4x32-10 counters (i, 100 + 3a, 2), (i, 101 + 3a, 2),
+ * (i, 102 + 3a, 2) for attempt a under key (seed, fit): (m12, m34) uniform in
+ * [m1+m2, M-m3-m4] x [m3+m4, M-m1-m2], kept when m12 + m34 < M and
+ * u3 * wmax < q(M; m12, m34) q(m12; m1, m2) q(m34; m3, m4) (wmax: 1.05 x the
+ * largest weight on an 801 x 801 grid of the box), then cos theta12 = 2 u4 - 1,
+ * cos theta34 = 2 u5 - 1, phi = (2 u6 - 1) pi.  Synchronous; replaces any
+ * previous sample.  FN_E_DOMAIN if a point is not resolved within 4096
+ * attempts (the model then has no sample). */
+fn_status fn_model_generate_norm_sample(fn_model* m, uint32_t seed, uint32_t fit, int64_t n_mc, void* stream);
 /* td4 only: size of the fixed-constant vector and (fixed_host != NULL) the
  * values from the description. */
 fn_status fn_model_fixed(const fn_model* m, int32_t* n_fixed, double* fixed_host);
@@ -330,9 +341,16 @@ fn_status fn_batch_results(fn_batch* b, int32_t* status, double* theta, double* 
 fn_status fn_generate_mix1d(uint32_t seed, uint32_t fit, int64_t n, const double* theta_gen, double lo, double hi,
                             double* x, void* stream);
 
-/* Toy events of a dalitz3 or tddp3 model at theta (host, P doubles) by
+/* Toy events of a dalitz3, tddp3 or td4 model at theta (host, P doubles) by
  * accept-reject on the device, for toy studies (the paper's Monte Carlo
- * generation with MCBooster, Sec. 5).  tddp3 (three rows s12, s13, t): event
+ * generation with MCBooster, Sec. 5).  td4 (six rows m12, m34, cos theta12,
+ * cos theta34, phi, t): attempt a draws a phase-space point as
+ * fn_model_generate_norm_sample does with word 4 and streams 4a, 4a + 1,
+ * 4a + 2, then (u7, u8) from (i, 4a + 3, 4): t = -ln(1 - u7)/lam and the
+ * point is kept when u8 * envelope * exp(-lam t) < R, as for tddp3; the
+ * automatic envelope is 1.2 x the largest (|A| + |Abar|)^2 over the model's
+ * normalization sample (which must be set); Box-Muller from (i, 0, 5); at
+ * most 65536 attempts per event.  tddp3 (three rows s12, s13, t): event
  * i, attempt a takes (u1, u2) from counter (i, 2a, 2) and (u3, u4) from
  * (i, 2a + 1, 2); the candidate point in the box below with
  * t = -ln(1 - u3)/lam, lam = (1 - |y|)/tau, is kept inside the region when

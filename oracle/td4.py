@@ -272,3 +272,94 @@ def generate(theta, desc, n: int, seed: int = 1710088260, fit: int = 0, batch: i
         got += idx.size
         rnd += 1
     return out
+
+
+def _q(m, ma, mb):
+    l = (m * m - (ma + mb) * (ma + mb)) * (m * m - (ma - mb) * (ma - mb))
+    return np.sqrt(np.maximum(l, 0.0)) / (2.0 * m)
+
+
+def ps_weight(desc, m12, m34):
+    """Four-body phase-space density in (m12, m34) with the angles uniform:
+    q(M; m12, m34) q(m12; m1, m2) q(m34; m3, m4) (q: two-body momentum)."""
+    M = float(desc["M"])
+    m1, m2, m3, m4 = (float(v) for v in desc["m"])
+    return _q(M, m12, m34) * _q(m12, m1, m2) * _q(m34, m3, m4)
+
+
+def ps_wmax(desc) -> float:
+    """1.05 x the largest phase-space weight on an 801 x 801 grid of the box."""
+    M = float(desc["M"])
+    m1, m2, m3, m4 = (float(v) for v in desc["m"])
+    a = np.linspace(m1 + m2, M - m3 - m4, 801)
+    b = np.linspace(m3 + m4, M - m1 - m2, 801)
+    A, B = np.meshgrid(a, b, indexing="ij")
+    w = np.where(A + B < M, ps_weight(desc, A, B), 0.0)
+    return 1.05 * float(w.max())
+
+
+GEN_MAX_ATTEMPTS = 65536  # the four-body acceptance is near 1e-3 per attempt
+
+
+def generate_events(theta, desc, n: int, seed: int, fit: int = 0, W: float = None, batch_env: int = 200_000):
+    """Toy events (6, n) of the model, event by event: attempt a of event i takes
+    (u1, u2), (u3, u4), (u5, u6), (u7, u8) from Philox counters (i, 4a + j,
+    word 4), j = 0..3, key (seed, fit): (m12, m34) uniform in the box, kept
+    when m12 + m34 < M and u3 wmax < ps_weight; c12 = 2 u4 - 1,
+    c34 = 2 u5 - 1, phi = (2 u6 - 1) pi; t = -ln(1 - u7)/lam,
+    lam = G (1 - |y|); kept when u8 W e^{-lam t} < R (the unconvolved rate,
+    at most e^{-lam t} (|A| + |Abar|)^2, as in `generate`).  The measured
+    time adds sigma_t times a Box-Muller normal from counter (i, 0, 5).
+    Returns (events, W, number of kept events with (|A| + |Abar|)^2 > W)."""
+    from synth import td4_phase_space
+    from synth.philox import key_from_seed, uniforms_at
+    model = TD4(desc)
+    th = as_t(theta)
+    M = model.M
+    m1, m2, m3, m4 = model.m
+    lo12, hi12 = m1 + m2, M - m3 - m4
+    lo34, hi34 = m3 + m4, M - m1 - m2
+    wmax = ps_wmax(desc)
+    G = 1.0 / model.tau
+    y = float(theta[model.P - 1])
+    lam = G * (1.0 - abs(y))
+    if W is None:
+        with torch.no_grad():
+            ps = torch.from_numpy(td4_phase_space(batch_env, seed, fit, stream0=5000))
+            A, Ab = model.amplitudes(th, model.basis(ps))
+            W = 1.2 * float(((A.abs() + Ab.abs()) ** 2).max())
+    key = key_from_seed(seed, fit)
+    out = np.full((6, n), np.nan)
+    todo = np.arange(n, dtype=np.uint64)
+    above = 0
+    for a in range(GEN_MAX_ATTEMPTS):
+        if todo.size == 0:
+            break
+        u1, u2 = uniforms_at(todo, key, 4 * a, 4)
+        u3, u4 = uniforms_at(todo, key, 4 * a + 1, 4)
+        u5, u6 = uniforms_at(todo, key, 4 * a + 2, 4)
+        u7, u8 = uniforms_at(todo, key, 4 * a + 3, 4)
+        m12 = lo12 + u1 * (hi12 - lo12)
+        m34 = lo34 + u2 * (hi34 - lo34)
+        ok = (m12 + m34 < M) & (u3 * wmax < ps_weight(desc, m12, m34))
+        keep = np.zeros(todo.size, dtype=bool)
+        if ok.any():
+            kin = np.stack([m12[ok], m34[ok], 2.0 * u4[ok] - 1.0, 2.0 * u5[ok] - 1.0, (2.0 * u6[ok] - 1.0) * math.pi])
+            t = -np.log1p(-u7[ok]) / lam
+            with torch.no_grad():
+                kt = torch.from_numpy(kin)
+                r = unconvolved_rate(model, th, kt, torch.from_numpy(t)).numpy()
+                A, Ab = model.amplitudes(th, model.basis(kt))
+                env = ((A.abs() + Ab.abs()) ** 2).numpy()
+            k = u8[ok] * W * np.exp(-lam * t) < r
+            sel = np.flatnonzero(ok)[k]
+            keep[sel] = True
+            above += int((env[k] > W).sum())
+            idx = todo[sel].astype(np.int64)
+            out[:5, idx] = kin[:, k]
+            out[5, idx] = t[k]
+        todo = todo[~keep]
+    i = np.arange(n, dtype=np.uint64)
+    v1, v2 = uniforms_at(i, key, 0, 5)
+    out[5] = out[5] + model.sigma * np.sqrt(-2.0 * np.log1p(-v1)) * np.cos(2.0 * math.pi * v2)
+    return out, W, above

@@ -144,6 +144,13 @@ class Model:
         check(self._lib.fn_model_set_norm_sample(self._h, C.c_void_p(mc.data_ptr()), mc.shape[1], mc.stride(0),
                                                  _stream_ptr(stream)))
 
+    def generate_norm_sample(self, n_mc: int, seed: int, fit: int = 0, stream=None):
+        """td4: generate the n_mc-point phase-space normalization sample on the
+        device (fn_model_generate_norm_sample)."""
+        check(self._lib.fn_model_generate_norm_sample(self._h, C.c_uint32(seed & 0xFFFFFFFF),
+                                                      C.c_uint32(fit & 0xFFFFFFFF), int(n_mc),
+                                                      _stream_ptr(stream)))
+
     def fixed(self) -> np.ndarray:
         """td4: the description's fixed-constant vector."""
         n = C.c_int32()
@@ -153,8 +160,9 @@ class Model:
         return v
 
     def generate(self, theta, n: int, seed: int, fit: int = 0, envelope: float = 0.0, stream=None):
-        """dalitz3: n toy events at theta by accept-reject on the device, as a
-        (2, n) float64 CUDA tensor, and the envelope used (fn_generate)."""
+        """dalitz3, tddp3, td4: n toy events at theta by accept-reject on the
+        device, as an (n_obs, n) float64 CUDA tensor, and the envelope used
+        (fn_generate)."""
         th, thp = self._theta(theta)
         ev = torch.empty((self.n_obs, n), dtype=torch.float64, device=f"cuda:{self.device}")
         used = C.c_double()

@@ -23,6 +23,10 @@ namespace fn {
 // on the integration grid when the caller gives none; attempts per event.
 constexpr double kGenEnvelopeFactor = 1.2;
 constexpr int kGenMaxAttemptsModel = 4096;
+constexpr int kGenMaxAttemptsTd4 = 65536;  // four-body model acceptance is near 1e-3 per attempt
+// First counter stream of the four-body phase-space sample (the sample of
+// fn_model_generate_norm_sample is that of the input sampler's default).
+constexpr uint32_t kPhaseSpaceStream0 = 100;
 
 // Chunk sizes (events per workgroup) tried by fn_model_autotune.
 constexpr int kTuneChunks[] = {256, 512, 1024, 2048, 4096, 8192, 16384};
@@ -287,6 +291,10 @@ static void compile_td4(const json::Value& d, fn_model* m, bool device = true) {
   if (!(mm[0] > 0 && mm[1] > 0 && mm[2] > 0 && mm[3] > 0) || !(M > mm[0] + mm[1] + mm[2] + mm[3]))
     throw Error(FN_E_INVALID, "td4: masses must be positive and M > m1 + m2 + m3 + m4");
   tc.M = M;
+  tc.m1 = mm[0];
+  tc.m2 = mm[1];
+  tc.m3 = mm[2];
+  tc.m4 = mm[3];
   tc.m1s = mm[0] * mm[0];
   tc.m2s = mm[1] * mm[1];
   tc.m3s = mm[2] * mm[2];
@@ -302,6 +310,7 @@ static void compile_td4(const json::Value& d, fn_model* m, bool device = true) {
   if (!(tau > 0.0)) throw Error(FN_E_INVALID, "td4: tau must be > 0");
   tc.gamma = 1.0 / tau;
   td4_weideman_coefficients(tc.wa, &tc.wL);
+  tc.ps_wmax = td4_ps_wmax(tc);
   std::vector<double> fixed;
   auto pair = [&](const char* key, int* n, int* L, int* nr) {
     const auto& rs = d.at(key).array();
@@ -560,6 +569,47 @@ void nll_binned_host(fn_model* m, const double* theta_host, const BinnedData& bd
     throw Error(FN_E_NONFINITE, "binned statistic is not finite (P <= 0 in a filled bin, invalid parameters, "
                                 "or no events)");
   if (gbad) throw Error(FN_E_NONFINITE, "gradient is not finite");
+}
+
+void generate_td4(fn_model* m, const double* theta_host, uint32_t seed, uint32_t fit, int64_t n, double envelope,
+                  double* ev_dev, int64_t ld, double* envelope_used, hipStream_t s) {
+  if (n < 0 || (n > 0 && !ev_dev)) throw Error(FN_E_INVALID, "bad output");
+  if (ld < n) throw Error(FN_E_INVALID, "ld must be >= n");
+  if (!(envelope >= 0.0) || !std::isfinite(envelope)) throw Error(FN_E_INVALID, "envelope must be finite and >= 0");
+  if (!(std::fabs(theta_host[m->P - 1]) < 1.0)) throw Error(FN_E_INVALID, "td4 generation needs |y| < 1");
+  hip_check(hipSetDevice(m->device), "hipSetDevice");
+  const Td4Const& tc = m->td4;
+  const ParamBlock pb = make_block(m, theta_host);
+  const Td4FitConst* fc = (const Td4FitConst*)m->d_fixed.ptr;
+  td4_launch_prologue(tc, &pb, nullptr, m->P, fc, nullptr, 1, m->table_td4(), s);
+  m->d_gen.reserve(3 * sizeof(unsigned long long));
+  unsigned long long* g = (unsigned long long*)m->d_gen.ptr;
+  hip_check(hipMemsetAsync(g, 0, 3 * sizeof(unsigned long long), s), "hipMemsetAsync");
+  double W = envelope;
+  if (W == 0.0) {
+    if (m->n_mc <= 0)
+      throw Error(FN_E_INVALID, "td4: the automatic envelope needs the normalization sample (or give an envelope)");
+    td4_launch_envmax(*m->td4_jit, tc, m->table_td4(), (const double*)m->d_mc.ptr, m->n_mc, m->n_mc, g, s);
+    hip_check(hipGetLastError(), "kernel launch");
+    unsigned long long bits = 0;
+    hip_check(hipMemcpyAsync(&bits, g, sizeof(bits), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    double vmax;
+    std::memcpy(&vmax, &bits, sizeof(vmax));
+    if (!(vmax > 0.0) || !std::isfinite(vmax)) throw Error(FN_E_INVALID, "the amplitudes vanish on the sample");
+    W = kGenEnvelopeFactor * vmax;
+  }
+  if (envelope_used) *envelope_used = W;
+  if (n == 0) return;
+  td4_launch_gen(*m->td4_jit, tc, m->table_td4(), seed, fit, n, W, kGenMaxAttemptsTd4, ev_dev, ld, g + 1, s);
+  hip_check(hipGetLastError(), "kernel launch");
+  unsigned long long bad[2] = {0, 0};
+  hip_check(hipMemcpyAsync(bad, g + 1, sizeof(bad), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+  hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+  if (bad[0])
+    throw Error(FN_E_DOMAIN, std::to_string(bad[0]) + " accepted events lie above the envelope " + std::to_string(W) +
+                                 ": raise it");
+  if (bad[1]) throw Error(FN_E_DOMAIN, std::to_string(bad[1]) + " events not resolved within the attempt limit");
 }
 
 }  // namespace fn
@@ -830,8 +880,12 @@ fn_status fn_generate(fn_model* m, const double* theta_host, uint32_t seed, uint
                       double envelope, double* ev_dev, int64_t ld, double* envelope_used, void* stream) {
   return guard([&] {
     if (!m || !theta_host) throw Error(FN_E_INVALID, "NULL argument");
+    if (m->kind == kKindTd4) {
+      generate_td4(m, theta_host, seed, fit, n, envelope, ev_dev, ld, envelope_used, (hipStream_t)stream);
+      return;
+    }
     if (m->kind != kKindDalitz3 && m->kind != kKindTddp3)
-      throw Error(FN_E_INVALID, "device generation by model is available for dalitz3 and tddp3 models "
+      throw Error(FN_E_INVALID, "device generation by model is available for dalitz3, tddp3 and td4 models "
                                 "(mix1d: fn_generate_mix1d)");
     const bool td = m->kind == kKindTddp3;
     if (n < 0 || (n > 0 && !ev_dev)) throw Error(FN_E_INVALID, "bad output");
@@ -883,6 +937,33 @@ fn_status fn_generate(fn_model* m, const double* theta_host, uint32_t seed, uint
       throw Error(FN_E_DOMAIN, std::to_string(bad[0]) + " accepted events lie above the envelope " +
                                    std::to_string(W) + ": raise it");
     if (bad[1]) throw Error(FN_E_DOMAIN, std::to_string(bad[1]) + " events not resolved within the attempt limit");
+  });
+}
+
+fn_status fn_model_generate_norm_sample(fn_model* m, uint32_t seed, uint32_t fit, int64_t n_mc, void* stream) {
+  return guard([&] {
+    if (!m) throw Error(FN_E_INVALID, "model is NULL");
+    if (m->kind != kKindTd4) throw Error(FN_E_INVALID, "only td4 models take a normalization sample");
+    if (n_mc <= 0) throw Error(FN_E_INVALID, "need n_mc > 0");
+    hip_check(hipSetDevice(m->device), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    m->d_mc.reserve(sizeof(double) * 5 * (size_t)n_mc);
+    m->d_gen.reserve(3 * sizeof(unsigned long long));
+    unsigned long long* g = (unsigned long long*)m->d_gen.ptr;
+    hip_check(hipMemsetAsync(g, 0, sizeof(unsigned long long), s), "hipMemsetAsync");
+    td4_launch_phase_space(m->td4, seed, fit, kPhaseSpaceStream0, kGenMaxAttemptsModel, n_mc, (double*)m->d_mc.ptr,
+                           n_mc, g, s);
+    hip_check(hipGetLastError(), "kernel launch");
+    unsigned long long bad = 0;
+    hip_check(hipMemcpyAsync(&bad, g, sizeof(bad), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    m->n_mc = n_mc;
+    m->mc_gen += 1;
+    m->M_valid = false;
+    if (bad) {
+      m->n_mc = 0;
+      throw Error(FN_E_DOMAIN, std::to_string(bad) + " phase-space points not resolved within the attempt limit");
+    }
   });
 }
 

@@ -4,6 +4,7 @@
 // finalize, per-event density, domain check).  The per-event and
 // normalization-matrix passes live in td4_device.hpp and are compiled at model
 // creation with the model's shape as compile-time constants (td4_jit below).
+#include <algorithm>
 #include <cmath>
 #include <sstream>
 #include <vector>
@@ -341,16 +342,19 @@ std::string td4_jit_source(const Td4Const& tc) {
   o << "};\n"
        "FN_TD4_EVENTS(fn_td4_ev0, fn_td4_shape, false)\n"
        "FN_TD4_EVENTS(fn_td4_ev1, fn_td4_shape, true)\n"
-       "FN_TD4_MROWS(fn_td4_mrows, fn_td4_shape)\n";
+       "FN_TD4_MROWS(fn_td4_mrows, fn_td4_shape)\n"
+       "FN_TD4_GEN(fn_td4_envmax, fn_td4_gen, fn_td4_shape)\n";
   return o.str();
 }
 
 std::shared_ptr<Td4Jit> td4_jit(const Td4Const& tc) {
   auto j = std::make_shared<Td4Jit>();
-  j->prog = jit_load(td4_jit_source(tc), {"fn_td4_ev0", "fn_td4_ev1", "fn_td4_mrows"});
+  j->prog = jit_load(td4_jit_source(tc), {"fn_td4_ev0", "fn_td4_ev1", "fn_td4_mrows", "fn_td4_envmax", "fn_td4_gen"});
   j->ev[0] = j->prog->fns[0];
   j->ev[1] = j->prog->fns[1];
   j->mrows = j->prog->fns[2];
+  j->envmax = j->prog->fns[3];
+  j->gen = j->prog->fns[4];
   return j;
 }
 
@@ -400,6 +404,74 @@ void td4_launch_eval(const Td4Const& tc, const Td4Table* tab, const double* ev, 
                      const double* norm, double* p, hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(td4_eval, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tc, tab, ev, ld, n, norm, p);
+}
+
+// ------------------------------------------------------- phase-space sample
+// 1.05 x the largest phase-space weight on a 801 x 801 grid of (m12, m34)
+// over the box, points spaced like a linear grid whose last point is the
+// upper edge, zero weight where m12 + m34 >= M.
+double td4_ps_wmax(const Td4Const& tc) {
+#pragma clang fp contract(off)
+  const int n = 801;
+  const double lo12 = tc.m1 + tc.m2, hi12 = tc.M - tc.m3 - tc.m4;
+  const double lo34 = tc.m3 + tc.m4, hi34 = tc.M - tc.m1 - tc.m2;
+  const double d12 = (hi12 - lo12) / (n - 1), d34 = (hi34 - lo34) / (n - 1);
+  double w = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double a = i == n - 1 ? hi12 : (double)i * d12 + lo12;
+    for (int j = 0; j < n; ++j) {
+      const double b = j == n - 1 ? hi34 : (double)j * d34 + lo34;
+      if (a + b < tc.M) w = std::max(w, td4_ps_weight(tc, a, b));
+    }
+  }
+  return 1.05 * w;
+}
+
+__global__ void td4_phase_space_kernel(Td4Const tc, uint32_t k0, uint32_t k1, uint32_t s0, int max_attempts,
+                                       int64_t n, double* __restrict__ out, int64_t ld,
+                                       unsigned long long* __restrict__ bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double x[5];
+  if (!td4_ps_point(tc, i, k0, k1, s0, max_attempts, x)) {
+    for (int j = 0; j < 5; ++j) x[j] = __builtin_nan("");
+    atomicAdd(bad, 1ull);
+  }
+  for (int j = 0; j < 5; ++j) out[j * ld + i] = x[j];
+}
+
+void td4_launch_phase_space(const Td4Const& tc, uint32_t k0, uint32_t k1, uint32_t s0, int max_attempts, int64_t n,
+                            double* out, int64_t ld, unsigned long long* bad, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(td4_phase_space_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tc, k0, k1, s0,
+                     max_attempts, n, out, ld, bad);
+}
+
+void td4_launch_envmax(const Td4Jit& j, const Td4Const& tc, const Td4Table* tab, const double* mc, int64_t ld,
+                       int64_t n, unsigned long long* vmax, hipStream_t s) {
+  const int64_t blocks = std::min<int64_t>((n + kBlock - 1) / kBlock, 4096);
+  Td4Const c = tc;
+  const Td4Table* t = tab;
+  const double* p = mc;
+  int64_t l = ld, nn = n;
+  unsigned long long* v = vmax;
+  void* args[] = {&c, &t, &p, &l, &nn, &v};
+  jit_launch(j.envmax, (unsigned)blocks, kBlock, s, args);
+}
+
+void td4_launch_gen(const Td4Jit& j, const Td4Const& tc, const Td4Table* tab, uint32_t k0, uint32_t k1, int64_t n,
+                    double W, int max_attempts, double* ev, int64_t ld, unsigned long long* bad, hipStream_t s) {
+  if (n == 0) return;
+  Td4Const c = tc;
+  const Td4Table* t = tab;
+  uint32_t a0 = k0, a1 = k1;
+  int64_t nn = n, l = ld;
+  double w = W;
+  int ma = max_attempts;
+  double* e = ev;
+  unsigned long long* b = bad;
+  void* args[] = {&c, &t, &a0, &a1, &nn, &w, &ma, &e, &l, &b};
+  jit_launch(j.gen, (unsigned)((n + kBlock - 1) / kBlock), kBlock, s, args);
 }
 
 }  // namespace fn

@@ -14,12 +14,26 @@ struct Td4Jit {
   std::shared_ptr<JitProgram> prog;
   hipFunction_t ev[2] = {nullptr, nullptr};  // without, with the gradient
   hipFunction_t mrows = nullptr;
+  hipFunction_t envmax = nullptr, gen = nullptr;  // toy generation
 };
 std::string td4_jit_source(const Td4Const& tc);
 std::shared_ptr<Td4Jit> td4_jit(const Td4Const& tc);
 int td4_kmax(int K);
 int td4_nv(int kmax, bool grad);
 void td4_weideman_coefficients(double* a, double* L);
+// Bound of the phase-space weight used by the generators (host).
+double td4_ps_wmax(const Td4Const& tc);
+// n unweighted phase-space points (5 rows of leading dimension ld) from key
+// (k0, k1) and first stream s0; bad counts points left NaN.
+void td4_launch_phase_space(const Td4Const& tc, uint32_t k0, uint32_t k1, uint32_t s0, int max_attempts, int64_t n,
+                            double* out, int64_t ld, unsigned long long* bad, hipStream_t s);
+// Toy events of the model (6 rows): vmax (zeroed by the caller) receives the
+// largest (|A| + |Abar|)^2 over a phase-space sample; bad[0] / bad[1] as for
+// the three-body generator.
+void td4_launch_envmax(const Td4Jit& j, const Td4Const& tc, const Td4Table* tab, const double* mc, int64_t ld,
+                       int64_t n, unsigned long long* vmax, hipStream_t s);
+void td4_launch_gen(const Td4Jit& j, const Td4Const& tc, const Td4Table* tab, uint32_t k0, uint32_t k1, int64_t n,
+                    double W, int max_attempts, double* ev, int64_t ld, unsigned long long* bad, hipStream_t s);
 // theta: n_fits rows of theta_stride doubles on the device, or (pb != null,
 // n_fits == 1) the parameter block passed by value.
 void td4_launch_prologue(const Td4Const& tc, const ParamBlock* pb, const double* theta, int theta_stride,

@@ -24,6 +24,7 @@
 #pragma once
 #include "device_common.hpp"
 #include "fastmath.hpp"
+#include "philox.hpp"
 #include "td4_types.hpp"
 
 namespace fn {
@@ -259,6 +260,151 @@ __device__ inline void td4_events_body(const Td4Const& tc, const Td4Table* __res
   block_sum_row<NV>(acc, lds, part + ((int64_t)f * nch + ch) * NV);
 }
 
+// ------------------------------------------------------ four-body phase space
+// Two-body momentum q(m; ma, mb) and the phase-space weight of (m12, m34)
+// with the angles uniform: q(M; m12, m34) q(m12; m1, m2) q(m34; m3, m4).
+// Contraction is off: the weight decides accept-reject draws and is the same
+// plain IEEE evaluation on the host and the device.
+__host__ __device__ inline double td4_q(double m, double ma, double mb) {
+#pragma clang fp contract(off)
+  const double l = (m * m - (ma + mb) * (ma + mb)) * (m * m - (ma - mb) * (ma - mb));
+  return sqrt(l > 0.0 ? l : 0.0) / (2.0 * m);
+}
+__host__ __device__ inline double td4_ps_weight(const Td4Const& tc, double m12, double m34) {
+#pragma clang fp contract(off)
+  return td4_q(tc.M, m12, m34) * td4_q(m12, tc.m1, tc.m2) * td4_q(m34, tc.m3, tc.m4);
+}
+
+// Unweighted phase-space point i (m12, m34, cos theta12, cos theta34, phi):
+// attempt a takes (u1, u2) from counter (i, s0 + 3a, 2), (u3, u4) from
+// (i, s0 + 3a + 1, 2) and (u5, u6) from (i, s0 + 3a + 2, 2); (m12, m34)
+// uniform in [m1 + m2, M - m3 - m4] x [m3 + m4, M - m1 - m2] is kept when
+// m12 + m34 < M and u3 wmax < weight; then c12 = 2 u4 - 1, c34 = 2 u5 - 1,
+// phi = (2 u6 - 1) pi.  false when no attempt is kept.
+__device__ inline bool td4_ps_point(const Td4Const& tc, int64_t i, uint32_t k0, uint32_t k1, uint32_t s0,
+                                    int max_attempts, double (&x)[5]) {
+#pragma clang fp contract(off)
+  const double lo12 = tc.m1 + tc.m2, hi12 = tc.M - tc.m3 - tc.m4;
+  const double lo34 = tc.m3 + tc.m4, hi34 = tc.M - tc.m1 - tc.m2;
+  for (int a = 0; a < max_attempts; ++a) {
+    double u1, u2, u3, u4, u5, u6;
+    philox_uniforms((uint64_t)i, s0 + 3u * a, 2u, k0, k1, u1, u2);
+    philox_uniforms((uint64_t)i, s0 + 3u * a + 1u, 2u, k0, k1, u3, u4);
+    philox_uniforms((uint64_t)i, s0 + 3u * a + 2u, 2u, k0, k1, u5, u6);
+    const double m12 = lo12 + u1 * (hi12 - lo12);
+    const double m34 = lo34 + u2 * (hi34 - lo34);
+    if (m12 + m34 < tc.M && u3 * tc.ps_wmax < td4_ps_weight(tc, m12, m34)) {
+      x[0] = m12;
+      x[1] = m34;
+      x[2] = 2.0 * u4 - 1.0;
+      x[3] = 2.0 * u5 - 1.0;
+      x[4] = (2.0 * u6 - 1.0) * 3.14159265358979323846;
+      return true;
+    }
+  }
+  return false;
+}
+
+// Toy events of the model by accept-reject: event i, attempt a draws a
+// phase-space point as td4_ps_point with key (k0, k1), word 2 replaced by 4
+// (streams 4a, 4a + 1, 4a + 2) and (u7, u8) from (i, 4a + 3, 4): t = -ln(1 - u7)/lam,
+// lam = G (1 - |y|); kept when u8 W e^{-lam t} < R (the unconvolved rate, at
+// most e^{-lam t} (|A| + |Abar|)^2); the measured time adds sigma times a
+// Box-Muller normal from counter (i, 0, 5).  bad[0] counts kept events with
+// (|A| + |Abar|)^2 > W, bad[1] events left NaN.
+template <class S>
+__device__ inline void td4_gen_body(const Td4Const& tc, const Td4Table* __restrict__ tab, uint32_t k0, uint32_t k1,
+                                    int64_t n, double W, int max_attempts, double* __restrict__ ev, int64_t ld,
+                                    unsigned long long* __restrict__ bad) {
+#pragma clang fp contract(off)
+  constexpr int K = S::K;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const Td4Table& tb = *tab;
+  const double G = tc.gamma, x = tb.x, y = tb.y;
+  const double lam = G * (1.0 - fabs(y));
+  const double lo12 = tc.m1 + tc.m2, hi12 = tc.M - tc.m3 - tc.m4;
+  const double lo34 = tc.m3 + tc.m4, hi34 = tc.M - tc.m1 - tc.m2;
+  double out[6];
+  for (int j = 0; j < 6; ++j) out[j] = __builtin_nan("");
+  double env = 0.0;
+  for (int a = 0; a < max_attempts; ++a) {
+    double u1, u2, u3, u4, u5, u6, u7, u8;
+    philox_uniforms((uint64_t)i, 4u * a, 4u, k0, k1, u1, u2);
+    philox_uniforms((uint64_t)i, 4u * a + 1u, 4u, k0, k1, u3, u4);
+    philox_uniforms((uint64_t)i, 4u * a + 2u, 4u, k0, k1, u5, u6);
+    philox_uniforms((uint64_t)i, 4u * a + 3u, 4u, k0, k1, u7, u8);
+    const double m12 = lo12 + u1 * (hi12 - lo12);
+    const double m34 = lo34 + u2 * (hi34 - lo34);
+    if (!(m12 + m34 < tc.M) || !(u3 * tc.ps_wmax < td4_ps_weight(tc, m12, m34))) continue;
+    const double c12 = 2.0 * u4 - 1.0, c34 = 2.0 * u5 - 1.0, phi = (2.0 * u6 - 1.0) * 3.14159265358979323846;
+    const double t = -log1p(-u7) / lam;
+    cplx B[K];
+    td4_basis_s<S>(tc, tb, m12, m34, c12, c34, phi, B);
+    cplx A = {0.0, 0.0}, Ab = {0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const cplx p = cmul({tb.c[k][0], tb.c[k][1]}, B[k]);
+      const cplx q = cmul({tb.cb[k][0], tb.cb[k][1]}, B[k]);
+      A = {A.re + p.re, A.im + p.im};
+      Ab = {Ab.re + q.re, Ab.im + q.im};
+    }
+    const double a2 = A.re * A.re + A.im * A.im, b2 = Ab.re * Ab.re + Ab.im * Ab.im;
+    const double zr = A.re * Ab.re + A.im * Ab.im, zi = A.re * Ab.im - A.im * Ab.re;
+    const double gt = G * t;
+    const double ep = exp(y * gt), em = exp(-y * gt);
+    double sx, cx;
+    sincos(x * gt, &sx, &cx);
+    const double R = 0.5 * exp(-gt) *
+                     ((a2 + b2) * (0.5 * (ep + em)) + (a2 - b2) * cx - 2.0 * zr * (0.5 * (ep - em)) - 2.0 * zi * sx);
+    if (u8 * W * exp(-lam * t) < R) {
+      out[0] = m12; out[1] = m34; out[2] = c12; out[3] = c34; out[4] = phi; out[5] = t;
+      const double e = sqrt(a2) + sqrt(b2);
+      env = e * e;
+      break;
+    }
+  }
+  double v1, v2;
+  philox_uniforms((uint64_t)i, 0u, 5u, k0, k1, v1, v2);
+  out[5] = out[5] + tb.sigma * (sqrt(-2.0 * log1p(-v1)) * cos(2.0 * 3.14159265358979323846 * v2));
+  for (int j = 0; j < 6; ++j) ev[j * ld + i] = out[j];
+  if (env > W) atomicAdd(bad, 1ull);
+  if (out[0] != out[0]) atomicAdd(bad + 1, 1ull);
+}
+
+// Largest (|A| + |Abar|)^2 over the points of a phase-space sample (bits of a
+// non-negative double) in *vmax.
+template <class S>
+__device__ inline void td4_envmax_body(const Td4Const& tc, const Td4Table* __restrict__ tab,
+                                       const double* __restrict__ mc, int64_t ld, int64_t n,
+                                       unsigned long long* __restrict__ vmax) {
+  constexpr int K = S::K;
+  __shared__ double lds[kBlock];
+  const Td4Table& tb = *tab;
+  double m = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+    cplx B[K];
+    td4_basis_s<S>(tc, tb, mc[i], mc[ld + i], mc[2 * ld + i], mc[3 * ld + i], mc[4 * ld + i], B);
+    cplx A = {0.0, 0.0}, Ab = {0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const cplx p = cmul({tb.c[k][0], tb.c[k][1]}, B[k]);
+      const cplx q = cmul({tb.cb[k][0], tb.cb[k][1]}, B[k]);
+      A = {A.re + p.re, A.im + p.im};
+      Ab = {Ab.re + q.re, Ab.im + q.im};
+    }
+    const double e = sqrt(A.re * A.re + A.im * A.im) + sqrt(Ab.re * Ab.re + Ab.im * Ab.im);
+    m = fmax(m, e * e);
+  }
+  lds[threadIdx.x] = m;
+  __syncthreads();
+  for (int h = kBlock / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) lds[threadIdx.x] = fmax(lds[threadIdx.x], lds[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(vmax, (unsigned long long)__double_as_longlong(lds[0]));
+}
+
 constexpr int kTd4RowBlock = 4;
 
 // Rows i0..i0+3 of M = sum over the phase-space sample of B_i conj(B_j) (per fit).
@@ -313,4 +459,15 @@ __device__ inline void td4_mrows_body(const Td4Const& tc, const Td4Table* __rest
       fn::Td4Const tc, const fn::Td4Table* __restrict__ tabs, const double* __restrict__ mc, int64_t ld,       \
       int64_t n, int chunk, int64_t nch, int n_fits, int i0, double* __restrict__ part) {                      \
     fn::td4_mrows_body<S>(tc, tabs, mc, ld, n, chunk, nch, n_fits, i0, part);                                   \
+  }
+#define FN_TD4_GEN(ENVMAX, GEN, S)                                                                             \
+  extern "C" __global__ __launch_bounds__(fn::kBlock) void ENVMAX(                                             \
+      fn::Td4Const tc, const fn::Td4Table* __restrict__ tab, const double* __restrict__ mc, int64_t ld,       \
+      int64_t n, unsigned long long* __restrict__ vmax) {                                                      \
+    fn::td4_envmax_body<S>(tc, tab, mc, ld, n, vmax);                                                          \
+  }                                                                                                            \
+  extern "C" __global__ __launch_bounds__(fn::kBlock) void GEN(                                                \
+      fn::Td4Const tc, const fn::Td4Table* __restrict__ tab, uint32_t k0, uint32_t k1, int64_t n, double W,    \
+      int max_attempts, double* __restrict__ ev, int64_t ld, unsigned long long* __restrict__ bad) {           \
+    fn::td4_gen_body<S>(tc, tab, k0, k1, n, W, max_attempts, ev, ld, bad);                                     \
   }

@@ -14,6 +14,8 @@ struct Td4Const {
   double m1s, m2s, m3s, m4s;           // squared daughter masses
   double sum12, dif12, sum34, dif34;   // (m1 +- m2)^2, (m3 +- m4)^2
   double r2;                           // squared barrier radius
+  double m1, m2, m3, m4;               // daughter masses
+  double ps_wmax;                      // phase-space weight bound of the generators
   double gamma;                        // 1 / tau
   double wL;                           // Faddeeva approximation scale L
   double wa[kWeidN];                   // its polynomial coefficients a_1..a_N

@@ -159,3 +159,46 @@ def test_generator_kinematics_follow_the_amplitude():
     exp = prob / prob.sum() * ev.shape[1]
     chi2 = (((counts - exp) ** 2) / exp).sum()
     assert chi2 < 35, chi2  # 11 dof
+
+
+# ------------------------------------------------ per-event generator (the device's definition)
+@pytest.fixture(scope="module")
+def per_event_toys():
+    ev, W, above = OT.generate_events(SMALL_TH, SMALL, 4000, seed=14)
+    th0 = SMALL_TH.copy()
+    th0[-2:] = 0.0
+    ev0, _, above0 = OT.generate_events(th0, SMALL, 4000, seed=15)
+    return ev, W, above, ev0, above0
+
+
+def test_per_event_generator_time_without_mixing(per_event_toys):
+    _, _, _, ev0, above0 = per_event_toys
+    assert above0 == 0 and np.isfinite(ev0).all()
+    n = ev0.shape[1]
+    tau, s = synth.TD4_TAU, synth.TD4_SIGMA_T
+    sd = math.sqrt(tau * tau + s * s)
+    assert abs(ev0[5].mean() - tau) < 4 * sd / math.sqrt(n)
+    assert abs(ev0[5].var() / (sd * sd) - 1) < 4 * math.sqrt(8.0 / n)
+
+
+def test_per_event_generator_kinematics(per_event_toys):
+    ev, W, above, _, _ = per_event_toys
+    assert above == 0 and np.isfinite(ev).all()
+    ps = synth.td4_phase_space(200_000, seed=16)
+    model = OT.TD4(SMALL)
+    with torch.no_grad():
+        w = model.integrated_rate(torch.tensor(SMALL_TH), torch.tensor(ps)).numpy()
+    for row in (0, 1, 2):
+        edges = np.quantile(ev[row], np.linspace(0, 1, 13))
+        edges[0], edges[-1] = -10.0, 10.0
+        counts, _ = np.histogram(ev[row], edges)
+        prob, _ = np.histogram(ps[row], edges, weights=w)
+        exp = prob / prob.sum() * ev.shape[1]
+        chi2 = (((counts - exp) ** 2) / exp).sum()
+        assert chi2 < 35, (row, chi2)  # 11 dof
+
+
+def test_per_event_generator_prefix(per_event_toys):
+    ev, W, _, _, _ = per_event_toys
+    head, W2, _ = OT.generate_events(SMALL_TH, SMALL, 200, seed=14, W=W)
+    assert W2 == W and np.array_equal(head, ev[:, :200])
