@@ -35,6 +35,16 @@ struct cplx {
 __device__ __forceinline__ cplx cmul(cplx a, cplx b) {
   return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
 }
+// c + a b as four chained FMAs
+__device__ __forceinline__ cplx cfma(cplx a, cplx b, cplx c) {
+  return {__builtin_fma(a.re, b.re, __builtin_fma(-a.im, b.im, c.re)),
+          __builtin_fma(a.re, b.im, __builtin_fma(a.im, b.re, c.im))};
+}
+// (gr, gi) += (Re(l b), -Im(l b)): a gradient pair d/dRe, d/dIm from l b
+__device__ __forceinline__ void grad_acc(cplx l, cplx b, double& gr, double& gi) {
+  gr = __builtin_fma(l.re, b.re, __builtin_fma(-l.im, b.im, gr));
+  gi = __builtin_fma(-l.re, b.im, __builtin_fma(-l.im, b.re, gi));
+}
 __device__ __forceinline__ cplx crcp(cplx a) {
   const double d = rcp_nr(__builtin_fma(a.re, a.re, a.im * a.im));
   return {a.re * d, -a.im * d};
@@ -53,10 +63,8 @@ __device__ inline cplx faddeeva(const double* __restrict__ wa, double L, cplx z)
   const cplx Z = cmul({L - z.im, z.re}, id);  // (L + i z)/(L - i z)
   cplx p = {wa[kWeidN - 1], 0.0};
 #pragma unroll
-  for (int n = kWeidN - 2; n >= 0; --n) {
-    const cplx q = cmul(p, Z);
-    p = {q.re + wa[n], q.im};
-  }
+  for (int n = kWeidN - 2; n >= 0; --n)
+    p = {__builtin_fma(p.re, Z.re, __builtin_fma(-p.im, Z.im, wa[n])), __builtin_fma(p.re, Z.im, p.im * Z.re)};
   const cplx t = cmul({2.0 * p.re, 2.0 * p.im}, id);
   return cmul({t.re + kInvSqrtPi, t.im}, id);
 }
@@ -224,10 +232,8 @@ __device__ inline void td4_events_body(const Td4Const& tc, const Td4Table* __res
     cplx A = {0.0, 0.0}, Ab = {0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const cplx x = cmul({tb.c[k][0], tb.c[k][1]}, B[k]);
-      const cplx y = cmul({tb.cb[k][0], tb.cb[k][1]}, B[k]);
-      A = {A.re + x.re, A.im + x.im};
-      Ab = {Ab.re + y.re, Ab.im + y.im};
+      A = cfma({tb.c[k][0], tb.c[k][1]}, B[k], A);
+      Ab = cfma({tb.cb[k][0], tb.cb[k][1]}, B[k], Ab);
     }
     const double Hc = 0.5 * (hp + hm), Hs = 0.5 * (hp - hm);
     const double a2 = A.re * A.re + A.im * A.im, b2 = Ab.re * Ab.re + Ab.im * Ab.im;
@@ -244,11 +250,8 @@ __device__ inline void td4_events_body(const Td4Const& tc, const Td4Table* __res
       const cplx lb = {w * (hmc * Ab.re - Hs * A.re + hc.im * A.im), w * (-hmc * Ab.im + Hs * A.im + hc.im * A.re)};
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const cplx ec = cmul(lc, B[k]), eb = cmul(lb, B[k]);
-        acc[1 + 2 * k] += ec.re;
-        acc[2 + 2 * k] -= ec.im;
-        acc[1 + 2 * K + 2 * k] += eb.re;
-        acc[2 + 2 * K + 2 * k] -= eb.im;
+        grad_acc(lc, B[k], acc[1 + 2 * k], acc[2 + 2 * k]);
+        grad_acc(lb, B[k], acc[1 + 2 * K + 2 * k], acc[2 + 2 * K + 2 * k]);
       }
       // x: d hc/dx = -i G dh(ac);  y: d hp/dy = -G dh(ap), d hm/dy = +G dh(am)
       const double dcos = G * dhc.im, dsin = -G * dhc.re;
@@ -436,8 +439,9 @@ __device__ inline void td4_mrows_body(const Td4Const& tc, const Td4Table* __rest
         if (k == i0 + ib) bi = B[k];
 #pragma unroll
       for (int j = 0; j < K; ++j) {
-        acc[2 * (ib * K + j)] += bi.re * B[j].re + bi.im * B[j].im;
-        acc[2 * (ib * K + j) + 1] += bi.im * B[j].re - bi.re * B[j].im;
+        acc[2 * (ib * K + j)] = __builtin_fma(bi.re, B[j].re, __builtin_fma(bi.im, B[j].im, acc[2 * (ib * K + j)]));
+        acc[2 * (ib * K + j) + 1] =
+            __builtin_fma(bi.im, B[j].re, __builtin_fma(-bi.re, B[j].im, acc[2 * (ib * K + j) + 1]));
       }
     }
   }

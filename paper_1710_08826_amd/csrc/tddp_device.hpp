@@ -90,8 +90,8 @@ __device__ inline void tddp_events_body(const DalitzConst& dc, const DalitzTable
     for (int k = 0; k < K; ++k) {
       const double cr = coef[2 * k], ci = coef[2 * k + 1];
       const double br = coef[2 * K + 2 * k], bi = coef[2 * K + 2 * k + 1];
-      A = {A.re + cr * Are[k] - ci * Aim[k], A.im + cr * Aim[k] + ci * Are[k]};
-      Ab = {Ab.re + br * Bre[k] - bi * Bim[k], Ab.im + br * Bim[k] + bi * Bre[k]};
+      A = cfma({cr, ci}, {Are[k], Aim[k]}, A);
+      Ab = cfma({br, bi}, {Bre[k], Bim[k]}, Ab);
     }
     const double Hc = 0.5 * (hp + hm), Hs = 0.5 * (hp - hm);
     const double a2 = A.re * A.re + A.im * A.im, b2 = Ab.re * Ab.re + Ab.im * Ab.im;
@@ -108,11 +108,8 @@ __device__ inline void tddp_events_body(const DalitzConst& dc, const DalitzTable
       const cplx lb = {w * (hmc * Ab.re - Hs * A.re + hc.im * A.im), w * (-hmc * Ab.im + Hs * A.im + hc.im * A.re)};
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const cplx ec = cmul(lc, {Are[k], Aim[k]}), eb = cmul(lb, {Bre[k], Bim[k]});
-        acc[1 + 2 * k] += ec.re;
-        acc[2 + 2 * k] -= ec.im;
-        acc[1 + 2 * K + 2 * k] += eb.re;
-        acc[2 + 2 * K + 2 * k] -= eb.im;
+        grad_acc(lc, {Are[k], Aim[k]}, acc[1 + 2 * k], acc[2 + 2 * k]);
+        grad_acc(lb, {Bre[k], Bim[k]}, acc[1 + 2 * K + 2 * k], acc[2 + 2 * K + 2 * k]);
       }
       // x: d hc/dx = -i G dh(ac);  y: d hp/dy = -G dh(ap), d hm/dy = +G dh(am)
       const double dcos = G * dhc.im, dsin = -G * dhc.re;
@@ -171,8 +168,8 @@ __device__ inline void tddp_mrows_body(const DalitzConst& dc, const DalitzTable*
       for (int j = 0; j < K; ++j) {
         // (xr + i xi) times conj(R_j) for WHICH 0/1, times R_j for WHICH 2
         const double rr = Rre[j], ri = WHICH == 2 ? Rim[j] : -Rim[j];
-        acc[2 * (ib * K + j)] += xr * rr - xi * ri;
-        acc[2 * (ib * K + j) + 1] += xr * ri + xi * rr;
+        acc[2 * (ib * K + j)] = __builtin_fma(xr, rr, __builtin_fma(-xi, ri, acc[2 * (ib * K + j)]));
+        acc[2 * (ib * K + j) + 1] = __builtin_fma(xr, ri, __builtin_fma(xi, rr, acc[2 * (ib * K + j) + 1]));
       }
     }
   }
