@@ -57,11 +57,10 @@ struct PairTerms {
 template <bool U1, bool U2>
 __device__ __forceinline__ void pair_terms_t(const DalitzChan& ch, double s_ab, double s_ac, double s_bc, double r2,
                                              double rD2, PairTerms& o) {
-  const double irs = rsqrt_nr(s_ab);
-  const double is = irs * irs;
+  const double is = rcp_fast(s_ab);
   const double lq = fmax((s_ab - ch.sum2) * (s_ab - ch.dif2), 0.0);
   const double q2 = 0.25 * lq * is;
-  const double qirs = 0.5 * sqrt_nr(lq) * is;
+  const double qirs = 0.5 * sqrt_fast(lq) * is;
   o.s = s_ab;
   o.G[0] = qirs;
   o.H[0] = 1.0;
@@ -71,16 +70,19 @@ __device__ __forceinline__ void pair_terms_t(const DalitzChan& ch, double s_ab, 
     const double p2 = 0.25 * lp * is;
     const double zq = q2 * r2, zp = p2 * rD2;
     const double z1 = __builtin_fma(ch.zc, is, s_ac - s_bc);
+    // 1/u_q = (1/sqrt(u_q u_p))^2 u_p: one reciprocal square root serves both
     if (U1) {
       const double uq = 1.0 + zq, up = 1.0 + zp;
-      o.G[1] = qirs * q2 * rcp_nr(uq);
-      o.H[1] = z1 * rsqrt_nr(uq * up);
+      const double r = rsqrt_fast(uq * up);
+      o.G[1] = qirs * q2 * (r * r * up);
+      o.H[1] = z1 * r;
     }
     if (U2) {
       const double vq = __builtin_fma(zq, zq + 3.0, 9.0), vp = __builtin_fma(zp, zp + 3.0, 9.0);
-      o.G[2] = qirs * q2 * q2 * rcp_nr(vq);
+      const double r = rsqrt_fast(vq * vp);
+      o.G[2] = qirs * q2 * q2 * (r * r * vp);
       const double z2 = z1 * z1 - (lp * is) * (lq * is) * (1.0 / 3.0);
-      o.H[2] = z2 * rsqrt_nr(vq * vp);
+      o.H[2] = z2 * r;
     }
   }
 }
@@ -147,7 +149,7 @@ __device__ __forceinline__ void dalitz_pair(const DalitzConst& dc, const double*
       // A_k = Ka H T with T = 1 / (a - i b) = (a + i b) d, d = 1 / (a^2 + b^2)
       const double a = rk[dM0SQ] - pt.s;
       const double b = rk[dKW] * G;
-      const double d = rcp_nr(__builtin_fma(a, a, b * b));
+      const double d = rcp_fast(__builtin_fma(a, a, b * b));
       const double u = (rk[dKA] * H) * d;
       const double ar = u * a, ai = u * b;
       if (KEEP_A) { Are[k] = ar; Aim[k] = ai; }
@@ -203,7 +205,7 @@ __device__ __forceinline__ void dalitz_point(const DalitzConst& dc, const double
   double w;  // multiplies dP~/dtheta
   if (MODE == kEvents) {
     add(0, -log_fast(Pt));
-    if (GRAD >= 1) w = -rcp_nr(Pt);
+    if (GRAD >= 1) w = -rcp_fast(Pt);
   } else {
     add(0, Pt);
     w = 1.0;

@@ -26,22 +26,22 @@
 
 namespace fn {
 
-__device__ __forceinline__ double rcp_nr(double x) {
+__device__ __forceinline__ double rcp_fast(double x) {
   const double r = __builtin_amdgcn_rcp(x);
   const double e = __builtin_fma(-x, r, 1.0);
   return __builtin_fma(r, __builtin_fma(e, e, e), r);
 }
 
-__device__ __forceinline__ double rsqrt_nr(double x) {
+__device__ __forceinline__ double rsqrt_fast(double x) {
   const double y = __builtin_amdgcn_rsq(x);
   const double e = __builtin_fma(-x * y, y, 1.0);
   return __builtin_fma(y, e * __builtin_fma(e, 0.375, 0.5), y);
 }
 
 // sqrt for x >= 0; arguments below 1e-300 are treated as 1e-300.
-__device__ __forceinline__ double sqrt_nr(double x) {
+__device__ __forceinline__ double sqrt_fast(double x) {
   const double xc = __builtin_fmax(x, 1e-300);
-  return xc * rsqrt_nr(xc);
+  return xc * rsqrt_fast(xc);
 }
 
 __device__ __forceinline__ double log_fast(double x) {
@@ -50,7 +50,7 @@ __device__ __forceinline__ double log_fast(double x) {
   const bool lo = m < 0.70710678118654752440;
   m = lo ? 2.0 * m : m;
   e = lo ? e - 1 : e;
-  const double f = (m - 1.0) * rcp_nr(m + 1.0);
+  const double f = (m - 1.0) * rcp_fast(m + 1.0);
   const double f2 = f * f;
   double p = 1.0 / 23.0;
   p = __builtin_fma(p, f2, 1.0 / 21.0);

@@ -145,7 +145,7 @@ __device__ inline double mix_shape(int type, const Mix1dTable& t, int k, double 
     }
     default: {  // kBW
       const double d = x - t.a[k];
-      const double s = rcp_nr(__builtin_fma(d, d, t.b[k]));
+      const double s = rcp_fast(__builtin_fma(d, d, t.b[k]));
       if (GRAD) { dl0 = 2.0 * d * s; dl1 = -0.5 * t.c[k] * s; }
       return s;
     }
@@ -199,7 +199,7 @@ __device__ inline void mix1d_chunk(const Mix1dConst& mc, const Mix1dTable* __res
       }
     }
     acc[0] -= log_fast(P);
-    if (GRAD) mix1d_add_dp<KMAX>(mc, t, u, dl, -rcp_nr(P), acc + 1);
+    if (GRAD) mix1d_add_dp<KMAX>(mc, t, u, dl, -rcp_fast(P), acc + 1);
   }
   block_sum_row<NV>(acc, lds, out_row);
 }
@@ -249,7 +249,7 @@ __device__ inline void mix1d_binned_chunk(const Mix1dConst& mc, const Mix1dTable
     }
     if (STAT == 0) {
       acc[1] += P;
-      const double cy = n != 0.0 ? n * rcp_nr(P) : 0.0;
+      const double cy = n != 0.0 ? n * rcp_fast(P) : 0.0;
       if (n != 0.0) acc[2] += n * log_fast(P);
       if (GRAD) {
         mix1d_add_dp<KMAX>(mc, t, u, dl, 1.0, acc + 3);

@@ -21,13 +21,13 @@ template <int NR>
 __device__ __forceinline__ void pair_amps(double m, double sum2, double dif2, double r2, const int* L, const int* nr,
                                           int n, const double (*rt)[3], cplx (&amp)[NR]) {
   const double s = m * m;
-  const double im = rcp_nr(m);
+  const double im = rcp_fast(m);
   const double lq = fmax((s - sum2) * (s - dif2), 0.0);
   const double q2 = 0.25 * lq * im * im;
-  const double q = sqrt_nr(q2);
+  const double q = sqrt_fast(q2);
   const double G0 = q * im;
   const double z = q2 * r2;
-  const double F1 = rsqrt_nr(1.0 + z);
+  const double F1 = rsqrt_fast(1.0 + z);
   const double G1 = G0 * q2 * F1 * F1;
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
@@ -38,7 +38,7 @@ __device__ __forceinline__ void pair_amps(double m, double sum2, double dif2, do
       const double F = l1 ? F1 : 1.0;
       const double a = rt[r][0] - s;
       const double b = rt[r][1] * G;
-      const double d = rcp_nr(__builtin_fma(a, a, b * b));
+      const double d = rcp_fast(__builtin_fma(a, a, b * b));
       const double k = rt[r][2] * F * d;
       amp[r] = {k * a, k * b};
     }
@@ -52,7 +52,7 @@ __device__ __forceinline__ void td4_basis(const Td4Const& tc, const Td4Table& tb
   cplx a12[kTd4MaxRes], a34[kTd4MaxRes];
   pair_amps<kTd4MaxRes>(m12, tc.sum12, tc.dif12, tc.r2, tc.L12, tc.nr12, tc.n12, tb.r12, a12);
   pair_amps<kTd4MaxRes>(m34, tc.sum34, tc.dif34, tc.r2, tc.L34, tc.nr34, tc.n34, tb.r34, a34);
-  const double ss = 0.5 * sqrt_nr(fmax(1.0 - c12 * c12, 0.0)) * sqrt_nr(fmax(1.0 - c34 * c34, 0.0));
+  const double ss = 0.5 * sqrt_fast(fmax(1.0 - c12 * c12, 0.0)) * sqrt_fast(fmax(1.0 - c34 * c34, 0.0));
   double sp, cp;
   sincos(phi, &sp, &cp);
 #pragma unroll

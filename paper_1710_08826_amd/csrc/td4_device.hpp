@@ -46,7 +46,7 @@ __device__ __forceinline__ void grad_acc(cplx l, cplx b, double& gr, double& gi)
   gi = __builtin_fma(-l.re, b.im, __builtin_fma(-l.im, b.re, gi));
 }
 __device__ __forceinline__ cplx crcp(cplx a) {
-  const double d = rcp_nr(__builtin_fma(a.re, a.re, a.im * a.im));
+  const double d = rcp_fast(__builtin_fma(a.re, a.re, a.im * a.im));
   return {a.re * d, -a.im * d};
 }
 
@@ -71,7 +71,7 @@ __device__ inline cplx faddeeva(const double* __restrict__ wa, double L, cplx z)
 
 // w(i y), y >= 0 (real on the imaginary axis): Z = (L - y)/(L + y).
 __device__ inline double faddeeva_imag(const double* __restrict__ wa, double L, double y) {
-  const double id = rcp_nr(L + y);
+  const double id = rcp_fast(L + y);
   const double Z = (L - y) * id;
   double p = wa[kWeidN - 1];
 #pragma unroll
@@ -128,13 +128,13 @@ template <int N, const int (&L)[N], const int (&NR)[N]>
 __device__ __forceinline__ void pair_amps_s(double m, double sum2, double dif2, double r2,
                                             const double (*__restrict__ rt)[3], cplx (&amp)[N]) {
   const double s = m * m;
-  const double im = rcp_nr(m);
+  const double im = rcp_fast(m);
   const double lq = fmax((s - sum2) * (s - dif2), 0.0);
   const double q2 = 0.25 * lq * im * im;
-  const double G0 = sqrt_nr(q2) * im;
+  const double G0 = sqrt_fast(q2) * im;
   double F1 = 1.0, G1 = 0.0;
   if (any_l1<N>(L, NR)) {
-    F1 = rsqrt_nr(1.0 + q2 * r2);
+    F1 = rsqrt_fast(1.0 + q2 * r2);
     G1 = G0 * q2 * F1 * F1;
   }
 #pragma unroll
@@ -144,7 +144,7 @@ __device__ __forceinline__ void pair_amps_s(double m, double sum2, double dif2, 
       const double G = L[r] == 1 ? G1 : G0;
       const double a = rt[r][0] - s;
       const double b = rt[r][1] * G;
-      const double d = rcp_nr(__builtin_fma(a, a, b * b));
+      const double d = rcp_fast(__builtin_fma(a, a, b * b));
       const double k = (L[r] == 1 ? rt[r][2] * F1 : rt[r][2]) * d;
       amp[r] = {k * a, k * b};
     }
@@ -166,7 +166,7 @@ __device__ __forceinline__ void td4_basis_s(const Td4Const& tc, const Td4Table& 
   }();
   double ss = 0.0, sp = 0.0, cp = 1.0;
   if (has_sc) {
-    ss = 0.5 * sqrt_nr(fmax(1.0 - c12 * c12, 0.0)) * sqrt_nr(fmax(1.0 - c34 * c34, 0.0));
+    ss = 0.5 * sqrt_fast(fmax(1.0 - c12 * c12, 0.0)) * sqrt_fast(fmax(1.0 - c34 * c34, 0.0));
     sincos(phi, &sp, &cp);
   }
 #pragma unroll
@@ -241,7 +241,7 @@ __device__ inline void td4_events_body(const Td4Const& tc, const Td4Table* __res
     const double R = 0.5 * ((a2 + b2) * Hc + (a2 - b2) * hc.re - 2.0 * zr * Hs - 2.0 * zi * hc.im);
     acc[0] -= log_fast(R);
     if (GRAD) {
-      const double w = -rcp_nr(R);
+      const double w = -rcp_fast(R);
       const double hpc = Hc + hc.re, hmc = Hc - hc.re;
       // dR/dRe c_k - i dR/dIm c_k = lc B_k and the same for cbar with lb, where
       // lc = hpc conj(A) - (Hs + i Hsin) conj(Abar), lb = hmc conj(Abar) - (Hs - i Hsin) conj(A)

@@ -99,7 +99,7 @@ __device__ inline void tddp_events_body(const DalitzConst& dc, const DalitzTable
     const double R = 0.5 * ((a2 + b2) * Hc + (a2 - b2) * hc.re - 2.0 * zr * Hs - 2.0 * zi * hc.im);
     acc[0] -= log_fast(R);
     if (GRAD) {
-      const double w = -rcp_nr(R);
+      const double w = -rcp_fast(R);
       const double hpc = Hc + hc.re, hmc = Hc - hc.re;
       // dR/dRe c_k - i dR/dIm c_k = lc A_k, and with lb and B_k for cbar:
       // lc = hpc conj(A) - (Hs + i Hsin) conj(Abar), lb = hmc conj(Abar) - (Hs - i Hsin) conj(A)
