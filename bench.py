@@ -35,12 +35,12 @@ PEAK_HBM_GBS = 8000.0
 # chunk, and its executed FP64 FLOPs per event from SQ_INSTS_VALU_FLOPS_FP64,
 # valid for the kernel sources with this hash; reported as null once they
 # change or for a chunk without a counter run.
-TRAFFIC_BYTES = {2048: 1.619e7, 1024: 1.627e7}
+TRAFFIC_BYTES = {2048: 1.620e7, 1024: 1.628e7}
 COUNTED_FP64_FLOPS_PER_EVENT = {2048: 493.4, 1024: 498.8}
 TRAFFIC_SOURCES = ["paper_1710_08826_amd/csrc/dalitz_device.hpp", "paper_1710_08826_amd/csrc/dalitz3.hip",
                    "paper_1710_08826_amd/csrc/fastmath.hpp", "paper_1710_08826_amd/csrc/device_common.hpp",
                    "paper_1710_08826_amd/csrc/model.hpp"]
-TRAFFIC_HASH = "8c5377aa6df07ce6"
+TRAFFIC_HASH = "3ebf4931e5d964e5"
 
 
 def counters_current() -> bool:

@@ -77,6 +77,7 @@ struct DalFinal {
   const double* coef;        // (Re c_k, Im c_k)
   double n_events;
   int with_grad;
+  int norm_ready;            // the events pass wrote I and dI into out (cached M)
   double* out;               // [NLL, grad(P), I, dI(P)]
   double* out_user;          // optional [NLL, grad(P)]
 };
@@ -101,15 +102,25 @@ __device__ void dalitz_finalize_body(const DalitzConst& dc, const DalitzTable* _
   const int P = dc.free_ls ? 4 * K : 2 * K;
   const int t = threadIdx.x;
   // the small inputs are loaded first: their latency overlaps the row sums
-  const double mv = !f.npart && t < 2 * K * K ? f.Mc[t] : 0.0;
-  const double cv = t < 2 * K ? f.coef[t] : 0.0;
+  const bool own_norm = !f.npart && !f.norm_ready;
+  const double mv = own_norm && t < 2 * K * K ? f.Mc[t] : 0.0;
+  const double cv = own_norm && t < 2 * K ? f.coef[t] : 0.0;
+  const double nv = f.norm_ready && t <= P ? f.out[1 + P + t] : 0.0;  // I, then dI
   sum_rows_t<kFinalBlock>(evpart, ev_rows, ev_nv, L.scratch, L.res);
   if (f.npart) sum_rows_t<kFinalBlock>(f.npart, f.n_rows, f.n_nv, L.scratch, L.nres);
-  if (t < 2 * K * K) L.M[t] = mv;
-  if (t < 2 * K) (t & 1 ? L.cim : L.cre)[t >> 1] = cv;
-  if (t < P) L.dI[t] = 0.0;
-  __syncthreads();
-  if (f.npart) {
+  if (f.norm_ready) {
+    // I and dI from the events pass
+    if (t == 0) L.I = nv;
+    if (t >= 1 && t <= P) L.dI[t - 1] = nv;
+    __syncthreads();
+  } else {
+    if (t < 2 * K * K) L.M[t] = mv;
+    if (t < 2 * K) (t & 1 ? L.cim : L.cre)[t >> 1] = cv;
+    if (t < P) L.dI[t] = 0.0;
+    __syncthreads();
+  }
+  if (f.norm_ready) {
+  } else if (f.npart) {
     if (t < K && f.n_nv > 1) {
       L.dI[2 * t] = dc.dA * L.nres[1 + 2 * t];
       L.dI[2 * t + 1] = dc.dA * L.nres[2 + 2 * t];
@@ -132,13 +143,15 @@ __device__ void dalitz_finalize_body(const DalitzConst& dc, const DalitzTable* _
     L.dI[2 * t] = 2.0 * xr;
     L.dI[2 * t + 1] = -2.0 * xi;
   }
-  __syncthreads();
-  if (!f.npart && t == 0) {
-    double I = 0.0;
-    for (int k = 0; k < K; ++k) I += L.ipart[k];
-    L.I = I;
+  if (!f.norm_ready) {
+    __syncthreads();
+    if (!f.npart && t == 0) {
+      double I = 0.0;
+      for (int k = 0; k < K; ++k) I += L.ipart[k];
+      L.I = I;
+    }
+    __syncthreads();
   }
-  __syncthreads();
   const double I = L.I;
   const bool okI = tab->valid != 0.0 && I > 0.0 && isfinite(I);
   if (t == 0) {
@@ -305,7 +318,7 @@ std::shared_ptr<DalitzJit> dalitz_jit(const DalitzConst& dc) {
 
 static void launch_pass(hipFunction_t f, const DalitzConst& dc, const DalitzTable* tab, const double* coef,
                         const double* ev, int64_t ld, int64_t n, int chunk, int64_t nchunks, int i0, double* part,
-                        hipStream_t s) {
+                        hipStream_t s, const double* Mc = nullptr, double* norm_out = nullptr) {
   if (!f) throw Error(FN_E_INVALID, "this model was not compiled with the requested pass");
   DalitzConst c = dc;
   const DalitzTable* t = tab;
@@ -314,13 +327,16 @@ static void launch_pass(hipFunction_t f, const DalitzConst& dc, const DalitzTabl
   int64_t l = ld, nn = n;
   int ch = chunk, ii = i0;
   double* p = part;
-  void* args[] = {&c, &t, &cf, &e, &l, &nn, &ch, &ii, &p};
+  const double* m = Mc;
+  double* no = norm_out;
+  void* args[] = {&c, &t, &cf, &e, &l, &nn, &ch, &ii, &p, &m, &no};
   jit_launch(f, (unsigned)nchunks, kBlock, s, args);
 }
 
 static DalFinal make_final(const double* npart, int64_t n_rows, int n_nv, const double* Mc, const double* coef,
-                           double n_events, bool grad, double* out, double* out_user) {
+                           double n_events, bool grad, bool norm_ready, double* out, double* out_user) {
   DalFinal f;
+  f.norm_ready = norm_ready ? 1 : 0;
   f.npart = npart;
   f.n_rows = n_rows;
   f.n_nv = n_nv;
@@ -335,16 +351,20 @@ static DalFinal make_final(const double* npart, int64_t n_rows, int n_nv, const 
 
 void dalitz_launch_events(const DalitzJit& j, const DalitzConst& dc, const DalitzTable* tab, const double* coef,
                           const double* ev, int64_t ld, int64_t n, int chunk, int64_t nchunks, int grad, double* part,
-                          hipStream_t s) {
+                          hipStream_t s, const double* Mc, double* out) {
   if (nchunks == 0) return;
-  launch_pass(j.ev[grad], dc, tab, coef, ev, ld, n, chunk, nchunks, 0, part, s);
+  const int P = dc.free_ls ? 4 * dc.K : 2 * dc.K;
+  launch_pass(j.ev[grad], dc, tab, coef, ev, ld, n, chunk, nchunks, 0, part, s, Mc,
+              Mc && out ? out + 1 + P : nullptr);
 }
 
 void dalitz_launch_finalize(const DalitzConst& dc, const DalitzTable* tab, const double* coef, const double* evpart,
                             int64_t ev_rows, int grad, const double* npart, int64_t n_rows, int n_nv,
-                            const double* Mc, double n_events, double* out, double* out_user, hipStream_t s) {
+                            const double* Mc, double n_events, double* out, double* out_user, hipStream_t s,
+                            bool norm_ready) {
   const int kmax = dalitz_kmax(dc.K);
-  const DalFinal fin = make_final(npart, n_rows, n_nv, Mc, coef, n_events, grad != 0, out, out_user);
+  const DalFinal fin = make_final(npart, n_rows, n_nv, Mc, coef, n_events, grad != 0, norm_ready && !npart, out,
+                                  out_user);
   hipLaunchKernelGGL(dalitz_finalize, dim3(1), dim3(kFinalBlock), 0, s, dc, tab, evpart, ev_rows,
                      dal_nv(kEvents, grad, kmax), kmax, fin);
 }

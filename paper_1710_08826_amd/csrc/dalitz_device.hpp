@@ -297,17 +297,55 @@ __device__ inline void dalitz_chunk(const DalitzConst& dc, const DalitzTable* __
   block_sum_row<NV>(acc, lds, out_row);
 }
 
+// Normalization of a model with fixed lineshapes from the cached grid matrix
+// M (K x K complex, M_kj = dA sum over cells of A_k conj(A_j)): I = c^H M c =
+// sum_k Re(c_k X_k) with X_k = sum_j M_kj conj(c_j), dI/dRe c_k = 2 Re X_k,
+// dI/dIm c_k = -2 Im X_k.  Writes out[0] = I and out[1 + 2k], out[2 + 2k];
+// all threads of the workgroup call it.
+template <class S>
+__device__ inline void dalitz_cached_norm(const double* __restrict__ M, const double* __restrict__ coef,
+                                          double* __restrict__ out) {
+  constexpr int K = S::K;
+  __shared__ double ip[K];
+  const int t = threadIdx.x;
+  if (t < K) {
+    double xr = 0.0, xi = 0.0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      const double mr = M[2 * (t * K + j)], mi = M[2 * (t * K + j) + 1];
+      const double cr = coef[2 * j], ci = coef[2 * j + 1];
+      xr = __builtin_fma(mr, cr, __builtin_fma(mi, ci, xr));
+      xi = __builtin_fma(mi, cr, __builtin_fma(-mr, ci, xi));
+    }
+    ip[t] = __builtin_fma(coef[2 * t], xr, -(coef[2 * t + 1] * xi));
+    out[1 + 2 * t] = 2.0 * xr;
+    out[2 + 2 * t] = -2.0 * xi;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double I = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) I += ip[k];
+    out[0] = I;
+  }
+}
+
 // One workgroup per chunk, one row of NV partial sums each.
 // coef: (Re c_k, Im c_k) of the resonances (theta's first 2K entries, or the
-// table's copy of them); unused by kMRows.
+// table's copy of them); unused by kMRows.  Events pass with a cached grid
+// matrix (M not null): the last workgroup, whose chunk is the shortest,
+// also evaluates the normalization into norm_out (dalitz_cached_norm), so
+// that the level-2 step only sums rows.
 template <class S, int MODE, int GRAD, int EPT = 1>
 __device__ inline void dalitz_pass_body(const DalitzConst& dc, const DalitzTable* __restrict__ tab,
                                         const double* __restrict__ coef, const double* __restrict__ ev, int64_t ld,
-                                        int64_t n, int chunk, int i0, double* __restrict__ part) {
+                                        int64_t n, int chunk, int i0, double* __restrict__ part,
+                                        const double* __restrict__ M, double* __restrict__ norm_out) {
   constexpr int NV = dal_nv(MODE, GRAD, S::K);
   __shared__ double lds[block_sum_lds(NV)];
   dalitz_chunk<S, MODE, GRAD, EPT>(dc, tab, coef, ev, ld, n, blockIdx.x, chunk, i0,
                                    part + (int64_t)blockIdx.x * NV, lds);
+  if (MODE == kEvents && M && blockIdx.x == gridDim.x - 1) dalitz_cached_norm<S>(M, coef, norm_out);
 }
 
 // ---------------------------------------------------------------- toy events
@@ -397,8 +435,9 @@ __device__ inline void dalitz_gen_body(const DalitzConst& dc, const DalitzTable*
 #define FN_DALITZ_KERNEL(NAME, S, MODE, GRAD, EPT)                                                           \
   extern "C" __global__ __launch_bounds__(fn::kBlock) void NAME(                                               \
       fn::DalitzConst dc, const fn::DalitzTable* __restrict__ tab, const double* __restrict__ coef,           \
-      const double* __restrict__ ev, int64_t ld, int64_t n, int chunk, int i0, double* __restrict__ part) {   \
-    fn::dalitz_pass_body<S, MODE, GRAD, EPT>(dc, tab, coef, ev, ld, n, chunk, i0, part);                       \
+      const double* __restrict__ ev, int64_t ld, int64_t n, int chunk, int i0, double* __restrict__ part,     \
+      const double* __restrict__ M, double* __restrict__ norm_out) {                                           \
+    fn::dalitz_pass_body<S, MODE, GRAD, EPT>(dc, tab, coef, ev, ld, n, chunk, i0, part, M, norm_out);          \
   }
 
 // Grid maximum and accept-reject generator for shape S.

@@ -487,13 +487,16 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
       t1 = m->take_event();
       hip_check(hipEventRecord(t0, s), "hipEventRecord");
     }
-    dalitz_launch_events(*m->dal_jit, dc, m->table_dal(), coef, ev, ld, n, m->chunk, nch, g, m->part(), s);
+    // cached M: the events pass evaluates I = c^H M c in its last workgroup
+    const bool norm_in_pass = !dc.free_ls && nch > 0;
+    dalitz_launch_events(*m->dal_jit, dc, m->table_dal(), coef, ev, ld, n, m->chunk, nch, g, m->part(), s,
+                         norm_in_pass ? m->Mc() : nullptr, norm_in_pass ? m->out() : nullptr);
     if (t0) {
       hip_check(hipEventRecord(t1, s), "hipEventRecord");
       m->ev_pending.emplace_back(t0, t1);
     }
     dalitz_launch_finalize(dc, m->table_dal(), coef, m->part(), nch, g, npart, nrows, nnv, m->Mc(), (double)n,
-                           m->out(), out_user, s);
+                           m->out(), out_user, s, norm_in_pass);
   }
   hip_check(hipGetLastError(), "kernel launch");
 }
