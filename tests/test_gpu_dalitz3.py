@@ -102,6 +102,20 @@ def test_full_size_config1(m1, cells1):
     assert ok, r
 
 
+def test_full_size_config3(m3, cells1):
+    """4M events with masses and widths free (32 parameters, the full grid
+    every call), at the model's default chunk as the benchmark runs it."""
+    ev = synth.dalitz_events(4_000_000, seed=37)
+    th = offset(TH3)
+    say("dalitz config3 full size: device")
+    v, g = m3.nll(th, to_dev(ev), grad=True)
+    say("dalitz config3 full size: oracle")
+    vo, go = OD.nll_grad(th, ev, D3, cells1)
+    assert rel_close(v, vo, 1e-12), (v, vo)
+    ok, r = grad_close(g, go, 1e-9)
+    assert ok, r
+
+
 def test_eval_matches_oracle_density(m1, cells1):
     ev = synth.dalitz_events(2000, seed=35)
     p = m1.eval(TH1, to_dev(ev)).cpu().numpy()
