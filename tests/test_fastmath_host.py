@@ -1,0 +1,129 @@
+"""Host emulation of the per-event FP64 sequences of the device library
+(reciprocal and reciprocal square root from a hardware seed plus one
+third-order correction, and the logarithm by argument reduction and the atanh
+series), with every fused multiply-add evaluated exactly and rounded once
+(rational arithmetic), and with seeds perturbed to twice the worst relative
+error measured for the gfx950 approximations (2^-24.2): the results stay
+within about one unit in the last place of the exact values."""
+import math
+import random
+from decimal import Decimal, getcontext
+from fractions import Fraction
+
+getcontext().prec = 60
+
+SEED_ERR = 2.0 ** -23
+
+
+def fma(a, b, c):
+    return float(Fraction(a) * Fraction(b) + Fraction(c))
+
+
+def seeded(exact, rng):
+    """A seed with relative error uniform in [-SEED_ERR, SEED_ERR] (its ends included now and then)."""
+    d = rng.choice([-SEED_ERR, SEED_ERR, rng.uniform(-SEED_ERR, SEED_ERR)])
+    return float(exact * (1 + Fraction(d)))
+
+
+def rcp_fast(x, rng):
+    r = seeded(1 / Fraction(x), rng)
+    e = fma(-x, r, 1.0)
+    return fma(r, fma(e, e, e), r)
+
+
+def rsqrt_fast(x, rng):
+    exact = Fraction(1 / Decimal(x).sqrt())
+    y = seeded(exact, rng)
+    e = fma(-x * y, y, 1.0)
+    return fma(y, e * fma(e, 0.375, 0.5), y)
+
+
+def ulps(v, exact):
+    """|v - exact| in units in the last place of exact."""
+    ex = float(exact)
+    return float(abs(Fraction(v) - Fraction(exact))) / math.ulp(ex)
+
+
+def samples(rng, n):
+    for _ in range(n):
+        yield math.ldexp(1.0 + rng.random(), rng.randint(-60, 60))
+
+
+def test_reciprocal_within_one_ulp():
+    rng = random.Random(11)
+    worst = max(ulps(rcp_fast(x, rng), 1 / Fraction(x)) for x in samples(rng, 3000))
+    assert worst <= 1.0, worst
+
+
+def test_reciprocal_square_root_within_one_ulp():
+    rng = random.Random(12)
+    worst = 0.0
+    for x in samples(rng, 2000):
+        exact = 1 / Decimal(x).sqrt()
+        worst = max(worst, ulps(rsqrt_fast(x, rng), Fraction(exact)))
+    assert worst <= 1.0, worst
+
+
+def test_one_newton_step_would_not_do():
+    """The same seeds after one Newton step (r + r e): errors of tens of ulps,
+    which is why the third-order term is kept."""
+    rng = random.Random(13)
+    worst = 0.0
+    for x in samples(rng, 500):
+        r = seeded(1 / Fraction(x), rng)
+        worst = max(worst, ulps(fma(r, fma(-x, r, 1.0), r), 1 / Fraction(x)))
+    assert worst > 4.0, worst
+
+
+LN2_HI = float.fromhex("0x1.62e42ff000000p-1")
+LN2_LO = float.fromhex("-0x1.718432a1b0e26p-35")
+
+
+def log_fast(x, rng):
+    m, e = math.frexp(x)  # m in [0.5, 1)
+    if m < 0.70710678118654752440:
+        m, e = 2.0 * m, e - 1
+    f = (m - 1.0) * rcp_fast(m + 1.0, rng)
+    f2 = f * f
+    p = 1.0 / 23.0
+    for c in (21, 19, 17, 15, 13, 11, 9, 7, 5, 3):
+        p = fma(p, f2, 1.0 / c)
+    f2x = 2.0 * f
+    lm = fma(f2x * f2, p, f2x)
+    de = float(e)
+    return fma(de, LN2_HI, fma(de, LN2_LO, lm))
+
+
+def test_log_split_constant():
+    """ln 2 = head + tail to far below double precision, with a 32-bit head
+    (so e * head is exact for |e| < 2^21)."""
+    ln2 = Decimal(2).ln()
+    assert abs(Decimal(LN2_HI) + Decimal(LN2_LO) - ln2) < Decimal(2) ** -85
+    assert Fraction(LN2_HI).denominator.bit_length() - 1 <= 32
+
+
+def test_log_series_truncation():
+    """Eleven terms of 2 atanh(f) for |f| <= (sqrt 2 - 1)/(sqrt 2 + 1): the
+    first omitted term, 2 f^23 / 23, is below 3e-17 of ln m."""
+    fmax = (Decimal(2).sqrt() - 1) / (Decimal(2).sqrt() + 1)
+    first_omitted = 2 * fmax ** 23 / 23
+    lnm = Decimal(2).sqrt().ln()  # |ln m| at the end of the range
+    assert first_omitted / lnm < Decimal("3e-17")
+
+
+def test_log_accuracy():
+    rng = random.Random(14)
+    xs = list(samples(rng, 1500)) + [1.0, 2.0, 0.5, 0.7071067811865476, 0.7071067811865475,
+                                     1.4142135623730951, 1e-300, 1e300, 1.0 + 2 ** -52, 1.0 - 2 ** -53]
+    worst = 0.0
+    for x in xs:
+        exact = Decimal(x).ln()
+        v = log_fast(x, rng)
+        if exact == 0:
+            assert v == 0.0
+            continue
+        # absolute error near x = 1 (where ln x -> 0) is measured against the ulp of 1e-16
+        err = abs(Decimal(v) - exact)
+        scale = max(abs(exact), Decimal("1e-16"))
+        worst = max(worst, float(err / scale))
+    assert worst < 2.5e-16, worst
