@@ -124,6 +124,19 @@ __host__ __device__ constexpr bool shape_uses(int c, int l) {
   return u;
 }
 
+// One resonance's amplitude from its pair's terms: A_k = Ka H T with
+// T = 1 / (a - i b) = (a + i b) d, a = m0^2 - s, b = Kw G, d = 1 / (a^2 + b^2)
+// (rk: the resonance's row of the table).
+__device__ __forceinline__ void dalitz_bw(const double* __restrict__ rk, double s, double G, double H, double& ar,
+                                          double& ai, double& a, double& b, double& d) {
+  a = rk[dM0SQ] - s;
+  b = rk[dKW] * G;
+  d = rcp_fast(__builtin_fma(a, a, b * b));
+  const double u = (rk[dKA] * H) * d;
+  ar = u * a;
+  ai = u * b;
+}
+
 // Amplitudes of the resonances of pair C (compile-time), added to the coherent sum.
 template <class S, int C, int MODE, bool KEEP_A, bool KEEP_T>
 __device__ __forceinline__ void dalitz_pair(const DalitzConst& dc, const double* __restrict__ r,
@@ -146,12 +159,8 @@ __device__ __forceinline__ void dalitz_pair(const DalitzConst& dc, const double*
       const double* rk = r + k * kDalFields;
       const double G = pt.G[L];
       const double H = pt.H[L];
-      // A_k = Ka H T with T = 1 / (a - i b) = (a + i b) d, d = 1 / (a^2 + b^2)
-      const double a = rk[dM0SQ] - pt.s;
-      const double b = rk[dKW] * G;
-      const double d = rcp_fast(__builtin_fma(a, a, b * b));
-      const double u = (rk[dKA] * H) * d;
-      const double ar = u * a, ai = u * b;
+      double ar, ai, a, b, d;
+      dalitz_bw(rk, pt.s, G, H, ar, ai, a, b, d);
       if (KEEP_A) { Are[k] = ar; Aim[k] = ai; }
       if (KEEP_T) { Tre[k] = a * d; Tim[k] = b * d; Gk[k] = G; }
       if (MODE != kMRows) {

@@ -29,18 +29,39 @@ struct TddpTime {
   double wa[kWeidN];
 };
 
-// Amplitudes A_k(s12, s13) (or, SWAP, A_k(s13, s12)) of every resonance.
-template <class S, bool SWAP>
-__device__ __forceinline__ void tddp_basis(const DalitzConst& dc, const double* __restrict__ r, double s12,
-                                           double s13, double (&re)[S::K], double (&im)[S::K]) {
+// Both amplitude sets at one point: A_k(s12, s13) and B_k = A_k(s13, s12).
+// With m2 = m3 (the model requires it) the pair terms at the mirrored point
+// are those at (s12, s13) with pairs "12" and "13" exchanged, and for pair
+// "23" only the spin-1 angular factor changes, by its sign (Z_1 = s_ac - s_bc
+// with s_ac and s_bc exchanged; its mass term vanishes for equal masses), so
+// each pair's terms are formed once per point.
+template <class S>
+__device__ __forceinline__ void tddp_basis2(const DalitzConst& dc, const double* __restrict__ r, double s12,
+                                            double s13, double (&are)[S::K], double (&aim)[S::K],
+                                            double (&bre)[S::K], double (&bim)[S::K]) {
   constexpr int K = S::K;
-  const double u = SWAP ? s13 : s12, v = SWAP ? s12 : s13;
+  constexpr bool u1_01 = shape_uses<S>(0, 1) || shape_uses<S>(1, 1);
+  constexpr bool u2_01 = shape_uses<S>(0, 2) || shape_uses<S>(1, 2);
+  constexpr bool any01 = u1_01 || u2_01 || shape_uses<S>(0, 0) || shape_uses<S>(1, 0);
+  constexpr bool any2 = shape_uses<S>(2, 0) || shape_uses<S>(2, 1) || shape_uses<S>(2, 2);
   const double s23 = dc.msum - s12 - s13;
-  double Tre[K], Tim[K], Gk[K];
-  double Sre = 0.0, Sim = 0.0;
-  dalitz_pair<S, 0, kMRows, true, false>(dc, r, nullptr, u, v, s23, re, im, Tre, Tim, Gk, Sre, Sim);
-  dalitz_pair<S, 1, kMRows, true, false>(dc, r, nullptr, u, v, s23, re, im, Tre, Tim, Gk, Sre, Sim);
-  dalitz_pair<S, 2, kMRows, true, false>(dc, r, nullptr, u, v, s23, re, im, Tre, Tim, Gk, Sre, Sim);
+  PairTerms p0, p1, p2;
+  if (any01) {
+    pair_terms_t<u1_01, u2_01>(dc.ch[0], s12, s13, s23, dc.r2, dc.rD2, p0);
+    pair_terms_t<u1_01, u2_01>(dc.ch[1], s13, s12, s23, dc.r2, dc.rD2, p1);
+  }
+  if (any2) pair_terms_t<shape_uses<S>(2, 1), shape_uses<S>(2, 2)>(dc.ch[2], s23, s12, s13, dc.r2, dc.rD2, p2);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int C = S::chan[k], L = S::L[k];
+    const PairTerms& pa = C == 0 ? p0 : (C == 1 ? p1 : p2);
+    const PairTerms& pb = C == 0 ? p1 : (C == 1 ? p0 : p2);
+    const double hb = (C == 2 && L == 1) ? -pb.H[L] : pb.H[L];
+    const double* rk = r + k * kDalFields;
+    double a, b, d;
+    dalitz_bw(rk, pa.s, pa.G[L], pa.H[L], are[k], aim[k], a, b, d);
+    dalitz_bw(rk, pb.s, pb.G[L], hb, bre[k], bim[k], a, b, d);
+  }
 }
 
 // Events pass: one workgroup per chunk of events (s12, s13, t rows at
@@ -83,8 +104,7 @@ __device__ inline void tddp_events_body(const DalitzConst& dc, const DalitzTable
     h_cplx(wa, tt.wL, ac, t, s, s2, g, hc, dhc);
     const double s12 = ev[i], s13 = ev[ld + i];
     double Are[K], Aim[K], Bre[K], Bim[K];
-    tddp_basis<S, false>(dc, r, s12, s13, Are, Aim);
-    tddp_basis<S, true>(dc, r, s12, s13, Bre, Bim);
+    tddp_basis2<S>(dc, r, s12, s13, Are, Aim, Bre, Bim);
     cplx A = {0.0, 0.0}, Ab = {0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -144,16 +164,14 @@ __device__ inline void tddp_mrows_body(const DalitzConst& dc, const DalitzTable*
     const double s12 = dc.a12 + (ix + 0.5) * dc.d12;
     const double s13 = dc.a13 + (iy + 0.5) * dc.d13;
     if (!dalitz_inside(dc, s12, s13)) continue;
-    double Lre[K], Lim[K], Rre[K], Rim[K];
-    tddp_basis<S, WHICH == 1>(dc, r, s12, s13, Lre, Lim);
-    if (WHICH == 2) {
-      tddp_basis<S, true>(dc, r, s12, s13, Rre, Rim);
-    } else {
+    double Are[K], Aim[K], Bre[K], Bim[K], Lre[K], Lim[K], Rre[K], Rim[K];
+    tddp_basis2<S>(dc, r, s12, s13, Are, Aim, Bre, Bim);
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        Rre[k] = Lre[k];
-        Rim[k] = Lim[k];
-      }
+    for (int k = 0; k < K; ++k) {
+      Lre[k] = WHICH == 1 ? Bre[k] : Are[k];
+      Lim[k] = WHICH == 1 ? Bim[k] : Aim[k];
+      Rre[k] = WHICH == 0 ? Are[k] : Bre[k];
+      Rim[k] = WHICH == 0 ? Aim[k] : Bim[k];
     }
 #pragma unroll
     for (int ib = 0; ib < kMRowBlock; ++ib) {
@@ -184,8 +202,7 @@ __device__ __forceinline__ void tddp_amps(const DalitzConst& dc, const double* _
                                           cplx& Ab) {
   constexpr int K = S::K;
   double Are[K], Aim[K], Bre[K], Bim[K];
-  tddp_basis<S, false>(dc, r, s12, s13, Are, Aim);
-  tddp_basis<S, true>(dc, r, s12, s13, Bre, Bim);
+  tddp_basis2<S>(dc, r, s12, s13, Are, Aim, Bre, Bim);
   A = {0.0, 0.0};
   Ab = {0.0, 0.0};
 #pragma unroll
