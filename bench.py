@@ -385,9 +385,12 @@ def td4_leg(steps: int = 10):
     tb = torch.from_numpy(th * (1.0 + 1e-3 * np.cos(np.arange(P)))).cuda()
     out = torch.empty(1 + P, dtype=torch.float64, device="cuda")
     fl_g, fl_0 = td4_flops_per_event(desc, True), td4_flops_per_event(desc, False)
+    _, tune_us = m.autotune(th, ev, reps=5)
     w, k = time_async(m, tdev, ev, out, steps, 2, True, alt=tb)
     w0, k0 = time_async(m, tdev, ev, out, steps, 2, False, alt=tb)
-    r = {"events": n, "mc_points": n_mc, "params": P, "cpu_generation_s": gen_s, "device_mc_sample_s": mc_gen_s,
+    r = {"events": n, "mc_points": n_mc, "params": P, "chunk": m.chunk,
+         "autotune_us": {str(c): v for c, v in tune_us.items()},
+         "cpu_generation_s": gen_s, "device_mc_sample_s": mc_gen_s,
          "single_events_per_s": n * steps / w, "single_ms_per_step": 1e3 * w / steps,
          "single_event_kernel_ms": k, "single_event_kernel_tflops": fl_g * n / (k * 1e-3) / 1e12,
          "nll_only_event_kernel_ms": k0, "nll_only_event_kernel_tflops": fl_0 * n / (k0 * 1e-3) / 1e12,
