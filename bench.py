@@ -40,7 +40,7 @@ COUNTED_FP64_FLOPS_PER_EVENT = {2048: 493.4, 1024: 498.8}
 TRAFFIC_SOURCES = ["paper_1710_08826_amd/csrc/dalitz_device.hpp", "paper_1710_08826_amd/csrc/dalitz3.hip",
                    "paper_1710_08826_amd/csrc/fastmath.hpp", "paper_1710_08826_amd/csrc/device_common.hpp",
                    "paper_1710_08826_amd/csrc/model.hpp"]
-TRAFFIC_HASH = "976e81ad0d0aa34e"
+TRAFFIC_HASH = "80ac09a6f9e24f2d"
 
 
 def counters_current() -> bool:

@@ -105,45 +105,42 @@ __device__ void dalitz_finalize_body(const DalitzConst& dc, const DalitzTable* _
   const bool own_norm = !f.npart && !f.norm_ready;
   const double mv = own_norm && t < 2 * K * K ? f.Mc[t] : 0.0;
   const double cv = own_norm && t < 2 * K ? f.coef[t] : 0.0;
-  const double nv = f.norm_ready && t <= P ? f.out[1 + P + t] : 0.0;  // I, then dI
+  const double nrm = f.norm_ready && t <= P ? f.out[1 + P + t] : 0.0;  // I, then dI
   sum_rows_t<kFinalBlock>(evpart, ev_rows, ev_nv, L.scratch, L.res);
   if (f.npart) sum_rows_t<kFinalBlock>(f.npart, f.n_rows, f.n_nv, L.scratch, L.nres);
   if (f.norm_ready) {
     // I and dI from the events pass
-    if (t == 0) L.I = nv;
-    if (t >= 1 && t <= P) L.dI[t - 1] = nv;
+    if (t == 0) L.I = nrm;
+    if (t >= 1 && t <= P) L.dI[t - 1] = nrm;
     __syncthreads();
   } else {
     if (t < 2 * K * K) L.M[t] = mv;
     if (t < 2 * K) (t & 1 ? L.cim : L.cre)[t >> 1] = cv;
     if (t < P) L.dI[t] = 0.0;
     __syncthreads();
-  }
-  if (f.norm_ready) {
-  } else if (f.npart) {
-    if (t < K && f.n_nv > 1) {
-      L.dI[2 * t] = dc.dA * L.nres[1 + 2 * t];
-      L.dI[2 * t + 1] = dc.dA * L.nres[2 + 2 * t];
-      if (dc.free_ls && f.n_nv > 1 + 2 * kmax) {
-        L.dI[2 * K + 2 * t] = dc.dA * L.nres[1 + 2 * kmax + 2 * t];
-        L.dI[2 * K + 2 * t + 1] = dc.dA * L.nres[2 + 2 * kmax + 2 * t];
+    if (f.npart) {
+      if (t < K && f.n_nv > 1) {
+        L.dI[2 * t] = dc.dA * L.nres[1 + 2 * t];
+        L.dI[2 * t + 1] = dc.dA * L.nres[2 + 2 * t];
+        if (dc.free_ls && f.n_nv > 1 + 2 * kmax) {
+          L.dI[2 * K + 2 * t] = dc.dA * L.nres[1 + 2 * kmax + 2 * t];
+          L.dI[2 * K + 2 * t + 1] = dc.dA * L.nres[2 + 2 * kmax + 2 * t];
+        }
       }
+      if (t == 0) L.I = dc.dA * L.nres[0];
+    } else if (t < K) {
+      // I = sum_k Re(c_k X_k), X_k = sum_j M_kj conj(c_j);
+      // dI/dRe c_k = 2 Re X_k, dI/dIm c_k = -2 Im X_k
+      double xr = 0.0, xi = 0.0;
+      for (int j = 0; j < K; ++j) {
+        const double mr = L.M[2 * (t * K + j)], mi = L.M[2 * (t * K + j) + 1];
+        xr += mr * L.cre[j] + mi * L.cim[j];
+        xi += mi * L.cre[j] - mr * L.cim[j];
+      }
+      L.ipart[t] = L.cre[t] * xr - L.cim[t] * xi;
+      L.dI[2 * t] = 2.0 * xr;
+      L.dI[2 * t + 1] = -2.0 * xi;
     }
-    if (t == 0) L.I = dc.dA * L.nres[0];
-  } else if (t < K) {
-    // I = sum_k Re(c_k X_k), X_k = sum_j M_kj conj(c_j);
-    // dI/dRe c_k = 2 Re X_k, dI/dIm c_k = -2 Im X_k
-    double xr = 0.0, xi = 0.0;
-    for (int j = 0; j < K; ++j) {
-      const double mr = L.M[2 * (t * K + j)], mi = L.M[2 * (t * K + j) + 1];
-      xr += mr * L.cre[j] + mi * L.cim[j];
-      xi += mi * L.cre[j] - mr * L.cim[j];
-    }
-    L.ipart[t] = L.cre[t] * xr - L.cim[t] * xi;
-    L.dI[2 * t] = 2.0 * xr;
-    L.dI[2 * t + 1] = -2.0 * xi;
-  }
-  if (!f.norm_ready) {
     __syncthreads();
     if (!f.npart && t == 0) {
       double I = 0.0;
