@@ -464,7 +464,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
-              "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+              "(sharding events or fits across GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
     if args.pmc_probe:
         pmc_probe(args.steps, args.chunk)
