@@ -220,10 +220,11 @@ fn_status fn_model_fixed(const fn_model* m, int32_t* n_fixed, double* fixed_host
 
 /* Kernel timing (measurement support, not on the result path).  With
  * every = k >= 1, the 1st, (k+1)-th, (2k+1)-th ... per-event evaluation launch
- * of the model from this call on is bracketed by HIP events recorded on the
- * launch stream (k = 1: every launch; the events themselves add a few
- * microseconds of device time to the launches they bracket, so a large k keeps
- * a timed loop close to an untimed one); every = 0 turns timing off.
+ * of the model from this call on is timed: the dispatch itself records the
+ * kernel's start and end times into a pair of HIP events
+ * (hipExtModuleLaunchKernel / hipExtLaunchKernel; k = 1: every launch, a
+ * large k keeps the timing work out of most of a timed loop); every = 0 turns
+ * timing off.
  * FN_E_INVALID if every < 0.  fn_model_kernel_time waits for the recorded
  * events, returns the summed duration in milliseconds and the number of timed
  * launches since the last query, and resets both. */

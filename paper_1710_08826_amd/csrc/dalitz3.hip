@@ -315,7 +315,8 @@ std::shared_ptr<DalitzJit> dalitz_jit(const DalitzConst& dc) {
 
 static void launch_pass(hipFunction_t f, const DalitzConst& dc, const DalitzTable* tab, const double* coef,
                         const double* ev, int64_t ld, int64_t n, int chunk, int64_t nchunks, int i0, double* part,
-                        hipStream_t s, const double* Mc = nullptr, double* norm_out = nullptr) {
+                        hipStream_t s, const double* Mc = nullptr, double* norm_out = nullptr,
+                        hipEvent_t start = nullptr, hipEvent_t stop = nullptr) {
   if (!f) throw Error(FN_E_INVALID, "this model was not compiled with the requested pass");
   DalitzConst c = dc;
   const DalitzTable* t = tab;
@@ -327,7 +328,7 @@ static void launch_pass(hipFunction_t f, const DalitzConst& dc, const DalitzTabl
   const double* m = Mc;
   double* no = norm_out;
   void* args[] = {&c, &t, &cf, &e, &l, &nn, &ch, &ii, &p, &m, &no};
-  jit_launch(f, (unsigned)nchunks, kBlock, s, args);
+  jit_launch(f, (unsigned)nchunks, kBlock, s, args, start, stop);
 }
 
 static DalFinal make_final(const double* npart, int64_t n_rows, int n_nv, const double* Mc, const double* coef,
@@ -348,11 +349,11 @@ static DalFinal make_final(const double* npart, int64_t n_rows, int n_nv, const 
 
 void dalitz_launch_events(const DalitzJit& j, const DalitzConst& dc, const DalitzTable* tab, const double* coef,
                           const double* ev, int64_t ld, int64_t n, int chunk, int64_t nchunks, int grad, double* part,
-                          hipStream_t s, const double* Mc, double* out) {
+                          hipStream_t s, const double* Mc, double* out, hipEvent_t start, hipEvent_t stop) {
   if (nchunks == 0) return;
   const int P = dc.free_ls ? 4 * dc.K : 2 * dc.K;
   launch_pass(j.ev[grad], dc, tab, coef, ev, ld, n, chunk, nchunks, 0, part, s, Mc,
-              Mc && out ? out + 1 + P : nullptr);
+              Mc && out ? out + 1 + P : nullptr, start, stop);
 }
 
 void dalitz_launch_finalize(const DalitzConst& dc, const DalitzTable* tab, const double* coef, const double* evpart,

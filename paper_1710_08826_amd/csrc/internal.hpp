@@ -70,13 +70,27 @@ struct fn_model {
   fn::DevBuf d_theta;                    // tddp3: theta on the device for host-theta calls
   double* h_out = nullptr;       // pinned
   long long stats_calls = 0;
-  int timing = 0;                // bracket every timing-th event-pass launch with HIP events (0 = off)
+  int timing = 0;                // time every timing-th event-pass launch with HIP events (0 = off)
   int64_t timing_count = 0;
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
   hipEvent_t take_event();
   // Whether this event-pass launch is one of the timed ones.
   bool timed_launch() { return timing > 0 && timing_count++ % timing == 0; }
+  // Start/stop events for an event-pass launch when it is one of the timed
+  // ones (both null otherwise): the dispatch records the kernel's own start
+  // and end times into them; pend() queues them for fn_model_kernel_time once
+  // the launch has been issued.
+  void timing_events(bool launch, hipEvent_t& t0, hipEvent_t& t1) {
+    t0 = t1 = nullptr;
+    if (launch && timed_launch()) {
+      t0 = take_event();
+      t1 = take_event();
+    }
+  }
+  void pend(hipEvent_t t0, hipEvent_t t1) {
+    if (t0) ev_pending.emplace_back(t0, t1);
+  }
 
   fn::Mix1dTable* table_mix() { return (fn::Mix1dTable*)d_table.ptr; }
   fn::DalitzTable* table_dal() { return (fn::DalitzTable*)d_table.ptr; }

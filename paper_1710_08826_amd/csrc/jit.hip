@@ -1,6 +1,7 @@
 // hipRTC compilation and the per-process program cache.
 #include "jit.hpp"
 
+#include <hip/hip_ext.h>
 #include <hip/hiprtc.h>
 
 #include <map>
@@ -77,7 +78,15 @@ std::shared_ptr<JitProgram> jit_load(const std::string& source, const std::vecto
   return prog;
 }
 
-void jit_launch(hipFunction_t f, unsigned grid, unsigned block, hipStream_t s, void** args) {
+void jit_launch(hipFunction_t f, unsigned grid, unsigned block, hipStream_t s, void** args, hipEvent_t start,
+                hipEvent_t stop) {
+  if (start || stop) {
+    const uint64_t items = (uint64_t)grid * block;
+    if (items > 0xffffffffull) throw Error(FN_E_INVALID, "launch too large for a timed dispatch");
+    hip_check(hipExtModuleLaunchKernel(f, (uint32_t)items, 1, 1, block, 1, 1, 0, s, args, nullptr, start, stop, 0),
+              "hipExtModuleLaunchKernel");
+    return;
+  }
   hip_check(hipModuleLaunchKernel(f, grid, 1, 1, block, 1, 1, 0, s, args, nullptr), "hipModuleLaunchKernel");
 }
 

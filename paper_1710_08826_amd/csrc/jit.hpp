@@ -28,6 +28,9 @@ std::vector<char> jit_compile(const std::string& source, const std::string& arch
 std::shared_ptr<JitProgram> jit_load(const std::string& source, const std::vector<std::string>& names);
 
 // Launch of a loaded kernel; args are pointers to the argument values.
-void jit_launch(hipFunction_t f, unsigned grid, unsigned block, hipStream_t s, void** args);
+// Launches f on grid x block; with start/stop events the dispatch itself
+// records the kernel's start and end times into them (hipExtModuleLaunchKernel).
+void jit_launch(hipFunction_t f, unsigned grid, unsigned block, hipStream_t s, void** args,
+                hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 
 }  // namespace fn

@@ -13,8 +13,10 @@ int mix1d_nv(int kmax, bool grad);
 void mix1d_launch_prologue(const Mix1dConst& mc, const ParamBlock& pb, const double* theta_dev, int n_fits,
                            int theta_stride, Mix1dTable* tab, hipStream_t s);
 // Events pass (one row of partial sums per chunk) and the level-2 step.
+// start/stop (optional): events the dispatch records its start and end times into.
 void mix1d_launch_events(const Mix1dConst& mc, const Mix1dTable* tab, const double* x, int64_t n, int chunk,
-                         int64_t nchunks, bool grad, double* part, hipStream_t s);
+                         int64_t nchunks, bool grad, double* part, hipStream_t s, hipEvent_t start = nullptr,
+                         hipEvent_t stop = nullptr);
 void mix1d_launch_finalize(const Mix1dConst& mc, const Mix1dTable* tab, const double* part, int64_t nrows,
                            bool grad, double n_events, double* out, double* out_user, hipStream_t s);
 // Binned data (counts of nb uniform bins on [lo, hi]): bins pass (one row per
@@ -51,7 +53,8 @@ void dalitz_launch_prologue(const DalitzConst& dc, const ParamBlock& pb, const d
 // out = [NLL, grad, I, dI], the pass also writes I and dI into out.
 void dalitz_launch_events(const DalitzJit& j, const DalitzConst& dc, const DalitzTable* tab, const double* coef,
                           const double* ev, int64_t ld, int64_t n, int chunk, int64_t nchunks, int grad, double* part,
-                          hipStream_t s, const double* Mc = nullptr, double* out = nullptr);
+                          hipStream_t s, const double* Mc = nullptr, double* out = nullptr,
+                          hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 // Level-2 sum of the event rows and of the normalization (grid rows, or the
 // cached M when npart is null), NLL assembly: out = [NLL, grad, I, dI].
 // norm_ready: the events pass already wrote I and dI into out (cached M).

@@ -373,16 +373,9 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
     ParamBlock zero;
     mix1d_launch_prologue(mc, pb ? *pb : zero, pb ? nullptr : theta_dev, 1, 0, m->table_mix(), s);
     hipEvent_t t0 = nullptr, t1 = nullptr;
-    if (nch > 0 && m->timed_launch()) {
-      t0 = m->take_event();
-      t1 = m->take_event();
-      hip_check(hipEventRecord(t0, s), "hipEventRecord");
-    }
-    mix1d_launch_events(mc, m->table_mix(), ev, n, m->chunk, nch, grad, m->part(), s);
-    if (t0) {
-      hip_check(hipEventRecord(t1, s), "hipEventRecord");
-      m->ev_pending.emplace_back(t0, t1);
-    }
+    m->timing_events(nch > 0, t0, t1);
+    mix1d_launch_events(mc, m->table_mix(), ev, n, m->chunk, nch, grad, m->part(), s, t0, t1);
+    m->pend(t0, t1);
     mix1d_launch_finalize(mc, m->table_mix(), m->part(), nch, grad, (double)n, m->out(), out_user, s);
   } else if (m->kind == kKindTddp3) {
     const DalitzConst& dc = m->dal;
@@ -406,17 +399,10 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
       m->M_valid = true;
     }
     hipEvent_t t0 = nullptr, t1 = nullptr;
-    if (nch > 0 && m->timed_launch()) {
-      t0 = m->take_event();
-      t1 = m->take_event();
-      hip_check(hipEventRecord(t0, s), "hipEventRecord");
-    }
+    m->timing_events(nch > 0, t0, t1);
     tddp_launch_events(*m->tddp_jit, dc, m->table_dal(), m->tdt, coef, ev, ld, n, m->chunk, nch, grad, m->part(),
-                       s);
-    if (t0) {
-      hip_check(hipEventRecord(t1, s), "hipEventRecord");
-      m->ev_pending.emplace_back(t0, t1);
-    }
+                       s, t0, t1);
+    m->pend(t0, t1);
     tddp_launch_finalize(dc, m->table_dal(), m->tdt, coef, m->part(), nch, grad, m->Mc(), (double)n, m->out(),
                          out_user, s);
   } else if (m->kind == kKindTd4) {
@@ -436,16 +422,10 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
       m->M_valid = true;
     }
     hipEvent_t t0 = nullptr, t1 = nullptr;
-    if (nch > 0 && m->timed_launch()) {
-      t0 = m->take_event();
-      t1 = m->take_event();
-      hip_check(hipEventRecord(t0, s), "hipEventRecord");
-    }
-    td4_launch_events(*m->td4_jit, tc, m->table_td4(), nullptr, 1, ev, ld, n, m->chunk, grad, m->part(), s);
-    if (t0) {
-      hip_check(hipEventRecord(t1, s), "hipEventRecord");
-      m->ev_pending.emplace_back(t0, t1);
-    }
+    m->timing_events(nch > 0, t0, t1);
+    td4_launch_events(*m->td4_jit, tc, m->table_td4(), nullptr, 1, ev, ld, n, m->chunk, grad, m->part(), s, t0,
+                      t1);
+    m->pend(t0, t1);
     td4_launch_finalize(tc, m->table_td4(), nullptr, 1, m->part(), nch, grad, m->Mc(), (double)n, m->out(), 0,
                         out_user, s);
   } else {
@@ -485,19 +465,12 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
       m->M_valid = true;
     }
     hipEvent_t t0 = nullptr, t1 = nullptr;
-    if (nch > 0 && m->timed_launch()) {
-      t0 = m->take_event();
-      t1 = m->take_event();
-      hip_check(hipEventRecord(t0, s), "hipEventRecord");
-    }
+    m->timing_events(nch > 0, t0, t1);
     // cached M: the events pass evaluates I = c^H M c in its last workgroup
     const bool norm_in_pass = !dc.free_ls && nch > 0;
     dalitz_launch_events(*m->dal_jit, dc, m->table_dal(), coef, ev, ld, n, m->chunk, nch, g, m->part(), s,
-                         norm_in_pass ? m->Mc() : nullptr, norm_in_pass ? m->out() : nullptr);
-    if (t0) {
-      hip_check(hipEventRecord(t1, s), "hipEventRecord");
-      m->ev_pending.emplace_back(t0, t1);
-    }
+                         norm_in_pass ? m->Mc() : nullptr, norm_in_pass ? m->out() : nullptr, t0, t1);
+    m->pend(t0, t1);
     dalitz_launch_finalize(dc, m->table_dal(), coef, m->part(), nch, g, npart, nrows, nnv, m->Mc(), (double)n,
                            m->out(), out_user, s, norm_in_pass);
   }

@@ -15,6 +15,7 @@
 //   mix1d_eval      P(x_i) per event;  mix1d_check  out-of-range count
 // HBM traffic per event is 8 bytes (x); the work is FP64 exp/log and a few
 // FMAs, so the events kernel is bound by FP64 VALU issue, not by HBM.
+#include <hip/hip_ext.h>
 #include <cmath>
 
 #include "kernels.hpp"
@@ -106,11 +107,13 @@ void mix1d_launch_prologue(const Mix1dConst& mc, const ParamBlock& pb, const dou
 }
 
 void mix1d_launch_events(const Mix1dConst& mc, const Mix1dTable* tab, const double* x, int64_t n, int chunk,
-                         int64_t nchunks, bool grad, double* part, hipStream_t s) {
+                         int64_t nchunks, bool grad, double* part, hipStream_t s, hipEvent_t start,
+                         hipEvent_t stop) {
   if (nchunks == 0) return;
   const int kmax = mix1d_kmax(mc.K);
   const dim3 g((unsigned)nchunks), b(kBlock);
-#define FN_MIX(G, K) hipLaunchKernelGGL((mix1d_events<G, K>), g, b, 0, s, mc, tab, x, n, chunk, part)
+#define FN_MIX(G, K) \
+  hipExtLaunchKernelGGL((mix1d_events<G, K>), g, b, 0, s, start, stop, 0, mc, tab, x, n, chunk, part)
   if (kmax == 2) {
     if (grad) FN_MIX(true, 2); else FN_MIX(false, 2);
   } else {

@@ -378,7 +378,8 @@ void td4_launch_mmatrix(const Td4Jit& j, const Td4Const& tc, const Td4Table* tab
 }
 
 void td4_launch_events(const Td4Jit& j, const Td4Const& tc, const Td4Table* tabs, const int* status, int n_fits,
-                       const double* ev, int64_t ld, int64_t n, int chunk, bool grad, double* part, hipStream_t s) {
+                       const double* ev, int64_t ld, int64_t n, int chunk, bool grad, double* part, hipStream_t s,
+                       hipEvent_t start, hipEvent_t stop) {
   const int64_t nch = (n + chunk - 1) / chunk;
   if (nch == 0) return;
   Td4Const c = tc;
@@ -389,7 +390,7 @@ void td4_launch_events(const Td4Jit& j, const Td4Const& tc, const Td4Table* tabs
   int ck = chunk, nf = n_fits;
   double* p = part;
   void* args[] = {&c, &t, &st, &e, &l, &nn, &ck, &nc, &nf, &p};
-  jit_launch(j.ev[grad ? 1 : 0], (unsigned)(nch * n_fits), kBlock, s, args);
+  jit_launch(j.ev[grad ? 1 : 0], (unsigned)(nch * n_fits), kBlock, s, args, start, stop);
 }
 
 void td4_launch_finalize(const Td4Const& tc, const Td4Table* tabs, const int* status, int n_fits, const double* part,

@@ -45,7 +45,8 @@ void td4_launch_mmatrix(const Td4Jit& j, const Td4Const& tc, const Td4Table* tab
 // Events pass for n_fits fits sharing one event sample (fit-major items); a
 // fit whose status entry is not running is skipped (status may be null).
 void td4_launch_events(const Td4Jit& j, const Td4Const& tc, const Td4Table* tabs, const int* status, int n_fits,
-                       const double* ev, int64_t ld, int64_t n, int chunk, bool grad, double* part, hipStream_t s);
+                       const double* ev, int64_t ld, int64_t n, int chunk, bool grad, double* part, hipStream_t s,
+                       hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 // Level-2 and NLL assembly per fit: out + f * out_stride = [NLL, grad(P), I, dI(P)].
 void td4_launch_finalize(const Td4Const& tc, const Td4Table* tabs, const int* status, int n_fits, const double* part,
                          int64_t rows_per_fit, bool grad, const double* Mc, double n_events, double* out,

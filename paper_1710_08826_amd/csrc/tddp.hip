@@ -236,7 +236,7 @@ void tddp_launch_gen(const TddpJit& j, const DalitzConst& dc, const DalitzTable*
 
 void tddp_launch_events(const TddpJit& j, const DalitzConst& dc, const DalitzTable* tab, const TddpTime& tt,
                         const double* coef, const double* ev, int64_t ld, int64_t n, int chunk, int64_t nchunks,
-                        bool grad, double* part, hipStream_t s) {
+                        bool grad, double* part, hipStream_t s, hipEvent_t start, hipEvent_t stop) {
   if (nchunks == 0) return;
   DalitzConst c = dc;
   const DalitzTable* t = tab;
@@ -247,7 +247,7 @@ void tddp_launch_events(const TddpJit& j, const DalitzConst& dc, const DalitzTab
   int ch = chunk;
   double* p = part;
   void* args[] = {&c, &t, &tm, &cf, &e, &l, &nn, &ch, &p};
-  jit_launch(j.ev[grad ? 1 : 0], (unsigned)nchunks, kBlock, s, args);
+  jit_launch(j.ev[grad ? 1 : 0], (unsigned)nchunks, kBlock, s, args, start, stop);
 }
 
 void tddp_launch_finalize(const DalitzConst& dc, const DalitzTable* tab, const TddpTime& tt, const double* coef,

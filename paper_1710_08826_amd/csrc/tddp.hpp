@@ -25,7 +25,8 @@ void tddp_launch_mmatrices(const TddpJit& j, const DalitzConst& dc, const Dalitz
 // Events pass: one row of partial sums per chunk.  coef: theta on the device.
 void tddp_launch_events(const TddpJit& j, const DalitzConst& dc, const DalitzTable* tab, const TddpTime& tt,
                         const double* coef, const double* ev, int64_t ld, int64_t n, int chunk, int64_t nchunks,
-                        bool grad, double* part, hipStream_t s);
+                        bool grad, double* part, hipStream_t s, hipEvent_t start = nullptr,
+                        hipEvent_t stop = nullptr);
 // Level-2 and NLL assembly: out = [NLL, grad(P), I, dI(P)].
 void tddp_launch_finalize(const DalitzConst& dc, const DalitzTable* tab, const TddpTime& tt, const double* coef,
                           const double* part, int64_t nrows, bool grad, const double* Mc, double n_events,
