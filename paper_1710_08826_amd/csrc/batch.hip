@@ -124,40 +124,54 @@ __global__ void batch_prologue(Mix1dConst mc, const BfgsState* __restrict__ st, 
 }
 
 // Single workgroup: item_base[f] = sum of chunk counts of running fits < f;
-// item_base[n_fits] = total; *n_running = number of running fits.
+// item_base[n_fits] = total; *n_running = number of running fits.  Thread t
+// takes a contiguous run of fits; the exclusive scan of the per-thread sums
+// (thread order) is a shuffle scan within each wave plus the totals of the
+// preceding waves: exact integer sums, the same as a serial loop.
 __global__ __launch_bounds__(kBlock) void batch_scan(const int* __restrict__ stat, const int64_t* __restrict__ nev,
                                                      int n_fits, int chunk, int64_t* __restrict__ item_base,
                                                      int* __restrict__ n_running) {
-  __shared__ int64_t sums[kBlock];
-  __shared__ int counts[kBlock];
-  const int t = threadIdx.x;
+  constexpr int kWaves = kBlock / 64;
+  __shared__ int64_t wsum[kWaves];
+  __shared__ int wcnt[kWaves];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int per = (n_fits + kBlock - 1) / kBlock;
-  const int f0 = t * per, f1 = min(f0 + per, n_fits);
+  const int f0 = min(t * per, n_fits), f1 = min(f0 + per, n_fits);
   int64_t s = 0;
   int c = 0;
+#pragma unroll 4
   for (int f = f0; f < f1; ++f) {
     if (stat[f] == kFitRunning) {
       s += (nev[f] + chunk - 1) / chunk;
       ++c;
     }
   }
-  sums[t] = s;
-  counts[t] = c;
-  __syncthreads();
-  if (t == 0) {
-    int64_t acc = 0;
-    int cacc = 0;
-    for (int u = 0; u < kBlock; ++u) {
-      const int64_t v = sums[u];
-      sums[u] = acc;
-      acc += v;
-      cacc += counts[u];
+  int64_t x = s;
+  int cx = c;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int64_t y = __shfl_up(x, d, 64);
+    const int cy = __shfl_up(cx, d, 64);
+    if (lane >= d) {
+      x += y;
+      cx += cy;
     }
-    item_base[n_fits] = acc;
-    *n_running = cacc;
+  }
+  if (lane == 63) {
+    wsum[w] = x;
+    wcnt[w] = cx;
   }
   __syncthreads();
-  int64_t b = sums[t];
+  int64_t before = 0;
+  for (int u = 0; u < w; ++u) before += wsum[u];
+  if (t == kBlock - 1) {
+    int total = 0;
+    for (int u = 0; u < kWaves; ++u) total += wcnt[u];
+    item_base[n_fits] = before + x;
+    *n_running = total;
+  }
+  int64_t b = before + x - s;
+#pragma unroll 4
   for (int f = f0; f < f1; ++f) {
     item_base[f] = b;
     if (stat[f] == kFitRunning) b += (nev[f] + chunk - 1) / chunk;
