@@ -187,7 +187,8 @@ class Model:
         return best.value, dict(zip(self.TUNE_CHUNKS, list(us)))
 
     def set_timing(self, enable: bool, every: int = 1):
-        """Bracket every `every`-th per-event kernel launch with HIP events."""
+        """Time every `every`-th per-event kernel launch (the dispatch records its own
+        start and end into a pair of HIP events)."""
         check(self._lib.fn_model_timing(self._h, every if enable else 0))
 
     def kernel_time(self):
