@@ -40,7 +40,7 @@ COUNTED_FP64_FLOPS_PER_EVENT = {2048: 493.4, 1024: 498.8}
 TRAFFIC_SOURCES = ["paper_1710_08826_amd/csrc/dalitz_device.hpp", "paper_1710_08826_amd/csrc/dalitz3.hip",
                    "paper_1710_08826_amd/csrc/fastmath.hpp", "paper_1710_08826_amd/csrc/device_common.hpp",
                    "paper_1710_08826_amd/csrc/model.hpp"]
-TRAFFIC_HASH = "383d4483a437b5d2"
+TRAFFIC_HASH = "2be739b3e7919796"
 
 
 def counters_current() -> bool:

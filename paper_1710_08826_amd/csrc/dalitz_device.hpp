@@ -230,23 +230,26 @@ __device__ __forceinline__ void dalitz_point(const DalitzConst& dc, const double
     }
   }
   if (GRAD == 2) {
-    const double w2 = 2.0 * w;
+    // (ur, ui) = 2 w S from the coefficient terms above
+    const double ur = 2.0 * w * Sre, ui = 2.0 * w * Sim;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const double* rk = r + k * kDalFields;
       const double cr = coef[2 * k], ci = coef[2 * k + 1];
-      // E = conj(S) c A
+      // E = 2 w conj(S) c A
       const double car = cr * Are[k] - ci * Aim[k], cai = cr * Aim[k] + ci * Are[k];
-      const double er = Sre * car + Sim * cai, ei = Sre * cai - Sim * car;
-      // dA/dm0 = A (dlnKa - T (2 m0 - i G dKw/dm0));  dP~ = 2 Re(E * (...))
+      const double er = __builtin_fma(ur, car, ui * cai), ei = __builtin_fma(ur, cai, -(ui * car));
+      // dA/dm0 = A (dlnKa - X), X = T (2 m0 - i G dKw/dm0);  dP~ = 2 Re(E (dlnKa - X))
       const double gd = Gk[k] * rk[dDKW_DM0], tm = rk[dTWOM0];
-      const double xr = tm * Tre[k] + Tim[k] * gd;
-      const double xi = tm * Tim[k] - Tre[k] * gd;
-      const double yr = rk[dDLNKA] - xr, yi = -xi;
-      add(1 + 2 * K + 2 * k, w2 * (er * yr - ei * yi));
-      // dA/dGamma0 = i A T G Kw/Gamma0
+      const double xr = __builtin_fma(tm, Tre[k], Tim[k] * gd);
+      const double xi = __builtin_fma(tm, Tim[k], -(Tre[k] * gd));
+      add2(1 + 2 * K + 2 * k, er, rk[dDLNKA] - xr, ei, xi);
+      // dA/dGamma0 = i A T gw with gw = G Kw/Gamma0, so dP~ (times 2w) = Re(E i T) gw
+      // = -gw (er Tim + ei Tre)
       const double gw = Gk[k] * rk[dKW_W0];
-      add(2 + 2 * K + 2 * k, w2 * gw * (-er * Tim[k] - ei * Tre[k]));
+      const double q = __builtin_fma(er, Tim[k], ei * Tre[k]);
+      const double t = __builtin_fma(-gw, q, acc[2 + 2 * K + 2 * k]);
+      acc[2 + 2 * K + 2 * k] = valid ? t : acc[2 + 2 * K + 2 * k];
     }
   }
 }
