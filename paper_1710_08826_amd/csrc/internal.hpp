@@ -77,18 +77,26 @@ struct fn_model {
   hipEvent_t take_event();
   // Whether this event-pass launch is one of the timed ones.
   bool timed_launch() { return timing > 0 && timing_count++ % timing == 0; }
-  // Start/stop events for an event-pass launch when it is one of the timed
-  // ones (both null otherwise): the dispatch records the kernel's own start
-  // and end times into them; pend() queues them for fn_model_kernel_time once
-  // the launch has been issued.
-  void timing_events(bool launch, hipEvent_t& t0, hipEvent_t& t1) {
-    t0 = t1 = nullptr;
-    if (launch && timed_launch()) {
+  // Issues an event-pass launch, launch(t0, t1): when it is one of the timed
+  // ones, t0 and t1 are events that the dispatch fills with the kernel's own
+  // start and end times (queued for fn_model_kernel_time once the launch has
+  // been issued, back to the pool if it throws); otherwise both are null.
+  template <class F>
+  void timed(bool launches, F&& launch) {
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (launches && timed_launch()) {
       t0 = take_event();
       t1 = take_event();
     }
-  }
-  void pend(hipEvent_t t0, hipEvent_t t1) {
+    try {
+      launch(t0, t1);
+    } catch (...) {
+      if (t0) {
+        ev_pool.push_back(t0);
+        ev_pool.push_back(t1);
+      }
+      throw;
+    }
     if (t0) ev_pending.emplace_back(t0, t1);
   }
 

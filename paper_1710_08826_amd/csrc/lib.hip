@@ -372,10 +372,9 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
     m->d_part.reserve(sizeof(double) * (size_t)(nch > 0 ? nch : 1) * nv);
     ParamBlock zero;
     mix1d_launch_prologue(mc, pb ? *pb : zero, pb ? nullptr : theta_dev, 1, 0, m->table_mix(), s);
-    hipEvent_t t0 = nullptr, t1 = nullptr;
-    m->timing_events(nch > 0, t0, t1);
-    mix1d_launch_events(mc, m->table_mix(), ev, n, m->chunk, nch, grad, m->part(), s, t0, t1);
-    m->pend(t0, t1);
+    m->timed(nch > 0, [&](hipEvent_t t0, hipEvent_t t1) {
+      mix1d_launch_events(mc, m->table_mix(), ev, n, m->chunk, nch, grad, m->part(), s, t0, t1);
+    });
     mix1d_launch_finalize(mc, m->table_mix(), m->part(), nch, grad, (double)n, m->out(), out_user, s);
   } else if (m->kind == kKindTddp3) {
     const DalitzConst& dc = m->dal;
@@ -398,11 +397,10 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
       tddp_launch_mmatrices(*m->tddp_jit, dc, m->table_dal(), m->grid_chunk, m->npart(), m->Mc(), s);
       m->M_valid = true;
     }
-    hipEvent_t t0 = nullptr, t1 = nullptr;
-    m->timing_events(nch > 0, t0, t1);
-    tddp_launch_events(*m->tddp_jit, dc, m->table_dal(), m->tdt, coef, ev, ld, n, m->chunk, nch, grad, m->part(),
-                       s, t0, t1);
-    m->pend(t0, t1);
+    m->timed(nch > 0, [&](hipEvent_t t0, hipEvent_t t1) {
+      tddp_launch_events(*m->tddp_jit, dc, m->table_dal(), m->tdt, coef, ev, ld, n, m->chunk, nch, grad,
+                         m->part(), s, t0, t1);
+    });
     tddp_launch_finalize(dc, m->table_dal(), m->tdt, coef, m->part(), nch, grad, m->Mc(), (double)n, m->out(),
                          out_user, s);
   } else if (m->kind == kKindTd4) {
@@ -421,11 +419,10 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
                          m->Mc(), s);
       m->M_valid = true;
     }
-    hipEvent_t t0 = nullptr, t1 = nullptr;
-    m->timing_events(nch > 0, t0, t1);
-    td4_launch_events(*m->td4_jit, tc, m->table_td4(), nullptr, 1, ev, ld, n, m->chunk, grad, m->part(), s, t0,
-                      t1);
-    m->pend(t0, t1);
+    m->timed(nch > 0, [&](hipEvent_t t0, hipEvent_t t1) {
+      td4_launch_events(*m->td4_jit, tc, m->table_td4(), nullptr, 1, ev, ld, n, m->chunk, grad, m->part(), s, t0,
+                        t1);
+    });
     td4_launch_finalize(tc, m->table_td4(), nullptr, 1, m->part(), nch, grad, m->Mc(), (double)n, m->out(), 0,
                         out_user, s);
   } else {
@@ -464,13 +461,12 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
         dalitz_launch_mrows(*m->dal_jit, dc, m->table_dal(), m->grid_chunk, mrows, i0, m->npart(), m->Mc(), s);
       m->M_valid = true;
     }
-    hipEvent_t t0 = nullptr, t1 = nullptr;
-    m->timing_events(nch > 0, t0, t1);
     // cached M: the events pass evaluates I = c^H M c in its last workgroup
     const bool norm_in_pass = !dc.free_ls && nch > 0;
-    dalitz_launch_events(*m->dal_jit, dc, m->table_dal(), coef, ev, ld, n, m->chunk, nch, g, m->part(), s,
-                         norm_in_pass ? m->Mc() : nullptr, norm_in_pass ? m->out() : nullptr, t0, t1);
-    m->pend(t0, t1);
+    m->timed(nch > 0, [&](hipEvent_t t0, hipEvent_t t1) {
+      dalitz_launch_events(*m->dal_jit, dc, m->table_dal(), coef, ev, ld, n, m->chunk, nch, g, m->part(), s,
+                           norm_in_pass ? m->Mc() : nullptr, norm_in_pass ? m->out() : nullptr, t0, t1);
+    });
     dalitz_launch_finalize(dc, m->table_dal(), coef, m->part(), nch, g, npart, nrows, nnv, m->Mc(), (double)n,
                            m->out(), out_user, s, norm_in_pass);
   }
