@@ -356,7 +356,34 @@ def tddp3_leg(steps: int = 50):
             "events_per_s": n * steps / w, "ms_per_step": 1e3 * w / steps,
             "event_kernel_us": k * 1e3, "nll_only_event_kernel_us": k0 * 1e3,
             "flops_per_event": fl, "event_kernel_tflops": fl * n / (k * 1e-3) / 1e12,
-            "plain_fd_grad_events_per_s": n / fd_step, "adjoint_vs_plain_fd": fd_step / (w / steps)}
+            "plain_fd_grad_events_per_s": n / fd_step, "adjoint_vs_plain_fd": fd_step / (w / steps),
+            **tddp3_whole_fit(m, th, n)}
+
+
+def tddp3_whole_fit(m, th, n):
+    """A whole fit (context for the paper's example wall times, which are for
+    whole fits of a recorded sample): n events generated on the device at the
+    truth, then the host quasi-Newton fit with the adjoint gradient from a
+    shifted start, c_1..c_7 and x, y free (c_0 and cbar fixed, as in the
+    parity tests), parabolic errors included."""
+    import torch
+    import synth
+    ev, _ = m.generate(th, n, seed=synth.BASE_SEED + 8)
+    P = th.size
+    free = np.zeros(P, np.int32)
+    free[2:16] = 1
+    free[-2:] = 1
+    start = th.copy()
+    start[2:16] *= 1.03
+    start[-2:] *= 1.5
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fr = m.fit(start, ev, free=free, raise_on_fail=False)
+    wall = time.perf_counter() - t0
+    pull = np.abs(fr.theta - th)[free == 1] / np.maximum(fr.errors[free == 1], 1e-300)
+    return {"fit_events": n, "fit_free_params": int(free.sum()), "fit_wall_s": wall,
+            "fit_iterations": fr.n_iter, "fit_nll_calls": fr.n_calls, "fit_status": fr.status,
+            "fit_max_pull": float(pull.max())}
 
 
 def td4_leg(steps: int = 10):
