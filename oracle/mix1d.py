@@ -223,6 +223,41 @@ def binned_value_grad(theta, counts, desc: dict, stat: str):
     return float(v.detach()), th.grad.numpy().copy()
 
 
+def nll_tensor(theta: torch.Tensor, x: torch.Tensor, desc: dict) -> torch.Tensor:
+    """The NLL as a differentiable tensor (event sum in plain float64)."""
+    return -torch.log(density(theta, x, desc)).sum() + extended_term(theta, int(x.numel()), desc)
+
+
+def fit(x, theta0, desc: dict, bounds=None):
+    """Maximum-likelihood fit of events x: scipy's L-BFGS-B on this module's
+    NLL and autograd gradient, then errors sqrt(diag(H^-1)) from the autograd
+    Hessian H of the NLL at the minimum (an NLL has error definition 1/2, so
+    H^-1 is the covariance).  Returns (theta, errors, nll)."""
+    from scipy import optimize
+    res = optimize.minimize(lambda t: nll_grad(t, x, desc), np.asarray(theta0, dtype=np.float64), jac=True,
+                            method="L-BFGS-B", bounds=bounds, options={"ftol": 1e-15, "gtol": 1e-9, "maxiter": 2000})
+    xt = as_t(x)
+    h = torch.autograd.functional.hessian(lambda t: nll_tensor(t, xt, desc), as_t(res.x)).numpy()
+    cov = np.linalg.inv(0.5 * (h + h.T))
+    return res.x, np.sqrt(np.diag(cov)), float(res.fun)
+
+
+CONFIG0_BOUNDS = [(-5.0, 5.0), (0.1, 5.0), (-3.0, 3.0), (0.01, 0.99)]
+
+
+def toy_pull(args):
+    """Pull (fitted - truth) / error of one config-0 toy: n events drawn at
+    the truth by the input sampler under key (seed, fit), fitted from the
+    truth.  args = (n, seed, fit, truth); for pull studies in worker
+    processes."""
+    import synth
+    n, seed, fit_index, truth = args
+    torch.set_num_threads(1)
+    x = synth.mix1d_events(n, seed=seed, fit=fit_index)
+    th, err, _ = fit(x, truth, config0_desc(), bounds=CONFIG0_BOUNDS)
+    return (th - np.asarray(truth)) / err
+
+
 def config0_desc(lo: float = -10.0, hi: float = 10.0) -> dict:
     """The 1-D fit: f Gaussian(mu, sigma) + (1-f) exponential(tau) on [lo, hi]."""
     return {"kind": "mix1d", "lo": lo, "hi": hi, "n_params": 4,
