@@ -176,51 +176,205 @@ def gpu_info():
     return {"name": p.name, "cus": p.multi_processor_count, "arch": getattr(p, "gcnArchName", "")}
 
 
-# Every TIMING_EVERY-th event-pass launch of the timed loop is timed by the
-# library (the dispatch records the kernel's own start and end times into a
-# pair of HIP events on its stream); sampling keeps the event bookkeeping out
-# of most of the loop whose wall time is the reported value.
-TIMING_EVERY = 10
+# Wall-time trials: each trial times exactly `steps` steps; trials repeat until
+# at least MIN_TRIALS of them and MIN_TIMED_S seconds of timed work, and the
+# median trial is reported.
+MIN_TRIALS = 5
+MIN_TIMED_S = 0.1
+MAX_TRIALS = 2000
+# Launches of the separate loop that times the per-event kernel itself (every
+# launch carries a HIP event pair; none of them is inside a wall-timed trial).
+KERNEL_TIMING_LAUNCHES = 50
 
 
-def time_async(model, theta_dev, ev, out, steps, warmup, with_grad=True, alt=None):
-    """Wall time of `steps` asynchronous NLL(+grad) calls (device theta), and
-    the average duration of the sampled per-event kernel launches in ms."""
+def capture_steps(model, thetas, ev, out, with_grad):
+    """One hipGraph per trial point, each holding one asynchronous NLL(+grad)
+    call (prologue if any, events pass, level-2 step), captured on a side
+    stream after the model's caches are built; None when capture fails."""
     import torch
-    for i in range(warmup):
-        model.nll_async(theta_dev if (alt is None or i % 2 == 0) else alt, ev, out, with_grad)
+    graphs = []
+    s = torch.cuda.Stream()
+    try:
+        for th in thetas:
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=s, capture_error_mode="thread_local"):
+                model.nll_async(th, ev, out, with_grad)
+            graphs.append(g)
+    except Exception as e:  # noqa: BLE001 - reported in the bench line
+        print(f"[bench] graph capture failed ({e}); timing direct launches", file=sys.stderr, flush=True)
+        return None
+    return graphs
+
+
+def time_async(model, theta_dev, ev, out, steps, warmup, with_grad=True, alt=None, graph=True):
+    """NLL(+grad) steps with device theta alternating between two points, so no
+    cache short-circuits the work.  Returns (median wall seconds of a trial of
+    exactly `steps` steps, average per-event kernel duration in ms from a
+    separate loop of individually timed launches, info)."""
+    import torch
+    thetas = [theta_dev] if alt is None else [theta_dev, alt]
+    for i in range(max(warmup, 2)):
+        model.nll_async(thetas[i % len(thetas)], ev, out, with_grad)
     torch.cuda.synchronize()
-    model.kernel_time()  # drop warm-up timings
-    model.set_timing(True, every=TIMING_EVERY if steps >= 5 * TIMING_EVERY else 1)
+    graphs = capture_steps(model, thetas, ev, out, with_grad) if graph else None
+
+    def run(k):
+        if graphs:
+            for i in range(k):
+                graphs[i % len(graphs)].replay()
+        else:
+            for i in range(k):
+                model.nll_async(thetas[i % len(thetas)], ev, out, with_grad)
+
+    run(max(warmup, 2))
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(steps):
-        model.nll_async(theta_dev if (alt is None or i % 2 == 0) else alt, ev, out, with_grad)
+    trials = []
+    while len(trials) < MAX_TRIALS and (len(trials) < MIN_TRIALS or sum(trials) < MIN_TIMED_S):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run(steps)
+        torch.cuda.synchronize()
+        trials.append(time.perf_counter() - t0)
+    # the kernel's own duration, outside the wall-timed trials
+    model.kernel_time()
+    model.set_timing(True, every=1)
+    for i in range(KERNEL_TIMING_LAUNCHES):
+        model.nll_async(thetas[i % len(thetas)], ev, out, with_grad)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
     model.set_timing(False)
     kms, launches = model.kernel_time()
-    return t1 - t0, kms / max(launches, 1)
+    info = {"trials": len(trials), "timed_s": sum(trials), "graph": graphs is not None,
+            "trial_ms_min": 1e3 * min(trials), "trial_ms_max": 1e3 * max(trials)}
+    return float(np.median(trials)), kms / max(launches, 1), info
 
 
-def cpu_baseline(events: np.ndarray, desc: dict, theta, budget_s: float = 12.0):
-    """The CPU oracle (NLL + autograd gradient, grid normalization each call)
-    on a bounded sample, repeated until about budget_s seconds."""
+def cpu_info():
+    """nproc, the threads torch uses and the CPU model string of this host."""
+    import torch
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "threads": torch.get_num_threads(),
+            "cpu_model": model}
+
+
+def _median_rate(fn, units, trials=5, min_s=0.3):
+    """Median over trials of units/second; a trial repeats fn until min_s."""
+    rates = []
+    for _ in range(trials):
+        calls = 0
+        t0 = time.perf_counter()
+        while True:
+            fn()
+            calls += 1
+            if time.perf_counter() - t0 >= min_s:
+                break
+        rates.append(units * calls / (time.perf_counter() - t0))
+    return float(np.median(rates))
+
+
+def cpu_baseline(events: np.ndarray, desc: dict, theta):
+    """The CPU oracle on a bounded sample of the config-1 workload, the same
+    work as the GPU step: the event term -sum ln P~ and its autograd gradient
+    (the GPU step takes I = c^H M c from the cached grid matrix, a 16 x 16
+    quadratic form).  Median of 5 trials with all host threads and with one.
+    Also the oracle call as it stands (grid normalization recomputed every
+    call) for reference."""
     import torch
     from oracle import dalitz3 as OD
-    cells = OD.Dalitz(desc).grid_cells()
-    calls = 0
+    from oracle.common import as_t
+    model = OD.Dalitz(desc)
+    s12, s13 = as_t(events[0]), as_t(events[1])
+    n = events.shape[1]
+
+    def event_term():
+        th = as_t(theta, requires_grad=True)
+        (-torch.log(model.density_unnorm(th, s12, s13)).sum()).backward()
+
+    info = cpu_info()
+    nthreads = torch.get_num_threads()
+    rate = _median_rate(event_term, n)
+    torch.set_num_threads(1)
+    sub = max(1, n // 8)
+    s12_1, s13_1 = s12[:sub].clone(), s13[:sub].clone()
+
+    def event_term_1():
+        th = as_t(theta, requires_grad=True)
+        (-torch.log(model.density_unnorm(th, s12_1, s13_1)).sum()).backward()
+
+    rate_1 = _median_rate(event_term_1, sub)
+    torch.set_num_threads(nthreads)
+    cells = model.grid_cells()
     t0 = time.perf_counter()
-    while True:
-        OD.nll_grad(theta, events, desc, cells)
-        calls += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": events.shape[1] * calls / dt, "unit": "events/s", "cores": torch.get_num_threads(),
-            "kind": "oracle",
-            "sample": f"{events.shape[1]} events of the same Dalitz workload, NLL + autograd gradient "
-                      f"with the 1024x1024 grid normalization recomputed per call, {calls} calls in {dt:.1f} s"}
+    OD.nll_grad(theta, events, desc, cells)
+    full = n / (time.perf_counter() - t0)
+    return {"value": rate, "unit": "events/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"{n} events of the config-1 Dalitz workload: the oracle's event term -sum ln P~ with its "
+                      f"autograd gradient (16 parameters), median of 5 trials of >= 0.3 s; normalization excluded on "
+                      f"both sides (the GPU step reads the cached grid matrix)",
+            "one_core_events_per_s": rate_1, "one_core_sample_events": sub,
+            "oracle_call_with_grid_events_per_s": full, **info}
+
+
+def cpu_baselines_other():
+    """The oracle on bounded samples of configs 0, 3 and 4 (events/s of NLL +
+    autograd gradient, median of 5 trials, all host threads), each with the
+    work its GPU step does: config 0 analytic normalization; config 3 the
+    event term at 4M events plus the full 1024 x 1024 grid every call
+    (per-call time from the two measured rates); config 4 the event term
+    (the GPU single fit reads the cached sample matrix)."""
+    import torch
+    import synth
+    from oracle import dalitz3 as OD, mix1d as OM, td4 as OT
+    from oracle.common import as_t
+    out = {}
+    x0 = synth.mix1d_events(100_000)
+    d0 = synth.mix1d_desc()
+    th0 = synth.mix1d_truth()
+    out["config0_events_per_s"] = _median_rate(lambda: OM.nll_grad(th0, x0, d0), x0.size, min_s=0.2)
+    d3 = synth.dalitz_desc(free_lineshapes=True)
+    th3 = synth.dalitz_truth(free_lineshapes=True)
+    ev3 = synth.dalitz_events(20_000, seed=synth.BASE_SEED + 3)
+    m3 = OD.Dalitz(d3)
+    a12, a13 = as_t(ev3[0]), as_t(ev3[1])
+
+    def ev_term3():
+        th = as_t(th3, requires_grad=True)
+        (-torch.log(m3.density_unnorm(th, a12, a13)).sum()).backward()
+
+    ev_rate3 = _median_rate(ev_term3, ev3.shape[1], min_s=0.2)
+    c12, c13, da = m3.grid_cells()
+    sub = 100_000
+    g12, g13 = as_t(c12[:sub]), as_t(c13[:sub])
+
+    def grid_term3():
+        th = as_t(th3, requires_grad=True)
+        (da * m3.density_unnorm(th, g12, g13).sum()).backward()
+
+    cell_rate3 = _median_rate(grid_term3, sub, min_s=0.2)
+    call3 = 4_000_000 / ev_rate3 + c12.size / cell_rate3
+    out["config3_events_per_s"] = 4_000_000 / call3
+    out["config3_grid_cells_per_s"] = cell_rate3
+    d4 = synth.td4_desc()
+    th4 = synth.td4_truth()
+    ev4 = synth.td4_events(5_000, seed=synth.BASE_SEED + 4)
+    m4 = OT.TD4(d4)
+    e4 = as_t(ev4)
+
+    def ev_term4():
+        th = as_t(th4, requires_grad=True)
+        (-torch.log(m4.rate(th, e4)).sum()).backward()
+
+    out["config4_events_per_s"] = _median_rate(ev_term4, ev4.shape[1], min_s=0.2)
+    out["sample"] = ("config 0: 100k events, analytic normalization; config 3: 20k events and 100k grid cells "
+                     "timed, per-call time of 4M events + 497,806 cells derived; config 4: 5k events, event term")
+    return out
 
 
 def pmc_probe(steps: int, chunk: int):
@@ -245,14 +399,14 @@ def pmc_probe(steps: int, chunk: int):
                       "nll": float(out[0])}), flush=True)
 
 
-def serving_leg(n_fits: int = 4096, one_at_a_time: int = 256, fd_fits: int = 32, lam_frac: float = 0.7):
+def serving_leg(n_fits: int = 4096, fd_fits: int = 32, lam_frac: float = 0.7):
     """Config 2: toy fits of the config-0 model with per-fit sizes drawn
     log-uniform in [1e3, 2e6], events generated on the device at admission.
     Returns fits/s and latency percentiles for (a) all requests at t = 0 and
     (b) Poisson arrivals at lam_frac x the batched throughput, on the
     continuous-batching server; (c) one fit at a time (host BFGS, adjoint
-    gradient) and (d) one fit at a time with finite-difference gradients, on
-    subsamples of the same request list."""
+    gradient) on every request at the same Poisson arrivals, and (d) one fit
+    at a time with finite-difference gradients on a subsample."""
     import torch
     import synth
     from paper_1710_08826_amd import Model, Server, generate_mix1d
@@ -290,31 +444,67 @@ def serving_leg(n_fits: int = 4096, one_at_a_time: int = 256, fd_fits: int = 32,
     out["poisson"]["rate_per_s"] = rate
 
     def sequential(reqs, mode):
+        """One fit at a time in arrival order (host BFGS on the single-fit
+        path, events generated on the device per request); a request waits
+        until it has arrived and until the previous fit is done."""
         lat = []
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         for q in reqs:
+            wait = q["arrival_s"] - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(wait)
             ev = generate_mix1d(q["n_events"], q["seed"], q["fit"], truth)
             model.fit(start, ev, grad_mode=mode, raise_on_fail=False)
-            lat.append(time.perf_counter() - t0)
+            lat.append(time.perf_counter() - t0 - q["arrival_s"])
         wall = time.perf_counter() - t0
+        lat = np.array(lat)
         return {"fits": len(reqs), "wall_s": wall, "fits_per_s": len(reqs) / wall,
+                "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
                 "events": int(sum(r["n_events"] for r in reqs))}
 
-    sub = base[:: max(1, n_fits // one_at_a_time)][:one_at_a_time]
-    out["one_at_a_time_adjoint"] = sequential(sub, "adjoint")
+    # every request, one at a time, at the batched run's Poisson arrivals
+    out["one_at_a_time_poisson"] = sequential(pois, "adjoint")
+    out["one_at_a_time_poisson"]["rate_per_s"] = rate
     subfd = base[:: max(1, n_fits // fd_fits)][:fd_fits]
     out["one_at_a_time_fd"] = sequential(subfd, "fd")
     # the same request subsample on the batched server, for a like-for-like ratio
     out["batched_same_subsample_fd"] = serve(subfd, len(subfd))
     out["speedup_batched_vs_plain_fd"] = out["closed_loop"]["fits_per_s"] / out["one_at_a_time_fd"]["fits_per_s"]
     out["speedup_batched_vs_one_at_a_time_adjoint"] = (out["closed_loop"]["fits_per_s"]
-                                                      / out["one_at_a_time_adjoint"]["fits_per_s"])
+                                                      / out["one_at_a_time_poisson"]["fits_per_s"])
     return out
+
+
+def config0_above_mall(n: int = 1 << 26, steps: int = 20):
+    """Config-0 events pass at 2^26 events (512 MB, above the 256 MB
+    Infinity Cache), events generated on the device: NLL + gradient steps and
+    the events kernel's duration, HBM GB/s and FP64 rate."""
+    import torch
+    import synth
+    from paper_1710_08826_amd import Model, generate_mix1d
+    truth = synth.mix1d_truth()
+    x = generate_mix1d(n, synth.BASE_SEED, 26, truth)
+    m = Model(synth.mix1d_desc())
+    t = torch.from_numpy(truth).cuda()
+    tb = torch.from_numpy(truth * 1.001).cuda()
+    o = torch.empty(1 + m.n_params, dtype=torch.float64, device="cuda")
+    w, k, info = time_async(m, t, x, o, steps, 3, True, alt=tb)
+    fl = mix1d_flops_per_event(True)
+    r = {"config0_mall_events": n, "config0_mall_chunk": m.chunk, "config0_mall_events_per_s": n * steps / w,
+         "config0_mall_ms_per_step": 1e3 * w / steps, "config0_mall_event_kernel_us": 1e3 * k,
+         "config0_mall_hbm_gbs": 8.0 * n / (k * 1e-3) / 1e9,
+         "config0_mall_tflops": fl * n / (k * 1e-3) / 1e12, "config0_mall_flops_per_event": fl,
+         "config0_mall_timing": info}
+    del x
+    return r
 
 
 def config3_leg(steps: int = 20):
     """Config 3: masses and widths free (32 parameters), 4M events, the full
-    grid normalization every call."""
+    grid normalization every call; then whole fits of 4M device-generated
+    events with the adjoint gradient and with central finite differences
+    (h = 1e-6 max(|theta|, 1)), from the same shifted start."""
     import torch
     import synth
     from paper_1710_08826_amd import Model
@@ -323,11 +513,48 @@ def config3_leg(steps: int = 20):
     ev3 = torch.from_numpy(synth.dalitz_events(4_000_000, seed=synth.BASE_SEED + 3)).cuda()
     m3 = Model(desc3)
     t3 = torch.from_numpy(th3).cuda()
+    t3b = torch.from_numpy(th3 * (1.0 + 1e-4 * np.cos(np.arange(th3.size)))).cuda()
     o3 = torch.empty(1 + m3.n_params, dtype=torch.float64, device="cuda")
-    w3, k3 = time_async(m3, t3, ev3, o3, steps, 3, True)
-    return {"config3_events_per_s": 4_000_000 * steps / w3, "config3_ms_per_step": 1e3 * w3 / steps,
-            "config3_event_kernel_us": k3 * 1e3,
-            "config3_event_kernel_tflops": dalitz_flops_per_event(desc3, 2) * 4e6 / (k3 * 1e-3) / 1e12}
+    w3, k3, info = time_async(m3, t3, ev3, o3, steps, 3, True, alt=t3b)
+    r = {"config3_events_per_s": 4_000_000 / w3 * steps, "config3_ms_per_step": 1e3 * w3 / steps,
+         "config3_event_kernel_us": k3 * 1e3,
+         "config3_event_kernel_tflops": dalitz_flops_per_event(desc3, 2) * 4e6 / (k3 * 1e-3) / 1e12,
+         "config3_timing": info}
+    r.update(config3_fits(m3, th3))
+    return r
+
+
+def config3_fits(m3, th3, n: int = 4_000_000):
+    """Minimizer wall time with and without the adjoint gradient on the
+    config-3 model: n events generated on the device at the truth, start at
+    coefficients x 1.03, masses x 1.002 and widths x 1.05 (c_0 fixed as the
+    reference amplitude), 30 free parameters."""
+    import torch
+    import synth
+    ev, _ = m3.generate(th3, n, seed=synth.BASE_SEED + 33)
+    P = th3.size
+    K = P // 4
+    free = np.ones(P, np.int32)
+    free[0:2] = 0
+    start = th3.copy()
+    start[2:2 * K] *= 1.03
+    start[2 * K::2] *= 1.002
+    start[2 * K + 1::2] *= 1.05
+    out = {"config3_fit_events": n, "config3_fit_free_params": int(free.sum())}
+    for mode in ("adjoint", "fd"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fr = m3.fit(start, ev, free=free, grad_mode=mode, raise_on_fail=False)
+        wall = time.perf_counter() - t0
+        pull = np.abs(fr.theta - th3)[free == 1] / np.maximum(fr.errors[free == 1], 1e-300)
+        out[f"config3_fit_{mode}_wall_s"] = wall
+        out[f"config3_fit_{mode}_iterations"] = fr.n_iter
+        out[f"config3_fit_{mode}_nll_calls"] = fr.n_calls
+        out[f"config3_fit_{mode}_status"] = fr.status
+        out[f"config3_fit_{mode}_nll"] = fr.nll
+        out[f"config3_fit_{mode}_max_pull"] = float(pull.max())
+    out["config3_fit_speedup_adjoint_vs_fd"] = out["config3_fit_fd_wall_s"] / out["config3_fit_adjoint_wall_s"]
+    return out
 
 
 def tddp3_leg(steps: int = 50):
@@ -347,8 +574,8 @@ def tddp3_leg(steps: int = 50):
     tdev = torch.from_numpy(th).cuda()
     tb = torch.from_numpy(th * (1.0 + 1e-3 * np.cos(np.arange(P)))).cuda()
     out = torch.empty(1 + P, dtype=torch.float64, device="cuda")
-    w, k = time_async(m, tdev, ev, out, steps, 3, True, alt=tb)
-    w0, k0 = time_async(m, tdev, ev, out, steps, 3, False, alt=tb)
+    w, k, info = time_async(m, tdev, ev, out, steps, 3, True, alt=tb)
+    w0, k0, _ = time_async(m, tdev, ev, out, steps, 3, False, alt=tb)
     fl = tddp3_flops_per_event(desc, True)
     fd_step = (2 * P + 1) * w0 / steps
     return {"events": n, "params": P, "grid": desc["grid"], "chunk": m.chunk,
@@ -357,7 +584,7 @@ def tddp3_leg(steps: int = 50):
             "event_kernel_us": k * 1e3, "nll_only_event_kernel_us": k0 * 1e3,
             "flops_per_event": fl, "event_kernel_tflops": fl * n / (k * 1e-3) / 1e12,
             "plain_fd_grad_events_per_s": n / fd_step, "adjoint_vs_plain_fd": fd_step / (w / steps),
-            **tddp3_whole_fit(m, th, n)}
+            "timing": info, **tddp3_whole_fit(m, th, n)}
 
 
 def tddp3_whole_fit(m, th, n):
@@ -413,15 +640,15 @@ def td4_leg(steps: int = 10):
     out = torch.empty(1 + P, dtype=torch.float64, device="cuda")
     fl_g, fl_0 = td4_flops_per_event(desc, True), td4_flops_per_event(desc, False)
     _, tune_us = m.autotune(th, ev, reps=5)
-    w, k = time_async(m, tdev, ev, out, steps, 2, True, alt=tb)
-    w0, k0 = time_async(m, tdev, ev, out, steps, 2, False, alt=tb)
+    w, k, info = time_async(m, tdev, ev, out, steps, 2, True, alt=tb)
+    w0, k0, _ = time_async(m, tdev, ev, out, steps, 2, False, alt=tb)
     r = {"events": n, "mc_points": n_mc, "params": P, "chunk": m.chunk,
          "autotune_us": {str(c): v for c, v in tune_us.items()},
          "cpu_generation_s": gen_s, "device_mc_sample_s": mc_gen_s,
          "single_events_per_s": n * steps / w, "single_ms_per_step": 1e3 * w / steps,
          "single_event_kernel_ms": k, "single_event_kernel_tflops": fl_g * n / (k * 1e-3) / 1e12,
          "nll_only_event_kernel_ms": k0, "nll_only_event_kernel_tflops": fl_0 * n / (k0 * 1e-3) / 1e12,
-         "flops_per_event_fit": fl_g, "flops_per_event_fit_nll_only": fl_0}
+         "flops_per_event_fit": fl_g, "flops_per_event_fit_nll_only": fl_0, "timing": info}
     # plain finite differences: 2P + 1 NLL-only evaluations per gradient, one call at a time
     reps = 2
     torch.cuda.synchronize()
@@ -481,7 +708,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--quick", action="store_true", help="skip the side measurements and the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--leg", choices=["td4", "serve", "tddp3", "config3"],
+    ap.add_argument("--no-graph", action="store_true", help="time direct launches instead of captured steps")
+    ap.add_argument("--leg", choices=["td4", "serve", "tddp3", "config3", "config0-mall", "cpu"],
                     help="run only the four-body leg or the serving leg and print its figures (for profiling)")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="for counter runs: one 256 MiB device copy (calibration) then --steps "
@@ -509,6 +737,15 @@ def main():
     if args.leg == "config3":
         print(json.dumps(config3_leg()), flush=True)
         return
+    if args.leg == "config0-mall":
+        print(json.dumps(config0_above_mall()), flush=True)
+        return
+    if args.leg == "cpu":
+        import synth
+        print(json.dumps({"cpu_baseline": cpu_baseline(synth.dalitz_events(100_000, seed=synth.BASE_SEED),
+                                                       synth.dalitz_desc(), synth.dalitz_truth()),
+                          "cpu_baselines": cpu_baselines_other()}), flush=True)
+        return
 
     import torch
     import synth
@@ -534,19 +771,20 @@ def main():
         tuned_chunk, tune_us = m1.autotune(th1, ev1, reps=20)
     print(f"[bench] config1 dalitz: {n1} events, P={P1}, chunk {tuned_chunk}, warmup {args.warmup}, "
           f"steps {args.steps}", file=sys.stderr, flush=True)
-    wall, kern_ms = time_async(m1, tdev, ev1, out, args.steps, args.warmup, True, alt=tdev_b)
+    wall, kern_ms, info1 = time_async(m1, tdev, ev1, out, args.steps, args.warmup, True, alt=tdev_b,
+                                      graph=not args.no_graph)
     ms_step = 1e3 * wall / args.steps
     value = n1 * args.steps / wall
     flops_ev = dalitz_flops_per_event(desc1, 1)
     achieved = flops_ev * n1 / (kern_ms * 1e-3) / 1e12
-    extra = {"config1_autotune_us": {str(k): v for k, v in tune_us.items()}}
+    extra = {"config1_autotune_us": {str(k): v for k, v in tune_us.items()}, "config1_timing": info1}
     print(f"[bench] {value:.4g} events/s, step {ms_step:.4f} ms, kernel {kern_ms * 1e3:.2f} us",
           file=sys.stderr, flush=True)
 
     if not args.quick:
         # NLL-only evaluations and the plain finite-difference gradient path:
         # one FD gradient = 2P+1 NLL-only evaluations, one call at a time
-        w0, k0 = time_async(m1, tdev, ev1, out, args.steps, 5, False)
+        w0, k0, _ = time_async(m1, tdev, ev1, out, args.steps, 5, False, alt=tdev_b)
         nll_only_rate = n1 * args.steps / w0
         nfd = max(10, args.steps // (2 * P1 + 1))
         theta_host = th1.copy()
@@ -585,10 +823,12 @@ def main():
         m0 = Model(d0)
         t0d = torch.from_numpy(np.array(synth.CONFIG0_TRUTH)).to(dev)
         o0 = torch.empty(5, dtype=torch.float64, device=dev)
-        w00, k00 = time_async(m0, t0d, x0, o0, args.steps, 10, True)
+        t0d_b = torch.from_numpy(np.array(synth.CONFIG0_TRUTH) * 1.001).to(dev)
+        w00, k00, _ = time_async(m0, t0d, x0, o0, args.steps, 10, True, alt=t0d_b)
         extra["config0_events_per_s"] = 100_000 * args.steps / w00
         extra["config0_ms_per_step"] = 1e3 * w00 / args.steps
         extra["config0_event_kernel_us"] = k00 * 1e3
+        extra.update(config0_above_mall())
         # single fits: adjoint vs finite-difference gradient (config 0, 100k events)
         start = np.array(synth.CONFIG0_TRUTH) * 1.1
         for mode in ("adjoint", "fd"):
@@ -628,13 +868,15 @@ def main():
         print(f"[bench] config2: {sv['closed_loop']['fits_per_s']:.4g} fits/s closed loop, "
               f"Poisson p50 {sv['poisson']['p50_latency_s'] * 1e3:.2f} ms p99 "
               f"{sv['poisson']['p99_latency_s'] * 1e3:.2f} ms; one-at-a-time adjoint "
-              f"{sv['one_at_a_time_adjoint']['fits_per_s']:.4g} fits/s, plain FD "
+              f"{sv['one_at_a_time_poisson']['fits_per_s']:.4g} fits/s (p50 "
+              f"{sv['one_at_a_time_poisson']['p50_latency_s'] * 1e3:.1f} ms), plain FD "
               f"{sv['one_at_a_time_fd']['fits_per_s']:.4g} fits/s", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.quick and not args.no_cpu:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         cpu = cpu_baseline(ev1_np[:, :100_000], desc1, th1)
+        extra["cpu_baselines"] = cpu_baselines_other()
 
     line = {
         "metric": "event-NLL(+grad) evals/sec vs plain; toy fits/sec with p50/p99 latency",

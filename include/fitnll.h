@@ -161,15 +161,22 @@ fn_status fn_events_check(fn_model* m, const double* ev, int64_t n, int64_t ld,
                           int64_t* n_bad, void* stream);
 
 /* NLL and, when grad_host != NULL, its gradient (P doubles), for host theta
- * (P doubles, copied before return).  Synchronous.  n may be 0 (NLL = 0). */
+ * (P doubles, copied before return): the objective a fit hands to the
+ * minimizer (Sec. 4, the FCN given to Minuit), whose cost is the independent
+ * evaluation of the density at every event (Sec. 1).  Synchronous.  n may be
+ * 0 (NLL = 0).  FN_E_INVALID for NULL theta, n < 0, NULL events with n > 0,
+ * or ld < n for a model with several observables. */
 fn_status fn_nll(fn_model* m, const double* theta_host, const double* ev, int64_t n,
                  int64_t ld, double* nll_host, double* grad_host, void* stream);
 
-/* Asynchronous form for device-resident loops: theta_dev (P doubles) and
+/* Asynchronous form of fn_nll for device-resident loops (the direct FCN
+ * access of Sec. 4 without a host round trip): theta_dev (P doubles) and
  * out_dev (1+P doubles: NLL then gradient; gradient entries untouched when
- * with_grad == 0) are device pointers.  No host synchronisation and no
- * allocation after the first call of a given size; non-finite results are
- * left in out_dev for the caller to inspect. */
+ * with_grad == 0) are device pointers, both read and written in stream
+ * order.  No host synchronisation; no allocation after the first call of a
+ * given size and kind (the first call may build the cached normalization
+ * matrix), after which the call can be captured into a graph.  Non-finite
+ * results are left in out_dev for the caller to inspect. */
 fn_status fn_nll_async(fn_model* m, const double* theta_dev, const double* ev, int64_t n,
                        int64_t ld, double* out_dev, int32_t with_grad, void* stream);
 
@@ -188,11 +195,18 @@ fn_status fn_nll_async(fn_model* m, const double* theta_dev, const double* ev, i
 fn_status fn_nll_binned(fn_model* m, const double* theta_host, const double* counts_dev, int64_t n_bins,
                         int32_t stat, double* value_host, double* grad_host, void* stream);
 
-/* Normalization integral I(theta) and, when dnorm_host != NULL, dI/dtheta. */
+/* Normalization integral I(theta) and, when dnorm_host != NULL, dI/dtheta
+ * (P doubles, host): the integral of P~ over the observable domain that
+ * makes the composed density a probability density (Sec. 1; by Monte Carlo
+ * over a phase-space sample for td4, Sec. 5).  theta_host: P doubles.
+ * Synchronous.  mix1d: I = 1 (each component normalized analytically). */
 fn_status fn_norm(fn_model* m, const double* theta_host, double* norm_host,
                   double* dnorm_host, void* stream);
 
-/* Normalized density P~(x_i)/I per event into p_dev (n doubles, device). */
+/* Normalized density P~(x_i)/I per event into p_dev (n doubles, device,
+ * caller-owned), the per-event function value of Sec. 1, for plots and tests.
+ * theta_host: P doubles.  Synchronous.  FN_E_INVALID for tddp3 models and
+ * for a NULL output with n > 0. */
 fn_status fn_eval(fn_model* m, const double* theta_host, const double* ev, int64_t n,
                   int64_t ld, double* p_dev, void* stream);
 
@@ -329,6 +343,36 @@ fn_status fn_batch_config(fn_batch* b, double tol, int32_t max_iter, int32_t use
  * returns the number of steps run and the slots still running. */
 fn_status fn_batch_run(fn_batch* b, int32_t max_steps, int32_t poll_every, int32_t* steps_done,
                        int32_t* n_running);
+/* Array form of fn_batch_set_slot (the paper's FitManager handed many fits of
+ * one PDF at once, Fig. 1 caption and Sec. 5): slots 0 .. n_fits-1 become
+ * fresh RUNNING fits with all parameters free, slots n_fits .. max_fits-1
+ * become IDLE.  Fit f reads n[f] device events at ev[f] (caller-owned, valid
+ * until the fit finishes or the batch is set again; ev and n are host arrays
+ * of n_fits entries); ld (host, may be NULL) gives each fit's leading
+ * dimension, which must be >= n[f] (a mix1d model has one observable, so it
+ * is only checked).  theta0_dev: device memory, n_fits x P start points,
+ * row-major; it must be ready (its producer synchronised) and is read before
+ * return.  Synchronous.  FN_E_INVALID for n_fits outside [0, max_fits], NULL
+ * pointers, event counts outside [1, max_events_per_fit] or ld < n. */
+fn_status fn_batch_set(fn_batch* b, int32_t n_fits, const double* const* ev, const int64_t* n, const int64_t* ld,
+                       const double* theta0_dev);
+/* One step of every running fit, enqueued on `stream` (the paper's direct
+ * access to the FCN from the caller's own loop, Sec. 4): NLL + gradient at
+ * each fit's trial point, then one BFGS / strong-Wolfe state-machine step.
+ * No host synchronisation, no allocation and no memset: when `stream` is
+ * being captured, the step's kernels are recorded into the caller's graph
+ * (replaying it steps the batch); otherwise the batch's own step graph is
+ * launched on `stream`.  Steps run on `stream` are ordered before later
+ * fn_batch_* calls on the same batch (which wait for them); a caller that
+ * replays a captured step synchronises its stream before reading status.
+ * The same sequence of steps gives bitwise the results of fn_batch_run. */
+fn_status fn_batch_step(fn_batch* b, void* stream);
+/* Per-fit status (FN_FIT_*), theta (max_fits x P), NLL and errors
+ * (max_fits x P: sqrt of the diagonal of the BFGS inverse-Hessian estimate,
+ * 0 for fixed parameters) into host arrays (any may be NULL) after the steps
+ * enqueued so far.  Synchronous. */
+fn_status fn_batch_status(fn_batch* b, int32_t* status_host, double* theta_host, double* nll_host,
+                          double* err_host);
 /* Per-slot results (host arrays of max_fits entries; any may be NULL):
  * status, theta (max_fits x P), nll, errors (sqrt of the diagonal of the BFGS
  * inverse-Hessian estimate; 0 for fixed parameters), iterations, evaluations. */
@@ -380,14 +424,26 @@ fn_status fn_generate(fn_model* m, const double* theta_host, uint32_t seed, uint
                       double envelope, double* ev_dev, int64_t ld, double* envelope_used, void* stream);
 
 /* ----------------------------------------------------------------- serving
- * A request loop over one batch: requests (toy-MC or systematic-variation
- * fits of a mix1d model) arrive at given times, are admitted at step
- * boundaries when a slot is free and their events fit the device-memory
- * budget, have their events generated on the device (or use caller events),
- * run inside the batch with the fits already on the GPU, and retire when
- * converged or failed, freeing slot and memory for queued requests
- * (continuous batching).  A request's result does not depend on which other
- * requests shared the batch. */
+ * A request loop over one batch: requests (toy-MC fits of a mix1d model, the
+ * paper's toy Monte Carlo studies, Sec. 5) arrive at given times, are
+ * admitted at step boundaries when a slot is free and their events fit the
+ * device-memory budget, have their events generated on the device (or use
+ * caller events), run inside the batch with the fits already on the GPU, and
+ * retire when converged or failed, freeing slot and memory for queued
+ * requests (continuous batching).  A request's result does not depend on
+ * which other requests shared the batch.
+ *
+ * Budget: every admitted, unfinished request is charged 8 * n_events bytes,
+ * whether its events are generated into the server's arena or owned by the
+ * caller; a request is admitted only while the charges stay within
+ * budget_bytes.  Admission follows arrival order with backfilling: a request
+ * that does not fit the free budget does not hold back later arrivals that
+ * do, until 256 requests have been admitted past it; then admission waits
+ * until it fits.  A request larger than the whole budget completes at once
+ * with status FN_E_BUDGET.
+ *
+ * Times: the server's clock starts with its first fn_server_run; arrival_s
+ * and the result times are seconds on that clock. */
 typedef struct fn_server fn_server;
 
 typedef struct {
@@ -397,7 +453,7 @@ typedef struct {
   const double* events;     /* optional caller-owned device events (n_events) */
   double theta_gen[4];      /* generation point (mu, sigma, tau, f) */
   double theta0[24];        /* start point, first P entries used */
-  double arrival_s;         /* arrival time, seconds after fn_server_run starts */
+  double arrival_s;         /* arrival time on the server clock */
 } fn_request;
 
 typedef struct {
@@ -406,7 +462,7 @@ typedef struct {
   int32_t iters, n_evals, pad;
   double nll;
   double theta[24], errors[24];
-  double t_arrival, t_admit, t_done;  /* seconds after the run started */
+  double t_arrival, t_admit, t_done;  /* server clock */
 } fn_result;
 
 /* Server over a mix1d model whose components are (gauss, exp) when events are
@@ -417,9 +473,12 @@ fn_status fn_server_create(fn_model* m, int32_t max_slots, int64_t max_events_pe
 fn_status fn_server_destroy(fn_server* s);
 /* Queue requests (copied). */
 fn_status fn_server_submit(fn_server* s, const fn_request* reqs, int32_t n);
-/* Serve every queued request (arrival times relative to the call), stepping
- * the batch poll_every steps between admission/retirement checks; stops early
- * after max_seconds (> 0).  Synchronous. */
+/* Serve every queued request, stepping the batch poll_every steps between
+ * admission/retirement checks, until none is queued or running; with
+ * max_seconds > 0 it returns after about that many seconds of this call
+ * instead, and fits still running keep their slots, memory and state for the
+ * next fn_server_run, which continues them.  *n_done: results so far.
+ * Synchronous. */
 fn_status fn_server_run(fn_server* s, int32_t poll_every, double max_seconds, int32_t* n_done);
 /* Results of finished requests, in completion order; *n_out <= max. */
 fn_status fn_server_results(fn_server* s, fn_result* out, int32_t max, int32_t* n_out);

@@ -67,6 +67,9 @@ PROTOTYPES = {
     "fn_batch_config": (i32, [vp, C.c_double, i32, i32]),
     "fn_batch_run": (i32, [vp, i32, i32, C.POINTER(i32), C.POINTER(i32)]),
     "fn_batch_results": (i32, [vp, C.POINTER(i32), dp, dp, dp, C.POINTER(i32), C.POINTER(i32)]),
+    "fn_batch_set": (i32, [vp, i32, C.POINTER(vp), C.POINTER(i64), C.POINTER(i64), vp]),
+    "fn_batch_step": (i32, [vp, vp]),
+    "fn_batch_status": (i32, [vp, C.POINTER(i32), dp, dp, dp]),
     "fn_generate_mix1d": (i32, [C.c_uint32, C.c_uint32, i64, dp, C.c_double, C.c_double, vp, vp]),
     "fn_generate": (i32, [vp, dp, C.c_uint32, C.c_uint32, i64, C.c_double, vp, i64, dp, vp]),
     "fn_model_autotune": (i32, [vp, dp, vp, i64, i64, i32, C.POINTER(i32), dp, vp]),

@@ -277,17 +277,19 @@ class Model:
 
 
 class NLLFunction(torch.autograd.Function):
-    """NLL as a differentiable function of theta (a float64 CPU tensor).
+    """NLL as a differentiable function of theta (a float64 tensor, CPU or
+    CUDA): ``NLLFunction.apply(theta, model, events)``.
 
-    forward runs the device NLL with the adjoint gradient; backward returns
-    grad_output times that gradient.
+    forward runs the device NLL with the adjoint gradient (fn_nll); backward
+    returns grad_output times that gradient.  The result and the gradient live
+    on theta's device.
     """
 
     @staticmethod
     def forward(ctx, theta: torch.Tensor, model: Model, events: torch.Tensor):
         v, g = model.nll(theta.detach().cpu().numpy(), events, grad=True)
-        ctx.save_for_backward(torch.from_numpy(g).to(theta.dtype))
-        return torch.tensor(v, dtype=theta.dtype)
+        ctx.save_for_backward(torch.from_numpy(g).to(device=theta.device, dtype=theta.dtype))
+        return torch.tensor(v, dtype=theta.dtype, device=theta.device)
 
     @staticmethod
     def backward(ctx, grad_out):
@@ -345,6 +347,44 @@ class Batch:
     def clear_slot(self, slot: int):
         check(self._lib.fn_batch_clear_slot(self._h, int(slot)))
         self._keep.pop(slot, None)
+
+    def set(self, events, theta0_dev: torch.Tensor):
+        """fn_batch_set: fit f of len(events) reads events[f] (a (1, n_f)
+        float64 CUDA tensor) from theta0_dev[f] (device, n_fits x P), all
+        parameters free; the remaining slots become idle."""
+        evs = list(events)
+        F = len(evs)
+        P = self.model.n_params
+        if F > 0:
+            assert theta0_dev.is_cuda and theta0_dev.dtype == torch.float64 and theta0_dev.is_contiguous()
+            assert theta0_dev.numel() >= F * P
+        ptrs = (C.c_void_p * max(F, 1))()
+        ns = (C.c_int64 * max(F, 1))()
+        lds = (C.c_int64 * max(F, 1))()
+        for f, ev in enumerate(evs):
+            p, n, ld = _events(ev, 1)
+            ptrs[f], ns[f], lds[f] = p.value, n, ld
+        torch.cuda.current_stream().synchronize()  # theta0_dev must be ready
+        check(self._lib.fn_batch_set(self._h, F, ptrs, ns, lds,
+                                     C.c_void_p(theta0_dev.data_ptr() if F > 0 else 0)))
+        self._keep = dict(enumerate(evs))
+
+    def step(self, stream=None):
+        """fn_batch_step: one NLL + gradient + BFGS step of every running fit,
+        enqueued on the stream (capturable into the caller's graph)."""
+        check(self._lib.fn_batch_step(self._h, _stream_ptr(stream)))
+
+    def status(self):
+        """fn_batch_status: (status, theta, nll, errors) per slot."""
+        n, P = self.max_fits, self.model.n_params
+        st = np.zeros(n, np.int32)
+        th = np.zeros((n, P))
+        nll = np.zeros(n)
+        er = np.zeros((n, P))
+        f64p = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+        check(self._lib.fn_batch_status(self._h, st.ctypes.data_as(C.POINTER(C.c_int32)), f64p(th), f64p(nll),
+                                        f64p(er)))
+        return st, th, nll, er
 
     def run(self, max_steps: int = 2000, poll_every: int = 8):
         done, running = C.c_int32(), C.c_int32()

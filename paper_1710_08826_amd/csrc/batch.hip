@@ -107,6 +107,34 @@ __global__ __launch_bounds__(kBlock) void batch_admit(const AdmitRec* __restrict
   if (v != v) atomicAdd(n_unresolved, 1u);
 }
 
+// fn_batch_set: workgroup f resets slot f -- a fresh fit at theta0[f] (all
+// parameters free) for f < n_fits, idle beyond; event pointers and counts are
+// copied separately.
+__global__ __launch_bounds__(kBlock) void batch_set_kernel(const double* __restrict__ theta0, int n_fits, int P,
+                                                           BatchDev b) {
+  const int f = blockIdx.x;
+  uint64_t* w = reinterpret_cast<uint64_t*>(b.st + f);
+  constexpr int kWords = (int)(sizeof(BfgsState) / sizeof(uint64_t));
+  for (int i = threadIdx.x; i < kWords; i += blockDim.x) w[i] = 0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (f < n_fits) {
+      BfgsState& st = b.st[f];
+      for (int i = 0; i < P; ++i) {
+        st.xt[i] = theta0[(int64_t)f * P + i];
+        st.mask[i] = 1;
+      }
+      st.status = kFitRunning;
+      st.phase = kPhaseStart;
+    }
+    b.stat[f] = f < n_fits ? kFitRunning : kFitIdle;
+  }
+}
+
+void batch_launch_set(const BatchDev& b, const double* theta0, int n_fits, int max_fits, int P, hipStream_t s) {
+  hipLaunchKernelGGL(batch_set_kernel, dim3((unsigned)max_fits), dim3(kBlock), 0, s, theta0, n_fits, P, b);
+}
+
 __global__ void batch_gather_rows(const double* __restrict__ rres, const int* __restrict__ slots, int n, int w,
                                   double* __restrict__ rows) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

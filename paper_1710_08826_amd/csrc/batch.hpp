@@ -47,6 +47,9 @@ struct AdmitRec {
 // workgroups [block0, block0 + ceil(n/256)), block0 ascending).
 void batch_launch_admit(const BatchDev& b, const AdmitRec* recs, int n_recs, int64_t gen_blocks, int P, double lo,
                         double hi, unsigned int* n_unresolved, hipStream_t s);
+// Slots [0, n_fits) become fresh fits at theta0 (device, n_fits x P, all
+// parameters free), slots [n_fits, max_fits) idle; one workgroup per slot.
+void batch_launch_set(const BatchDev& b, const double* theta0, int n_fits, int max_fits, int P, hipStream_t s);
 // rows_out[i] = rres row of slot slots[i] (3 + 2P doubles), for n slots.
 void batch_launch_gather_rows(const BatchDev& b, const int* slots, int n, int P, double* rows_out, hipStream_t s);
 

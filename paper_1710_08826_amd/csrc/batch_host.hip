@@ -23,6 +23,8 @@ struct fn_batch {
   bool use_graph = true;
   hipStream_t stream = nullptr;
   hipGraphExec_t exec = nullptr;
+  hipEvent_t step_done = nullptr;  // recorded after each fn_batch_step outside a capture
+  bool step_pending = false;
   DevBuf st, tabs, evp, nev, item_base, part_base, part, out, nrun, stat, rres;
   DevBuf adm, fin_slots, fin_rows;  // serving: admission records, finished-slot list and gathered rows
   // pinned staging of per-slot inputs (stable sources for async copies)
@@ -52,6 +54,7 @@ struct fn_batch {
   }
   ~fn_batch() {
     drop_graph();
+    if (step_done) (void)hipEventDestroy(step_done);
     if (stream) (void)hipStreamDestroy(stream);
     if (h_st) (void)hipHostFree(h_st);
     if (h_ev) (void)hipHostFree(h_ev);
@@ -68,23 +71,37 @@ static void* pinned(size_t bytes) {
   return p;
 }
 
+// The step graph (the five step launches captured once on the batch stream).
+static hipGraphExec_t step_graph(fn_batch* b) {
+  if (!b->exec) {
+    hipGraph_t g = nullptr;
+    hip_check(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    batch_launch_step(b->dev(), b->m->mix, b->max_fits, b->P, b->chunk, b->eval_grid, b->tol, b->max_iter,
+                      b->stream);
+    hip_check(hipStreamEndCapture(b->stream, &g), "hipStreamEndCapture");
+    const hipError_t e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    hip_check(e, "hipGraphInstantiate");
+  }
+  return b->exec;
+}
+
 static void step(fn_batch* b) {
   if (b->use_graph) {
-    if (!b->exec) {
-      hipGraph_t g = nullptr;
-      hip_check(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-      batch_launch_step(b->dev(), b->m->mix, b->max_fits, b->P, b->chunk, b->eval_grid, b->tol, b->max_iter,
-                        b->stream);
-      hip_check(hipStreamEndCapture(b->stream, &g), "hipStreamEndCapture");
-      const hipError_t e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      hip_check(e, "hipGraphInstantiate");
-    }
-    hip_check(hipGraphLaunch(b->exec, b->stream), "hipGraphLaunch");
+    hip_check(hipGraphLaunch(step_graph(b), b->stream), "hipGraphLaunch");
   } else {
     batch_launch_step(b->dev(), b->m->mix, b->max_fits, b->P, b->chunk, b->eval_grid, b->tol, b->max_iter,
                       b->stream);
     hip_check(hipGetLastError(), "kernel launch");
+  }
+}
+
+// Work on the batch stream starts after the steps fn_batch_step enqueued on
+// caller streams.
+static void after_caller_steps(fn_batch* b) {
+  if (b->step_pending) {
+    hip_check(hipStreamWaitEvent(b->stream, b->step_done, 0), "hipStreamWaitEvent");
+    b->step_pending = false;
   }
 }
 
@@ -151,6 +168,7 @@ fn_status fn_batch_create(fn_model* m, int32_t max_fits, int64_t max_events_per_
 fn_status fn_batch_destroy(fn_batch* b) {
   return guard([&] {
     if (b) {
+      if (b->step_pending) (void)hipEventSynchronize(b->step_done);
       (void)hipStreamSynchronize(b->stream);
       delete b;
     }
@@ -163,6 +181,9 @@ fn_status fn_batch_config(fn_batch* b, double tol, int32_t max_iter, int32_t use
     b->tol = tol > 0.0 ? tol : 1e-7;
     b->max_iter = max_iter > 0 ? max_iter : 500;
     b->use_graph = use_graph != 0;
+    // a step graph launched on a caller stream may still run
+    if (b->step_pending) hip_check(hipEventSynchronize(b->step_done), "hipEventSynchronize");
+    b->step_pending = false;
     b->drop_graph();
   });
 }
@@ -175,6 +196,7 @@ fn_status fn_batch_set_slot(fn_batch* b, int32_t slot, const double* ev, int64_t
     if (n < 1 || n > b->max_ev) throw Error(FN_E_INVALID, "event count must be in [1, max_events_per_fit]");
     if (!ev) throw Error(FN_E_INVALID, "events pointer is NULL");
     hip_check(hipSetDevice(b->m->device), "hipSetDevice");
+    after_caller_steps(b);
     // the previous copy out of this staging entry must have completed
     hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
     BfgsState& s = b->h_st[slot];
@@ -206,6 +228,7 @@ fn_status fn_batch_clear_slot(fn_batch* b, int32_t slot) {
     if (!b) throw Error(FN_E_INVALID, "batch is NULL");
     if (slot < 0 || slot >= b->max_fits) throw Error(FN_E_INVALID, "slot out of range");
     hip_check(hipSetDevice(b->m->device), "hipSetDevice");
+    after_caller_steps(b);
     hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
     // status lives at a fixed offset: write only that int
     b->h_st[slot].status = kFitIdle;
@@ -224,6 +247,7 @@ fn_status fn_batch_run(fn_batch* b, int32_t max_steps, int32_t poll_every, int32
   return guard([&] {
     if (!b) throw Error(FN_E_INVALID, "batch is NULL");
     hip_check(hipSetDevice(b->m->device), "hipSetDevice");
+    after_caller_steps(b);
     if (poll_every < 1) poll_every = 1;
     int done = 0;
     int running = -1;
@@ -247,6 +271,7 @@ fn_status fn_batch_results(fn_batch* b, int32_t* status, double* theta, double* 
   return guard([&] {
     if (!b) throw Error(FN_E_INVALID, "batch is NULL");
     hip_check(hipSetDevice(b->m->device), "hipSetDevice");
+    after_caller_steps(b);
     std::vector<BfgsState> hs(b->max_fits);
     hip_check(hipMemcpyAsync(hs.data(), b->st.ptr, sizeof(BfgsState) * b->max_fits, hipMemcpyDeviceToHost,
                              b->stream),
@@ -266,6 +291,66 @@ fn_status fn_batch_results(fn_batch* b, int32_t* status, double* theta, double* 
       if (n_evals) n_evals[f] = s.n_eval;
     }
   });
+}
+
+fn_status fn_batch_set(fn_batch* b, int32_t n_fits, const double* const* ev, const int64_t* n, const int64_t* ld,
+                       const double* theta0_dev) {
+  return guard([&] {
+    if (!b) throw Error(FN_E_INVALID, "batch is NULL");
+    if (n_fits < 0 || n_fits > b->max_fits) throw Error(FN_E_INVALID, "n_fits must be in [0, max_fits]");
+    if (n_fits > 0 && (!ev || !n || !theta0_dev)) throw Error(FN_E_INVALID, "NULL argument");
+    for (int f = 0; f < n_fits; ++f) {
+      if (n[f] < 1 || n[f] > b->max_ev)
+        throw Error(FN_E_INVALID, "fit " + std::to_string(f) + ": event count must be in [1, max_events_per_fit]");
+      if (!ev[f]) throw Error(FN_E_INVALID, "fit " + std::to_string(f) + ": events pointer is NULL");
+      if (ld && ld[f] < n[f]) throw Error(FN_E_INVALID, "fit " + std::to_string(f) + ": ld must be >= n");
+    }
+    hip_check(hipSetDevice(b->m->device), "hipSetDevice");
+    after_caller_steps(b);
+    // the staging arrays may still feed an earlier copy
+    hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    for (int f = 0; f < b->max_fits; ++f) {
+      b->h_ev[f] = f < n_fits ? ev[f] : nullptr;
+      b->h_nev[f] = f < n_fits ? n[f] : 0;
+    }
+    hip_check(hipMemcpyAsync(b->evp.ptr, b->h_ev, sizeof(double*) * b->max_fits, hipMemcpyHostToDevice, b->stream),
+              "hipMemcpyAsync");
+    hip_check(hipMemcpyAsync(b->nev.ptr, b->h_nev, sizeof(int64_t) * b->max_fits, hipMemcpyHostToDevice, b->stream),
+              "hipMemcpyAsync");
+    batch_launch_set(b->dev(), theta0_dev, n_fits, b->max_fits, b->P, b->stream);
+    hip_check(hipGetLastError(), "kernel launch");
+    hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+  });
+}
+
+fn_status fn_batch_step(fn_batch* b, void* stream) {
+  return guard([&] {
+    if (!b) throw Error(FN_E_INVALID, "batch is NULL");
+    hip_check(hipSetDevice(b->m->device), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hip_check(hipStreamIsCapturing(s, &cs), "hipStreamIsCapturing");
+    if (cs == hipStreamCaptureStatusActive) {
+      // recorded into the caller's graph: the step's kernels themselves
+      batch_launch_step(b->dev(), b->m->mix, b->max_fits, b->P, b->chunk, b->eval_grid, b->tol, b->max_iter, s);
+      hip_check(hipGetLastError(), "kernel launch");
+      return;
+    }
+    if (b->use_graph) {
+      hip_check(hipGraphLaunch(step_graph(b), s), "hipGraphLaunch");
+    } else {
+      batch_launch_step(b->dev(), b->m->mix, b->max_fits, b->P, b->chunk, b->eval_grid, b->tol, b->max_iter, s);
+      hip_check(hipGetLastError(), "kernel launch");
+    }
+    if (!b->step_done) hip_check(hipEventCreateWithFlags(&b->step_done, hipEventDisableTiming), "hipEventCreate");
+    hip_check(hipEventRecord(b->step_done, s), "hipEventRecord");
+    b->step_pending = true;
+  });
+}
+
+fn_status fn_batch_status(fn_batch* b, int32_t* status_host, double* theta_host, double* nll_host,
+                          double* err_host) {
+  return fn_batch_results(b, status_host, theta_host, nll_host, err_host, nullptr, nullptr);
 }
 
 fn_status fn_generate_mix1d(uint32_t seed, uint32_t fit, int64_t n, const double* theta_gen, double lo, double hi,

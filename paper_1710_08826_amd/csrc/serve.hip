@@ -1,11 +1,18 @@
 // Continuous-batching request loop over one fn_batch (fn_server_*).
 //
 // Loop: admit visible requests into free slots while their events fit the
-// device-memory budget (first-fit arena, no hipMalloc/hipFree in the loop),
-// generate their events on the batch stream, advance the batch poll_every
-// steps, read the per-slot status mirror, retire finished fits (result rows,
-// timestamps, arena space and slot released), repeat.  New requests join at
-// step boundaries while earlier ones are still running.
+// device-memory budget (first-fit arena for generated events, caller-owned
+// events charged by size; no hipMalloc/hipFree in the loop), generate their
+// events on the batch stream, advance the batch poll_every steps, read the
+// per-slot status mirror, retire finished fits (result rows, timestamps,
+// arena space, budget and slot released), repeat.  New requests join at step
+// boundaries while earlier ones are still running.
+//
+// Admission order: arrival order, with backfilling -- a request whose events
+// do not fit the free budget does not stop later (smaller) arrivals from
+// being admitted, until kMaxBypass requests have been admitted past it; from
+// then on nothing more is admitted until it fits, so a large request cannot
+// be starved by a stream of small ones.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -69,10 +76,14 @@ class Arena {
 
 struct Pending {
   fn_request r;
-  int64_t off = -1;
-  int64_t bytes = 0;
+  int64_t off = -1;     // arena offset of generated events (-1: caller events)
+  int64_t bytes = 0;    // budget charge: the request's event bytes
   double t_admit = -1.0;
+  int bypassed = 0;     // requests admitted past this one while it was blocked
 };
+
+// Requests admitted past a blocked one before admission waits for it.
+constexpr int kMaxBypass = 256;
 
 }  // namespace
 
@@ -83,11 +94,14 @@ struct fn_server {
   int P = 0;
   int64_t max_ev = 0;
   int64_t budget = 0;
+  int64_t in_use = 0;                   // budget charged by admitted, unfinished requests
   DevBuf arena_mem;
   Arena arena;
   DevBuf gen_count;
-  std::vector<Pending> queue;           // submitted, not yet admitted
-  std::vector<int> slot_req;            // slot -> index into running, -1 free
+  bool started = false;                 // server clock: starts with the first fn_server_run
+  std::chrono::steady_clock::time_point t0;
+  std::vector<Pending> queue;           // submitted, not yet admitted (sorted by arrival)
+  std::vector<int> slot_req;            // slot -> 1 while a request runs in it, -1 free
   std::vector<int> free_slots;          // stack of free slots
   std::vector<Pending> running;         // by slot
   std::vector<fn_result> done;
@@ -161,23 +175,37 @@ fn_status fn_server_run(fn_server* s, int32_t poll_every, double max_seconds, in
     if (poll_every < 1) poll_every = 1;
     const Mix1dConst& mc = s->m->mix;
     const bool can_generate = mc.K == 2 && mc.type[0] == kGauss && mc.type[1] == kExp;
-    const auto t0 = std::chrono::steady_clock::now();
-    auto now = [&] { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
+    if (!s->started) {
+      s->t0 = std::chrono::steady_clock::now();
+      s->started = true;
+    }
+    const auto t_call = std::chrono::steady_clock::now();
+    auto now = [&] { return std::chrono::duration<double>(std::chrono::steady_clock::now() - s->t0).count(); };
+    auto call_s = [&] { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t_call).count(); };
     const int W = 3 + 2 * s->P;
-    size_t next = 0;  // queue is sorted by arrival
+    // fits still running from an earlier call that stopped on max_seconds
     int n_running = 0;
+    for (int k = 0; k < s->slots; ++k) n_running += s->slot_req[k] >= 0;
     std::vector<int> fin_slots;
+    std::vector<char> taken;
     while (true) {
+      if (max_seconds > 0.0 && call_s() > max_seconds) break;
       const double t = now();
-      if (max_seconds > 0.0 && t > max_seconds) break;
-      // admission: arrivals visible now, free slot, budget; the round's
+      // admission: arrivals visible now, in arrival order with backfilling,
+      // while a slot is free and the events fit the budget; the round's
       // records go to the device in one copy and one launch (state reset,
       // status, event pointers, event generation)
       int n_adm = 0;
       int64_t gen_blocks = 0;
-      while (next < s->queue.size() && s->queue[next].r.arrival_s <= t) {
-        Pending& p = s->queue[next];
-        if (p.bytes > s->budget) {
+      taken.assign(s->queue.size(), 0);
+      Pending* blocked = nullptr;  // earliest arrival that did not fit
+      for (size_t i = 0; i < s->queue.size() && !s->free_slots.empty(); ++i) {
+        Pending& p = s->queue[i];
+        if (p.r.arrival_s > t) break;
+        const double* ev = p.r.events;
+        const bool gen = ev == nullptr;
+        // generated events take whole 256-byte arena units
+        if ((gen ? (p.bytes + 255) & ~int64_t(255) : p.bytes) > s->budget) {
           fn_result r;
           std::memset(&r, 0, sizeof(r));
           r.id = p.r.id;
@@ -185,19 +213,31 @@ fn_status fn_server_run(fn_server* s, int32_t poll_every, double max_seconds, in
           r.t_arrival = p.r.arrival_s;
           r.t_admit = r.t_done = t;
           s->done.push_back(r);
-          ++next;
+          taken[i] = 1;
           continue;
         }
-        if (s->free_slots.empty()) break;
-        const int slot = s->free_slots.back();
-        const double* ev = p.r.events;
-        const bool gen = ev == nullptr;
-        if (gen) {
-          if (!can_generate) throw Error(FN_E_INVALID, "generation needs a (gauss, exp) mixture model");
-          p.off = s->arena.alloc(p.bytes);
-          if (p.off < 0) break;  // wait for memory to free up
-          ev = (const double*)((char*)s->arena_mem.ptr + p.off);
+        if (gen && !can_generate) throw Error(FN_E_INVALID, "generation needs a (gauss, exp) mixture model");
+        bool fits = s->in_use + p.bytes <= s->budget;
+        int64_t off = -1;
+        if (fits && gen) {
+          off = s->arena.alloc(p.bytes);
+          fits = off >= 0;
         }
+        if (!fits) {
+          if (!blocked) blocked = &p;
+          continue;
+        }
+        if (blocked) {
+          if (blocked->bypassed >= kMaxBypass) {
+            if (off >= 0) s->arena.release(off, p.bytes);
+            break;  // wait for the starved request
+          }
+          ++blocked->bypassed;
+        }
+        if (gen) ev = (const double*)((char*)s->arena_mem.ptr + off);
+        p.off = off;
+        s->in_use += p.bytes;
+        const int slot = s->free_slots.back();
         s->free_slots.pop_back();
         AdmitRec& a = s->h_adm[n_adm++];
         a.slot = slot;
@@ -214,13 +254,21 @@ fn_status fn_server_run(fn_server* s, int32_t poll_every, double max_seconds, in
         s->running[slot] = p;
         s->slot_req[slot] = 1;
         ++n_running;
-        ++next;
+        taken[i] = 1;
+      }
+      if (std::find(taken.begin(), taken.end(), 1) != taken.end()) {
+        size_t w = 0;
+        for (size_t i = 0; i < s->queue.size(); ++i)
+          if (!taken[i]) s->queue[w++] = s->queue[i];
+        s->queue.resize(w);
       }
       batch_admit_async(s->b, s->h_adm, n_adm, gen_blocks, mc.lo, mc.hi, (unsigned int*)s->gen_count.ptr);
       if (n_running == 0) {
-        if (next >= s->queue.size()) break;
-        // idle until the next arrival
-        const double wait = s->queue[next].r.arrival_s - now();
+        if (s->queue.empty()) break;
+        // idle until the next arrival (a request that is still waiting here
+        // has arrived and fits once nothing runs, so only a future arrival
+        // can be pending)
+        const double wait = s->queue.front().r.arrival_s - now();
         if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(std::min(wait, 1e-3)));
         continue;
       }
@@ -253,14 +301,15 @@ fn_status fn_server_run(fn_server* s, int32_t poll_every, double max_seconds, in
           r.t_done = td;
           s->done.push_back(r);
           if (p.off >= 0) s->arena.release(p.off, p.bytes);
+          s->in_use -= p.bytes;
           s->slot_req[k] = -1;
           s->free_slots.push_back(k);
           --n_running;
         }
       }
     }
-    // drop what was admitted (their results are in `done`)
-    s->queue.erase(s->queue.begin(), s->queue.begin() + next);
+    // Requests admitted but unfinished when max_seconds ran out keep their
+    // slots, memory and device state; the next fn_server_run continues them.
     if (n_done) *n_done = (int32_t)s->done.size();
   });
 }

@@ -123,3 +123,81 @@ def test_invalid_start_fails_cleanly(model):
     b.run(2000, 4)
     r = b.results()
     assert r.status[0] == 3 and r.status[1] == 2
+
+
+def _set_all(b, evs, start):
+    th0 = torch.from_numpy(np.tile(start, (len(evs), 1))).cuda().contiguous()
+    b.set(evs, th0)
+
+
+def test_batch_step_matches_run(model):
+    """fn_batch_set + fn_batch_step on a caller stream, one step at a time,
+    reach bitwise the results of fn_batch_set_slot + fn_batch_run; slots
+    beyond n_fits stay idle."""
+    from paper_1710_08826_amd import Batch
+    sizes = [12_000, 3_000, 50_000, 1_000, 777]
+    evs = _events(sizes, seed=905)
+    ref = Batch(model, 6, max(sizes))
+    for i, e in enumerate(evs):
+        ref.set_slot(i, e, START)
+    steps, running = ref.run(3000, 1)
+    assert running == 0
+    r = ref.results()
+    b = Batch(model, 6, max(sizes))
+    _set_all(b, evs, START)
+    st, _, _, _ = b.status()
+    assert list(st) == [1, 1, 1, 1, 1, 0]
+    s = torch.cuda.Stream()
+    for k in range(steps):
+        b.step(stream=s)
+        if k % 50 == 0:
+            st, _, _, _ = b.status()  # waits for the steps enqueued so far
+    st, th, nll, er = b.status()
+    say("steps", steps, "status", st)
+    assert np.array_equal(st, r.status) and np.array_equal(th, r.theta) and np.array_equal(nll, r.nll)
+    assert np.array_equal(er, r.errors)
+
+
+def test_batch_step_in_caller_graph(model):
+    """A step captured into the caller's graph (fn_batch_step on a capturing
+    stream) and replayed, with eager work and synchronisations between the
+    replays, advances the batch exactly as eager steps of an identical batch:
+    every replay is checked against the eager batch, bitwise."""
+    from paper_1710_08826_amd import Batch
+    sizes = [9_000, 30_000, 2_000]
+    evs = _events(sizes, seed=906)
+    eager = Batch(model, 3, max(sizes))
+    graphed = Batch(model, 3, max(sizes))
+    _set_all(eager, evs, START)
+    _set_all(graphed, evs, START)
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=s, capture_error_mode="thread_local"):
+        graphed.step(stream=s)
+    # capturing recorded the kernels without running them
+    assert np.array_equal(graphed.status()[1], eager.status()[1])
+    scratch = torch.ones(1 << 20, dtype=torch.float64, device="cuda")
+    for k in range(40):
+        eager.step()
+        g.replay()
+        scratch.mul_(1.0000001).sum()  # eager work between replays
+        torch.cuda.synchronize()
+        a, b = eager.status(), graphed.status()
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y), k
+    say("after 40 steps", eager.status()[0])
+
+
+def test_batch_set_rejects_bad_arguments(model):
+    from paper_1710_08826_amd import Batch
+    from paper_1710_08826_amd._lib import FitNLLError
+    evs = _events([1_000, 2_000], seed=907)
+    b = Batch(model, 2, 1_500)
+    th0 = torch.from_numpy(np.tile(START, (2, 1))).cuda()
+    with pytest.raises(FitNLLError):
+        b.set(evs, th0)  # 2000 events > max_events_per_fit
+    with pytest.raises(FitNLLError):
+        b.set(evs[:1] * 3, torch.from_numpy(np.tile(START, (3, 1))).cuda())  # more fits than slots
+    b.set([], th0)
+    assert (b.status()[0] == 0).all()
