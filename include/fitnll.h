@@ -180,6 +180,28 @@ fn_status fn_nll(fn_model* m, const double* theta_host, const double* ev, int64_
 fn_status fn_nll_async(fn_model* m, const double* theta_dev, const double* ev, int64_t n,
                        int64_t ld, double* out_dev, int32_t with_grad, void* stream);
 
+/* fn_nll_async without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc).  Same arguments, kernels and results as
+ * fn_nll_async (bitwise), but the partial rows of the call (the events
+ * pass's level-1 rows, and on the first call of a model whose cached
+ * normalization is not built yet, or every call of a free-lineshape dalitz3
+ * model, the normalization's rows) live in a static device array of the
+ * library: 2^21 doubles (16 MiB) per device, whose address is looked up
+ * when the device's context is created and which is held until the process
+ * ends.  The call makes no hipMalloc, hipFree or other allocating call;
+ * every row it reads was written earlier in the same call, so nothing needs
+ * clearing between calls.  The array is shared by every call on one device:
+ * calls that overlap on one device (different streams, models or host
+ * threads) race and give wrong results; serialise them.  The event pass is
+ * never timed by fn_model_timing.  FN_E_INVALID as fn_nll_async, and when
+ * the rows do not fit (about 2^21 / (1 + P) chunks of the model's chunk
+ * size: 123k chunks, 250M events at 2048 per chunk, for a 16-parameter
+ * dalitz3 gradient); nothing is enqueued then except, possibly, the
+ * parameter prologue. */
+fn_status fn_nll_async_noalloc(fn_model* m, const double* theta_dev, const double* ev, int64_t n,
+                               int64_t ld, double* out_dev, int32_t with_grad, void* stream);
+
 /* Binned data of a mix1d model (the paper's binned DataSet, Fig. 1 and
  * Sec. 4): counts_dev holds n_bins >= 1 counts (device doubles, finite and
  * >= 0) of uniform bins on [lo, hi].  The expected count of bin b is

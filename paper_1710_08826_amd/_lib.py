@@ -46,6 +46,7 @@ PROTOTYPES = {
     "fn_events_check": (i32, [vp, vp, i64, i64, C.POINTER(i64), vp]),
     "fn_nll": (i32, [vp, dp, vp, i64, i64, dp, dp, vp]),
     "fn_nll_async": (i32, [vp, vp, vp, i64, i64, vp, i32, vp]),
+    "fn_nll_async_noalloc": (i32, [vp, vp, vp, i64, i64, vp, i32, vp]),
     "fn_norm": (i32, [vp, dp, dp, dp, vp]),
     "fn_eval": (i32, [vp, dp, vp, i64, i64, vp, vp]),
     "fn_model_set_norm_sample": (i32, [vp, vp, i64, i64, vp]),

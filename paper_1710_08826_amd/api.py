@@ -117,6 +117,17 @@ class Model:
                                      C.c_void_p(out_dev.data_ptr()), 1 if with_grad else 0,
                                      _stream_ptr(stream)))
 
+    def nll_async_noalloc(self, theta_dev: torch.Tensor, events: torch.Tensor, out_dev: torch.Tensor,
+                          with_grad: bool = True, stream=None):
+        """nll_async whose partial rows live in the library's static scratch
+        array: no allocation; calls on one device must not overlap."""
+        evp, n, ld = _events(events, self.n_obs)
+        assert theta_dev.is_cuda and theta_dev.dtype == torch.float64 and theta_dev.numel() >= self.n_params
+        assert out_dev.is_cuda and out_dev.dtype == torch.float64 and out_dev.numel() >= 1 + self.n_params
+        check(self._lib.fn_nll_async_noalloc(self._h, C.c_void_p(theta_dev.data_ptr()), evp, n, ld,
+                                             C.c_void_p(out_dev.data_ptr()), 1 if with_grad else 0,
+                                             _stream_ptr(stream)))
+
     def norm(self, theta, stream=None):
         """(I, dI/dtheta)."""
         th, thp = self._theta(theta)

@@ -43,6 +43,7 @@ enum ModelKind : int { kKindMix1d = 1, kKindDalitz3 = 2, kKindTd4 = 3, kKindTddp
 
 struct fn_ctx {
   int device = 0;
+  double* scratch = nullptr;  // this device's copy of the library's static scratch array
 };
 
 struct fn_model {
@@ -112,8 +113,18 @@ struct fn_model {
 };
 
 namespace fn {
+// A caller-provided device region for the partial rows of one NLL call
+// (sizes in doubles): the events pass takes its rows from the front, the
+// normalization from the back; a request that does not fit throws.
+struct Workspace {
+  double* base = nullptr;
+  size_t cap = 0;
+  size_t front = 0, back = 0;
+  double* take_front(size_t count);
+  double* take_back(size_t count);
+};
 void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const double* ev, int64_t n, int64_t ld,
-             bool grad, double* out_user, hipStream_t s);
+             bool grad, double* out_user, hipStream_t s, Workspace* ws = nullptr);
 void nll_host(fn_model* m, const double* theta_host, const double* ev, int64_t n, int64_t ld, double* nll,
               double* grad, hipStream_t s);
 void check_events_args(fn_model* m, const double* ev, int64_t n, int64_t ld);

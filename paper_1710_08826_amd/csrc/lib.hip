@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -32,6 +33,31 @@ constexpr uint32_t kPhaseSpaceStream0 = 100;
 constexpr int kTuneChunks[] = {256, 512, 1024, 2048, 4096, 8192, 16384};
 constexpr int kTuneCount = (int)(sizeof(kTuneChunks) / sizeof(kTuneChunks[0]));
 constexpr double kTuneTie = 0.02;  // relative time difference treated as a tie
+
+// Scratch of the allocation-free NLL entry point (fn_nll_async_noalloc): the
+// partial rows of one call, 2^21 doubles (16 MiB) on every device the library
+// runs on, held until the process ends.  In host code `scratch` names a
+// host-side stand-in; kernels get this device's address, taken once per
+// device when its context is created.
+constexpr size_t kScratchDoubles = size_t(1) << 21;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+void hip_check(hipError_t e, const char* what);
+
+// Device address of `scratch` on the current device (looked up on first use).
+static double* scratch_address(int device) {
+  static std::mutex mu;
+  static std::vector<double*> addr;
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)addr.size() <= device) addr.resize((size_t)device + 1, nullptr);
+  if (!addr[device]) {
+    void* p = nullptr;
+    hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!p) throw Error(FN_E_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+    addr[device] = (double*)p;
+  }
+  return addr[device];
+}
 
 static thread_local std::string g_last_error;
 
@@ -362,24 +388,62 @@ static void compile_td4(const json::Value& d, fn_model* m, bool device = true) {
 // ------------------------------------------------------------ pipeline
 static int64_t nchunks_for(int64_t n, int chunk) { return (n + chunk - 1) / chunk; }
 
+double* Workspace::take_front(size_t count) {
+  if (count > cap - front - back)
+    throw Error(FN_E_INVALID, "the call needs " + std::to_string(front + back + count) +
+                                  " doubles of scratch, more than the " + std::to_string(cap) + " available");
+  double* p = base + front;
+  front += count;
+  return p;
+}
+double* Workspace::take_back(size_t count) {
+  if (count > cap - front - back)
+    throw Error(FN_E_INVALID, "the call needs " + std::to_string(front + back + count) +
+                                  " doubles of scratch, more than the " + std::to_string(cap) + " available");
+  back += count;
+  return base + (cap - back);
+}
+
 void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const double* ev, int64_t n, int64_t ld,
-             bool grad, double* out_user, hipStream_t s) {
+             bool grad, double* out_user, hipStream_t s, Workspace* ws) {
   const int64_t nch = nchunks_for(n, m->chunk);
+  // level-1 partial rows of the events pass, and the normalization's partial
+  // rows: model-owned buffers, or the front and the back of a workspace
+  double* part = nullptr;
+  double* npart = nullptr;
+  auto events_rows = [&](size_t doubles) {
+    if (ws) {
+      part = ws->take_front(doubles);
+    } else {
+      m->d_part.reserve(sizeof(double) * doubles);
+      part = m->part();
+    }
+  };
+  auto norm_rows = [&](size_t doubles) {
+    if (ws) {
+      npart = ws->take_back(doubles);
+    } else {
+      m->d_npart.reserve(sizeof(double) * doubles);
+      npart = m->npart();
+    }
+  };
+  // workspace calls are never timed: timing takes HIP events from a pool
+  const bool launches = nch > 0 && !ws;
   if (m->kind == kKindMix1d) {
     const Mix1dConst& mc = m->mix;
     const int kmax = mix1d_kmax(mc.K);
     const int nv = mix1d_nv(kmax, grad);
-    m->d_part.reserve(sizeof(double) * (size_t)(nch > 0 ? nch : 1) * nv);
+    events_rows((size_t)(nch > 0 ? nch : 1) * nv);
     ParamBlock zero;
     mix1d_launch_prologue(mc, pb ? *pb : zero, pb ? nullptr : theta_dev, 1, 0, m->table_mix(), s);
-    m->timed(nch > 0, [&](hipEvent_t t0, hipEvent_t t1) {
-      mix1d_launch_events(mc, m->table_mix(), ev, n, m->chunk, nch, grad, m->part(), s, t0, t1);
+    m->timed(launches, [&](hipEvent_t t0, hipEvent_t t1) {
+      mix1d_launch_events(mc, m->table_mix(), ev, n, m->chunk, nch, grad, part, s, t0, t1);
     });
-    mix1d_launch_finalize(mc, m->table_mix(), m->part(), nch, grad, (double)n, m->out(), out_user, s);
+    mix1d_launch_finalize(mc, m->table_mix(), part, nch, grad, (double)n, m->out(), out_user, s);
   } else if (m->kind == kKindTddp3) {
     const DalitzConst& dc = m->dal;
     const int nv = tddp_nv(dc.K, grad);
-    m->d_part.reserve(sizeof(double) * (size_t)(nch > 0 ? nch : 1) * nv);
+    events_rows((size_t)(nch > 0 ? nch : 1) * nv);
     if (pb || !m->table_ready) {
       ParamBlock zero;
       dalitz_launch_prologue(dc, pb ? *pb : zero, pb ? nullptr : theta_dev, m->fixed(), 1, 0, m->table_dal(), s);
@@ -393,44 +457,44 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
     if (!m->M_valid) {
       const int64_t ncell = (int64_t)dc.nx * dc.ny;
       const int64_t mrows = nchunks_for(ncell, m->grid_chunk);
-      m->d_npart.reserve(sizeof(double) * (size_t)mrows * 2 * kMRowBlock * dc.K);
-      tddp_launch_mmatrices(*m->tddp_jit, dc, m->table_dal(), m->grid_chunk, m->npart(), m->Mc(), s);
+      norm_rows((size_t)mrows * 2 * kMRowBlock * dc.K);
+      tddp_launch_mmatrices(*m->tddp_jit, dc, m->table_dal(), m->grid_chunk, npart, m->Mc(), s);
       m->M_valid = true;
     }
-    m->timed(nch > 0, [&](hipEvent_t t0, hipEvent_t t1) {
+    m->timed(launches, [&](hipEvent_t t0, hipEvent_t t1) {
       tddp_launch_events(*m->tddp_jit, dc, m->table_dal(), m->tdt, coef, ev, ld, n, m->chunk, nch, grad,
-                         m->part(), s, t0, t1);
+                         part, s, t0, t1);
     });
-    tddp_launch_finalize(dc, m->table_dal(), m->tdt, coef, m->part(), nch, grad, m->Mc(), (double)n, m->out(),
+    tddp_launch_finalize(dc, m->table_dal(), m->tdt, coef, part, nch, grad, m->Mc(), (double)n, m->out(),
                          out_user, s);
   } else if (m->kind == kKindTd4) {
     const Td4Const& tc = m->td4;
     if (m->n_mc <= 0) throw Error(FN_E_INVALID, "td4: normalization sample not set (fn_model_set_norm_sample)");
     const int kmax = td4_kmax(tc.K);
-    m->d_part.reserve(sizeof(double) * (size_t)(nch > 0 ? nch : 1) * td4_nv(kmax, grad));
+    events_rows((size_t)(nch > 0 ? nch : 1) * td4_nv(kmax, grad));
     const Td4FitConst* fc = (const Td4FitConst*)m->d_fixed.ptr;
     td4_launch_prologue(tc, pb, theta_dev, m->P, fc, nullptr, 1, m->table_td4(), s);
     if (!m->M_valid) {
       const int mchunk = 1024;
       const int64_t mrows = nchunks_for(m->n_mc, mchunk);
-      m->d_npart.reserve(sizeof(double) * (size_t)mrows * 8 * kmax);
+      norm_rows((size_t)mrows * 8 * kmax);
       td4_launch_mmatrix(*m->td4_jit, tc, m->table_td4(), 1, (const double*)m->d_mc.ptr, m->n_mc, m->n_mc, mchunk,
-                         m->npart(),
+                         npart,
                          m->Mc(), s);
       m->M_valid = true;
     }
-    m->timed(nch > 0, [&](hipEvent_t t0, hipEvent_t t1) {
-      td4_launch_events(*m->td4_jit, tc, m->table_td4(), nullptr, 1, ev, ld, n, m->chunk, grad, m->part(), s, t0,
+    m->timed(launches, [&](hipEvent_t t0, hipEvent_t t1) {
+      td4_launch_events(*m->td4_jit, tc, m->table_td4(), nullptr, 1, ev, ld, n, m->chunk, grad, part, s, t0,
                         t1);
     });
-    td4_launch_finalize(tc, m->table_td4(), nullptr, 1, m->part(), nch, grad, m->Mc(), (double)n, m->out(), 0,
+    td4_launch_finalize(tc, m->table_td4(), nullptr, 1, part, nch, grad, m->Mc(), (double)n, m->out(), 0,
                         out_user, s);
   } else {
     const DalitzConst& dc = m->dal;
     const int kmax = dalitz_kmax(dc.K);
     const int g = grad ? (dc.free_ls ? 2 : 1) : 0;
     const int nv = dalitz_nv_events(kmax, g);
-    m->d_part.reserve(sizeof(double) * (size_t)(nch > 0 ? nch : 1) * nv);
+    events_rows((size_t)(nch > 0 ? nch : 1) * nv);
     // The table holds the lineshape constants (functions of theta only when the
     // lineshapes are free) and a copy of the coefficients; with fixed lineshapes
     // and theta on the device, the passes read the coefficients from theta and
@@ -441,7 +505,7 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
       if (!dc.free_ls) m->table_ready = true;
     }
     const double* coef = theta_dev ? theta_dev : m->table_dal()->coef;
-    const double* npart = nullptr;
+    const double* grid_rows = nullptr;
     int64_t nrows = 0;
     int nnv = 0;
     if (dc.free_ls) {
@@ -449,25 +513,25 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
       const int64_t ncell = (int64_t)dc.nx * dc.ny;
       nrows = nchunks_for(ncell, m->grid_chunk);
       nnv = dalitz_nv_events(kmax, g);
-      m->d_npart.reserve(sizeof(double) * (size_t)nrows * nnv);
-      dalitz_launch_grid(*m->dal_jit, dc, m->table_dal(), coef, m->grid_chunk, nrows, g, m->npart(), s);
-      npart = m->npart();
+      norm_rows((size_t)nrows * nnv);
+      dalitz_launch_grid(*m->dal_jit, dc, m->table_dal(), coef, m->grid_chunk, nrows, g, npart, s);
+      grid_rows = npart;
     } else if (!m->M_valid) {
       // fixed lineshapes: reduce the grid once to M_ij = dA sum A_i conj(A_j)
       const int64_t ncell = (int64_t)dc.nx * dc.ny;
       const int64_t mrows = nchunks_for(ncell, m->grid_chunk);
-      m->d_npart.reserve(sizeof(double) * (size_t)mrows * dalitz_nv_mrows(kmax));
+      norm_rows((size_t)mrows * dalitz_nv_mrows(kmax));
       for (int i0 = 0; i0 < dc.K; i0 += 4)
-        dalitz_launch_mrows(*m->dal_jit, dc, m->table_dal(), m->grid_chunk, mrows, i0, m->npart(), m->Mc(), s);
+        dalitz_launch_mrows(*m->dal_jit, dc, m->table_dal(), m->grid_chunk, mrows, i0, npart, m->Mc(), s);
       m->M_valid = true;
     }
     // cached M: the events pass evaluates I = c^H M c in its last workgroup
     const bool norm_in_pass = !dc.free_ls && nch > 0;
-    m->timed(nch > 0, [&](hipEvent_t t0, hipEvent_t t1) {
-      dalitz_launch_events(*m->dal_jit, dc, m->table_dal(), coef, ev, ld, n, m->chunk, nch, g, m->part(), s,
+    m->timed(launches, [&](hipEvent_t t0, hipEvent_t t1) {
+      dalitz_launch_events(*m->dal_jit, dc, m->table_dal(), coef, ev, ld, n, m->chunk, nch, g, part, s,
                            norm_in_pass ? m->Mc() : nullptr, norm_in_pass ? m->out() : nullptr, t0, t1);
     });
-    dalitz_launch_finalize(dc, m->table_dal(), coef, m->part(), nch, g, npart, nrows, nnv, m->Mc(), (double)n,
+    dalitz_launch_finalize(dc, m->table_dal(), coef, part, nch, g, grid_rows, nrows, nnv, m->Mc(), (double)n,
                            m->out(), out_user, s, norm_in_pass);
   }
   hip_check(hipGetLastError(), "kernel launch");
@@ -603,8 +667,10 @@ fn_status fn_ctx_create(int32_t device, fn_ctx** out) {
     hip_check(hipGetDeviceCount(&n), "hipGetDeviceCount");
     if (device < 0 || device >= n) throw Error(FN_E_INVALID, "no such device");
     hip_check(hipSetDevice(device), "hipSetDevice");
+    double* sp = scratch_address(device);
     fn_ctx* c = new fn_ctx;
     c->device = device;
+    c->scratch = sp;
     *out = c;
   });
 }
@@ -803,6 +869,20 @@ fn_status fn_nll_async(fn_model* m, const double* theta_dev, const double* ev, i
     hip_check(hipSetDevice(m->device), "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
     run_nll(m, nullptr, theta_dev, ev, n, ld, with_grad != 0, out_dev, s);
+  });
+}
+
+fn_status fn_nll_async_noalloc(fn_model* m, const double* theta_dev, const double* ev, int64_t n, int64_t ld,
+                               double* out_dev, int32_t with_grad, void* stream) {
+  return guard([&] {
+    if (!m || !theta_dev || !out_dev) throw Error(FN_E_INVALID, "NULL argument");
+    check_events_args(m, ev, n, ld);
+    if (!m->ctx || !m->ctx->scratch) throw Error(FN_E_INVALID, "the model's context has no scratch address");
+    hip_check(hipSetDevice(m->device), "hipSetDevice");
+    Workspace ws;
+    ws.base = m->ctx->scratch;
+    ws.cap = kScratchDoubles;
+    run_nll(m, nullptr, theta_dev, ev, n, ld, with_grad != 0, out_dev, (hipStream_t)stream, &ws);
   });
 }
 
