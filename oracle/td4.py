@@ -14,7 +14,13 @@ Amplitudes.  Basis functions B_k = a12[r1_k](m12) a34[r2_k](m34) Omega_k with
   Omega by helicity structure: 0 S x S: 1;  1 S x V: c34;  2 V x S: c12;
   3 V x V (lambda 0): c12 c34;  4 V x V (lambda +1): 1/2 s12 s34 e^{i phi};
   5 V x V (lambda -1): 1/2 s12 s34 e^{-i phi}   (s = sqrt(1 - c^2)).
-A = sum_k c_k B_k and Abar = sum_k cbar_k B_k (same basis, two coefficient sets).
+Every basis function enters the D0 amplitude A, the Dbar0 amplitude Abar, or
+both (an optional fourth entry "A", "Abar" or "both" of each amplitude;
+"both" when absent): A = sum_{k in A} c_k B_k, Abar = sum_{k in Abar} cbar_k B_k.
+With "both" everywhere the two sums share one basis and differ only in their
+coefficients; with disjoint sets, A and Abar are built from distinct basis
+functions (the doubly Cabibbo-suppressed and the Cabibbo-favoured amplitudes
+of a four-body analysis, Sec. 5, read as ten distinct functions each).
 
 Time dependence (q/p = 1, Gamma = 1/tau, mixing x, y):
   R(x, t) = 1/2 e^{-Gamma t} [(|A|^2 + |Abar|^2) cosh(y Gamma t) + (|A|^2 - |Abar|^2) cos(x Gamma t)
@@ -33,7 +39,8 @@ average over an unweighted phase-space sample of
   1/2 [(|A|^2+|Abar|^2)/(G(1-y^2)) + (|A|^2-|Abar|^2)/(G(1+x^2))
        - 2 Re(A* Abar) y/(G(1-y^2)) - 2 Im(A* Abar) x/(G(1+x^2))].
 
-theta = (Re c_k, Im c_k)_k, (Re cbar_k, Im cbar_k)_k, x, y.
+theta = (Re c_k, Im c_k) for the members of A in description order, then
+(Re cbar_k, Im cbar_k) for the members of Abar in description order, then x, y.
 
 Pins (tests/test_oracle_td4.py): h against direct quadrature of the
 convolution (real and complex a, t from -0.3 to 5 ps), the sigma -> 0 limit,
@@ -104,9 +111,14 @@ class TD4:
         self.sigma = float(desc["sigma_t"])
         self.r12 = [(int(e["L"]), float(e["m0"]), float(e["w0"])) for e in desc["r12"]]
         self.r34 = [(int(e["L"]), float(e["m0"]), float(e["w0"])) for e in desc["r34"]]
-        self.amps = [tuple(int(v) for v in a) for a in desc["amps"]]
+        self.amps = [tuple(int(v) for v in a[:3]) for a in desc["amps"]]
         self.K = len(self.amps)
-        self.P = 4 * self.K + 2
+        sides = [a[3] if len(a) > 3 else "both" for a in desc["amps"]]
+        if any(sd not in ("both", "A", "Abar") for sd in sides):
+            raise ValueError("an amplitude's sum must be \"both\", \"A\" or \"Abar\"")
+        self.in_a = [k for k in range(self.K) if sides[k] in ("both", "A")]
+        self.in_b = [k for k in range(self.K) if sides[k] in ("both", "Abar")]
+        self.P = 2 * len(self.in_a) + 2 * len(self.in_b) + 2
 
     @staticmethod
     def lam(a, b, c):
@@ -155,9 +167,13 @@ class TD4:
         return [a12[i] * a34[j] * self.omega(typ, c12, c34, phi) for (i, j, typ) in self.amps]
 
     def amplitudes(self, theta, B):
-        K = self.K
-        A = sum(torch.complex(theta[2 * k], theta[2 * k + 1]) * B[k] for k in range(K))
-        Ab = sum(torch.complex(theta[2 * K + 2 * k], theta[2 * K + 2 * k + 1]) * B[k] for k in range(K))
+        off = 2 * len(self.in_a)
+        A = torch.zeros_like(B[0])
+        for j, k in enumerate(self.in_a):
+            A = A + torch.complex(theta[2 * j], theta[2 * j + 1]) * B[k]
+        Ab = torch.zeros_like(B[0])
+        for j, k in enumerate(self.in_b):
+            Ab = Ab + torch.complex(theta[off + 2 * j], theta[off + 2 * j + 1]) * B[k]
         return A, Ab
 
     def rate(self, theta, ev):

@@ -10,6 +10,7 @@ from .samplers import (  # noqa: F401
 from .workloads import mix1d_desc, mix1d_truth, dalitz_desc, dalitz_truth  # noqa: F401,E402
 from .td4 import (  # noqa: F401,E402
     TD4_MASSES, TD4_TAU, TD4_SIGMA_T, td4_desc, td4_truth, td4_phase_space, td4_events,
+    td4_split_desc, td4_split_truth,
 )
 from .tddp3 import (  # noqa: F401,E402
     TDDP_MASSES, TDDP_RESONANCES, tddp3_desc, tddp3_truth, tddp3_events,

@@ -33,6 +33,43 @@ TD4_C = ((0.25, 0.0), (0.05, 0.09), (-0.12, 0.20), (0.10, -0.04), (0.30, 0.22),
          (-0.08, 0.11), (0.21, -0.17), (-0.14, -0.10), (0.09, 0.16), (0.04, -0.06))
 
 
+# The twenty-amplitude model: four entries per pair and every spin-compatible
+# (r12, r34, angular type) combination once (S x S: type 0; S x V: 1; V x S: 2;
+# V x V: 3, 4, 5), ten of them in Abar (Cabibbo-favoured, D0bar-like) and the
+# other ten in A (doubly Cabibbo-suppressed), so A and Abar share no basis
+# function.  Lineshapes are Breit-Wigners of the named resonances.
+TD4S_R12 = ((0, 0.0, 0.0), (1, 1.019461, 0.004249), (0, 1.370, 0.350), (0, 1.505, 0.109))
+#           NR              phi(1020)                 f0(1370)           f0(1500)
+TD4S_R34 = ((0, 0.0, 0.0), (1, 0.77526, 0.1491), (0, 0.990, 0.070), (1, 0.78266, 0.00868))
+#           NR              rho(770)              f0(980)            omega(782)
+TD4S_ABAR = ((1, 1, 3), (1, 1, 4), (1, 1, 5), (1, 0, 2), (1, 2, 2),
+             (0, 1, 1), (2, 1, 1), (0, 0, 0), (0, 2, 0), (2, 2, 0))
+TD4S_A = ((1, 3, 3), (1, 3, 4), (1, 3, 5), (0, 3, 1), (2, 3, 1),
+          (3, 1, 1), (3, 3, 1), (2, 0, 0), (3, 0, 0), (3, 2, 0))
+TD4S_CBAR = ((1.0, 0.0), (0.55, -0.35), (-0.40, 0.60), (1.30, 0.25), (0.35, -0.45),
+             (0.70, 0.40), (-0.25, 0.50), (0.60, -0.20), (0.45, 0.35), (-0.30, -0.25))
+TD4S_C = ((0.20, 0.0), (0.06, 0.08), (-0.05, 0.09), (0.12, -0.07), (0.04, 0.10),
+          (0.09, -0.11), (-0.07, 0.05), (0.10, 0.03), (-0.04, -0.08), (0.06, 0.05))
+
+
+def td4_split_desc(sigma_t: float = TD4_SIGMA_T, r12=TD4S_R12, r34=TD4S_R34, chunk: int | None = None) -> dict:
+    """The twenty-amplitude model: Abar's ten basis functions first, then A's."""
+    d = td4_desc(sigma_t=sigma_t, r12=r12, r34=r34, chunk=chunk)
+    d["amps"] = [list(a) + ["Abar"] for a in TD4S_ABAR] + [list(a) + ["A"] for a in TD4S_A]
+    return d
+
+
+def td4_split_truth() -> np.ndarray:
+    """theta of the twenty-amplitude model: A's coefficients, Abar's, x, y."""
+    th = []
+    for c in TD4S_C:
+        th += [c[0], c[1]]
+    for c in TD4S_CBAR:
+        th += [c[0], c[1]]
+    th += [TD4_X, TD4_Y]
+    return np.array(th, dtype=np.float64)
+
+
 def td4_desc(sigma_t: float = TD4_SIGMA_T, r12=TD4_R12, r34=TD4_R34, chunk: int | None = None) -> dict:
     M, m1, m2, m3, m4 = TD4_MASSES
     d = {"kind": "td4", "M": M, "m": [m1, m2, m3, m4], "r_res": 1.5, "tau": TD4_TAU, "sigma_t": sigma_t,

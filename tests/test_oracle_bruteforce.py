@@ -230,7 +230,8 @@ class FourBody:
         self.r = mp.mpf(desc.get("r_res", 1.5))
         self.r12 = [(int(e["L"]), mp.mpf(e["m0"]), mp.mpf(e["w0"])) for e in desc["r12"]]
         self.r34 = [(int(e["L"]), mp.mpf(e["m0"]), mp.mpf(e["w0"])) for e in desc["r34"]]
-        self.amps = [tuple(int(v) for v in a) for a in desc["amps"]]
+        self.amps = [tuple(int(v) for v in a[:3]) for a in desc["amps"]]
+        self.sides = [a[3] if len(a) > 3 else "both" for a in desc["amps"]]
 
     def lineshape(self, m, ma, mb, e):
         L, m0, w0 = e
@@ -255,16 +256,36 @@ class FourBody:
         return [a12[i] * a34[j] * self.angular(typ, c12, c34, phi) for (i, j, typ) in amps]
 
 
-@pytest.mark.parametrize("xy", [(0.004, 0.006), (0.25, 0.3)])
-def test_td4_nll_brute_force(xy):
-    desc = synth.td4_desc()
-    th = synth.td4_truth()
+def four_body_coefs(bf, th):
+    """Per basis function its coefficient in A and in Abar (0 where it is not
+    a member): theta lists the members of A in description order, then those
+    of Abar, then x and y."""
+    K = len(bf.amps)
+    members_a = [k for k in range(K) if bf.sides[k] != "Abar"]
+    members_b = [k for k in range(K) if bf.sides[k] != "A"]
+    c, cb = [mp.mpc(0)] * K, [mp.mpc(0)] * K
+    for j, k in enumerate(members_a):
+        c[k] = mp.mpc(th[2 * j], th[2 * j + 1])
+    off = 2 * len(members_a)
+    for j, k in enumerate(members_b):
+        cb[k] = mp.mpc(th[off + 2 * j], th[off + 2 * j + 1])
+    assert off + 2 * len(members_b) + 2 == len(th)
+    return c, cb
+
+
+@pytest.mark.parametrize("model,xy", [("shared", (0.004, 0.006)), ("shared", (0.25, 0.3)),
+                                      ("split", (0.004, 0.006)), ("split", (-0.2, 0.35))])
+def test_td4_nll_brute_force(model, xy):
+    """Ten shared basis functions with two coefficient sets, and twenty
+    distinct ones split ten into A and ten into Abar."""
+    desc = synth.td4_desc() if model == "shared" else synth.td4_split_desc()
+    th = synth.td4_truth() if model == "shared" else synth.td4_split_truth()
     th[-2:] = xy
     ev = synth.td4_events(NEV, seed=4713)
     mc = synth.td4_phase_space(40, seed=4714)
     bf = FourBody(desc)
     K = len(desc["amps"])
-    c, cb = coefs(th, K), coefs(th, K, 2 * K)
+    c, cb = four_body_coefs(bf, th)
     G = 1 / mp.mpf(desc["tau"])
 
     def amps(kin):

@@ -107,6 +107,34 @@ def test_autograd_vs_central_fd():
     assert (np.abs(g - fd) <= tol).all(), np.abs(g - fd) / tol
 
 
+def test_split_model_equals_shared_basis_with_zero_coefficients():
+    """Twenty distinct basis functions, ten in A and ten in Abar, give the NLL
+    and gradient of the same twenty functions entering both sums, with the
+    coefficients of the non-members set to zero (the split layout lists A's
+    members, then Abar's, then x and y)."""
+    ds, ths = synth.td4_split_desc(), synth.td4_split_truth()
+    ths = ths * (1 + 0.05 * np.cos(np.arange(ths.size)))
+    ths[-2:] = [0.04, -0.03]
+    db = dict(ds, amps=[a[:3] for a in ds["amps"]])
+    K = len(ds["amps"])
+    in_a = [k for k, a in enumerate(ds["amps"]) if a[3] == "A"]
+    in_b = [k for k, a in enumerate(ds["amps"]) if a[3] == "Abar"]
+    thb = np.zeros(4 * K + 2)
+    for j, k in enumerate(in_a):
+        thb[2 * k:2 * k + 2] = ths[2 * j:2 * j + 2]
+    for j, k in enumerate(in_b):
+        thb[2 * K + 2 * k:2 * K + 2 * k + 2] = ths[2 * len(in_a) + 2 * j:2 * len(in_a) + 2 * j + 2]
+    thb[-2:] = ths[-2:]
+    ev = synth.td4_events(400, seed=17)
+    mc = synth.td4_phase_space(2000, seed=18)
+    vs, gs = OT.nll_grad(ths, ev, mc, ds)
+    vb, gb = OT.nll_grad(thb, ev, mc, db)
+    assert abs(vs - vb) <= 1e-13 * abs(vb)
+    gmap = np.r_[np.concatenate([gb[2 * k:2 * k + 2] for k in in_a]),
+                 np.concatenate([gb[2 * K + 2 * k:2 * K + 2 * k + 2] for k in in_b]), gb[-2:]]
+    assert np.allclose(gs, gmap, rtol=1e-12, atol=1e-12 * np.abs(gmap).max())
+
+
 def test_phase_space_marginal():
     """m12 marginal of the phase-space sample against 1-D quadrature of the
     phase-space density (chi-square over 20 bins)."""
