@@ -135,7 +135,7 @@ class TD4:
         s = m * m
         q = torch.sqrt(torch.clamp(self.lam(s, ma * ma, mb * mb), min=0.0)) / (2.0 * m)
         q0 = math.sqrt(self.lam(m0 * m0, ma * ma, mb * mb)) / (2.0 * m0)
-        fr = self.bw_factor(L, (q * self.r) ** 2) / self.bw_factor(L, torch.tensor((q0 * self.r) ** 2))
+        fr = self.bw_factor(L, (q * self.r) ** 2) / self.bw_factor(L, torch.tensor((q0 * self.r) ** 2, dtype=torch.float64))
         gam = w0 * (q / q0) ** (2 * L + 1) * (m0 / m) * fr * fr
         t = 1.0 / torch.complex(m0 * m0 - s, -m0 * gam)
         return fr * t
