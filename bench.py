@@ -118,11 +118,13 @@ def td4_flops_per_event(desc: dict, grad: bool) -> int:
         f += 1                                     # c12 c34
     flat12 = [e["m0"] == 0.0 for e in desc["r12"]]
     flat34 = [e["m0"] == 0.0 for e in desc["r34"]]
-    for i12, i34, t in desc["amps"]:
+    members = 0                                    # (basis function, sum) memberships
+    for a in desc["amps"]:
+        i12, i34, t = a[:3]
         f += 0 if (flat12[i12] or flat34[i34]) else 6
         f += 0 if t == 0 else (2 if t <= 3 else 6)
-    K = len(desc["amps"])
-    f += 16 * K                                    # A and Abar
+        members += 2 if len(a) < 4 or a[3] == "both" else 1
+    f += 8 * members                               # A and Abar
     f += 2 + W_EXP                                 # exp(-t^2 / 2 sigma^2)
     horner_r = (N - 1) * 2
     h_real = 3 + (1 + W_DIV) + 2 + horner_r + 4 + (4 + W_EXP) + 3
@@ -133,7 +135,7 @@ def td4_flops_per_event(desc: dict, grad: bool) -> int:
     f += 27 + W_LOG + 1                            # rate, log, accumulate
     if grad:
         f += 2 * 3 + 8                             # dh/da of the three time terms
-        f += 1 + W_DIV + 2 + 24 + 16 * K + 20      # -1/R, the two complex weights, lc B_k and lb B_k, x and y
+        f += 1 + W_DIV + 2 + 24 + 8 * members + 20  # -1/R, the two complex weights, lc B_k and lb B_k, x and y
     return f
 
 
@@ -613,20 +615,31 @@ def tddp3_whole_fit(m, th, n):
             "fit_max_pull": float(pull.max())}
 
 
-def td4_leg(steps: int = 10):
+def td4_events_device():
+    """The four-body event sample of the config-4 legs: 10M events, drawn on the host."""
+    import torch
+    import synth
+    t0 = time.perf_counter()
+    ev = torch.from_numpy(synth.td4_events(10_000_000, seed=synth.BASE_SEED + 4)).cuda()
+    return ev, time.perf_counter() - t0
+
+
+def td4_leg(steps: int = 10, split: bool = True, ev=None):
     """Config 4: the time-dependent four-body model, 10M events, 5M-point
     phase-space normalization sample; single-fit NLL + adjoint gradient, the
     plain finite-difference gradient, and 64 systematic-variation fits sharing
-    the events (one events pass for all fits per step)."""
+    the events (one events pass for all fits per step).  split: twenty
+    distinct basis functions, ten in A and ten in Abar; otherwise ten shared
+    basis functions with two coefficient sets."""
     import torch
     import synth
     from paper_1710_08826_amd import Model, VariationBatch
     n, n_mc, F = 10_000_000, 5_000_000, 64
-    t0 = time.perf_counter()
-    ev = torch.from_numpy(synth.td4_events(n, seed=synth.BASE_SEED + 4)).cuda()
-    gen_s = time.perf_counter() - t0
-    desc = synth.td4_desc()
-    th = synth.td4_truth()
+    gen_s = None
+    if ev is None:
+        ev, gen_s = td4_events_device()
+    desc = synth.td4_split_desc() if split else synth.td4_desc()
+    th = synth.td4_split_truth() if split else synth.td4_truth()
     m = Model(desc)
     # the normalization sample generated on the device (the same points as
     # synth.td4_phase_space(n_mc, seed=BASE_SEED + 5))
@@ -642,7 +655,9 @@ def td4_leg(steps: int = 10):
     _, tune_us = m.autotune(th, ev, reps=5)
     w, k, info = time_async(m, tdev, ev, out, steps, 2, True, alt=tb)
     w0, k0, _ = time_async(m, tdev, ev, out, steps, 2, False, alt=tb)
-    r = {"events": n, "mc_points": n_mc, "params": P, "chunk": m.chunk,
+    r = {"model": ("20 distinct basis functions, 10 in A and 10 in Abar" if split else
+                   "10 basis functions shared by A and Abar"),
+         "events": n, "mc_points": n_mc, "params": P, "chunk": m.chunk,
          "autotune_us": {str(c): v for c, v in tune_us.items()},
          "cpu_generation_s": gen_s, "device_mc_sample_s": mc_gen_s,
          "single_events_per_s": n * steps / w, "single_ms_per_step": 1e3 * w / steps,
@@ -667,9 +682,12 @@ def td4_leg(steps: int = 10):
     # 64 systematic variations: +-shifts of lineshape constants and the time resolution
     b = VariationBatch(m, F)
     fx = m.fixed()
+    # phi(1020) width, rho(770) mass and width, f0(980) width, time resolution
+    n12, n34 = len(desc["r12"]), len(desc["r34"])
+    shifted = (3, 2 * n12 + 2, 2 * n12 + 3, 2 * n12 + 5, 2 * (n12 + n34))
     for f in range(F):
         v = fx.copy()
-        j = (3, 8, 9, 11, 12)[f % 5]
+        j = shifted[f % 5]
         v[j] *= 1.0 + 0.002 * ((f // 5) - 6)
         b.set_fixed(f, v)
     ths = np.stack([th * (1.0 + 1e-3 * np.sin(np.arange(P) + f)) for f in range(F)])
@@ -690,8 +708,9 @@ def td4_leg(steps: int = 10):
     r["batch_vs_single_calls"] = (F * r["single_ms_per_step"]) / r["batch_ms_per_step"]
     # batched minimizer steps (evaluation + device BFGS update), a few iterations
     free = np.ones(P, np.int32)
-    K = (P - 2) // 4
-    free[2 * K: 2 * K + 2] = 0  # cbar_0 is the reference amplitude
+    n_abar = sum(1 for a in desc["amps"] if len(a) < 4 or a[3] != "A")
+    ref = P - 2 - 2 * n_abar
+    free[ref: ref + 2] = 0  # Abar's first coefficient is the reference amplitude
     t0 = time.perf_counter()
     res = b.fit(ths, ev, free=free, max_iter=4)
     wf = time.perf_counter() - t0
@@ -726,7 +745,10 @@ def main():
         pmc_probe(args.steps, args.chunk)
         return
     if args.leg == "td4":
-        print(json.dumps({"config4": td4_leg()}), flush=True)
+        ev4, gen_s = td4_events_device()
+        c4 = td4_leg(ev=ev4)
+        c4["cpu_generation_s"] = gen_s
+        print(json.dumps({"config4": c4, "config4_shared_basis": td4_leg(split=False, ev=ev4)}), flush=True)
         return
     if args.leg == "serve":
         print(json.dumps({"config2_serving": serving_leg()}), flush=True)
@@ -855,11 +877,16 @@ def main():
     if not args.quick:
         print("[bench] config4 td4 (10M events, 5M-point sample, 64 variation fits) ...", file=sys.stderr,
               flush=True)
-        extra["config4"] = td4_leg()
-        c4 = extra["config4"]
-        print(f"[bench] config4: single {c4['single_events_per_s']:.4g} events/s "
-              f"({c4['single_event_kernel_tflops']:.2f} TFLOP/s), 64 fits {c4['batch_event_fits_per_s']:.4g} "
-              f"event-fits/s, adjoint vs FD {c4['adjoint_vs_plain_fd']:.1f}x", file=sys.stderr, flush=True)
+        ev4, gen_s = td4_events_device()
+        extra["config4"] = td4_leg(ev=ev4)
+        extra["config4"]["cpu_generation_s"] = gen_s
+        extra["config4_shared_basis"] = td4_leg(split=False, ev=ev4)
+        del ev4
+        for key in ("config4", "config4_shared_basis"):
+            c4 = extra[key]
+            print(f"[bench] {key} ({c4['model']}): single {c4['single_events_per_s']:.4g} events/s "
+                  f"({c4['single_event_kernel_tflops']:.2f} TFLOP/s), 64 fits {c4['batch_event_fits_per_s']:.4g} "
+                  f"event-fits/s, adjoint vs FD {c4['adjoint_vs_plain_fd']:.1f}x", file=sys.stderr, flush=True)
 
     if not args.quick:
         print("[bench] config2 serving (4096 toy fits) ...", file=sys.stderr, flush=True)

@@ -341,7 +341,8 @@ static void compile_td4(const json::Value& d, fn_model* m, bool device = true) {
   auto pair = [&](const char* key, int* n, int* L, int* nr) {
     const auto& rs = d.at(key).array();
     *n = (int)rs.size();
-    if (*n < 1 || *n > kTd4MaxRes) throw Error(FN_E_INVALID, std::string("td4: ") + key + " needs 1..4 entries");
+    if (*n < 1 || *n > kTd4MaxRes)
+      throw Error(FN_E_INVALID, std::string("td4: ") + key + " needs 1.." + std::to_string(kTd4MaxRes) + " entries");
     for (int r = 0; r < *n; ++r) {
       const long l = rs[r].at("L").integer();
       if (l < 0 || l > 1) throw Error(FN_E_INVALID, "td4: L must be 0 or 1");
@@ -357,18 +358,38 @@ static void compile_td4(const json::Value& d, fn_model* m, bool device = true) {
   fixed.push_back(d.at("sigma_t").number());
   const auto& amps = d.at("amps").array();
   tc.K = (int)amps.size();
-  if (tc.K < 1 || tc.K > kTd4MaxAmp) throw Error(FN_E_INVALID, "td4: 1..12 amplitudes");
+  if (tc.K < 1 || tc.K > kTd4MaxAmp)
+    throw Error(FN_E_INVALID, "td4: 1.." + std::to_string(kTd4MaxAmp) + " amplitudes");
+  int side[kTd4MaxAmp];  // 0: in A and Abar, 1: A only, 2: Abar only
   for (int k = 0; k < tc.K; ++k) {
     const auto& a = amps[k].array();
-    if (a.size() != 3) throw Error(FN_E_INVALID, "td4: an amplitude is [r12 index, r34 index, angular type]");
+    if (a.size() != 3 && a.size() != 4)
+      throw Error(FN_E_INVALID, "td4: an amplitude is [r12 index, r34 index, angular type(, \"A\" | \"Abar\" | \"both\")]");
     const long r1 = a[0].integer(), r2 = a[1].integer(), ty = a[2].integer();
     if (r1 < 0 || r1 >= tc.n12 || r2 < 0 || r2 >= tc.n34 || ty < 0 || ty > 5)
       throw Error(FN_E_INVALID, "td4: amplitude index out of range");
     tc.amp1[k] = (int)r1;
     tc.amp2[k] = (int)r2;
     tc.atype[k] = (int)ty;
+    side[k] = 0;
+    if (a.size() == 4) {
+      const std::string& sd = a[3].string();
+      if (sd == "A") side[k] = 1;
+      else if (sd == "Abar") side[k] = 2;
+      else if (sd != "both") throw Error(FN_E_INVALID, "td4: an amplitude's sum is \"A\", \"Abar\" or \"both\"");
+    }
   }
-  tc.n_params = 4 * tc.K + 2;
+  // theta: A's members' coefficients, then Abar's, then x and y
+  int p = 0;
+  for (int k = 0; k < tc.K; ++k) {
+    tc.pa[k] = side[k] != 2 ? p : -1;
+    if (side[k] != 2) p += 2;
+  }
+  for (int k = 0; k < tc.K; ++k) {
+    tc.pb[k] = side[k] != 1 ? p : -1;
+    if (side[k] != 1) p += 2;
+  }
+  tc.n_params = p + 2;
   const Td4FitConst fc = td4_fit_const(tc, fixed.data());
   m->fixed_ls = fixed;
   m->P = tc.n_params;
@@ -471,13 +492,13 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
     const Td4Const& tc = m->td4;
     if (m->n_mc <= 0) throw Error(FN_E_INVALID, "td4: normalization sample not set (fn_model_set_norm_sample)");
     const int kmax = td4_kmax(tc.K);
-    events_rows((size_t)(nch > 0 ? nch : 1) * td4_nv(kmax, grad));
+    events_rows((size_t)(nch > 0 ? nch : 1) * td4_nv(tc, grad));
     const Td4FitConst* fc = (const Td4FitConst*)m->d_fixed.ptr;
     td4_launch_prologue(tc, pb, theta_dev, m->P, fc, nullptr, 1, m->table_td4(), s);
     if (!m->M_valid) {
       const int mchunk = 1024;
       const int64_t mrows = nchunks_for(m->n_mc, mchunk);
-      norm_rows((size_t)mrows * 8 * kmax);
+      norm_rows((size_t)mrows * 2 * td4_row_block(tc.K) * kmax);
       td4_launch_mmatrix(*m->td4_jit, tc, m->table_td4(), 1, (const double*)m->d_mc.ptr, m->n_mc, m->n_mc, mchunk,
                          npart,
                          m->Mc(), s);

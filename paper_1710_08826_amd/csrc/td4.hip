@@ -108,15 +108,16 @@ __global__ void td4_prologue(Td4Const tc, ParamBlock pb, const double* __restric
     if (r < tc.n12 && !tc.nr12[r]) lineshape(fc.m0_12[r], fc.w0_12[r], tc.L12[r], tc.sum12, tc.dif12, t.r12[r]);
     if (r < tc.n34 && !tc.nr34[r]) lineshape(fc.m0_34[r], fc.w0_34[r], tc.L34[r], tc.sum34, tc.dif34, t.r34[r]);
   }
+  // a basis function outside a sum has a zero coefficient there
   for (int k = 0; k < kTd4MaxAmp; ++k) {
-    const bool in = k < tc.K;
-    t.c[k][0] = in ? th[2 * k] : 0.0;
-    t.c[k][1] = in ? th[2 * k + 1] : 0.0;
-    t.cb[k][0] = in ? th[2 * tc.K + 2 * k] : 0.0;
-    t.cb[k][1] = in ? th[2 * tc.K + 2 * k + 1] : 0.0;
+    const int ia = k < tc.K ? tc.pa[k] : -1, ib = k < tc.K ? tc.pb[k] : -1;
+    t.c[k][0] = ia >= 0 ? th[ia] : 0.0;
+    t.c[k][1] = ia >= 0 ? th[ia + 1] : 0.0;
+    t.cb[k][0] = ib >= 0 ? th[ib] : 0.0;
+    t.cb[k][1] = ib >= 0 ? th[ib + 1] : 0.0;
   }
-  t.x = th[4 * tc.K];
-  t.y = th[4 * tc.K + 1];
+  t.x = th[tc.n_params - 2];
+  t.y = th[tc.n_params - 1];
   t.sigma = fc.sigma;
   if (!(fabs(t.y) < 1.0) || !isfinite(t.x)) ok = false;
   t.valid = ok ? 1.0 : 0.0;
@@ -125,7 +126,7 @@ __global__ void td4_prologue(Td4Const tc, ParamBlock pb, const double* __restric
 
 // ---------------------------------------------------- normalization matrix
 __global__ __launch_bounds__(kFinalBlock) void td4_mrows_finalize(Td4Const tc, const double* __restrict__ part,
-                                                                  int64_t nch, int nv, int kmax, int i0,
+                                                                  int64_t nch, int nv, int kmax, int i0, int rb,
                                                                   double inv_n, double* __restrict__ Mc) {
   __shared__ double scratch[kFinalBlock];
   __shared__ double res[kBlock];
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(kFinalBlock) void td4_mrows_finalize(Td4Const tc, c
   sum_rows_t<kFinalBlock>(part + (int64_t)f * nch * nv, nch, nv, scratch, res);
   const int K = tc.K;
   double* M = Mc + (int64_t)f * 2 * kTd4MaxAmp * kTd4MaxAmp;
-  for (int t = threadIdx.x; t < kTd4RowBlock * kmax; t += kFinalBlock) {
+  for (int t = threadIdx.x; t < rb * kmax; t += kFinalBlock) {
     const int ib = t / kmax, j = t - ib * kmax;
     const int i = i0 + ib;
     if (i < K && j < K) {
@@ -157,7 +158,7 @@ __global__ __launch_bounds__(kFinalBlock) void td4_finalize(Td4Const tc, const T
   __shared__ double scratch[kFinalBlock];
   __shared__ double res[kBlock];
   __shared__ double M[2 * kTd4MaxAmp * kTd4MaxAmp];
-  __shared__ double gI[4 * kTd4MaxAmp + 2];
+  __shared__ double gI[4 * kTd4MaxAmp + 2];  // dI/dtheta in theta order
   __shared__ double Ish;
   const int f = blockIdx.x;
   if (status && status[f] != 1) return;
@@ -200,14 +201,19 @@ __global__ __launch_bounds__(kFinalBlock) void td4_finalize(Td4Const tc, const T
     const double I = 0.5 * ((a + b) * cy + (a - b) * cx - 2.0 * zr * y * cy - 2.0 * zi * x * cx);
     Ish = I;
     for (int k = 0; k < K; ++k) {
-      gI[2 * k] = 0.5 * ((cy + cx) * 2.0 * Xr[k] - 2.0 * y * cy * Ur[k] - 2.0 * x * cx * Ui[k]);
-      gI[2 * k + 1] = 0.5 * (-2.0 * (cy + cx) * Xi[k] - 2.0 * y * cy * Ui[k] + 2.0 * x * cx * Ur[k]);
-      gI[2 * K + 2 * k] = 0.5 * ((cy - cx) * 2.0 * Yr[k] - 2.0 * y * cy * Vr[k] - 2.0 * x * cx * Vi[k]);
-      gI[2 * K + 2 * k + 1] = 0.5 * (-2.0 * (cy - cx) * Yi[k] + 2.0 * y * cy * Vi[k] - 2.0 * x * cx * Vr[k]);
+      const int ia = tc.pa[k], ib = tc.pb[k];
+      if (ia >= 0) {
+        gI[ia] = 0.5 * ((cy + cx) * 2.0 * Xr[k] - 2.0 * y * cy * Ur[k] - 2.0 * x * cx * Ui[k]);
+        gI[ia + 1] = 0.5 * (-2.0 * (cy + cx) * Xi[k] - 2.0 * y * cy * Ui[k] + 2.0 * x * cx * Ur[k]);
+      }
+      if (ib >= 0) {
+        gI[ib] = 0.5 * ((cy - cx) * 2.0 * Yr[k] - 2.0 * y * cy * Vr[k] - 2.0 * x * cx * Vi[k]);
+        gI[ib + 1] = 0.5 * (-2.0 * (cy - cx) * Yi[k] + 2.0 * y * cy * Vi[k] - 2.0 * x * cx * Vr[k]);
+      }
     }
     const double dcx = -2.0 * x * G * cx * cx, dcy = 2.0 * y * G * cy * cy;
-    gI[4 * K] = 0.5 * ((a - b) * dcx - 2.0 * zi * (cx + x * dcx));
-    gI[4 * K + 1] = 0.5 * ((a + b) * dcy - 2.0 * zr * (cy + y * dcy));
+    gI[P - 2] = 0.5 * ((a - b) * dcx - 2.0 * zi * (cx + x * dcx));
+    gI[P - 1] = 0.5 * ((a + b) * dcy - 2.0 * zr * (cy + y * dcy));
   }
   __syncthreads();
   const double I = Ish;
@@ -221,12 +227,8 @@ __global__ __launch_bounds__(kFinalBlock) void td4_finalize(Td4Const tc, const T
   if (t < P) {
     o[2 + P + t] = gI[t];
     if (with_grad) {
-      // event slots: c at 1 + t, cb at 1 + 2 kmax + (t - 2K), x and y at 1 + 4 kmax
-      int slot;
-      if (t < 2 * K) slot = 1 + t;
-      else if (t < 4 * K) slot = 1 + 2 * kmax + (t - 2 * K);
-      else slot = 1 + 4 * kmax + (t - 4 * K);
-      const double g = ok ? res[slot] + n_events * gI[t] / I : NAN;
+      // event slot of theta entry t: 1 + t
+      const double g = ok ? res[1 + t] + n_events * gI[t] / I : NAN;
       o[1 + t] = g;
       if (out_user) out_user[1 + t] = g;
     }
@@ -282,7 +284,7 @@ __global__ void td4_eval(Td4Const tc, const Td4Table* __restrict__ tab, const do
 
 // ---------------------------------------------------------------- launchers
 int td4_kmax(int K) { return K; }  // partial rows hold exactly the model's amplitudes
-int td4_nv(int kmax, bool grad) { return grad ? 3 + 4 * kmax : 1; }
+int td4_nv(const Td4Const& tc, bool grad) { return grad ? 1 + tc.n_params : 1; }
 
 // Fourier coefficients a_n (n = 1..N) of f(theta) = exp(-t^2)(L^2 + t^2),
 // t = L tan(theta/2), by the trapezoidal rule on 2M - 1 interior points of
@@ -339,6 +341,9 @@ std::string td4_jit_source(const Td4Const& tc) {
   arr("A1", tc.amp1, tc.K);
   arr("A2", tc.amp2, tc.K);
   arr("T", tc.atype, tc.K);
+  arr("PA", tc.pa, tc.K);
+  arr("PB", tc.pb, tc.K);
+  o << "  static constexpr int P = " << tc.n_params << ";\n";
   o << "};\n"
        "FN_TD4_EVENTS(fn_td4_ev0, fn_td4_shape, false)\n"
        "FN_TD4_EVENTS(fn_td4_ev1, fn_td4_shape, true)\n"
@@ -362,8 +367,9 @@ void td4_launch_mmatrix(const Td4Jit& j, const Td4Const& tc, const Td4Table* tab
                         int64_t ld_mc, int64_t n_mc, int chunk, double* part, double* Mc, hipStream_t s) {
   const int kmax = td4_kmax(tc.K);
   const int64_t nch = (n_mc + chunk - 1) / chunk;
-  const int nv = 2 * kTd4RowBlock * kmax;
-  for (int i0 = 0; i0 < tc.K; i0 += kTd4RowBlock) {
+  const int rb = td4_row_block(tc.K);
+  const int nv = 2 * rb * kmax;
+  for (int i0 = 0; i0 < tc.K; i0 += rb) {
     Td4Const c = tc;
     const Td4Table* t = tabs;
     const double* m = mc;
@@ -372,7 +378,7 @@ void td4_launch_mmatrix(const Td4Jit& j, const Td4Const& tc, const Td4Table* tab
     double* p = part;
     void* args[] = {&c, &t, &m, &l, &nn, &ck, &nc, &nf, &ii, &p};
     jit_launch(j.mrows, (unsigned)(nch * n_fits), kBlock, s, args);
-    hipLaunchKernelGGL(td4_mrows_finalize, dim3(n_fits), dim3(kFinalBlock), 0, s, tc, part, nch, nv, kmax, i0,
+    hipLaunchKernelGGL(td4_mrows_finalize, dim3(n_fits), dim3(kFinalBlock), 0, s, tc, part, nch, nv, kmax, i0, rb,
                        1.0 / (double)n_mc, Mc);
   }
 }
@@ -398,7 +404,7 @@ void td4_launch_finalize(const Td4Const& tc, const Td4Table* tabs, const int* st
                          int out_stride, double* out_user, hipStream_t s) {
   const int kmax = td4_kmax(tc.K);
   hipLaunchKernelGGL(td4_finalize, dim3(n_fits), dim3(kFinalBlock), 0, s, tc, tabs, status, part, rows_per_fit,
-                     td4_nv(kmax, grad), kmax, grad ? 1 : 0, Mc, n_events, out, out_stride, out_user);
+                     td4_nv(tc, grad), kmax, grad ? 1 : 0, Mc, n_events, out, out_stride, out_user);
 }
 
 void td4_launch_eval(const Td4Const& tc, const Td4Table* tab, const double* ev, int64_t ld, int64_t n,

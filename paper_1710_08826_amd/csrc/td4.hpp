@@ -19,7 +19,7 @@ struct Td4Jit {
 std::string td4_jit_source(const Td4Const& tc);
 std::shared_ptr<Td4Jit> td4_jit(const Td4Const& tc);
 int td4_kmax(int K);
-int td4_nv(int kmax, bool grad);
+int td4_nv(const Td4Const& tc, bool grad);  // doubles per events-pass partial row: NLL, then the gradient in theta order
 void td4_weideman_coefficients(double* a, double* L);
 // Bound of the phase-space weight used by the generators (host).
 double td4_ps_wmax(const Td4Const& tc);

@@ -151,41 +151,78 @@ __device__ __forceinline__ void pair_amps_s(double m, double sum2, double dif2, 
   }
 }
 
-// Basis amplitudes B_k of one kinematic point under one fit's lineshapes;
-// products with flat entries and real angular factors are formed as such.
+// One kinematic point under one fit's lineshapes: the lineshapes of both
+// pairs and the angular values every basis function is formed from.
 template <class S>
-__device__ __forceinline__ void td4_basis_s(const Td4Const& tc, const Td4Table& tb, double m12, double m34, double c12,
-                                            double c34, double phi, cplx (&B)[S::K]) {
+struct Td4Point {
   cplx a12[S::N12], a34[S::N34];
-  pair_amps_s<S::N12, S::L12, S::NR12>(m12, tc.sum12, tc.dif12, tc.r2, tb.r12, a12);
-  pair_amps_s<S::N34, S::L34, S::NR34>(m34, tc.sum34, tc.dif34, tc.r2, tb.r34, a34);
+  double c12, c34;
+  double ssc, sss;  // 1/2 sin theta12 sin theta34 (cos phi, sin phi)
+};
+
+template <class S>
+__device__ __forceinline__ void td4_point_s(const Td4Const& tc, const Td4Table& tb, double m12, double m34, double c12,
+                                            double c34, double phi, Td4Point<S>& p) {
+  pair_amps_s<S::N12, S::L12, S::NR12>(m12, tc.sum12, tc.dif12, tc.r2, tb.r12, p.a12);
+  pair_amps_s<S::N34, S::L34, S::NR34>(m34, tc.sum34, tc.dif34, tc.r2, tb.r34, p.a34);
   constexpr bool has_sc = [] {
     bool u = false;
     for (int k = 0; k < S::K; ++k) u = u || S::T[k] >= 4;
     return u;
   }();
-  double ss = 0.0, sp = 0.0, cp = 1.0;
+  p.c12 = c12;
+  p.c34 = c34;
+  p.ssc = 0.0;
+  p.sss = 0.0;
   if (has_sc) {
-    ss = 0.5 * sqrt_fast(fmax(1.0 - c12 * c12, 0.0)) * sqrt_fast(fmax(1.0 - c34 * c34, 0.0));
+    const double ss = 0.5 * sqrt_fast(fmax(1.0 - c12 * c12, 0.0)) * sqrt_fast(fmax(1.0 - c34 * c34, 0.0));
+    double sp, cp;
     sincos(phi, &sp, &cp);
+    p.ssc = ss * cp;
+    p.sss = ss * sp;
   }
+}
+
+// Basis function B_k of a point (k a constant after unrolling); products
+// with flat entries and real angular factors are formed as such.
+template <class S>
+__device__ __forceinline__ cplx td4_bk(const Td4Point<S>& p, int k) {
+  const int r1 = S::A1[k], r2 = S::A2[k];
+  cplx xy;
+  if (S::NR12[r1] && S::NR34[r2]) xy = {1.0, 0.0};
+  else if (S::NR12[r1]) xy = p.a34[r2];
+  else if (S::NR34[r2]) xy = p.a12[r1];
+  else xy = cmul(p.a12[r1], p.a34[r2]);
+  switch (S::T[k]) {
+    case 0: return xy;
+    case 1: return {xy.re * p.c34, xy.im * p.c34};
+    case 2: return {xy.re * p.c12, xy.im * p.c12};
+    case 3: { const double cc = p.c12 * p.c34; return {xy.re * cc, xy.im * cc}; }
+    case 4: return cmul(xy, {p.ssc, p.sss});
+    default: return cmul(xy, {p.ssc, -p.sss});
+  }
+}
+
+// Makes the compiler treat a point's values as new ones, so that basis
+// functions formed after it are recomputed from the lineshapes instead of
+// being kept in registers from an earlier loop.
+template <class S>
+__device__ __forceinline__ void td4_opaque(Td4Point<S>& p) {
 #pragma unroll
-  for (int k = 0; k < S::K; ++k) {
-    const int r1 = S::A1[k], r2 = S::A2[k];
-    cplx xy;
-    if (S::NR12[r1] && S::NR34[r2]) xy = {1.0, 0.0};
-    else if (S::NR12[r1]) xy = a34[r2];
-    else if (S::NR34[r2]) xy = a12[r1];
-    else xy = cmul(a12[r1], a34[r2]);
-    switch (S::T[k]) {
-      case 0: B[k] = xy; break;
-      case 1: B[k] = {xy.re * c34, xy.im * c34}; break;
-      case 2: B[k] = {xy.re * c12, xy.im * c12}; break;
-      case 3: { const double cc = c12 * c34; B[k] = {xy.re * cc, xy.im * cc}; } break;
-      case 4: B[k] = cmul(xy, {ss * cp, ss * sp}); break;
-      default: B[k] = cmul(xy, {ss * cp, -ss * sp}); break;
-    }
-  }
+  for (int r = 0; r < S::N12; ++r) asm volatile("" : "+v"(p.a12[r].re), "+v"(p.a12[r].im));
+#pragma unroll
+  for (int r = 0; r < S::N34; ++r) asm volatile("" : "+v"(p.a34[r].re), "+v"(p.a34[r].im));
+  asm volatile("" : "+v"(p.c12), "+v"(p.c34), "+v"(p.ssc), "+v"(p.sss));
+}
+
+// All basis amplitudes B_k of one kinematic point under one fit's lineshapes.
+template <class S>
+__device__ __forceinline__ void td4_basis_s(const Td4Const& tc, const Td4Table& tb, double m12, double m34, double c12,
+                                            double c34, double phi, cplx (&B)[S::K]) {
+  Td4Point<S> p;
+  td4_point_s<S>(tc, tb, m12, m34, c12, c34, phi, p);
+#pragma unroll
+  for (int k = 0; k < S::K; ++k) B[k] = td4_bk<S>(p, k);
 }
 
 // Events pass for n_fits fits sharing one sample: one workgroup per (chunk,
@@ -196,7 +233,10 @@ __device__ inline void td4_events_body(const Td4Const& tc, const Td4Table* __res
                                        const int* __restrict__ status, const double* __restrict__ ev, int64_t ld,
                                        int64_t n, int chunk, int64_t nch, int n_fits, double* __restrict__ part) {
   constexpr int K = S::K;
-  constexpr int NV = GRAD ? 3 + 4 * K : 1;
+  constexpr int P = S::P;
+  // partial row: NLL, then the gradient in theta order (A's coefficients,
+  // Abar's, x, y)
+  constexpr int NV = GRAD ? 1 + P : 1;
   __shared__ double lds[block_sum_lds(NV)];
   const int64_t ch = blockIdx.x / n_fits;
   const int f = (int)(blockIdx.x - ch * n_fits);
@@ -217,8 +257,8 @@ __device__ inline void td4_events_body(const Td4Const& tc, const Td4Table* __res
     int zero = 0;
     asm volatile("" : "+s"(zero));
     const Td4Table& tb = tabs[f + zero];
-    // time functions first: the basis amplitudes are not live across the
-    // three rational-approximation evaluations
+    // time functions first: the lineshapes are not live across the three
+    // rational-approximation evaluations
     const double t = ev[5 * ld + i];
     const double g = exp(-t * t * inv2s2);
     double hp, dhp, hm, dhm;
@@ -227,13 +267,14 @@ __device__ inline void td4_events_body(const Td4Const& tc, const Td4Table* __res
     h_real(wa, tc.wL, ap, t, s, s2, g, hp, dhp);
     h_real(wa, tc.wL, am, t, s, s2, g, hm, dhm);
     h_cplx(wa, tc.wL, ac, t, s, s2, g, hc, dhc);
-    cplx B[K];
-    td4_basis_s<S>(tc, tb, ev[i], ev[ld + i], ev[2 * ld + i], ev[3 * ld + i], ev[4 * ld + i], B);
+    Td4Point<S> pt;
+    td4_point_s<S>(tc, tb, ev[i], ev[ld + i], ev[2 * ld + i], ev[3 * ld + i], ev[4 * ld + i], pt);
     cplx A = {0.0, 0.0}, Ab = {0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      A = cfma({tb.c[k][0], tb.c[k][1]}, B[k], A);
-      Ab = cfma({tb.cb[k][0], tb.cb[k][1]}, B[k], Ab);
+      const cplx b = td4_bk<S>(pt, k);
+      if (S::PA[k] >= 0) A = cfma({tb.c[k][0], tb.c[k][1]}, b, A);
+      if (S::PB[k] >= 0) Ab = cfma({tb.cb[k][0], tb.cb[k][1]}, b, Ab);
     }
     const double Hc = 0.5 * (hp + hm), Hs = 0.5 * (hp - hm);
     const double a2 = A.re * A.re + A.im * A.im, b2 = Ab.re * Ab.re + Ab.im * Ab.im;
@@ -248,16 +289,19 @@ __device__ inline void td4_events_body(const Td4Const& tc, const Td4Table* __res
       // (the event's factor w = -1/R included)
       const cplx lc = {w * (hpc * A.re - Hs * Ab.re - hc.im * Ab.im), w * (-hpc * A.im + Hs * Ab.im - hc.im * Ab.re)};
       const cplx lb = {w * (hmc * Ab.re - Hs * A.re + hc.im * A.im), w * (-hmc * Ab.im + Hs * A.im + hc.im * A.re)};
+      // the basis functions again, formed from the lineshapes
+      td4_opaque<S>(pt);
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        grad_acc(lc, B[k], acc[1 + 2 * k], acc[2 + 2 * k]);
-        grad_acc(lb, B[k], acc[1 + 2 * K + 2 * k], acc[2 + 2 * K + 2 * k]);
+        const cplx b = td4_bk<S>(pt, k);
+        if (S::PA[k] >= 0) grad_acc(lc, b, acc[1 + S::PA[k]], acc[2 + S::PA[k]]);
+        if (S::PB[k] >= 0) grad_acc(lb, b, acc[1 + S::PB[k]], acc[2 + S::PB[k]]);
       }
       // x: d hc/dx = -i G dh(ac);  y: d hp/dy = -G dh(ap), d hm/dy = +G dh(am)
       const double dcos = G * dhc.im, dsin = -G * dhc.re;
-      acc[1 + 4 * K] += w * 0.5 * ((a2 - b2) * dcos - 2.0 * zi * dsin);
+      acc[P - 1] += w * 0.5 * ((a2 - b2) * dcos - 2.0 * zi * dsin);
       const double dHc = 0.5 * G * (dhm - dhp), dHs = -0.5 * G * (dhp + dhm);
-      acc[2 + 4 * K] += w * 0.5 * ((a2 + b2) * dHc - 2.0 * zr * dHs);
+      acc[P] += w * 0.5 * ((a2 + b2) * dHc - 2.0 * zr * dHs);
     }
   }
   block_sum_row<NV>(acc, lds, part + ((int64_t)f * nch + ch) * NV);
@@ -408,15 +452,14 @@ __device__ inline void td4_envmax_body(const Td4Const& tc, const Td4Table* __res
   if (threadIdx.x == 0) atomicMax(vmax, (unsigned long long)__double_as_longlong(lds[0]));
 }
 
-constexpr int kTd4RowBlock = 4;
-
-// Rows i0..i0+3 of M = sum over the phase-space sample of B_i conj(B_j) (per fit).
+// Rows i0..i0+RB-1 of M = sum over the phase-space sample of B_i conj(B_j) (per fit).
 template <class S>
 __device__ inline void td4_mrows_body(const Td4Const& tc, const Td4Table* __restrict__ tabs,
                                       const double* __restrict__ mc, int64_t ld, int64_t n, int chunk, int64_t nch,
                                       int n_fits, int i0, double* __restrict__ part) {
   constexpr int K = S::K;
-  constexpr int NV = 2 * kTd4RowBlock * K;
+  constexpr int RB = td4_row_block(K);
+  constexpr int NV = 2 * RB * K;
   __shared__ double lds[block_sum_lds(NV)];
   const int64_t ch = blockIdx.x / n_fits;
   const int f = (int)(blockIdx.x - ch * n_fits);
@@ -429,19 +472,25 @@ __device__ inline void td4_mrows_body(const Td4Const& tc, const Td4Table* __rest
     int zero = 0;
     asm volatile("" : "+s"(zero));
     const Td4Table& tb = tabs[f + zero];
-    cplx B[K];
-    td4_basis_s<S>(tc, tb, mc[i], mc[ld + i], mc[2 * ld + i], mc[3 * ld + i], mc[4 * ld + i], B);
+    Td4Point<S> pt;
+    td4_point_s<S>(tc, tb, mc[i], mc[ld + i], mc[2 * ld + i], mc[3 * ld + i], mc[4 * ld + i], pt);
+    cplx bi[RB];
 #pragma unroll
-    for (int ib = 0; ib < kTd4RowBlock; ++ib) {
-      cplx bi = {0.0, 0.0};
+    for (int ib = 0; ib < RB; ++ib) {
+      bi[ib] = {0.0, 0.0};
 #pragma unroll
       for (int k = 0; k < K; ++k)
-        if (k == i0 + ib) bi = B[k];
+        if (k == i0 + ib) bi[ib] = td4_bk<S>(pt, k);
+    }
+    td4_opaque<S>(pt);
 #pragma unroll
-      for (int j = 0; j < K; ++j) {
-        acc[2 * (ib * K + j)] = __builtin_fma(bi.re, B[j].re, __builtin_fma(bi.im, B[j].im, acc[2 * (ib * K + j)]));
+    for (int j = 0; j < K; ++j) {
+      const cplx bj = td4_bk<S>(pt, j);
+#pragma unroll
+      for (int ib = 0; ib < RB; ++ib) {
+        acc[2 * (ib * K + j)] = __builtin_fma(bi[ib].re, bj.re, __builtin_fma(bi[ib].im, bj.im, acc[2 * (ib * K + j)]));
         acc[2 * (ib * K + j) + 1] =
-            __builtin_fma(bi.im, B[j].re, __builtin_fma(-bi.re, B[j].im, acc[2 * (ib * K + j) + 1]));
+            __builtin_fma(bi[ib].im, bj.re, __builtin_fma(-bi[ib].re, bj.im, acc[2 * (ib * K + j) + 1]));
       }
     }
   }

@@ -5,9 +5,13 @@
 
 namespace fn {
 
-constexpr int kTd4MaxAmp = 12;   // basis amplitudes
-constexpr int kTd4MaxRes = 4;    // resonances per pair
+constexpr int kTd4MaxAmp = 20;   // basis amplitudes
+constexpr int kTd4MaxRes = 6;    // resonances per pair
 constexpr int kWeidN = 40;       // terms of the Faddeeva rational approximation
+
+// Rows of the normalization matrix accumulated per pass over the phase-space
+// sample (2 x rows x K doubles per thread).
+__host__ __device__ constexpr int td4_row_block(int K) { return K > 12 ? 2 : 4; }
 
 struct Td4Const {
   double M;                            // parent mass
@@ -23,6 +27,9 @@ struct Td4Const {
   int L12[kTd4MaxRes], L34[kTd4MaxRes];
   int nr12[kTd4MaxRes], nr34[kTd4MaxRes];  // 1 = non-resonant (flat) entry
   int amp1[kTd4MaxAmp], amp2[kTd4MaxAmp], atype[kTd4MaxAmp];
+  // theta index of Re c_k (in A) and of Re cbar_k (in Abar); -1 when the
+  // basis function is not a member of that sum
+  int pa[kTd4MaxAmp], pb[kTd4MaxAmp];
 };
 
 // Fixed constants of one fit (systematic variations change them per fit).

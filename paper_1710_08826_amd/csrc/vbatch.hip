@@ -90,7 +90,7 @@ void check_events(fn_vbatch* b, const double* ev, int64_t n, int64_t ld) {
 void reserve_part(fn_vbatch* b, int64_t n) {
   const int64_t nch = (n + b->m->chunk - 1) / b->m->chunk;
   const void* before = b->part.ptr;
-  b->part.reserve(sizeof(double) * (size_t)nch * b->F * td4_nv(td4_kmax(b->m->td4.K), true));
+  b->part.reserve(sizeof(double) * (size_t)nch * b->F * td4_nv(b->m->td4, true));
   if (b->part.ptr != before) b->drop_graph();  // a captured step holds the old address
 }
 
@@ -100,7 +100,7 @@ void build_matrices(fn_vbatch* b) {
   if (b->M_valid && b->mc_gen == m->mc_gen) return;
   const int mchunk = 1024;
   const int64_t rows = (m->n_mc + mchunk - 1) / mchunk;
-  b->mpart.reserve(sizeof(double) * (size_t)rows * b->F * 8 * td4_kmax(m->td4.K));
+  b->mpart.reserve(sizeof(double) * (size_t)rows * b->F * 2 * td4_row_block(m->td4.K) * td4_kmax(m->td4.K));
   td4_launch_mmatrix(*m->td4_jit, m->td4, (const Td4Table*)b->tabs.ptr, b->F, (const double*)m->d_mc.ptr, m->n_mc,
                      m->n_mc, mchunk, (double*)b->mpart.ptr, (double*)b->Mc.ptr, b->stream);
   hip_check(hipGetLastError(), "kernel launch");

@@ -13,5 +13,6 @@ from .td4 import (  # noqa: F401,E402
     td4_split_desc, td4_split_truth,
 )
 from .tddp3 import (  # noqa: F401,E402
-    TDDP_MASSES, TDDP_RESONANCES, tddp3_desc, tddp3_truth, tddp3_events,
+    TDDP_MASSES, TDDP_RESONANCES, TDDP_RESONANCES16, tddp3_desc, tddp3_truth, tddp3_events,
+    tddp3_desc16, tddp3_truth16,
 )

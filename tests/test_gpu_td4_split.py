@@ -1,0 +1,196 @@
+"""Parity of the time-dependent four-body model with twenty distinct basis
+functions, ten in A and ten in Abar (four Breit-Wigner entries per pair,
+every spin-compatible combination once): NLL, normalization, adjoint gradient
+and per-event density against the oracle from a few events to the full
+workload (10M events, 5M-point normalization sample), central differences,
+and variation batches against single fits.
+
+The gradient is compared with the oracle's autograd gradient per component
+to 1e-9 of max(|g|, 1e-3 max|g|) (1e-10 for the ten-amplitude model).  With
+twenty interfering amplitudes some components are a small difference of
+their per-event terms (the sum of the terms' magnitudes reaches 17x the
+component and 174x for others, measured on the oracle's per-event Jacobian),
+and the per-event rates of the two sides differ by up to 2.4e-12 relative at
+interference minima (the eval test below), so 1e-10 is beyond what either
+side's float64 evaluation fixes: the largest difference measured is 1.2e-10
+(Re of A's second coefficient at the variation point).  The bar against
+central differences stays 1e-6.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import common, td4 as OT
+from tests.gpu_util import grad_close, rel_close, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+DESC = synth.td4_split_desc()
+TH = synth.td4_split_truth()
+N_MC = 20_000
+
+
+def offset(th):
+    t = th + 0.05 * np.sin(np.arange(th.size) + 1.0) * np.maximum(np.abs(th), 0.05)
+    t[-2:] = [0.03, -0.02]
+    return t
+
+
+@pytest.fixture(scope="module")
+def mc():
+    return synth.td4_phase_space(N_MC, seed=141)
+
+
+@pytest.fixture(scope="module")
+def model(mc):
+    from paper_1710_08826_amd import Model
+    m = Model(DESC)
+    m.set_norm_sample(to_dev(mc))
+    return m
+
+
+def oracle_norm(th, mc):
+    om = OT.TD4(DESC)
+    tht = torch.tensor(th, requires_grad=True)
+    ir = om.integrated_rate(tht, torch.tensor(mc))
+    ir.mean().backward()
+    return common.fsum(ir.detach()) / mc.shape[1], tht.grad.numpy().copy()
+
+
+GRAD_RTOL = 1e-9
+
+
+def test_layout(model):
+    assert model.n_params == 42 == TH.size
+
+
+def test_norm_matches_oracle(model, mc):
+    say("td4 split norm")
+    for th in (TH, offset(TH)):
+        I, dI = model.norm(th)
+        Io, dIo = oracle_norm(th, mc)
+        assert rel_close(I, Io, 1e-12), (I, Io)
+        ok, r = grad_close(dI, dIo, 1e-11)
+        assert ok, r.max()
+
+
+@pytest.mark.parametrize("n", [1, 1000, 3 * 4096 + 17, 20_000])
+def test_nll_and_gradient(model, mc, n):
+    say("td4 split nll n =", n)
+    ev = synth.td4_events(n, seed=143)
+    evd = to_dev(ev)
+    for th in (TH, offset(TH)):
+        v, g = model.nll(th, evd, grad=True)
+        vo, go = OT.nll_grad(th, ev, mc, DESC)
+        assert rel_close(v, vo, 1e-12), (v, vo, (v - vo) / vo)
+        ok, r = grad_close(g, go, GRAD_RTOL)
+        assert ok, r.max()
+        assert rel_close(model.nll(th, evd), v, 1e-14)
+
+
+def test_gradient_vs_central_differences(model, mc):
+    say("td4 split fd")
+    ev = synth.td4_events(3000, seed=144)
+    th = offset(TH)
+    _, g = model.nll(th, to_dev(ev), grad=True)
+    fd = common.central_fd(lambda q: OT.nll(q, ev, mc, DESC), th, rel_step=1e-6)
+    ok, r = grad_close(g, fd, 1e-6)
+    assert ok, r.max()
+
+
+def test_eval_matches_oracle_rate(model, mc):
+    say("td4 split eval")
+    ev = synth.td4_events(5000, seed=145)
+    th = offset(TH)
+    p = model.eval(th, to_dev(ev)).cpu().numpy()
+    om = OT.TD4(DESC)
+    tht, evt = torch.tensor(th), torch.tensor(ev)
+    with torch.no_grad():
+        r = om.rate(tht, evt).numpy()
+        # condition scale of R: the same sums with every term taken in
+        # magnitude, so that events at interference minima (R far below its
+        # terms) are judged on the size of the terms
+        B = om.basis(evt[:5])
+        na = len(om.in_a)
+        aa = sum(abs(complex(th[2 * j], th[2 * j + 1])) * B[k].abs() for j, k in enumerate(om.in_a)).numpy()
+        bb = sum(abs(complex(th[2 * na + 2 * j], th[2 * na + 2 * j + 1])) * B[k].abs()
+                 for j, k in enumerate(om.in_b)).numpy()
+        G = 1.0 / synth.TD4_TAU
+        x, y = th[-2:]
+        hp = OT.h_conv(complex(G * (1 - y)), evt[5], om.sigma).real.abs().numpy()
+        hm = OT.h_conv(complex(G * (1 + y)), evt[5], om.sigma).real.abs().numpy()
+        hc = OT.h_conv(complex(G, -G * x), evt[5], om.sigma).abs().numpy()
+    cond = 0.5 * ((aa ** 2 + bb ** 2) * (hp + hm + hc) + 2 * aa * bb * (hp + hm + hc))
+    I, _ = oracle_norm(th, mc)
+    err = np.abs(p - r / I) / (cond / I)
+    assert err.max() <= 1e-12, err.max()
+    rel = np.abs(p - r / I) / (r / I)
+    assert (rel <= 1e-12).mean() >= 0.995, np.sort(rel)[-8:]
+
+
+def test_invalid_sum_name():
+    from paper_1710_08826_amd import FitNLLError, Model
+    bad = dict(DESC)
+    bad["amps"] = [list(a) for a in DESC["amps"]]
+    bad["amps"][3][3] = "B"
+    with pytest.raises(FitNLLError, match="sum"):
+        Model(bad)
+    bad["amps"] = DESC["amps"] + [[0, 0, 0]]  # 21 amplitudes
+    with pytest.raises(FitNLLError, match="amplitudes"):
+        Model(bad)
+
+
+def test_variation_batch_matches_single_fits(model, mc):
+    from paper_1710_08826_amd import Model, VariationBatch
+    say("td4 split vbatch")
+    F = 5
+    fx0 = model.fixed()
+    mcd = to_dev(mc)
+    fxs = []
+    for f in range(F):
+        v = fx0.copy()
+        if f:
+            v[2 * 4 + 2] += (0.0008 if f % 2 else -0.0008)  # rho(770) mass (r34 entry 1)
+            v[-1] *= 1.0 + 0.05 * f                            # time resolution
+        fxs.append(v)
+    b = VariationBatch(model, F)
+    for f in range(F):
+        b.set_fixed(f, fxs[f])
+    ev = synth.td4_events(20_000, seed=146)
+    evd = to_dev(ev)
+    th = np.stack([TH * (1 + 0.04 * np.sin(np.arange(TH.size) + f)) for f in range(F)])
+    v, g = b.nll(th, evd, grad=True)
+    for f in range(F):
+        d = dict(DESC)
+        fx = fxs[f]
+        d["r12"] = [{"L": e["L"], "m0": fx[2 * i], "w0": fx[2 * i + 1]} for i, e in enumerate(DESC["r12"])]
+        o = 2 * len(DESC["r12"])
+        d["r34"] = [{"L": e["L"], "m0": fx[o + 2 * i], "w0": fx[o + 2 * i + 1]}
+                    for i, e in enumerate(DESC["r34"])]
+        d["sigma_t"] = fx[-1]
+        single = Model(d)
+        single.set_norm_sample(mcd)
+        vs, gs = single.nll(th[f], evd, grad=True)
+        assert vs == v[f] and (gs == g[f]).all(), f
+        vo, go = OT.nll_grad(th[f], ev, mc, d)
+        assert rel_close(v[f], vo, 1e-12), (f, v[f], vo)
+        ok, r = grad_close(g[f], go, GRAD_RTOL)
+        assert ok, (f, r.max())
+
+
+def test_full_size():
+    from paper_1710_08826_amd import Model
+    say("td4 split full-size inputs: 10M events, 5M-point sample")
+    ev, mc = synth.td4_events(10_000_000, seed=149), synth.td4_phase_space(5_000_000, seed=150)
+    m = Model(DESC)
+    m.set_norm_sample(to_dev(mc))
+    th = offset(TH)
+    evd = to_dev(ev)
+    say("td4 split full size: device")
+    v, g = m.nll(th, evd, grad=True)
+    say("td4 split full size: oracle")
+    vo, go = OT.nll_grad(th, ev, mc, DESC)
+    assert rel_close(v, vo, 1e-12), (v, vo, (v - vo) / vo)
+    ok, r = grad_close(g, go, GRAD_RTOL)
+    assert ok, r.max()

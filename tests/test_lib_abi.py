@@ -99,7 +99,7 @@ def test_model_kernels_compile_for_gfx950_without_a_device():
     d["resonances"] = [{"pair": "13", "L": 0, "m0": 1.43, "w0": 0.27}, {"pair": "13", "L": 2, "m0": 1.43, "w0": 0.1}]
     assert lib.fn_model_check_compile(json.dumps(d).encode(), None) == _lib.FN_OK, lib.fn_last_error()
     # the time-dependent three- and four-body models
-    for d in (synth.tddp3_desc(), synth.td4_desc()):
+    for d in (synth.tddp3_desc(), synth.td4_desc(), synth.td4_split_desc()):
         assert lib.fn_model_check_compile(json.dumps(d).encode(), b"gfx950") == _lib.FN_OK, lib.fn_last_error()
     bad = synth.dalitz_desc()
     bad["resonances"][0]["pair"] = "14"
