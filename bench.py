@@ -379,26 +379,65 @@ def cpu_baselines_other():
     return out
 
 
-def pmc_probe(steps: int, chunk: int):
+def pmc_probe(steps: int, chunk: int, workload: str = "config1"):
     """Workload for hardware-counter runs: a plain 256 MiB copy (its counter
-    reading calibrates bytes per counter unit), then config-1 NLL+gradient
-    steps at the given summation chunk."""
+    reading calibrates bytes per counter unit), then `steps` NLL+gradient
+    evaluations of one workload: config1 (Dalitz, 1M events, at the given
+    summation chunk), config3 (free lineshapes, 4M events), tddp3 (sixteen
+    resonances, 1M events), td4 (twenty amplitudes, 10M events), td4batch (64
+    variation fits of td4), config0mall (1-D mixture, 2^26 events)."""
     import torch
     import synth
-    from paper_1710_08826_amd import Model
+    from paper_1710_08826_amd import Model, VariationBatch
     src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")  # 256 MiB
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
-    ev = torch.from_numpy(synth.dalitz_events(1_000_000, seed=synth.BASE_SEED)).cuda()
-    m = Model(synth.dalitz_desc(chunk=chunk))
-    th = torch.from_numpy(synth.dalitz_truth()).cuda()
+    del src, dst
+    seed = synth.BASE_SEED
+    batch = None
+    if workload == "config1":
+        ev = torch.from_numpy(synth.dalitz_events(1_000_000, seed=seed)).cuda()
+        m = Model(synth.dalitz_desc(chunk=chunk))
+        th = synth.dalitz_truth()
+    elif workload == "config3":
+        ev = torch.from_numpy(synth.dalitz_events(4_000_000, seed=seed + 3)).cuda()
+        m = Model(synth.dalitz_desc(free_lineshapes=True))
+        th = synth.dalitz_truth(free_lineshapes=True)
+    elif workload == "tddp3":
+        res = synth.TDDP_RESONANCES16
+        ev = torch.from_numpy(synth.tddp3_events(1_000_000, seed=seed + 7, resonances=res)).cuda()
+        m = Model(synth.tddp3_desc(resonances=res))
+        th = synth.tddp3_truth(resonances=res)
+    elif workload in ("td4", "td4batch"):
+        ev = torch.from_numpy(synth.td4_events(10_000_000, seed=seed + 4)).cuda()
+        m = Model(synth.td4_split_desc(chunk=8192))
+        m.generate_norm_sample(5_000_000, seed=seed + 5)
+        th = synth.td4_split_truth()
+        if workload == "td4batch":
+            batch = VariationBatch(m, 64)
+            fx = m.fixed()
+            for f in range(64):
+                v = fx.copy()
+                v[-1] *= 1.0 + 0.002 * (f - 32)
+                batch.set_fixed(f, v)
+            ths = np.stack([th * (1.0 + 1e-3 * np.sin(np.arange(th.size) + f)) for f in range(64)])
+    elif workload == "config0mall":
+        ev = torch.from_numpy(synth.mix1d_events(1 << 26, seed=seed + 1)[None, :]).cuda()
+        m = Model(dict(synth.mix1d_desc(), chunk=1024))
+        th = synth.mix1d_truth()
+    else:
+        raise ValueError(workload)
+    tdev = torch.from_numpy(np.asarray(th, dtype=np.float64)).cuda()
     out = torch.empty(1 + m.n_params, dtype=torch.float64, device="cuda")
     for _ in range(steps):
-        m.nll_async(th, ev, out, True)
+        if batch is not None:
+            batch.nll(ths, ev, grad=True)
+        else:
+            m.nll_async(tdev, ev, out, True)
     torch.cuda.synchronize()
-    print(json.dumps({"pmc_probe": True, "copy_bytes": 2 * src.numel() * 8, "steps": steps, "chunk": m.chunk,
-                      "nll": float(out[0])}), flush=True)
+    print(json.dumps({"pmc_probe": workload, "copy_bytes": 2 * 32 * 1024 * 1024 * 8, "steps": steps,
+                      "chunk": m.chunk, "nll": float(out[0]) if batch is None else None}), flush=True)
 
 
 def serving_leg(n_fits: int = 4096, fd_fits: int = 32, lam_frac: float = 0.7):
@@ -559,17 +598,19 @@ def config3_fits(m3, th3, n: int = 4_000_000):
     return out
 
 
-def tddp3_leg(steps: int = 50):
+def tddp3_leg(steps: int = 50, k16: bool = True):
     """Time-dependent Dalitz-plot fit (the paper's pi+ pi- pi0 mixing
-    workload class): 1M events, 34 parameters, NLL + adjoint gradient, and the
-    plain finite-difference gradient (2P + 1 NLL-only calls)."""
+    workload class): 1M events, sixteen resonances (66 parameters; eight
+    resonances and 34 parameters with k16 False), NLL + adjoint gradient, and
+    the plain finite-difference gradient (2P + 1 NLL-only calls)."""
     import torch
     import synth
     from paper_1710_08826_amd import Model
     n = 1_000_000
-    desc = synth.tddp3_desc()
-    th = synth.tddp3_truth()
-    ev = torch.from_numpy(synth.tddp3_events(n, seed=synth.BASE_SEED + 7)).cuda()
+    res = synth.TDDP_RESONANCES16 if k16 else synth.TDDP_RESONANCES
+    desc = synth.tddp3_desc(resonances=res)
+    th = synth.tddp3_truth(resonances=res)
+    ev = torch.from_numpy(synth.tddp3_events(n, seed=synth.BASE_SEED + 7, resonances=res)).cuda()
     m = Model(desc)
     P = m.n_params
     _, tune_us = m.autotune(th, ev, reps=10)
@@ -580,7 +621,7 @@ def tddp3_leg(steps: int = 50):
     w0, k0, _ = time_async(m, tdev, ev, out, steps, 3, False, alt=tb)
     fl = tddp3_flops_per_event(desc, True)
     fd_step = (2 * P + 1) * w0 / steps
-    return {"events": n, "params": P, "grid": desc["grid"], "chunk": m.chunk,
+    return {"resonances": len(res), "events": n, "params": P, "grid": desc["grid"], "chunk": m.chunk,
             "autotune_us": {str(c): v for c, v in tune_us.items()},
             "events_per_s": n * steps / w, "ms_per_step": 1e3 * w / steps,
             "event_kernel_us": k * 1e3, "nll_only_event_kernel_us": k0 * 1e3,
@@ -599,11 +640,12 @@ def tddp3_whole_fit(m, th, n):
     import synth
     ev, _ = m.generate(th, n, seed=synth.BASE_SEED + 8)
     P = th.size
+    K = (P - 2) // 4
     free = np.zeros(P, np.int32)
-    free[2:16] = 1
+    free[2:2 * K] = 1
     free[-2:] = 1
     start = th.copy()
-    start[2:16] *= 1.03
+    start[2:2 * K] *= 1.03
     start[-2:] *= 1.5
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -730,9 +772,10 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="time direct launches instead of captured steps")
     ap.add_argument("--leg", choices=["td4", "serve", "tddp3", "config3", "config0-mall", "cpu"],
                     help="run only the four-body leg or the serving leg and print its figures (for profiling)")
-    ap.add_argument("--pmc-probe", action="store_true",
+    ap.add_argument("--pmc-probe", nargs="?", const="config1",
+                    choices=["config1", "config3", "tddp3", "td4", "td4batch", "config0mall"],
                     help="for counter runs: one 256 MiB device copy (calibration) then --steps "
-                         "config-1 steps, nothing printed but a summary line")
+                         "NLL+gradient steps of one workload, nothing printed but a summary line")
     ap.add_argument("--chunk", type=int, default=2048, help="summation chunk of the --pmc-probe steps")
     ap.add_argument("--chunk-c1", type=int, default=0,
                     help="config-1 summation chunk instead of the autotuner's choice (profiling runs)")
@@ -742,7 +785,7 @@ def main():
               "(sharding events or fits across GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
     if args.pmc_probe:
-        pmc_probe(args.steps, args.chunk)
+        pmc_probe(args.steps, args.chunk, args.pmc_probe)
         return
     if args.leg == "td4":
         ev4, gen_s = td4_events_device()
@@ -754,7 +797,7 @@ def main():
         print(json.dumps({"config2_serving": serving_leg()}), flush=True)
         return
     if args.leg == "tddp3":
-        print(json.dumps({"tddp3": tddp3_leg()}), flush=True)
+        print(json.dumps({"tddp3": tddp3_leg(), "tddp3_8res": tddp3_leg(k16=False)}), flush=True)
         return
     if args.leg == "config3":
         print(json.dumps(config3_leg()), flush=True)
@@ -867,12 +910,15 @@ def main():
               f"fd {extra['config0_fit_fd_ms']:.2f} ms", file=sys.stderr, flush=True)
 
     if not args.quick:
-        print("[bench] time-dependent Dalitz (pi+ pi- pi0-like, 8 resonances, 1M events) ...", file=sys.stderr,
-              flush=True)
+        print("[bench] time-dependent Dalitz (pi+ pi- pi0-like, 16 and 8 resonances, 1M events) ...",
+              file=sys.stderr, flush=True)
         extra["tddp3"] = tddp3_leg()
-        t3 = extra["tddp3"]
-        print(f"[bench] tddp3: {t3['events_per_s']:.4g} events/s ({t3['event_kernel_tflops']:.2f} TFLOP/s), "
-              f"adjoint vs FD {t3['adjoint_vs_plain_fd']:.1f}x", file=sys.stderr, flush=True)
+        extra["tddp3_8res"] = tddp3_leg(k16=False)
+        for key in ("tddp3", "tddp3_8res"):
+            t3 = extra[key]
+            print(f"[bench] {key} ({t3['resonances']} resonances): {t3['events_per_s']:.4g} events/s "
+                  f"({t3['event_kernel_tflops']:.2f} TFLOP/s), adjoint vs FD {t3['adjoint_vs_plain_fd']:.1f}x, "
+                  f"whole fit {t3['fit_wall_s']:.3f} s", file=sys.stderr, flush=True)
 
     if not args.quick:
         print("[bench] config4 td4 (10M events, 5M-point sample, 64 variation fits) ...", file=sys.stderr,

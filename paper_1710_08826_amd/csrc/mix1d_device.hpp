@@ -34,7 +34,9 @@ __device__ inline double lower_gamma_half(int twice_a, double y) {
 // theta -> per-fit table: fractions, 1/N_k and d ln N_k / d(parameters) of
 // each component from its closed-form integral on [lo, hi], shape constants.
 __device__ inline void mix1d_table(const Mix1dConst& mc, const double* __restrict__ th, Mix1dTable& out) {
-  Mix1dTable t;
+  // written in place: the components are indexed at run time, so a local
+  // copy of the table would live in scratch memory
+  Mix1dTable& t = out;
   bool ok = true;
   const double lo = mc.lo, hi = mc.hi;
   double rest = 1.0;
@@ -120,7 +122,6 @@ __device__ inline void mix1d_table(const Mix1dConst& mc, const double* __restric
   t.yield = mc.yidx >= 0 ? th[mc.yidx] : 0.0;
   if (mc.yidx >= 0 && !(t.yield > 0.0 && isfinite(t.yield))) ok = false;
   t.valid = ok ? 1.0 : 0.0;
-  out = t;
 }
 
 // Component shape s(x) and d ln s / d(its parameters).

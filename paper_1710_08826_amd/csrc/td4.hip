@@ -88,7 +88,7 @@ __global__ void td4_prologue(Td4Const tc, ParamBlock pb, const double* __restric
   if (f >= n_fits || (status && status[f] != 1)) return;
   const double* th = theta ? theta + (int64_t)f * theta_stride : pb.v;
   const Td4FitConst& fc = fcs[f];
-  Td4Table t;
+  Td4Table& t = tabs[f];  // written in place (a local copy of the table spills to scratch)
   bool ok = fc.sigma > 0.0;
   auto lineshape = [&](double m0, double w0, int L, double sum2, double dif2, double* out) {
     const double x = m0 * m0;
@@ -121,7 +121,6 @@ __global__ void td4_prologue(Td4Const tc, ParamBlock pb, const double* __restric
   t.sigma = fc.sigma;
   if (!(fabs(t.y) < 1.0) || !isfinite(t.x)) ok = false;
   t.valid = ok ? 1.0 : 0.0;
-  tabs[f] = t;
 }
 
 // ---------------------------------------------------- normalization matrix
@@ -158,7 +157,9 @@ __global__ __launch_bounds__(kFinalBlock) void td4_finalize(Td4Const tc, const T
   __shared__ double scratch[kFinalBlock];
   __shared__ double res[kBlock];
   __shared__ double M[2 * kTd4MaxAmp * kTd4MaxAmp];
-  __shared__ double gI[4 * kTd4MaxAmp + 2];  // dI/dtheta in theta order
+  __shared__ double XYUV[8][kTd4MaxAmp];       // Re, Im of X, Y, U, V per amplitude
+  __shared__ double gI[4 * kTd4MaxAmp + 2];    // dI/dtheta in theta order
+  __shared__ double form[4];                   // a, b, Re z, Im z
   __shared__ double Ish;
   const int f = blockIdx.x;
   if (status && status[f] != 1) return;
@@ -169,48 +170,63 @@ __global__ __launch_bounds__(kFinalBlock) void td4_finalize(Td4Const tc, const T
   for (int i = t; i < 2 * kTd4MaxAmp * kTd4MaxAmp; i += kFinalBlock)
     M[i] = Mc[(int64_t)f * 2 * kTd4MaxAmp * kTd4MaxAmp + i];
   __syncthreads();
+  auto m = [&](int i, int j) { return cplx{M[2 * (i * kTd4MaxAmp + j)], M[2 * (i * kTd4MaxAmp + j) + 1]}; };
+  // thread k < K: the k-th entries of the four matrix-vector products
+  if (t < K) {
+    const int k = t;
+    double Xr = 0.0, Xi = 0.0, Yr = 0.0, Yi = 0.0, Ur = 0.0, Ui = 0.0, Vr = 0.0, Vi = 0.0;
+    for (int j = 0; j < K; ++j) {
+      const cplx mkj = m(k, j), mjk = m(j, k);
+      const double cjr = tb.c[j][0], cji = tb.c[j][1], bjr = tb.cb[j][0], bji = tb.cb[j][1];
+      // X_k += M_kj conj(c_j), Y_k += M_kj conj(cb_j)
+      Xr += mkj.re * cjr + mkj.im * cji;
+      Xi += mkj.im * cjr - mkj.re * cji;
+      Yr += mkj.re * bjr + mkj.im * bji;
+      Yi += mkj.im * bjr - mkj.re * bji;
+      // U_k += cb_j M_jk, V_k += conj(c_j) M_kj
+      Ur += bjr * mjk.re - bji * mjk.im;
+      Ui += bjr * mjk.im + bji * mjk.re;
+      Vr += cjr * mkj.re + cji * mkj.im;
+      Vi += cjr * mkj.im - cji * mkj.re;
+    }
+    XYUV[0][k] = Xr; XYUV[1][k] = Xi; XYUV[2][k] = Yr; XYUV[3][k] = Yi;
+    XYUV[4][k] = Ur; XYUV[5][k] = Ui; XYUV[6][k] = Vr; XYUV[7][k] = Vi;
+  }
+  __syncthreads();
+  const double G = tc.gamma, x = tb.x, y = tb.y;
+  const double cy = 1.0 / (G * (1.0 - y * y)), cx = 1.0 / (G * (1.0 + x * x));
   if (t == 0) {
-    const double G = tc.gamma, x = tb.x, y = tb.y;
-    const double cy = 1.0 / (G * (1.0 - y * y)), cx = 1.0 / (G * (1.0 + x * x));
-    auto m = [&](int i, int j) { return cplx{M[2 * (i * kTd4MaxAmp + j)], M[2 * (i * kTd4MaxAmp + j) + 1]}; };
+    // the quadratic forms, summed over k in order
     double a = 0.0, b = 0.0, zr = 0.0, zi = 0.0;
-    double Xr[kTd4MaxAmp], Xi[kTd4MaxAmp], Yr[kTd4MaxAmp], Yi[kTd4MaxAmp];
-    double Ur[kTd4MaxAmp], Ui[kTd4MaxAmp], Vr[kTd4MaxAmp], Vi[kTd4MaxAmp];
     for (int k = 0; k < K; ++k) {
-      Xr[k] = Xi[k] = Yr[k] = Yi[k] = Ur[k] = Ui[k] = Vr[k] = Vi[k] = 0.0;
-      for (int j = 0; j < K; ++j) {
-        const cplx mkj = m(k, j), mjk = m(j, k);
-        const double cjr = tb.c[j][0], cji = tb.c[j][1], bjr = tb.cb[j][0], bji = tb.cb[j][1];
-        // X_k += M_kj conj(c_j), Y_k += M_kj conj(cb_j)
-        Xr[k] += mkj.re * cjr + mkj.im * cji;
-        Xi[k] += mkj.im * cjr - mkj.re * cji;
-        Yr[k] += mkj.re * bjr + mkj.im * bji;
-        Yi[k] += mkj.im * bjr - mkj.re * bji;
-        // U_k += cb_j M_jk, V_k += conj(c_j) M_kj
-        Ur[k] += bjr * mjk.re - bji * mjk.im;
-        Ui[k] += bjr * mjk.im + bji * mjk.re;
-        Vr[k] += cjr * mkj.re + cji * mkj.im;
-        Vi[k] += cjr * mkj.im - cji * mkj.re;
-      }
-      a += tb.c[k][0] * Xr[k] - tb.c[k][1] * Xi[k];
-      b += tb.cb[k][0] * Yr[k] - tb.cb[k][1] * Yi[k];
+      a += tb.c[k][0] * XYUV[0][k] - tb.c[k][1] * XYUV[1][k];
+      b += tb.cb[k][0] * XYUV[2][k] - tb.cb[k][1] * XYUV[3][k];
       // z = sum_k conj(c_k) U_k
-      zr += tb.c[k][0] * Ur[k] + tb.c[k][1] * Ui[k];
-      zi += tb.c[k][0] * Ui[k] - tb.c[k][1] * Ur[k];
+      zr += tb.c[k][0] * XYUV[4][k] + tb.c[k][1] * XYUV[5][k];
+      zi += tb.c[k][0] * XYUV[5][k] - tb.c[k][1] * XYUV[4][k];
     }
-    const double I = 0.5 * ((a + b) * cy + (a - b) * cx - 2.0 * zr * y * cy - 2.0 * zi * x * cx);
-    Ish = I;
-    for (int k = 0; k < K; ++k) {
-      const int ia = tc.pa[k], ib = tc.pb[k];
-      if (ia >= 0) {
-        gI[ia] = 0.5 * ((cy + cx) * 2.0 * Xr[k] - 2.0 * y * cy * Ur[k] - 2.0 * x * cx * Ui[k]);
-        gI[ia + 1] = 0.5 * (-2.0 * (cy + cx) * Xi[k] - 2.0 * y * cy * Ui[k] + 2.0 * x * cx * Ur[k]);
-      }
-      if (ib >= 0) {
-        gI[ib] = 0.5 * ((cy - cx) * 2.0 * Yr[k] - 2.0 * y * cy * Vr[k] - 2.0 * x * cx * Vi[k]);
-        gI[ib + 1] = 0.5 * (-2.0 * (cy - cx) * Yi[k] + 2.0 * y * cy * Vi[k] - 2.0 * x * cx * Vr[k]);
-      }
+    form[0] = a;
+    form[1] = b;
+    form[2] = zr;
+    form[3] = zi;
+    Ish = 0.5 * ((a + b) * cy + (a - b) * cx - 2.0 * zr * y * cy - 2.0 * zi * x * cx);
+  }
+  if (t < K) {
+    const int k = t, ia = tc.pa[k], ib = tc.pb[k];
+    const double Xr = XYUV[0][k], Xi = XYUV[1][k], Yr = XYUV[2][k], Yi = XYUV[3][k];
+    const double Ur = XYUV[4][k], Ui = XYUV[5][k], Vr = XYUV[6][k], Vi = XYUV[7][k];
+    if (ia >= 0) {
+      gI[ia] = 0.5 * ((cy + cx) * 2.0 * Xr - 2.0 * y * cy * Ur - 2.0 * x * cx * Ui);
+      gI[ia + 1] = 0.5 * (-2.0 * (cy + cx) * Xi - 2.0 * y * cy * Ui + 2.0 * x * cx * Ur);
     }
+    if (ib >= 0) {
+      gI[ib] = 0.5 * ((cy - cx) * 2.0 * Yr - 2.0 * y * cy * Vr - 2.0 * x * cx * Vi);
+      gI[ib + 1] = 0.5 * (-2.0 * (cy - cx) * Yi + 2.0 * y * cy * Vi - 2.0 * x * cx * Vr);
+    }
+  }
+  __syncthreads();
+  if (t == 0) {
+    const double a = form[0], b = form[1], zr = form[2], zi = form[3];
     const double dcx = -2.0 * x * G * cx * cx, dcy = 2.0 * y * G * cy * cy;
     gI[P - 2] = 0.5 * ((a - b) * dcx - 2.0 * zi * (cx + x * dcx));
     gI[P - 1] = 0.5 * ((a + b) * dcy - 2.0 * zr * (cy + y * dcy));
@@ -377,7 +393,7 @@ void td4_launch_mmatrix(const Td4Jit& j, const Td4Const& tc, const Td4Table* tab
     int ck = chunk, nf = n_fits, ii = i0;
     double* p = part;
     void* args[] = {&c, &t, &m, &l, &nn, &ck, &nc, &nf, &ii, &p};
-    jit_launch(j.mrows, (unsigned)(nch * n_fits), kBlock, s, args);
+    jit_launch(j.mrows, (unsigned)td4_blocks(nch, n_fits), kBlock, s, args);
     hipLaunchKernelGGL(td4_mrows_finalize, dim3(n_fits), dim3(kFinalBlock), 0, s, tc, part, nch, nv, kmax, i0, rb,
                        1.0 / (double)n_mc, Mc);
   }
@@ -396,7 +412,9 @@ void td4_launch_events(const Td4Jit& j, const Td4Const& tc, const Td4Table* tabs
   int ck = chunk, nf = n_fits;
   double* p = part;
   void* args[] = {&c, &t, &st, &e, &l, &nn, &ck, &nc, &nf, &p};
-  jit_launch(j.ev[grad ? 1 : 0], (unsigned)(nch * n_fits), kBlock, s, args, start, stop);
+  const int64_t blocks = td4_blocks(nch, n_fits);
+  if (blocks > 0x7fffffff) throw Error(FN_E_INVALID, "td4: too many workgroups (chunks x fits)");
+  jit_launch(j.ev[grad ? 1 : 0], (unsigned)blocks, kBlock, s, args, start, stop);
 }
 
 void td4_launch_finalize(const Td4Const& tc, const Td4Table* tabs, const int* status, int n_fits, const double* part,

@@ -225,9 +225,31 @@ __device__ __forceinline__ void td4_basis_s(const Td4Const& tc, const Td4Table& 
   for (int k = 0; k < S::K; ++k) B[k] = td4_bk<S>(p, k);
 }
 
+// Workgroup -> (chunk, fit) of a pass over a sample shared by n_fits fits.
+// Workgroups are handed to the eight XCDs round robin by index, and each XCD
+// has its own L2: the n_fits workgroups of one chunk are given indices that
+// are equal modulo 8, so that the chunk is fetched into one L2 only.  The
+// launch has td4_blocks(nch, n_fits) workgroups; false for padding ones.
+constexpr int kXcds = 8;
+__host__ __device__ inline int64_t td4_blocks(int64_t nch, int n_fits) {
+  return n_fits == 1 ? nch : (nch + kXcds - 1) / kXcds * kXcds * n_fits;
+}
+__device__ __forceinline__ bool td4_block_item(int64_t nch, int n_fits, int64_t& ch, int& f) {
+  const int64_t b = blockIdx.x;
+  if (n_fits == 1) {
+    ch = b;
+    f = 0;
+    return true;
+  }
+  const int64_t x = b % kXcds, j = b / kXcds;
+  f = (int)(j % n_fits);
+  ch = (j / n_fits) * kXcds + x;
+  return ch < nch;
+}
+
 // Events pass for n_fits fits sharing one sample: one workgroup per (chunk,
-// fit), fits fastest so the workgroups of a chunk share it through L2; a fit
-// whose status entry is not running is skipped (status may be null).
+// fit), the fits of a chunk on one XCD so that they share it through its L2;
+// a fit whose status entry is not running is skipped (status may be null).
 template <class S, bool GRAD>
 __device__ inline void td4_events_body(const Td4Const& tc, const Td4Table* __restrict__ tabs,
                                        const int* __restrict__ status, const double* __restrict__ ev, int64_t ld,
@@ -238,8 +260,9 @@ __device__ inline void td4_events_body(const Td4Const& tc, const Td4Table* __res
   // Abar's, x, y)
   constexpr int NV = GRAD ? 1 + P : 1;
   __shared__ double lds[block_sum_lds(NV)];
-  const int64_t ch = blockIdx.x / n_fits;
-  const int f = (int)(blockIdx.x - ch * n_fits);
+  int64_t ch;
+  int f;
+  if (!td4_block_item(nch, n_fits, ch, f)) return;
   if (status && status[f] != 1) return;
   double acc[NV];
 #pragma unroll
@@ -461,8 +484,9 @@ __device__ inline void td4_mrows_body(const Td4Const& tc, const Td4Table* __rest
   constexpr int RB = td4_row_block(K);
   constexpr int NV = 2 * RB * K;
   __shared__ double lds[block_sum_lds(NV)];
-  const int64_t ch = blockIdx.x / n_fits;
-  const int f = (int)(blockIdx.x - ch * n_fits);
+  int64_t ch;
+  int f;
+  if (!td4_block_item(nch, n_fits, ch, f)) return;
   double acc[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) acc[i] = 0.0;
