@@ -333,6 +333,37 @@ fn_status fn_vbatch_fit(fn_vbatch* b, const double* theta0_host, const int32_t* 
                         double* theta_out, double* err_out, double* nll_out, int32_t* iters_out,
                         int32_t* n_evals_out, void* stream);
 
+/* Continuous serving of systematic-variation fits (the fits of one recorded
+ * sample under varied fixed constants, Sec. 5) on the batch's slots: a
+ * request carries its fixed constants and start point and arrives at
+ * arrival_s seconds after the call starts.  At every step boundary the
+ * arrivals visible by then are admitted, in arrival order, into free slots:
+ * their fixed constants and start points are copied to the device and their
+ * tables and normalization matrices built (one pass over the phase-space
+ * sample for all fits admitted together); they then share every events pass
+ * with the fits already running.  A fit that converges or fails retires at
+ * the next poll (every poll_every steps) and frees its slot.  Device memory
+ * is reserved per slot at fn_vbatch_create (state, table, matrix, partial
+ * rows), so admission is by free slot; the events are the shared sample.  A
+ * request's result is bitwise the same as when it runs alone in a batch.
+ * Outputs are per request, in the order of reqs (host arrays of n_req, or
+ * n_req x P for theta and err; any may be NULL); t_admit and t_done are
+ * seconds after the call starts.  Synchronous.  The batch's fixed constants
+ * afterwards are those of the last request each slot served.  FN_E_INVALID
+ * for a request without a start point, a negative or non-finite arrival
+ * time, or invalid fixed constants (nothing runs then). */
+typedef struct {
+  int64_t id;
+  double arrival_s;
+  const double* fixed;      /* host, fn_model_fixed layout; NULL = the model's constants */
+  const double* theta0;     /* host, P doubles */
+} fn_vrequest;
+fn_status fn_vbatch_serve(fn_vbatch* b, const fn_vrequest* reqs, int32_t n_req, const int32_t* free_mask,
+                          const double* ev, int64_t n, int64_t ld, double tol, int32_t max_iter, int32_t poll_every,
+                          int32_t* status_out, double* theta_out, double* err_out, double* nll_out,
+                          int32_t* iters_out, int32_t* n_evals_out, double* t_admit_out, double* t_done_out,
+                          void* stream);
+
 /* ---------------------------------------------------------------- batching
  * Many independent fits of one "mix1d" model advanced together on the device
  * (the paper's toy Monte Carlo studies: many fits of the same PDF to

@@ -61,6 +61,8 @@ PROTOTYPES = {
     "fn_vbatch_nll": (i32, [vp, dp, vp, i64, i64, dp, dp, vp]),
     "fn_vbatch_fit": (i32, [vp, dp, C.POINTER(i32), vp, i64, i64, C.c_double, i32, i32, C.POINTER(i32), dp, dp,
                             dp, C.POINTER(i32), C.POINTER(i32), vp]),
+    "fn_vbatch_serve": (i32, [vp, vp, i32, C.POINTER(i32), vp, i64, i64, C.c_double, i32, i32, C.POINTER(i32),
+                              dp, dp, dp, C.POINTER(i32), C.POINTER(i32), dp, dp, vp]),
     "fn_batch_create": (i32, [vp, i32, i64, C.POINTER(vp)]),
     "fn_batch_destroy": (i32, [vp]),
     "fn_batch_set_slot": (i32, [vp, i32, vp, i64, dp, C.POINTER(i32)]),

@@ -484,6 +484,54 @@ class VariationBatch:
                                       i32p(ne), _stream_ptr(stream)))
         return BatchResults(st, x, v, er, it, ne)
 
+    def serve(self, requests, events: torch.Tensor, free=None, tol: float = 1e-7, max_iter: int = 500,
+              poll_every: int = 2, stream=None) -> dict:
+        """Continuous serving of variation requests on this batch's slots.
+        requests: sequence of (id, arrival_s, fixed or None, theta0).  Returns
+        per-request arrays in request order: id, status, theta, errors, nll,
+        iters, n_evals, t_admit, t_done (seconds after the call starts)."""
+        evp, n, ld = _events(events, self.model.n_obs)
+        P = self.model.n_params
+        R = len(requests)
+        keep = []
+        arr = (_VRequest * max(R, 1))()
+        for i, (rid, arrival, fixed, theta0) in enumerate(requests):
+            th = np.ascontiguousarray(np.asarray(theta0, dtype=np.float64))
+            if th.size != P:
+                raise ValueError(f"theta0 must have {P} entries")
+            keep.append(th)
+            arr[i].id = int(rid)
+            arr[i].arrival_s = float(arrival)
+            arr[i].theta0 = th.ctypes.data_as(C.POINTER(C.c_double))
+            if fixed is None:
+                arr[i].fixed = None
+            else:
+                fx = np.ascontiguousarray(np.asarray(fixed, dtype=np.float64))
+                keep.append(fx)
+                arr[i].fixed = fx.ctypes.data_as(C.POINTER(C.c_double))
+        mask = None
+        if free is not None:
+            mk = np.ascontiguousarray(np.asarray(free, dtype=np.int32))
+            keep.append(mk)
+            mask = mk.ctypes.data_as(C.POINTER(C.c_int32))
+        out = {"id": np.array([int(r[0]) for r in requests], np.int64), "status": np.zeros(R, np.int32),
+               "theta": np.zeros((R, P)), "errors": np.zeros((R, P)), "nll": np.zeros(R),
+               "iters": np.zeros(R, np.int32), "n_evals": np.zeros(R, np.int32),
+               "t_admit": np.zeros(R), "t_done": np.zeros(R)}
+        i32p = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
+        f64p = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+        check(self._lib.fn_vbatch_serve(self._h, C.cast(arr, C.c_void_p), R, mask, evp, n, ld, float(tol),
+                                        int(max_iter), int(poll_every), i32p(out["status"]), f64p(out["theta"]),
+                                        f64p(out["errors"]), f64p(out["nll"]), i32p(out["iters"]),
+                                        i32p(out["n_evals"]), f64p(out["t_admit"]), f64p(out["t_done"]),
+                                        _stream_ptr(stream)))
+        return out
+
+
+class _VRequest(C.Structure):
+    _fields_ = [("id", C.c_int64), ("arrival_s", C.c_double), ("fixed", C.POINTER(C.c_double)),
+                ("theta0", C.POINTER(C.c_double))]
+
 
 def generate_mix1d(n: int, seed: int, fit: int, theta_gen, lo: float = -10.0, hi: float = 10.0,
                    device: str = "cuda", stream=None) -> torch.Tensor:

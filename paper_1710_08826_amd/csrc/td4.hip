@@ -124,12 +124,14 @@ __global__ void td4_prologue(Td4Const tc, ParamBlock pb, const double* __restric
 }
 
 // ---------------------------------------------------- normalization matrix
-__global__ __launch_bounds__(kFinalBlock) void td4_mrows_finalize(Td4Const tc, const double* __restrict__ part,
-                                                                  int64_t nch, int nv, int kmax, int i0, int rb,
-                                                                  double inv_n, double* __restrict__ Mc) {
+__global__ __launch_bounds__(kFinalBlock) void td4_mrows_finalize(Td4Const tc, const int* __restrict__ sel,
+                                                                  const double* __restrict__ part, int64_t nch,
+                                                                  int nv, int kmax, int i0, int rb, double inv_n,
+                                                                  double* __restrict__ Mc) {
   __shared__ double scratch[kFinalBlock];
   __shared__ double res[kBlock];
   const int f = blockIdx.x;
+  if (sel && !sel[f]) return;
   sum_rows_t<kFinalBlock>(part + (int64_t)f * nch * nv, nch, nv, scratch, res);
   const int K = tc.K;
   double* M = Mc + (int64_t)f * 2 * kTd4MaxAmp * kTd4MaxAmp;
@@ -380,7 +382,8 @@ std::shared_ptr<Td4Jit> td4_jit(const Td4Const& tc) {
 }
 
 void td4_launch_mmatrix(const Td4Jit& j, const Td4Const& tc, const Td4Table* tabs, int n_fits, const double* mc,
-                        int64_t ld_mc, int64_t n_mc, int chunk, double* part, double* Mc, hipStream_t s) {
+                        int64_t ld_mc, int64_t n_mc, int chunk, double* part, double* Mc, hipStream_t s,
+                        const int* sel) {
   const int kmax = td4_kmax(tc.K);
   const int64_t nch = (n_mc + chunk - 1) / chunk;
   const int rb = td4_row_block(tc.K);
@@ -388,14 +391,15 @@ void td4_launch_mmatrix(const Td4Jit& j, const Td4Const& tc, const Td4Table* tab
   for (int i0 = 0; i0 < tc.K; i0 += rb) {
     Td4Const c = tc;
     const Td4Table* t = tabs;
+    const int* se = sel;
     const double* m = mc;
     int64_t l = ld_mc, nn = n_mc, nc = nch;
     int ck = chunk, nf = n_fits, ii = i0;
     double* p = part;
-    void* args[] = {&c, &t, &m, &l, &nn, &ck, &nc, &nf, &ii, &p};
+    void* args[] = {&c, &t, &se, &m, &l, &nn, &ck, &nc, &nf, &ii, &p};
     jit_launch(j.mrows, (unsigned)td4_blocks(nch, n_fits), kBlock, s, args);
-    hipLaunchKernelGGL(td4_mrows_finalize, dim3(n_fits), dim3(kFinalBlock), 0, s, tc, part, nch, nv, kmax, i0, rb,
-                       1.0 / (double)n_mc, Mc);
+    hipLaunchKernelGGL(td4_mrows_finalize, dim3(n_fits), dim3(kFinalBlock), 0, s, tc, sel, part, nch, nv, kmax, i0,
+                       rb, 1.0 / (double)n_mc, Mc);
   }
 }
 

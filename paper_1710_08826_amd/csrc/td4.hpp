@@ -40,8 +40,11 @@ void td4_launch_prologue(const Td4Const& tc, const ParamBlock* pb, const double*
                          const Td4FitConst* fc, const int* status, int n_fits, Td4Table* tabs, hipStream_t s);
 // Normalization matrices M_f[i][j] = mean over the phase-space sample of
 // B_i conj(B_j), for fits [0, n_fits) (constants fc), into Mc (n_fits x K x K complex).
+// Normalization matrices of n_fits fits (only those with sel[f] != 0 when
+// sel, a device array, is not null).
 void td4_launch_mmatrix(const Td4Jit& j, const Td4Const& tc, const Td4Table* tabs, int n_fits, const double* mc,
-                        int64_t ld_mc, int64_t n_mc, int chunk, double* part, double* Mc, hipStream_t s);
+                        int64_t ld_mc, int64_t n_mc, int chunk, double* part, double* Mc, hipStream_t s,
+                        const int* sel = nullptr);
 // Events pass for n_fits fits sharing one event sample (fit-major items); a
 // fit whose status entry is not running is skipped (status may be null).
 void td4_launch_events(const Td4Jit& j, const Td4Const& tc, const Td4Table* tabs, const int* status, int n_fits,

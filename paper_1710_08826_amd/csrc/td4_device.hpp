@@ -475,11 +475,13 @@ __device__ inline void td4_envmax_body(const Td4Const& tc, const Td4Table* __res
   if (threadIdx.x == 0) atomicMax(vmax, (unsigned long long)__double_as_longlong(lds[0]));
 }
 
-// Rows i0..i0+RB-1 of M = sum over the phase-space sample of B_i conj(B_j) (per fit).
+// Rows i0..i0+RB-1 of M = sum over the phase-space sample of B_i conj(B_j)
+// (per fit; fits with sel[f] == 0 are skipped, sel may be null).
 template <class S>
 __device__ inline void td4_mrows_body(const Td4Const& tc, const Td4Table* __restrict__ tabs,
-                                      const double* __restrict__ mc, int64_t ld, int64_t n, int chunk, int64_t nch,
-                                      int n_fits, int i0, double* __restrict__ part) {
+                                      const int* __restrict__ sel, const double* __restrict__ mc, int64_t ld,
+                                      int64_t n, int chunk, int64_t nch, int n_fits, int i0,
+                                      double* __restrict__ part) {
   constexpr int K = S::K;
   constexpr int RB = td4_row_block(K);
   constexpr int NV = 2 * RB * K;
@@ -487,6 +489,7 @@ __device__ inline void td4_mrows_body(const Td4Const& tc, const Td4Table* __rest
   int64_t ch;
   int f;
   if (!td4_block_item(nch, n_fits, ch, f)) return;
+  if (sel && !sel[f]) return;
   double acc[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) acc[i] = 0.0;
@@ -533,9 +536,10 @@ __device__ inline void td4_mrows_body(const Td4Const& tc, const Td4Table* __rest
   }
 #define FN_TD4_MROWS(NAME, S)                                                                                  \
   extern "C" __global__ __launch_bounds__(fn::kBlock) void NAME(                                                \
-      fn::Td4Const tc, const fn::Td4Table* __restrict__ tabs, const double* __restrict__ mc, int64_t ld,       \
-      int64_t n, int chunk, int64_t nch, int n_fits, int i0, double* __restrict__ part) {                      \
-    fn::td4_mrows_body<S>(tc, tabs, mc, ld, n, chunk, nch, n_fits, i0, part);                                   \
+      fn::Td4Const tc, const fn::Td4Table* __restrict__ tabs, const int* __restrict__ sel,                     \
+      const double* __restrict__ mc, int64_t ld, int64_t n, int chunk, int64_t nch, int n_fits, int i0,        \
+      double* __restrict__ part) {                                                                              \
+    fn::td4_mrows_body<S>(tc, tabs, sel, mc, ld, n, chunk, nch, n_fits, i0, part);                              \
   }
 #define FN_TD4_GEN(ENVMAX, GEN, S)                                                                             \
   extern "C" __global__ __launch_bounds__(fn::kBlock) void ENVMAX(                                             \

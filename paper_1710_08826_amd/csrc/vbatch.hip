@@ -12,8 +12,11 @@
 // depend on the other fits.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "bfgs_device.hpp"
@@ -49,12 +52,13 @@ struct fn_vbatch {
   int g_iter = 0;
   bool M_valid = false;
   int64_t mc_gen = -1;           // normalization sample the matrices were built from
-  DevBuf fc, tabs, Mc, part, mpart, out, theta, st, stat, rres;
+  DevBuf fc, tabs, Mc, part, mpart, out, theta, st, stat, rres, sel;
   Td4FitConst* h_fc = nullptr;
   VState* h_st = nullptr;
   double* h_theta = nullptr;
   double* h_out = nullptr;
   int* h_stat = nullptr;
+  int* h_sel = nullptr;  // serving: fits admitted in one round
 
   void drop_graph() {
     if (exec) (void)hipGraphExecDestroy(exec);
@@ -69,6 +73,7 @@ struct fn_vbatch {
     if (h_theta) (void)hipHostFree(h_theta);
     if (h_out) (void)hipHostFree(h_out);
     if (h_stat) (void)hipHostFree(h_stat);
+    if (h_sel) (void)hipHostFree(h_sel);
   }
 };
 
@@ -185,6 +190,8 @@ fn_status fn_vbatch_create(fn_model* m, int32_t n_fits, fn_vbatch** out) {
     b->h_theta = (double*)pinned(sizeof(double) * (size_t)n_fits * b->P);
     b->h_out = (double*)pinned(sizeof(double) * (size_t)n_fits * (2 + 2 * b->P));
     b->h_stat = (int*)pinned(sizeof(int) * n_fits);
+    b->h_sel = (int*)pinned(sizeof(int) * n_fits);
+    b->sel.reserve(sizeof(int) * n_fits);
     const Td4FitConst dflt = td4_fit_const(m->td4, m->fixed_ls.data());
     for (int f = 0; f < n_fits; ++f) b->h_fc[f] = dflt;
     *out = b;
@@ -320,6 +327,137 @@ fn_status fn_vbatch_fit(fn_vbatch* b, const double* theta0_host, const int32_t* 
       for (int i = 0; i < P; ++i) {
         if (theta_out) theta_out[(size_t)f * P + i] = s.x[i];
         if (err_out) err_out[(size_t)f * P + i] = s.mask[i] ? std::sqrt(std::fabs(s.H[i * kVbMaxP + i])) : 0.0;
+      }
+    }
+  });
+}
+
+fn_status fn_vbatch_serve(fn_vbatch* b, const fn_vrequest* reqs, int32_t n_req, const int32_t* free_mask,
+                          const double* ev, int64_t n, int64_t ld, double tol, int32_t max_iter, int32_t poll_every,
+                          int32_t* status_out, double* theta_out, double* err_out, double* nll_out,
+                          int32_t* iters_out, int32_t* n_evals_out, double* t_admit_out, double* t_done_out,
+                          void* stream) {
+  return guard([&] {
+    if (!b || (n_req > 0 && !reqs)) throw Error(FN_E_INVALID, "NULL argument");
+    if (n_req < 0) throw Error(FN_E_INVALID, "n_req must be >= 0");
+    check_events(b, ev, n, ld);
+    fn_model* m = b->m;
+    const Td4Const& tc = m->td4;
+    const int F = b->F, P = b->P;
+    if (tol <= 0.0) tol = 1e-7;
+    if (max_iter <= 0) max_iter = 500;
+    if (poll_every < 1) poll_every = 1;
+    // every request's constants are checked before anything runs
+    std::vector<Td4FitConst> fcs(n_req);
+    std::vector<int> order(n_req);
+    for (int r = 0; r < n_req; ++r) {
+      if (!reqs[r].theta0) throw Error(FN_E_INVALID, "request without a start point");
+      if (!(reqs[r].arrival_s >= 0.0) || !std::isfinite(reqs[r].arrival_s))
+        throw Error(FN_E_INVALID, "arrival times must be finite and >= 0");
+      fcs[r] = td4_fit_const(tc, reqs[r].fixed ? reqs[r].fixed : m->fixed_ls.data());
+      order[r] = r;
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int c) { return reqs[a].arrival_s < reqs[c].arrival_s; });
+    hip_check(hipSetDevice(m->device), "hipSetDevice");
+    hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    wait_caller(b, stream);
+    reserve_part(b, n);
+    // every slot idle; a slot's matrix is built when a request is admitted to it
+    std::vector<int> slot_req(F, -1), free_slots;
+    for (int f = F - 1; f >= 0; --f) free_slots.push_back(f);
+    for (int f = 0; f < F; ++f) b->h_stat[f] = kFitIdle;
+    hip_check(hipMemcpyAsync(b->stat.ptr, b->h_stat, sizeof(int) * F, hipMemcpyHostToDevice, b->stream),
+              "hipMemcpyAsync");
+    b->M_valid = false;  // the matrices no longer follow fn_vbatch_set_fixed
+    const int stride = (int)(sizeof(VState) / sizeof(double));
+    const auto t0 = std::chrono::steady_clock::now();
+    auto now = [&] { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
+    std::vector<double> t_admit(n_req, -1.0);
+    VState done_state;
+    int next = 0, n_running = 0;
+    std::vector<int> fin;
+    while (true) {
+      // admission at a step boundary: arrivals visible now, in arrival order, into free slots
+      const double t = now();
+      int n_adm = 0;
+      for (int f = 0; f < F; ++f) b->h_sel[f] = 0;
+      while (next < n_req && !free_slots.empty() && reqs[order[next]].arrival_s <= t) {
+        const int r = order[next++];
+        const int f = free_slots.back();
+        free_slots.pop_back();
+        b->h_fc[f] = fcs[r];
+        VState& st = b->h_st[f];
+        std::memset(&st, 0, sizeof(st));
+        for (int i = 0; i < P; ++i) {
+          st.xt[i] = reqs[r].theta0[i];
+          st.mask[i] = free_mask ? (free_mask[i] != 0) : 1;
+        }
+        st.status = kFitRunning;
+        st.phase = kPhaseStart;
+        b->h_stat[f] = kFitRunning;
+        b->h_sel[f] = 1;
+        slot_req[f] = r;
+        t_admit[r] = t;
+        ++n_adm;
+        ++n_running;
+        hip_check(hipMemcpyAsync((Td4FitConst*)b->fc.ptr + f, &b->h_fc[f], sizeof(Td4FitConst),
+                                 hipMemcpyHostToDevice, b->stream), "hipMemcpyAsync");
+        hip_check(hipMemcpyAsync((VState*)b->st.ptr + f, &b->h_st[f], sizeof(VState), hipMemcpyHostToDevice,
+                                 b->stream), "hipMemcpyAsync");
+        hip_check(hipMemcpyAsync((int*)b->stat.ptr + f, &b->h_stat[f], sizeof(int), hipMemcpyHostToDevice,
+                                 b->stream), "hipMemcpyAsync");
+      }
+      if (n_adm > 0) {
+        // the admitted fits' tables (their lineshape constants) and normalization matrices
+        hip_check(hipMemcpyAsync(b->sel.ptr, b->h_sel, sizeof(int) * F, hipMemcpyHostToDevice, b->stream),
+                  "hipMemcpyAsync");
+        const int* sel = (const int*)b->sel.ptr;
+        td4_launch_prologue(tc, nullptr, (const double*)b->st.ptr, stride, (const Td4FitConst*)b->fc.ptr, sel, F,
+                            (Td4Table*)b->tabs.ptr, b->stream);
+        const int mchunk = 1024;
+        const int64_t rows = (m->n_mc + mchunk - 1) / mchunk;
+        b->mpart.reserve(sizeof(double) * (size_t)rows * F * 2 * td4_row_block(tc.K) * td4_kmax(tc.K));
+        td4_launch_mmatrix(*m->td4_jit, tc, (const Td4Table*)b->tabs.ptr, F, (const double*)m->d_mc.ptr, m->n_mc,
+                           m->n_mc, mchunk, (double*)b->mpart.ptr, (double*)b->Mc.ptr, b->stream, sel);
+        hip_check(hipGetLastError(), "kernel launch");
+        // the pinned staging of this round must not change before the copies ran
+        hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+      }
+      if (n_running == 0) {
+        if (next >= n_req) break;
+        const double wait = reqs[order[next]].arrival_s - now();
+        if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(std::min(wait, 1e-3)));
+        continue;
+      }
+      for (int i = 0; i < poll_every; ++i) step(b, true, ev, n, ld, tol, max_iter);
+      hip_check(hipMemcpyAsync(b->h_stat, b->stat.ptr, sizeof(int) * F, hipMemcpyDeviceToHost, b->stream),
+                "hipMemcpyAsync");
+      hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+      fin.clear();
+      for (int f = 0; f < F; ++f)
+        if (slot_req[f] >= 0 && (b->h_stat[f] == kFitConverged || b->h_stat[f] == kFitFailed)) fin.push_back(f);
+      if (fin.empty()) continue;
+      const double td = now();
+      for (int f : fin) {
+        hip_check(hipMemcpyAsync(&done_state, (VState*)b->st.ptr + f, sizeof(VState), hipMemcpyDeviceToHost,
+                                 b->stream), "hipMemcpyAsync");
+        hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+        const int r = slot_req[f];
+        const VState& st = done_state;
+        if (status_out) status_out[r] = st.status;
+        if (nll_out) nll_out[r] = st.f;
+        if (iters_out) iters_out[r] = st.iter;
+        if (n_evals_out) n_evals_out[r] = st.n_eval;
+        for (int i = 0; i < P; ++i) {
+          if (theta_out) theta_out[(size_t)r * P + i] = st.x[i];
+          if (err_out) err_out[(size_t)r * P + i] = st.mask[i] ? std::sqrt(std::fabs(st.H[i * kVbMaxP + i])) : 0.0;
+        }
+        if (t_admit_out) t_admit_out[r] = t_admit[r];
+        if (t_done_out) t_done_out[r] = td;
+        slot_req[f] = -1;
+        free_slots.push_back(f);
+        --n_running;
       }
     }
   });
