@@ -324,6 +324,67 @@ def cpu_baseline(events: np.ndarray, desc: dict, theta):
             "oracle_call_with_grid_events_per_s": full, **info}
 
 
+def variation_serving_leg(n_req: int = 192, slots: int = 64, lam_frac: float = 0.7, n: int = 1_000_000):
+    """Systematic-variation fits of the twenty-amplitude four-body model served
+    continuously (fn_vbatch_serve): a 1M-event sample of the config-4 events,
+    the 5M-point normalization sample, 64 slots, 192 requests (ten kinds of
+    +-shifted lineshape constants and time resolution, start points near the
+    generation point, all coefficients but Abar's reference and x, y free,
+    each request capped at 100 minimizer iterations: the synthetic events are
+    not drawn from the model, and with 40 free parameters few fits converge
+    within the cap, so the leg measures the serving loop's throughput and
+    latency for fixed-length fits).  Closed loop (all requests at t = 0), then
+    Poisson arrivals at lam_frac of the closed-loop rate."""
+    import torch
+    import synth
+    from paper_1710_08826_amd import Model, VariationBatch
+    desc = synth.td4_split_desc()
+    th = synth.td4_split_truth()
+    m = Model(desc)
+    m.generate_norm_sample(5_000_000, seed=synth.BASE_SEED + 5)
+    ev = torch.from_numpy(synth.td4_events(n, seed=synth.BASE_SEED + 4)).cuda()
+    m.autotune(th, ev, reps=5)
+    P = m.n_params
+    fx = m.fixed()
+    n12, n34 = len(desc["r12"]), len(desc["r34"])
+    shifted = (3, 2 * n12 + 2, 2 * n12 + 3, 2 * n12 + 5, 2 * (n12 + n34))
+    free = np.ones(P, np.int32)
+    n_abar = sum(1 for a in desc["amps"] if a[3] != "A")
+    free[P - 2 - 2 * n_abar: P - 2 * n_abar] = 0
+    rng = np.random.default_rng(17100882)
+
+    def make(arrivals):
+        reqs = []
+        for i, t in enumerate(arrivals):
+            v = fx.copy()
+            v[shifted[i % 5]] *= 1.0 + 0.002 * (1 if (i // 5) % 2 else -1)
+            th0 = th * (1.0 + 2e-3 * np.sin(np.arange(P) + i))
+            th0[free == 0] = th[free == 0]
+            reqs.append((i, float(t), v, th0))
+        return reqs
+
+    b = VariationBatch(m, slots)
+    out = {"events": n, "mc_points": 5_000_000, "params": P, "slots": slots, "requests": n_req,
+           "max_iter": 100, "chunk": m.chunk}
+    b.serve(make([0.0] * 8), ev, free=free, max_iter=100)  # warm-up: graph capture, kernels
+    for label, arrivals in (("closed_loop", np.zeros(n_req)), ("poisson", None)):
+        if arrivals is None:
+            lam = lam_frac * out["closed_loop"]["fits_per_s"]
+            arrivals = np.cumsum(rng.exponential(1.0 / lam, n_req))
+        reqs = make(arrivals)
+        t0 = time.perf_counter()
+        r = b.serve(reqs, ev, free=free, max_iter=100)
+        wall = time.perf_counter() - t0
+        lat = r["t_done"] - arrivals
+        out[label] = {"wall_s": wall, "fits_per_s": n_req / wall, "converged": int((r["status"] == 2).sum()),
+                      "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+                      "mean_iterations": float(r["iters"].mean()), "mean_evaluations": float(r["n_evals"].mean())}
+        if label == "poisson":
+            out[label]["rate_per_s"] = float(lam)
+    b.close()
+    return out
+
+
 def cpu_baselines_other():
     """The oracle on bounded samples of configs 0, 3 and 4 (events/s of NLL +
     autograd gradient, median of 5 trials, all host threads), each with the
@@ -770,7 +831,7 @@ def main():
     ap.add_argument("--quick", action="store_true", help="skip the side measurements and the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time direct launches instead of captured steps")
-    ap.add_argument("--leg", choices=["td4", "serve", "tddp3", "config3", "config0-mall", "cpu"],
+    ap.add_argument("--leg", choices=["td4", "serve", "vserve", "tddp3", "config3", "config0-mall", "cpu"],
                     help="run only the four-body leg or the serving leg and print its figures (for profiling)")
     ap.add_argument("--pmc-probe", nargs="?", const="config1",
                     choices=["config1", "config3", "tddp3", "td4", "td4batch", "config0mall"],
@@ -795,6 +856,9 @@ def main():
         return
     if args.leg == "serve":
         print(json.dumps({"config2_serving": serving_leg()}), flush=True)
+        return
+    if args.leg == "vserve":
+        print(json.dumps({"config4_variation_serving": variation_serving_leg()}), flush=True)
         return
     if args.leg == "tddp3":
         print(json.dumps({"tddp3": tddp3_leg(), "tddp3_8res": tddp3_leg(k16=False)}), flush=True)
@@ -933,6 +997,14 @@ def main():
             print(f"[bench] {key} ({c4['model']}): single {c4['single_events_per_s']:.4g} events/s "
                   f"({c4['single_event_kernel_tflops']:.2f} TFLOP/s), 64 fits {c4['batch_event_fits_per_s']:.4g} "
                   f"event-fits/s, adjoint vs FD {c4['adjoint_vs_plain_fd']:.1f}x", file=sys.stderr, flush=True)
+
+    if not args.quick:
+        print("[bench] config4 variation serving (192 requests, 64 slots) ...", file=sys.stderr, flush=True)
+        vs = variation_serving_leg()
+        extra["config4_variation_serving"] = vs
+        print(f"[bench] config4 variations: {vs['closed_loop']['fits_per_s']:.4g} fits/s closed loop, Poisson "
+              f"p50 {vs['poisson']['p50_latency_s']:.3f} s p99 {vs['poisson']['p99_latency_s']:.3f} s",
+              file=sys.stderr, flush=True)
 
     if not args.quick:
         print("[bench] config2 serving (4096 toy fits) ...", file=sys.stderr, flush=True)
