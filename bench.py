@@ -35,12 +35,12 @@ PEAK_HBM_GBS = 8000.0
 # chunk, and its executed FP64 FLOPs per event from SQ_INSTS_VALU_FLOPS_FP64,
 # valid for the kernel sources with this hash; reported as null once they
 # change or for a chunk without a counter run.
-TRAFFIC_BYTES = {2048: 1.620e7, 1024: 1.628e7}
-COUNTED_FP64_FLOPS_PER_EVENT = {2048: 493.4, 1024: 498.8}
+TRAFFIC_BYTES = {2048: 1.620e7}
+COUNTED_FP64_FLOPS_PER_EVENT = {2048: 493.4}
 TRAFFIC_SOURCES = ["paper_1710_08826_amd/csrc/dalitz_device.hpp", "paper_1710_08826_amd/csrc/dalitz3.hip",
                    "paper_1710_08826_amd/csrc/fastmath.hpp", "paper_1710_08826_amd/csrc/device_common.hpp",
                    "paper_1710_08826_amd/csrc/model.hpp"]
-TRAFFIC_HASH = "2be739b3e7919796"
+TRAFFIC_HASH = "281df0357d25487e"
 
 
 def counters_current() -> bool:
@@ -211,42 +211,66 @@ def capture_steps(model, thetas, ev, out, with_grad):
 def time_async(model, theta_dev, ev, out, steps, warmup, with_grad=True, alt=None, graph=True):
     """NLL(+grad) steps with device theta alternating between two points, so no
     cache short-circuits the work.  Returns (median wall seconds of a trial of
-    exactly `steps` steps, average per-event kernel duration in ms from a
-    separate loop of individually timed launches, info)."""
+    exactly `steps` steps, average per-event kernel duration in ms, info).
+    Dalitz models: the kernel duration is the average span of the per-event
+    launches of a second, identical loop of trials, measured by the launches
+    themselves on the device wall clock (fn_model_timing span mode, captured
+    into the replayed graphs; its bookkeeping adds about 2 us to a step, so
+    the wall-timed trials run without it); other models: a separate loop of
+    launches each timed by its own dispatch (HIP events)."""
     import torch
     thetas = [theta_dev] if alt is None else [theta_dev, alt]
+    span = model.desc.get("kind") == "dalitz3"
     for i in range(max(warmup, 2)):
         model.nll_async(thetas[i % len(thetas)], ev, out, with_grad)
     torch.cuda.synchronize()
+
+    def trials_of(graphs):
+        def run(k):
+            if graphs:
+                for i in range(k):
+                    graphs[i % len(graphs)].replay()
+            else:
+                for i in range(k):
+                    model.nll_async(thetas[i % len(thetas)], ev, out, with_grad)
+        run(max(warmup, 2))
+        torch.cuda.synchronize()
+        if span:
+            model.kernel_time()  # drop the warm-up launches
+        trials = []
+        while len(trials) < MAX_TRIALS and (len(trials) < MIN_TRIALS or sum(trials) < MIN_TIMED_S):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            run(steps)
+            torch.cuda.synchronize()
+            trials.append(time.perf_counter() - t0)
+        return trials
+
     graphs = capture_steps(model, thetas, ev, out, with_grad) if graph else None
-
-    def run(k):
-        if graphs:
-            for i in range(k):
-                graphs[i % len(graphs)].replay()
-        else:
-            for i in range(k):
-                model.nll_async(thetas[i % len(thetas)], ev, out, with_grad)
-
-    run(max(warmup, 2))
-    torch.cuda.synchronize()
-    trials = []
-    while len(trials) < MAX_TRIALS and (len(trials) < MIN_TRIALS or sum(trials) < MIN_TIMED_S):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        run(steps)
-        torch.cuda.synchronize()
-        trials.append(time.perf_counter() - t0)
-    # the kernel's own duration, outside the wall-timed trials
-    model.kernel_time()
-    model.set_timing(True, every=1)
-    for i in range(KERNEL_TIMING_LAUNCHES):
-        model.nll_async(thetas[i % len(thetas)], ev, out, with_grad)
-    torch.cuda.synchronize()
-    model.set_timing(False)
-    kms, launches = model.kernel_time()
+    trials = trials_of(graphs)
     info = {"trials": len(trials), "timed_s": sum(trials), "graph": graphs is not None,
             "trial_ms_min": 1e3 * min(trials), "trial_ms_max": 1e3 * max(trials)}
+    if span:
+        model.set_timing(True, span=True)
+        model.nll_async(thetas[0], ev, out, with_grad)  # sizes the stamp buffer before capture
+        torch.cuda.synchronize()
+        sgraphs = capture_steps(model, thetas, ev, out, with_grad) if graph else None
+        strials = trials_of(sgraphs)
+        kms, launches = model.kernel_time()
+        model.set_timing(False)
+        info.update({"kernel_timing": "in-kernel spans of every launch of a second loop of trials",
+                     "kernel_launches_timed": launches, "span_loop_ms_per_step": 1e3 * float(np.median(strials)) / steps})
+    else:
+        # the kernel's own duration, outside the wall-timed trials
+        model.kernel_time()
+        model.set_timing(True, every=1)
+        for i in range(KERNEL_TIMING_LAUNCHES):
+            model.nll_async(thetas[i % len(thetas)], ev, out, with_grad)
+        torch.cuda.synchronize()
+        model.set_timing(False)
+        kms, launches = model.kernel_time()
+        info.update({"kernel_timing": f"{KERNEL_TIMING_LAUNCHES} separately timed launches (dispatch events)",
+                     "kernel_launches_timed": launches})
     return float(np.median(trials)), kms / max(launches, 1), info
 
 

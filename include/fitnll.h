@@ -260,10 +260,18 @@ fn_status fn_model_fixed(const fn_model* m, int32_t* n_fixed, double* fixed_host
  * kernel's start and end times into a pair of HIP events
  * (hipExtModuleLaunchKernel / hipExtLaunchKernel; k = 1: every launch, a
  * large k keeps the timing work out of most of a timed loop); every = 0 turns
- * timing off.
- * FN_E_INVALID if every < 0.  fn_model_kernel_time waits for the recorded
- * events, returns the summed duration in milliseconds and the number of timed
- * launches since the last query, and resets both. */
+ * timing off.  every = -1 (dalitz3 models): every per-event launch from now
+ * on, including launches captured into graphs while the mode is on and
+ * replayed later, measures itself: each workgroup stores its start and end
+ * on the device wall clock, and the level-2 kernel after it adds the
+ * launch's span (last end - first start) to a device record.  This times
+ * launches inside a timed loop of graph replays without HIP events.
+ * Synchronous when set; the first launch of a larger sample than before in
+ * this mode synchronizes the device (capture graphs after a warm-up call).
+ * FN_E_INVALID if every < -1, or -1 for another model kind.
+ * fn_model_kernel_time waits for the recorded events (span mode: for the
+ * device), returns the summed duration in milliseconds and the number of
+ * timed launches since the last query, and resets both. */
 fn_status fn_model_timing(fn_model* m, int32_t every);
 fn_status fn_model_kernel_time(fn_model* m, double* total_ms, int64_t* launches);
 

@@ -197,10 +197,11 @@ class Model:
         self.chunk = best.value
         return best.value, dict(zip(self.TUNE_CHUNKS, list(us)))
 
-    def set_timing(self, enable: bool, every: int = 1):
+    def set_timing(self, enable: bool, every: int = 1, span: bool = False):
         """Time every `every`-th per-event kernel launch (the dispatch records its own
-        start and end into a pair of HIP events)."""
-        check(self._lib.fn_model_timing(self._h, every if enable else 0))
+        start and end into a pair of HIP events); span=True (dalitz3): every
+        launch, graph replays included, measures its own span on the device."""
+        check(self._lib.fn_model_timing(self._h, (-1 if span else every) if enable else 0))
 
     def kernel_time(self):
         """(total ms, launches) of timed per-event kernels since the last query."""

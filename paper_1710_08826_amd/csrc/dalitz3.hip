@@ -80,6 +80,7 @@ struct DalFinal {
   int norm_ready;            // the events pass wrote I and dI into out (cached M)
   double* out;               // [NLL, grad(P), I, dI(P)]
   double* out_user;          // optional [NLL, grad(P)]
+  unsigned long long* span;  // span record of the measured events pass (or nullptr)
 };
 
 struct DalFinalLds {
@@ -175,7 +176,10 @@ __global__ __launch_bounds__(kFinalBlock) void dalitz_finalize(DalitzConst dc, c
                                                           const double* __restrict__ evpart, int64_t ev_rows,
                                                           int ev_nv, int kmax, DalFinal fin) {
   __shared__ DalFinalLds L;
+  unsigned long long lo = 0, hi = 0;
+  if (fin.span) span_load<kFinalBlock>(fin.span, ev_rows, lo, hi);
   dalitz_finalize_body(dc, tab, evpart, ev_rows, ev_nv, kmax, fin, L);
+  if (fin.span) span_add<kFinalBlock>(fin.span, ev_rows, lo, hi, L.scratch);
 }
 
 // Level-2 of the M-row passes: rows i0..i0+3 of M (scaled by dA) into Mc.
@@ -316,7 +320,8 @@ std::shared_ptr<DalitzJit> dalitz_jit(const DalitzConst& dc) {
 static void launch_pass(hipFunction_t f, const DalitzConst& dc, const DalitzTable* tab, const double* coef,
                         const double* ev, int64_t ld, int64_t n, int chunk, int64_t nchunks, int i0, double* part,
                         hipStream_t s, const double* Mc = nullptr, double* norm_out = nullptr,
-                        hipEvent_t start = nullptr, hipEvent_t stop = nullptr) {
+                        hipEvent_t start = nullptr, hipEvent_t stop = nullptr,
+                        unsigned long long* span = nullptr) {
   if (!f) throw Error(FN_E_INVALID, "this model was not compiled with the requested pass");
   DalitzConst c = dc;
   const DalitzTable* t = tab;
@@ -327,13 +332,15 @@ static void launch_pass(hipFunction_t f, const DalitzConst& dc, const DalitzTabl
   double* p = part;
   const double* m = Mc;
   double* no = norm_out;
-  void* args[] = {&c, &t, &cf, &e, &l, &nn, &ch, &ii, &p, &m, &no};
+  unsigned long long* sp = span;
+  void* args[] = {&c, &t, &cf, &e, &l, &nn, &ch, &ii, &p, &m, &no, &sp};
   jit_launch(f, (unsigned)nchunks, kBlock, s, args, start, stop);
 }
 
 static DalFinal make_final(const double* npart, int64_t n_rows, int n_nv, const double* Mc, const double* coef,
                            double n_events, bool grad, bool norm_ready, double* out, double* out_user) {
   DalFinal f;
+  f.span = nullptr;
   f.norm_ready = norm_ready ? 1 : 0;
   f.npart = npart;
   f.n_rows = n_rows;
@@ -349,20 +356,22 @@ static DalFinal make_final(const double* npart, int64_t n_rows, int n_nv, const 
 
 void dalitz_launch_events(const DalitzJit& j, const DalitzConst& dc, const DalitzTable* tab, const double* coef,
                           const double* ev, int64_t ld, int64_t n, int chunk, int64_t nchunks, int grad, double* part,
-                          hipStream_t s, const double* Mc, double* out, hipEvent_t start, hipEvent_t stop) {
+                          hipStream_t s, const double* Mc, double* out, hipEvent_t start, hipEvent_t stop,
+                          unsigned long long* span) {
   if (nchunks == 0) return;
   const int P = dc.free_ls ? 4 * dc.K : 2 * dc.K;
   launch_pass(j.ev[grad], dc, tab, coef, ev, ld, n, chunk, nchunks, 0, part, s, Mc,
-              Mc && out ? out + 1 + P : nullptr, start, stop);
+              Mc && out ? out + 1 + P : nullptr, start, stop, span);
 }
 
 void dalitz_launch_finalize(const DalitzConst& dc, const DalitzTable* tab, const double* coef, const double* evpart,
                             int64_t ev_rows, int grad, const double* npart, int64_t n_rows, int n_nv,
                             const double* Mc, double n_events, double* out, double* out_user, hipStream_t s,
-                            bool norm_ready) {
+                            bool norm_ready, unsigned long long* span) {
   const int kmax = dalitz_kmax(dc.K);
-  const DalFinal fin = make_final(npart, n_rows, n_nv, Mc, coef, n_events, grad != 0, norm_ready && !npart, out,
-                                  out_user);
+  DalFinal fin = make_final(npart, n_rows, n_nv, Mc, coef, n_events, grad != 0, norm_ready && !npart, out,
+                            out_user);
+  fin.span = span;
   hipLaunchKernelGGL(dalitz_finalize, dim3(1), dim3(kFinalBlock), 0, s, dc, tab, evpart, ev_rows,
                      dal_nv(kEvents, grad, kmax), kmax, fin);
 }

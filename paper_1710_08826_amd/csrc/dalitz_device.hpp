@@ -347,17 +347,21 @@ __device__ inline void dalitz_cached_norm(const double* __restrict__ M, const do
 // table's copy of them); unused by kMRows.  Events pass with a cached grid
 // matrix (M not null): the last workgroup, whose chunk is the shortest,
 // also evaluates the normalization into norm_out (dalitz_cached_norm), so
-// that the level-2 step only sums rows.
+// that the level-2 step only sums rows.  span: the launch's span record
+// (span_begin / span_end), null when the launch is not measured.
 template <class S, int MODE, int GRAD, int EPT = 1>
 __device__ inline void dalitz_pass_body(const DalitzConst& dc, const DalitzTable* __restrict__ tab,
                                         const double* __restrict__ coef, const double* __restrict__ ev, int64_t ld,
                                         int64_t n, int chunk, int i0, double* __restrict__ part,
-                                        const double* __restrict__ M, double* __restrict__ norm_out) {
+                                        const double* __restrict__ M, double* __restrict__ norm_out,
+                                        unsigned long long* __restrict__ span) {
   constexpr int NV = dal_nv(MODE, GRAD, S::K);
   __shared__ double lds[block_sum_lds(NV)];
+  if (span) span_begin(span);
   dalitz_chunk<S, MODE, GRAD, EPT>(dc, tab, coef, ev, ld, n, blockIdx.x, chunk, i0,
                                    part + (int64_t)blockIdx.x * NV, lds);
   if (MODE == kEvents && M && blockIdx.x == gridDim.x - 1) dalitz_cached_norm<S>(M, coef, norm_out);
+  if (span) span_end(span);
 }
 
 // ---------------------------------------------------------------- toy events
@@ -448,8 +452,8 @@ __device__ inline void dalitz_gen_body(const DalitzConst& dc, const DalitzTable*
   extern "C" __global__ __launch_bounds__(fn::kBlock) void NAME(                                               \
       fn::DalitzConst dc, const fn::DalitzTable* __restrict__ tab, const double* __restrict__ coef,           \
       const double* __restrict__ ev, int64_t ld, int64_t n, int chunk, int i0, double* __restrict__ part,     \
-      const double* __restrict__ M, double* __restrict__ norm_out) {                                           \
-    fn::dalitz_pass_body<S, MODE, GRAD, EPT>(dc, tab, coef, ev, ld, n, chunk, i0, part, M, norm_out);          \
+      const double* __restrict__ M, double* __restrict__ norm_out, unsigned long long* __restrict__ span) {    \
+    fn::dalitz_pass_body<S, MODE, GRAD, EPT>(dc, tab, coef, ev, ld, n, chunk, i0, part, M, norm_out, span);    \
   }
 
 // Grid maximum and accept-reject generator for shape S.

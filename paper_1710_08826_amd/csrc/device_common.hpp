@@ -108,4 +108,61 @@ __device__ inline void sum_rows(const double* __restrict__ part, int64_t nrows, 
   sum_rows_t<kBlock>(part, nrows, nv, scratch, res);
 }
 
+// Kernel span (measurement support, used only when a launch is given a span
+// record): span[0] the sum over launches of (last workgroup end - earliest
+// workgroup start) on the device wall clock, span[1] the number of launches,
+// then two stamps per workgroup of the running launch (start, end), written
+// with plain stores to distinct addresses -- no atomics or fences in the
+// measured kernel -- and reduced by the level-2 kernel that follows it.
+__device__ __forceinline__ void span_begin(unsigned long long* span) {
+  if (threadIdx.x == 0) span[2 + 2 * (int64_t)blockIdx.x] = wall_clock64();
+}
+__device__ inline void span_end(unsigned long long* span) {
+  __syncthreads();
+  if (threadIdx.x == 0) span[3 + 2 * (int64_t)blockIdx.x] = wall_clock64();
+}
+// In the level-2 kernel (one workgroup of TB threads, after the measured
+// launch on the same stream): span_load takes each thread's share of the
+// stamps of the launch's `blocks` workgroups (issued before the row sums, so
+// that their latency overlaps them), span_add reduces them (wave shuffles,
+// then one value per wave) and adds the launch's span to the record.
+template <int TB>
+__device__ __forceinline__ void span_load(const unsigned long long* span, int64_t blocks, unsigned long long& lo,
+                                          unsigned long long& hi) {
+  lo = ~0ull;
+  hi = 0ull;
+  for (int64_t b = threadIdx.x; b < blocks; b += TB) {
+    const unsigned long long s0 = span[2 + 2 * b], s1 = span[3 + 2 * b];
+    lo = s0 < lo ? s0 : lo;
+    hi = s1 > hi ? s1 : hi;
+  }
+}
+template <int TB>
+__device__ inline void span_add(unsigned long long* span, int64_t blocks, unsigned long long lo,
+                                unsigned long long hi, double* scratch) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) {
+    const unsigned long long ol = __shfl_xor(lo, d), oh = __shfl_xor(hi, d);
+    lo = ol < lo ? ol : lo;
+    hi = oh > hi ? oh : hi;
+  }
+  unsigned long long* u = reinterpret_cast<unsigned long long*>(scratch);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    u[2 * (threadIdx.x >> 6)] = lo;
+    u[2 * (threadIdx.x >> 6) + 1] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && blocks > 0) {
+    unsigned long long first = u[0], last = u[1];
+    for (int w = 1; w < TB / 64; ++w) {
+      first = u[2 * w] < first ? u[2 * w] : first;
+      last = u[2 * w + 1] > last ? u[2 * w + 1] : last;
+    }
+    span[0] += last - first;
+    span[1] += 1ull;
+  }
+  __syncthreads();
+}
+
 }  // namespace fn

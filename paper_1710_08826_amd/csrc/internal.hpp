@@ -71,7 +71,10 @@ struct fn_model {
   fn::DevBuf d_theta;                    // tddp3: theta on the device for host-theta calls
   double* h_out = nullptr;       // pinned
   long long stats_calls = 0;
-  int timing = 0;                // time every timing-th event-pass launch with HIP events (0 = off)
+  int timing = 0;                // time every timing-th event-pass launch with HIP events (0 = off,
+                                 // -1: in-kernel spans of every Dalitz event-pass launch into d_span)
+  fn::DevBuf d_span;             // span record (sum of spans, launches), then two stamps per workgroup
+  double span_khz = 0.0;         // device wall-clock rate
   int64_t timing_count = 0;
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;

@@ -54,14 +54,15 @@ void dalitz_launch_prologue(const DalitzConst& dc, const ParamBlock& pb, const d
 void dalitz_launch_events(const DalitzJit& j, const DalitzConst& dc, const DalitzTable* tab, const double* coef,
                           const double* ev, int64_t ld, int64_t n, int chunk, int64_t nchunks, int grad, double* part,
                           hipStream_t s, const double* Mc = nullptr, double* out = nullptr,
-                          hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
+                          hipEvent_t start = nullptr, hipEvent_t stop = nullptr,
+                          unsigned long long* span = nullptr);
 // Level-2 sum of the event rows and of the normalization (grid rows, or the
 // cached M when npart is null), NLL assembly: out = [NLL, grad, I, dI].
 // norm_ready: the events pass already wrote I and dI into out (cached M).
 void dalitz_launch_finalize(const DalitzConst& dc, const DalitzTable* tab, const double* coef, const double* evpart,
                             int64_t ev_rows, int grad, const double* npart, int64_t n_rows, int n_nv,
                             const double* Mc, double n_events, double* out, double* out_user, hipStream_t s,
-                            bool norm_ready = false);
+                            bool norm_ready = false, unsigned long long* span = nullptr);
 void dalitz_launch_grid(const DalitzJit& j, const DalitzConst& dc, const DalitzTable* tab, const double* coef,
                         int chunk, int64_t nchunks, int grad, double* part, hipStream_t s);
 // Level-2 of a row-block pass of K x K matrices (rows i0..i0+3, 2 K doubles

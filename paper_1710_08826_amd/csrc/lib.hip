@@ -548,12 +548,28 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
     }
     // cached M: the events pass evaluates I = c^H M c in its last workgroup
     const bool norm_in_pass = !dc.free_ls && nch > 0;
+    // span mode: the pass stamps its workgroups, the level-2 kernel adds the span
+    unsigned long long* span = nullptr;
+    if (m->timing < 0 && !ws && nch > 0) {
+      const size_t need = sizeof(unsigned long long) * (size_t)(2 + 2 * nch);
+      if (need > m->d_span.bytes) {
+        // room for this launch's stamps; the record so far moves with it
+        // (synchronous: the first launch of a larger sample must not be
+        // captured into a graph)
+        unsigned long long rec[2];
+        hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+        hip_check(hipMemcpy(rec, m->d_span.ptr, sizeof(rec), hipMemcpyDeviceToHost), "hipMemcpy");
+        m->d_span.reserve(need);
+        hip_check(hipMemcpy(m->d_span.ptr, rec, sizeof(rec), hipMemcpyHostToDevice), "hipMemcpy");
+      }
+      span = (unsigned long long*)m->d_span.ptr;
+    }
     m->timed(launches, [&](hipEvent_t t0, hipEvent_t t1) {
       dalitz_launch_events(*m->dal_jit, dc, m->table_dal(), coef, ev, ld, n, m->chunk, nch, g, part, s,
-                           norm_in_pass ? m->Mc() : nullptr, norm_in_pass ? m->out() : nullptr, t0, t1);
+                           norm_in_pass ? m->Mc() : nullptr, norm_in_pass ? m->out() : nullptr, t0, t1, span);
     });
     dalitz_launch_finalize(dc, m->table_dal(), coef, part, nch, g, grid_rows, nrows, nnv, m->Mc(), (double)n,
-                           m->out(), out_user, s, norm_in_pass);
+                           m->out(), out_user, s, norm_in_pass, span);
   }
   hip_check(hipGetLastError(), "kernel launch");
 }
@@ -1071,10 +1087,27 @@ fn_status fn_model_fixed(const fn_model* m, int32_t* n_fixed, double* fixed_host
   });
 }
 
+// The span record of span mode: summed span and launch count back to zero.
+static void span_reset(fn_model* m) {
+  const unsigned long long init[2] = {0ull, 0ull};
+  hip_check(hipMemcpy(m->d_span.ptr, init, sizeof(init), hipMemcpyHostToDevice), "hipMemcpy");
+}
+
 fn_status fn_model_timing(fn_model* m, int32_t every) {
   return guard([&] {
     if (!m) throw Error(FN_E_INVALID, "model is NULL");
-    if (every < 0) throw Error(FN_E_INVALID, "every must be >= 0");
+    if (every < -1) throw Error(FN_E_INVALID, "every must be >= -1");
+    if (every == -1) {
+      if (m->kind != kKindDalitz3) throw Error(FN_E_INVALID, "in-kernel span timing is available for dalitz3 models");
+      hip_check(hipSetDevice(m->device), "hipSetDevice");
+      int khz = 0;
+      hip_check(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, m->device), "hipDeviceGetAttribute");
+      if (khz <= 0) throw Error(FN_E_HIP, "the device reports no wall-clock rate");
+      m->span_khz = khz;
+      m->d_span.reserve(2 * sizeof(unsigned long long));
+      hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+      span_reset(m);
+    }
     m->timing = every;
     m->timing_count = 0;
   });
@@ -1084,6 +1117,16 @@ fn_status fn_model_kernel_time(fn_model* m, double* total_ms, int64_t* launches)
   return guard([&] {
     if (!m) throw Error(FN_E_INVALID, "model is NULL");
     hip_check(hipSetDevice(m->device), "hipSetDevice");
+    if (m->timing < 0) {
+      // span mode: the launches may sit on any stream or inside graphs
+      hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+      unsigned long long rec[2];
+      hip_check(hipMemcpy(rec, m->d_span.ptr, sizeof(rec), hipMemcpyDeviceToHost), "hipMemcpy");
+      if (total_ms) *total_ms = (double)rec[0] / m->span_khz;
+      if (launches) *launches = (int64_t)rec[1];
+      span_reset(m);
+      return;
+    }
     double tot = 0.0;
     for (auto& pr : m->ev_pending) {
       hip_check(hipEventSynchronize(pr.second), "hipEventSynchronize");

@@ -64,3 +64,46 @@ def test_empty_sample_is_not_timed():
     m.nll(synth.dalitz_truth(), ev, grad=True)
     assert m.kernel_time() == (0.0, 0)
     m.set_timing(False)
+
+
+def test_span_mode_counts_graph_replays_and_keeps_results():
+    """Span mode (dalitz3): every launch measures itself on the device, also
+    inside captured graphs; results are bitwise the untimed ones, one span per
+    launch (direct calls and graph replays), each span positive and of the
+    order of the event-timed duration; other model kinds refuse the mode."""
+    import torch
+    from paper_1710_08826_amd import FitNLLError, Model
+    for free in (False, True):
+        say("span timing, free lineshapes", free)
+        d = synth.dalitz_desc(free_lineshapes=free)
+        th = synth.dalitz_truth(free_lineshapes=free)
+        m = Model(d)
+        ev = to_dev(synth.dalitz_events(200_000, seed=87))
+        ref = m.nll(th, ev, grad=True)
+        ms_ev = _check(m, th, ev)
+        m.set_timing(True, span=True)
+        v, g = m.nll(th, ev, grad=True)
+        assert v == ref[0] and np.array_equal(g, ref[1])
+        tdev = torch.from_numpy(th).cuda()
+        out = torch.empty(1 + m.n_params, dtype=torch.float64, device="cuda")
+        s = torch.cuda.Stream()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=s, capture_error_mode="thread_local"):
+            m.nll_async(tdev, ev, out, True)
+        replays = 7
+        for _ in range(replays):
+            graph.replay()
+        torch.cuda.synchronize()
+        assert out[0].item() == ref[0] and np.array_equal(out[1:].cpu().numpy(), ref[1])
+        ms, launches = m.kernel_time()
+        assert launches == 1 + replays, launches
+        per = ms / launches
+        say("  span ms per launch", per, "event-timed", ms_ev)
+        assert 0.0 < per < 3.0 * ms_ev
+        assert m.kernel_time() == (0.0, 0)  # reset by the query
+        m.set_timing(False)
+        m.nll(th, ev, grad=True)
+        assert m.kernel_time() == (0.0, 0)
+    mm = Model(synth.mix1d_desc())
+    with pytest.raises(FitNLLError, match="span"):
+        mm.set_timing(True, span=True)
