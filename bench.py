@@ -189,23 +189,40 @@ MAX_TRIALS = 2000
 KERNEL_TIMING_LAUNCHES = 50
 
 
+GRAPH_STEPS = 8  # NLL steps per captured graph (a replay costs about 4.7 us of launch latency)
+
+
 def capture_steps(model, thetas, ev, out, with_grad):
-    """One hipGraph per trial point, each holding one asynchronous NLL(+grad)
-    call (prologue if any, events pass, level-2 step), captured on a side
+    """Captured step graphs: for each size 8, 4, 2, 1 one hipGraph holding that
+    many asynchronous NLL(+grad) calls (prologue if any, events pass, level-2
+    step) with theta alternating between the trial points, captured on a side
     stream after the model's caches are built; None when capture fails."""
     import torch
-    graphs = []
+    graphs = {}
     s = torch.cuda.Stream()
     try:
-        for th in thetas:
+        for size in (GRAPH_STEPS, 4, 2, 1):
             g = torch.cuda.CUDAGraph()
             with torch.cuda.graph(g, stream=s, capture_error_mode="thread_local"):
-                model.nll_async(th, ev, out, with_grad)
-            graphs.append(g)
+                for i in range(size):
+                    model.nll_async(thetas[i % len(thetas)], ev, out, with_grad)
+            graphs[size] = g
     except Exception as e:  # noqa: BLE001 - reported in the bench line
         print(f"[bench] graph capture failed ({e}); timing direct launches", file=sys.stderr, flush=True)
         return None
     return graphs
+
+
+def replay_steps(graphs, k):
+    """Exactly k steps from the captured graphs: k // 8 replays of the 8-step
+    graph, then the remainder by its binary digits."""
+    for _ in range(k // GRAPH_STEPS):
+        graphs[GRAPH_STEPS].replay()
+    r = k % GRAPH_STEPS
+    for size in (4, 2, 1):
+        if r >= size:
+            graphs[size].replay()
+            r -= size
 
 
 def time_async(model, theta_dev, ev, out, steps, warmup, with_grad=True, alt=None, graph=True):
@@ -228,8 +245,7 @@ def time_async(model, theta_dev, ev, out, steps, warmup, with_grad=True, alt=Non
     def trials_of(graphs):
         def run(k):
             if graphs:
-                for i in range(k):
-                    graphs[i % len(graphs)].replay()
+                replay_steps(graphs, k)
             else:
                 for i in range(k):
                     model.nll_async(thetas[i % len(thetas)], ev, out, with_grad)
