@@ -102,11 +102,20 @@ __device__ void dalitz_finalize_body(const DalitzConst& dc, const DalitzTable* _
   const int K = dc.K;
   const int P = dc.free_ls ? 4 * K : 2 * K;
   const int t = threadIdx.x;
-  // the small inputs are loaded first: their latency overlaps the row sums
+  // the small inputs are loaded first, so that their latency overlaps the row
+  // sums, in forms that make no wave wait for them before the rows are
+  // requested (a zero written before a load; I and dI loaded by every thread
+  // at a clamped index and used only where t <= P)
   const bool own_norm = !f.npart && !f.norm_ready;
-  const double mv = own_norm && t < 2 * K * K ? f.Mc[t] : 0.0;
-  const double cv = own_norm && t < 2 * K ? f.coef[t] : 0.0;
-  const double nrm = f.norm_ready && t <= P ? f.out[1 + P + t] : 0.0;  // I, then dI
+  double mv = 0.0, cv = 0.0;
+  if (own_norm && t < 2 * K * K) mv = f.Mc[t];
+  if (own_norm && t < 2 * K) cv = f.coef[t];
+  const double nrm = f.out[1 + P + (t <= P ? t : P)];  // I, then dI
+  // the validity flag as a vector load (lane-varying zero offset): a scalar
+  // one would be waited for with the kernel arguments, before the rows
+  int zero = 0;
+  asm volatile("" : "+v"(zero));
+  const double valid = (&tab->valid)[zero];
   sum_rows_t<kFinalBlock>(evpart, ev_rows, ev_nv, L.scratch, L.res);
   if (f.npart) sum_rows_t<kFinalBlock>(f.npart, f.n_rows, f.n_nv, L.scratch, L.nres);
   if (f.norm_ready) {
@@ -151,7 +160,7 @@ __device__ void dalitz_finalize_body(const DalitzConst& dc, const DalitzTable* _
     __syncthreads();
   }
   const double I = L.I;
-  const bool okI = tab->valid != 0.0 && I > 0.0 && isfinite(I);
+  const bool okI = valid != 0.0 && I > 0.0 && isfinite(I);
   if (t == 0) {
     const double v = okI ? L.res[0] + f.n_events * log(I) : INFINITY;
     f.out[0] = v;

@@ -55,51 +55,87 @@ __device__ inline void block_sum_row(double (&v)[NV], double* lds /* block_sum_l
 }
 
 // Level 2: res[v] = sum over rows r of part[r*nv + v], for v < nv <= TB (the
-// block size).  Thread t takes column t % nv and rows g, g+G, g+2G, ... with
-// g = t / nv, G = TB / nv, in eight interleaved partial sums (eight
-// independent loads in flight per thread: the rows were just written by other
-// compute units, so this step is load-latency bound; a large block keeps the
-// number of rounds per thread small); the partial sums are added pairwise and
-// the G group sums of each column by a pairwise tree over g.  scratch holds TB
+// block size).  The rows were just written by other compute units and the
+// whole block runs on one compute unit, so the step is bound by load latency,
+// by the compute unit's load bandwidth and by its barriers (measured on
+// gfx950 with the device wall clock, 1M events of the three-body model, 489
+// rows of 17 values: the first thread's rows back after 0.9 us, every
+// thread's after 1.6 us).  Thread t takes column v = t % nv and rows g, g+G,
+// g+2G, ... (g = t / nv, G = TB / nv): ten rows per round, all loads issued
+// before the first is used (rows past the end are not loaded and count zero;
+// up to 10 G rows -- 600 of 17 values with a 1024-thread block -- take one
+// round trip), added in row order.  Addresses are 32-bit byte offsets from
+// the uniform base whenever the rows span less than 4 GB.  The G group sums
+// of each column are then added in two levels, one barrier each: J = min(8,
+// G) threads per column each add the groups j, j+J, j+2J, ... in order, then
+// one thread per column adds the J results in order.  scratch holds TB
 // doubles.
 template <int TB>
 __device__ inline void sum_rows_t(const double* __restrict__ part, int64_t nrows, int nv, double* scratch,
                                   double* res) {
-  constexpr int U = 8;
+  constexpr int U = 10;
   const int t = threadIdx.x;
   const int G = TB / nv;
   const int g = t / nv;
   const int v = t - g * nv;
   double s = 0.0;
   if (g < G) {
-    double a[U];
+    if ((nrows + (int64_t)U * G) * nv * 8 < (int64_t(1) << 32)) {
+      const char* __restrict__ base = reinterpret_cast<const char*>(part);
+      const unsigned step = (unsigned)(G * nv) * 8u;
+      unsigned o = (unsigned)(g * nv + v) * 8u;
+      for (int64_t r = g; r < nrows; r += (int64_t)U * G, o += U * step) {
+        double x[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) a[u] = 0.0;
-    int64_t r = g;
-    const int64_t step = G;
-    for (; r + (U - 1) * step < nrows; r += U * step) {
-      double x[U];
+        for (int u = 0; u < U; ++u) {
+          x[u] = 0.0;
+          if (r + (int64_t)u * G < nrows) x[u] = *reinterpret_cast<const double*>(base + o + u * step);
+        }
 #pragma unroll
-      for (int u = 0; u < U; ++u) x[u] = part[(r + u * step) * nv + v];
+        for (int u = 0; u < U; ++u) s += x[u];
+      }
+    } else {
+      for (int64_t r = g; r < nrows; r += (int64_t)U * G) {
+        double x[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) a[u] += x[u];
+        for (int u = 0; u < U; ++u) {
+          x[u] = 0.0;
+          if (r + (int64_t)u * G < nrows) x[u] = part[(r + (int64_t)u * G) * nv + v];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) s += x[u];
+      }
     }
-    for (; r < nrows; r += step) a[0] += part[r * nv + v];
-#pragma unroll
-    for (int w = U / 2; w > 0; w >>= 1)
-#pragma unroll
-      for (int u = 0; u < w; ++u) a[u] += a[u + w];
-    s = a[0];
+    scratch[t] = s;
   }
-  scratch[t] = s;
   __syncthreads();
-  int h = 1;
-  while (h < G) h <<= 1;
-  for (h >>= 1; h > 0; h >>= 1) {
-    if (g < h && g + h < G) scratch[t] += scratch[t + h * nv];
-    __syncthreads();
+  // (each level's LDS reads are issued eight at a time, at clamped indices,
+  // so that their latencies overlap)
+  const int J = G < 8 ? G : 8;
+  if (g < J) {
+    double a = 0.0;
+    for (int h0 = g; h0 < G; h0 += 8 * J) {
+      double y[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int h = h0 + i * J;
+        y[i] = scratch[(h < G ? h : g) * nv + v];
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) a += h0 + i * J < G ? y[i] : 0.0;
+    }
+    scratch[t] = a;  // read by no other thread of this level
   }
-  if (t < nv) res[t] = scratch[t];
+  __syncthreads();
+  if (t < nv) {
+    double y[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) y[j] = scratch[(j < J ? j : 0) * nv + t];
+    double a = y[0];
+#pragma unroll
+    for (int j = 1; j < 8; ++j) a += j < J ? y[j] : 0.0;
+    res[t] = a;
+  }
   __syncthreads();
 }
 

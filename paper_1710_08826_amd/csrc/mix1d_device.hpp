@@ -286,14 +286,20 @@ __device__ inline void mix1d_finalize_one(const Mix1dConst& mc, const Mix1dTable
                                           const double* part, int64_t nrows, int nv, int kmax,
                                           int with_grad, double n_events, double* out, double* out_user,
                                           double* scratch, double* res) {
+  // the validity flag and the yield as vector loads issued before the row
+  // sums (a lane-varying zero offset: scalar loads would be waited for with
+  // the first kernel argument, before the rows are requested)
+  int zero = 0;
+  asm volatile("" : "+v"(zero));
+  const double valid = (&t.valid)[zero], yield = (&t.yield)[zero];
   sum_rows(part, nrows, nv, scratch, res);
   const int P = mc.n_params;
   const int p = threadIdx.x;
-  const bool ok = t.valid != 0.0;
+  const bool ok = valid != 0.0;
   const bool ext = mc.yidx >= 0;
   if (p == 0) {
     double v = res[0];
-    if (ext) v += t.yield - n_events * log(t.yield);
+    if (ext) v += yield - n_events * log(yield);
     out[0] = ok ? v : INFINITY;
     out[1 + P] = 1.0;
     if (out_user) out_user[0] = out[0];
@@ -302,7 +308,7 @@ __device__ inline void mix1d_finalize_one(const Mix1dConst& mc, const Mix1dTable
     out[2 + P + p] = 0.0;
     if (with_grad) {
       double g = mix1d_param_grad(mc, kmax, res + 1, p);
-      if (ext && p == mc.yidx) g += 1.0 - n_events / t.yield;
+      if (ext && p == mc.yidx) g += 1.0 - n_events / yield;
       if (!ok) g = NAN;
       out[1 + p] = g;
       if (out_user) out_user[1 + p] = g;

@@ -163,23 +163,40 @@ __global__ __launch_bounds__(kFinalBlock) void td4_finalize(Td4Const tc, const T
   __shared__ double gI[4 * kTd4MaxAmp + 2];    // dI/dtheta in theta order
   __shared__ double form[4];                   // a, b, Re z, Im z
   __shared__ double Ish;
+  __shared__ double cc[4 * kTd4MaxAmp];        // c then cb, (Re, Im) per amplitude
+  static_assert(2 * kTd4MaxAmp * kTd4MaxAmp <= kFinalBlock, "one entry of M per thread");
   const int f = blockIdx.x;
   if (status && status[f] != 1) return;
   const Td4Table& tb = tabs[f];
   const int K = tc.K, P = tc.n_params;
   const int t = threadIdx.x;
+  // M, the coefficients, x, y and the validity flag are loaded first, by every
+  // thread (clamped indices, values not needed discarded; lane-varying offsets
+  // so that the uniform ones are vector loads too): no wait for them comes
+  // before the rows are requested, and their latency overlaps the row sums
+  int zero = 0;
+  asm volatile("" : "+v"(zero));
+  constexpr int nm = 2 * kTd4MaxAmp * kTd4MaxAmp;
+  const double mv = Mc[(int64_t)f * nm + (t < nm ? t : 0)];
+  static_assert(offsetof(Td4Table, cb) == offsetof(Td4Table, c) + 2 * kTd4MaxAmp * sizeof(double),
+                "cb follows c");
+  const double cv = reinterpret_cast<const double*>(&tb)[offsetof(Td4Table, c) / sizeof(double) +
+                                                         (t < 4 * kTd4MaxAmp ? t : 0)];
+  const double x = (&tb.x)[zero], y = (&tb.y)[zero], valid = (&tb.valid)[zero];
   sum_rows_t<kFinalBlock>(part + (int64_t)f * rows * nv, rows, nv, scratch, res);
-  for (int i = t; i < 2 * kTd4MaxAmp * kTd4MaxAmp; i += kFinalBlock)
-    M[i] = Mc[(int64_t)f * 2 * kTd4MaxAmp * kTd4MaxAmp + i];
+  if (t < nm) M[t] = mv;
+  if (t < 4 * kTd4MaxAmp) cc[t] = cv;
   __syncthreads();
   auto m = [&](int i, int j) { return cplx{M[2 * (i * kTd4MaxAmp + j)], M[2 * (i * kTd4MaxAmp + j) + 1]}; };
+  const double* c = cc;
+  const double* cb = cc + 2 * kTd4MaxAmp;
   // thread k < K: the k-th entries of the four matrix-vector products
   if (t < K) {
     const int k = t;
     double Xr = 0.0, Xi = 0.0, Yr = 0.0, Yi = 0.0, Ur = 0.0, Ui = 0.0, Vr = 0.0, Vi = 0.0;
     for (int j = 0; j < K; ++j) {
       const cplx mkj = m(k, j), mjk = m(j, k);
-      const double cjr = tb.c[j][0], cji = tb.c[j][1], bjr = tb.cb[j][0], bji = tb.cb[j][1];
+      const double cjr = c[2 * j], cji = c[2 * j + 1], bjr = cb[2 * j], bji = cb[2 * j + 1];
       // X_k += M_kj conj(c_j), Y_k += M_kj conj(cb_j)
       Xr += mkj.re * cjr + mkj.im * cji;
       Xi += mkj.im * cjr - mkj.re * cji;
@@ -195,17 +212,17 @@ __global__ __launch_bounds__(kFinalBlock) void td4_finalize(Td4Const tc, const T
     XYUV[4][k] = Ur; XYUV[5][k] = Ui; XYUV[6][k] = Vr; XYUV[7][k] = Vi;
   }
   __syncthreads();
-  const double G = tc.gamma, x = tb.x, y = tb.y;
+  const double G = tc.gamma;
   const double cy = 1.0 / (G * (1.0 - y * y)), cx = 1.0 / (G * (1.0 + x * x));
   if (t == 0) {
     // the quadratic forms, summed over k in order
     double a = 0.0, b = 0.0, zr = 0.0, zi = 0.0;
     for (int k = 0; k < K; ++k) {
-      a += tb.c[k][0] * XYUV[0][k] - tb.c[k][1] * XYUV[1][k];
-      b += tb.cb[k][0] * XYUV[2][k] - tb.cb[k][1] * XYUV[3][k];
+      a += c[2 * k] * XYUV[0][k] - c[2 * k + 1] * XYUV[1][k];
+      b += cb[2 * k] * XYUV[2][k] - cb[2 * k + 1] * XYUV[3][k];
       // z = sum_k conj(c_k) U_k
-      zr += tb.c[k][0] * XYUV[4][k] + tb.c[k][1] * XYUV[5][k];
-      zi += tb.c[k][0] * XYUV[5][k] - tb.c[k][1] * XYUV[4][k];
+      zr += c[2 * k] * XYUV[4][k] + c[2 * k + 1] * XYUV[5][k];
+      zi += c[2 * k] * XYUV[5][k] - c[2 * k + 1] * XYUV[4][k];
     }
     form[0] = a;
     form[1] = b;
@@ -235,7 +252,7 @@ __global__ __launch_bounds__(kFinalBlock) void td4_finalize(Td4Const tc, const T
   }
   __syncthreads();
   const double I = Ish;
-  const bool ok = tb.valid != 0.0 && I > 0.0 && isfinite(I);
+  const bool ok = valid != 0.0 && I > 0.0 && isfinite(I);
   double* o = out + (int64_t)f * out_stride;
   if (t == 0) {
     o[0] = ok ? res[0] + n_events * log(I) : INFINITY;

@@ -81,14 +81,23 @@ __global__ __launch_bounds__(kFinalBlock) void tddp_finalize(DalitzConst dc, con
   const int K = dc.K;
   const int P = 4 * K + 2;
   const int t = threadIdx.x;
-  // the three matrices are loaded first: their latency overlaps the row sums
+  // the three matrices and the coefficients are loaded first, by every thread
+  // (clamped indices, values past the end discarded: no branch makes a wave
+  // wait for them), so that their latency overlaps the row sums
   const int nm = 6 * K * K;
   double mv[(6 * kDalMaxRes * kDalMaxRes + kFinalBlock - 1) / kFinalBlock];
 #pragma unroll
   for (int u = 0; u < (int)(sizeof(mv) / sizeof(mv[0])); ++u) {
     const int i = t + u * kFinalBlock;
-    mv[u] = i < nm ? Mc[i] : 0.0;
+    mv[u] = Mc[i < nm ? i : 0];
   }
+  const int tc = t < K ? t : 0;
+  const double c0 = coef[2 * tc], c1 = coef[2 * tc + 1], c2 = coef[2 * K + 2 * tc], c3 = coef[2 * K + 2 * tc + 1];
+  // the same for the uniform values, as vector loads (a lane-varying zero
+  // offset): scalar ones would be waited for before the rows are requested
+  int zero = 0;
+  asm volatile("" : "+v"(zero));
+  const double x = coef[4 * K + zero], y = coef[4 * K + 1 + zero], valid = (&tab->valid)[zero];
   sum_rows_t<kFinalBlock>(part, nrows, nv, L.scratch, L.res);
 #pragma unroll
   for (int u = 0; u < (int)(sizeof(mv) / sizeof(mv[0])); ++u) {
@@ -96,10 +105,10 @@ __global__ __launch_bounds__(kFinalBlock) void tddp_finalize(DalitzConst dc, con
     if (i < nm) L.M[i] = mv[u];
   }
   if (t < K) {
-    L.cre[t] = coef[2 * t];
-    L.cim[t] = coef[2 * t + 1];
-    L.bre[t] = coef[2 * K + 2 * t];
-    L.bim[t] = coef[2 * K + 2 * t + 1];
+    L.cre[t] = c0;
+    L.cim[t] = c1;
+    L.bre[t] = c2;
+    L.bim[t] = c3;
   }
   __syncthreads();
   const double* MAA = L.M;
@@ -141,12 +150,11 @@ __global__ __launch_bounds__(kFinalBlock) void tddp_finalize(DalitzConst dc, con
     L.Ia = ia; L.Ib = ib; L.Zr = zr; L.Zi = zi;
   }
   __syncthreads();
-  const double x = coef[4 * K], y = coef[4 * K + 1];
   const double tau = 1.0 / tt.gamma;
   const double dy = 1.0 - y * y, dx = 1.0 + x * x;
   const double cy = tau / dy, cx = tau / dx;
   const double I = 0.5 * (cy * (L.Ia + L.Ib) + cx * (L.Ia - L.Ib) - 2.0 * y * cy * L.Zr - 2.0 * x * cx * L.Zi);
-  const bool ok = tab->valid != 0.0 && I > 0.0 && isfinite(I) && dy > 0.0;
+  const bool ok = valid != 0.0 && I > 0.0 && isfinite(I) && dy > 0.0;
   if (t == 0) {
     const double v = ok ? L.res[0] + n_events * log(I) : INFINITY;
     out[0] = v;
