@@ -81,6 +81,7 @@ struct DalFinal {
   double* out;               // [NLL, grad(P), I, dI(P)]
   double* out_user;          // optional [NLL, grad(P)]
   unsigned long long* span;  // span record of the measured events pass (or nullptr)
+  int64_t span_blocks;       // workgroups of that pass
 };
 
 struct DalFinalLds {
@@ -186,9 +187,31 @@ __global__ __launch_bounds__(kFinalBlock) void dalitz_finalize(DalitzConst dc, c
                                                           int ev_nv, int kmax, DalFinal fin) {
   __shared__ DalFinalLds L;
   unsigned long long lo = 0, hi = 0;
-  if (fin.span) span_load<kFinalBlock>(fin.span, ev_rows, lo, hi);
+  if (fin.span) span_load<kFinalBlock>(fin.span, fin.span_blocks, lo, hi);
   dalitz_finalize_body(dc, tab, evpart, ev_rows, ev_nv, kmax, fin, L);
-  if (fin.span) span_add<kFinalBlock>(fin.span, ev_rows, lo, hi, L.scratch);
+  if (fin.span) span_add<kFinalBlock>(fin.span, fin.span_blocks, lo, hi, L.scratch);
+}
+
+// Pre-summation of long row sets (before the level-2 step, which then reads
+// one row per workgroup here instead of all of them through one compute
+// unit): workgroup b < s0 adds rows [b R, (b+1) R) of set 0 in row order into
+// row b of o0, the others the same for set 1.
+__global__ __launch_bounds__(kBlock) void rows_presum(const double* __restrict__ p0, int64_t n0, int nv0,
+                                                      double* __restrict__ o0, int64_t s0,
+                                                      const double* __restrict__ p1, int64_t n1, int nv1,
+                                                      double* __restrict__ o1, int rows_per_block) {
+  __shared__ double scratch[kBlock];
+  __shared__ double res[kBlock];
+  const int64_t b = blockIdx.x;
+  const bool first = b < s0;
+  const int64_t bb = first ? b : b - s0;
+  const double* p = first ? p0 : p1;
+  const int64_t n = first ? n0 : n1;
+  const int nv = first ? nv0 : nv1;
+  const int64_t r0 = bb * rows_per_block;
+  const int64_t rr = n - r0 < rows_per_block ? n - r0 : rows_per_block;
+  sum_rows_t<kBlock>(p + r0 * nv, rr, nv, scratch, res);
+  if ((int)threadIdx.x < nv) (first ? o0 : o1)[bb * nv + threadIdx.x] = res[threadIdx.x];
 }
 
 // Level-2 of the M-row passes: rows i0..i0+3 of M (scaled by dA) into Mc.
@@ -350,6 +373,7 @@ static DalFinal make_final(const double* npart, int64_t n_rows, int n_nv, const 
                            double n_events, bool grad, bool norm_ready, double* out, double* out_user) {
   DalFinal f;
   f.span = nullptr;
+  f.span_blocks = 0;
   f.norm_ready = norm_ready ? 1 : 0;
   f.npart = npart;
   f.n_rows = n_rows;
@@ -373,16 +397,40 @@ void dalitz_launch_events(const DalitzJit& j, const DalitzConst& dc, const Dalit
               Mc && out ? out + 1 + P : nullptr, start, stop, span);
 }
 
-void dalitz_launch_finalize(const DalitzConst& dc, const DalitzTable* tab, const double* coef, const double* evpart,
-                            int64_t ev_rows, int grad, const double* npart, int64_t n_rows, int n_nv,
+int64_t dalitz_presum_blocks(int64_t rows, int nv, int64_t other_rows, int other_nv) {
+  const int64_t bytes = 8 * (rows * nv + other_rows * other_nv);
+  return bytes > kPresumMinBytes ? (rows + kPresumRows - 1) / kPresumRows : 0;
+}
+
+void dalitz_launch_finalize(const DalitzConst& dc, const DalitzTable* tab, const double* coef, double* evpart,
+                            int64_t ev_rows, int grad, double* npart, int64_t n_rows, int n_nv,
                             const double* Mc, double n_events, double* out, double* out_user, hipStream_t s,
                             bool norm_ready, unsigned long long* span) {
   const int kmax = dalitz_kmax(dc.K);
+  const int ev_nv = dal_nv(kEvents, grad, kmax);
+  const int64_t span_blocks = ev_rows;
+  // long row sets: pre-summed by many workgroups into the room the caller
+  // left after each set's rows
+  const int64_t se = dalitz_presum_blocks(ev_rows, ev_nv, npart ? n_rows : 0, n_nv);
+  if (se > 0) {
+    const int64_t sg = npart ? dalitz_presum_blocks(n_rows, n_nv, ev_rows, ev_nv) : 0;
+    double* ev_red = evpart + ev_rows * ev_nv;
+    double* n_red = npart ? npart + n_rows * n_nv : nullptr;
+    hipLaunchKernelGGL(rows_presum, dim3((unsigned)(se + sg)), dim3(kBlock), 0, s, evpart, ev_rows, ev_nv, ev_red,
+                       se, npart, n_rows, n_nv, n_red, kPresumRows);
+    evpart = ev_red;
+    ev_rows = se;
+    if (npart) {
+      npart = n_red;
+      n_rows = sg;
+    }
+  }
   DalFinal fin = make_final(npart, n_rows, n_nv, Mc, coef, n_events, grad != 0, norm_ready && !npart, out,
                             out_user);
   fin.span = span;
-  hipLaunchKernelGGL(dalitz_finalize, dim3(1), dim3(kFinalBlock), 0, s, dc, tab, evpart, ev_rows,
-                     dal_nv(kEvents, grad, kmax), kmax, fin);
+  fin.span_blocks = span_blocks;
+  hipLaunchKernelGGL(dalitz_finalize, dim3(1), dim3(kFinalBlock), 0, s, dc, tab, evpart, ev_rows, ev_nv, kmax,
+                     fin);
 }
 
 void dalitz_launch_grid(const DalitzJit& j, const DalitzConst& dc, const DalitzTable* tab, const double* coef,

@@ -59,8 +59,14 @@ void dalitz_launch_events(const DalitzJit& j, const DalitzConst& dc, const Dalit
 // Level-2 sum of the event rows and of the normalization (grid rows, or the
 // cached M when npart is null), NLL assembly: out = [NLL, grad, I, dI].
 // norm_ready: the events pass already wrote I and dI into out (cached M).
-void dalitz_launch_finalize(const DalitzConst& dc, const DalitzTable* tab, const double* coef, const double* evpart,
-                            int64_t ev_rows, int grad, const double* npart, int64_t n_rows, int n_nv,
+// When the two row sets hold more than kPresumMinBytes, workgroups of
+// kPresumRows rows each pre-sum them first, into dalitz_presum_blocks(...)
+// rows that the caller leaves free after each set (evpart, npart: writable).
+constexpr int kPresumRows = 16;
+constexpr int64_t kPresumMinBytes = 131072;
+int64_t dalitz_presum_blocks(int64_t rows, int nv, int64_t other_rows, int other_nv);
+void dalitz_launch_finalize(const DalitzConst& dc, const DalitzTable* tab, const double* coef, double* evpart,
+                            int64_t ev_rows, int grad, double* npart, int64_t n_rows, int n_nv,
                             const double* Mc, double n_events, double* out, double* out_user, hipStream_t s,
                             bool norm_ready = false, unsigned long long* span = nullptr);
 void dalitz_launch_grid(const DalitzJit& j, const DalitzConst& dc, const DalitzTable* tab, const double* coef,

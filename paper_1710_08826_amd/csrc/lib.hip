@@ -515,7 +515,13 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
     const int kmax = dalitz_kmax(dc.K);
     const int g = grad ? (dc.free_ls ? 2 : 1) : 0;
     const int nv = dalitz_nv_events(kmax, g);
-    events_rows((size_t)(nch > 0 ? nch : 1) * nv);
+    // grid rows when the lineshapes are free; long row sets get room for
+    // their pre-summed rows after them (see dalitz_launch_finalize)
+    const int64_t grid_rows_n = dc.free_ls ? nchunks_for((int64_t)dc.nx * dc.ny, m->grid_chunk) : 0;
+    const int grid_nv = dc.free_ls ? dalitz_nv_events(kmax, g) : 0;
+    const int64_t pre_e = dalitz_presum_blocks(nch, nv, grid_rows_n, grid_nv);
+    const int64_t pre_g = pre_e > 0 && dc.free_ls ? dalitz_presum_blocks(grid_rows_n, grid_nv, nch, nv) : 0;
+    events_rows((size_t)((nch > 0 ? nch : 1) + pre_e) * nv);
     // The table holds the lineshape constants (functions of theta only when the
     // lineshapes are free) and a copy of the coefficients; with fixed lineshapes
     // and theta on the device, the passes read the coefficients from theta and
@@ -526,15 +532,14 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
       if (!dc.free_ls) m->table_ready = true;
     }
     const double* coef = theta_dev ? theta_dev : m->table_dal()->coef;
-    const double* grid_rows = nullptr;
+    double* grid_rows = nullptr;
     int64_t nrows = 0;
     int nnv = 0;
     if (dc.free_ls) {
       // lineshapes move: integrate P~ (and dP~) over the grid every call
-      const int64_t ncell = (int64_t)dc.nx * dc.ny;
-      nrows = nchunks_for(ncell, m->grid_chunk);
-      nnv = dalitz_nv_events(kmax, g);
-      norm_rows((size_t)nrows * nnv);
+      nrows = grid_rows_n;
+      nnv = grid_nv;
+      norm_rows((size_t)(nrows + pre_g) * nnv);
       dalitz_launch_grid(*m->dal_jit, dc, m->table_dal(), coef, m->grid_chunk, nrows, g, npart, s);
       grid_rows = npart;
     } else if (!m->M_valid) {

@@ -116,6 +116,30 @@ def test_full_size_config3(m3, cells1):
     assert ok, r
 
 
+def test_presummed_level2(m1, cells1):
+    """2.5M events at chunk 2048 give 1221 event rows of 17 sums, more than the
+    level-2 step reads through one compute unit: workgroups of 16 rows pre-sum
+    them first.  The result matches the oracle, and a level-2 step over the
+    154 rows of chunk 16384 (no pre-summation), within rounding."""
+    from paper_1710_08826_amd import Model
+    ev = synth.dalitz_events(2_500_000, seed=38)
+    evd = to_dev(ev)
+    th = offset(TH1)
+    say("dalitz presummed level 2: device")
+    m_big = Model(dict(D1, chunk=16384))
+    v, g = m1.nll(th, evd, grad=True)
+    vb, gb = m_big.nll(th, evd, grad=True)
+    assert m1.chunk == 2048 and m_big.chunk == 16384
+    assert rel_close(v, vb, 1e-13), (v, vb)
+    ok, r = grad_close(g, gb, 1e-12)
+    assert ok, r
+    say("dalitz presummed level 2: oracle")
+    vo, go = OD.nll_grad(th, ev, D1, cells1)
+    assert rel_close(v, vo, 1e-12), (v, vo)
+    ok, r = grad_close(g, go, 1e-10)
+    assert ok, r
+
+
 def test_eval_matches_oracle_density(m1, cells1):
     ev = synth.dalitz_events(2000, seed=35)
     p = m1.eval(TH1, to_dev(ev)).cpu().numpy()
