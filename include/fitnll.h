@@ -123,9 +123,9 @@ typedef struct fn_model fn_model;
  *     The lineshape constants and sigma_t form the model's fixed-constant
  *     vector (fn_model_fixed): (m0, w0) of every r12 entry, of every r34
  *     entry, then sigma_t.
- *  Optional keys for every kind: "chunk" (events per workgroup, a power of two
- *  in [256, 65536], default chosen per kind) -- fixed per model, it defines
- *  the summation tree.
+ *  Optional keys for every kind: "chunk" (events per workgroup, a multiple of
+ *  256 in [256, 2^22], default chosen per kind) -- fixed per model, it
+ *  defines the summation tree.
  * Returns FN_E_INVALID with a message for a malformed description. */
 fn_status fn_model_create(fn_ctx* ctx, const char* desc_json, fn_model** out);
 /* Compile a description's structure-specialized kernels for the GPU
@@ -141,17 +141,23 @@ fn_status fn_model_info(const fn_model* m, int32_t* n_params, int32_t* n_obs, in
 fn_status fn_model_destroy(fn_model* m);
 /* Autotuner of the summation chunk (events per workgroup; it also fixes the
  * order of the sums): times the full NLL + gradient evaluation at theta (host,
- * P doubles) on the caller's events (device, as fn_nll) for the chunks 256,
- * 512, ..., 16384 (3 warm-up calls, then the median of reps timed calls, HIP
- * events on `stream`; reps < 1 means 20), keeps the largest chunk whose time
- * is within 2% of the fastest as the model's chunk (reported by fn_model_info
+ * P doubles) on the caller's events (device, as fn_nll) for each candidate
+ * chunk (3 warm-up calls, then the median of reps timed calls, HIP events on
+ * `stream`; reps < 1 means 20), keeps the largest candidate whose time is
+ * within 2% of the fastest as the model's chunk (reported by fn_model_info
  * and used by every later evaluation and by batches created afterwards) and
- * writes it to *chunk_out.  us_out (may be
- * NULL) receives the 7 median times in microseconds.  Synchronous.
- * FN_E_INVALID for NULL theta, n < 1 or bad event arguments; the model keeps
- * its previous chunk on any error. */
+ * writes it to *chunk_out.  The candidates are the powers of two 256 ..
+ * 16384, then the multiples of 256 that give the sample j x (number of
+ * compute units) workgroups, j = 1 .. 8 (workgroup counts that fill the
+ * device's resident slots evenly), where they differ from the first.
+ * chunks_out and us_out (each may be NULL, else FN_TUNE_MAX entries) receive
+ * the candidates and their median times in microseconds, in the order tried;
+ * unused entries hold chunk 0 and NaN.  Synchronous.  FN_E_INVALID for NULL
+ * theta, n < 1 or bad event arguments; the model keeps its previous chunk on
+ * any error. */
+#define FN_TUNE_MAX 16
 fn_status fn_model_autotune(fn_model* m, const double* theta_host, const double* ev, int64_t n, int64_t ld,
-                            int32_t reps, int32_t* chunk_out, double* us_out, void* stream);
+                            int32_t reps, int32_t* chunk_out, int32_t* chunks_out, double* us_out, void* stream);
 
 /* Count events outside the observable domain (range for mix1d; bounding box
  * and physical region, with a relative tolerance of 1e-9, for dalitz3).

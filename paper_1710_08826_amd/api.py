@@ -182,20 +182,23 @@ class Model:
                                     C.byref(used), _stream_ptr(stream)))
         return ev, used.value
 
-    TUNE_CHUNKS = (256, 512, 1024, 2048, 4096, 8192, 16384)
+    TUNE_MAX = 16  # FN_TUNE_MAX
 
     def autotune(self, theta, events: torch.Tensor, reps: int = 20, stream=None):
         """Pick the summation chunk for these events (fn_model_autotune: the
-        largest within 2% of the fastest);
-        returns (chunk, {chunk: median microseconds per NLL + gradient})."""
+        largest candidate within 2% of the fastest; candidates are the powers
+        of two 256..16384 and the chunks giving j x (compute units) workgroups,
+        j = 1..8); returns (chunk, {candidate: median microseconds per NLL +
+        gradient})."""
         th, thp = self._theta(theta)
         evp, n, ld = _events(events, self.n_obs)
         best = C.c_int32()
-        us = (C.c_double * len(self.TUNE_CHUNKS))()
-        check(self._lib.fn_model_autotune(self._h, thp, evp, n, ld, int(reps), C.byref(best), us,
+        chunks = (C.c_int32 * self.TUNE_MAX)()
+        us = (C.c_double * self.TUNE_MAX)()
+        check(self._lib.fn_model_autotune(self._h, thp, evp, n, ld, int(reps), C.byref(best), chunks, us,
                                           _stream_ptr(stream)))
         self.chunk = best.value
-        return best.value, dict(zip(self.TUNE_CHUNKS, list(us)))
+        return best.value, {c: t for c, t in zip(chunks, us) if c > 0}
 
     def set_timing(self, enable: bool, every: int = 1, span: bool = False):
         """Time every `every`-th per-event kernel launch (the dispatch records its own

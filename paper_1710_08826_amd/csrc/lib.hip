@@ -29,10 +29,31 @@ constexpr int kGenMaxAttemptsTd4 = 65536;  // four-body model acceptance is near
 // fn_model_generate_norm_sample is that of the input sampler's default).
 constexpr uint32_t kPhaseSpaceStream0 = 100;
 
-// Chunk sizes (events per workgroup) tried by fn_model_autotune.
-constexpr int kTuneChunks[] = {256, 512, 1024, 2048, 4096, 8192, 16384};
-constexpr int kTuneCount = (int)(sizeof(kTuneChunks) / sizeof(kTuneChunks[0]));
+// Chunk sizes (events per workgroup) tried by fn_model_autotune: the powers
+// of two 256 .. 16384, then the chunks (multiples of 256) that give j times
+// as many workgroups as the device has compute units, j = 1 .. 8 -- counts
+// that fill the resident workgroup slots evenly, without a partly filled last
+// round (a pass of 1221 workgroups at two per compute unit runs 2.4 rounds
+// on 256 compute units) -- where they differ from the first ones.
+constexpr int kTunePow2 = 7;
+constexpr int kTuneMultiples = 8;
+constexpr int kMaxChunk = 1 << 22;
+static_assert(kTunePow2 + kTuneMultiples <= FN_TUNE_MAX, "candidate table");
 constexpr double kTuneTie = 0.02;  // relative time difference treated as a tie
+
+static int tune_candidates(int64_t n, int cus, int32_t* out) {
+  int c = 0;
+  for (int k = 0; k < kTunePow2; ++k) out[c++] = 256 << k;
+  for (int j = 1; j <= kTuneMultiples; ++j) {
+    const int64_t per = (n + (int64_t)j * cus - 1) / ((int64_t)j * cus);
+    int64_t ch = (per + 255) / 256 * 256;
+    ch = ch < 256 ? 256 : (ch > kMaxChunk ? kMaxChunk : ch);
+    bool seen = false;
+    for (int i = 0; i < c; ++i) seen = seen || out[i] == (int32_t)ch;
+    if (!seen) out[c++] = (int32_t)ch;
+  }
+  return c;
+}
 
 // Scratch of the allocation-free NLL entry point (fn_nll_async_noalloc): the
 // partial rows of one call, 2^21 doubles (16 MiB) on every device the library
@@ -106,7 +127,6 @@ void DevBuf::release() {
 }
 
 // ------------------------------------------------------------ model compiler
-static bool is_pow2(long v) { return v > 0 && (v & (v - 1)) == 0; }
 
 static void compile_mix1d(const json::Value& d, fn_model* m) {
   Mix1dConst& mc = m->mix;
@@ -754,7 +774,8 @@ fn_status fn_model_create(fn_ctx* ctx, const char* desc_json, fn_model** out) {
       }
       if (d.has("chunk")) {
         const long c = d.at("chunk").integer();
-        if (!is_pow2(c) || c < 256 || c > 65536) throw Error(FN_E_INVALID, "chunk must be a power of two in [256, 65536]");
+        if (c % 256 != 0 || c < 256 || c > kMaxChunk)
+          throw Error(FN_E_INVALID, "chunk must be a multiple of 256 in [256, " + std::to_string(kMaxChunk) + "]");
         m->chunk = (int)c;
       }
     } catch (const Error&) {
@@ -824,7 +845,7 @@ fn_status fn_model_destroy(fn_model* m) {
 }
 
 fn_status fn_model_autotune(fn_model* m, const double* theta_host, const double* ev, int64_t n, int64_t ld,
-                            int32_t reps, int32_t* chunk_out, double* us_out, void* stream) {
+                            int32_t reps, int32_t* chunk_out, int32_t* chunks_out, double* us_out, void* stream) {
   return guard([&] {
     if (!m || !theta_host) throw Error(FN_E_INVALID, "NULL argument");
     if (n < 1) throw Error(FN_E_INVALID, "autotuning needs events");
@@ -834,12 +855,21 @@ fn_status fn_model_autotune(fn_model* m, const double* theta_host, const double*
     hipStream_t s = (hipStream_t)stream;
     const ParamBlock pb = make_block(m, theta_host);
     const int saved = m->chunk;
+    int cus = 0;
+    hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device),
+              "hipDeviceGetAttribute");
+    int32_t cand[FN_TUNE_MAX];
+    const int count = tune_candidates(n, cus > 0 ? cus : 1, cand);
+    if (chunks_out)
+      for (int c = 0; c < FN_TUNE_MAX; ++c) chunks_out[c] = c < count ? cand[c] : 0;
+    if (us_out)
+      for (int c = 0; c < FN_TUNE_MAX; ++c) us_out[c] = NAN;
     std::vector<hipEvent_t> evs(2 * (size_t)reps);
     for (auto& e : evs) hip_check(hipEventCreate(&e), "hipEventCreate");
-    std::vector<double> med(kTuneCount, INFINITY);
+    std::vector<double> med(count, INFINITY);
     try {
-      for (int c = 0; c < kTuneCount; ++c) {
-        m->chunk = kTuneChunks[c];
+      for (int c = 0; c < count; ++c) {
+        m->chunk = cand[c];
         for (int w = 0; w < 3; ++w) run_nll(m, &pb, nullptr, ev, n, ld, true, nullptr, s);  // warm-up, buffers
         for (int r = 0; r < reps; ++r) {
           hip_check(hipEventRecord(evs[2 * r], s), "hipEventRecord");
@@ -866,9 +896,9 @@ fn_status fn_model_autotune(fn_model* m, const double* theta_host, const double*
     // the largest chunk within kTuneTie of the fastest: fewer partial rows for
     // the level-2 step, and a stable choice when candidates time alike
     const double fastest = *std::min_element(med.begin(), med.end());
-    int best = kTuneChunks[0];
-    for (int c = 0; c < kTuneCount; ++c)
-      if (med[c] <= (1.0 + kTuneTie) * fastest) best = kTuneChunks[c];
+    int best = cand[0];
+    for (int c = 0; c < count; ++c)
+      if (med[c] <= (1.0 + kTuneTie) * fastest && cand[c] > best) best = cand[c];
     m->chunk = best;
     if (chunk_out) *chunk_out = best;
   });

@@ -30,8 +30,19 @@ def test_dalitz_autotune_then_parity():
     ev = to_dev(x)
     chunk, table = m.autotune(th, ev, reps=10)
     say("  chunk", chunk, {k: round(v, 1) for k, v in table.items()})
-    assert chunk in m.TUNE_CHUNKS and table[chunk] <= 1.02 * min(table.values())
-    assert all(table[c] > 1.02 * min(table.values()) for c in m.TUNE_CHUNKS if c > chunk)
+    # candidates: the powers of two 256..16384, and the multiples of 256 that
+    # give j x (compute units) workgroups for the 200k events, j = 1..8
+    import torch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+
+    def ceil_div(a, b):
+        return -(-a // b)
+
+    pow2 = {256 << k for k in range(7)}
+    multiples = {max(256, ceil_div(ceil_div(200_000, j * cus), 256) * 256) for j in range(1, 9)}
+    assert set(table) == pow2 | multiples, sorted(table)
+    assert chunk in table and table[chunk] <= 1.02 * min(table.values())
+    assert all(table[c] > 1.02 * min(table.values()) for c in table if c > chunk)
     assert all(np.isfinite(v) and v > 0 for v in table.values())
     assert m.chunk == chunk == _info_chunk(m)
     v, g = m.nll(th, ev, grad=True)
