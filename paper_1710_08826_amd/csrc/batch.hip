@@ -206,7 +206,7 @@ __global__ __launch_bounds__(kBlock) void batch_scan(const int* __restrict__ sta
   }
 }
 
-template <bool GRAD, int KMAX>
+template <bool GRAD, int KMAX, int SIG>
 __global__ __launch_bounds__(kBlock) void batch_eval(Mix1dConst mc, const Mix1dTable* __restrict__ tabs,
                                                      const double* const* __restrict__ ev,
                                                      const int64_t* __restrict__ nev,
@@ -227,7 +227,7 @@ __global__ __launch_bounds__(kBlock) void batch_eval(Mix1dConst mc, const Mix1dT
     }
     const int f = lo;
     const int64_t ch = it - item_base[f];
-    mix1d_chunk<GRAD, KMAX>(mc, tabs + f, ev[f], nev[f], ch, chunk, part + (part_base[f] + ch) * NV, lds);
+    mix1d_chunk<GRAD, KMAX, SIG>(mc, tabs + f, ev[f], nev[f], ch, chunk, part + (part_base[f] + ch) * NV, lds);
     __syncthreads();
   }
 }
@@ -279,12 +279,21 @@ void batch_launch_step(const BatchDev& b, const Mix1dConst& mc, int n_fits, int 
   hipLaunchKernelGGL(batch_prologue, fg, fb, 0, s, mc, b.st, b.stat, n_fits, b.tabs);
   hipLaunchKernelGGL(batch_scan, dim3(1), dim3(kBlock), 0, s, b.stat, b.nev, n_fits, chunk, b.item_base,
                      b.n_running);
-  if (kmax == 2)
-    hipLaunchKernelGGL((batch_eval<true, 2>), dim3(eval_grid), dim3(kBlock), 0, s, mc, b.tabs, b.ev, b.nev,
-                       b.item_base, b.part_base, n_fits, chunk, b.part);
-  else
-    hipLaunchKernelGGL((batch_eval<true, 8>), dim3(eval_grid), dim3(kBlock), 0, s, mc, b.tabs, b.ev, b.nev,
-                       b.item_base, b.part_base, n_fits, chunk, b.part);
+#define FN_EVAL(K, SIG)                                                                               \
+  hipLaunchKernelGGL((batch_eval<true, K, SIG>), dim3(eval_grid), dim3(kBlock), 0, s, mc, b.tabs, b.ev, b.nev, \
+                     b.item_base, b.part_base, n_fits, chunk, b.part)
+#define FN_EVAL_SIG(SIG) \
+  case SIG:              \
+    FN_EVAL(2, SIG);     \
+    break;
+  switch (mix1d_sig(mc)) {
+    FN_MIX_SIGS(FN_EVAL_SIG)
+    default:
+      if (kmax == 2) FN_EVAL(2, 0);
+      else FN_EVAL(8, 0);
+  }
+#undef FN_EVAL_SIG
+#undef FN_EVAL
   hipLaunchKernelGGL(batch_finalize, dim3(n_fits), dim3(kBlock), 0, s, mc, b.tabs, b.stat, b.nev, b.part_base, b.part,
                      chunk, nv, kmax, b.out, 2 + 2 * P);
   bfgs_launch<kBatchMaxP>(b.st, b.out, 2 + 2 * P, n_fits, P, tol, max_iter, b.stat, b.rres, s);
@@ -292,10 +301,19 @@ void batch_launch_step(const BatchDev& b, const Mix1dConst& mc, int n_fits, int 
 
 int batch_eval_blocks_per_cu(const Mix1dConst& mc) {
   int nb = 0;
-  if (mix1d_kmax(mc.K) == 2)
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_eval<true, 2>, kBlock, 0);
-  else
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_eval<true, 8>, kBlock, 0);
+#define FN_OCC_SIG(SIG)                                                                     \
+  case SIG:                                                                                 \
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_eval<true, 2, SIG>, kBlock, 0); \
+    break;
+  switch (mix1d_sig(mc)) {
+    FN_MIX_SIGS(FN_OCC_SIG)
+    default:
+      if (mix1d_kmax(mc.K) == 2)
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_eval<true, 2, 0>, kBlock, 0);
+      else
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_eval<true, 8, 0>, kBlock, 0);
+  }
+#undef FN_OCC_SIG
   return nb > 0 ? nb : 1;
 }
 

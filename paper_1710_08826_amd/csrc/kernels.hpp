@@ -9,6 +9,12 @@ namespace fn {
 
 // mix1d
 int mix1d_kmax(int K);
+// Type signature a mixture's per-event passes are compiled for (mix_sig_K):
+// 1..20 for one or two components, 0 (generic passes) for more.
+int mix1d_sig(const Mix1dConst& mc);
+// X(sig) for every signature of one or two components.
+#define FN_MIX_SIGS(X) \
+  X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) X(20)
 int mix1d_nv(int kmax, bool grad);
 void mix1d_launch_prologue(const Mix1dConst& mc, const ParamBlock& pb, const double* theta_dev, int n_fits,
                            int theta_stride, Mix1dTable* tab, hipStream_t s);

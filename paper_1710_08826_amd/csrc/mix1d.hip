@@ -31,14 +31,15 @@ __global__ void mix1d_prologue(Mix1dConst mc, ParamBlock pb, const double* __res
   mix1d_table(mc, th, tab[f]);
 }
 
-// Single fit: one workgroup per chunk of events, one row of partial sums each.
-template <bool GRAD, int KMAX>
+// Single fit: one workgroup per chunk of events, one row of partial sums each
+// (SIG: the type signature the pass is compiled for, 0 for the generic one).
+template <bool GRAD, int KMAX, int SIG>
 __global__ __launch_bounds__(kBlock) void mix1d_events(Mix1dConst mc, const Mix1dTable* __restrict__ tab,
                                                        const double* __restrict__ x, int64_t n, int chunk,
                                                        double* __restrict__ part) {
   constexpr int NV = GRAD ? mix_nv(KMAX) : 1;
   __shared__ double lds[block_sum_lds(NV)];
-  mix1d_chunk<GRAD, KMAX>(mc, tab, x, n, blockIdx.x, chunk, part + (int64_t)blockIdx.x * NV, lds);
+  mix1d_chunk<GRAD, KMAX, SIG>(mc, tab, x, n, blockIdx.x, chunk, part + (int64_t)blockIdx.x * NV, lds);
 }
 
 // Level-2 step of a single fit.
@@ -98,6 +99,11 @@ __global__ void mix1d_check(Mix1dConst mc, const double* __restrict__ x, int64_t
 
 // ---------------------------------------------------------------- launchers
 int mix1d_kmax(int K) { return K <= 2 ? 2 : 8; }
+int mix1d_sig(const Mix1dConst& mc) {
+  if (mc.K == 1) return 1 + mc.type[0];
+  if (mc.K == 2) return 5 + 4 * mc.type[0] + mc.type[1];
+  return 0;
+}
 int mix1d_nv(int kmax, bool grad) { return grad ? mix_nv(kmax) : 1; }
 
 void mix1d_launch_prologue(const Mix1dConst& mc, const ParamBlock& pb, const double* theta_dev, int n_fits,
@@ -112,13 +118,22 @@ void mix1d_launch_events(const Mix1dConst& mc, const Mix1dTable* tab, const doub
   if (nchunks == 0) return;
   const int kmax = mix1d_kmax(mc.K);
   const dim3 g((unsigned)nchunks), b(kBlock);
-#define FN_MIX(G, K) \
-  hipExtLaunchKernelGGL((mix1d_events<G, K>), g, b, 0, s, start, stop, 0, mc, tab, x, n, chunk, part)
-  if (kmax == 2) {
-    if (grad) FN_MIX(true, 2); else FN_MIX(false, 2);
-  } else {
-    if (grad) FN_MIX(true, 8); else FN_MIX(false, 8);
+#define FN_MIX(G, K, SIG) \
+  hipExtLaunchKernelGGL((mix1d_events<G, K, SIG>), g, b, 0, s, start, stop, 0, mc, tab, x, n, chunk, part)
+#define FN_MIX_SIG(SIG)                                  \
+  case SIG:                                              \
+    if (grad) FN_MIX(true, 2, SIG); else FN_MIX(false, 2, SIG); \
+    break;
+  switch (mix1d_sig(mc)) {
+    FN_MIX_SIGS(FN_MIX_SIG)
+    default:
+      if (kmax == 2) {
+        if (grad) FN_MIX(true, 2, 0); else FN_MIX(false, 2, 0);
+      } else {
+        if (grad) FN_MIX(true, 8, 0); else FN_MIX(false, 8, 0);
+      }
   }
+#undef FN_MIX_SIG
 #undef FN_MIX
 }
 

@@ -153,34 +153,48 @@ __device__ inline double mix_shape(int type, const Mix1dTable& t, int k, double 
   }
 }
 
+// Type signature of a mixture compiled for its component types: 0 for the
+// generic passes (types read at run time), 1 + t0 for one component of type
+// t0, 5 + 4 t0 + t1 for two (types in MixType order).  The per-event passes of
+// mixtures of one or two components are instantiated for each signature, so
+// that each component's shape code is selected at compile time.
+constexpr int kMixSigCount = 21;
+__host__ __device__ constexpr int mix_sig_K(int sig) { return sig == 0 ? 0 : (sig < 5 ? 1 : 2); }
+__host__ __device__ constexpr int mix_sig_type(int sig, int k) {
+  return sig < 5 ? sig - 1 : (k == 0 ? (sig - 5) / 4 : (sig - 5) % 4);
+}
+
 // slot[s] += w * dP/d(slot s) at one point: shape parameters of component k at
 // 2k, 2k + 1 (dP = f_k u_k (d ln s_k - d ln N_k)), fraction k < K-1 at
 // 2 KMAX + k (dP = u_k - u_{K-1}, the last component taking 1 - sum f).
 template <int KMAX>
-__device__ __forceinline__ void mix1d_add_dp(const Mix1dConst& mc, const Mix1dTable& t, const double (&u)[KMAX],
+__device__ __forceinline__ void mix1d_add_dp(int K, const Mix1dTable& t, const double (&u)[KMAX],
                                              const double (&dl)[KMAX][2], double w, double* slot) {
   double ul = 0.0;
 #pragma unroll
   for (int k = 0; k < KMAX; ++k)
-    if (k == mc.K - 1) ul = u[k];
+    if (k == K - 1) ul = u[k];
 #pragma unroll
   for (int k = 0; k < KMAX; ++k) {
-    if (k < mc.K) {
+    if (k < K) {
       const double wu = w * t.frac[k] * u[k];
       slot[2 * k] += wu * (dl[k][0] - t.dlnN[k][0]);
       slot[2 * k + 1] += wu * (dl[k][1] - t.dlnN[k][1]);
-      if (k < mc.K - 1) slot[2 * KMAX + k] += w * (u[k] - ul);
+      if (k < K - 1) slot[2 * KMAX + k] += w * (u[k] - ul);
     }
   }
 }
 
 // One chunk of events -> one partial row (shared by the single-fit and the
-// batched launches so that both produce the same bits).
-template <bool GRAD, int KMAX>
+// batched launches so that both produce the same bits).  SIG: the type
+// signature the code is compiled for (0: generic, KMAX components at most).
+template <bool GRAD, int KMAX, int SIG = 0>
 __device__ inline void mix1d_chunk(const Mix1dConst& mc, const Mix1dTable* __restrict__ tabp,
                                    const double* __restrict__ x, int64_t n, int64_t chunk_idx,
                                    int chunk, double* __restrict__ out_row, double* lds) {
+  static_assert(SIG == 0 || KMAX == 2, "typed passes hold two components");
   constexpr int NV = GRAD ? mix_nv(KMAX) : 1;
+  const int K = SIG ? mix_sig_K(SIG) : mc.K;
   const Mix1dTable& t = *tabp;
   double acc[NV];
 #pragma unroll
@@ -194,13 +208,14 @@ __device__ inline void mix1d_chunk(const Mix1dConst& mc, const Mix1dTable* __res
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
       u[k] = 0.0; dl[k][0] = 0.0; dl[k][1] = 0.0;
-      if (k < mc.K) {
-        u[k] = mix_shape<GRAD>(mc.type[k], t, k, xv, dl[k][0], dl[k][1]) * t.invN[k];
+      if (k < K) {
+        const int type = SIG ? mix_sig_type(SIG, k) : mc.type[k];
+        u[k] = mix_shape<GRAD>(type, t, k, xv, dl[k][0], dl[k][1]) * t.invN[k];
         P += t.frac[k] * u[k];
       }
     }
     acc[0] -= log_fast(P);
-    if (GRAD) mix1d_add_dp<KMAX>(mc, t, u, dl, -rcp_fast(P), acc + 1);
+    if (GRAD) mix1d_add_dp<KMAX>(K, t, u, dl, -rcp_fast(P), acc + 1);
   }
   block_sum_row<NV>(acc, lds, out_row);
 }
@@ -253,15 +268,15 @@ __device__ inline void mix1d_binned_chunk(const Mix1dConst& mc, const Mix1dTable
       const double cy = n != 0.0 ? n * rcp_fast(P) : 0.0;
       if (n != 0.0) acc[2] += n * log_fast(P);
       if (GRAD) {
-        mix1d_add_dp<KMAX>(mc, t, u, dl, 1.0, acc + 3);
-        mix1d_add_dp<KMAX>(mc, t, u, dl, cy, acc + 3 + G);
+        mix1d_add_dp<KMAX>(mc.K, t, u, dl, 1.0, acc + 3);
+        mix1d_add_dp<KMAX>(mc.K, t, u, dl, cy, acc + 3 + G);
       }
     } else if (n > 0.0) {
       const double in = 1.0 / n;
       const double r = n - N * delta * P;  // n_b - nu_b
       acc[1] += r * r * in;
       acc[2] -= 2.0 * delta * r * P * in;
-      if (GRAD) mix1d_add_dp<KMAX>(mc, t, u, dl, -2.0 * N * delta * r * in, acc + 3);
+      if (GRAD) mix1d_add_dp<KMAX>(mc.K, t, u, dl, -2.0 * N * delta * r * in, acc + 3);
     }
   }
   block_sum_row<NV>(acc, lds, out_row);
