@@ -397,9 +397,16 @@ void dalitz_launch_events(const DalitzJit& j, const DalitzConst& dc, const Dalit
               Mc && out ? out + 1 + P : nullptr, start, stop, span);
 }
 
-int64_t dalitz_presum_blocks(int64_t rows, int nv, int64_t other_rows, int other_nv) {
+int64_t presum_blocks(int64_t rows, int nv, int64_t other_rows, int other_nv) {
   const int64_t bytes = 8 * (rows * nv + other_rows * other_nv);
   return bytes > kPresumMinBytes ? (rows + kPresumRows - 1) / kPresumRows : 0;
+}
+
+void launch_rows_presum(const double* p0, int64_t n0, int nv0, double* o0, int64_t s0, const double* p1, int64_t n1,
+                        int nv1, double* o1, int64_t s1, hipStream_t s) {
+  if (s0 + s1 == 0) return;
+  hipLaunchKernelGGL(rows_presum, dim3((unsigned)(s0 + s1)), dim3(kBlock), 0, s, p0, n0, nv0, o0, s0, p1, n1, nv1, o1,
+                     kPresumRows);
 }
 
 void dalitz_launch_finalize(const DalitzConst& dc, const DalitzTable* tab, const double* coef, double* evpart,
@@ -411,13 +418,12 @@ void dalitz_launch_finalize(const DalitzConst& dc, const DalitzTable* tab, const
   const int64_t span_blocks = ev_rows;
   // long row sets: pre-summed by many workgroups into the room the caller
   // left after each set's rows
-  const int64_t se = dalitz_presum_blocks(ev_rows, ev_nv, npart ? n_rows : 0, n_nv);
+  const int64_t se = presum_blocks(ev_rows, ev_nv, npart ? n_rows : 0, n_nv);
   if (se > 0) {
-    const int64_t sg = npart ? dalitz_presum_blocks(n_rows, n_nv, ev_rows, ev_nv) : 0;
+    const int64_t sg = npart ? presum_blocks(n_rows, n_nv, ev_rows, ev_nv) : 0;
     double* ev_red = evpart + ev_rows * ev_nv;
     double* n_red = npart ? npart + n_rows * n_nv : nullptr;
-    hipLaunchKernelGGL(rows_presum, dim3((unsigned)(se + sg)), dim3(kBlock), 0, s, evpart, ev_rows, ev_nv, ev_red,
-                       se, npart, n_rows, n_nv, n_red, kPresumRows);
+    launch_rows_presum(evpart, ev_rows, ev_nv, ev_red, se, npart, n_rows, n_nv, n_red, sg, s);
     evpart = ev_red;
     ev_rows = se;
     if (npart) {

@@ -66,11 +66,16 @@ void dalitz_launch_events(const DalitzJit& j, const DalitzConst& dc, const Dalit
 // cached M when npart is null), NLL assembly: out = [NLL, grad, I, dI].
 // norm_ready: the events pass already wrote I and dI into out (cached M).
 // When the two row sets hold more than kPresumMinBytes, workgroups of
-// kPresumRows rows each pre-sum them first, into dalitz_presum_blocks(...)
+// kPresumRows rows each pre-sum them first (the same for the single-fit
+// time-dependent passes), into presum_blocks(...)
 // rows that the caller leaves free after each set (evpart, npart: writable).
 constexpr int kPresumRows = 16;
 constexpr int64_t kPresumMinBytes = 131072;
-int64_t dalitz_presum_blocks(int64_t rows, int nv, int64_t other_rows, int other_nv);
+int64_t presum_blocks(int64_t rows, int nv, int64_t other_rows, int other_nv);
+// The pre-summation itself: s0 workgroups add set 0 (n0 rows of nv0 sums at
+// p0) in groups of kPresumRows rows into s0 rows at o0, s1 workgroups set 1.
+void launch_rows_presum(const double* p0, int64_t n0, int nv0, double* o0, int64_t s0, const double* p1, int64_t n1,
+                        int nv1, double* o1, int64_t s1, hipStream_t s);
 void dalitz_launch_finalize(const DalitzConst& dc, const DalitzTable* tab, const double* coef, double* evpart,
                             int64_t ev_rows, int grad, double* npart, int64_t n_rows, int n_nv,
                             const double* Mc, double n_events, double* out, double* out_user, hipStream_t s,

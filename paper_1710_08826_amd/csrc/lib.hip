@@ -484,7 +484,8 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
   } else if (m->kind == kKindTddp3) {
     const DalitzConst& dc = m->dal;
     const int nv = tddp_nv(dc.K, grad);
-    events_rows((size_t)(nch > 0 ? nch : 1) * nv);
+    const int64_t pre = presum_blocks(nch, nv, 0, 0);
+    events_rows((size_t)((nch > 0 ? nch : 1) + pre) * nv);
     if (pb || !m->table_ready) {
       ParamBlock zero;
       dalitz_launch_prologue(dc, pb ? *pb : zero, pb ? nullptr : theta_dev, m->fixed(), 1, 0, m->table_dal(), s);
@@ -506,13 +507,17 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
       tddp_launch_events(*m->tddp_jit, dc, m->table_dal(), m->tdt, coef, ev, ld, n, m->chunk, nch, grad,
                          part, s, t0, t1);
     });
-    tddp_launch_finalize(dc, m->table_dal(), m->tdt, coef, part, nch, grad, m->Mc(), (double)n, m->out(),
-                         out_user, s);
+    // long row sets: pre-summed into the room after the rows
+    launch_rows_presum(part, nch, nv, part + nch * nv, pre, nullptr, 0, 0, nullptr, 0, s);
+    tddp_launch_finalize(dc, m->table_dal(), m->tdt, coef, pre ? part + nch * nv : part, pre ? pre : nch, grad,
+                         m->Mc(), (double)n, m->out(), out_user, s);
   } else if (m->kind == kKindTd4) {
     const Td4Const& tc = m->td4;
     if (m->n_mc <= 0) throw Error(FN_E_INVALID, "td4: normalization sample not set (fn_model_set_norm_sample)");
     const int kmax = td4_kmax(tc.K);
-    events_rows((size_t)(nch > 0 ? nch : 1) * td4_nv(tc, grad));
+    const int nv = td4_nv(tc, grad);
+    const int64_t pre = presum_blocks(nch, nv, 0, 0);
+    events_rows((size_t)((nch > 0 ? nch : 1) + pre) * nv);
     const Td4FitConst* fc = (const Td4FitConst*)m->d_fixed.ptr;
     td4_launch_prologue(tc, pb, theta_dev, m->P, fc, nullptr, 1, m->table_td4(), s);
     if (!m->M_valid) {
@@ -528,8 +533,10 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
       td4_launch_events(*m->td4_jit, tc, m->table_td4(), nullptr, 1, ev, ld, n, m->chunk, grad, part, s, t0,
                         t1);
     });
-    td4_launch_finalize(tc, m->table_td4(), nullptr, 1, part, nch, grad, m->Mc(), (double)n, m->out(), 0,
-                        out_user, s);
+    // long row sets: pre-summed into the room after the rows
+    launch_rows_presum(part, nch, nv, part + nch * nv, pre, nullptr, 0, 0, nullptr, 0, s);
+    td4_launch_finalize(tc, m->table_td4(), nullptr, 1, pre ? part + nch * nv : part, pre ? pre : nch, grad, m->Mc(),
+                        (double)n, m->out(), 0, out_user, s);
   } else {
     const DalitzConst& dc = m->dal;
     const int kmax = dalitz_kmax(dc.K);
@@ -539,8 +546,8 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
     // their pre-summed rows after them (see dalitz_launch_finalize)
     const int64_t grid_rows_n = dc.free_ls ? nchunks_for((int64_t)dc.nx * dc.ny, m->grid_chunk) : 0;
     const int grid_nv = dc.free_ls ? dalitz_nv_events(kmax, g) : 0;
-    const int64_t pre_e = dalitz_presum_blocks(nch, nv, grid_rows_n, grid_nv);
-    const int64_t pre_g = pre_e > 0 && dc.free_ls ? dalitz_presum_blocks(grid_rows_n, grid_nv, nch, nv) : 0;
+    const int64_t pre_e = presum_blocks(nch, nv, grid_rows_n, grid_nv);
+    const int64_t pre_g = pre_e > 0 && dc.free_ls ? presum_blocks(grid_rows_n, grid_nv, nch, nv) : 0;
     events_rows((size_t)((nch > 0 ? nch : 1) + pre_e) * nv);
     // The table holds the lineshape constants (functions of theta only when the
     // lineshapes are free) and a copy of the coefficients; with fixed lineshapes

@@ -81,15 +81,25 @@ __device__ __forceinline__ void td4_basis(const Td4Const& tc, const Td4Table& tb
 }
 
 // --------------------------------------------------------------- prologue
-__global__ void td4_prologue(Td4Const tc, ParamBlock pb, const double* __restrict__ theta, int theta_stride,
-                             const Td4FitConst* __restrict__ fcs, const int* __restrict__ status, int n_fits,
-                             Td4Table* __restrict__ tabs) {
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+// One 64-thread workgroup per fit, each table entry written by its own thread
+// (so that the loads of theta and of the fixed constants are issued together,
+// not one after the other): threads 0..5 the r12 lineshapes, 8..13 the r34
+// ones, 16..35 the coefficients of basis function j - 16 in A and in Abar,
+// 40 x, y, sigma; thread 0 writes the validity flag once all checks are in.
+constexpr int kTd4PrologueThreads = 64;
+static_assert(16 + kTd4MaxAmp <= 40 && kTd4MaxRes <= 8, "prologue thread map");
+__global__ __launch_bounds__(kTd4PrologueThreads) void td4_prologue(Td4Const tc, ParamBlock pb,
+                                                                    const double* __restrict__ theta, int theta_stride,
+                                                                    const Td4FitConst* __restrict__ fcs,
+                                                                    const int* __restrict__ status, int n_fits,
+                                                                    Td4Table* __restrict__ tabs) {
+  const int f = blockIdx.x;
   if (f >= n_fits || (status && status[f] != 1)) return;
+  const int j = threadIdx.x;
   const double* th = theta ? theta + (int64_t)f * theta_stride : pb.v;
   const Td4FitConst& fc = fcs[f];
-  Td4Table& t = tabs[f];  // written in place (a local copy of the table spills to scratch)
-  bool ok = fc.sigma > 0.0;
+  Td4Table& t = tabs[f];
+  bool ok = true;
   auto lineshape = [&](double m0, double w0, int L, double sum2, double dif2, double* out) {
     const double x = m0 * m0;
     const double lam = (x - sum2) * (x - dif2);
@@ -102,25 +112,30 @@ __global__ void td4_prologue(Td4Const tc, ParamBlock pb, const double* __restric
     out[2] = sqrt(poly);
     if (!(m0 > 0.0) || !(w0 > 0.0) || !(lam > 0.0)) ok = false;
   };
-  for (int r = 0; r < kTd4MaxRes; ++r) {
+  if (j < kTd4MaxRes) {
+    const int r = j;
     t.r12[r][0] = t.r12[r][1] = t.r12[r][2] = 0.0;
-    t.r34[r][0] = t.r34[r][1] = t.r34[r][2] = 0.0;
     if (r < tc.n12 && !tc.nr12[r]) lineshape(fc.m0_12[r], fc.w0_12[r], tc.L12[r], tc.sum12, tc.dif12, t.r12[r]);
+  } else if (j >= 8 && j < 8 + kTd4MaxRes) {
+    const int r = j - 8;
+    t.r34[r][0] = t.r34[r][1] = t.r34[r][2] = 0.0;
     if (r < tc.n34 && !tc.nr34[r]) lineshape(fc.m0_34[r], fc.w0_34[r], tc.L34[r], tc.sum34, tc.dif34, t.r34[r]);
-  }
-  // a basis function outside a sum has a zero coefficient there
-  for (int k = 0; k < kTd4MaxAmp; ++k) {
+  } else if (j >= 16 && j < 16 + kTd4MaxAmp) {
+    // a basis function outside a sum has a zero coefficient there
+    const int k = j - 16;
     const int ia = k < tc.K ? tc.pa[k] : -1, ib = k < tc.K ? tc.pb[k] : -1;
     t.c[k][0] = ia >= 0 ? th[ia] : 0.0;
     t.c[k][1] = ia >= 0 ? th[ia + 1] : 0.0;
     t.cb[k][0] = ib >= 0 ? th[ib] : 0.0;
     t.cb[k][1] = ib >= 0 ? th[ib + 1] : 0.0;
+  } else if (j == 40) {
+    t.x = th[tc.n_params - 2];
+    t.y = th[tc.n_params - 1];
+    t.sigma = fc.sigma;
+    ok = fc.sigma > 0.0 && fabs(t.y) < 1.0 && isfinite(t.x);
   }
-  t.x = th[tc.n_params - 2];
-  t.y = th[tc.n_params - 1];
-  t.sigma = fc.sigma;
-  if (!(fabs(t.y) < 1.0) || !isfinite(t.x)) ok = false;
-  t.valid = ok ? 1.0 : 0.0;
+  const bool bad = __syncthreads_or(!ok);
+  if (j == 0) t.valid = bad ? 0.0 : 1.0;
 }
 
 // ---------------------------------------------------- normalization matrix
@@ -345,7 +360,8 @@ void td4_weideman_coefficients(double* a, double* L_out) {
 void td4_launch_prologue(const Td4Const& tc, const ParamBlock* pb, const double* theta, int theta_stride,
                          const Td4FitConst* fc, const int* status, int n_fits, Td4Table* tabs, hipStream_t s) {
   ParamBlock zero;
-  hipLaunchKernelGGL(td4_prologue, dim3((n_fits + 63) / 64), dim3(64), 0, s, tc, pb ? *pb : zero,
+  if (n_fits <= 0) return;
+  hipLaunchKernelGGL(td4_prologue, dim3(n_fits), dim3(kTd4PrologueThreads), 0, s, tc, pb ? *pb : zero,
                      pb ? nullptr : theta, theta_stride, fc, status, n_fits, tabs);
 }
 
