@@ -40,7 +40,7 @@ COUNTED_FP64_FLOPS_PER_EVENT = {2048: 493.4}
 TRAFFIC_SOURCES = ["paper_1710_08826_amd/csrc/dalitz_device.hpp", "paper_1710_08826_amd/csrc/dalitz3.hip",
                    "paper_1710_08826_amd/csrc/fastmath.hpp", "paper_1710_08826_amd/csrc/device_common.hpp",
                    "paper_1710_08826_amd/csrc/model.hpp"]
-TRAFFIC_HASH = "90cb0e12d923f6bf"
+TRAFFIC_HASH = "b5cf73499d826fc3"
 
 
 def counters_current() -> bool:
