@@ -23,12 +23,21 @@
 
 namespace fn {
 
-__global__ void mix1d_prologue(Mix1dConst mc, ParamBlock pb, const double* __restrict__ theta_dev,
-                               int n_fits, int theta_stride, Mix1dTable* __restrict__ tab) {
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+// One 64-thread workgroup per fit, component k computed by thread k (its
+// theta loads and special functions run alongside the other components').
+constexpr int kMixPrologueThreads = 64;
+static_assert(kMixMaxComp <= kMixPrologueThreads, "one thread per component");
+__global__ __launch_bounds__(kMixPrologueThreads) void mix1d_prologue(Mix1dConst mc, ParamBlock pb,
+                                                                      const double* __restrict__ theta_dev,
+                                                                      int n_fits, int theta_stride,
+                                                                      Mix1dTable* __restrict__ tab) {
+  const int f = blockIdx.x;
   if (f >= n_fits) return;
   const double* th = theta_dev ? theta_dev + (int64_t)f * theta_stride : pb.v;
-  mix1d_table(mc, th, tab[f]);
+  const int k = threadIdx.x;
+  const bool ok = k < mc.K ? mix1d_component(mc, th, k, tab[f]) : true;
+  const bool bad = __syncthreads_or(!ok);
+  if (k == 0) mix1d_table_rest(mc, th, !bad, tab[f]);
 }
 
 // Single fit: one workgroup per chunk of events, one row of partial sums each
@@ -108,7 +117,8 @@ int mix1d_nv(int kmax, bool grad) { return grad ? mix_nv(kmax) : 1; }
 
 void mix1d_launch_prologue(const Mix1dConst& mc, const ParamBlock& pb, const double* theta_dev, int n_fits,
                            int theta_stride, Mix1dTable* tab, hipStream_t s) {
-  hipLaunchKernelGGL(mix1d_prologue, dim3((n_fits + 63) / 64), dim3(64), 0, s, mc, pb, theta_dev, n_fits,
+  if (n_fits <= 0) return;
+  hipLaunchKernelGGL(mix1d_prologue, dim3(n_fits), dim3(kMixPrologueThreads), 0, s, mc, pb, theta_dev, n_fits,
                      theta_stride, tab);
 }
 

@@ -31,97 +31,110 @@ __device__ inline double lower_gamma_half(int twice_a, double y) {
   return 1.5 * g32 - y * ry * exp(-y);
 }
 
-// theta -> per-fit table: fractions, 1/N_k and d ln N_k / d(parameters) of
-// each component from its closed-form integral on [lo, hi], shape constants.
-__device__ inline void mix1d_table(const Mix1dConst& mc, const double* __restrict__ th, Mix1dTable& out) {
-  // written in place: the components are indexed at run time, so a local
-  // copy of the table would live in scratch memory
-  Mix1dTable& t = out;
+// theta -> component k of the per-fit table: its fraction, 1/N_k and
+// d ln N_k / d(its parameters) from its closed-form integral on [lo, hi], and
+// its shape constants (written in place).  Returns false when the parameters
+// do not define a density.
+__device__ inline bool mix1d_component(const Mix1dConst& mc, const double* __restrict__ th, int k, Mix1dTable& t) {
   bool ok = true;
   const double lo = mc.lo, hi = mc.hi;
-  double rest = 1.0;
-  for (int k = 0; k < kMixMaxComp; ++k) {
+  t.a[k] = 0.0; t.b[k] = 0.0; t.c[k] = 0.0;
+  if (k < mc.K - 1) {
+    t.frac[k] = th[mc.fidx[k]];
+  } else {
+    // the last component takes 1 - sum of the others, subtracted in order
+    double rest = 1.0;
+    for (int j = 0; j < mc.K - 1; ++j) rest -= th[mc.fidx[j]];
+    t.frac[k] = rest;
+  }
+  const double p0 = th[mc.pidx[k][0]];
+  const double p1 = mc.npar[k] > 1 ? th[mc.pidx[k][1]] : 0.0;
+  double N = 0.0, d0 = 0.0, d1 = 0.0;
+  switch (mc.type[k]) {
+    case kGauss: {
+      const double mu = p0, sg = p1;
+      if (!(sg > 0.0)) { ok = false; break; }
+      const double s2 = sg * 1.41421356237309504880;
+      const double A = (lo - mu) / s2, B = (hi - mu) / s2;
+      double D;
+      if (A > 0.0) D = erfc(A) - erfc(B);
+      else if (B < 0.0) D = erfc(-B) - erfc(-A);
+      else D = erf(B) - erf(A);
+      N = sg * 1.25331413731550025121 * D;  // sqrt(pi/2)
+      const double eA = exp(-A * A), eB = exp(-B * B);
+      d0 = (eA - eB) / N;
+      d1 = 1.0 / sg + 1.41421356237309504880 * (A * eA - B * eB) / N;
+      t.a[k] = mu; t.b[k] = 1.0 / sg;
+      break;
+    }
+    case kExp: {
+      const double tau = p0, D = hi - lo;
+      if (fabs(tau) < 1e-12) N = D * (1.0 + 0.5 * tau * (hi + lo));
+      else N = exp(tau * lo) * expm1(tau * D) / tau;
+      const double td = tau * D;
+      if (fabs(td) < 1e-3) d0 = 0.5 * (hi + lo) + tau * D * D / 12.0 - td * td * td * D / 720.0;
+      else d0 = lo + D / (-expm1(-td)) - 1.0 / tau;
+      t.a[k] = tau;
+      break;
+    }
+    case kArgus: {
+      const double m0 = p0, c = p1;
+      if (!(m0 > 0.0) || !(c < 0.0)) { ok = false; break; }
+      const double kk = -c, im2 = 1.0 / (m0 * m0);
+      const double wlo = fmax(0.0, 1.0 - lo * lo * im2), whi = fmax(0.0, 1.0 - hi * hi * im2);
+      const double k32 = pow(kk, -1.5), k52 = pow(kk, -2.5), h = 0.5 * m0 * m0;
+      N = h * k32 * (lower_gamma_half(3, kk * wlo) - lower_gamma_half(3, kk * whi));
+      const double dNc = h * k52 * (lower_gamma_half(5, kk * wlo) - lower_gamma_half(5, kk * whi));
+      const double im3 = im2 / m0;
+      const double flo = wlo > 0.0 ? sqrt(wlo) * exp(-kk * wlo) * 2.0 * lo * lo * im3 : 0.0;
+      const double fhi = whi > 0.0 ? sqrt(whi) * exp(-kk * whi) * 2.0 * hi * hi * im3 : 0.0;
+      const double dNm = 2.0 * N / m0 + h * (flo - fhi);
+      d0 = dNm / N;
+      d1 = dNc / N;
+      t.a[k] = im2; t.b[k] = c; t.c[k] = 1.0 / m0;
+      break;
+    }
+    case kBW: {
+      const double m0 = p0, g = p1;
+      if (!(g > 0.0)) { ok = false; break; }
+      const double hg = 0.5 * g, uh = (hi - m0) / hg, ul = (lo - m0) / hg;
+      N = (atan(uh) - atan(ul)) / hg;
+      const double ih = 1.0 / (1.0 + uh * uh), il = 1.0 / (1.0 + ul * ul);
+      const double dNm = (il - ih) / (hg * hg);
+      const double dNg = -N / g + (-uh * ih + ul * il) / (g * hg);
+      d0 = dNm / N;
+      d1 = dNg / N;
+      t.a[k] = m0; t.b[k] = hg * hg; t.c[k] = g;
+      break;
+    }
+    default:
+      ok = false;
+  }
+  if (!(N > 0.0) || !isfinite(N)) ok = false;
+  t.invN[k] = 1.0 / N;
+  t.dlnN[k][0] = d0;
+  t.dlnN[k][1] = d1;
+  return ok;
+}
+
+// The table entries past the components, the yield (extended likelihood) and
+// the validity flag; ok: every component's check.
+__device__ inline void mix1d_table_rest(const Mix1dConst& mc, const double* __restrict__ th, bool ok, Mix1dTable& t) {
+  for (int k = mc.K; k < kMixMaxComp; ++k) {
     t.frac[k] = 0.0; t.invN[k] = 0.0; t.a[k] = 0.0; t.b[k] = 0.0; t.c[k] = 0.0;
     t.dlnN[k][0] = 0.0; t.dlnN[k][1] = 0.0;
-  }
-  for (int k = 0; k < mc.K; ++k) {
-    if (k < mc.K - 1) {
-      t.frac[k] = th[mc.fidx[k]];
-      rest -= t.frac[k];
-    } else {
-      t.frac[k] = rest;
-    }
-    const double p0 = th[mc.pidx[k][0]];
-    const double p1 = mc.npar[k] > 1 ? th[mc.pidx[k][1]] : 0.0;
-    double N = 0.0, d0 = 0.0, d1 = 0.0;
-    switch (mc.type[k]) {
-      case kGauss: {
-        const double mu = p0, sg = p1;
-        if (!(sg > 0.0)) { ok = false; break; }
-        const double s2 = sg * 1.41421356237309504880;
-        const double A = (lo - mu) / s2, B = (hi - mu) / s2;
-        double D;
-        if (A > 0.0) D = erfc(A) - erfc(B);
-        else if (B < 0.0) D = erfc(-B) - erfc(-A);
-        else D = erf(B) - erf(A);
-        N = sg * 1.25331413731550025121 * D;  // sqrt(pi/2)
-        const double eA = exp(-A * A), eB = exp(-B * B);
-        d0 = (eA - eB) / N;
-        d1 = 1.0 / sg + 1.41421356237309504880 * (A * eA - B * eB) / N;
-        t.a[k] = mu; t.b[k] = 1.0 / sg;
-        break;
-      }
-      case kExp: {
-        const double tau = p0, D = hi - lo;
-        if (fabs(tau) < 1e-12) N = D * (1.0 + 0.5 * tau * (hi + lo));
-        else N = exp(tau * lo) * expm1(tau * D) / tau;
-        const double td = tau * D;
-        if (fabs(td) < 1e-3) d0 = 0.5 * (hi + lo) + tau * D * D / 12.0 - td * td * td * D / 720.0;
-        else d0 = lo + D / (-expm1(-td)) - 1.0 / tau;
-        t.a[k] = tau;
-        break;
-      }
-      case kArgus: {
-        const double m0 = p0, c = p1;
-        if (!(m0 > 0.0) || !(c < 0.0)) { ok = false; break; }
-        const double kk = -c, im2 = 1.0 / (m0 * m0);
-        const double wlo = fmax(0.0, 1.0 - lo * lo * im2), whi = fmax(0.0, 1.0 - hi * hi * im2);
-        const double k32 = pow(kk, -1.5), k52 = pow(kk, -2.5), h = 0.5 * m0 * m0;
-        N = h * k32 * (lower_gamma_half(3, kk * wlo) - lower_gamma_half(3, kk * whi));
-        const double dNc = h * k52 * (lower_gamma_half(5, kk * wlo) - lower_gamma_half(5, kk * whi));
-        const double im3 = im2 / m0;
-        const double flo = wlo > 0.0 ? sqrt(wlo) * exp(-kk * wlo) * 2.0 * lo * lo * im3 : 0.0;
-        const double fhi = whi > 0.0 ? sqrt(whi) * exp(-kk * whi) * 2.0 * hi * hi * im3 : 0.0;
-        const double dNm = 2.0 * N / m0 + h * (flo - fhi);
-        d0 = dNm / N;
-        d1 = dNc / N;
-        t.a[k] = im2; t.b[k] = c; t.c[k] = 1.0 / m0;
-        break;
-      }
-      case kBW: {
-        const double m0 = p0, g = p1;
-        if (!(g > 0.0)) { ok = false; break; }
-        const double hg = 0.5 * g, uh = (hi - m0) / hg, ul = (lo - m0) / hg;
-        N = (atan(uh) - atan(ul)) / hg;
-        const double ih = 1.0 / (1.0 + uh * uh), il = 1.0 / (1.0 + ul * ul);
-        const double dNm = (il - ih) / (hg * hg);
-        const double dNg = -N / g + (-uh * ih + ul * il) / (g * hg);
-        d0 = dNm / N;
-        d1 = dNg / N;
-        t.a[k] = m0; t.b[k] = hg * hg; t.c[k] = g;
-        break;
-      }
-      default:
-        ok = false;
-    }
-    if (!(N > 0.0) || !isfinite(N)) ok = false;
-    t.invN[k] = 1.0 / N;
-    t.dlnN[k][0] = d0;
-    t.dlnN[k][1] = d1;
   }
   t.yield = mc.yidx >= 0 ? th[mc.yidx] : 0.0;
   if (mc.yidx >= 0 && !(t.yield > 0.0 && isfinite(t.yield))) ok = false;
   t.valid = ok ? 1.0 : 0.0;
+}
+
+// theta -> per-fit table, the components one after the other (one thread per
+// fit; the single-fit prologue gives each component its own thread).
+__device__ inline void mix1d_table(const Mix1dConst& mc, const double* __restrict__ th, Mix1dTable& out) {
+  bool ok = true;
+  for (int k = 0; k < mc.K; ++k) ok = mix1d_component(mc, th, k, out) && ok;
+  mix1d_table_rest(mc, th, ok, out);
 }
 
 // Component shape s(x) and d ln s / d(its parameters).

@@ -86,7 +86,7 @@ def test_config3_gradient_vs_central_fd(m3):
     th = offset(OD.truth_theta(d))
     _, g = m.nll(th, to_dev(ev), grad=True)
     cells = OD.Dalitz(d).grid_cells()
-    fd = common.central_fd(lambda t: OD.nll(t, ev, d, cells), th, rel_step=2e-7)
+    fd = common.central_fd(lambda t: OD.nll(t, ev, d, cells), th, rel_step=1e-6)  # config 3's h = 1e-6
     ok, r = grad_close(g, fd, 1e-6)
     assert ok, r
 

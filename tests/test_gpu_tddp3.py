@@ -64,7 +64,7 @@ def test_gradient_vs_central_fd():
     ev = events(2000, 62, d)
     th = theta(0.05, 0.04)
     _, g = m.nll(th, to_dev(ev), grad=True)
-    fd = common.central_fd(lambda t: T.nll(t, ev, d), th, rel_step=2e-7)
+    fd = common.central_fd(lambda t: T.nll(t, ev, d), th, rel_step=1e-6)
     ok, r = grad_close(g, fd, 1e-6)
     assert ok, r
 
