@@ -67,11 +67,17 @@ W_SQRT, W_RSQRT, W_DIV, W_LOG, W_EXP = 19, 9, 17, 85, 30
 W_SINCOS = 59  # the small-argument path (|x| below the large-reduction threshold)
 
 
-def dalitz_flops_per_event(desc: dict, grad: int) -> int:
-    """Algorithmic FP64 FLOPs per event of the Dalitz NLL (grad: 0 none,
-    1 coefficients, 2 coefficients + masses and widths), counted from the
-    formula as evaluated: per-pair kinematics shared by the pair's
-    resonances, one complex reciprocal per resonance, one log per event."""
+def log_sum_flops(chunk: int) -> float:
+    """FLOPs per event of -sum ln P as the passes evaluate it: one multiply
+    into the thread's running product per event, and one logarithm per
+    thread (chunk / 256 events each), shared by its events."""
+    return 1 + W_LOG * 256 / chunk
+
+
+def dalitz_amp_flops(desc: dict) -> int:
+    """FP64 FLOPs per point of the Dalitz amplitudes and their coherent sum:
+    per-pair kinematics shared by the pair's resonances, one complex
+    reciprocal per resonance."""
     pairs = {}
     for r in desc["resonances"]:
         pairs.setdefault(r["pair"], set()).add(int(r["L"]))
@@ -86,7 +92,16 @@ def dalitz_flops_per_event(desc: dict, grad: int) -> int:
         if 2 in Ls:
             f += 17 + W_DIV + W_RSQRT              # polynomials, G2, Z2, H2
     f += K * (16 + W_DIV)                          # T = (a + i b)/(a^2 + b^2), A, coherent sum
-    f += 4 + W_LOG                                 # |S|^2, log, accumulate
+    return f
+
+
+def dalitz_flops_per_event(desc: dict, grad: int, chunk: int) -> float:
+    """Algorithmic FP64 FLOPs per event of the Dalitz NLL (grad: 0 none,
+    1 coefficients, 2 coefficients + masses and widths), counted from the
+    formula as evaluated: the amplitudes (dalitz_amp_flops), |S|^2 and the
+    log sum (log_sum_flops), the gradient terms."""
+    K = len(desc["resonances"])
+    f = dalitz_amp_flops(desc) + 3 + log_sum_flops(chunk)  # |S|^2, -sum ln P~
     if grad >= 1:
         f += 4 + W_DIV + 6 * K                     # -1/P~, 2 Re(conj(S) A) per coefficient
     if grad >= 2:
@@ -94,13 +109,13 @@ def dalitz_flops_per_event(desc: dict, grad: int) -> int:
     return f
 
 
-def td4_flops_per_event(desc: dict, grad: bool) -> int:
+def td4_flops_per_event(desc: dict, grad: bool, chunk: int) -> float:
     """Algorithmic FP64 FLOPs per (event, fit) of the time-dependent
     four-body NLL, counted from the formula as evaluated: per-pair kinematics
     shared by the pair's resonances, one complex reciprocal per resonance,
     products with flat (non-resonant) entries free, the three time terms
     through the rational Faddeeva approximation (40 coefficients, Horner),
-    one log per event."""
+    the log sum (log_sum_flops)."""
     N = 40
     f = 0
     pairs = (desc["r12"], desc["r34"])
@@ -132,7 +147,7 @@ def td4_flops_per_event(desc: dict, grad: bool) -> int:
     w_c = 1 + (5 + W_DIV) + 7 + horner_c + 8 + 7
     h_cplx = 5 + w_c + 9 + W_SINCOS + W_EXP + 7
     f += 2 * h_real + h_cplx
-    f += 27 + W_LOG + 1                            # rate, log, accumulate
+    f += 27 + log_sum_flops(chunk)                 # rate, -sum ln R
     if grad:
         f += 2 * 3 + 8                             # dh/da of the three time terms
         f += 1 + W_DIV + 2 + 24 + 8 * members + 20  # -1/R, the two complex weights, lc B_k and lb B_k, x and y
@@ -149,24 +164,24 @@ def time_terms_flops() -> int:
     return 2 + W_EXP + 2 * h_real + h_cplx
 
 
-def tddp3_flops_per_event(desc: dict, grad: bool) -> int:
+def tddp3_flops_per_event(desc: dict, grad: bool, chunk: int) -> float:
     """Algorithmic FP64 FLOPs per event of the time-dependent Dalitz NLL: the
     three-body amplitudes at (s12, s13) and at (s13, s12) (per-pair kinematics
     shared by the pair's resonances, one complex reciprocal per resonance),
-    both coherent sums, the time terms, the rate and its log."""
+    both coherent sums, the time terms, the rate and the log sum."""
     K = len(desc["resonances"])
-    amp = dalitz_flops_per_event(dict(desc, kind="dalitz3"), 0) - (4 + W_LOG)  # one amplitude set + sum
-    f = 2 * amp + time_terms_flops() + 27 + W_LOG + 1
+    amp = dalitz_amp_flops(dict(desc, kind="dalitz3"))  # one amplitude set + sum
+    f = 2 * amp + time_terms_flops() + 27 + log_sum_flops(chunk)
     if grad:
         f += 2 * 3 + 8                              # dh/da of the three time terms
         f += 1 + W_DIV + 2 + 24 + 16 * K + 20       # -1/R, the two complex weights, c and cbar slots, x and y
     return f
 
 
-def mix1d_flops_per_event(grad: bool) -> int:
-    """Config-0 mixture (Gaussian + exponential): 2 exp, 1 log, ~14 others;
-    the gradient adds one division and ~22 FLOPs."""
-    f = 2 * W_EXP + W_LOG + 14
+def mix1d_flops_per_event(grad: bool, chunk: int) -> float:
+    """Config-0 mixture (Gaussian + exponential): 2 exp, the log sum, ~14
+    others; the gradient adds one division and ~22 FLOPs."""
+    f = 2 * W_EXP + log_sum_flops(chunk) + 14
     if grad:
         f += W_DIV + 22
     return f
@@ -632,7 +647,7 @@ def config0_above_mall(n: int = 1 << 26, steps: int = 20):
     tb = torch.from_numpy(truth * 1.001).cuda()
     o = torch.empty(1 + m.n_params, dtype=torch.float64, device="cuda")
     w, k, info = time_async(m, t, x, o, steps, 3, True, alt=tb)
-    fl = mix1d_flops_per_event(True)
+    fl = mix1d_flops_per_event(True, m.chunk)
     r = {"config0_mall_events": n, "config0_mall_chunk": m.chunk, "config0_mall_events_per_s": n * steps / w,
          "config0_mall_ms_per_step": 1e3 * w / steps, "config0_mall_event_kernel_us": 1e3 * k,
          "config0_mall_hbm_gbs": 8.0 * n / (k * 1e-3) / 1e9,
@@ -660,7 +675,7 @@ def config3_leg(steps: int = 20):
     w3, k3, info = time_async(m3, t3, ev3, o3, steps, 3, True, alt=t3b)
     r = {"config3_events_per_s": 4_000_000 / w3 * steps, "config3_ms_per_step": 1e3 * w3 / steps,
          "config3_event_kernel_us": k3 * 1e3,
-         "config3_event_kernel_tflops": dalitz_flops_per_event(desc3, 2) * 4e6 / (k3 * 1e-3) / 1e12,
+         "config3_event_kernel_tflops": dalitz_flops_per_event(desc3, 2, m3.chunk) * 4e6 / (k3 * 1e-3) / 1e12,
          "config3_timing": info}
     r.update(config3_fits(m3, th3))
     return r
@@ -720,7 +735,7 @@ def tddp3_leg(steps: int = 50, k16: bool = True):
     out = torch.empty(1 + P, dtype=torch.float64, device="cuda")
     w, k, info = time_async(m, tdev, ev, out, steps, 3, True, alt=tb)
     w0, k0, _ = time_async(m, tdev, ev, out, steps, 3, False, alt=tb)
-    fl = tddp3_flops_per_event(desc, True)
+    fl = tddp3_flops_per_event(desc, True, m.chunk)
     fd_step = (2 * P + 1) * w0 / steps
     return {"resonances": len(res), "events": n, "params": P, "grid": desc["grid"], "chunk": m.chunk,
             "autotune_us": {str(c): v for c, v in tune_us.items()},
@@ -794,8 +809,8 @@ def td4_leg(steps: int = 10, split: bool = True, ev=None):
     tdev = torch.from_numpy(th).cuda()
     tb = torch.from_numpy(th * (1.0 + 1e-3 * np.cos(np.arange(P)))).cuda()
     out = torch.empty(1 + P, dtype=torch.float64, device="cuda")
-    fl_g, fl_0 = td4_flops_per_event(desc, True), td4_flops_per_event(desc, False)
     _, tune_us = m.autotune(th, ev, reps=5)
+    fl_g, fl_0 = td4_flops_per_event(desc, True, m.chunk), td4_flops_per_event(desc, False, m.chunk)
     w, k, info = time_async(m, tdev, ev, out, steps, 2, True, alt=tb)
     w0, k0, _ = time_async(m, tdev, ev, out, steps, 2, False, alt=tb)
     r = {"model": ("20 distinct basis functions, 10 in A and 10 in Abar" if split else
@@ -944,7 +959,7 @@ def main():
                                       graph=not args.no_graph)
     ms_step = 1e3 * wall / args.steps
     value = n1 * args.steps / wall
-    flops_ev = dalitz_flops_per_event(desc1, 1)
+    flops_ev = dalitz_flops_per_event(desc1, 1, m1.chunk)
     achieved = flops_ev * n1 / (kern_ms * 1e-3) / 1e12
     extra = {"config1_autotune_us": {str(k): v for k, v in tune_us.items()}, "config1_timing": info1}
     print(f"[bench] {value:.4g} events/s, step {ms_step:.4f} ms, kernel {kern_ms * 1e3:.2f} us",

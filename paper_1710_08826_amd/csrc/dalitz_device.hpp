@@ -178,7 +178,7 @@ __device__ __forceinline__ void dalitz_pair(const DalitzConst& dc, const double*
 template <class S, int MODE, int GRAD>
 __device__ __forceinline__ void dalitz_point(const DalitzConst& dc, const double* __restrict__ r,
                                              const double* __restrict__ coef, double s12, double s13, bool valid,
-                                             int i0, double (&acc)[dal_nv(MODE, GRAD, S::K)]) {
+                                             int i0, double (&acc)[dal_nv(MODE, GRAD, S::K)], LogProd& lp) {
   constexpr int K = S::K;
   constexpr bool KEEP_A = (GRAD >= 1) || MODE == kMRows;
   constexpr bool KEEP_T = GRAD == 2;
@@ -213,7 +213,7 @@ __device__ __forceinline__ void dalitz_point(const DalitzConst& dc, const double
   const double Pt = __builtin_fma(Sre, Sre, Sim * Sim);
   double w;  // multiplies dP~/dtheta
   if (MODE == kEvents) {
-    add(0, -log_fast(Pt));
+    lp.mul(valid ? Pt : 1.0);  // -ln P~ enters acc[0] once per thread, at the end
     if (GRAD >= 1) w = -rcp_fast(Pt);
   } else {
     add(0, Pt);
@@ -272,6 +272,7 @@ __device__ inline void dalitz_chunk(const DalitzConst& dc, const DalitzTable* __
   const int64_t base = chunk_idx * chunk;
   const int64_t end = base + chunk < n ? base + chunk : n;
   const double* const r0 = &tab->r[0][0];
+  LogProd lp;
   for (int64_t i = base + threadIdx.x; i < end; i += EPT * kBlock) {
     // The per-resonance constants are read through the scalar cache on every
     // event: an empty asm makes a zero offset opaque to the loop so that the
@@ -303,9 +304,10 @@ __device__ inline void dalitz_chunk(const DalitzConst& dc, const DalitzTable* __
           valid = valid && inside;
         }
       }
-      dalitz_point<S, MODE, GRAD>(dc, r, coef, s12, s13, valid, i0, acc);
+      dalitz_point<S, MODE, GRAD>(dc, r, coef, s12, s13, valid, i0, acc, lp);
     }
   }
+  if (MODE == kEvents) acc[0] = -lp.log();
   block_sum_row<NV>(acc, lds, out_row);
 }
 

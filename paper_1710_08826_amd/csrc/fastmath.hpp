@@ -75,4 +75,31 @@ __device__ __forceinline__ double log_fast(double x) {
   return finite_pos ? r : (x == 0.0 ? -__builtin_inf() : (x > 0.0 ? x : __builtin_nan("")));
 }
 
+// Sum of logarithms through a running product: sum_i ln x_i = ln m + e ln 2,
+// the product of the factors kept as m in [0.5, 1) times 2^e (split again
+// after every factor, so that it neither overflows nor underflows), and one
+// logarithm at the end serves all the factors: one multiply and two
+// mantissa/exponent splits per factor instead of a logarithm each.  Each
+// multiply rounds once, so after n factors the product's relative error is
+// below n 2^-53 and the sum's absolute error below n 2^-53 plus the final
+// logarithm's.  A zero factor gives -inf, a negative or NaN factor NaN and an
+// infinite one +inf, as the sum of the factors' logarithms would.
+struct LogProd {
+  double m = 1.0;
+  int e = 0;
+  __device__ __forceinline__ void mul(double x) {
+    const double p = m * x;
+    e += __builtin_amdgcn_frexp_exp(p);
+    m = __builtin_amdgcn_frexp_mant(p);
+  }
+  __device__ __forceinline__ double log() const {
+    // ln 2 rounded to 32 significant bits, and the remainder (e ln 2 formed
+    // without rounding error in the head for |e| < 2^21)
+    constexpr double kLn2Hi = 0x1.62e42ff000000p-1;
+    constexpr double kLn2Lo = -0x1.718432a1b0e26p-35;
+    const double de = (double)e;
+    return __builtin_fma(de, kLn2Hi, __builtin_fma(de, kLn2Lo, log_fast(m)));
+  }
+};
+
 }  // namespace fn

@@ -214,6 +214,7 @@ __device__ inline void mix1d_chunk(const Mix1dConst& mc, const Mix1dTable* __res
   for (int i = 0; i < NV; ++i) acc[i] = 0.0;
   const int64_t base = chunk_idx * chunk;
   const int64_t end = base + chunk < n ? base + chunk : n;
+  LogProd lp;  // -sum ln P enters acc[0] once per thread, at the end
   for (int64_t i = base + threadIdx.x; i < end; i += kBlock) {
     const double xv = x[i];
     double u[KMAX], dl[KMAX][2];
@@ -227,9 +228,10 @@ __device__ inline void mix1d_chunk(const Mix1dConst& mc, const Mix1dTable* __res
         P += t.frac[k] * u[k];
       }
     }
-    acc[0] -= log_fast(P);
+    lp.mul(P);
     if (GRAD) mix1d_add_dp<KMAX>(K, t, u, dl, -rcp_fast(P), acc + 1);
   }
+  acc[0] = -lp.log();
   block_sum_row<NV>(acc, lds, out_row);
 }
 

@@ -273,6 +273,7 @@ __device__ inline void td4_events_body(const Td4Const& tc, const Td4Table* __res
   const cplx ac = {G, -G * tabs[f].x};
   const int64_t base = ch * chunk;
   const int64_t end = base + chunk < n ? base + chunk : n;
+  LogProd lp;  // -sum ln R enters acc[0] once per thread, at the end
   for (int64_t i = base + threadIdx.x; i < end; i += kBlock) {
     // the fit's constants are re-read through the scalar cache on every event
     // (an opaque zero offset keeps them from being hoisted into SGPRs that
@@ -303,7 +304,7 @@ __device__ inline void td4_events_body(const Td4Const& tc, const Td4Table* __res
     const double a2 = A.re * A.re + A.im * A.im, b2 = Ab.re * Ab.re + Ab.im * Ab.im;
     const double zr = A.re * Ab.re + A.im * Ab.im, zi = A.re * Ab.im - A.im * Ab.re;  // conj(A) Abar
     const double R = 0.5 * ((a2 + b2) * Hc + (a2 - b2) * hc.re - 2.0 * zr * Hs - 2.0 * zi * hc.im);
-    acc[0] -= log_fast(R);
+    lp.mul(R);
     if (GRAD) {
       const double w = -rcp_fast(R);
       const double hpc = Hc + hc.re, hmc = Hc - hc.re;
@@ -327,6 +328,7 @@ __device__ inline void td4_events_body(const Td4Const& tc, const Td4Table* __res
       acc[P] += w * 0.5 * ((a2 + b2) * dHc - 2.0 * zr * dHs);
     }
   }
+  acc[0] = -lp.log();
   block_sum_row<NV>(acc, lds, part + ((int64_t)f * nch + ch) * NV);
 }
 

@@ -87,6 +87,7 @@ __device__ inline void tddp_events_body(const DalitzConst& dc, const DalitzTable
   const int64_t base = (int64_t)blockIdx.x * chunk;
   const int64_t end = base + chunk < n ? base + chunk : n;
   const double* const r0 = &tab->r[0][0];
+  LogProd lp;  // -sum ln R enters acc[0] once per thread, at the end
   for (int64_t i = base + threadIdx.x; i < end; i += kBlock) {
     // constants re-read through the scalar cache per event (an opaque zero
     // offset keeps them out of SGPRs that would overflow into VGPR lanes)
@@ -117,7 +118,7 @@ __device__ inline void tddp_events_body(const DalitzConst& dc, const DalitzTable
     const double a2 = A.re * A.re + A.im * A.im, b2 = Ab.re * Ab.re + Ab.im * Ab.im;
     const double zr = A.re * Ab.re + A.im * Ab.im, zi = A.re * Ab.im - A.im * Ab.re;  // conj(A) Abar
     const double R = 0.5 * ((a2 + b2) * Hc + (a2 - b2) * hc.re - 2.0 * zr * Hs - 2.0 * zi * hc.im);
-    acc[0] -= log_fast(R);
+    lp.mul(R);
     if (GRAD) {
       const double w = -rcp_fast(R);
       const double hpc = Hc + hc.re, hmc = Hc - hc.re;
@@ -138,6 +139,7 @@ __device__ inline void tddp_events_body(const DalitzConst& dc, const DalitzTable
       acc[2 + 4 * K] += w * 0.5 * ((a2 + b2) * dHc - 2.0 * zr * dHs);
     }
   }
+  acc[0] = -lp.log();
   block_sum_row<NV>(acc, lds, part + (int64_t)blockIdx.x * NV);
 }
 

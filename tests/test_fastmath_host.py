@@ -127,3 +127,56 @@ def test_log_accuracy():
         scale = max(abs(exact), Decimal("1e-16"))
         worst = max(worst, float(err / scale))
     assert worst < 2.5e-16, worst
+
+
+class LogProd:
+    """The device running product: m in [0.5, 1) times 2^e, split after every
+    factor (frexp, as the hardware mantissa/exponent instructions for finite
+    non-zero values), one logarithm at the end."""
+
+    def __init__(self):
+        self.m, self.e = 1.0, 0
+
+    def mul(self, x):
+        p = self.m * x  # one IEEE rounding, like the device multiply
+        mant, ex = math.frexp(p)
+        self.m, self.e = mant, self.e + ex
+
+    def log(self, rng):
+        de = float(self.e)
+        return fma(de, LN2_HI, fma(de, LN2_LO, log_fast(self.m, rng)))
+
+
+def test_logprod_sum_accuracy():
+    """The sum of logarithms of n factors through the running product is within
+    n 2^-53 + 3e-16 (absolute, scaled by max(1, |sum|)) of the exact sum, for
+    factors spread over the double range and for long runs of factors near
+    the density values of the fits (where the product alone would underflow)."""
+    rng = random.Random(18)
+    cases = []
+    for n in (1, 2, 8, 64, 1000):
+        cases.append([math.ldexp(1.0 + rng.random(), rng.randint(-300, 300)) for _ in range(n)])
+        cases.append([rng.uniform(1e-4, 10.0) for _ in range(n)])
+    cases.append([1e-300] * 50)  # the plain product would underflow after two factors
+    cases.append([1e300] * 50)
+    for xs in cases:
+        lp = LogProd()
+        for x in xs:
+            lp.mul(x)
+        v = lp.log(rng)
+        exact = sum(Decimal(x).ln() for x in xs)
+        bound = (len(xs) * Decimal(2) ** -53 + Decimal("3e-16")) * max(Decimal(1), abs(exact))
+        assert abs(Decimal(v) - exact) <= bound, (len(xs), v, exact)
+
+
+def test_logprod_special_factors():
+    """A zero factor gives -inf, a negative one NaN, as the summed logarithms would."""
+    rng = random.Random(19)
+    lp = LogProd()
+    for x in (2.0, 0.0, 3.0):
+        lp.mul(x)
+    assert lp.m == 0.0  # the device's log of 0 is -inf (checked in the log emulation's domain)
+    lp = LogProd()
+    for x in (2.0, -1.0):
+        lp.mul(x)
+    assert lp.m < 0.0  # log of a negative mantissa: NaN on the device
