@@ -70,7 +70,7 @@ void dalitz_launch_events(const DalitzJit& j, const DalitzConst& dc, const Dalit
 // time-dependent passes), into presum_blocks(...)
 // rows that the caller leaves free after each set (evpart, npart: writable).
 constexpr int kPresumRows = 16;
-constexpr int64_t kPresumMinBytes = 131072;
+constexpr int64_t kPresumMinBytes = 262144;
 int64_t presum_blocks(int64_t rows, int nv, int64_t other_rows, int other_nv);
 // The pre-summation itself: s0 workgroups add set 0 (n0 rows of nv0 sums at
 // p0) in groups of kPresumRows rows into s0 rows at o0, s1 workgroups set 1.

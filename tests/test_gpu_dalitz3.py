@@ -116,20 +116,21 @@ def test_full_size_config3(m3, cells1):
     assert ok, r
 
 
-def test_presummed_level2(m1, cells1):
-    """2.5M events at chunk 2048 give 1221 event rows of 17 sums, more than the
-    level-2 step reads through one compute unit: workgroups of 16 rows pre-sum
-    them first.  The result matches the oracle, and a level-2 step over the
-    154 rows of chunk 16384 (no pre-summation), within rounding."""
+def test_presummed_level2(cells1):
+    """2.5M events at chunk 1024 give 2442 event rows of 17 sums (332 KB), more
+    than the level-2 step reads through one compute unit: workgroups of 16 rows
+    pre-sum them first.  The result matches the oracle, and a level-2 step over
+    the 154 rows of chunk 16384 (no pre-summation), within rounding."""
     from paper_1710_08826_amd import Model
     ev = synth.dalitz_events(2_500_000, seed=38)
     evd = to_dev(ev)
     th = offset(TH1)
     say("dalitz presummed level 2: device")
+    m_small = Model(dict(D1, chunk=1024))
     m_big = Model(dict(D1, chunk=16384))
-    v, g = m1.nll(th, evd, grad=True)
+    v, g = m_small.nll(th, evd, grad=True)
     vb, gb = m_big.nll(th, evd, grad=True)
-    assert m1.chunk == 2048 and m_big.chunk == 16384
+    assert m_small.chunk == 1024 and m_big.chunk == 16384
     assert rel_close(v, vb, 1e-13), (v, vb)
     ok, r = grad_close(g, gb, 1e-12)
     assert ok, r

@@ -117,3 +117,29 @@ def test_fit_matches_oracle_fit(m0):
     assert (np.abs(rf.theta - res.x) < 1e-3 * ra.errors).all()
     assert (np.abs(ra.errors / rf.errors - 1) < 1e-3).all()
     assert (np.abs(ra.theta - TRUTH) < 5 * ra.errors).all()
+
+
+def test_tiny_densities_far_tails():
+    """A narrow Gaussian over events spread on [-8, 8]: densities down to
+    e^-525 (the product of two of them underflows a double), where the passes'
+    running product of densities must renormalize after every event; NLL and
+    gradient match the oracle's sum of logarithms.  Densities that are exactly
+    zero (events 160 sigma out, where exp underflows) make the NLL +inf."""
+    from paper_1710_08826_amd import FitNLLError, Model
+    from paper_1710_08826_amd._lib import FN_E_NONFINITE
+    d = {"kind": "mix1d", "lo": -10.0, "hi": 10.0, "n_params": 2,
+         "components": [{"type": "gauss", "params": [0, 1]}], "fracs": []}
+    m = Model(d)
+    rng = np.random.default_rng(23)
+    x = rng.uniform(-8.0, 8.0, 5000)
+    th = np.array([0.1, 0.25])  # x - mu up to 8.1 = 32 sigma: ln P down to -525
+    v, g = m.nll(th, to_dev(x), grad=True)
+    vo, go = OM.nll_grad(th, x, d)
+    assert np.isfinite(v) and v > 1e5
+    assert rel_close(v, vo, 1e-12), (v, vo)
+    ok, r = grad_close(g, go, 1e-10)
+    assert ok, r
+    th_narrow = np.array([0.1, 0.05])  # up to 162 sigma: exp(-13000) = 0 for the far events
+    with pytest.raises(FitNLLError) as e:
+        m.nll(th_narrow, to_dev(x))
+    assert e.value.status == FN_E_NONFINITE
