@@ -379,17 +379,16 @@ def cpu_baseline(events: np.ndarray, desc: dict, theta):
             "oracle_call_with_grid_events_per_s": full, **info}
 
 
-def variation_serving_leg(n_req: int = 192, slots: int = 64, lam_frac: float = 0.7, n: int = 1_000_000):
+def variation_serving_leg(n_req: int = 192, slots: int = 64, lam_frac: float = 0.7, n: int = 1_000_000,
+                          max_iter: int = 2000):
     """Systematic-variation fits of the twenty-amplitude four-body model served
-    continuously (fn_vbatch_serve): a 1M-event sample of the config-4 events,
-    the 5M-point normalization sample, 64 slots, 192 requests (ten kinds of
-    +-shifted lineshape constants and time resolution, start points near the
-    generation point, all coefficients but Abar's reference and x, y free,
-    each request capped at 100 minimizer iterations: the synthetic events are
-    not drawn from the model, and with 40 free parameters few fits converge
-    within the cap, so the leg measures the serving loop's throughput and
-    latency for fixed-length fits).  Closed loop (all requests at t = 0), then
-    Poisson arrivals at lam_frac of the closed-loop rate."""
+    continuously (fn_vbatch_serve): 1M toys of the model drawn on the device
+    at the generation point, the 5M-point normalization sample, 64 slots, 192
+    requests (ten kinds of +-shifted lineshape constants and time resolution,
+    start points near the generation point, all coefficients but Abar's
+    reference and x, y free, each request capped at max_iter minimizer
+    iterations).  Closed loop (all requests at t = 0), then Poisson arrivals
+    at lam_frac of the closed-loop rate."""
     import torch
     import synth
     from paper_1710_08826_amd import Model, VariationBatch
@@ -397,7 +396,7 @@ def variation_serving_leg(n_req: int = 192, slots: int = 64, lam_frac: float = 0
     th = synth.td4_split_truth()
     m = Model(desc)
     m.generate_norm_sample(5_000_000, seed=synth.BASE_SEED + 5)
-    ev = torch.from_numpy(synth.td4_events(n, seed=synth.BASE_SEED + 4)).cuda()
+    ev, _ = m.generate(th, n, seed=synth.BASE_SEED + 40)
     m.autotune(th, ev, reps=5)
     P = m.n_params
     fx = m.fixed()
@@ -420,15 +419,15 @@ def variation_serving_leg(n_req: int = 192, slots: int = 64, lam_frac: float = 0
 
     b = VariationBatch(m, slots)
     out = {"events": n, "mc_points": 5_000_000, "params": P, "slots": slots, "requests": n_req,
-           "max_iter": 100, "chunk": m.chunk}
-    b.serve(make([0.0] * 8), ev, free=free, max_iter=100)  # warm-up: graph capture, kernels
+           "max_iter": max_iter, "chunk": m.chunk, "data": "model toys drawn on the device"}
+    b.serve(make([0.0] * 8), ev, free=free, max_iter=max_iter)  # warm-up: graph capture, kernels
     for label, arrivals in (("closed_loop", np.zeros(n_req)), ("poisson", None)):
         if arrivals is None:
             lam = lam_frac * out["closed_loop"]["fits_per_s"]
             arrivals = np.cumsum(rng.exponential(1.0 / lam, n_req))
         reqs = make(arrivals)
         t0 = time.perf_counter()
-        r = b.serve(reqs, ev, free=free, max_iter=100)
+        r = b.serve(reqs, ev, free=free, max_iter=max_iter)
         wall = time.perf_counter() - t0
         lat = r["t_done"] - arrivals
         out[label] = {"wall_s": wall, "fits_per_s": n_req / wall, "converged": int((r["status"] == 2).sum()),

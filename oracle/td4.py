@@ -314,36 +314,94 @@ def ps_wmax(desc) -> float:
     return 1.05 * float(w.max())
 
 
-GEN_MAX_ATTEMPTS = 65536  # the four-body acceptance is near 1e-3 per attempt
+GEN_MAX_ATTEMPTS = 65536  # attempts per event before it is left unresolved
+
+
+def pair_proposal(lo: float, hi: float, entries):
+    """Proposal density of one pair mass for the toy generator: probability
+    1/2 uniform on [lo, hi] and 1/2 split equally over the pair's resonant
+    entries (all of it uniform when there are none); entry r through a
+    Student-t density of two degrees of freedom, (1 + x^2)^(-3/2) / 2 with
+    x = (m - m0)/s, s = w0/2 (m0 +- s is the peak's half maximum), truncated
+    to [lo, hi].  Its distribution function is (1 + v)/2, v = x/sqrt(1 + x^2),
+    so a truncated draw is v uniform between the ends' values and
+    x = v / sqrt(1 - v^2)."""
+    m, s, vlo, vhi = [], [], [], []
+    for e in entries:
+        if float(e["m0"]) == 0.0:  # flat (non-resonant) entry
+            continue
+        m0, sc = float(e["m0"]), 0.5 * float(e["w0"])
+        xlo, xhi = (lo - m0) / sc, (hi - m0) / sc
+        m.append(m0)
+        s.append(sc)
+        vlo.append(xlo / math.sqrt(1.0 + xlo * xlo))
+        vhi.append(xhi / math.sqrt(1.0 + xhi * xhi))
+    return {"lo": lo, "hi": hi, "n": len(m), "wu": 0.5 if m else 1.0, "m": m, "s": s, "vlo": vlo, "vhi": vhi}
+
+
+def proposal_draw(p, usel, upos):
+    """Masses drawn from the pair proposal with component selectors usel and
+    positions upos (arrays of uniforms)."""
+    out = p["lo"] + upos * (p["hi"] - p["lo"])
+    if p["n"] == 0:
+        return out
+    n, wu = p["n"], p["wu"]
+    r = np.minimum(((usel - wu) / (1.0 - wu) * n).astype(np.int64), n - 1)
+    res = usel >= wu
+    for k in range(n):
+        sel = res & (r == k)
+        v = p["vlo"][k] + upos[sel] * (p["vhi"][k] - p["vlo"][k])
+        out[sel] = p["m"][k] + p["s"][k] * (v / np.sqrt(1.0 - v * v))
+    return out
+
+
+def proposal_density(p, m):
+    """The pair proposal's density at the masses m."""
+    q = np.full(np.shape(m), (1.0 if p["n"] == 0 else p["wu"]) / (p["hi"] - p["lo"]))
+    if p["n"]:
+        wr = (1.0 - p["wu"]) / p["n"]
+        for k in range(p["n"]):
+            x = (m - p["m"][k]) / p["s"][k]
+            t = 1.0 + x * x
+            q = q + wr / ((p["s"][k] * (p["vhi"][k] - p["vlo"][k])) * (t * np.sqrt(t)))
+    return q
 
 
 def generate_events(theta, desc, n: int, seed: int, fit: int = 0, W: float = None, batch_env: int = 200_000):
-    """Toy events (6, n) of the model, event by event: attempt a of event i takes
-    (u1, u2), (u3, u4), (u5, u6), (u7, u8) from Philox counters (i, 4a + j,
-    word 4), j = 0..3, key (seed, fit): (m12, m34) uniform in the box, kept
-    when m12 + m34 < M and u3 wmax < ps_weight; c12 = 2 u4 - 1,
-    c34 = 2 u5 - 1, phi = (2 u6 - 1) pi; t = -ln(1 - u7)/lam,
-    lam = G (1 - |y|); kept when u8 W e^{-lam t} < R (the unconvolved rate,
-    at most e^{-lam t} (|A| + |Abar|)^2, as in `generate`).  The measured
-    time adds sigma_t times a Box-Muller normal from counter (i, 0, 5).
-    Returns (events, W, number of kept events with (|A| + |Abar|)^2 > W)."""
+    """Toy events (6, n) of the model, event by event, by accept-reject with
+    importance sampling of the pair masses: attempt a of event i takes
+    (u1, u2) ... (u9, u10) from Philox counters (i, 5a + j, word 4),
+    j = 0..4, key (seed, fit); m12 from the r12 proposal (`pair_proposal`)
+    with selector u1 and position u3, m34 from the r34 proposal with u2 and
+    u4, c12 = 2 u5 - 1, c34 = 2 u6 - 1, phi = (2 u7 - 1) pi,
+    t = -ln(1 - u8)/lam with lam = G (1 - |y|); kept when m12 + m34 < M and
+    u9 W q12(m12) q34(m34) e^{-lam t} < w(m12, m34) R, w the phase-space
+    weight and R the unconvolved rate (at most e^{-lam t} (|A| + |Abar|)^2,
+    as in `generate`), so that the kept events follow w R; W bounds
+    w (|A| + |Abar|)^2 / (q12 q34), by default 1.2 x its largest value on a
+    phase-space sample.  The measured time adds sigma_t times a Box-Muller
+    normal from counter (i, 0, 5).  Returns (events, W, number of kept events
+    above W)."""
     from synth import td4_phase_space
     from synth.philox import key_from_seed, uniforms_at
     model = TD4(desc)
     th = as_t(theta)
     M = model.M
     m1, m2, m3, m4 = model.m
-    lo12, hi12 = m1 + m2, M - m3 - m4
-    lo34, hi34 = m3 + m4, M - m1 - m2
-    wmax = ps_wmax(desc)
+    p12 = pair_proposal(m1 + m2, M - m3 - m4, desc["r12"])
+    p34 = pair_proposal(m3 + m4, M - m1 - m2, desc["r34"])
     G = 1.0 / model.tau
     y = float(theta[model.P - 1])
     lam = G * (1.0 - abs(y))
-    if W is None:
+
+    def ratio(kin):
         with torch.no_grad():
-            ps = torch.from_numpy(td4_phase_space(batch_env, seed, fit, stream0=5000))
-            A, Ab = model.amplitudes(th, model.basis(ps))
-            W = 1.2 * float(((A.abs() + Ab.abs()) ** 2).max())
+            A, Ab = model.amplitudes(th, model.basis(torch.from_numpy(kin)))
+            env = ((A.abs() + Ab.abs()) ** 2).numpy()
+        return ps_weight(desc, kin[0], kin[1]) * env / (proposal_density(p12, kin[0]) * proposal_density(p34, kin[1]))
+
+    if W is None:
+        W = 1.2 * float(ratio(td4_phase_space(batch_env, seed, fit, stream0=5000)).max())
     key = key_from_seed(seed, fit)
     out = np.full((6, n), np.nan)
     todo = np.arange(n, dtype=np.uint64)
@@ -351,26 +409,27 @@ def generate_events(theta, desc, n: int, seed: int, fit: int = 0, W: float = Non
     for a in range(GEN_MAX_ATTEMPTS):
         if todo.size == 0:
             break
-        u1, u2 = uniforms_at(todo, key, 4 * a, 4)
-        u3, u4 = uniforms_at(todo, key, 4 * a + 1, 4)
-        u5, u6 = uniforms_at(todo, key, 4 * a + 2, 4)
-        u7, u8 = uniforms_at(todo, key, 4 * a + 3, 4)
-        m12 = lo12 + u1 * (hi12 - lo12)
-        m34 = lo34 + u2 * (hi34 - lo34)
-        ok = (m12 + m34 < M) & (u3 * wmax < ps_weight(desc, m12, m34))
+        u1, u2 = uniforms_at(todo, key, 5 * a, 4)
+        u3, u4 = uniforms_at(todo, key, 5 * a + 1, 4)
+        u5, u6 = uniforms_at(todo, key, 5 * a + 2, 4)
+        u7, u8 = uniforms_at(todo, key, 5 * a + 3, 4)
+        u9, _ = uniforms_at(todo, key, 5 * a + 4, 4)
+        m12 = proposal_draw(p12, u1, u3)
+        m34 = proposal_draw(p34, u2, u4)
+        w = np.where(m12 + m34 < M, ps_weight(desc, m12, m34), 0.0)
+        ok = w > 0.0
         keep = np.zeros(todo.size, dtype=bool)
         if ok.any():
-            kin = np.stack([m12[ok], m34[ok], 2.0 * u4[ok] - 1.0, 2.0 * u5[ok] - 1.0, (2.0 * u6[ok] - 1.0) * math.pi])
-            t = -np.log1p(-u7[ok]) / lam
+            kin = np.stack([m12[ok], m34[ok], 2.0 * u5[ok] - 1.0, 2.0 * u6[ok] - 1.0, (2.0 * u7[ok] - 1.0) * math.pi])
+            t = -np.log1p(-u8[ok]) / lam
             with torch.no_grad():
-                kt = torch.from_numpy(kin)
-                r = unconvolved_rate(model, th, kt, torch.from_numpy(t)).numpy()
-                A, Ab = model.amplitudes(th, model.basis(kt))
-                env = ((A.abs() + Ab.abs()) ** 2).numpy()
-            k = u8[ok] * W * np.exp(-lam * t) < r
+                r = unconvolved_rate(model, th, torch.from_numpy(kin), torch.from_numpy(t)).numpy()
+            q12, q34 = proposal_density(p12, kin[0]), proposal_density(p34, kin[1])
+            k = u9[ok] * W * q12 * q34 * np.exp(-lam * t) < w[ok] * r
             sel = np.flatnonzero(ok)[k]
             keep[sel] = True
-            above += int((env[k] > W).sum())
+            if k.any():
+                above += int((ratio(kin[:, k]) > W).sum())
             idx = todo[sel].astype(np.int64)
             out[:5, idx] = kin[:, k]
             out[5, idx] = t[k]

@@ -690,6 +690,7 @@ void generate_td4(fn_model* m, const double* theta_host, uint32_t seed, uint32_t
   const ParamBlock pb = make_block(m, theta_host);
   const Td4FitConst* fc = (const Td4FitConst*)m->d_fixed.ptr;
   td4_launch_prologue(tc, &pb, nullptr, m->P, fc, nullptr, 1, m->table_td4(), s);
+  const Td4Proposal pr = td4_proposal(tc, td4_fit_const(tc, m->fixed_ls.data()));
   m->d_gen.reserve(3 * sizeof(unsigned long long));
   unsigned long long* g = (unsigned long long*)m->d_gen.ptr;
   hip_check(hipMemsetAsync(g, 0, 3 * sizeof(unsigned long long), s), "hipMemsetAsync");
@@ -697,7 +698,7 @@ void generate_td4(fn_model* m, const double* theta_host, uint32_t seed, uint32_t
   if (W == 0.0) {
     if (m->n_mc <= 0)
       throw Error(FN_E_INVALID, "td4: the automatic envelope needs the normalization sample (or give an envelope)");
-    td4_launch_envmax(*m->td4_jit, tc, m->table_td4(), (const double*)m->d_mc.ptr, m->n_mc, m->n_mc, g, s);
+    td4_launch_envmax(*m->td4_jit, tc, m->table_td4(), pr, (const double*)m->d_mc.ptr, m->n_mc, m->n_mc, g, s);
     hip_check(hipGetLastError(), "kernel launch");
     unsigned long long bits = 0;
     hip_check(hipMemcpyAsync(&bits, g, sizeof(bits), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
@@ -709,7 +710,7 @@ void generate_td4(fn_model* m, const double* theta_host, uint32_t seed, uint32_t
   }
   if (envelope_used) *envelope_used = W;
   if (n == 0) return;
-  td4_launch_gen(*m->td4_jit, tc, m->table_td4(), seed, fit, n, W, kGenMaxAttemptsTd4, ev_dev, ld, g + 1, s);
+  td4_launch_gen(*m->td4_jit, tc, m->table_td4(), pr, seed, fit, n, W, kGenMaxAttemptsTd4, ev_dev, ld, g + 1, s);
   hip_check(hipGetLastError(), "kernel launch");
   unsigned long long bad[2] = {0, 0};
   hip_check(hipMemcpyAsync(bad, g + 1, sizeof(bad), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");

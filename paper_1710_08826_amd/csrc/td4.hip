@@ -6,6 +6,7 @@
 // creation with the model's shape as compile-time constants (td4_jit below).
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <sstream>
 #include <vector>
 
@@ -509,30 +510,60 @@ void td4_launch_phase_space(const Td4Const& tc, uint32_t k0, uint32_t k1, uint32
                      max_attempts, n, out, ld, bad);
 }
 
-void td4_launch_envmax(const Td4Jit& j, const Td4Const& tc, const Td4Table* tab, const double* mc, int64_t ld,
-                       int64_t n, unsigned long long* vmax, hipStream_t s) {
+static Td4PairProposal pair_proposal(double lo, double hi, int n, const int* nr, const double* m0,
+                                     const double* w0) {
+#pragma clang fp contract(off)
+  Td4PairProposal p;
+  std::memset(&p, 0, sizeof(p));
+  p.lo = lo;
+  p.hi = hi;
+  for (int r = 0; r < n; ++r) {
+    if (nr[r]) continue;
+    const int k = p.n++;
+    p.m[k] = m0[r];
+    p.s[k] = 0.5 * w0[r];
+    const double xlo = (lo - p.m[k]) / p.s[k], xhi = (hi - p.m[k]) / p.s[k];
+    p.vlo[k] = xlo / std::sqrt(1.0 + xlo * xlo);
+    p.vhi[k] = xhi / std::sqrt(1.0 + xhi * xhi);
+  }
+  p.wu = p.n ? 0.5 : 1.0;
+  return p;
+}
+
+Td4Proposal td4_proposal(const Td4Const& tc, const Td4FitConst& fc) {
+  Td4Proposal pr;
+  pr.p12 = pair_proposal(tc.m1 + tc.m2, tc.M - tc.m3 - tc.m4, tc.n12, tc.nr12, fc.m0_12, fc.w0_12);
+  pr.p34 = pair_proposal(tc.m3 + tc.m4, tc.M - tc.m1 - tc.m2, tc.n34, tc.nr34, fc.m0_34, fc.w0_34);
+  return pr;
+}
+
+void td4_launch_envmax(const Td4Jit& j, const Td4Const& tc, const Td4Table* tab, const Td4Proposal& pr,
+                       const double* mc, int64_t ld, int64_t n, unsigned long long* vmax, hipStream_t s) {
   const int64_t blocks = std::min<int64_t>((n + kBlock - 1) / kBlock, 4096);
   Td4Const c = tc;
   const Td4Table* t = tab;
+  Td4Proposal q = pr;
   const double* p = mc;
   int64_t l = ld, nn = n;
   unsigned long long* v = vmax;
-  void* args[] = {&c, &t, &p, &l, &nn, &v};
+  void* args[] = {&c, &t, &q, &p, &l, &nn, &v};
   jit_launch(j.envmax, (unsigned)blocks, kBlock, s, args);
 }
 
-void td4_launch_gen(const Td4Jit& j, const Td4Const& tc, const Td4Table* tab, uint32_t k0, uint32_t k1, int64_t n,
-                    double W, int max_attempts, double* ev, int64_t ld, unsigned long long* bad, hipStream_t s) {
+void td4_launch_gen(const Td4Jit& j, const Td4Const& tc, const Td4Table* tab, const Td4Proposal& pr, uint32_t k0,
+                    uint32_t k1, int64_t n, double W, int max_attempts, double* ev, int64_t ld,
+                    unsigned long long* bad, hipStream_t s) {
   if (n == 0) return;
   Td4Const c = tc;
   const Td4Table* t = tab;
+  Td4Proposal q = pr;
   uint32_t a0 = k0, a1 = k1;
   int64_t nn = n, l = ld;
   double w = W;
   int ma = max_attempts;
   double* e = ev;
   unsigned long long* b = bad;
-  void* args[] = {&c, &t, &a0, &a1, &nn, &w, &ma, &e, &l, &b};
+  void* args[] = {&c, &t, &q, &a0, &a1, &nn, &w, &ma, &e, &l, &b};
   jit_launch(j.gen, (unsigned)((n + kBlock - 1) / kBlock), kBlock, s, args);
 }
 

@@ -28,12 +28,18 @@ double td4_ps_wmax(const Td4Const& tc);
 void td4_launch_phase_space(const Td4Const& tc, uint32_t k0, uint32_t k1, uint32_t s0, int max_attempts, int64_t n,
                             double* out, int64_t ld, unsigned long long* bad, hipStream_t s);
 // Toy events of the model (6 rows): vmax (zeroed by the caller) receives the
-// largest (|A| + |Abar|)^2 over a phase-space sample; bad[0] / bad[1] as for
-// the three-body generator.
-void td4_launch_envmax(const Td4Jit& j, const Td4Const& tc, const Td4Table* tab, const double* mc, int64_t ld,
-                       int64_t n, unsigned long long* vmax, hipStream_t s);
-void td4_launch_gen(const Td4Jit& j, const Td4Const& tc, const Td4Table* tab, uint32_t k0, uint32_t k1, int64_t n,
-                    double W, int max_attempts, double* ev, int64_t ld, unsigned long long* bad, hipStream_t s);
+// largest w (|A| + |Abar|)^2 / (q12 q34) over a phase-space sample (w the
+// phase-space weight, q the pair proposals' densities); bad[0] / bad[1] as
+// for the three-body generator.
+// The toy generator's pair-mass proposals for the fit constants fc: half
+// uniform and half split equally over the resonant entries of the pair,
+// scale half the width (m0 +- s is the half-maximum of the peak).
+Td4Proposal td4_proposal(const Td4Const& tc, const Td4FitConst& fc);
+void td4_launch_envmax(const Td4Jit& j, const Td4Const& tc, const Td4Table* tab, const Td4Proposal& pr,
+                       const double* mc, int64_t ld, int64_t n, unsigned long long* vmax, hipStream_t s);
+void td4_launch_gen(const Td4Jit& j, const Td4Const& tc, const Td4Table* tab, const Td4Proposal& pr, uint32_t k0,
+                    uint32_t k1, int64_t n, double W, int max_attempts, double* ev, int64_t ld,
+                    unsigned long long* bad, hipStream_t s);
 // theta: n_fits rows of theta_stride doubles on the device, or (pb != null,
 // n_fits == 1) the parameter block passed by value.
 void td4_launch_prologue(const Td4Const& tc, const ParamBlock* pb, const double* theta, int theta_stride,

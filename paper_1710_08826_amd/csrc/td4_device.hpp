@@ -377,17 +377,40 @@ __device__ inline bool td4_ps_point(const Td4Const& tc, int64_t i, uint32_t k0, 
   return false;
 }
 
-// Toy events of the model by accept-reject: event i, attempt a draws a
-// phase-space point as td4_ps_point with key (k0, k1), word 2 replaced by 4
-// (streams 4a, 4a + 1, 4a + 2) and (u7, u8) from (i, 4a + 3, 4): t = -ln(1 - u7)/lam,
-// lam = G (1 - |y|); kept when u8 W e^{-lam t} < R (the unconvolved rate, at
-// most e^{-lam t} (|A| + |Abar|)^2); the measured time adds sigma times a
-// Box-Muller normal from counter (i, 0, 5).  bad[0] counts kept events with
-// (|A| + |Abar|)^2 > W, bad[1] events left NaN.
+// (|A| + |Abar|)^2 at one point of the model (the bound of the rate at t = 0).
 template <class S>
-__device__ inline void td4_gen_body(const Td4Const& tc, const Td4Table* __restrict__ tab, uint32_t k0, uint32_t k1,
-                                    int64_t n, double W, int max_attempts, double* __restrict__ ev, int64_t ld,
-                                    unsigned long long* __restrict__ bad) {
+__device__ inline double td4_env(const Td4Const& tc, const Td4Table& tb, double m12, double m34, double c12,
+                                 double c34, double phi) {
+  constexpr int K = S::K;
+  cplx B[K];
+  td4_basis_s<S>(tc, tb, m12, m34, c12, c34, phi, B);
+  cplx A = {0.0, 0.0}, Ab = {0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const cplx p = cmul({tb.c[k][0], tb.c[k][1]}, B[k]);
+    const cplx q = cmul({tb.cb[k][0], tb.cb[k][1]}, B[k]);
+    A = {A.re + p.re, A.im + p.im};
+    Ab = {Ab.re + q.re, Ab.im + q.im};
+  }
+  const double e = sqrt(A.re * A.re + A.im * A.im) + sqrt(Ab.re * Ab.re + Ab.im * Ab.im);
+  return e * e;
+}
+
+// Toy events of the model by accept-reject with importance sampling of the
+// pair masses: event i, attempt a takes (u1, u2) ... (u9, u10) from Philox
+// counters (i, 5a + j, word 4), j = 0..4, key (k0, k1): m12 from the r12
+// proposal with selector u1 and position u3, m34 from the r34 proposal with
+// u2 and u4 (Td4Proposal), c12 = 2 u5 - 1, c34 = 2 u6 - 1, phi = (2 u7 - 1) pi,
+// t = -ln(1 - u8)/lam with lam = G (1 - |y|); kept when
+// u9 W q12(m12) q34(m34) e^{-lam t} < w(m12, m34) R, w the phase-space weight
+// and R the unconvolved rate (at most e^{-lam t} (|A| + |Abar|)^2), so W
+// must bound w (|A| + |Abar|)^2 / (q12 q34).  The measured time adds sigma
+// times a Box-Muller normal from counter (i, 0, 5).  bad[0] counts kept
+// events above the bound, bad[1] events left NaN.
+template <class S>
+__device__ inline void td4_gen_body(const Td4Const& tc, const Td4Table* __restrict__ tab, const Td4Proposal& pr,
+                                    uint32_t k0, uint32_t k1, int64_t n, double W, int max_attempts,
+                                    double* __restrict__ ev, int64_t ld, unsigned long long* __restrict__ bad) {
 #pragma clang fp contract(off)
   constexpr int K = S::K;
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -395,22 +418,23 @@ __device__ inline void td4_gen_body(const Td4Const& tc, const Td4Table* __restri
   const Td4Table& tb = *tab;
   const double G = tc.gamma, x = tb.x, y = tb.y;
   const double lam = G * (1.0 - fabs(y));
-  const double lo12 = tc.m1 + tc.m2, hi12 = tc.M - tc.m3 - tc.m4;
-  const double lo34 = tc.m3 + tc.m4, hi34 = tc.M - tc.m1 - tc.m2;
   double out[6];
   for (int j = 0; j < 6; ++j) out[j] = __builtin_nan("");
-  double env = 0.0;
+  double ratio = 0.0;
   for (int a = 0; a < max_attempts; ++a) {
-    double u1, u2, u3, u4, u5, u6, u7, u8;
-    philox_uniforms((uint64_t)i, 4u * a, 4u, k0, k1, u1, u2);
-    philox_uniforms((uint64_t)i, 4u * a + 1u, 4u, k0, k1, u3, u4);
-    philox_uniforms((uint64_t)i, 4u * a + 2u, 4u, k0, k1, u5, u6);
-    philox_uniforms((uint64_t)i, 4u * a + 3u, 4u, k0, k1, u7, u8);
-    const double m12 = lo12 + u1 * (hi12 - lo12);
-    const double m34 = lo34 + u2 * (hi34 - lo34);
-    if (!(m12 + m34 < tc.M) || !(u3 * tc.ps_wmax < td4_ps_weight(tc, m12, m34))) continue;
-    const double c12 = 2.0 * u4 - 1.0, c34 = 2.0 * u5 - 1.0, phi = (2.0 * u6 - 1.0) * 3.14159265358979323846;
-    const double t = -log1p(-u7) / lam;
+    double u1, u2, u3, u4, u5, u6, u7, u8, u9, u10;
+    philox_uniforms((uint64_t)i, 5u * a, 4u, k0, k1, u1, u2);
+    philox_uniforms((uint64_t)i, 5u * a + 1u, 4u, k0, k1, u3, u4);
+    philox_uniforms((uint64_t)i, 5u * a + 2u, 4u, k0, k1, u5, u6);
+    philox_uniforms((uint64_t)i, 5u * a + 3u, 4u, k0, k1, u7, u8);
+    philox_uniforms((uint64_t)i, 5u * a + 4u, 4u, k0, k1, u9, u10);
+    const double m12 = td4_prop_draw(pr.p12, u1, u3);
+    const double m34 = td4_prop_draw(pr.p34, u2, u4);
+    if (!(m12 + m34 < tc.M)) continue;
+    const double w = td4_ps_weight(tc, m12, m34);
+    if (!(w > 0.0)) continue;
+    const double c12 = 2.0 * u5 - 1.0, c34 = 2.0 * u6 - 1.0, phi = (2.0 * u7 - 1.0) * 3.14159265358979323846;
+    const double t = -log1p(-u8) / lam;
     cplx B[K];
     td4_basis_s<S>(tc, tb, m12, m34, c12, c34, phi, B);
     cplx A = {0.0, 0.0}, Ab = {0.0, 0.0};
@@ -429,10 +453,11 @@ __device__ inline void td4_gen_body(const Td4Const& tc, const Td4Table* __restri
     sincos(x * gt, &sx, &cx);
     const double R = 0.5 * exp(-gt) *
                      ((a2 + b2) * (0.5 * (ep + em)) + (a2 - b2) * cx - 2.0 * zr * (0.5 * (ep - em)) - 2.0 * zi * sx);
-    if (u8 * W * exp(-lam * t) < R) {
+    const double q12 = td4_prop_density(pr.p12, m12), q34 = td4_prop_density(pr.p34, m34);
+    if (u9 * W * q12 * q34 * exp(-lam * t) < w * R) {
       out[0] = m12; out[1] = m34; out[2] = c12; out[3] = c34; out[4] = phi; out[5] = t;
       const double e = sqrt(a2) + sqrt(b2);
-      env = e * e;
+      ratio = w * (e * e) / (q12 * q34);
       break;
     }
   }
@@ -440,33 +465,24 @@ __device__ inline void td4_gen_body(const Td4Const& tc, const Td4Table* __restri
   philox_uniforms((uint64_t)i, 0u, 5u, k0, k1, v1, v2);
   out[5] = out[5] + tb.sigma * (sqrt(-2.0 * log1p(-v1)) * cos(2.0 * 3.14159265358979323846 * v2));
   for (int j = 0; j < 6; ++j) ev[j * ld + i] = out[j];
-  if (env > W) atomicAdd(bad, 1ull);
+  if (ratio > W) atomicAdd(bad, 1ull);
   if (out[0] != out[0]) atomicAdd(bad + 1, 1ull);
 }
 
-// Largest (|A| + |Abar|)^2 over the points of a phase-space sample (bits of a
-// non-negative double) in *vmax.
+// Largest w (|A| + |Abar|)^2 / (q12 q34) over the points of a phase-space
+// sample (the generator's bound; bits of a non-negative double) in *vmax.
 template <class S>
-__device__ inline void td4_envmax_body(const Td4Const& tc, const Td4Table* __restrict__ tab,
+__device__ inline void td4_envmax_body(const Td4Const& tc, const Td4Table* __restrict__ tab, const Td4Proposal& pr,
                                        const double* __restrict__ mc, int64_t ld, int64_t n,
                                        unsigned long long* __restrict__ vmax) {
-  constexpr int K = S::K;
   __shared__ double lds[kBlock];
   const Td4Table& tb = *tab;
   double m = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
-    cplx B[K];
-    td4_basis_s<S>(tc, tb, mc[i], mc[ld + i], mc[2 * ld + i], mc[3 * ld + i], mc[4 * ld + i], B);
-    cplx A = {0.0, 0.0}, Ab = {0.0, 0.0};
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const cplx p = cmul({tb.c[k][0], tb.c[k][1]}, B[k]);
-      const cplx q = cmul({tb.cb[k][0], tb.cb[k][1]}, B[k]);
-      A = {A.re + p.re, A.im + p.im};
-      Ab = {Ab.re + q.re, Ab.im + q.im};
-    }
-    const double e = sqrt(A.re * A.re + A.im * A.im) + sqrt(Ab.re * Ab.re + Ab.im * Ab.im);
-    m = fmax(m, e * e);
+    const double m12 = mc[i], m34 = mc[ld + i];
+    const double e = td4_env<S>(tc, tb, m12, m34, mc[2 * ld + i], mc[3 * ld + i], mc[4 * ld + i]);
+    const double r = td4_ps_weight(tc, m12, m34) * e / (td4_prop_density(pr.p12, m12) * td4_prop_density(pr.p34, m34));
+    m = fmax(m, r);
   }
   lds[threadIdx.x] = m;
   __syncthreads();
@@ -545,12 +561,13 @@ __device__ inline void td4_mrows_body(const Td4Const& tc, const Td4Table* __rest
   }
 #define FN_TD4_GEN(ENVMAX, GEN, S)                                                                             \
   extern "C" __global__ __launch_bounds__(fn::kBlock) void ENVMAX(                                             \
-      fn::Td4Const tc, const fn::Td4Table* __restrict__ tab, const double* __restrict__ mc, int64_t ld,       \
-      int64_t n, unsigned long long* __restrict__ vmax) {                                                      \
-    fn::td4_envmax_body<S>(tc, tab, mc, ld, n, vmax);                                                          \
+      fn::Td4Const tc, const fn::Td4Table* __restrict__ tab, fn::Td4Proposal pr, const double* __restrict__ mc, \
+      int64_t ld, int64_t n, unsigned long long* __restrict__ vmax) {                                          \
+    fn::td4_envmax_body<S>(tc, tab, pr, mc, ld, n, vmax);                                                      \
   }                                                                                                            \
   extern "C" __global__ __launch_bounds__(fn::kBlock) void GEN(                                                \
-      fn::Td4Const tc, const fn::Td4Table* __restrict__ tab, uint32_t k0, uint32_t k1, int64_t n, double W,    \
-      int max_attempts, double* __restrict__ ev, int64_t ld, unsigned long long* __restrict__ bad) {           \
-    fn::td4_gen_body<S>(tc, tab, k0, k1, n, W, max_attempts, ev, ld, bad);                                     \
+      fn::Td4Const tc, const fn::Td4Table* __restrict__ tab, fn::Td4Proposal pr, uint32_t k0, uint32_t k1,     \
+      int64_t n, double W, int max_attempts, double* __restrict__ ev, int64_t ld,                              \
+      unsigned long long* __restrict__ bad) {                                                                  \
+    fn::td4_gen_body<S>(tc, tab, pr, k0, k1, n, W, max_attempts, ev, ld, bad);                                 \
   }

@@ -38,6 +38,48 @@ struct Td4FitConst {
   double sigma;
 };
 
+// Proposal density of one pair mass in the toy generator: with probability
+// wu uniform on [lo, hi]; otherwise resonance r (probability (1 - wu)/n each)
+// through a Student-t density of two degrees of freedom, g(x) = (1 + x^2)^(-3/2)
+// / 2, x = (m - m_r)/s_r, truncated to [lo, hi].  Its distribution function is
+// (1 + v)/2 with v = x / sqrt(1 + x^2), so a truncated draw is v uniform in
+// [vlo_r, vhi_r] and x = v / sqrt(1 - v^2): additions, products, quotients and
+// square roots only, which the host reference reproduces bit for bit.  Its
+// tails fall as |x|^-3, past the |x|^-2 of a Breit-Wigner intensity, so the
+// uniform part carries the proposal away from the peaks.
+struct Td4PairProposal {
+  int n;                               // resonant entries (0: uniform only)
+  double lo, hi, wu;
+  double m[kTd4MaxRes], s[kTd4MaxRes], vlo[kTd4MaxRes], vhi[kTd4MaxRes];
+};
+struct Td4Proposal {
+  Td4PairProposal p12, p34;
+};
+
+// Draw from the pair proposal with the component selector usel and the
+// position upos (both uniform in [0, 1)).
+__host__ __device__ inline double td4_prop_draw(const Td4PairProposal& p, double usel, double upos) {
+#pragma clang fp contract(off)
+  if (p.n == 0 || usel < p.wu) return p.lo + upos * (p.hi - p.lo);
+  int r = (int)((usel - p.wu) / (1.0 - p.wu) * p.n);
+  r = r < p.n ? r : p.n - 1;
+  const double v = p.vlo[r] + upos * (p.vhi[r] - p.vlo[r]);
+  return p.m[r] + p.s[r] * (v / sqrt(1.0 - v * v));
+}
+
+// The pair proposal's density at m (on [lo, hi]).
+__host__ __device__ inline double td4_prop_density(const Td4PairProposal& p, double m) {
+#pragma clang fp contract(off)
+  double q = (p.n == 0 ? 1.0 : p.wu) / (p.hi - p.lo);
+  const double wr = p.n == 0 ? 0.0 : (1.0 - p.wu) / p.n;
+  for (int r = 0; r < p.n; ++r) {
+    const double x = (m - p.m[r]) / p.s[r];
+    const double t = 1.0 + x * x;
+    q = q + wr / ((p.s[r] * (p.vhi[r] - p.vlo[r])) * (t * sqrt(t)));
+  }
+  return q;
+}
+
 // Per-fit table (prologue output).
 struct Td4Table {
   double r12[kTd4MaxRes][3];  // m0^2, Kw, Ka  (resonant entries)
