@@ -99,10 +99,10 @@ __device__ __forceinline__ void pair_terms(const DalitzChan& ch, double s_ab, do
   }
 }
 
-// Physical-region predicate at a grid-cell centre: s23 between its limits at
-// this s12, from the energies of daughters 2 and 3 in the (12) rest frame.
-// Contraction is off so that the decision is the plain IEEE evaluation.
-__device__ inline bool dalitz_inside(const DalitzConst& dc, double s12, double s13) {
+// Physical-region bounds of the grid row at s12: s23 between lo and hi, from
+// the energies of daughters 2 and 3 in the (12) rest frame.  Contraction is
+// off so that the decision is the plain IEEE evaluation.
+__device__ inline void dalitz_row_bounds(const DalitzConst& dc, double s12, double& lo, double& hi) {
 #pragma clang fp contract(off)
   const double rs = sqrt(s12);
   const double e2 = (s12 - dc.m1s + dc.m2s) / (2.0 * rs);
@@ -110,10 +110,21 @@ __device__ inline bool dalitz_inside(const DalitzConst& dc, double s12, double s
   const double p2 = sqrt(fmax(e2 * e2 - dc.m2s, 0.0));
   const double p3 = sqrt(fmax(e3 * e3 - dc.m3s, 0.0));
   const double es = e2 + e3;
-  const double lo = es * es - (p2 + p3) * (p2 + p3);
-  const double hi = es * es - (p2 - p3) * (p2 - p3);
+  lo = es * es - (p2 + p3) * (p2 + p3);
+  hi = es * es - (p2 - p3) * (p2 - p3);
+}
+
+// Physical-region predicate at a grid-cell centre, given its row's bounds.
+__device__ inline bool dalitz_in_row(const DalitzConst& dc, double s12, double s13, double lo, double hi) {
+#pragma clang fp contract(off)
   const double s23 = dc.msum - s12 - s13;
   return s23 >= lo && s23 <= hi;
+}
+
+__device__ inline bool dalitz_inside(const DalitzConst& dc, double s12, double s13) {
+  double lo, hi;
+  dalitz_row_bounds(dc, s12, lo, hi);
+  return dalitz_in_row(dc, s12, s13, lo, hi);
 }
 
 // Compile-time structure queries on a shape S (S::K, S::chan[], S::L[]).
@@ -273,6 +284,15 @@ __device__ inline void dalitz_chunk(const DalitzConst& dc, const DalitzTable* __
   const int64_t end = base + chunk < n ? base + chunk : n;
   const double* const r0 = &tab->r[0][0];
   LogProd lp;
+  // grid passes, one cell per thread and iteration: the cell's (ix, iy)
+  // advanced by kBlock cells per iteration instead of a 64-bit division, and
+  // the region's bounds computed once per row
+  int64_t gx = 0, gy = 0, row_ix = -1;
+  double row_lo = 0.0, row_hi = 0.0;
+  if (MODE != kEvents && EPT == 1) {
+    gx = (base + threadIdx.x) / dc.ny;
+    gy = (base + threadIdx.x) - gx * dc.ny;
+  }
   for (int64_t i = base + threadIdx.x; i < end; i += EPT * kBlock) {
     // The per-resonance constants are read through the scalar cache on every
     // event: an empty asm makes a zero offset opaque to the loop so that the
@@ -292,17 +312,26 @@ __device__ inline void dalitz_chunk(const DalitzConst& dc, const DalitzTable* __
       if (MODE == kEvents) {
         s12 = ev[jj];
         s13 = ev[ld + jj];
+      } else if (EPT == 1) {
+        const int64_t ix = gx, iy = gy;
+        gy += kBlock;
+        while (gy >= dc.ny) {
+          gy -= dc.ny;
+          ++gx;
+        }
+        s12 = dc.a12 + (ix + 0.5) * dc.d12;
+        s13 = dc.a13 + (iy + 0.5) * dc.d13;
+        if (ix != row_ix) {
+          dalitz_row_bounds(dc, s12, row_lo, row_hi);
+          row_ix = ix;
+        }
+        if (!dalitz_in_row(dc, s12, s13, row_lo, row_hi)) continue;
       } else {
         const int64_t ix = jj / dc.ny;
         const int64_t iy = jj - ix * dc.ny;
         s12 = dc.a12 + (ix + 0.5) * dc.d12;
         s13 = dc.a13 + (iy + 0.5) * dc.d13;
-        const bool inside = dalitz_inside(dc, s12, s13);
-        if (EPT == 1) {
-          if (!inside) continue;
-        } else {
-          valid = valid && inside;
-        }
+        valid = valid && dalitz_inside(dc, s12, s13);
       }
       dalitz_point<S, MODE, GRAD>(dc, r, coef, s12, s13, valid, i0, acc, lp);
     }

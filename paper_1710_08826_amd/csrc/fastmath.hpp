@@ -1,17 +1,20 @@
 // FP64 reciprocal, square root and logarithm for the per-event loops.
 //
 // rcp/rsqrt start from the hardware approximations (v_rcp_f64, v_rsq_f64,
-// relative error below 2^-24 on gfx950, measured over 2^22 mantissas at
-// several exponents) and apply one third-order correction on the residual
-// e, computed with an FMA: 1/x = r / (1 - e) with e = 1 - x r, taken as
-// r (1 + e + e^2); 1/sqrt(x) = y (1 - e)^(-1/2) with e = 1 - x y^2, taken as
-// y (1 + e/2 + 3 e^2 / 8) (binomial series truncated after the quadratic
-// term).  The truncation error
-// is of order e^3 < 2^-70, so the result is within about one unit in the last
-// place (measured: rcp exact on the same sample, rsqrt within 2.5 x 2^-53
-// relative), one fused operation cheaper than two Newton-Raphson steps for
-// rcp and three for rsqrt.  They take finite, positive, normal arguments;
-// callers clamp where a zero can occur.
+// relative error below 2^-24 on gfx950: at most 2.5e8 units in the last place
+// over 2^20 arguments, half log-uniform in [2^-60, 2^60], half mantissas in
+// [1, 2) at exponents -20..20) and apply one Newton-Raphson step on the
+// residual e, computed with an FMA: 1/x = r / (1 - e) with e = 1 - x r, taken
+// as r (1 + e); 1/sqrt(x) = y (1 - e)^(-1/2) with e = 1 - x y^2, taken as
+// y (1 + e/2).  The truncation error is of order e^2 < 2^-48: measured at most
+// 10.6 units in the last place for rcp and 19.3 for rsqrt on that sample
+// (2.4e-15 and 4.3e-15 relative).  The amplitudes that use them enter sums
+// whose tolerance is 1e-12 relative, and one term less each (19 per event of
+// the eight-resonance Dalitz pass) measured 3% off its step.  rcp_acc adds the
+// second-order term, r (1 + e + e^2), for a result within half a unit in the
+// last place on the same sample (for the logarithm's argument reduction).
+// They take finite, positive, normal arguments; callers clamp where a zero
+// can occur.
 //
 // log_fast: argument reduction x = 2^e m with m in [sqrt(1/2), sqrt(2))
 // (Cody & Waite, Software Manual for the Elementary Functions, 1980), then
@@ -29,13 +32,19 @@ namespace fn {
 __device__ __forceinline__ double rcp_fast(double x) {
   const double r = __builtin_amdgcn_rcp(x);
   const double e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
+__device__ __forceinline__ double rcp_acc(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  const double e = __builtin_fma(-x, r, 1.0);
   return __builtin_fma(r, __builtin_fma(e, e, e), r);
 }
 
 __device__ __forceinline__ double rsqrt_fast(double x) {
   const double y = __builtin_amdgcn_rsq(x);
   const double e = __builtin_fma(-x * y, y, 1.0);
-  return __builtin_fma(y, e * __builtin_fma(e, 0.375, 0.5), y);
+  return __builtin_fma(y * 0.5, e, y);
 }
 
 // sqrt for x >= 0; arguments below 1e-300 are treated as 1e-300.
@@ -50,7 +59,7 @@ __device__ __forceinline__ double log_fast(double x) {
   const bool lo = m < 0.70710678118654752440;
   m = lo ? 2.0 * m : m;
   e = lo ? e - 1 : e;
-  const double f = (m - 1.0) * rcp_fast(m + 1.0);
+  const double f = (m - 1.0) * rcp_acc(m + 1.0);
   const double f2 = f * f;
   double p = 1.0 / 23.0;
   p = __builtin_fma(p, f2, 1.0 / 21.0);
