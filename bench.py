@@ -31,16 +31,16 @@ PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector, FMA counted as 2
 PEAK_HBM_GBS = 8000.0
 
 # HBM bytes per launch of the config-1 event kernel from the FETCH_SIZE and
-# WRITE_SIZE counter runs (profiles/dalitz_events_grad_1M.md), by summation
-# chunk, and its executed FP64 FLOPs per event from SQ_INSTS_VALU_FLOPS_FP64,
-# valid for the kernel sources with this hash; reported as null once they
-# change or for a chunk without a counter run.
-TRAFFIC_BYTES = {2048: 1.620e7}
-COUNTED_FP64_FLOPS_PER_EVENT = {2048: 420.9}
+# WRITE_SIZE counter runs (profiles/dalitz_events_grad_1M.md), by (summation
+# chunk, events per thread), and its executed FP64 FLOPs per event from
+# SQ_INSTS_VALU_FLOPS_FP64, valid for the kernel sources with this hash;
+# reported as null once they change or for a choice without a counter run.
+TRAFFIC_BYTES = {(2048, 1): 1.620e7}
+COUNTED_FP64_FLOPS_PER_EVENT = {(2048, 1): 420.9}
 TRAFFIC_SOURCES = ["paper_1710_08826_amd/csrc/dalitz_device.hpp", "paper_1710_08826_amd/csrc/dalitz3.hip",
                    "paper_1710_08826_amd/csrc/fastmath.hpp", "paper_1710_08826_amd/csrc/device_common.hpp",
                    "paper_1710_08826_amd/csrc/model.hpp"]
-TRAFFIC_HASH = "0bce546c90813e1b"
+TRAFFIC_HASH = "5c7e3dcb9a536254"
 
 
 def counters_current() -> bool:
@@ -52,12 +52,12 @@ def counters_current() -> bool:
     return h.hexdigest()[:16] == TRAFFIC_HASH
 
 
-def measured_traffic(chunk: int):
-    return TRAFFIC_BYTES.get(chunk) if counters_current() else None
+def measured_traffic(chunk: int, ept: int = 1):
+    return TRAFFIC_BYTES.get((chunk, ept)) if counters_current() else None
 
 
-def counted_flops(chunk: int):
-    return COUNTED_FP64_FLOPS_PER_EVENT.get(chunk) if counters_current() else None
+def counted_flops(chunk: int, ept: int = 1):
+    return COUNTED_FP64_FLOPS_PER_EVENT.get((chunk, ept)) if counters_current() else None
 
 # FP64 FLOPs of the correctly rounded gfx950 sequences of the ROCm device
 # library (FMA = 2, other FP64 arithmetic = 1, compares 0), counted from the
@@ -949,18 +949,20 @@ def main():
     # summation chunk from the library's autotuner on this sample (or given, for profiling runs)
     if args.chunk_c1:
         m1 = Model(dict(desc1, chunk=args.chunk_c1))
-        tuned_chunk, tune_us = m1.chunk, {}
+        tune_us = {}
     else:
-        tuned_chunk, tune_us = m1.autotune(th1, ev1, reps=20)
-    print(f"[bench] config1 dalitz: {n1} events, P={P1}, chunk {tuned_chunk}, warmup {args.warmup}, "
-          f"steps {args.steps}", file=sys.stderr, flush=True)
+        m1.autotune(th1, ev1, reps=20)
+        # "chunk" for one event per thread and loop iteration, "chunk x2" for two
+        tune_us = {(str(c) if e == 1 else f"{c} x2"): t for (c, e), t in m1.tune_table.items()}
+    print(f"[bench] config1 dalitz: {n1} events, P={P1}, chunk {m1.chunk}, events per thread "
+          f"{m1.events_per_thread}, warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
     wall, kern_ms, info1 = time_async(m1, tdev, ev1, out, args.steps, args.warmup, True, alt=tdev_b,
                                       graph=not args.no_graph)
     ms_step = 1e3 * wall / args.steps
     value = n1 * args.steps / wall
     flops_ev = dalitz_flops_per_event(desc1, 1, m1.chunk)
     achieved = flops_ev * n1 / (kern_ms * 1e-3) / 1e12
-    extra = {"config1_autotune_us": {str(k): v for k, v in tune_us.items()}, "config1_timing": info1}
+    extra = {"config1_autotune_us": tune_us, "config1_timing": info1}
     print(f"[bench] {value:.4g} events/s, step {ms_step:.4f} ms, kernel {kern_ms * 1e3:.2f} us",
           file=sys.stderr, flush=True)
 
@@ -1092,14 +1094,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": "dalitz3 8-resonance amplitude fit, NLL + adjoint gradient",
                    "events": n1, "params": P1, "grid": [1024, 1024], "normalization": "cached grid matrix",
-                   "chunk": m1.chunk, "parallelism": "single GPU"},
+                   "chunk": m1.chunk, "events_per_thread": m1.events_per_thread, "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(m1.chunk),
+                     "frac": achieved / PEAK_FP64_TFLOPS,
+                     "traffic": measured_traffic(m1.chunk, m1.events_per_thread),
                      "kernel": "fn_dal_ev1 (Dalitz events pass, coefficient gradient)",
                      "kernel_us": kern_ms * 1e3, "flops_per_event": flops_ev,
-                     "counted_fp64_flops_per_event": counted_flops(m1.chunk),
-                     "counted_fp64_tflops": (counted_flops(m1.chunk) * n1 / (kern_ms * 1e-3) / 1e12
-                                             if counted_flops(m1.chunk) else None),
+                     "counted_fp64_flops_per_event": counted_flops(m1.chunk, m1.events_per_thread),
+                     "counted_fp64_tflops": (counted_flops(m1.chunk, m1.events_per_thread) * n1
+                                             / (kern_ms * 1e-3) / 1e12
+                                             if counted_flops(m1.chunk, m1.events_per_thread) else None),
                      "hbm_gbs": 16 * n1 / (kern_ms * 1e-3) / 1e9},
         "cpu_baseline": cpu,
         "extra": extra,

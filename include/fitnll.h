@@ -125,7 +125,10 @@ typedef struct fn_model fn_model;
  *     entry, then sigma_t.
  *  Optional keys for every kind: "chunk" (events per workgroup, a multiple of
  *  256 in [256, 2^22], default chosen per kind) -- fixed per model, it
- *  defines the summation tree.
+ *  defines the summation tree.  dalitz3 only: "events_per_thread" (1, the
+ *  default, or 2: events each thread of the events passes evaluates per loop
+ *  iteration; a thread adds its events in index order either way, so the
+ *  results are bitwise the same).
  * Returns FN_E_INVALID with a message for a malformed description. */
 fn_status fn_model_create(fn_ctx* ctx, const char* desc_json, fn_model** out);
 /* Compile a description's structure-specialized kernels for the GPU
@@ -140,24 +143,32 @@ fn_status fn_model_info(const fn_model* m, int32_t* n_params, int32_t* n_obs, in
 /* Frees the model's device memory.  Streams using it must be synchronised. */
 fn_status fn_model_destroy(fn_model* m);
 /* Autotuner of the summation chunk (events per workgroup; it also fixes the
- * order of the sums): times the full NLL + gradient evaluation at theta (host,
- * P doubles) on the caller's events (device, as fn_nll) for each candidate
- * chunk (3 warm-up calls, then the median of reps timed calls, HIP events on
- * `stream`; reps < 1 means 20), keeps the largest candidate whose time is
- * within 2% of the fastest as the model's chunk (reported by fn_model_info
- * and used by every later evaluation and by batches created afterwards) and
- * writes it to *chunk_out.  The candidates are the powers of two 256 ..
+ * order of the sums) and, for dalitz3, of the events per thread and loop
+ * iteration of the events passes (1 or 2; the sums are bitwise the same):
+ * times the full NLL + gradient evaluation at theta (host, P doubles) on the
+ * caller's events (device, as fn_nll) for each candidate (3 warm-up calls,
+ * then the median of reps timed calls, HIP events on `stream`; reps < 1 means
+ * 20).  Among the candidates within 2% of the fastest it keeps one event per
+ * thread if any has it, then the largest chunk; the choice becomes the
+ * model's (reported by fn_model_info, used by every later evaluation and by
+ * batches created afterwards) and is written to *chunk_out and *ept_out
+ * (each may be NULL).  The chunk candidates are the powers of two 256 ..
  * 16384, then the multiples of 256 that give the sample j x (number of
  * compute units) workgroups, j = 1 .. 8 (workgroup counts that fill the
  * device's resident slots evenly), where they differ from the first.
- * chunks_out and us_out (each may be NULL, else FN_TUNE_MAX entries) receive
- * the candidates and their median times in microseconds, in the order tried;
- * unused entries hold chunk 0 and NaN.  Synchronous.  FN_E_INVALID for NULL
- * theta, n < 1 or bad event arguments; the model keeps its previous chunk on
- * any error. */
+ * chunks_out (NULL or FN_TUNE_MAX entries) receives the chunk candidates in
+ * the order tried, unused entries 0; us_out (NULL or FN_TUNE_EPT x
+ * FN_TUNE_MAX entries) their median times in microseconds, one event per
+ * thread in entries 0 .. FN_TUNE_MAX - 1, two from FN_TUNE_MAX on, NaN where
+ * nothing was timed.  The workgroup size is fixed (256 threads: the
+ * two-level sums and their LDS layout are built for four wave64s).
+ * Synchronous.  FN_E_INVALID for NULL theta, n < 1 or bad event arguments;
+ * the model keeps its previous choice on any error. */
 #define FN_TUNE_MAX 16
+#define FN_TUNE_EPT 2
 fn_status fn_model_autotune(fn_model* m, const double* theta_host, const double* ev, int64_t n, int64_t ld,
-                            int32_t reps, int32_t* chunk_out, int32_t* chunks_out, double* us_out, void* stream);
+                            int32_t reps, int32_t* chunk_out, int32_t* ept_out, int32_t* chunks_out, double* us_out,
+                            void* stream);
 
 /* Count events outside the observable domain (range for mix1d; bounding box
  * and physical region, with a relative tolerance of 1e-9, for dalitz3).

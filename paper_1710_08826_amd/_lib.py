@@ -75,7 +75,8 @@ PROTOTYPES = {
     "fn_batch_status": (i32, [vp, C.POINTER(i32), dp, dp, dp]),
     "fn_generate_mix1d": (i32, [C.c_uint32, C.c_uint32, i64, dp, C.c_double, C.c_double, vp, vp]),
     "fn_generate": (i32, [vp, dp, C.c_uint32, C.c_uint32, i64, C.c_double, vp, i64, dp, vp]),
-    "fn_model_autotune": (i32, [vp, dp, vp, i64, i64, i32, C.POINTER(i32), C.POINTER(i32), dp, vp]),
+    "fn_model_autotune": (i32, [vp, dp, vp, i64, i64, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), dp,
+                                vp]),
     "fn_model_generate_norm_sample": (i32, [vp, C.c_uint32, C.c_uint32, i64, vp]),
     "fn_nll_binned": (i32, [vp, dp, vp, i64, i32, dp, dp, vp]),
     "fn_fit_binned": (i32, [vp, dp, C.POINTER(i32), vp, i64, i32, i32, C.c_double, i32, dp, dp, dp,

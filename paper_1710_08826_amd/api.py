@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import json
+import math
 from dataclasses import dataclass
 
 import numpy as np
@@ -79,6 +80,8 @@ class Model:
         p, o, c = C.c_int32(), C.c_int32(), C.c_int32()
         check(lib.fn_model_info(h, C.byref(p), C.byref(o), C.byref(c)))
         self.n_params, self.n_obs, self.chunk = p.value, o.value, c.value
+        self.events_per_thread = int(self.desc.get("events_per_thread", 1))
+        self.tune_table = {}
 
     def close(self):
         if getattr(self, "_h", None):
@@ -183,22 +186,33 @@ class Model:
         return ev, used.value
 
     TUNE_MAX = 16  # FN_TUNE_MAX
+    TUNE_EPT = 2   # FN_TUNE_EPT
 
     def autotune(self, theta, events: torch.Tensor, reps: int = 20, stream=None):
-        """Pick the summation chunk for these events (fn_model_autotune: the
-        largest candidate within 2% of the fastest; candidates are the powers
-        of two 256..16384 and the chunks giving j x (compute units) workgroups,
-        j = 1..8); returns (chunk, {candidate: median microseconds per NLL +
-        gradient})."""
+        """Pick the summation chunk (and for dalitz3 the events per thread and
+        loop iteration, 1 or 2) for these events (fn_model_autotune: among the
+        candidates within 2% of the fastest, one event per thread if any, then
+        the largest chunk; chunk candidates are the powers of two 256..16384
+        and the chunks giving j x (compute units) workgroups, j = 1..8);
+        returns (chunk, {candidate chunk: median microseconds per NLL +
+        gradient at the chosen events per thread}); every timing is in
+        self.tune_table, keyed by (chunk, events per thread)."""
         th, thp = self._theta(theta)
         evp, n, ld = _events(events, self.n_obs)
-        best = C.c_int32()
+        best, ept = C.c_int32(), C.c_int32()
         chunks = (C.c_int32 * self.TUNE_MAX)()
-        us = (C.c_double * self.TUNE_MAX)()
-        check(self._lib.fn_model_autotune(self._h, thp, evp, n, ld, int(reps), C.byref(best), chunks, us,
-                                          _stream_ptr(stream)))
+        us = (C.c_double * (self.TUNE_EPT * self.TUNE_MAX))()
+        check(self._lib.fn_model_autotune(self._h, thp, evp, n, ld, int(reps), C.byref(best), C.byref(ept), chunks,
+                                          us, _stream_ptr(stream)))
         self.chunk = best.value
-        return best.value, {c: t for c, t in zip(chunks, us) if c > 0}
+        self.events_per_thread = ept.value
+        self.tune_table = {}
+        for e in range(self.TUNE_EPT):
+            for i, c in enumerate(chunks):
+                t = us[e * self.TUNE_MAX + i]
+                if c > 0 and not math.isnan(t):
+                    self.tune_table[(c, e + 1)] = t
+        return best.value, {c: t for (c, e), t in self.tune_table.items() if e == ept.value}
 
     def set_timing(self, enable: bool, every: int = 1, span: bool = False):
         """Time every `every`-th per-event kernel launch (the dispatch records its own

@@ -300,8 +300,10 @@ void dalitz_launch_prologue(const DalitzConst& dc, const ParamBlock& pb, const d
 // and spin of every resonance) as compile-time constants, then the kernels the
 // model uses (fixed lineshapes: events without and with the coefficient
 // gradient, the M rows; free lineshapes: events and grid without and with the
-// full gradient).
-std::string dalitz_jit_source(const DalitzConst& dc) {
+// full gradient).  ept = 2: only the events passes, with two events per
+// thread and loop iteration (each thread still adds its events in index
+// order, so the sums are bitwise those of the one-event form).
+std::string dalitz_jit_source(const DalitzConst& dc, int ept) {
   std::ostringstream o;
   o << "#include \"dalitz_device.hpp\"\n";
   o << "struct fn_shape {\n  static constexpr int K = " << dc.K << ";\n  static constexpr int chan[" << dc.K
@@ -310,6 +312,12 @@ std::string dalitz_jit_source(const DalitzConst& dc) {
   o << "};\n  static constexpr int L[" << dc.K << "] = {";
   for (int k = 0; k < dc.K; ++k) o << (k ? ", " : "") << dc.L[k];
   o << "};\n};\n";
+  if (ept == 2) {
+    o << "FN_DALITZ_KERNEL(fn_dal_ev0, fn_shape, fn::kEvents, 0, 2)\n";
+    if (!dc.free_ls) o << "FN_DALITZ_KERNEL(fn_dal_ev1, fn_shape, fn::kEvents, 1, 2)\n";
+    else o << "FN_DALITZ_KERNEL(fn_dal_ev2, fn_shape, fn::kEvents, 2, 2)\n";
+    return o.str();
+  }
   if (!dc.free_ls) {
     o << "FN_DALITZ_KERNEL(fn_dal_ev0, fn_shape, fn::kEvents, 0, 1)\n"
          "FN_DALITZ_KERNEL(fn_dal_ev1, fn_shape, fn::kEvents, 1, 1)\n"
@@ -324,15 +332,22 @@ std::string dalitz_jit_source(const DalitzConst& dc) {
   return o.str();
 }
 
-std::shared_ptr<DalitzJit> dalitz_jit(const DalitzConst& dc) {
+std::shared_ptr<DalitzJit> dalitz_jit(const DalitzConst& dc, int ept) {
   auto j = std::make_shared<DalitzJit>();
   std::vector<std::string> names;
+  if (ept == 2) {
+    names = {"fn_dal_ev0", dc.free_ls ? "fn_dal_ev2" : "fn_dal_ev1"};
+    j->prog = jit_load(dalitz_jit_source(dc, 2), names);
+    j->ev[0] = j->prog->fns[0];
+    j->ev[dc.free_ls ? 2 : 1] = j->prog->fns[1];
+    return j;
+  }
   if (!dc.free_ls) names = {"fn_dal_ev0", "fn_dal_ev1", "fn_dal_mrows"};
   else names = {"fn_dal_ev0", "fn_dal_ev2", "fn_dal_gr0", "fn_dal_gr2"};
   const size_t ngen = names.size();
   names.push_back("fn_dal_gmax");
   names.push_back("fn_dal_gen");
-  j->prog = jit_load(dalitz_jit_source(dc), names);
+  j->prog = jit_load(dalitz_jit_source(dc, 1), names);
   const auto& f = j->prog->fns;
   if (!dc.free_ls) {
     j->ev[0] = f[0];

@@ -58,6 +58,8 @@ struct fn_model {
   fn::DalitzConst dal;
   fn::Td4Const td4;
   std::shared_ptr<fn::DalitzJit> dal_jit;  // structure-specialized passes
+  int ept = 1;                              // dalitz3 events passes: events per thread and iteration
+  std::shared_ptr<fn::DalitzJit> dal_jit2;  // their two-event form (built when first chosen)
   std::shared_ptr<fn::Td4Jit> td4_jit;
   std::shared_ptr<fn::TddpJit> tddp_jit;  // time-dependent Dalitz passes
   fn::TddpTime tdt;                        // its decay-time constants

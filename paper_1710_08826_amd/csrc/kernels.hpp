@@ -46,8 +46,10 @@ struct DalitzJit {
   hipFunction_t mrows = nullptr;
   hipFunction_t gmax = nullptr, gen = nullptr;  // toy generation: grid maximum, accept-reject
 };
-std::string dalitz_jit_source(const DalitzConst& dc);
-std::shared_ptr<DalitzJit> dalitz_jit(const DalitzConst& dc);
+// ept: events per thread and loop iteration of the events passes (1, or 2
+// for a module with the events passes alone).
+std::string dalitz_jit_source(const DalitzConst& dc, int ept = 1);
+std::shared_ptr<DalitzJit> dalitz_jit(const DalitzConst& dc, int ept = 1);
 int dalitz_kmax(int K);
 int dalitz_nv_events(int kmax, int grad);
 int dalitz_nv_mrows(int kmax);

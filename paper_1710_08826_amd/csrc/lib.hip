@@ -597,7 +597,8 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
       span = (unsigned long long*)m->d_span.ptr;
     }
     m->timed(launches, [&](hipEvent_t t0, hipEvent_t t1) {
-      dalitz_launch_events(*m->dal_jit, dc, m->table_dal(), coef, ev, ld, n, m->chunk, nch, g, part, s,
+      dalitz_launch_events(m->ept == 2 ? *m->dal_jit2 : *m->dal_jit, dc, m->table_dal(), coef, ev, ld, n, m->chunk,
+                           nch, g, part, s,
                            norm_in_pass ? m->Mc() : nullptr, norm_in_pass ? m->out() : nullptr, t0, t1, span);
     });
     dalitz_launch_finalize(dc, m->table_dal(), coef, part, nch, g, grid_rows, nrows, nnv, m->Mc(), (double)n,
@@ -749,6 +750,15 @@ fn_status fn_ctx_destroy(fn_ctx* ctx) {
   return guard([&] { delete ctx; });
 }
 
+// Events per thread and loop iteration of a dalitz3 model's events passes
+// (1 or 2); the two-event module is compiled when first chosen.
+static void set_dalitz_ept(fn_model* m, long ept) {
+  if (m->kind != kKindDalitz3) throw Error(FN_E_INVALID, "events_per_thread applies to dalitz3 models");
+  if (ept != 1 && ept != 2) throw Error(FN_E_INVALID, "events_per_thread must be 1 or 2");
+  if (ept == 2 && !m->dal_jit2) m->dal_jit2 = dalitz_jit(m->dal, 2);
+  m->ept = (int)ept;
+}
+
 fn_status fn_model_create(fn_ctx* ctx, const char* desc_json, fn_model** out) {
   fn_model* m = nullptr;
   fn_status st = guard([&] {
@@ -786,6 +796,7 @@ fn_status fn_model_create(fn_ctx* ctx, const char* desc_json, fn_model** out) {
           throw Error(FN_E_INVALID, "chunk must be a multiple of 256 in [256, " + std::to_string(kMaxChunk) + "]");
         m->chunk = (int)c;
       }
+      if (d.has("events_per_thread")) set_dalitz_ept(m, d.at("events_per_thread").integer());
     } catch (const Error&) {
       throw;
     } catch (const std::exception& e) {
@@ -819,9 +830,16 @@ fn_status fn_model_check_compile(const char* desc_json, const char* arch) {
     fn_model tmp;
     try {
       const std::string& kind = d.at("kind").string();
+      if (d.has("events_per_thread") && kind != "dalitz3")
+        throw Error(FN_E_INVALID, "events_per_thread applies to dalitz3 models");
       if (kind == "dalitz3") {
         compile_dalitz3(d, &tmp, false);
-        (void)jit_compile(dalitz_jit_source(tmp.dal), target);
+        (void)jit_compile(dalitz_jit_source(tmp.dal, 1), target);
+        if (d.has("events_per_thread")) {
+          const long e = d.at("events_per_thread").integer();
+          if (e != 1 && e != 2) throw Error(FN_E_INVALID, "events_per_thread must be 1 or 2");
+          if (e == 2) (void)jit_compile(dalitz_jit_source(tmp.dal, 2), target);
+        }
       } else if (kind == "td4") {
         compile_td4(d, &tmp, false);
         (void)jit_compile(td4_jit_source(tmp.td4), target);
@@ -853,7 +871,8 @@ fn_status fn_model_destroy(fn_model* m) {
 }
 
 fn_status fn_model_autotune(fn_model* m, const double* theta_host, const double* ev, int64_t n, int64_t ld,
-                            int32_t reps, int32_t* chunk_out, int32_t* chunks_out, double* us_out, void* stream) {
+                            int32_t reps, int32_t* chunk_out, int32_t* ept_out, int32_t* chunks_out, double* us_out,
+                            void* stream) {
   return guard([&] {
     if (!m || !theta_host) throw Error(FN_E_INVALID, "NULL argument");
     if (n < 1) throw Error(FN_E_INVALID, "autotuning needs events");
@@ -862,53 +881,68 @@ fn_status fn_model_autotune(fn_model* m, const double* theta_host, const double*
     hip_check(hipSetDevice(m->device), "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
     const ParamBlock pb = make_block(m, theta_host);
-    const int saved = m->chunk;
+    const int saved = m->chunk, saved_ept = m->ept;
     int cus = 0;
     hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device),
               "hipDeviceGetAttribute");
     int32_t cand[FN_TUNE_MAX];
     const int count = tune_candidates(n, cus > 0 ? cus : 1, cand);
+    // dalitz3 events passes also come with two events per thread and iteration
+    const int n_ept = m->kind == kKindDalitz3 ? 2 : 1;
     if (chunks_out)
       for (int c = 0; c < FN_TUNE_MAX; ++c) chunks_out[c] = c < count ? cand[c] : 0;
     if (us_out)
-      for (int c = 0; c < FN_TUNE_MAX; ++c) us_out[c] = NAN;
+      for (int c = 0; c < FN_TUNE_EPT * FN_TUNE_MAX; ++c) us_out[c] = NAN;
     std::vector<hipEvent_t> evs(2 * (size_t)reps);
     for (auto& e : evs) hip_check(hipEventCreate(&e), "hipEventCreate");
-    std::vector<double> med(count, INFINITY);
+    std::vector<double> med((size_t)n_ept * count, INFINITY);
     try {
-      for (int c = 0; c < count; ++c) {
-        m->chunk = cand[c];
-        for (int w = 0; w < 3; ++w) run_nll(m, &pb, nullptr, ev, n, ld, true, nullptr, s);  // warm-up, buffers
-        for (int r = 0; r < reps; ++r) {
-          hip_check(hipEventRecord(evs[2 * r], s), "hipEventRecord");
-          run_nll(m, &pb, nullptr, ev, n, ld, true, nullptr, s);
-          hip_check(hipEventRecord(evs[2 * r + 1], s), "hipEventRecord");
+      if (n_ept == 2 && !m->dal_jit2) m->dal_jit2 = dalitz_jit(m->dal, 2);
+      for (int e = 0; e < n_ept; ++e) {
+        m->ept = e + 1;
+        for (int c = 0; c < count; ++c) {
+          m->chunk = cand[c];
+          for (int w = 0; w < 3; ++w) run_nll(m, &pb, nullptr, ev, n, ld, true, nullptr, s);  // warm-up, buffers
+          for (int r = 0; r < reps; ++r) {
+            hip_check(hipEventRecord(evs[2 * r], s), "hipEventRecord");
+            run_nll(m, &pb, nullptr, ev, n, ld, true, nullptr, s);
+            hip_check(hipEventRecord(evs[2 * r + 1], s), "hipEventRecord");
+          }
+          hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+          std::vector<double> t(reps);
+          for (int r = 0; r < reps; ++r) {
+            float ms = 0.0f;
+            hip_check(hipEventElapsedTime(&ms, evs[2 * r], evs[2 * r + 1]), "hipEventElapsedTime");
+            t[r] = 1e3 * ms;
+          }
+          std::nth_element(t.begin(), t.begin() + reps / 2, t.end());
+          med[(size_t)e * count + c] = t[reps / 2];
+          if (us_out) us_out[e * FN_TUNE_MAX + c] = t[reps / 2];
         }
-        hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
-        std::vector<double> t(reps);
-        for (int r = 0; r < reps; ++r) {
-          float ms = 0.0f;
-          hip_check(hipEventElapsedTime(&ms, evs[2 * r], evs[2 * r + 1]), "hipEventElapsedTime");
-          t[r] = 1e3 * ms;
-        }
-        std::nth_element(t.begin(), t.begin() + reps / 2, t.end());
-        med[c] = t[reps / 2];
-        if (us_out) us_out[c] = med[c];
       }
     } catch (...) {
       m->chunk = saved;
+      m->ept = saved_ept;
       for (auto& e : evs) (void)hipEventDestroy(e);
       throw;
     }
     for (auto& e : evs) (void)hipEventDestroy(e);
-    // the largest chunk within kTuneTie of the fastest: fewer partial rows for
-    // the level-2 step, and a stable choice when candidates time alike
+    // among the candidates within kTuneTie of the fastest: one event per
+    // thread when it has one (fewer registers), then the largest chunk (fewer
+    // partial rows for the level-2 step, and a stable choice when candidates
+    // time alike)
     const double fastest = *std::min_element(med.begin(), med.end());
-    int best = cand[0];
-    for (int c = 0; c < count; ++c)
-      if (med[c] <= (1.0 + kTuneTie) * fastest && cand[c] > best) best = cand[c];
-    m->chunk = best;
-    if (chunk_out) *chunk_out = best;
+    int best_e = -1, best_c = 0;
+    for (int e = 0; e < n_ept && best_e < 0; ++e)
+      for (int c = 0; c < count; ++c)
+        if (med[(size_t)e * count + c] <= (1.0 + kTuneTie) * fastest && cand[c] > best_c) {
+          best_e = e;
+          best_c = cand[c];
+        }
+    m->chunk = best_c;
+    m->ept = best_e + 1;
+    if (chunk_out) *chunk_out = best_c;
+    if (ept_out) *ept_out = best_e + 1;
   });
 }
 

@@ -94,6 +94,14 @@ def test_model_kernels_compile_for_gfx950_without_a_device():
     for free in (False, True):
         d = synth.dalitz_desc(free_lineshapes=free)
         assert lib.fn_model_check_compile(json.dumps(d).encode(), b"gfx950") == _lib.FN_OK, lib.fn_last_error()
+        # the events passes with two events per thread and loop iteration
+        d["events_per_thread"] = 2
+        assert lib.fn_model_check_compile(json.dumps(d).encode(), b"gfx950") == _lib.FN_OK, lib.fn_last_error()
+        d["events_per_thread"] = 3
+        assert lib.fn_model_check_compile(json.dumps(d).encode(), None) == _lib.FN_E_INVALID
+    d = synth.td4_desc()
+    d["events_per_thread"] = 2
+    assert lib.fn_model_check_compile(json.dumps(d).encode(), None) == _lib.FN_E_INVALID
     # a two-resonance model in one pair with spins 0 and 2 only
     d = synth.dalitz_desc()
     d["resonances"] = [{"pair": "13", "L": 0, "m0": 1.43, "w0": 0.27}, {"pair": "13", "L": 2, "m0": 1.43, "w0": 0.1}]
