@@ -40,7 +40,7 @@ COUNTED_FP64_FLOPS_PER_EVENT = {(2048, 1): 420.9}
 TRAFFIC_SOURCES = ["paper_1710_08826_amd/csrc/dalitz_device.hpp", "paper_1710_08826_amd/csrc/dalitz3.hip",
                    "paper_1710_08826_amd/csrc/fastmath.hpp", "paper_1710_08826_amd/csrc/device_common.hpp",
                    "paper_1710_08826_amd/csrc/model.hpp"]
-TRAFFIC_HASH = "5c7e3dcb9a536254"
+TRAFFIC_HASH = "d56107e48f3b9c7b"
 
 
 def counters_current() -> bool:

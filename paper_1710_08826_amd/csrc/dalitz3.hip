@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <sstream>
+#include <vector>
 
 #include "dalitz_device.hpp"
 #include "internal.hpp"
@@ -285,7 +286,59 @@ __global__ void dalitz_check(DalitzConst dc, const double* __restrict__ ev, int6
   if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(bad, (unsigned long long)__popcll(cnt));
 }
 
+// The grid cells inside the region, per column ix (s12): counted, then
+// listed in column-major order at the offsets of the counts' prefix sums;
+// the same predicate and cell centres as every grid pass.
+__global__ void dalitz_grid_count(DalitzConst dc, int32_t* __restrict__ cnt) {
+  const int64_t ix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ix >= dc.nx) return;
+  const double s12 = grid_centre(dc.a12, ix, dc.d12);
+  double lo, hi;
+  dalitz_row_bounds(dc, s12, lo, hi);
+  int32_t c = 0;
+  for (int64_t iy = 0; iy < dc.ny; ++iy) c += dalitz_in_row(dc, s12, grid_centre(dc.a13, iy, dc.d13), lo, hi);
+  cnt[ix] = c;
+}
+
+__global__ void dalitz_grid_fill(DalitzConst dc, const int64_t* __restrict__ off, GridCell* __restrict__ cells) {
+  const int64_t ix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ix >= dc.nx) return;
+  const double s12 = grid_centre(dc.a12, ix, dc.d12);
+  double lo, hi;
+  dalitz_row_bounds(dc, s12, lo, hi);
+  int64_t o = off[ix];
+  const int64_t end = off[ix + 1];
+  for (int64_t iy = 0; iy < dc.ny && o < end; ++iy)
+    if (dalitz_in_row(dc, s12, grid_centre(dc.a13, iy, dc.d13), lo, hi)) cells[o++] = GridCell{(int32_t)ix, (int32_t)iy};
+}
+
 // ---------------------------------------------------------------- launchers
+int64_t dalitz_build_grid_cells(const DalitzConst& dc, DevBuf& cells, hipStream_t s) {
+  const int64_t nx = dc.nx;
+  DevBuf d_cnt, d_off;
+  d_cnt.reserve(sizeof(int32_t) * nx);
+  d_off.reserve(sizeof(int64_t) * (nx + 1));
+  const unsigned blocks = (unsigned)((nx + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(dalitz_grid_count, dim3(blocks), dim3(kBlock), 0, s, dc, (int32_t*)d_cnt.ptr);
+  hip_check(hipGetLastError(), "dalitz_grid_count");
+  std::vector<int32_t> cnt(nx);
+  hip_check(hipMemcpyAsync(cnt.data(), d_cnt.ptr, sizeof(int32_t) * nx, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+  hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+  std::vector<int64_t> off(nx + 1, 0);
+  for (int64_t i = 0; i < nx; ++i) off[i + 1] = off[i] + cnt[i];
+  const int64_t n_in = off[nx];
+  cells.reserve(sizeof(GridCell) * (size_t)(n_in > 0 ? n_in : 1));
+  if (n_in > 0) {
+    hip_check(hipMemcpyAsync(d_off.ptr, off.data(), sizeof(int64_t) * (nx + 1), hipMemcpyHostToDevice, s),
+              "hipMemcpyAsync");
+    hipLaunchKernelGGL(dalitz_grid_fill, dim3(blocks), dim3(kBlock), 0, s, dc, (const int64_t*)d_off.ptr,
+                       (GridCell*)cells.ptr);
+    hip_check(hipGetLastError(), "dalitz_grid_fill");
+  }
+  hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+  return n_in;
+}
+
 int dalitz_kmax(int K) { return K; }  // partial rows hold exactly the model's resonances
 int dalitz_nv_events(int kmax, int grad) { return dal_nv(kEvents, grad, kmax); }
 int dalitz_nv_mrows(int kmax) { return dal_nv(kMRows, 0, kmax); }
@@ -455,9 +508,10 @@ void dalitz_launch_finalize(const DalitzConst& dc, const DalitzTable* tab, const
 }
 
 void dalitz_launch_grid(const DalitzJit& j, const DalitzConst& dc, const DalitzTable* tab, const double* coef,
-                        int chunk, int64_t nchunks, int grad, double* part, hipStream_t s) {
-  const int64_t ncell = (int64_t)dc.nx * dc.ny;
-  launch_pass(j.gr[grad], dc, tab, coef, nullptr, 0, ncell, chunk, nchunks, 0, part, s);
+                        const GridCell* cells, int64_t n_inside, int chunk, int64_t nchunks, int grad, double* part,
+                        hipStream_t s) {
+  launch_pass(j.gr[grad], dc, tab, coef, reinterpret_cast<const double*>(cells), 0, n_inside, chunk, nchunks, 0,
+              part, s);
 }
 
 void dalitz_launch_mrows(const DalitzJit& j, const DalitzConst& dc, const DalitzTable* tab, int chunk,

@@ -99,6 +99,14 @@ __device__ __forceinline__ void pair_terms(const DalitzChan& ch, double s_ab, do
   }
 }
 
+// Centre of cell i along a grid axis that starts at a with cells of size d,
+// as the plain IEEE evaluation (no contraction), so that every pass and the
+// cell list see the same bits.
+__device__ inline double grid_centre(double a, int64_t i, double d) {
+#pragma clang fp contract(off)
+  return a + (i + 0.5) * d;
+}
+
 // Physical-region bounds of the grid row at s12: s23 between lo and hi, from
 // the energies of daughters 2 and 3 in the (12) rest frame.  Contraction is
 // off so that the decision is the plain IEEE evaluation.
@@ -284,12 +292,13 @@ __device__ inline void dalitz_chunk(const DalitzConst& dc, const DalitzTable* __
   const int64_t end = base + chunk < n ? base + chunk : n;
   const double* const r0 = &tab->r[0][0];
   LogProd lp;
-  // grid passes, one cell per thread and iteration: the cell's (ix, iy)
-  // advanced by kBlock cells per iteration instead of a 64-bit division, and
-  // the region's bounds computed once per row
+  // matrix-row passes over the whole grid, one cell per thread and
+  // iteration: the cell's (ix, iy) advanced by kBlock cells per iteration
+  // instead of a 64-bit division, and the region's bounds computed once per
+  // grid column
   int64_t gx = 0, gy = 0, row_ix = -1;
   double row_lo = 0.0, row_hi = 0.0;
-  if (MODE != kEvents && EPT == 1) {
+  if (MODE == kMRows && EPT == 1) {
     gx = (base + threadIdx.x) / dc.ny;
     gy = (base + threadIdx.x) - gx * dc.ny;
   }
@@ -312,6 +321,11 @@ __device__ inline void dalitz_chunk(const DalitzConst& dc, const DalitzTable* __
       if (MODE == kEvents) {
         s12 = ev[jj];
         s13 = ev[ld + jj];
+      } else if (MODE == kGrid) {
+        // grid passes walk the list of the cells inside the region (ev)
+        const GridCell g = reinterpret_cast<const GridCell*>(ev)[jj];
+        s12 = grid_centre(dc.a12, g.ix, dc.d12);
+        s13 = grid_centre(dc.a13, g.iy, dc.d13);
       } else if (EPT == 1) {
         const int64_t ix = gx, iy = gy;
         gy += kBlock;
@@ -319,8 +333,8 @@ __device__ inline void dalitz_chunk(const DalitzConst& dc, const DalitzTable* __
           gy -= dc.ny;
           ++gx;
         }
-        s12 = dc.a12 + (ix + 0.5) * dc.d12;
-        s13 = dc.a13 + (iy + 0.5) * dc.d13;
+        s12 = grid_centre(dc.a12, ix, dc.d12);
+        s13 = grid_centre(dc.a13, iy, dc.d13);
         if (ix != row_ix) {
           dalitz_row_bounds(dc, s12, row_lo, row_hi);
           row_ix = ix;
@@ -329,8 +343,8 @@ __device__ inline void dalitz_chunk(const DalitzConst& dc, const DalitzTable* __
       } else {
         const int64_t ix = jj / dc.ny;
         const int64_t iy = jj - ix * dc.ny;
-        s12 = dc.a12 + (ix + 0.5) * dc.d12;
-        s13 = dc.a13 + (iy + 0.5) * dc.d13;
+        s12 = grid_centre(dc.a12, ix, dc.d12);
+        s13 = grid_centre(dc.a13, iy, dc.d13);
         valid = valid && dalitz_inside(dc, s12, s13);
       }
       dalitz_point<S, MODE, GRAD>(dc, r, coef, s12, s13, valid, i0, acc, lp);
@@ -421,8 +435,8 @@ __device__ inline void dalitz_gridmax_body(const DalitzConst& dc, const DalitzTa
   double m = 0.0;
   for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < ncell; c += (int64_t)gridDim.x * kBlock) {
     const int64_t ix = c / dc.ny, iy = c - ix * dc.ny;
-    const double s12 = dc.a12 + (ix + 0.5) * dc.d12;
-    const double s13 = dc.a13 + (iy + 0.5) * dc.d13;
+    const double s12 = grid_centre(dc.a12, ix, dc.d12);
+    const double s13 = grid_centre(dc.a13, iy, dc.d13);
     if (!dalitz_inside(dc, s12, s13)) continue;
     m = fmax(m, dalitz_value<S>(dc, r, tab->coef, s12, s13));
   }

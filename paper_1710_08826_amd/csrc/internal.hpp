@@ -69,6 +69,8 @@ struct fn_model {
   bool M_valid = false;          // cached normalization matrix is current
   bool table_ready = false;      // fixed lineshapes: the table's lineshape constants are built
   fn::DevBuf d_table, d_part, d_npart, d_out, d_fixed, d_M, d_count, d_mc, d_gen;
+  fn::DevBuf d_cells;            // dalitz3, free lineshapes: the grid cells inside the region (GridCell)
+  int64_t n_inside = 0;          // their number
   double box[4] = {0.0, 0.0, 0.0, 0.0};  // Dalitz: kinematic box (s12 lo, hi, s13 lo, hi)
   fn::DevBuf d_theta;                    // tddp3: theta on the device for host-theta calls
   double* h_out = nullptr;       // pinned

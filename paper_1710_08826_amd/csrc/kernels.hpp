@@ -7,6 +7,8 @@
 
 namespace fn {
 
+struct DevBuf;
+
 // mix1d
 int mix1d_kmax(int K);
 // Type signature a mixture's per-event passes are compiled for (mix_sig_K):
@@ -82,8 +84,14 @@ void dalitz_launch_finalize(const DalitzConst& dc, const DalitzTable* tab, const
                             int64_t ev_rows, int grad, double* npart, int64_t n_rows, int n_nv,
                             const double* Mc, double n_events, double* out, double* out_user, hipStream_t s,
                             bool norm_ready = false, unsigned long long* span = nullptr);
+// The list of the grid cells inside the region (column-major) into `cells`;
+// returns their number.  Synchronous on s (at model creation).
+int64_t dalitz_build_grid_cells(const DalitzConst& dc, DevBuf& cells, hipStream_t s);
+// Grid pass of a model with free lineshapes over the n_inside listed cells
+// (nchunks >= 1 rows of partial sums; a row of an empty chunk holds zeros).
 void dalitz_launch_grid(const DalitzJit& j, const DalitzConst& dc, const DalitzTable* tab, const double* coef,
-                        int chunk, int64_t nchunks, int grad, double* part, hipStream_t s);
+                        const GridCell* cells, int64_t n_inside, int chunk, int64_t nchunks, int grad, double* part,
+                        hipStream_t s);
 // Level-2 of a row-block pass of K x K matrices (rows i0..i0+3, 2 K doubles
 // each per chunk row) into Mc, scaled by the cell area.
 void dalitz_launch_mrows_finalize(const DalitzConst& dc, const double* part, int64_t nchunks, int i0, double* Mc,

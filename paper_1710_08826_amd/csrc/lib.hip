@@ -267,6 +267,8 @@ static void compile_dalitz3(const json::Value& d, fn_model* m, bool device = tru
   m->grid_chunk = 1024;
   if (!device) return;
   m->dal_jit = dalitz_jit(dc);
+  // free lineshapes: the grid passes walk the list of the inside cells
+  if (dc.free_ls) m->n_inside = dalitz_build_grid_cells(dc, m->d_cells, nullptr);
   m->d_table.reserve(sizeof(DalitzTable));
   m->d_fixed.reserve(sizeof(double) * 2 * dc.K);
   hip_check(hipMemcpy(m->d_fixed.ptr, m->fixed_ls.data(), sizeof(double) * 2 * dc.K, hipMemcpyHostToDevice),
@@ -544,7 +546,8 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
     const int nv = dalitz_nv_events(kmax, g);
     // grid rows when the lineshapes are free; long row sets get room for
     // their pre-summed rows after them (see dalitz_launch_finalize)
-    const int64_t grid_rows_n = dc.free_ls ? nchunks_for((int64_t)dc.nx * dc.ny, m->grid_chunk) : 0;
+    const int64_t grid_rows_n =
+        dc.free_ls ? std::max<int64_t>(1, nchunks_for(m->n_inside, m->grid_chunk)) : 0;
     const int grid_nv = dc.free_ls ? dalitz_nv_events(kmax, g) : 0;
     const int64_t pre_e = presum_blocks(nch, nv, grid_rows_n, grid_nv);
     const int64_t pre_g = pre_e > 0 && dc.free_ls ? presum_blocks(grid_rows_n, grid_nv, nch, nv) : 0;
@@ -567,7 +570,8 @@ void run_nll(fn_model* m, const ParamBlock* pb, const double* theta_dev, const d
       nrows = grid_rows_n;
       nnv = grid_nv;
       norm_rows((size_t)(nrows + pre_g) * nnv);
-      dalitz_launch_grid(*m->dal_jit, dc, m->table_dal(), coef, m->grid_chunk, nrows, g, npart, s);
+      dalitz_launch_grid(*m->dal_jit, dc, m->table_dal(), coef, (const GridCell*)m->d_cells.ptr, m->n_inside,
+                         m->grid_chunk, nrows, g, npart, s);
       grid_rows = npart;
     } else if (!m->M_valid) {
       // fixed lineshapes: reduce the grid once to M_ij = dA sum A_i conj(A_j)

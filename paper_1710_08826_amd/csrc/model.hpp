@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #else  // runtime compilation: the HIP device environment is built in, fixed-width integers live here
+using __hip_internal::int32_t;
 using __hip_internal::int64_t;
 using __hip_internal::uint32_t;
 using __hip_internal::uint64_t;
@@ -77,6 +78,13 @@ struct DalitzConst {
   int chan[kDalMaxRes];           // 0 = "12", 1 = "13", 2 = "23"
   int L[kDalMaxRes];
   DalitzChan ch[3];
+};
+
+// A grid cell inside the physical region: column ix (s12) and row iy (s13).
+// The grid passes of models with free lineshapes walk the list of these cells
+// (built once per model, in column-major order) instead of the whole grid.
+struct alignas(8) GridCell {
+  int32_t ix, iy;
 };
 
 // Per-fit per-resonance record (prologue output).

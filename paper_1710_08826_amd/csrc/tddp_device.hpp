@@ -163,8 +163,8 @@ __device__ inline void tddp_mrows_body(const DalitzConst& dc, const DalitzTable*
     asm volatile("" : "+s"(zero));
     const double* r = r0 + zero;
     const int64_t ix = c / dc.ny, iy = c - ix * dc.ny;
-    const double s12 = dc.a12 + (ix + 0.5) * dc.d12;
-    const double s13 = dc.a13 + (iy + 0.5) * dc.d13;
+    const double s12 = grid_centre(dc.a12, ix, dc.d12);
+    const double s13 = grid_centre(dc.a13, iy, dc.d13);
     if (!dalitz_inside(dc, s12, s13)) continue;
     double Are[K], Aim[K], Bre[K], Bim[K], Lre[K], Lim[K], Rre[K], Rim[K];
     tddp_basis2<S>(dc, r, s12, s13, Are, Aim, Bre, Bim);
@@ -227,8 +227,8 @@ __device__ inline void tddp_gridmax_body(const DalitzConst& dc, const DalitzTabl
   double m = 0.0;
   for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < ncell; c += (int64_t)gridDim.x * kBlock) {
     const int64_t ix = c / dc.ny, iy = c - ix * dc.ny;
-    const double s12 = dc.a12 + (ix + 0.5) * dc.d12;
-    const double s13 = dc.a13 + (iy + 0.5) * dc.d13;
+    const double s12 = grid_centre(dc.a12, ix, dc.d12);
+    const double s13 = grid_centre(dc.a13, iy, dc.d13);
     if (!dalitz_inside(dc, s12, s13)) continue;
     cplx A, Ab;
     tddp_amps<S>(dc, r, coef, s12, s13, A, Ab);
