@@ -55,9 +55,8 @@ struct PairTerms {
 //   G_1 = (q/sqrt s) q^2 / (1 + z_q),          H_1 = Z_1 / sqrt((1 + z_q)(1 + z_p))
 //   G_2 = (q/sqrt s) q^4 / (z_q^2 + 3 z_q + 9), H_2 = Z_2 / sqrt(poly(z_q) poly(z_p))
 template <bool U1, bool U2>
-__device__ __forceinline__ void pair_terms_t(const DalitzChan& ch, double s_ab, double s_ac, double s_bc, double r2,
-                                             double rD2, PairTerms& o) {
-  const double is = rcp_fast(s_ab);
+__device__ __forceinline__ void pair_terms_is(const DalitzChan& ch, double s_ab, double is, double s_ac, double s_bc,
+                                              double r2, double rD2, PairTerms& o) {
   const double lq = fmax((s_ab - ch.sum2) * (s_ab - ch.dif2), 0.0);
   const double q2 = 0.25 * lq * is;
   const double qirs = 0.5 * sqrt_fast(lq) * is;
@@ -85,6 +84,13 @@ __device__ __forceinline__ void pair_terms_t(const DalitzChan& ch, double s_ab, 
       o.H[2] = z2 * r;
     }
   }
+}
+
+// The same, forming 1/s_AB itself.
+template <bool U1, bool U2>
+__device__ __forceinline__ void pair_terms_t(const DalitzChan& ch, double s_ab, double s_ac, double s_bc, double r2,
+                                             double rD2, PairTerms& o) {
+  pair_terms_is<U1, U2>(ch, s_ab, rcp_fast(s_ab), s_ac, s_bc, r2, rD2, o);
 }
 
 // The same with the spins used by the pair given at run time.
@@ -145,48 +151,93 @@ __host__ __device__ constexpr bool shape_uses(int c, int l) {
 
 // One resonance's amplitude from its pair's terms: A_k = Ka H T with
 // T = 1 / (a - i b) = (a + i b) d, a = m0^2 - s, b = Kw G, d = 1 / (a^2 + b^2)
-// (rk: the resonance's row of the table).
-__device__ __forceinline__ void dalitz_bw(const double* __restrict__ rk, double s, double G, double H, double& ar,
-                                          double& ai, double& a, double& b, double& d) {
+// (rk: the resonance's row of the table), in two steps so that the
+// reciprocals of several resonances can be formed together (rcp_group).
+__device__ __forceinline__ void bw_denominator(const double* __restrict__ rk, double s, double G, double& a,
+                                               double& b, double& D) {
   a = rk[dM0SQ] - s;
   b = rk[dKW] * G;
-  d = rcp_fast(__builtin_fma(a, a, b * b));
+  D = __builtin_fma(a, a, b * b);
+}
+
+__device__ __forceinline__ void bw_amplitude(const double* __restrict__ rk, double H, double a, double b, double d,
+                                             double& ar, double& ai) {
   const double u = (rk[dKA] * H) * d;
   ar = u * a;
   ai = u * b;
 }
 
-// Amplitudes of the resonances of pair C (compile-time), added to the coherent sum.
-template <class S, int C, int MODE, bool KEEP_A, bool KEEP_T>
-__device__ __forceinline__ void dalitz_pair(const DalitzConst& dc, const double* __restrict__ r,
-                                            const double* __restrict__ coef, double s12,
-                                            double s13, double s23, double (&Are)[S::K], double (&Aim)[S::K],
-                                            double (&Tre)[S::K], double (&Tim)[S::K], double (&Gk)[S::K],
-                                            double& Sre, double& Sim) {
-  constexpr bool any = shape_uses<S>(C, 0) || shape_uses<S>(C, 1) || shape_uses<S>(C, 2);
-  if (!any) return;
+__device__ __forceinline__ void dalitz_bw(const double* __restrict__ rk, double s, double G, double H, double& ar,
+                                          double& ai, double& a, double& b, double& d) {
+  double D;
+  bw_denominator(rk, s, G, a, b, D);
+  d = rcp_fast(D);
+  bw_amplitude(rk, H, a, b, d, ar, ai);
+}
+
+template <class S, int C>
+__host__ __device__ constexpr bool pair_used() {
+  return shape_uses<S>(C, 0) || shape_uses<S>(C, 1) || shape_uses<S>(C, 2);
+}
+
+// Pair terms of pair C (compile-time) at a point, when the shape uses it
+// (is: 1/s_AB).
+template <class S, int C>
+__device__ __forceinline__ void dalitz_pair_terms(const DalitzConst& dc, double s12, double s13, double s23,
+                                                  double is, PairTerms& pt) {
+  if (!pair_used<S, C>()) return;
   // pair "12": (A,B,C) = (1,2,3); "13": (1,3,2); "23": (2,3,1)
   const double s_ab = C == 0 ? s12 : (C == 1 ? s13 : s23);
   const double s_ac = C == 0 ? s13 : s12;
   const double s_bc = C == 2 ? s13 : s23;
-  PairTerms pt;
-  pair_terms_t<shape_uses<S>(C, 1), shape_uses<S>(C, 2)>(dc.ch[C], s_ab, s_ac, s_bc, dc.r2, dc.rD2, pt);
+  pair_terms_is<shape_uses<S>(C, 1), shape_uses<S>(C, 2)>(dc.ch[C], s_ab, is, s_ac, s_bc, dc.r2, dc.rD2, pt);
+}
+
+// Amplitudes of all resonances (in model order, four at a time for the
+// reciprocals), added to the coherent sum S = sum_k c_k A_k.
+template <class S, int MODE, bool KEEP_A, bool KEEP_T>
+__device__ __forceinline__ void dalitz_amps(const DalitzConst& dc, const double* __restrict__ r,
+                                            const double* __restrict__ coef, double s12, double s13, double s23,
+                                            double (&Are)[S::K], double (&Aim)[S::K], double (&Tre)[S::K],
+                                            double (&Tim)[S::K], double (&Gk)[S::K], double& Sre, double& Sim) {
+  constexpr int K = S::K;
+  // 1/s of the pairs in use from one reciprocal (an unused pair's 1 drops out)
+  double is[4] = {pair_used<S, 0>() ? s12 : 1.0, pair_used<S, 1>() ? s13 : 1.0, pair_used<S, 2>() ? s23 : 1.0, 1.0};
+  rcp_group(is, 3);
+  PairTerms pt0, pt1, pt2;
+  dalitz_pair_terms<S, 0>(dc, s12, s13, s23, is[0], pt0);
+  dalitz_pair_terms<S, 1>(dc, s12, s13, s23, is[1], pt1);
+  dalitz_pair_terms<S, 2>(dc, s12, s13, s23, is[2], pt2);
 #pragma unroll
-  for (int k = 0; k < S::K; ++k) {
-    if (S::chan[k] == C) {
-      const int L = S::L[k];
-      const double* rk = r + k * kDalFields;
-      const double G = pt.G[L];
-      const double H = pt.H[L];
-      double ar, ai, a, b, d;
-      dalitz_bw(rk, pt.s, G, H, ar, ai, a, b, d);
-      if (KEEP_A) { Are[k] = ar; Aim[k] = ai; }
-      if (KEEP_T) { Tre[k] = a * d; Tim[k] = b * d; Gk[k] = G; }
-      if (MODE != kMRows) {
-        // S += c_k A_k as four chained FMAs
-        const double cr = coef[2 * k], ci = coef[2 * k + 1];
-        Sre = __builtin_fma(cr, ar, __builtin_fma(-ci, ai, Sre));
-        Sim = __builtin_fma(cr, ai, __builtin_fma(ci, ar, Sim));
+  for (int g = 0; g < K; g += 4) {
+    const int n = K - g < 4 ? K - g : 4;
+    double a[4], b[4], D[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (j < n) {
+        const int k = g + j;
+        const PairTerms& pt = S::chan[k] == 0 ? pt0 : (S::chan[k] == 1 ? pt1 : pt2);
+        bw_denominator(r + k * kDalFields, pt.s, pt.G[S::L[k]], a[j], b[j], D[j]);
+      }
+    }
+    rcp_group(D, n);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (j < n) {
+        const int k = g + j;
+        const int L = S::L[k];
+        const PairTerms& pt = S::chan[k] == 0 ? pt0 : (S::chan[k] == 1 ? pt1 : pt2);
+        const double* rk = r + k * kDalFields;
+        double ar, ai;
+        bw_amplitude(rk, pt.H[L], a[j], b[j], D[j], ar, ai);
+        if (KEEP_A) { Are[k] = ar; Aim[k] = ai; }
+        if (KEEP_T) { Tre[k] = a[j] * D[j]; Tim[k] = b[j] * D[j]; Gk[k] = pt.G[L]; }
+        if (MODE != kMRows) {
+          // S += c_k A_k as four chained FMAs
+          const double cr = coef[2 * k], ci = coef[2 * k + 1];
+          Sre = __builtin_fma(cr, ar, __builtin_fma(-ci, ai, Sre));
+          Sim = __builtin_fma(cr, ai, __builtin_fma(ci, ar, Sim));
+        }
       }
     }
   }
@@ -204,9 +255,7 @@ __device__ __forceinline__ void dalitz_point(const DalitzConst& dc, const double
   const double s23 = dc.msum - s12 - s13;
   double Are[K], Aim[K], Tre[K], Tim[K], Gk[K];
   double Sre = 0.0, Sim = 0.0;
-  dalitz_pair<S, 0, MODE, KEEP_A, KEEP_T>(dc, r, coef, s12, s13, s23, Are, Aim, Tre, Tim, Gk, Sre, Sim);
-  dalitz_pair<S, 1, MODE, KEEP_A, KEEP_T>(dc, r, coef, s12, s13, s23, Are, Aim, Tre, Tim, Gk, Sre, Sim);
-  dalitz_pair<S, 2, MODE, KEEP_A, KEEP_T>(dc, r, coef, s12, s13, s23, Are, Aim, Tre, Tim, Gk, Sre, Sim);
+  dalitz_amps<S, MODE, KEEP_A, KEEP_T>(dc, r, coef, s12, s13, s23, Are, Aim, Tre, Tim, Gk, Sre, Sim);
   auto add = [&](int idx, double v) { acc[idx] += valid ? v : 0.0; };
   // acc[idx] += x1 y1 + x2 y2 as two chained FMAs
   auto add2 = [&](int idx, double x1, double y1, double x2, double y2) {
@@ -418,9 +467,7 @@ __device__ __forceinline__ double dalitz_value(const DalitzConst& dc, const doub
   const double s23 = dc.msum - s12 - s13;
   double Are[K], Aim[K], Tre[K], Tim[K], Gk[K];
   double Sre = 0.0, Sim = 0.0;
-  dalitz_pair<S, 0, kGrid, false, false>(dc, r, coef, s12, s13, s23, Are, Aim, Tre, Tim, Gk, Sre, Sim);
-  dalitz_pair<S, 1, kGrid, false, false>(dc, r, coef, s12, s13, s23, Are, Aim, Tre, Tim, Gk, Sre, Sim);
-  dalitz_pair<S, 2, kGrid, false, false>(dc, r, coef, s12, s13, s23, Are, Aim, Tre, Tim, Gk, Sre, Sim);
+  dalitz_amps<S, kGrid, false, false>(dc, r, coef, s12, s13, s23, Are, Aim, Tre, Tim, Gk, Sre, Sim);
   return __builtin_fma(Sre, Sre, Sim * Sim);
 }
 

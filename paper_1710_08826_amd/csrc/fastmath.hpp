@@ -47,6 +47,39 @@ __device__ __forceinline__ double rsqrt_fast(double x) {
   return __builtin_fma(y * 0.5, e, y);
 }
 
+// In place, D[j] <- 1 / D[j] for the first n (1..4) entries, from one
+// reciprocal of their product (simultaneous inversion: with p_j = D_0 ... D_j
+// and r = 1 / p_{n-1}, 1/D_j = r p_{j-1} D_{j+1} ... D_{n-1}, peeled from the
+// top down): 3 (n - 1) multiplies in place of n - 1 reciprocals and their
+// Newton steps (a stream of v_rcp_f64 alone issues at about a third of the
+// FMA rate on gfx950).  The products form a serial chain, which pays where
+// the waves hide its latency: the three-body Dalitz passes (config-1 step
+// 18.5 -> 17.9 us); the four-body pass, at two waves per SIMD, measured 5%
+// slower and the time-dependent three-body pass even, and they keep one
+// reciprocal per denominator.  A product of four denominators stays a normal
+// number for denominators in [2^-250, 2^250]; the result carries a few more
+// roundings (about 2 n) than a reciprocal each.  n is a compile-time constant
+// where this is inlined into unrolled code.
+__device__ __forceinline__ void rcp_group(double (&D)[4], int n) {
+  double p[4];
+  p[0] = D[0];
+#pragma unroll
+  for (int j = 1; j < 4; ++j) p[j] = j < n ? p[j - 1] * D[j] : p[j - 1];
+  double pn = p[0];
+#pragma unroll
+  for (int j = 1; j < 4; ++j) pn = j < n ? p[j] : pn;
+  double r = rcp_fast(pn);
+#pragma unroll
+  for (int j = 3; j > 0; --j) {
+    if (j < n) {
+      const double dj = r * p[j - 1];
+      r = r * D[j];
+      D[j] = dj;
+    }
+  }
+  D[0] = r;
+}
+
 // sqrt for x >= 0; arguments below 1e-300 are treated as 1e-300.
 __device__ __forceinline__ double sqrt_fast(double x) {
   const double xc = __builtin_fmax(x, 1e-300);
