@@ -36,11 +36,11 @@ PEAK_HBM_GBS = 8000.0
 # SQ_INSTS_VALU_FLOPS_FP64, valid for the kernel sources with this hash;
 # reported as null once they change or for a choice without a counter run.
 TRAFFIC_BYTES = {(2048, 1): 1.620e7}
-COUNTED_FP64_FLOPS_PER_EVENT = {(2048, 1): 420.9}
+COUNTED_FP64_FLOPS_PER_EVENT = {(2048, 1): 404.9}
 TRAFFIC_SOURCES = ["paper_1710_08826_amd/csrc/dalitz_device.hpp", "paper_1710_08826_amd/csrc/dalitz3.hip",
                    "paper_1710_08826_amd/csrc/fastmath.hpp", "paper_1710_08826_amd/csrc/device_common.hpp",
                    "paper_1710_08826_amd/csrc/model.hpp"]
-TRAFFIC_HASH = "d56107e48f3b9c7b"
+TRAFFIC_HASH = "790966b396f769e5"
 
 
 def counters_current() -> bool:
