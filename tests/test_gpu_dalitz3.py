@@ -91,6 +91,29 @@ def test_config3_gradient_vs_central_fd(m3):
     assert ok, r
 
 
+@pytest.mark.parametrize("grid", [(37, 23), (1200, 7), (1, 1)])
+def test_free_lineshapes_on_uneven_grids(grid):
+    """The list of inside cells on grids where it is shorter than one
+    workgroup's 1024 cells, spans many grid columns per workgroup (columns of
+    a few cells each), or holds the single centre cell: NLL, normalization
+    and full gradient against the oracle on the same grid."""
+    from paper_1710_08826_amd import Model
+    say("uneven grid", grid)
+    d = OD.config1_desc(grid=grid, free_lineshapes=True)
+    m = Model(d)
+    cells = OD.Dalitz(d).grid_cells()
+    assert cells[0].size >= 1
+    ev = synth.dalitz_events(3000, seed=36)
+    th = offset(OD.truth_theta(d))
+    v, g = m.nll(th, to_dev(ev), grad=True)
+    vo, go = OD.nll_grad(th, ev, d, cells)
+    assert rel_close(v, vo, 1e-12), (v, vo)
+    ok, r = grad_close(g, go, 1e-10)
+    assert ok, r
+    I, _ = m.norm(th)
+    assert rel_close(I, OD.norm_value(OD.Dalitz(d), th, cells), 1e-12)
+
+
 def test_full_size_config1(m1, cells1):
     """1M events, the benchmark's configuration."""
     ev = synth.dalitz_events(1_000_000, seed=34)
