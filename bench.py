@@ -40,7 +40,7 @@ COUNTED_FP64_FLOPS_PER_EVENT = {(2048, 1): 404.9}
 TRAFFIC_SOURCES = ["paper_1710_08826_amd/csrc/dalitz_device.hpp", "paper_1710_08826_amd/csrc/dalitz3.hip",
                    "paper_1710_08826_amd/csrc/fastmath.hpp", "paper_1710_08826_amd/csrc/device_common.hpp",
                    "paper_1710_08826_amd/csrc/model.hpp"]
-TRAFFIC_HASH = "790966b396f769e5"
+TRAFFIC_HASH = "ea741244afb06c3e"
 
 
 def counters_current() -> bool:

@@ -326,8 +326,9 @@ __device__ __forceinline__ void dalitz_point(const DalitzConst& dc, const double
 // GRAD: 0 none, 1 coefficients only, 2 coefficients + masses and widths.
 // EPT events per thread and loop iteration (independent work for the
 // scheduler to interleave); each thread still adds its points in index order.
-// Two per iteration measured slower than one for the config-1 structure on
-// MI355X (more VGPRs, one wave less per SIMD), so the generated kernels use one.
+// Two per iteration measured slower than one for the eight-resonance model on
+// MI355X (more VGPRs); the events passes come in both forms and the
+// autotuner times them, the grid and matrix-row passes use one.
 template <class S, int MODE, int GRAD, int EPT = 1>
 __device__ inline void dalitz_chunk(const DalitzConst& dc, const DalitzTable* __restrict__ tab,
                                     const double* __restrict__ coef0, const double* __restrict__ ev, int64_t ld,

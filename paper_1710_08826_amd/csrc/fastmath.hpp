@@ -53,10 +53,10 @@ __device__ __forceinline__ double rsqrt_fast(double x) {
 // top down): 3 (n - 1) multiplies in place of n - 1 reciprocals and their
 // Newton steps (a stream of v_rcp_f64 alone issues at about a third of the
 // FMA rate on gfx950).  The products form a serial chain, which pays where
-// the waves hide its latency: the three-body Dalitz passes (config-1 step
-// 18.5 -> 17.9 us); the four-body pass, at two waves per SIMD, measured 5%
-// slower and the time-dependent three-body pass even, and they keep one
-// reciprocal per denominator.  A product of four denominators stays a normal
+// the waves hide its latency: the three-body Dalitz passes (eight
+// resonances, 1M events: step 18.5 -> 17.9 us); the four-body pass, at two
+// waves per SIMD, measured 5% slower and the time-dependent three-body pass
+// even, and they keep one reciprocal per denominator.  A product of four denominators stays a normal
 // number for denominators in [2^-250, 2^250]; the result carries a few more
 // roundings (about 2 n) than a reciprocal each.  n is a compile-time constant
 // where this is inlined into unrolled code.
