@@ -8,7 +8,8 @@ measured for the gfx950 approximations (2^-24.1): the one-step results stay
 within their second-order bounds (relative e^2 for the reciprocal, 1.5 e^2 for
 the reciprocal square root, e the seed's error, plus the roundings), the
 second-order reciprocal and the logarithm within about one unit in the last
-place of the exact values."""
+place of the exact values; the grouped reciprocal (one reciprocal of a product
+of up to four denominators) within the seed's term plus its roundings."""
 import math
 import random
 from decimal import Decimal, getcontext
@@ -199,3 +200,34 @@ def test_logprod_special_factors():
     for x in (2.0, -1.0):
         lp.mul(x)
     assert lp.m < 0.0  # log of a negative mantissa: NaN on the device
+
+
+def rcp_group(D, rng):
+    """The grouped reciprocal of csrc/fastmath.hpp: prefix products, one
+    seeded reciprocal with its Newton step, then the reciprocals peeled from
+    the top down (each product a correctly rounded double multiply)."""
+    n = len(D)
+    p = [D[0]]
+    for j in range(1, n):
+        p.append(p[j - 1] * D[j])
+    r = rcp_fast(p[n - 1], rng)
+    out = [0.0] * n
+    for j in range(n - 1, 0, -1):
+        out[j] = r * p[j - 1]
+        r = r * D[j]
+    out[0] = r
+    return out
+
+
+def test_grouped_reciprocals_within_bound():
+    """1/D_j from one reciprocal of the product of n <= 4 denominators (spread
+    over nine decades, as Breit-Wigner denominators are): the error stays
+    below the seed's second-order term plus 3 n roundings."""
+    rng = random.Random(17)
+    for n in (1, 2, 3, 4):
+        worst = 0.0
+        for _ in range(400):
+            D = [10.0 ** rng.uniform(-6.0, 3.0) for _ in range(n)]
+            got = rcp_group(D, rng)
+            worst = max(worst, max(rel_err(g, 1 / Fraction(d)) for g, d in zip(got, D)))
+        assert worst <= SEED_ERR ** 2 + 3 * n * 2.0 ** -53, (n, worst)
